@@ -1,0 +1,102 @@
+/* pbref -- plain FP64 CPU oracle for the three-region FEM-BEM nonlinear
+ * Poisson-Boltzmann problem.  TEST INFRASTRUCTURE ONLY: it exists to check the
+ * HIP library, it is slow on purpose, and no product code may link or call it.
+ *
+ * Unknowns: Phi = [u (FEM nodes) | lambda_m (Gamma_m vertices) | lambda_s
+ * (Gamma_s vertices)], surface vertices numbered by ascending FEM node id.
+ *
+ * Coupled system (Sec. 2, eq. fembem_matrix, rewritten for FEM in the shell
+ * only, with the interior Laplace BIE of Sec. 2.3 as the Gamma_m row):
+ *   A u + N(u) + eps_m T_m^T M_m lam_m - eps_s T_s^T M_s lam_s = 0
+ *   (1/2 M_m + K0_m) T_m u - V0_m lam_m                        = f_m
+ *   (1/2 M_s - Kk_s) T_s u + Vk_s lam_s                        = 0
+ */
+#ifndef PBREF_H
+#define PBREF_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbref pbref;
+
+enum { PBREF_LIN = 0, PBREF_T3 = 1, PBREF_HS = 2 };
+
+/* quadrature rules (weights normalised to sum 1 over the reference cell) */
+int pbref_rule_tri6(double *bary /*6x3*/, double *w /*6*/);
+int pbref_rule_tet27(double *bary /*27x4*/, double *w /*27*/);
+int pbref_rule_gauss01(int n, double *x, double *w);
+int pbref_rule_tri_collapsed(int m, double *bary /*m*m x 3*/, double *w);
+
+/* reg_order: 0 = 6-point degree-4 triangle rule, m>0 = m x m collapsed Gauss
+ * rule; n_ss: Gauss points per direction of the Sauter-Schwab rules. */
+pbref *pbref_create(int64_t n_nodes, const double *nodes, int64_t n_tets, const int32_t *tets,
+                    int64_t n_tri_m, const int32_t *tri_m, int64_t n_tri_s, const int32_t *tri_s,
+                    int64_t n_q, const double *q_xyz, const double *q_z,
+                    double eps_in, double eps_out, double kappa, double temperature,
+                    int reg_order, int n_ss);
+void pbref_destroy(pbref *);
+void pbref_sizes(const pbref *, int64_t out[4]); /* n_nodes, n_m, n_s, n_unknowns */
+void pbref_constants(const pbref *, double out[2]); /* Bjerrum length (A), kT (kcal/mol) */
+void pbref_surface_nodes(const pbref *, int surf, int32_t *out);
+
+/* surface operators; surf 0 = Gamma_m (Laplace), 1 = Gamma_s (Yukawa) */
+int pbref_bem_dense(pbref *, int surf);                           /* assemble and keep */
+int pbref_bem_get(const pbref *, int surf, double *V, double *K);  /* copy dense N x N */
+int pbref_bem_rows(pbref *, int surf, int64_t nrows, const int64_t *rows, double *V, double *K);
+int pbref_pair_integral(pbref *, int surf, int64_t tau, int64_t sig, double *V9, double *K9);
+void pbref_surface_mass_apply(const pbref *, int surf, const double *x, double *y);
+void pbref_coulomb_load(const pbref *, double *f);
+
+/* FEM pieces: element entries (16 per tet) and matrix-free products on u */
+void pbref_stiffness_entries(const pbref *, int32_t *rows, int32_t *cols, double *vals);
+void pbref_mass_entries(const pbref *, int32_t *rows, int32_t *cols, double *vals);
+void pbref_fem_nonlinear(const pbref *, int scheme, const double *u, double *out);
+void pbref_fem_jacobian(const pbref *, int scheme, const double *u, const double *v, double *out);
+void pbref_fem_hessian(const pbref *, int scheme, const double *u, const double *v, double *out);
+
+/* coupled operator (needs the dense surface operators of both surfaces) */
+int pbref_apply_A(pbref *, const double *phi, double *y);
+int pbref_rhs(pbref *, double *b);
+int pbref_residual(pbref *, int scheme, const double *phi, double *F);
+int pbref_apply_jacobian(pbref *, int scheme, const double *phi, const double *v, double *Jv);
+/* selected rows of F or J v without dense assembly; rows are global unknown ids */
+int pbref_residual_rows(pbref *, int scheme, const double *phi, int64_t nrows, const int64_t *rows, double *out);
+int pbref_jacobian_rows(pbref *, int scheme, const double *phi, const double *v, int64_t nrows,
+                        const int64_t *rows, double *out);
+
+typedef struct {
+    int scheme_first, omega_auto;
+    double omega_fixed, tol_nl, tol_gr, tol_gr0, tol_omega, l_e, omega0_first, omega0_next,
+        omega_min, omega_max;
+    int max_newton, max_omega_it, gmres_restart, max_gmres;
+} pbref_opts;
+
+typedef struct {
+    int status; /* 0 ok, -6 not converged, -7 non-finite */
+    double total, lc, nc, dg_omega_i;
+    int newton_iters, gmres_iters_total, gmres_lin;
+    int gmres_iters[64];
+    double omega[64], e_k[64];
+    int omega_iters[64];
+    int omega_fallback;
+} pbref_result;
+
+void pbref_opts_default(pbref_opts *);
+int pbref_gmres(pbref *, int scheme, const double *phi, const double *b, double *x, double tol,
+                int restart, int maxit, int *iters);
+int pbref_solve(pbref *, const pbref_opts *, pbref_result *, double *phi_lin, double *phi_nl);
+/* f_d(omega) and f_d'(omega) for the step D at phi (out[0], out[1]) */
+int pbref_fd(pbref *, int scheme, const double *phi, const double *D, double omega, double out[2]);
+/* Newton search for the root of f_d starting at *omega; returns 1 on fallback */
+int pbref_omega_search(pbref *, int scheme, const double *phi, const double *D, const pbref_opts *o,
+                       double *omega, int *iters);
+/* energy pieces from given Phi_L and Phi_NL (kcal/mol) */
+int pbref_energy(pbref *, const double *phi_lin, const double *phi_nl, double out[4]);
+/* reaction potential u_r at arbitrary points from a given Phi (units of kT/e) */
+int pbref_reaction_potential(const pbref *, const double *phi, int64_t np, const double *pts, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,414 @@
+"""Seeded synthetic inputs for the three-region FEM-BEM Poisson-Boltzmann problem.
+
+This module only builds meshes, charges and physical parameters.  It holds
+none of the method's arithmetic (no quadrature, no operators, no solver), so
+both the CPU oracle and the HIP library can be fed from it.
+
+Geometry recipe (the paper meshes molecular SES surfaces with NanoShaper and
+fills the shell with TetMesh; those inputs are replaced here by synthetic
+star-shaped solutes of the same size class):
+
+* Gamma_m: class-I geodesic icosphere of frequency n (20 n^2 triangles,
+  10 n^2 + 2 vertices), mapped radially by r(x) = spheroid radius plus a seeded
+  real spherical-harmonic bump (l = 1..8) rescaled to amplitude A in [0.5, 1.5] A.
+* Gamma_s: the radial copy r(x) + t.
+* Shell Omega_i: L uniform radial layers of prisms, each prism split into three
+  tetrahedra with the diagonal rule "lower-id bottom vertex to higher-id top
+  vertex", which is conforming across neighbouring prisms.
+* Charges: a double helix of unit negative charges (two strands half a turn
+  apart, 11 charges per turn, 28 A pitch, radius 9 A, centred at z = 0) plus
+  partial charges N(0, 0.3) drawn uniformly inside Gamma_m.  Helix charges that
+  would sit outside Gamma_m or closer than ``clearance`` to it are pulled
+  towards the origin until they keep that clearance.
+
+Node numbering: FEM node (layer l, surface vertex v) has id l*Nv + v, so the
+Gamma_m nodes are 0..Nv-1 and the Gamma_s nodes are L*Nv..(L+1)*Nv-1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = ["Problem", "icosphere", "make_problem", "make_config", "config_params",
+           "point_mesh_distance", "validate", "batch_instance"]
+
+
+@dataclasses.dataclass
+class Problem:
+    nodes: np.ndarray      # (n_nodes, 3) float64, Angstrom
+    tets: np.ndarray       # (n_tets, 4) int32, positive orientation
+    tri_m: np.ndarray      # (Nt, 3) int32 FEM node ids, outward (into the shell)
+    tri_s: np.ndarray      # (Nt, 3) int32 FEM node ids, outward (into the far solvent)
+    q_xyz: np.ndarray      # (Nq, 3) float64
+    q_z: np.ndarray        # (Nq,) float64, valence in units of e
+    eps_in: float
+    eps_out: float
+    kappa: float
+    info: dict
+
+    @property
+    def n_nodes(self):
+        return int(self.nodes.shape[0])
+
+
+# ----------------------------------------------------------------------------
+# surfaces
+# ----------------------------------------------------------------------------
+def _icosahedron():
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([[-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
+                  [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
+                  [p, 0, -1], [p, 0, 1], [-p, 0, -1], [-p, 0, 1]], dtype=np.float64)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    return v, f
+
+
+def icosphere(n: int):
+    """Class-I geodesic subdivision of frequency n, projected to the unit sphere.
+
+    Returns (verts (10n^2+2, 3), tris (20n^2, 3) int32, outward oriented).
+    Grid points are keyed exactly by their integer barycentric weights on the
+    icosahedron corners, so points on shared edges are merged exactly.
+    """
+    if n < 1:
+        raise ValueError("frequency must be >= 1")
+    V, F = _icosahedron()
+    key_to_id = {}
+    pts = []
+
+    def vid(face, i, j):
+        a, b, c = (int(x) for x in F[face])
+        w = {}
+        for corner, weight in ((a, n - i - j), (b, i), (c, j)):
+            if weight:
+                w[corner] = w.get(corner, 0) + weight
+        key = tuple(sorted(w.items()))
+        if key not in key_to_id:
+            key_to_id[key] = len(pts)
+            p = sum(V[k] * (wt / n) for k, wt in key)
+            pts.append(p / np.linalg.norm(p))
+        return key_to_id[key]
+
+    tris = []
+    for face in range(20):
+        for i in range(n):
+            for j in range(n - i):
+                tris.append((vid(face, i, j), vid(face, i + 1, j), vid(face, i, j + 1)))
+                if i + j < n - 1:
+                    tris.append((vid(face, i + 1, j), vid(face, i + 1, j + 1), vid(face, i, j + 1)))
+    verts = np.array(pts)
+    tris = np.array(tris, dtype=np.int64)
+    # outward orientation
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    flip = np.einsum("ij,ij->i", nrm, a + b + c) < 0
+    tris[flip] = tris[flip][:, [0, 2, 1]]
+    assert verts.shape[0] == 10 * n * n + 2 and tris.shape[0] == 20 * n * n
+    return verts, tris.astype(np.int32)
+
+
+def _real_sph_harm(lmax, xyz):
+    """Real spherical harmonics Y_lm for l = 1..lmax (m = -l..l) at unit vectors."""
+    from scipy import special
+    theta = np.arccos(np.clip(xyz[:, 2], -1.0, 1.0))
+    phi = np.arctan2(xyz[:, 1], xyz[:, 0])
+    cols = []
+    for l in range(1, lmax + 1):
+        for m in range(-l, l + 1):
+            y = special.sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                cols.append(math.sqrt(2.0) * (-1) ** m * y.real)
+            elif m < 0:
+                cols.append(math.sqrt(2.0) * (-1) ** m * y.imag)
+            else:
+                cols.append(y.real)
+    return np.stack(cols, axis=1)
+
+
+def radial_surface(unit, a, c, rng=None, lmax=8, amp_range=(0.5, 1.5)):
+    """Radius r(x) of the star-shaped solute along each unit direction.
+
+    Spheroid with semi-axes (a, a, c) plus, if rng is given, a seeded real
+    spherical-harmonic bump sum_{l,m} c_lm Y_lm with c_lm ~ N(0,1)/(l+1)^2,
+    rescaled so that max |bump| over the given directions equals A ~ U(amp_range).
+    """
+    r = 1.0 / np.sqrt((unit[:, 0] ** 2 + unit[:, 1] ** 2) / a ** 2 + unit[:, 2] ** 2 / c ** 2)
+    amp = 0.0
+    if rng is not None:
+        amp = float(rng.uniform(*amp_range))
+        ls = np.concatenate([[l] * (2 * l + 1) for l in range(1, lmax + 1)])
+        coef = rng.standard_normal(ls.size) / (ls + 1.0) ** 2
+        bump = _real_sph_harm(lmax, unit) @ coef
+        bump *= amp / np.max(np.abs(bump))
+        r = r + bump
+    return r, amp
+
+
+def shell_mesh(unit, tris, r_in, thickness, layers):
+    """Prism shell between r_in(x) x and (r_in(x)+thickness) x, split into tets."""
+    nv = unit.shape[0]
+    L = int(layers)
+    nodes = np.concatenate([(r_in + thickness * l / L)[:, None] * unit for l in range(L + 1)])
+    t = np.sort(tris.astype(np.int64), axis=1)  # a < b < c by global id
+    a, b, c = t[:, 0], t[:, 1], t[:, 2]
+    tets = []
+    for l in range(L):
+        lo, hi = l * nv, (l + 1) * nv
+        A, B, C = a + lo, b + lo, c + lo
+        A2, B2, C2 = a + hi, b + hi, c + hi
+        tets.append(np.stack([A, B, C, C2], 1))
+        tets.append(np.stack([A, B, B2, C2], 1))
+        tets.append(np.stack([A, A2, B2, C2], 1))
+    tets = np.concatenate(tets)
+    p = nodes[tets]
+    vol = np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
+    neg = vol < 0
+    tets[neg] = tets[neg][:, [0, 2, 1, 3]]
+    tri_m = tris.astype(np.int64)
+    tri_s = tris.astype(np.int64) + L * nv
+    return nodes, tets.astype(np.int32), tri_m.astype(np.int32), tri_s.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# geometry queries used for charge placement and validation
+# ----------------------------------------------------------------------------
+def point_mesh_distance(p, verts, tris):
+    """Exact Euclidean distance from each point p (k,3) to a triangle mesh."""
+    A = verts[tris[:, 0]]
+    B = verts[tris[:, 1]]
+    C = verts[tris[:, 2]]
+    out = np.empty(p.shape[0])
+    for i, x in enumerate(np.atleast_2d(p)):
+        out[i] = np.sqrt(np.min(_pt_tri_dist2(x, A, B, C)))
+    return out
+
+
+def _pt_tri_dist2(x, A, B, C):
+    # closest point on triangle (Ericson, Real-Time Collision Detection, 5.1.5)
+    ab, ac, ap = B - A, C - A, x - A
+    d1 = np.einsum("ij,ij->i", ab, ap)
+    d2 = np.einsum("ij,ij->i", ac, ap)
+    bp = x - B
+    d3 = np.einsum("ij,ij->i", ab, bp)
+    d4 = np.einsum("ij,ij->i", ac, bp)
+    cp = x - C
+    d5 = np.einsum("ij,ij->i", ab, cp)
+    d6 = np.einsum("ij,ij->i", ac, cp)
+    va = d3 * d6 - d5 * d4
+    vb = d5 * d2 - d1 * d6
+    vc = d1 * d4 - d3 * d2
+    denom = va + vb + vc
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = vb / denom
+        w = vc / denom
+    q = A + ab * v[:, None] + ac * w[:, None]
+    # region tests, later assignments take priority in reverse order of checks
+    m = (d1 <= 0) & (d2 <= 0)
+    q[m] = A[m]
+    m2 = (d3 >= 0) & (d4 <= d3)
+    q[m2 & ~m] = B[m2 & ~m]
+    done = m | m2
+    m3 = (d6 >= 0) & (d5 <= d6) & ~done
+    q[m3] = C[m3]
+    done |= m3
+    m4 = (vc <= 0) & (d1 >= 0) & (d3 <= 0) & ~done
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t4 = d1 / (d1 - d3)
+    q[m4] = A[m4] + t4[m4, None] * ab[m4]
+    done |= m4
+    m5 = (vb <= 0) & (d2 >= 0) & (d6 <= 0) & ~done
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t5 = d2 / (d2 - d6)
+    q[m5] = A[m5] + t5[m5, None] * ac[m5]
+    done |= m5
+    m6 = (va <= 0) & ((d4 - d3) >= 0) & ((d5 - d6) >= 0) & ~done
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t6 = (d4 - d3) / ((d4 - d3) + (d5 - d6))
+    q[m6] = B[m6] + t6[m6, None] * (C[m6] - B[m6])
+    d = x - q
+    return np.einsum("ij,ij->i", d, d)
+
+
+def inside_star(p, verts, tris):
+    """Inside test for a surface star-shaped about the origin (ray from origin)."""
+    A = verts[tris[:, 0]]
+    E1 = verts[tris[:, 1]] - A
+    E2 = verts[tris[:, 2]] - A
+    res = np.zeros(p.shape[0], dtype=bool)
+    for i, x in enumerate(p):
+        rn = np.linalg.norm(x)
+        if rn == 0:
+            res[i] = True
+            continue
+        d = x / rn
+        h = np.cross(d, E2)
+        det = np.einsum("ij,ij->i", E1, h)
+        ok = np.abs(det) > 1e-14
+        inv = np.where(ok, 1.0 / np.where(ok, det, 1.0), 0.0)
+        s = -A
+        u = np.einsum("ij,ij->i", s, h) * inv
+        qv = np.cross(s, E1)
+        v = (qv @ d) * inv
+        t = np.einsum("ij,ij->i", E2, qv) * inv
+        hit = ok & (u >= -1e-12) & (v >= -1e-12) & (u + v <= 1 + 1e-12) & (t > 0)
+        res[i] = bool(np.any(hit)) and rn < np.min(t[hit])
+    return res
+
+
+def _place_helix(n_per_strand, radius, verts, tris, clearance, log):
+    pts = []
+    rise = 28.0 / 11.0
+    for s in range(2):
+        for k in range(n_per_strand):
+            th = 2.0 * math.pi * k / 11.0 + math.pi * s
+            z = (k - (n_per_strand - 1) / 2.0) * rise
+            pts.append([radius * math.cos(th), radius * math.sin(th), z])
+    pts = np.array(pts)
+    out = pts.copy()
+    tapered = 0
+    for i, x in enumerate(pts):
+        def ok(s):
+            y = x * s
+            return inside_star(y[None], verts, tris)[0] and point_mesh_distance(y[None], verts, tris)[0] >= clearance
+        if ok(1.0):
+            continue
+        tapered += 1
+        s_hi = 1.0
+        step = 1.0
+        while True:
+            step = max(0.0, step - 0.05)
+            if step == 0.0 or ok(step):
+                break
+            s_hi = step
+        s_lo = step
+        for _ in range(16):  # bisect towards the feasible boundary
+            mid = 0.5 * (s_lo + s_hi)
+            if ok(mid):
+                s_lo = mid
+            else:
+                s_hi = mid
+        out[i] = x * s_lo
+    log["helix_tapered"] = tapered
+    return out
+
+
+def _place_partials(count, sigma, rng, verts, tris, clearance):
+    lo = verts.min(0)
+    hi = verts.max(0)
+    acc = []
+    while len(acc) < count:
+        cand = rng.uniform(lo, hi, size=(max(64, 2 * (count - len(acc))), 3))
+        ins = inside_star(cand, verts, tris)
+        cand = cand[ins]
+        if cand.size:
+            d = point_mesh_distance(cand, verts, tris)
+            cand = cand[d >= clearance]
+        for c in cand:
+            if len(acc) < count:
+                acc.append(c)
+    z = rng.normal(0.0, sigma, size=count)
+    return np.array(acc).reshape(-1, 3), z
+
+
+# ----------------------------------------------------------------------------
+# configurations
+# ----------------------------------------------------------------------------
+def config_params(cfg: int):
+    """Geometry/charge recipe for the named workloads."""
+    if cfg == 0:
+        return dict(n=4, a=4.0, c=4.0, bump=False, t=4.0, L=6, helix=0, partials=0, kappa=0.125)
+    if cfg == 1:
+        return dict(n=32, a=10.0, c=30.0, bump=True, t=6.0, L=10, helix=24, partials=400, kappa=0.125)
+    if cfg == 2:
+        return dict(n=64, a=12.0, c=70.0, bump=True, t=6.0, L=12, helix=60, partials=400, kappa=0.125)
+    raise ValueError(f"unknown config {cfg}")
+
+
+def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
+                 eps_in=4.0, eps_out=80.0, clearance=1.5, center_charge=None):
+    rng = np.random.default_rng(list(seed))
+    unit, tris = icosphere(n)
+    r, amp = radial_surface(unit, a, c, rng if bump else None)
+    nodes, tets, tri_m, tri_s = shell_mesh(unit, tris, r, t, L)
+    log = dict(n=n, a=a, c=c, amp=amp, t=t, L=L, seed=list(seed))
+    gm = nodes[: unit.shape[0]]
+    qx, qz = [], []
+    if center_charge is not None:
+        qx.append(np.zeros((1, 3)))
+        qz.append(np.array([float(center_charge)]))
+    if helix:
+        hx = _place_helix(helix, 9.0, gm, tris, clearance, log)
+        qx.append(hx)
+        qz.append(-np.ones(hx.shape[0]))
+    if partials:
+        px, pz = _place_partials(partials, 0.3, rng, gm, tris, clearance)
+        qx.append(px)
+        qz.append(pz)
+    q_xyz = np.concatenate(qx) if qx else np.zeros((0, 3))
+    q_z = np.concatenate(qz) if qz else np.zeros(0)
+    return Problem(nodes=np.ascontiguousarray(nodes), tets=np.ascontiguousarray(tets),
+                   tri_m=np.ascontiguousarray(tri_m), tri_s=np.ascontiguousarray(tri_s),
+                   q_xyz=np.ascontiguousarray(q_xyz, dtype=np.float64),
+                   q_z=np.ascontiguousarray(q_z, dtype=np.float64),
+                   eps_in=eps_in, eps_out=eps_out, kappa=kappa, info=log)
+
+
+def make_config(cfg: int, instance: int = 0, **override):
+    """Workload `cfg` (0: charged sphere, 1: RNA-like 20k-triangle solute,
+    2: RNA-like 80k-triangle solute), seeded by default_rng([cfg, instance])."""
+    p = config_params(cfg)
+    p.update(override)
+    center = 1.0 if cfg == 0 else None
+    return make_problem(seed=(cfg, instance), center_charge=center, **p)
+
+
+def batch_instance(cfg: int, instance: int, n_lo=4, n_hi=44):
+    """One instance of the batched / serving workloads: triangle count log-uniform
+    over frequencies [n_lo, n_hi], kappa ~ U(0.03, 0.33), half sphere-type
+    (central +1 charge) and half RNA-type (helix of 4..60 charges)."""
+    rng = np.random.default_rng([cfg, instance, 7])
+    n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+    kappa = float(rng.uniform(0.03, 0.33))
+    if instance % 2 == 0:
+        return make_problem(n=n, a=4.0, c=4.0, bump=False, t=4.0, L=6, helix=0, partials=0,
+                            kappa=kappa, seed=(cfg, instance), center_charge=1.0)
+    h = int(rng.integers(4, 61))
+    per = (h + 1) // 2
+    span = (per - 1) * 28.0 / 11.0
+    c = max(15.0, span / 2.0 + 8.0)
+    L = 10
+    return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=L, helix=per, partials=0,
+                        kappa=kappa, seed=(cfg, instance))
+
+
+# ----------------------------------------------------------------------------
+# validation (mesh sanity; no method arithmetic)
+# ----------------------------------------------------------------------------
+def validate(p: Problem, clearance=1.0):
+    nodes, tets = p.nodes, p.tets
+    x = nodes[tets]
+    vol = np.einsum("ij,ij->i", np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]), x[:, 3] - x[:, 0]) / 6
+    assert np.all(vol > 0), "non-positive tet volume"
+    for tri in (p.tri_m, p.tri_s):
+        e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+        directed = set(map(tuple, e.tolist()))
+        assert len(directed) == e.shape[0], "directed edge repeated"
+        assert all((b, a) in directed for a, b in directed), "surface not closed"
+        nv = np.unique(tri).size
+        ne = e.shape[0] // 2
+        assert nv - ne + tri.shape[0] == 2, "Euler characteristic != 2"
+        v = nodes[tri]
+        sv = np.einsum("ij,ij->i", v[:, 0], np.cross(v[:, 1], v[:, 2])).sum() / 6
+        assert sv > 0, "surface not outward"
+    if p.q_xyz.shape[0]:
+        vm = np.unique(p.tri_m)
+        d = point_mesh_distance(p.q_xyz, nodes, p.tri_m)
+        assert np.all(d >= clearance), "charge too close to Gamma_m"
+        assert np.all(inside_star(p.q_xyz, nodes, p.tri_m)), "charge outside Gamma_m"
+    return True
