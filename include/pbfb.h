@@ -1,0 +1,173 @@
+/* pbfb.h -- C ABI of the MI355X FEM-BEM nonlinear Poisson-Boltzmann library.
+ *
+ * Problem (paper Sec. 2.1, eqs. EcGeneral_PBE, Variables_2Superficie, pbe_vp):
+ * three regions -- solute Omega_m (eps_in, point charges), shell Omega_i
+ * (eps_out, screening kappa, nonlinear sinh term) and far solvent Omega_s
+ * (eps_out, kappa, linear) -- separated by the triangulated interfaces
+ * Gamma_m and Gamma_s.  The shell is discretised with P1 tetrahedra; the
+ * interior uses the Laplace boundary integral equation of Sec. 2.3 and the
+ * exterior the Yukawa boundary integral equation of Sec. 2.2, both as dense
+ * Galerkin P1 operators.  Unknowns Phi = [u | lambda_m | lambda_s] (FEM nodal
+ * potential in units of kT/e, normal derivatives on Gamma_m and Gamma_s):
+ *
+ *   A u + N(u) + eps_in T_m^T M_m lambda_m - eps_out T_s^T M_s lambda_s = 0
+ *   (1/2 M_m + K_m) T_m u - V_m lambda_m                                = f_m
+ *   (1/2 M_s - K_s) T_s u + V_s lambda_s                                = 0
+ *
+ * (the 2x2 block system of eq. fembem_matrix, extended by the interior
+ * Laplace equation as a third block row), with N(u) = eps_out kappa^2
+ * int sinh(u_h) v.  Newton-Raphson with a cubic first step and a
+ * self-adjusted relaxation factor solves it (Sec. 2.4-2.5, App. A, App. B).
+ *
+ * Conventions for every entry point:
+ *  - return value: pbfb_status, 0 = success, negative = error; the message of
+ *    the last failing call on this thread is returned by pbfb_last_error();
+ *  - array arguments are borrowed for the duration of the call and copied;
+ *    the caller keeps ownership; outputs are written into caller buffers;
+ *  - `mem` says where vector arguments live: PBFB_MEM_HOST (pageable host
+ *    memory) or PBFB_MEM_DEVICE (device memory of the context's GPU);
+ *  - `hip_stream` is a hipStream_t (NULL = the library's own stream); device
+ *    outputs are complete when the stream reaches the end of the call; host
+ *    outputs are complete when the call returns;
+ *  - a pbfb_problem is not thread-safe: serialise calls per handle.
+ */
+#ifndef PBFB_H
+#define PBFB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbfb_ctx pbfb_ctx;
+typedef struct pbfb_problem pbfb_problem;
+
+typedef enum {
+    PBFB_OK = 0,
+    PBFB_EINVAL = -1,   /* bad argument (null pointer, eps <= 0, kappa < 0, size) */
+    PBFB_EMESH = -2,    /* inverted/degenerate tet, open or non-manifold surface */
+    PBFB_ECHARGE = -3,  /* charge outside Gamma_m or closer than 1 A to it */
+    PBFB_ENOMEM = -4,   /* device allocation failed */
+    PBFB_EDEVICE = -5,  /* HIP runtime error */
+    PBFB_ENOTCONV = -6, /* Newton or GMRES iteration limit reached (results hold the last iterate) */
+    PBFB_ENAN = -7,     /* non-finite residual */
+    PBFB_ESTATE = -8    /* call order violated (mesh/charges/params missing) */
+} pbfb_status;
+
+typedef enum { PBFB_FP64 = 0, PBFB_MIXED = 1 } pbfb_precision;
+/* nonlinearity of the shell reaction term: N(u) = u, u + u^3/6, sinh(u) */
+typedef enum { PBFB_LIN = 0, PBFB_T3 = 1, PBFB_HS = 2 } pbfb_scheme;
+enum { PBFB_MEM_HOST = 0, PBFB_MEM_DEVICE = 1 };
+
+/* ---- context ------------------------------------------------------------ */
+pbfb_status pbfb_ctx_create(int device, pbfb_ctx **out);
+void pbfb_ctx_destroy(pbfb_ctx *ctx);
+const char *pbfb_last_error(void);
+
+/* ---- problem ------------------------------------------------------------ */
+/* precision PBFB_FP64: every operator stored and applied in FP64.
+ * PBFB_MIXED: dense boundary operators and FEM matrix values stored in FP32
+ * (evaluated in FP32 relative to panel centroids, accumulated in FP64),
+ * FP64 accumulation in every product, FP32-basis inner GMRES inside FP64
+ * iterative refinement; Newton update, relaxation search, orthogonalisation
+ * and touching-panel integrals stay FP64. */
+pbfb_status pbfb_problem_create(pbfb_ctx *ctx, int precision, pbfb_problem **out);
+void pbfb_problem_destroy(pbfb_problem *p);
+
+/* Shell mesh in Angstrom (Sec. 2.1 three-region model).  nodes[3*n_nodes];
+ * tets[4*n_tets] 0-based FEM node ids, any orientation with nonzero volume;
+ * tri_m[3*n_tri_m] / tri_s[3*n_tri_s]: Gamma_m / Gamma_s triangles over FEM
+ * node ids, oriented so that the right-hand normal points away from the
+ * solute.  The surface unknowns are numbered by ascending FEM node id.
+ * Errors: EINVAL (sizes / ids out of range), EMESH (degenerate tet,
+ * zero-area triangle, surface not closed). */
+pbfb_status pbfb_set_mesh(pbfb_problem *p, int64_t n_nodes, const double *nodes, int64_t n_tets,
+                          const int32_t *tets, int64_t n_tri_m, const int32_t *tri_m, int64_t n_tri_s,
+                          const int32_t *tri_s);
+/* Point charges (Sec. 2.1, rho_c): positions xyz[3*n] in Angstrom and
+ * valences z[n] in units of e.  ECHARGE if a charge is outside Gamma_m or
+ * within 1 A of it (the surface integrals of the Coulomb load assume it). */
+pbfb_status pbfb_set_charges(pbfb_problem *p, int64_t n, const double *xyz, const double *z);
+/* eps_in = eps_m, eps_out = eps_s (relative permittivities, > 0), kappa in
+ * 1/Angstrom (>= 0), temperature in K (> 0; potentials are in kT/e). */
+pbfb_status pbfb_set_params(pbfb_problem *p, double eps_in, double eps_out, double kappa, double temperature_K);
+/* sizes: FEM nodes, Gamma_m vertices, Gamma_s vertices, unknowns, device bytes held */
+pbfb_status pbfb_get_sizes(const pbfb_problem *p, int64_t *n_nodes, int64_t *n_m, int64_t *n_s,
+                           int64_t *n_unknowns, int64_t *hbm_bytes);
+/* Device setup: geometry, CSR pattern, stiffness, surface masses, Coulomb
+ * load, dense boundary operators with touching-panel corrections.  Done
+ * lazily by the first call that needs it. */
+pbfb_status pbfb_setup(pbfb_problem *p, void *hip_stream);
+
+/* ---- operator evaluations (vectors of length n_unknowns, FP64) ---------- */
+/* F = A Phi + [N_scheme(u); 0; 0] - b (eq. general_nonlinear) */
+pbfb_status pbfb_residual(pbfb_problem *p, int scheme, const double *phi, double *F, int mem, void *hip_stream);
+/* Jv = (A + [J_scheme(u) 0 0; 0 0 0; 0 0 0]) v, the Newton matrix of eq. NR_main */
+pbfb_status pbfb_apply_jacobian(pbfb_problem *p, int scheme, const double *phi, const double *v, double *Jv,
+                                int mem, void *hip_stream);
+
+/* ---- Newton solve (Sec. 2.4.2, 2.5, App. A, App. B) --------------------- */
+typedef struct {
+    int scheme_first;    /* PBFB_T3 (cubic start, default) or PBFB_HS */
+    int omega_auto;      /* 1: relaxation factor from the root of f_d; 0: omega_fixed */
+    double omega_fixed;  /* constant relaxation factor when omega_auto == 0 */
+    double tol_nl;       /* stop when omega ||Delta||_2 < tol_nl (1e-3) */
+    double tol_gr;       /* final GMRES relative tolerance (1e-6) */
+    double tol_gr0;      /* initial GMRES tolerance (1e-3); == tol_gr disables adaptivity */
+    double tol_omega;    /* |f_d| tolerance of the omega search (0.1) */
+    double l_e;          /* freeze omega once omega ||Delta|| < l_e (0.35; 0 disables) */
+    double omega0_first; /* omega search start in the cubic step (2) */
+    double omega0_next;  /* omega search start afterwards (1) */
+    double omega_min, omega_max; /* clamp of the search (0, 4) */
+    int max_newton;      /* 50 */
+    int max_omega_it;    /* 50 */
+    int gmres_restart;   /* 200 */
+    int max_gmres;       /* iterations per linear solve (2000) */
+} pbfb_solve_opts;
+void pbfb_solve_opts_default(pbfb_solve_opts *o);
+
+typedef struct {
+    pbfb_status status;
+    double total, lc, nc, dg_omega_i; /* kcal/mol: Total = LC + NC + dG_Omega_i (eq. Esolv) */
+    int newton_iters, gmres_iters_total, gmres_lin;
+    int gmres_iters[64];
+    double omega[64], e_k[64];
+    int omega_iters[64];
+    double t_setup_s, t_solve_s;
+} pbfb_result;
+
+/* Full solve: linear component Phi_L, Newton on Phi_NL, energy.  phi_out
+ * (nullable, length 2*n_unknowns) receives [Phi_L | Phi_NL]. */
+pbfb_status pbfb_solve(pbfb_problem *p, const pbfb_solve_opts *o, pbfb_result *res, double *phi_out, int mem,
+                       void *hip_stream);
+/* Energy split {Total, LC, NC, dG_Omega_i} (kcal/mol) of given Phi_L, Phi_NL
+ * (eqs. Esolv, Esolv_Lineal, Potential_in_Omega_m); phi_nl may be NULL. */
+pbfb_status pbfb_energy(pbfb_problem *p, const double *phi_lin, const double *phi_nl, double out[4], int mem,
+                        void *hip_stream);
+
+/* ---- inspection --------------------------------------------------------- */
+/* Copy the two dense blocks stored for surface `surf` (0 = Gamma_m, Laplace;
+ * 1 = Gamma_s, Yukawa) as row-major n x n host arrays (either may be NULL):
+ *   Gamma_m: Kp = 1/2 M_m + K0_m,  Vp = -V0_m
+ *   Gamma_s: Kp = 1/2 M_s - Kk_s,  Vp = +Vk_s
+ * i.e. the Galerkin blocks of the second and third block rows above, with
+ * M the P1 surface mass, V/K the single/double layer (Sec. 2.2, eq. KV).
+ * In mixed precision the FP32 stored values are widened. */
+pbfb_status pbfb_export_bem(pbfb_problem *p, int surf, double *Vp, double *Kp);
+/* Right-hand side b = [0 | f_m | 0] (host array of length n_unknowns). */
+pbfb_status pbfb_export_rhs(pbfb_problem *p, double *b);
+/* Kernel timing with HIP events recorded on the stream each kernel runs on.
+ * While enabled, every launch of the timed kernel classes is bracketed by an
+ * event pair; pbfb_timing returns the average duration (ms) and the number
+ * of launches since the last reset for: which = 0 coupled apply (dense GEMV +
+ * FEM SpMV), 1 dense GEMV, 2 FEM SpMV, 3 regular BEM assembly, 4 touching-
+ * panel integrals.  pbfb_timing synchronises the problem's last stream. */
+pbfb_status pbfb_timing_enable(pbfb_problem *p, int on);
+pbfb_status pbfb_timing(pbfb_problem *p, int which, double *avg_ms, int64_t *count, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBFB_H */

@@ -1,0 +1,611 @@
+// Dense Galerkin P1 boundary operators on one surface:
+//   V_ij = int int zeta_i(x) g(x,y) zeta_j(y),   K_ij = int int zeta_i(x) dg/dn_y zeta_j(y),
+//   g = exp(-kappa r) / (4 pi r)   (Sec. 2.2 Yukawa kernel; kappa = 0: Sec. 2.3 Laplace kernel)
+// stored as one row-major matrix per surface, row i = [K'_i | V'_i] with
+//   Gamma_m: K' = 1/2 M + K0,  V' = -V0   (interior Laplace equation)
+//   Gamma_s: K' = 1/2 M - Kk,  V' = +Vk   (exterior Yukawa equation)
+// so the Galerkin rows of the coupled operator are one dense GEMV each.
+//
+// Assembly, deterministic and free of atomics:
+//  1. regular tiles: a workgroup takes 16 target x 32 source Morton-ordered
+//     triangles, evaluates the 6 x 6 product rule for every non-touching pair,
+//     reduces the 3x3 pair blocks to the block's local vertex tile in LDS and
+//     stores it in an expanded matrix E whose rows are (target block, local
+//     vertex) and whose columns are (source block, local vertex);
+//  2. two coalesced gather passes fold the duplicated rows and columns of E
+//     back onto surface vertices;
+//  3. touching pairs (identical, common edge, common vertex) are integrated
+//     with the Sauter-Schwab rules (one wavefront per pair) and added, with
+//     the 1/2 M term, by a row-owned scatter.
+#include <cmath>
+
+#include "pbfb_internal.hpp"
+
+namespace pbfb {
+
+struct QRule6 {
+    double b[6][3];
+    double w[6];
+};
+struct GL4 {
+    double x[4];
+    double w[4];
+};
+
+static QRule6 q6arg()
+{
+    QRule6 r;
+    const Rules &R = rules();
+    for (int q = 0; q < 6; ++q) {
+        for (int k = 0; k < 3; ++k) r.b[q][k] = R.tri_bary[q][k];
+        r.w[q] = R.tri_w[q];
+    }
+    return r;
+}
+static GL4 gl4arg()
+{
+    GL4 r;
+    for (int i = 0; i < 4; ++i) {
+        r.x[i] = rules().gl_x[i];
+        r.w[i] = rules().gl_w[i];
+    }
+    return r;
+}
+
+static inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+constexpr double INV4PI = 0.079577471545947667884441881686257181;
+
+// Morton-ordered copies of the triangle data used by the regular assembly.
+__global__ void k_tri_morton(int64_t nt, const int32_t *__restrict__ morton, const int32_t *__restrict__ tri,
+                             const double *__restrict__ qp, const double *__restrict__ nrm,
+                             const double *__restrict__ area, int32_t *__restrict__ m_tri,
+                             double *__restrict__ m_qp, double *__restrict__ m_nrm, double *__restrict__ m_area)
+{
+    int64_t m = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (m >= nt) return;
+    int32_t t = morton[m];
+    for (int k = 0; k < 3; ++k) {
+        m_tri[3 * m + k] = tri[3 * t + k];
+        m_nrm[3 * m + k] = nrm[3 * t + k];
+    }
+    for (int k = 0; k < 18; ++k) m_qp[18 * m + k] = qp[18 * t + k];
+    m_area[m] = area[t];
+}
+
+
+// ---------------------------------------------------------------------------
+// 1. regular tiles
+// ---------------------------------------------------------------------------
+template <bool YUK>
+__global__ void __launch_bounds__(256)
+    k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const double *__restrict__ m_qp,
+                  const double *__restrict__ m_nrm, const double *__restrict__ m_area,
+                  const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
+                  const int32_t *__restrict__ A_slots, const int32_t *__restrict__ B_pref,
+                  const int32_t *__restrict__ B_nv, const int32_t *__restrict__ B_slots, int64_t bA0,
+                  int64_t rowbase, double *__restrict__ EV, double *__restrict__ EK, int64_t ldE, double kappa,
+                  QRule6 R)
+{
+    __shared__ double sX[BA][18];
+    __shared__ double sY[BB][18];
+    __shared__ double sN[BB][3];
+    __shared__ double sAa[BA], sAb[BB];
+    __shared__ int sVa[BA][3], sVb[BB][3];
+    __shared__ int sSa[BA * 3][MAXS], sSb[BB * 3][MAXS];
+    __shared__ double acc[BA * 3][BB * 3 + 1];
+
+    const int tid = threadIdx.x;
+    const int64_t bB = blockIdx.x;
+    const int64_t bA = bA0 + blockIdx.y;
+    const int nA = A_nv[bA], nB = B_nv[bB];
+    const int64_t pA = A_pref[bA], pB = B_pref[bB];
+
+    for (int k = tid; k < BA * 18; k += 256) {
+        int tl = k / 18, c = k % 18;
+        int64_t m = bA * BA + tl;
+        sX[tl][c] = m < nt ? m_qp[18 * m + c] : 0.0;
+    }
+    for (int k = tid; k < BB * 18; k += 256) {
+        int sl = k / 18, c = k % 18;
+        int64_t m = bB * BB + sl;
+        sY[sl][c] = m < nt ? m_qp[18 * m + c] : 0.0;
+    }
+    if (tid < BB * 3) {
+        int sl = tid / 3, c = tid % 3;
+        int64_t m = bB * BB + sl;
+        sN[sl][c] = m < nt ? m_nrm[3 * m + c] : 0.0;
+        sVb[sl][c] = m < nt ? m_tri[3 * m + c] : -1;
+    }
+    if (tid < BA * 3) {
+        int tl = tid / 3, c = tid % 3;
+        int64_t m = bA * BA + tl;
+        sVa[tl][c] = m < nt ? m_tri[3 * m + c] : -2;
+    }
+    if (tid < BA) sAa[tid] = (bA * BA + tid) < nt ? m_area[bA * BA + tid] : 0.0;
+    if (tid < BB) sAb[tid] = (bB * BB + tid) < nt ? m_area[bB * BB + tid] : 0.0;
+    for (int k = tid; k < BA * 3 * MAXS; k += 256) {
+        int r = k / MAXS, c = k % MAXS;
+        sSa[r][c] = r < nA ? A_slots[(pA + r) * MAXS + c] : -1;
+    }
+    for (int k = tid; k < BB * 3 * MAXS; k += 256) {
+        int r = k / MAXS, c = k % MAXS;
+        sSb[r][c] = r < nB ? B_slots[(pB + r) * MAXS + c] : -1;
+    }
+    __syncthreads();
+
+    // two pairs per thread: (tl, sl) = (tid / 32 + 8 h, tid % 32)
+    double Vl[2][9], Kl[2][9];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int tl = tid / BB + 8 * h, sl = tid % BB;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Vl[h][k] = Kl[h][k] = 0.0;
+        bool touch = false;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
+        bool valid = (sVa[tl][0] >= 0) && (sVb[sl][0] >= 0) && !touch;
+        if (!valid) continue;
+        double SV[6][3], SK[6][3];
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) SV[p][b] = SK[p][b] = 0.0;
+        const double n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double y0 = sY[sl][3 * q], y1 = sY[sl][3 * q + 1], y2 = sY[sl][3 * q + 2];
+            const double wb0 = R.w[q] * R.b[q][0], wb1 = R.w[q] * R.b[q][1], wb2 = R.w[q] * R.b[q][2];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const double d0 = sX[tl][3 * p] - y0, d1 = sX[tl][3 * p + 1] - y1, d2 = sX[tl][3 * p + 2] - y2;
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double ri = rsqrt(r2);
+                const double dn = d0 * n0 + d1 * n1 + d2 * n2;
+                double gv, gk;
+                if (YUK) {
+                    const double r = r2 * ri;
+                    const double e = exp(-kappa * r);
+                    gv = e * ri;
+                    gk = dn * (1.0 + kappa * r) * e * ri * ri * ri;
+                } else {
+                    gv = ri;
+                    gk = dn * ri * ri * ri;
+                }
+                SV[p][0] += wb0 * gv;
+                SV[p][1] += wb1 * gv;
+                SV[p][2] += wb2 * gv;
+                SK[p][0] += wb0 * gk;
+                SK[p][1] += wb1 * gk;
+                SK[p][2] += wb2 * gk;
+            }
+        }
+        const double sc = sAa[tl] * sAb[sl] * INV4PI;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double wa = sc * R.w[p] * R.b[p][a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    Vl[h][3 * a + b] += wa * SV[p][b];
+                    Kl[h][3 * a + b] += wa * SK[p][b];
+                }
+            }
+        }
+    }
+
+    // reduce both operators through the shared tile, V then K
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int tl = tid / BB + 8 * h, sl = tid % BB;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[h][3 * a + b] : Kl[h][3 * a + b];
+        }
+        __syncthreads();
+        double *E = op == 0 ? EV : EK;
+        for (int o = tid; o < nA * nB; o += 256) {
+            const int ia = o / nB, jb = o % nB;
+            double s = 0.0;
+            for (int k = 0; k < MAXS; ++k) {
+                const int sa = sSa[ia][k];
+                if (sa < 0) break;
+                for (int l = 0; l < MAXS; ++l) {
+                    const int sb = sSb[jb][l];
+                    if (sb < 0) break;
+                    s += acc[sa][sb];
+                }
+            }
+            E[(pA - rowbase + ia) * ldE + pB + jb] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. gather passes
+// ---------------------------------------------------------------------------
+// W[i][c] (+)= sum of E rows of vertex i that belong to target blocks [bA0, bA1)
+__global__ void k_bem_pass1(int64_t nv, int64_t SB, const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA,
+                            const int32_t *__restrict__ LA_blk, int64_t bA0, int64_t bA1, int64_t rowbase,
+                            const double *__restrict__ EV, const double *__restrict__ EK, double *__restrict__ WV,
+                            double *__restrict__ WK, int first)
+{
+    const int64_t i = blockIdx.y;
+    const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (c >= SB) return;
+    double sv = 0.0, sk = 0.0;
+    bool any = false;
+    for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) {
+        const int32_t b = LA_blk[e];
+        if (b < bA0 || b >= bA1) continue;
+        const int64_t r = LA[e] - rowbase;
+        sv += EV[r * SB + c];
+        sk += EK[r * SB + c];
+        any = true;
+    }
+    if (first) {
+        WV[i * SB + c] = sv;
+        WK[i * SB + c] = sk;
+    } else if (any) {
+        WV[i * SB + c] += sv;
+        WK[i * SB + c] += sk;
+    }
+}
+
+// B64[i][j] = sK * sum W_K[i][cols of j],  B64[i][nv + j] = sV * sum W_V[i][cols of j]
+__global__ void k_bem_pass2(int64_t nv, int64_t SB, int64_t ld, const int32_t *__restrict__ LB_ptr,
+                            const int32_t *__restrict__ LB, const double *__restrict__ WV,
+                            const double *__restrict__ WK, double sV, double sK, double *__restrict__ Bo)
+{
+    const int64_t i = blockIdx.y;
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j >= nv) return;
+    double v = 0.0, k = 0.0;
+    for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) {
+        v += WV[i * SB + LB[e]];
+        k += WK[i * SB + LB[e]];
+    }
+    Bo[i * ld + j] = sK * k;
+    Bo[i * ld + nv + j] = sV * v;
+}
+
+// ---------------------------------------------------------------------------
+// 3. touching pairs: Sauter-Schwab (Sauter & Schwab, Boundary Element
+//    Methods, Sec. 5.2) on the reference triangle {0 <= xi2 <= xi1 <= 1},
+//    chi(xi) = P0 + xi1 (P1 - P0) + xi2 (P2 - P1), shape functions
+//    (1 - xi1, xi1 - xi2, xi2); vertices reordered so that the shared
+//    vertex is P0 (common vertex) or the shared edge is P0 P1 (common edge).
+// ---------------------------------------------------------------------------
+struct RefPair {
+    double x1, x2, y1, y2;
+};
+
+__device__ inline int ss_region(int kind, int r, double xi, double e1, double e2, double e3, RefPair &m)
+{
+    // returns via m the r-th region map; the Jacobian is applied by the caller
+    if (kind == 3) {
+        switch (r) {
+        case 0: m = {xi, xi * (1 - e1 + e1 * e2), xi * (1 - e1 * e2 * e3), xi * (1 - e1)}; break;
+        case 1: m = {xi * (1 - e1 * e2 * e3), xi * (1 - e1), xi, xi * (1 - e1 + e1 * e2)}; break;
+        case 2: m = {xi, xi * e1 * (1 - e2 + e2 * e3), xi * (1 - e1 * e2), xi * e1 * (1 - e2)}; break;
+        case 3: m = {xi * (1 - e1 * e2), xi * e1 * (1 - e2), xi, xi * e1 * (1 - e2 + e2 * e3)}; break;
+        case 4: m = {xi * (1 - e1 * e2 * e3), xi * e1 * (1 - e2 * e3), xi, xi * e1 * (1 - e2)}; break;
+        default: m = {xi, xi * e1 * (1 - e2), xi * (1 - e1 * e2 * e3), xi * e1 * (1 - e2 * e3)}; break;
+        }
+        return 0;
+    }
+    if (kind == 2) {
+        switch (r) {
+        case 0: m = {xi, xi * e1 * e3, xi * (1 - e1 * e2), xi * e1 * (1 - e2)}; break;
+        case 1: m = {xi, xi * e1, xi * (1 - e1 * e2 * e3), xi * e1 * e2 * (1 - e3)}; break;
+        case 2: m = {xi * (1 - e1 * e2), xi * e1 * (1 - e2), xi, xi * e1 * e2 * e3}; break;
+        case 3: m = {xi * (1 - e1 * e2 * e3), xi * e1 * e2 * (1 - e3), xi, xi * e1}; break;
+        default: m = {xi * (1 - e1 * e2 * e3), xi * e1 * (1 - e2 * e3), xi, xi * e1 * e2}; break;
+        }
+        return 0;
+    }
+    if (r == 0)
+        m = {xi, xi * e1, xi * e2, xi * e2 * e3};
+    else
+        m = {xi * e2, xi * e2 * e3, xi, xi * e1};
+    return 0;
+}
+
+__device__ inline double ss_jac(int kind, int r, double xi, double e1, double e2)
+{
+    const double x3 = xi * xi * xi;
+    if (kind == 3) return x3 * e1 * e1 * e2;
+    if (kind == 2) return r == 0 ? x3 * e1 * e1 : x3 * e1 * e1 * e2;
+    return x3 * e2;
+}
+
+// One wavefront per touching ordered pair (tau, sigma); lanes split the
+// regions x n^4 Gauss points; the 3x3 V and K blocks (in the triangles' own
+// vertex order) go to out[18 * pair].
+template <bool YUK>
+__global__ void __launch_bounds__(256)
+    k_bem_singular(int64_t ntp, const int32_t *__restrict__ tp_tau, const int32_t *__restrict__ tp_sig,
+                   const int32_t *__restrict__ tri, const double *__restrict__ vx, const double *__restrict__ nrm,
+                   const double *__restrict__ area, double kappa, GL4 G, double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t pair = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) >> 6;
+    if (pair >= ntp) return;
+    const int32_t ta = tp_tau[pair], sb = tp_sig[pair];
+    int A[3], B[3];
+    for (int k = 0; k < 3; ++k) {
+        A[k] = tri[3 * ta + k];
+        B[k] = tri[3 * sb + k];
+    }
+    int shared = 0, ia[3] = {0, 0, 0}, ib[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (A[a] == B[b]) {
+                ia[shared] = a;
+                ib[shared] = b;
+                ++shared;
+            }
+    int pa[3], pb[3];
+    if (shared == 3) {
+        pa[0] = pb[0] = 0;
+        pa[1] = pb[1] = 1;
+        pa[2] = pb[2] = 2;
+    } else if (shared == 2) {
+        pa[0] = ia[0];
+        pa[1] = ia[1];
+        pa[2] = 3 - ia[0] - ia[1];
+        pb[0] = ib[0];
+        pb[1] = ib[1];
+        pb[2] = 3 - ib[0] - ib[1];
+    } else {
+        pa[0] = ia[0];
+        pa[1] = (ia[0] + 1) % 3;
+        pa[2] = (ia[0] + 2) % 3;
+        pb[0] = ib[0];
+        pb[1] = (ib[0] + 1) % 3;
+        pb[2] = (ib[0] + 2) % 3;
+    }
+    double P[3][3], Q[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) {
+            P[k][d] = vx[3 * A[pa[k]] + d];
+            Q[k][d] = vx[3 * B[pb[k]] + d];
+        }
+    const double ny0 = nrm[3 * sb], ny1 = nrm[3 * sb + 1], ny2 = nrm[3 * sb + 2];
+    const int nreg = shared == 3 ? 6 : shared == 2 ? 5 : 2;
+    double V[9], K[9];
+    for (int k = 0; k < 9; ++k) V[k] = K[k] = 0.0;
+    const int npt = nreg * 256;
+    for (int idx = lane; idx < npt; idx += 64) {
+        const int r = idx >> 8, pt = idx & 255;
+        const int i0 = pt >> 6, i1 = (pt >> 4) & 3, i2 = (pt >> 2) & 3, i3 = pt & 3;
+        const double xi = G.x[i0], e1 = G.x[i1], e2 = G.x[i2], e3 = G.x[i3];
+        RefPair m;
+        ss_region(shared, r, xi, e1, e2, e3, m);
+        const double w = G.w[i0] * G.w[i1] * G.w[i2] * G.w[i3] * ss_jac(shared, r, xi, e1, e2);
+        double x[3], y[3];
+        for (int d = 0; d < 3; ++d) {
+            x[d] = P[0][d] + m.x1 * (P[1][d] - P[0][d]) + m.x2 * (P[2][d] - P[1][d]);
+            y[d] = Q[0][d] + m.y1 * (Q[1][d] - Q[0][d]) + m.y2 * (Q[2][d] - Q[1][d]);
+        }
+        const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const double ri = rsqrt(r2);
+        double gv, gk;
+        if (YUK) {
+            const double rr = r2 * ri;
+            const double e = exp(-kappa * rr);
+            gv = e * ri;
+            gk = (d0 * ny0 + d1 * ny1 + d2 * ny2) * (1.0 + kappa * rr) * e * ri * ri * ri;
+        } else {
+            gv = ri;
+            gk = (d0 * ny0 + d1 * ny1 + d2 * ny2) * ri * ri * ri;
+        }
+        if (shared == 3) gk = 0.0; // (x - y).n_y vanishes on a flat panel
+        const double fx[3] = {1.0 - m.x1, m.x1 - m.x2, m.x2};
+        const double fy[3] = {1.0 - m.y1, m.y1 - m.y2, m.y2};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double ww = w * fx[a] * fy[b];
+                V[3 * a + b] += ww * gv;
+                K[3 * a + b] += ww * gk;
+            }
+    }
+    for (int k = 0; k < 9; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            V[k] += __shfl_xor(V[k], off);
+            K[k] += __shfl_xor(K[k], off);
+        }
+    if (lane == 0) {
+        const double sc = 4.0 * area[ta] * area[sb] * INV4PI;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                out[18 * pair + 3 * pa[a] + pb[b]] = sc * V[3 * a + b];
+                out[18 * pair + 9 + 3 * pa[a] + pb[b]] = sc * K[3 * a + b];
+            }
+    }
+}
+
+// Row-owned scatter of the touching-pair blocks and of the 1/2 M term.
+__global__ void k_bem_scatter(int64_t nv, int64_t ld, const int32_t *__restrict__ v2t_ptr,
+                              const int32_t *__restrict__ v2t, const int32_t *__restrict__ tri,
+                              const int32_t *__restrict__ tp_ptr, const int32_t *__restrict__ tp_sig,
+                              const double *__restrict__ tpv, const double *__restrict__ area, double sV, double sK,
+                              double *__restrict__ Bo)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    double *row = Bo + i * ld;
+    for (int32_t e = v2t_ptr[i]; e < v2t_ptr[i + 1]; ++e) {
+        const int32_t ta = v2t[e] / 3, a = v2t[e] % 3;
+        for (int32_t pp = tp_ptr[ta]; pp < tp_ptr[ta + 1]; ++pp) {
+            const int32_t sb = tp_sig[pp];
+            const double *blk = tpv + 18 * int64_t(pp);
+            for (int b = 0; b < 3; ++b) {
+                const int32_t j = tri[3 * sb + b];
+                row[nv + j] += sV * blk[3 * a + b];
+                row[j] += sK * blk[9 + 3 * a + b];
+            }
+        }
+        for (int b = 0; b < 3; ++b) row[tri[3 * ta + b]] += 0.5 * area[ta] * (a == b ? 2.0 : 1.0) / 12.0;
+    }
+}
+
+__global__ void k_gather_coords(int64_t nv, const int32_t *__restrict__ g, const double *__restrict__ x,
+                                double *__restrict__ vx)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    for (int d = 0; d < 3; ++d) vx[3 * i + d] = x[3 * g[i] + d];
+}
+
+__global__ void k_diag_and_narrow(int64_t nv, int64_t ld, int64_t ld_out, const double *__restrict__ B64,
+                                  double *__restrict__ vdiag, float *__restrict__ B32)
+{
+    const int64_t i = blockIdx.y;
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j == 0) vdiag[i] = B64[i * ld + nv + i];
+    if (B32 && j < ld_out) B32[i * ld_out + j] = j < 2 * nv ? float(B64[i * ld + j]) : 0.0f;
+}
+
+// ===========================================================================
+// host orchestration
+// ===========================================================================
+int64_t bem_ld(int64_t nv) { return ((2 * nv + 255) / 256) * 256; }
+
+void ensure_bem(Problem &p, int w, hipStream_t s)
+{
+    if (p.bem_ready[w]) return;
+    ensure_geometry(p, s);
+    SurfaceTopo &T = p.topo[w];
+    SurfaceDev &S = p.surf[w];
+    Arena &A = p.bem_arena[w];
+    A.release();
+    const bool yuk = (w == 1) && p.kappa > 0.0;
+    const double kappa = (w == 1) ? p.kappa : 0.0;
+    // Morton copies and block tables
+    S.m_tri = A.alloc<int32_t>(3 * T.nt);
+    S.m_qp = A.alloc<double>(18 * T.nt);
+    S.m_nrm = A.alloc<double>(3 * T.nt);
+    S.m_area = A.alloc<double>(T.nt);
+    int32_t *d_morton = A.upload(T.morton, s);
+    hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, d_morton, S.tri, S.qp, S.nrm,
+                       S.area, S.m_tri, S.m_qp, S.m_nrm, S.m_area);
+    S.A_pref = A.upload(T.A_pref, s);
+    S.A_nv = A.upload(T.A_nv, s);
+    S.A_slots = A.upload(T.A_slots, s);
+    S.B_pref = A.upload(T.B_pref, s);
+    S.B_nv = A.upload(T.B_nv, s);
+    S.B_slots = A.upload(T.B_slots, s);
+    S.LA_ptr = A.upload(T.LA_ptr, s);
+    S.LA = A.upload(T.LA, s);
+    S.LA_blk = A.upload(T.LA_blk, s);
+    S.LB_ptr = A.upload(T.LB_ptr, s);
+    S.LB = A.upload(T.LB, s);
+    S.tp_ptr = A.upload(T.tp_ptr, s);
+    S.tp_sig = A.upload(T.tp_sig, s);
+    S.nbA = T.nbA;
+    S.nbB = T.nbB;
+    S.SA = T.SA;
+    S.SB = T.SB;
+    S.ntp = int64_t(T.tp_sig.size());
+    std::vector<int32_t> tp_tau(S.ntp);
+    for (int64_t t = 0; t < T.nt; ++t)
+        for (int32_t k = T.tp_ptr[t]; k < T.tp_ptr[t + 1]; ++k) tp_tau[k] = int32_t(t);
+    int32_t *d_tptau = A.upload(tp_tau, s);
+
+    const int64_t nv = T.nv, ld = bem_ld(nv);
+    // FP64 storage assembles in place; mixed precision assembles in an FP64
+    // scratch copy and narrows at the end
+    double *B64 = p.precision == PBFB_MIXED ? scratch<double>(p, SCR_B64, nv * ld) : A.alloc<double>(nv * ld);
+    double *WV = scratch<double>(p, SCR_W0, nv * T.SB);
+    double *WK = scratch<double>(p, SCR_W1, nv * T.SB);
+    // chunk the target blocks so that E stays within ~8 GB per operator
+    const int64_t max_rows = std::max<int64_t>(BA * 3, (int64_t(1) << 30) / std::max<int64_t>(T.SB, 1));
+    QRule6 R = q6arg();
+    int64_t b0 = 0;
+    bool first = true;
+    while (b0 < T.nbA) {
+        int64_t b1 = b0;
+        while (b1 < T.nbA && T.A_pref[b1 + 1] - T.A_pref[b0] <= max_rows) ++b1;
+        if (b1 == b0) b1 = b0 + 1;
+        const int64_t rows = T.A_pref[b1] - T.A_pref[b0];
+        double *EV = scratch<double>(p, SCR_E0, rows * T.SB);
+        double *EK = scratch<double>(p, SCR_E1, rows * T.SB);
+        dim3 grid(unsigned(T.nbB), unsigned(b1 - b0));
+        if (p.timing) p.timer.begin(T_ASM, s);
+        if (yuk)
+            hipLaunchKernelGGL(k_bem_regular<true>, grid, dim3(256), 0, s, T.nt, S.m_tri, S.m_qp, S.m_nrm, S.m_area,
+                               S.A_pref, S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]),
+                               EV, EK, T.SB, kappa, R);
+        else
+            hipLaunchKernelGGL(k_bem_regular<false>, grid, dim3(256), 0, s, T.nt, S.m_tri, S.m_qp, S.m_nrm, S.m_area,
+                               S.A_pref, S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]),
+                               EV, EK, T.SB, kappa, R);
+        if (p.timing) p.timer.end(s);
+        PB_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_bem_pass1, dim3(nblk(T.SB, 256), unsigned(nv)), dim3(256), 0, s, nv, T.SB, S.LA_ptr,
+                           S.LA, S.LA_blk, b0, b1, int64_t(T.A_pref[b0]), EV, EK, WV, WK, first ? 1 : 0);
+        PB_HIP(hipGetLastError());
+        first = false;
+        b0 = b1;
+    }
+    release_scratch(p, SCR_E0);
+    release_scratch(p, SCR_E1);
+    const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
+    PB_HIP(hipMemsetAsync(B64, 0, sizeof(double) * nv * ld, s));
+    hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, T.SB, ld, S.LB_ptr, S.LB,
+                       WV, WK, sV, sK, B64);
+    PB_HIP(hipGetLastError());
+    release_scratch(p, SCR_W0);
+    release_scratch(p, SCR_W1);
+    // touching pairs
+    double *vx = scratch<double>(p, SCR_VX, 3 * nv);
+    hipLaunchKernelGGL(k_gather_coords, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, S.g, p.d_x, vx);
+    double *tpv = scratch<double>(p, SCR_TPVAL, 18 * S.ntp);
+    GL4 G = gl4arg();
+    if (p.timing) p.timer.begin(T_SING, s);
+    if (yuk)
+        hipLaunchKernelGGL(k_bem_singular<true>, dim3(nblk(S.ntp * 64, 256)), dim3(256), 0, s, S.ntp, d_tptau,
+                           S.tp_sig, S.tri, vx, S.nrm, S.area, kappa, G, tpv);
+    else
+        hipLaunchKernelGGL(k_bem_singular<false>, dim3(nblk(S.ntp * 64, 256)), dim3(256), 0, s, S.ntp, d_tptau,
+                           S.tp_sig, S.tri, vx, S.nrm, S.area, kappa, G, tpv);
+    if (p.timing) p.timer.end(s);
+    PB_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bem_scatter, dim3(nblk(nv, 64)), dim3(64), 0, s, nv, ld, S.v2t_ptr, S.v2t, S.tri, S.tp_ptr,
+                       S.tp_sig, tpv, S.area, sV, sK, B64);
+    PB_HIP(hipGetLastError());
+    // final storage
+    S.vdiag = A.alloc<double>(nv);
+    if (p.precision == PBFB_MIXED) {
+        float *B32 = A.alloc<float>(nv * ld);
+        hipLaunchKernelGGL(k_diag_and_narrow, dim3(nblk(ld, 256), unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64,
+                           S.vdiag, B32);
+        S.B = B32;
+        PB_HIP(hipStreamSynchronize(s));
+        release_scratch(p, SCR_B64);
+    } else {
+        hipLaunchKernelGGL(k_diag_and_narrow, dim3(1, unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64, S.vdiag,
+                           (float *)nullptr);
+        S.B = B64;
+    }
+    PB_HIP(hipGetLastError());
+    release_scratch(p, SCR_TPVAL);
+    p.bem_ready[w] = true;
+}
+
+void ensure_all(Problem &p, hipStream_t s)
+{
+    ensure_geometry(p, s);
+    ensure_rhs(p, s);
+    ensure_bem(p, 0, s);
+    ensure_bem(p, 1, s);
+}
+
+} // namespace pbfb

@@ -1,0 +1,228 @@
+// Internal declarations of the pbfb library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pbfb.h"
+
+namespace pbfb {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+
+struct Error {
+    pbfb_status code;
+    std::string msg;
+};
+
+#define PB_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            throw ::pbfb::Error{e_ == hipErrorOutOfMemory ? PBFB_ENOMEM : PBFB_EDEVICE,                \
+                                std::string(#call) + ": " + hipGetErrorString(e_)};                   \
+    } while (0)
+
+#define PB_CHECK(cond, code, msg)                                                                      \
+    do {                                                                                               \
+        if (!(cond)) throw ::pbfb::Error{code, msg};                                                   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// quadrature rules (host copies; kernels receive them through constant memory)
+// ---------------------------------------------------------------------------
+struct Rules {
+    double tri_bary[6][3], tri_w[6];   // symmetric degree-4 triangle rule, weights sum to 1
+    double tet_bary[27][4], tet_w[27]; // conical product rule, degree 5, weights sum to 1
+    double gl_x[4], gl_w[4];           // Gauss-Legendre on [0,1], Sauter-Schwab directions
+};
+const Rules &rules();
+void upload_rules(hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device memory owned by a problem
+// ---------------------------------------------------------------------------
+struct Arena {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    template <class T> T *alloc(size_t n) {
+        void *p = nullptr;
+        size_t b = sizeof(T) * (n ? n : 1);
+        PB_HIP(hipMalloc(&p, b));
+        ptrs.push_back(p);
+        bytes += b;
+        return static_cast<T *>(p);
+    }
+    template <class T> T *upload(const std::vector<T> &v, hipStream_t s) {
+        T *d = alloc<T>(v.size());
+        if (!v.empty()) PB_HIP(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+        return d;
+    }
+    void release();
+    ~Arena() { release(); }
+};
+
+// block sizes of the regular assembly (target x source triangles per workgroup)
+constexpr int BA = 16;
+constexpr int BB = 32;
+constexpr int MAXS = 12; // slots per local vertex in a block (max triangles of a block at one vertex)
+
+// host-side topology of one boundary surface
+struct SurfaceTopo {
+    int64_t nv = 0, nt = 0;
+    std::vector<int32_t> g;            // local vertex -> FEM node (ascending)
+    std::vector<int32_t> tri;          // 3*nt local vertex ids, original order
+    std::vector<int32_t> v2t_ptr, v2t; // vertex -> (tri*3 + local index)
+    std::vector<int32_t> morton;       // Morton position -> triangle id
+    // regular-assembly blocks (over Morton-ordered triangles)
+    int64_t nbA = 0, nbB = 0, SA = 0, SB = 0;
+    std::vector<int32_t> A_pref, A_nv, A_loc, A_slots; // A_loc: 3 per Morton position
+    std::vector<int32_t> B_pref, B_nv, B_loc, B_slots;
+    std::vector<int32_t> LA_ptr, LA, LA_blk; // vertex -> expanded rows (and their A block)
+    std::vector<int32_t> LB_ptr, LB;         // vertex -> expanded columns
+    // touching pairs (tau, sigma) sharing at least one vertex, grouped by tau
+    std::vector<int32_t> tp_ptr, tp_sig;
+};
+
+struct SurfaceDev {
+    int64_t nv = 0, nt = 0;
+    int32_t *g = nullptr, *tri = nullptr, *v2t_ptr = nullptr, *v2t = nullptr;
+    double *qp = nullptr, *nrm = nullptr, *area = nullptr; // original order: 18, 3, 1 per triangle
+    // Morton-ordered triangle data for the regular assembly
+    int32_t *m_tri = nullptr;
+    double *m_qp = nullptr, *m_nrm = nullptr, *m_area = nullptr;
+    int32_t *A_pref = nullptr, *A_nv = nullptr, *A_loc = nullptr, *A_slots = nullptr;
+    int32_t *B_pref = nullptr, *B_nv = nullptr, *B_loc = nullptr, *B_slots = nullptr;
+    int32_t *LA_ptr = nullptr, *LA = nullptr, *LA_blk = nullptr, *LB_ptr = nullptr, *LB = nullptr;
+    int64_t nbA = 0, nbB = 0, SA = 0, SB = 0;
+    int32_t *tp_ptr = nullptr, *tp_sig = nullptr;
+    int64_t ntp = 0;
+    int32_t *cslot = nullptr; // CSR slot of the coupling entry per (v2t entry, b)
+    // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
+    void *B = nullptr;
+    double *vdiag = nullptr; // diagonal of the signed single-layer block V'
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+};
+
+enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_NCLASS = 5 };
+
+struct EventTimer {
+    std::vector<hipEvent_t> ev;   // pairs
+    std::vector<int> cls;         // class of each recorded pair
+    int used = 0;
+    double sum_ms[T_NCLASS] = {0};
+    int64_t cnt[T_NCLASS] = {0};
+    void begin(int c, hipStream_t s);
+    void end(hipStream_t s);
+    void drain();
+    void destroy();
+};
+
+enum ScratchSlot {
+    SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_E0, SCR_E1, SCR_W0, SCR_W1,
+    SCR_TPVAL, SCR_B64, SCR_VX, SCR_TPTAU,
+    SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
+    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_N
+};
+
+struct ScratchBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Problem {
+    Ctx *ctx = nullptr;
+    int precision = PBFB_FP64;
+    bool have_mesh = false, have_charges = false, have_params = false;
+    bool geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
+    // host copies
+    int64_t nn = 0, ntet = 0, nq = 0;
+    std::vector<double> x;
+    std::vector<int32_t> tet;
+    std::vector<double> q; // 4 per charge: x, y, z, valence
+    SurfaceTopo topo[2];
+    double eps_m = 0, eps_s = 0, kappa = 0, temp = 298.15, lB = 0, kT = 0;
+    // device
+    Arena mesh_arena, bem_arena[2];
+    ScratchBuf scr[SCR_N];
+    double *d_x = nullptr, *d_tgeo = nullptr, *d_q = nullptr;
+    int32_t *d_tet = nullptr, *d_n2t_ptr = nullptr, *d_n2t = nullptr, *d_slot4 = nullptr;
+    int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr;
+    double *d_val0 = nullptr, *d_val = nullptr;
+    float *d_val32 = nullptr;
+    int64_t nnz = 0;
+    double *d_b = nullptr; // right-hand side, length n
+    SurfaceDev surf[2];
+    int64_t n() const { return nn + topo[0].nv + topo[1].nv; }
+    // timers
+    bool timing = false;
+    EventTimer timer;
+    hipStream_t last_stream = nullptr;
+};
+
+// reusable device scratch buffers, grown on demand (hipFree synchronises)
+void *scratch_bytes(Problem &p, int slot, size_t bytes);
+template <class T> T *scratch(Problem &p, int slot, size_t n)
+{
+    return static_cast<T *>(scratch_bytes(p, slot, sizeof(T) * (n ? n : 1)));
+}
+void release_scratch(Problem &p, int slot);
+void release_all_scratch(Problem &p);
+
+// host preprocessing (setup.hip)
+void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri);
+void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
+                        std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,
+                        std::vector<int32_t> &diag, std::vector<int32_t> cslot[2]);
+
+// device setup and operators (kernels_*.hip, solver.hip)
+void ensure_geometry(Problem &p, hipStream_t s);
+void ensure_rhs(Problem &p, hipStream_t s);
+void ensure_bem(Problem &p, int surf, hipStream_t s);
+void ensure_all(Problem &p, hipStream_t s);
+
+// FEM element kernels (row gather over the tets around each node)
+void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t s); // d_val = A + J(u)
+void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s);
+void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN,
+                     double *rJ, double *rH, hipStream_t s);
+double fem_energy_integral(Problem &p, const double *u_lin, const double *u_nl, hipStream_t s);
+
+// coupled operator y = J x with the current CSR values (pack + GEMV + SpMV)
+void coupled_apply(Problem &p, const double *x, double *y, hipStream_t s);
+void coupled_apply_linear(Problem &p, const double *x, double *y, hipStream_t s); // A only (no J_N)
+
+// vector helpers
+int64_t bem_ld(int64_t nv); // padded row length of the dense surface operator
+void vec_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+void vec_mul(int64_t n, const double *a, const double *x, double *y, hipStream_t s);
+void vec_add(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
+double dot(Problem &p, const double *a, const double *b, int64_t n, hipStream_t s);
+void dots(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out, hipStream_t s);
+
+// energy
+void energy(Problem &p, const double *phi_lin, const double *phi_nl, double out[4], hipStream_t s);
+
+// solver
+int gmres(Problem &p, int scheme_for_diag, const double *u_for_diag, const double *b, double *x, double tol,
+          int restart, int maxit, int *iters, hipStream_t s);
+pbfb_status solve(Problem &p, const pbfb_solve_opts &o, pbfb_result &res, double *phi_out_dev, hipStream_t s);
+
+} // namespace pbfb
+
+struct pbfb_ctx {
+    pbfb::Ctx c;
+};
+struct pbfb_problem {
+    pbfb::Problem p;
+};

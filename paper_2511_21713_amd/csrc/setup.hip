@@ -1,0 +1,245 @@
+// Host-side topology preprocessing: surfaces, adjacency, Morton blocks for the
+// regular boundary-element assembly, touching panel pairs and the FEM CSR
+// pattern.  Integer work only; every floating-point quantity of the method is
+// computed on the device.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <unordered_map>
+
+#include "pbfb_internal.hpp"
+
+namespace pbfb {
+
+static uint32_t spread10(uint32_t v)
+{
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Blocks of `bs` consecutive Morton-ordered triangles: unique local vertex
+// lists, each triangle corner's local index, and for every local vertex the
+// (triangle-in-block * 3 + corner) slots that touch it.
+static void make_blocks(const SurfaceTopo &S, int bs, int64_t &nb, int64_t &total, std::vector<int32_t> &pref,
+                        std::vector<int32_t> &nvb, std::vector<int32_t> &loc, std::vector<int32_t> &slots,
+                        std::vector<std::vector<std::pair<int32_t, int32_t>>> &vlist)
+{
+    nb = (S.nt + bs - 1) / bs;
+    pref.assign(nb + 1, 0);
+    nvb.assign(nb, 0);
+    loc.assign(nb * bs * 3, -1);
+    vlist.assign(S.nv, {});
+    std::vector<std::vector<int32_t>> blk_verts(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        std::vector<int32_t> vs;
+        for (int k = 0; k < bs; ++k) {
+            int64_t m = b * bs + k;
+            if (m >= S.nt) break;
+            int32_t t = S.morton[m];
+            for (int a = 0; a < 3; ++a) vs.push_back(S.tri[3 * t + a]);
+        }
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        blk_verts[b] = vs;
+        nvb[b] = (int32_t)vs.size();
+        pref[b + 1] = pref[b] + nvb[b];
+    }
+    total = pref[nb];
+    slots.assign(total * MAXS, -1);
+    for (int64_t b = 0; b < nb; ++b) {
+        const auto &vs = blk_verts[b];
+        std::vector<int> fill(vs.size(), 0);
+        for (int k = 0; k < bs; ++k) {
+            int64_t m = b * bs + k;
+            if (m >= S.nt) break;
+            int32_t t = S.morton[m];
+            for (int a = 0; a < 3; ++a) {
+                int32_t v = S.tri[3 * t + a];
+                int32_t li = int32_t(std::lower_bound(vs.begin(), vs.end(), v) - vs.begin());
+                loc[m * 3 + a] = li;
+                PB_CHECK(fill[li] < MAXS, PBFB_EMESH, "vertex valence too high for the assembly blocks");
+                slots[(int64_t(pref[b]) + li) * MAXS + fill[li]++] = k * 3 + a;
+            }
+        }
+        for (size_t li = 0; li < vs.size(); ++li) vlist[vs[li]].push_back({pref[b] + int32_t(li), int32_t(b)});
+    }
+}
+
+void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
+{
+    SurfaceTopo &S = p.topo[which];
+    S = SurfaceTopo();
+    S.nt = ntri;
+    PB_CHECK(ntri >= 4, PBFB_EMESH, "surface needs at least 4 triangles");
+    std::vector<int32_t> loc(p.nn, -1);
+    for (int64_t k = 0; k < 3 * ntri; ++k) {
+        PB_CHECK(tri[k] >= 0 && tri[k] < p.nn, PBFB_EINVAL, "surface triangle references a node out of range");
+        loc[tri[k]] = 0;
+    }
+    for (int64_t i = 0; i < p.nn; ++i)
+        if (loc[i] == 0) {
+            loc[i] = int32_t(S.g.size());
+            S.g.push_back(int32_t(i));
+        }
+    S.nv = int64_t(S.g.size());
+    S.tri.resize(3 * ntri);
+    for (int64_t k = 0; k < 3 * ntri; ++k) S.tri[k] = loc[tri[k]];
+    // closed oriented 2-manifold: every directed edge once, with its reverse
+    {
+        std::vector<uint64_t> e;
+        e.reserve(3 * ntri);
+        for (int64_t t = 0; t < ntri; ++t)
+            for (int a = 0; a < 3; ++a) {
+                uint32_t i = S.tri[3 * t + a], j = S.tri[3 * t + (a + 1) % 3];
+                PB_CHECK(i != j, PBFB_EMESH, "degenerate surface triangle");
+                e.push_back((uint64_t(i) << 32) | j);
+            }
+        std::vector<uint64_t> es = e;
+        std::sort(es.begin(), es.end());
+        PB_CHECK(std::adjacent_find(es.begin(), es.end()) == es.end(), PBFB_EMESH,
+                 "surface has a repeated directed edge (non-manifold or inconsistent orientation)");
+        for (uint64_t k : e) {
+            uint64_t r = (k << 32) | (k >> 32);
+            PB_CHECK(std::binary_search(es.begin(), es.end(), r), PBFB_EMESH, "surface is not closed");
+        }
+    }
+    // vertex -> triangles
+    S.v2t_ptr.assign(S.nv + 1, 0);
+    for (int64_t k = 0; k < 3 * ntri; ++k) S.v2t_ptr[S.tri[k] + 1]++;
+    for (int64_t i = 0; i < S.nv; ++i) S.v2t_ptr[i + 1] += S.v2t_ptr[i];
+    S.v2t.resize(3 * ntri);
+    {
+        std::vector<int32_t> fill(S.v2t_ptr.begin(), S.v2t_ptr.end() - 1);
+        for (int64_t t = 0; t < ntri; ++t)
+            for (int a = 0; a < 3; ++a) S.v2t[fill[S.tri[3 * t + a]]++] = int32_t(t * 3 + a);
+    }
+    // Morton order of triangle centroids
+    {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < S.nv; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], p.x[3 * S.g[i] + d]);
+                hi[d] = std::max(hi[d], p.x[3 * S.g[i] + d]);
+            }
+        double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-30});
+        std::vector<std::pair<uint32_t, int32_t>> key(ntri);
+        for (int64_t t = 0; t < ntri; ++t) {
+            uint32_t code = 0;
+            for (int d = 0; d < 3; ++d) {
+                double c = 0;
+                for (int a = 0; a < 3; ++a) c += p.x[3 * S.g[S.tri[3 * t + a]] + d];
+                c = (c / 3.0 - lo[d]) / span;
+                code |= spread10(uint32_t(std::min(1023.0, std::max(0.0, c * 1023.0)))) << d;
+            }
+            key[t] = {code, int32_t(t)};
+        }
+        std::sort(key.begin(), key.end());
+        S.morton.resize(ntri);
+        for (int64_t m = 0; m < ntri; ++m) S.morton[m] = key[m].second;
+    }
+    // assembly blocks and vertex -> expanded row/column lists
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> vlA, vlB;
+    make_blocks(S, BA, S.nbA, S.SA, S.A_pref, S.A_nv, S.A_loc, S.A_slots, vlA);
+    make_blocks(S, BB, S.nbB, S.SB, S.B_pref, S.B_nv, S.B_loc, S.B_slots, vlB);
+    S.LA_ptr.assign(S.nv + 1, 0);
+    S.LB_ptr.assign(S.nv + 1, 0);
+    for (int64_t i = 0; i < S.nv; ++i) {
+        S.LA_ptr[i + 1] = S.LA_ptr[i] + int32_t(vlA[i].size());
+        S.LB_ptr[i + 1] = S.LB_ptr[i] + int32_t(vlB[i].size());
+        for (auto &e : vlA[i]) {
+            S.LA.push_back(e.first);
+            S.LA_blk.push_back(e.second);
+        }
+        for (auto &e : vlB[i]) S.LB.push_back(e.first);
+    }
+    // touching pairs, grouped by the first triangle
+    S.tp_ptr.assign(ntri + 1, 0);
+    S.tp_sig.clear();
+    std::vector<int32_t> nb;
+    for (int64_t t = 0; t < ntri; ++t) {
+        nb.clear();
+        for (int a = 0; a < 3; ++a) {
+            int32_t v = S.tri[3 * t + a];
+            for (int32_t e = S.v2t_ptr[v]; e < S.v2t_ptr[v + 1]; ++e) nb.push_back(S.v2t[e] / 3);
+        }
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        S.tp_sig.insert(S.tp_sig.end(), nb.begin(), nb.end());
+        S.tp_ptr[t + 1] = int32_t(S.tp_sig.size());
+    }
+}
+
+void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
+                        std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,
+                        std::vector<int32_t> &diag, std::vector<int32_t> cslot[2])
+{
+    const int64_t nn = p.nn, nt = p.ntet;
+    n2t_ptr.assign(nn + 1, 0);
+    for (int64_t k = 0; k < 4 * nt; ++k) n2t_ptr[p.tet[k] + 1]++;
+    for (int64_t i = 0; i < nn; ++i) n2t_ptr[i + 1] += n2t_ptr[i];
+    n2t.resize(4 * nt);
+    {
+        std::vector<int32_t> fill(n2t_ptr.begin(), n2t_ptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int a = 0; a < 4; ++a) n2t[fill[p.tet[4 * t + a]]++] = int32_t(t * 4 + a);
+    }
+    // local surface ids of FEM nodes
+    std::vector<int32_t> loc[2];
+    for (int w = 0; w < 2; ++w) {
+        loc[w].assign(nn, -1);
+        for (int64_t i = 0; i < p.topo[w].nv; ++i) loc[w][p.topo[w].g[i]] = int32_t(i);
+    }
+    const int64_t off[2] = {nn, nn + p.topo[0].nv};
+    rowptr.assign(nn + 1, 0);
+    col.clear();
+    std::vector<int32_t> cols;
+    for (int64_t a = 0; a < nn; ++a) {
+        cols.clear();
+        for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
+            int32_t t = n2t[e] / 4;
+            for (int b = 0; b < 4; ++b) cols.push_back(p.tet[4 * t + b]);
+        }
+        for (int w = 0; w < 2; ++w) {
+            int32_t i = loc[w][a];
+            if (i < 0) continue;
+            const SurfaceTopo &S = p.topo[w];
+            for (int32_t e = S.v2t_ptr[i]; e < S.v2t_ptr[i + 1]; ++e) {
+                int32_t t = S.v2t[e] / 3;
+                for (int b = 0; b < 3; ++b) cols.push_back(int32_t(off[w] + S.tri[3 * t + b]));
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        col.insert(col.end(), cols.begin(), cols.end());
+        rowptr[a + 1] = int32_t(col.size());
+    }
+    auto find = [&](int64_t row, int64_t c) {
+        auto b = col.begin() + rowptr[row], e = col.begin() + rowptr[row + 1];
+        auto it = std::lower_bound(b, e, int32_t(c));
+        return int32_t(it - col.begin());
+    };
+    slot4.resize(4 * n2t.size());
+    for (int64_t a = 0; a < nn; ++a)
+        for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
+            int32_t t = n2t[e] / 4;
+            for (int b = 0; b < 4; ++b) slot4[4 * int64_t(e) + b] = find(a, p.tet[4 * t + b]);
+        }
+    diag.resize(nn);
+    for (int64_t a = 0; a < nn; ++a) diag[a] = find(a, a);
+    for (int w = 0; w < 2; ++w) {
+        const SurfaceTopo &S = p.topo[w];
+        cslot[w].resize(3 * S.v2t.size());
+        for (int64_t i = 0; i < S.nv; ++i)
+            for (int32_t e = S.v2t_ptr[i]; e < S.v2t_ptr[i + 1]; ++e) {
+                int32_t t = S.v2t[e] / 3;
+                for (int b = 0; b < 3; ++b) cslot[w][3 * int64_t(e) + b] = find(S.g[i], off[w] + S.tri[3 * t + b]);
+            }
+    }
+}
+
+} // namespace pbfb
