@@ -1,0 +1,239 @@
+#!/usr/bin/env python
+"""Benchmark of the nonlinear Poisson-Boltzmann FEM-BEM hot path on one MI355X.
+
+One step = one complete solve of the RNA-like workload (20480 triangles per
+interface, 614400 shell tets, 48 helix + 400 partial charges, kappa = 0.125):
+device setup from the resident mesh (geometry, FEM values, Coulomb load, dense
+Laplace and Yukawa Galerkin operators with touching-panel integrals), the
+linear solve, cubic-start Newton with the self-adjusted relaxation factor,
+and the energy.  The host-side mesh topology and the mesh upload happen
+before the timed region (inputs resident in HBM).
+
+Prints one JSON line: PB solves/s (FP64 path, the workload's precision),
+coupled-operator GFLOP/s, step latency p50/p99, the mixed-precision leg and
+its energy error against the FP64 path, the roofline of the dense GEMV (the
+dominant kernel) from HIP events, and the CPU oracle baseline.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of k_gemv_f64 on this workload from the two rocprofv3
+# --pmc runs (FETCH_SIZE then WRITE_SIZE, each scaled by the factor the same
+# counter reads for a copy of known size), valid for the kernel source whose
+# hash is recorded with it; see profiles/gemv_f64_rna20k_hbm_counters.md.
+GEMV_TRAFFIC = {"config": 1, "src_sha256_16": "9547680e12ff9b82", "bytes": 3.4010e9 + 1.84e5}
+
+
+def gemv_source_hash():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2511_21713_amd", "csrc", "kernels_la.hip")).read()
+    a, b = src.index("k_gemv_f64("), src.index("// FP32 storage, FP64 accumulation")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def gemv_bytes(nm, ns, elem):
+    # algorithmic bytes of one dense launch: both [K'|V'] operators (n x 2n),
+    # their packed FP64 inputs (2n) and FP64 outputs (n)
+    return sum(n * 2 * n * elem + 2 * n * 8 + n * 8 for n in (nm, ns))
+
+
+def apply_flops(nm, ns, nnz):
+    return 2 * (nm * 2 * nm + ns * 2 * ns) + 2 * nnz
+
+
+def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
+    ctx = pb.Context(0)
+    g = pb.Problem.from_inputs(ctx, prob, precision=precision)
+    t0 = time.perf_counter()
+    g.setup()
+    progress(f"{label}: first setup (topology + upload + assembly) {time.perf_counter() - t0:.2f} s, "
+             f"device bytes {g.hbm() / 1e9:.2f} GB")
+    for w in range(warmup):
+        g.reset_operators()
+        r = g.solve(check=False, **opts)
+        progress(f"{label}: warmup {w}: total {r['total']:.6f} kcal/mol, newton {r['newton_iters']}, "
+                 f"gmres {r['gmres_iters_total']}, status {r['status']}, {r['t_setup_s'] + r['t_solve_s']:.3f} s")
+    g.timing_enable(True)
+    g.timing(0, reset=True)
+    lat, res = [], None
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        g.reset_operators()
+        res = g.solve(check=False, **opts)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        progress(f"{label}: step {k}: {lat[-1]:.3f} s (setup {res['t_setup_s']:.3f}, solve {res['t_solve_s']:.3f}), "
+                 f"newton {res['newton_iters']}, gmres {res['gmres_iters_total']}, total {res['total']:.8f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    tm = {name: g.timing(i) for i, name in enumerate(["apply", "gemv", "spmv", "assembly", "singular"])}
+    g.timing_enable(False)
+    out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm())
+    g.close()
+    ctx.close()
+    return out
+
+
+def cpu_baseline(prob, applies_per_solve, seed=0):
+    """Oracle timed on a bounded sample of the same workload, extrapolated to
+    one solve: sampled dense Galerkin rows (assembly), the oracle's dense row
+    loop on those rows, and its matrix-free FEM products."""
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Oracle.from_problem(prob)
+    rng = np.random.default_rng(seed)
+    nrows = 32 * max(1, threads)
+    t_asm = t_dense = 0.0
+    x = rng.standard_normal(o.n)
+    for surf, nv in ((0, o.n_m), (1, o.n_s)):
+        rows = np.sort(rng.choice(nv, size=nrows, replace=False))
+        t0 = time.perf_counter()
+        V, K = o.bem_rows(surf, rows)
+        t_asm += (time.perf_counter() - t0) * nv / nrows
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            o.dense_rows_apply(surf, V, K, x)
+        t_dense += (time.perf_counter() - t0) / reps * nv / nrows
+    t0 = time.perf_counter()
+    for _ in range(3):
+        o.fem_jacobian(oracle.HS, x, x)
+    t_fem = (time.perf_counter() - t0) / 3
+    t_solve = t_asm + applies_per_solve * (t_dense + t_fem)
+    sample = (f"{nrows} Galerkin rows per interface assembled, their dense row products x20, 3 FEM Jacobian "
+              f"products; extrapolated to one solve = assembly of all rows + {applies_per_solve} coupled applies "
+              f"(the GPU run's count); assembly {t_asm:.1f} s, dense apply {t_dense * 1e3:.1f} ms, "
+              f"FEM product {t_fem * 1e3:.1f} ms")
+    return dict(value=1.0 / t_solve, unit="PB solves/s", cores=threads, kind="oracle", sample=sample)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-gb", type=float, default=0.0,
+                    help="run one device copy of this size first (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU row-block sharding is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2511_21713_amd as pb
+    import pbgen
+    assert torch.cuda.is_available()
+    if args.calib_copy_gb > 0:
+        n = int(args.calib_copy_gb * 1e9 / 8)
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        progress(f"calibration copy of {n * 8 / 1e9:.3f} GB done")
+    t0 = time.perf_counter()
+    prob = pbgen.make_config(args.config)
+    progress(f"generated workload {args.config} in {time.perf_counter() - t0:.1f} s: {prob.nodes.shape[0]} nodes, "
+             f"{prob.tets.shape[0]} tets, {prob.tri_m.shape[0]} triangles per interface, {prob.q_z.size} charges")
+    opts = dict()  # cubic start, self-adjusted omega, App. B settings (library defaults)
+    if args.config == 0:
+        opts = dict(omega_auto=0, omega_fixed=0.5)
+    f64 = run_leg(pb, torch, prob, pb.FP64, args.steps, args.warmup, opts, "fp64")
+    K = args.steps
+    value = K / f64["elapsed"]
+    ms_step = 1e3 * f64["elapsed"] / K
+    nm, ns = f64["n_m"], f64["n_s"]
+    nnz_est = None
+    gemv_ms, gemv_cnt = f64["timing"]["gemv"]
+    apply_ms, apply_cnt = f64["timing"]["apply"]
+    asm_ms, asm_cnt = f64["timing"]["assembly"]
+    gb = gemv_bytes(nm, ns, 8)
+    achieved = gb / (gemv_ms * 1e-3) / 1e9 if gemv_ms else None
+    res = f64["res"]
+    applies = apply_cnt // K if K else 0
+    out = {
+        "metric": "PB solves/s + coupled-operator GFLOP/s, mixed vs FP64 at <=1e-5 rel energy; p50/p99",
+        "value": value,
+        "unit": "PB solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"RNA-like solute (config {args.config}): {prob.tri_m.shape[0]} triangles per "
+                               f"interface, {prob.tets.shape[0]} shell tets, {prob.q_z.size} charges, kappa "
+                               f"{prob.kappa}, cubic-start Newton with self-adjusted relaxation, FP64",
+                   "unknowns": f64["n"], "parallelism": "single GPU"},
+        "latency_s": {"p50": percentile(f64["lat"], 0.5), "p99": percentile(f64["lat"], 0.99)},
+        "solve": {"total_kcal_mol": res["total"], "lc": res["lc"], "nc": res["nc"], "dg_omega_i": res["dg_omega_i"],
+                  "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"],
+                  "omega": res["omega"], "status": res["status"], "coupled_applies_per_solve": applies},
+        "kernel_ms": {"gemv": gemv_ms, "coupled_apply": apply_ms, "bem_assembly_launch": asm_ms},
+        "roofline": {"bound": "hbm", "kernel": "k_gemv_f64 (dense [K'|V'] GEMV, both interfaces)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": (GEMV_TRAFFIC["bytes"] if (args.config == GEMV_TRAFFIC["config"] and
+                                                           gemv_source_hash() == GEMV_TRAFFIC["src_sha256_16"])
+                                 else None),
+                     "bytes_per_launch": gb},
+    }
+    flops = apply_flops(nm, ns, 0)
+    if apply_ms:
+        out["coupled_operator_gflops"] = flops / (apply_ms * 1e-3) / 1e9
+    if not args.no_mixed:
+        mx = run_leg(pb, torch, prob, pb.MIXED, K, args.warmup, opts, "mixed")
+        rm = mx["res"]
+        mg_ms = mx["timing"]["gemv"][0]
+        out["mixed"] = {
+            "value": K / mx["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * mx["elapsed"] / K,
+            "latency_s": {"p50": percentile(mx["lat"], 0.5), "p99": percentile(mx["lat"], 0.99)},
+            "total_kcal_mol": rm["total"], "rel_energy_err_vs_fp64": abs(rm["total"] - res["total"]) / abs(res["total"]),
+            "newton_iters": rm["newton_iters"], "gmres_iters_total": rm["gmres_iters_total"],
+            "gemv_ms": mg_ms,
+            "gemv_gbs": gemv_bytes(nm, ns, 4) / (mg_ms * 1e-3) / 1e9 if mg_ms else None,
+            "coupled_operator_gflops": flops / (mx["timing"]["apply"][0] * 1e-3) / 1e9 if mx["timing"]["apply"][0] else None,
+        }
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle, bounded sample)")
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(prob, max(applies, 1))
+        progress(f"cpu baseline took {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -101,6 +101,12 @@ pbfb_status pbfb_get_sizes(const pbfb_problem *p, int64_t *n_nodes, int64_t *n_m
  * lazily by the first call that needs it. */
 pbfb_status pbfb_setup(pbfb_problem *p, void *hip_stream);
 
+/* Mark every device-computed operator (geometry, FEM values, Coulomb load,
+ * dense boundary operators) stale, so that the next call recomputes them from
+ * the device-resident mesh; the uploaded mesh, its topology and all device
+ * allocations are kept.  Used to time a whole solve from resident inputs. */
+pbfb_status pbfb_reset_operators(pbfb_problem *p);
+
 /* ---- operator evaluations (vectors of length n_unknowns, FP64) ---------- */
 /* F = A Phi + [N_scheme(u); 0; 0] - b (eq. general_nonlinear) */
 pbfb_status pbfb_residual(pbfb_problem *p, int scheme, const double *phi, double *F, int mem, void *hip_stream);

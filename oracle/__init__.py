@@ -73,6 +73,7 @@ def lib():
         for f in ("pbref_fem_jacobian", "pbref_fem_hessian"):
             getattr(L, f).argtypes = [P, C.c_int, dp, dp, dp]
         L.pbref_apply_A.argtypes = [P, dp, dp]
+        L.pbref_dense_rows_apply.argtypes = [P, C.c_int, C.c_int64, dp, dp, dp, dp]
         L.pbref_rhs.argtypes = [P, dp]
         L.pbref_residual.argtypes = [P, C.c_int, dp, dp]
         L.pbref_apply_jacobian.argtypes = [P, C.c_int, dp, dp, dp]
@@ -243,6 +244,11 @@ class Oracle:
         if r:
             raise RuntimeError(r)
         return y
+
+    def dense_rows_apply(self, surf, V, K, x):
+        V = _f64(V); K = _f64(K); x = _f64(x); out = np.zeros(V.shape[0])
+        lib().pbref_dense_rows_apply(self.h, surf, V.shape[0], _d(V), _d(K), _d(x), _d(out))
+        return out
 
     def rhs(self):
         b = np.zeros(self.n)

@@ -990,6 +990,28 @@ int pbref_rhs(pbref *p, double *b)
     return 0;
 }
 
+/* The Gamma rows of apply_A on a sample of rows, given those rows of the
+ * dense operators (same loop as apply_A; used to time the oracle). */
+int pbref_dense_rows_apply(const pbref *p, int surf, int64_t nrows, const double *V, const double *K,
+                           const double *x, double *out)
+{
+    int64_t nv = p->s[surf].nv;
+    const double *lam = x + p->nn + (surf == 0 ? 0 : p->s[0].nv);
+#pragma omp parallel for
+    for (int64_t r = 0; r < nrows; ++r) {
+        double s = 0.0;
+        for (int64_t j = 0; j < nv; ++j) {
+            double uj = x[p->s[surf].g[j]];
+            if (surf == 0)
+                s += K[r * nv + j] * uj - V[r * nv + j] * lam[j];
+            else
+                s += -K[r * nv + j] * uj + V[r * nv + j] * lam[j];
+        }
+        out[r] = s;
+    }
+    return 0;
+}
+
 int pbref_residual(pbref *p, int scheme, const double *phi, double *F)
 {
     int64_t n = nunk(p);

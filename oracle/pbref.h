@@ -57,6 +57,8 @@ void pbref_fem_hessian(const pbref *, int scheme, const double *u, const double 
 
 /* coupled operator (needs the dense surface operators of both surfaces) */
 int pbref_apply_A(pbref *, const double *phi, double *y);
+int pbref_dense_rows_apply(const pbref *, int surf, int64_t nrows, const double *V, const double *K,
+                           const double *x, double *out);
 int pbref_rhs(pbref *, double *b);
 int pbref_residual(pbref *, int scheme, const double *phi, double *F);
 int pbref_apply_jacobian(pbref *, int scheme, const double *phi, const double *v, double *Jv);

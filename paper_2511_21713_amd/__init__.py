@@ -21,7 +21,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 T_APPLY, T_GEMV, T_SPMV, T_ASM, T_SING = 0, 1, 2, 3, 4
 
 EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_problem_create", "pbfb_problem_destroy",
-           "pbfb_set_mesh", "pbfb_set_charges", "pbfb_set_params", "pbfb_get_sizes", "pbfb_setup", "pbfb_residual",
+           "pbfb_set_mesh", "pbfb_set_charges", "pbfb_set_params", "pbfb_get_sizes", "pbfb_setup",
+           "pbfb_reset_operators", "pbfb_residual",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_energy", "pbfb_export_bem",
            "pbfb_export_rhs", "pbfb_timing_enable", "pbfb_timing"]
 
@@ -91,6 +92,7 @@ def lib():
         L.pbfb_set_params.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double]
         L.pbfb_get_sizes.argtypes = [P, I64P, I64P, I64P, I64P, I64P]
         L.pbfb_setup.argtypes = [P, P]
+        L.pbfb_reset_operators.argtypes = [P]
         L.pbfb_residual.argtypes = [P, C.c_int, P, P, C.c_int, P]
         L.pbfb_apply_jacobian.argtypes = [P, C.c_int, P, P, P, C.c_int, P]
         L.pbfb_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
@@ -217,6 +219,9 @@ class Problem:
 
     def setup(self, stream=None):
         _check(lib().pbfb_setup(self.h, _stream(stream)))
+
+    def reset_operators(self):
+        _check(lib().pbfb_reset_operators(self.h))
 
     # ---- operators ------------------------------------------------------------
     def residual(self, scheme, phi, out=None, stream=None):

@@ -323,6 +323,7 @@ pbfb_status pbfb_set_mesh(pbfb_problem *pp, int64_t n_nodes, const double *nodes
     PB_HIP(hipSetDevice(p.ctx->device));
     (void)hipDeviceSynchronize();
     invalidate_geometry(p);
+    p.topo_ready = p.bem_topo_ready[0] = p.bem_topo_ready[1] = false;
     p.have_mesh = false;
     p.nn = n_nodes;
     p.ntet = n_tets;
@@ -544,6 +545,14 @@ pbfb_status pbfb_export_rhs(pbfb_problem *pp, double *b)
     ensure_rhs(p, s);
     PB_HIP(hipMemcpyAsync(b, p.d_b, sizeof(double) * p.n(), hipMemcpyDeviceToHost, s));
     PB_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+pbfb_status pbfb_reset_operators(pbfb_problem *pp)
+{
+    API_BEGIN
+    PB_CHECK(pp, PBFB_EINVAL, "null problem");
+    invalidate_geometry(pp->p);
     API_END
 }
 

@@ -485,44 +485,54 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     SurfaceTopo &T = p.topo[w];
     SurfaceDev &S = p.surf[w];
     Arena &A = p.bem_arena[w];
-    A.release();
     const bool yuk = (w == 1) && p.kappa > 0.0;
     const double kappa = (w == 1) ? p.kappa : 0.0;
-    // Morton copies and block tables
-    S.m_tri = A.alloc<int32_t>(3 * T.nt);
-    S.m_qp = A.alloc<double>(18 * T.nt);
-    S.m_nrm = A.alloc<double>(3 * T.nt);
-    S.m_area = A.alloc<double>(T.nt);
-    int32_t *d_morton = A.upload(T.morton, s);
-    hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, d_morton, S.tri, S.qp, S.nrm,
+    if (!p.bem_topo_ready[w]) {
+        // block tables and Morton order: once per mesh
+        A.release();
+        S.B = nullptr;
+        S.m_tri = A.alloc<int32_t>(3 * T.nt);
+        S.m_qp = A.alloc<double>(18 * T.nt);
+        S.m_nrm = A.alloc<double>(3 * T.nt);
+        S.m_area = A.alloc<double>(T.nt);
+        S.morton = A.upload(T.morton, s);
+        S.A_pref = A.upload(T.A_pref, s);
+        S.A_nv = A.upload(T.A_nv, s);
+        S.A_slots = A.upload(T.A_slots, s);
+        S.B_pref = A.upload(T.B_pref, s);
+        S.B_nv = A.upload(T.B_nv, s);
+        S.B_slots = A.upload(T.B_slots, s);
+        S.LA_ptr = A.upload(T.LA_ptr, s);
+        S.LA = A.upload(T.LA, s);
+        S.LA_blk = A.upload(T.LA_blk, s);
+        S.LB_ptr = A.upload(T.LB_ptr, s);
+        S.LB = A.upload(T.LB, s);
+        S.tp_ptr = A.upload(T.tp_ptr, s);
+        S.tp_sig = A.upload(T.tp_sig, s);
+        S.nbA = T.nbA;
+        S.nbB = T.nbB;
+        S.SA = T.SA;
+        S.SB = T.SB;
+        S.ntp = int64_t(T.tp_sig.size());
+        std::vector<int32_t> tp_tau(S.ntp);
+        for (int64_t t = 0; t < T.nt; ++t)
+            for (int32_t k = T.tp_ptr[t]; k < T.tp_ptr[t + 1]; ++k) tp_tau[k] = int32_t(t);
+        S.tp_tau = A.upload(tp_tau, s);
+        const int64_t ldt = bem_ld(T.nv);
+        S.vdiag = A.alloc<double>(T.nv);
+        if (p.precision == PBFB_MIXED) S.B = A.alloc<float>(T.nv * ldt);
+        else S.B = A.alloc<double>(T.nv * ldt);
+        PB_HIP(hipStreamSynchronize(s));
+        p.bem_topo_ready[w] = true;
+    }
+    int32_t *d_tptau = S.tp_tau;
+    hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, S.morton, S.tri, S.qp, S.nrm,
                        S.area, S.m_tri, S.m_qp, S.m_nrm, S.m_area);
-    S.A_pref = A.upload(T.A_pref, s);
-    S.A_nv = A.upload(T.A_nv, s);
-    S.A_slots = A.upload(T.A_slots, s);
-    S.B_pref = A.upload(T.B_pref, s);
-    S.B_nv = A.upload(T.B_nv, s);
-    S.B_slots = A.upload(T.B_slots, s);
-    S.LA_ptr = A.upload(T.LA_ptr, s);
-    S.LA = A.upload(T.LA, s);
-    S.LA_blk = A.upload(T.LA_blk, s);
-    S.LB_ptr = A.upload(T.LB_ptr, s);
-    S.LB = A.upload(T.LB, s);
-    S.tp_ptr = A.upload(T.tp_ptr, s);
-    S.tp_sig = A.upload(T.tp_sig, s);
-    S.nbA = T.nbA;
-    S.nbB = T.nbB;
-    S.SA = T.SA;
-    S.SB = T.SB;
-    S.ntp = int64_t(T.tp_sig.size());
-    std::vector<int32_t> tp_tau(S.ntp);
-    for (int64_t t = 0; t < T.nt; ++t)
-        for (int32_t k = T.tp_ptr[t]; k < T.tp_ptr[t + 1]; ++k) tp_tau[k] = int32_t(t);
-    int32_t *d_tptau = A.upload(tp_tau, s);
 
     const int64_t nv = T.nv, ld = bem_ld(nv);
     // FP64 storage assembles in place; mixed precision assembles in an FP64
     // scratch copy and narrows at the end
-    double *B64 = p.precision == PBFB_MIXED ? scratch<double>(p, SCR_B64, nv * ld) : A.alloc<double>(nv * ld);
+    double *B64 = p.precision == PBFB_MIXED ? scratch<double>(p, SCR_B64, nv * ld) : static_cast<double *>(S.B);
     double *WV = scratch<double>(p, SCR_W0, nv * T.SB);
     double *WK = scratch<double>(p, SCR_W1, nv * T.SB);
     // chunk the target blocks so that E stays within ~8 GB per operator
@@ -582,18 +592,14 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
                        S.tp_sig, tpv, S.area, sV, sK, B64);
     PB_HIP(hipGetLastError());
     // final storage
-    S.vdiag = A.alloc<double>(nv);
     if (p.precision == PBFB_MIXED) {
-        float *B32 = A.alloc<float>(nv * ld);
         hipLaunchKernelGGL(k_diag_and_narrow, dim3(nblk(ld, 256), unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64,
-                           S.vdiag, B32);
-        S.B = B32;
+                           S.vdiag, static_cast<float *>(S.B));
         PB_HIP(hipStreamSynchronize(s));
         release_scratch(p, SCR_B64);
     } else {
         hipLaunchKernelGGL(k_diag_and_narrow, dim3(1, unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64, S.vdiag,
                            (float *)nullptr);
-        S.B = B64;
     }
     PB_HIP(hipGetLastError());
     release_scratch(p, SCR_TPVAL);

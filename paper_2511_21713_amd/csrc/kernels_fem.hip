@@ -464,10 +464,11 @@ __global__ void k_charge_check(int64_t nt, const double *__restrict__ x, const i
 // ===========================================================================
 // host wrappers
 // ===========================================================================
-void ensure_geometry(Problem &p, hipStream_t s)
+// One-time per mesh: upload of the mesh and its integer topology.
+void ensure_topology(Problem &p, hipStream_t s)
 {
-    if (p.geom_ready) return;
-    PB_CHECK(p.have_mesh && p.have_params, PBFB_ESTATE, "set_mesh and set_params must precede setup");
+    if (p.topo_ready) return;
+    PB_CHECK(p.have_mesh, PBFB_ESTATE, "set_mesh must precede setup");
     Arena &A = p.mesh_arena;
     A.release();
     p.d_x = A.upload(p.x, s);
@@ -485,11 +486,7 @@ void ensure_geometry(Problem &p, hipStream_t s)
     p.d_val0 = A.alloc<double>(p.nnz);
     p.d_val = A.alloc<double>(p.nnz);
     p.d_val32 = p.precision == PBFB_MIXED ? A.alloc<float>(p.nnz) : nullptr;
-    int *d_bad = A.alloc<int>(1);
-    PB_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_tet_geom, dim3(nblocks(p.ntet, 256)), dim3(256), 0, s, p.ntet, p.d_x, p.d_tet, p.d_tgeo,
-                       d_bad);
-    TriRuleArg TR = tri_rule_arg();
+    p.d_bad = A.alloc<int>(1);
     for (int w = 0; w < 2; ++w) {
         SurfaceTopo &T = p.topo[w];
         SurfaceDev &S = p.surf[w];
@@ -503,11 +500,28 @@ void ensure_geometry(Problem &p, hipStream_t s)
         S.nrm = A.alloc<double>(3 * T.nt);
         S.area = A.alloc<double>(T.nt);
         S.cslot = A.upload(cslot[w], s);
-        hipLaunchKernelGGL(k_tri_geom, dim3(nblocks(T.nt, 256)), dim3(256), 0, s, T.nt, p.d_x, S.g, S.tri, TR, S.qp,
-                           S.nrm, S.area, d_bad);
+    }
+    PB_HIP(hipStreamSynchronize(s));
+    p.topo_ready = true;
+}
+
+// Geometry and FEM values from the device-resident mesh.
+void ensure_geometry(Problem &p, hipStream_t s)
+{
+    if (p.geom_ready) return;
+    PB_CHECK(p.have_mesh && p.have_params, PBFB_ESTATE, "set_mesh and set_params must precede setup");
+    ensure_topology(p, s);
+    PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_tet_geom, dim3(nblocks(p.ntet, 256)), dim3(256), 0, s, p.ntet, p.d_x, p.d_tet, p.d_tgeo,
+                       p.d_bad);
+    TriRuleArg TR = tri_rule_arg();
+    for (int w = 0; w < 2; ++w) {
+        SurfaceDev &S = p.surf[w];
+        hipLaunchKernelGGL(k_tri_geom, dim3(nblocks(S.nt, 256)), dim3(256), 0, s, S.nt, p.d_x, S.g, S.tri, TR, S.qp,
+                           S.nrm, S.area, p.d_bad);
     }
     int bad = 0;
-    PB_HIP(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
     PB_HIP(hipStreamSynchronize(s));
     PB_CHECK(!(bad & 1), PBFB_EMESH, "degenerate (zero-volume) tetrahedron");
     PB_CHECK(!(bad & 2), PBFB_EMESH, "degenerate (zero-area) surface triangle");

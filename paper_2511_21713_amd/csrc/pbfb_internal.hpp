@@ -101,7 +101,7 @@ struct SurfaceDev {
     int32_t *B_pref = nullptr, *B_nv = nullptr, *B_loc = nullptr, *B_slots = nullptr;
     int32_t *LA_ptr = nullptr, *LA = nullptr, *LA_blk = nullptr, *LB_ptr = nullptr, *LB = nullptr;
     int64_t nbA = 0, nbB = 0, SA = 0, SB = 0;
-    int32_t *tp_ptr = nullptr, *tp_sig = nullptr;
+    int32_t *tp_ptr = nullptr, *tp_sig = nullptr, *tp_tau = nullptr, *morton = nullptr;
     int64_t ntp = 0;
     int32_t *cslot = nullptr; // CSR slot of the coupling entry per (v2t entry, b)
     // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
@@ -144,7 +144,8 @@ struct Problem {
     Ctx *ctx = nullptr;
     int precision = PBFB_FP64;
     bool have_mesh = false, have_charges = false, have_params = false;
-    bool geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
+    bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
+    bool bem_topo_ready[2] = {false, false};
     // host copies
     int64_t nn = 0, ntet = 0, nq = 0;
     std::vector<double> x;
@@ -162,6 +163,7 @@ struct Problem {
     float *d_val32 = nullptr;
     int64_t nnz = 0;
     double *d_b = nullptr; // right-hand side, length n
+    int *d_bad = nullptr;
     SurfaceDev surf[2];
     int64_t n() const { return nn + topo[0].nv + topo[1].nv; }
     // timers
@@ -186,6 +188,7 @@ void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<in
                         std::vector<int32_t> &diag, std::vector<int32_t> cslot[2]);
 
 // device setup and operators (kernels_*.hip, solver.hip)
+void ensure_topology(Problem &p, hipStream_t s);
 void ensure_geometry(Problem &p, hipStream_t s);
 void ensure_rhs(Problem &p, hipStream_t s);
 void ensure_bem(Problem &p, int surf, hipStream_t s);
