@@ -69,10 +69,9 @@ const char *pbfb_last_error(void);
 /* ---- problem ------------------------------------------------------------ */
 /* precision PBFB_FP64: every operator stored and applied in FP64.
  * PBFB_MIXED: dense boundary operators and FEM matrix values stored in FP32
- * (evaluated in FP32 relative to panel centroids, accumulated in FP64),
- * FP64 accumulation in every product, FP32-basis inner GMRES inside FP64
- * iterative refinement; Newton update, relaxation search, orthogonalisation
- * and touching-panel integrals stay FP64. */
+ * (integrated in FP64, rounded once), every product accumulated in FP64;
+ * Krylov vectors, Newton update, relaxation search, orthogonalisation and
+ * touching-panel integrals stay FP64. */
 pbfb_status pbfb_problem_create(pbfb_ctx *ctx, int precision, pbfb_problem **out);
 void pbfb_problem_destroy(pbfb_problem *p);
 
