@@ -147,6 +147,35 @@ typedef struct {
  * (nullable, length 2*n_unknowns) receives [Phi_L | Phi_NL]. */
 pbfb_status pbfb_solve(pbfb_problem *p, const pbfb_solve_opts *o, pbfb_result *res, double *phi_out, int mem,
                        void *hip_stream);
+/* Batched solve (Sec. 2.4-2.5 for each instance): n independent problems
+ * of one context, any mix of sizes and parameters, advanced together.  Each
+ * round runs every instance to its next linear solve and then one batched
+ * GMRES over all of them (one launch per Krylov step for the whole batch,
+ * no host synchronisation between steps).  res[n] receives each instance's
+ * result; the per-instance arithmetic does not depend on the batch, so each
+ * result equals the one pbfb_solve gives alone.  Returns PBFB_OK when every
+ * instance succeeded, otherwise the first failing status. */
+pbfb_status pbfb_solve_batch(pbfb_ctx *ctx, int n, pbfb_problem *const *probs, const pbfb_solve_opts *o,
+                             pbfb_result *res, void *hip_stream);
+
+/* ---- serving: continuous batching -------------------------------------- */
+/* A server owns two streams and two host threads.  Submitted problems wait
+ * until a slot (at most max_slots concurrent requests) is free and their
+ * estimated device footprint fits in hbm_budget_bytes; they are then set up
+ * on a side stream while the running requests keep iterating, join the
+ * running set at the next Newton-step boundary and leave it when done.  The
+ * problem is borrowed from submit until poll reports done (the caller must
+ * not touch it meanwhile and destroys it afterwards); the budget counts a
+ * request from admission to completion.  ENOMEM at submit: the request alone
+ * exceeds the budget. */
+typedef struct pbfb_server pbfb_server;
+pbfb_status pbfb_server_create(pbfb_ctx *ctx, size_t hbm_budget_bytes, int max_slots, pbfb_server **out);
+pbfb_status pbfb_server_submit(pbfb_server *s, pbfb_problem *p, const pbfb_solve_opts *o, uint64_t *ticket);
+/* done = 1 once the request finished; res (nullable) then receives its result */
+pbfb_status pbfb_server_poll(pbfb_server *s, uint64_t ticket, int *done, pbfb_result *res);
+/* drains every submitted request, then stops the threads and frees the server */
+pbfb_status pbfb_server_destroy(pbfb_server *s);
+
 /* Energy split {Total, LC, NC, dG_Omega_i} (kcal/mol) of given Phi_L, Phi_NL
  * (eqs. Esolv, Esolv_Lineal, Potential_in_Omega_m); phi_nl may be NULL. */
 pbfb_status pbfb_energy(pbfb_problem *p, const double *phi_lin, const double *phi_nl, double out[4], int mem,

@@ -23,7 +23,8 @@ T_APPLY, T_GEMV, T_SPMV, T_ASM, T_SING = 0, 1, 2, 3, 4
 EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_problem_create", "pbfb_problem_destroy",
            "pbfb_set_mesh", "pbfb_set_charges", "pbfb_set_params", "pbfb_get_sizes", "pbfb_setup",
            "pbfb_reset_operators", "pbfb_residual",
-           "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_energy", "pbfb_export_bem",
+           "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
+           "pbfb_server_submit", "pbfb_server_poll", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
            "pbfb_export_rhs", "pbfb_timing_enable", "pbfb_timing"]
 
 
@@ -99,6 +100,11 @@ def lib():
         L.pbfb_solve_opts_default.restype = None
         L.pbfb_solve.argtypes = [P, C.POINTER(SolveOpts), C.POINTER(Result), P, C.c_int, P]
         L.pbfb_energy.argtypes = [P, P, P, C.POINTER(C.c_double), C.c_int, P]
+        L.pbfb_solve_batch.argtypes = [P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(SolveOpts), C.POINTER(Result), P]
+        L.pbfb_server_create.argtypes = [P, C.c_size_t, C.c_int, PP]
+        L.pbfb_server_submit.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(C.c_uint64)]
+        L.pbfb_server_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(Result)]
+        L.pbfb_server_destroy.argtypes = [P]
         L.pbfb_export_bem.argtypes = [P, C.c_int, P, P]
         L.pbfb_export_rhs.argtypes = [P, P]
         L.pbfb_timing_enable.argtypes = [P, C.c_int]
@@ -159,6 +165,52 @@ class Context:
 
     def __del__(self):
         self.close()
+
+
+def solve_batch(ctx, problems, stream=None, **opts):
+    """Solve several problems of one context together; returns a list of result dicts."""
+    n = len(problems)
+    arr = (C.c_void_p * max(n, 1))(*[p.h.value for p in problems])
+    res = (Result * max(n, 1))()
+    o = default_opts(**opts)
+    code = lib().pbfb_solve_batch(ctx.h, n, arr, C.byref(o), res, _stream(stream))
+    out = [res[i].as_dict() for i in range(n)]
+    return code, out
+
+
+class Server:
+    """Continuous-batching server: submit problems, poll tickets."""
+
+    def __init__(self, ctx, hbm_budget_bytes, max_slots):
+        h = C.c_void_p()
+        _check(lib().pbfb_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self._keep = {}
+
+    def submit(self, problem, **opts):
+        o = default_opts(**opts)
+        t = C.c_uint64()
+        _check(lib().pbfb_server_submit(self.h, problem.h, C.byref(o), C.byref(t)))
+        self._keep[t.value] = problem
+        return t.value
+
+    def poll(self, ticket):
+        done = C.c_int()
+        res = Result()
+        _check(lib().pbfb_server_poll(self.h, ticket, C.byref(done), C.byref(res)))
+        return (res.as_dict() if done.value else None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            code = lib().pbfb_server_destroy(self.h)
+            self.h = None
+            _check(code)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().pbfb_server_destroy(self.h)
+            self.h = None
 
 
 class Problem:

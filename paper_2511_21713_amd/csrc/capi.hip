@@ -496,6 +496,38 @@ pbfb_status pbfb_solve(pbfb_problem *pp, const pbfb_solve_opts *o, pbfb_result *
     API_END
 }
 
+pbfb_status pbfb_solve_batch(pbfb_ctx *ctx, int n, pbfb_problem *const *probs, const pbfb_solve_opts *o,
+                             pbfb_result *res, void *stream)
+{
+    API_BEGIN
+    PB_CHECK(ctx && n >= 0 && (n == 0 || (probs && res)), PBFB_EINVAL, "bad batch arguments");
+    pbfb_solve_opts def;
+    pbfb_solve_opts_default(&def);
+    const pbfb_solve_opts &O = o ? *o : def;
+    PB_CHECK(O.gmres_restart >= 1 && O.gmres_restart <= 1000 && O.max_gmres >= 1, PBFB_EINVAL, "bad GMRES options");
+    PB_HIP(hipSetDevice(ctx->c.device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->c.stream;
+    std::vector<NewtonRun> runs;
+    runs.reserve(n);
+    for (int q = 0; q < n; ++q) {
+        PB_CHECK(probs[q] && probs[q]->p.ctx == &ctx->c, PBFB_EINVAL, "problem missing or from another context");
+        for (int r = 0; r < q; ++r) PB_CHECK(probs[r] != probs[q], PBFB_EINVAL, "a problem appears twice in the batch");
+        probs[q]->p.last_stream = s;
+        runs.emplace_back(&probs[q]->p, O, &res[q], nullptr);
+    }
+    std::vector<NewtonRun *> ptrs;
+    for (auto &r : runs) ptrs.push_back(&r);
+    run_newton(ptrs, s);
+    pbfb_status first = PBFB_OK;
+    for (int q = 0; q < n; ++q)
+        if (res[q].status != PBFB_OK && first == PBFB_OK) {
+            first = res[q].status;
+            set_error(runs[q].message.empty() ? "instance " + std::to_string(q) + " failed" : runs[q].message);
+        }
+    return first;
+    API_END
+}
+
 pbfb_status pbfb_energy(pbfb_problem *pp, const double *phi_lin, const double *phi_nl, double out[4], int mem,
                         void *stream)
 {

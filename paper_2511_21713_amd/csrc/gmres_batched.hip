@@ -1,0 +1,607 @@
+// Batched restarted GMRES with device-resident control.
+//
+// Every instance of a batch solves its own system J x = b (right
+// preconditioned by the block diagonal, x0 = 0, classical Gram-Schmidt
+// applied twice, Givens rotations), and all of them advance together: each
+// kernel below takes a packed work list that covers every instance, so one
+// launch per step serves the whole batch whatever the mesh sizes.  The Krylov
+// scalars (Hessenberg column, rotations, residual estimate, restart and
+// convergence decisions, triangular solve) live on the device in one thread
+// per instance, so the host only enqueues iterations and polls a completion
+// counter asynchronously; nothing waits on the host between iterations.
+//
+// Per-instance state machine:
+//   INIT  -> w = b, V_0 = b/|b|, target = tol |b|              -> ARN (or DONE if b = 0)
+//   ARN   -> w = J D^{-1} V_j, CGS2, V_{j+1}, Givens            -> UPD at convergence/restart/limit
+//   UPD   -> y = H^{-1} g, x += D^{-1} V y                       -> RES
+//   RES   -> w = b - J x, beta = |w|: beta <= target -> DONE, else V_0 = w/beta -> ARN
+// which is the restarted GMRES of the oracle (true residual at every restart).
+#include <algorithm>
+#include <cmath>
+
+#include "pbfb_internal.hpp"
+
+namespace pbfb {
+
+enum GSt { G_INIT = 0, G_ARN = 1, G_UPD = 2, G_RES = 3, G_DONE = 4, G_FAIL = 5 };
+
+struct GDesc {
+    const void *Bm, *Bs;
+    int64_t ldm, lds, nm, ns;
+    int f32;
+    const int32_t *gm, *gs;
+    const int32_t *rowptr, *col;
+    const void *val;
+    int64_t nn, n;
+    const double *dinv;
+    double *V, *w, *xm, *xs, *x;
+    const double *b;
+    double *H, *cs, *sn, *g, *y, *h1, *h2, *part, *npart;
+    int64_t nch;
+    double tol;
+    int m, maxit;
+};
+
+struct GState {
+    int st, j, total, code;
+    double beta, target, hn, pad;
+};
+
+struct WItem {
+    int inst, a;
+    int64_t b;
+};
+
+constexpr int CH = 2048;     // rows per reduction chunk (256 threads x 8)
+constexpr int GROWS = 16;    // GEMV rows per workgroup (4 wavefronts x 4 rows)
+constexpr int SROWS = 32;    // SpMV rows per workgroup (8 lanes per row)
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ inline bool applies(int st) { return st == G_ARN || st == G_RES; }
+
+// ---------------------------------------------------------------------------
+// apply: pack, dense GEMV, CSR SpMV on the current input of each instance
+// (ARN: D^{-1} V_j, RES: x)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (!applies(s.st)) return;
+    const GDesc &d = D[it.inst];
+    const double *in = s.st == G_ARN ? d.V + int64_t(s.j) * d.n : d.x;
+    const bool sc = s.st == G_ARN;
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CH; k += 256) {
+        if (k < d.ldm) {
+            double v = 0.0;
+            if (k < d.nm) {
+                const int32_t r = d.gm[k];
+                v = sc ? in[r] * d.dinv[r] : in[r];
+            } else if (k < 2 * d.nm) {
+                const int64_t r = d.nn + (k - d.nm);
+                v = sc ? in[r] * d.dinv[r] : in[r];
+            }
+            d.xm[k] = v;
+        }
+        if (k < d.lds) {
+            double v = 0.0;
+            if (k < d.ns) {
+                const int32_t r = d.gs[k];
+                v = sc ? in[r] * d.dinv[r] : in[r];
+            } else if (k < 2 * d.ns) {
+                const int64_t r = d.nn + d.nm + (k - d.ns);
+                v = sc ? in[r] * d.dinv[r] : in[r];
+            }
+            d.xs[k] = v;
+        }
+    }
+}
+
+template <typename MT>
+__device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
+                                 int64_t n, int64_t ld, int64_t r0, int lane)
+{
+    constexpr int RW = 4;
+    double acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r] = 0.0;
+    if constexpr (sizeof(MT) == 8) {
+        const dvec2 *xv = reinterpret_cast<const dvec2 *>(x);
+        const dvec2 *rows[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) rows[r] = reinterpret_cast<const dvec2 *>(B + (r0 + r < n ? r0 + r : n - 1) * ld);
+        const int64_t nc = ld / 128;
+#pragma unroll 2
+        for (int64_t c = 0; c < nc; ++c) {
+            const dvec2 xx = xv[c * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const dvec2 bb = __builtin_nontemporal_load(rows[r] + c * 64 + lane);
+                acc[r] = fma(bb.x, xx.x, acc[r]);
+                acc[r] = fma(bb.y, xx.y, acc[r]);
+            }
+        }
+    } else {
+        const dvec2 *xv = reinterpret_cast<const dvec2 *>(x);
+        const fvec4 *rows[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) rows[r] = reinterpret_cast<const fvec4 *>(B + (r0 + r < n ? r0 + r : n - 1) * ld);
+        const int64_t nc = ld / 256;
+#pragma unroll 2
+        for (int64_t c = 0; c < nc; ++c) {
+            const dvec2 xa = xv[(c * 64 + lane) * 2], xb = xv[(c * 64 + lane) * 2 + 1];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const fvec4 bb = __builtin_nontemporal_load(rows[r] + c * 64 + lane);
+                acc[r] = fma(double(bb.x), xa.x, acc[r]);
+                acc[r] = fma(double(bb.y), xa.y, acc[r]);
+                acc[r] = fma(double(bb.z), xb.x, acc[r]);
+                acc[r] = fma(double(bb.w), xb.y, acc[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+    if (lane < RW && r0 + lane < n) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < RW; ++r)
+            if (lane == r) v = acc[r];
+        y[r0 + lane] = v;
+    }
+}
+
+// work item: inst, a = interface (0/1), b = first row of the workgroup
+__global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    if (!applies(S[it.inst].st)) return;
+    const GDesc &d = D[it.inst];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = it.b + wv * 4;
+    const int64_t n = it.a == 0 ? d.nm : d.ns;
+    if (r0 >= n) return;
+    const int64_t ld = it.a == 0 ? d.ldm : d.lds;
+    const double *x = it.a == 0 ? d.xm : d.xs;
+    double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
+    const void *B = it.a == 0 ? d.Bm : d.Bs;
+    if (d.f32) gemv_rows<float>(static_cast<const float *>(B), x, y, n, ld, r0, lane);
+    else gemv_rows<double>(static_cast<const double *>(B), x, y, n, ld, r0, lane);
+}
+
+__global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (!applies(s.st)) return;
+    const GDesc &d = D[it.inst];
+    const int64_t row = it.b + (threadIdx.x >> 3);
+    const int sub = threadIdx.x & 7;
+    const double *in = s.st == G_ARN ? d.V + int64_t(s.j) * d.n : d.x;
+    const bool sc = s.st == G_ARN;
+    double acc = 0.0;
+    if (row < d.nn) {
+        const int32_t e = d.rowptr[row + 1];
+        if (d.f32) {
+            const float *val = static_cast<const float *>(d.val);
+            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) {
+                const int32_t c = d.col[k];
+                acc = fma(double(val[k]), sc ? in[c] * d.dinv[c] : in[c], acc);
+            }
+        } else {
+            const double *val = static_cast<const double *>(d.val);
+            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) {
+                const int32_t c = d.col[k];
+                acc = fma(val[k], sc ? in[c] * d.dinv[c] : in[c], acc);
+            }
+        }
+    }
+    acc += __shfl_xor(acc, 4);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 1);
+    if (sub == 0 && row < d.nn) d.w[row] = acc;
+}
+
+// RES: w = b - w;  INIT: w = b
+__global__ void __launch_bounds__(256) k_bpost(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    const int st = S[it.inst].st;
+    if (st != G_RES && st != G_INIT) return;
+    const GDesc &d = D[it.inst];
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256)
+        d.w[k] = st == G_RES ? d.b[k] - d.w[k] : d.b[k];
+}
+
+// ---------------------------------------------------------------------------
+// classical Gram-Schmidt pass: partial dot products V_i . w per chunk
+// work item: inst, a = chunk index, b = first row; blockIdx.y = group of 8 i
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_bmdot(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S)
+{
+    __shared__ double red[8][256];
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (s.st != G_ARN) return;
+    const int i0 = blockIdx.y * 8;
+    if (i0 > s.j) return;
+    const GDesc &d = D[it.inst];
+    const int kk = min(8, s.j + 1 - i0);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) {
+        const double wk = d.w[k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < kk) acc[q] = fma(d.V[int64_t(i0 + q) * d.n + k], wk, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int wd = 128; wd > 0; wd >>= 1) {
+        if (threadIdx.x < wd)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + wd];
+        __syncthreads();
+    }
+    if (threadIdx.x < kk) d.part[int64_t(it.a) * (d.m + 1) + i0 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// w -= sum_i h_i V_i with h_i summed from the chunk partials in a fixed order
+// (every workgroup gets the same h); the chunk-0 workgroup stores h.  With
+// with_norm, also the chunk's partial |w|^2 (for ARN after the update, and
+// for INIT/RES on the unmodified w).
+__global__ void __launch_bounds__(256) k_bmsub(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S, int second)
+{
+    __shared__ double hs[1024];
+    __shared__ double red[256];
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    const GDesc &d = D[it.inst];
+    const bool arn = s.st == G_ARN;
+    const bool nrm = second && (arn || s.st == G_RES || s.st == G_INIT);
+    if (!arn && !nrm) return;
+    const int jj = arn ? s.j + 1 : 0;
+    for (int i = threadIdx.x; i < jj; i += 256) {
+        double h = 0.0;
+        for (int64_t c = 0; c < d.nch; ++c) h += d.part[c * (d.m + 1) + i];
+        hs[i] = h;
+        if (it.a == 0) (second ? d.h2 : d.h1)[i] = h;
+    }
+    __syncthreads();
+    double sq = 0.0;
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) {
+        double v = d.w[k];
+        for (int i = 0; i < jj; ++i) v = fma(-hs[i], d.V[int64_t(i) * d.n + k], v);
+        if (arn) d.w[k] = v;
+        sq = fma(v, v, sq);
+    }
+    if (!nrm) return;
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int wd = 128; wd > 0; wd >>= 1) {
+        if (threadIdx.x < wd) red[threadIdx.x] += red[threadIdx.x + wd];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.npart[it.a] = red[0];
+}
+
+// ARN: V_{j+1} = w / |w|;  INIT/RES: V_0 = w / |w|  (|w|^2 from the chunk partials)
+__global__ void __launch_bounds__(256) k_bscale(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                                const GState *__restrict__ S)
+{
+    __shared__ double nr;
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (s.st != G_ARN && s.st != G_RES && s.st != G_INIT) return;
+    const GDesc &d = D[it.inst];
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int64_t c = 0; c < d.nch; ++c) t += d.npart[c];
+        nr = sqrt(t);
+    }
+    __syncthreads();
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    double *dst = d.V + (s.st == G_ARN ? int64_t(s.j + 1) * d.n : 0);
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) dst[k] = d.w[k] * inv;
+}
+
+// ---------------------------------------------------------------------------
+// control: one thread per instance
+// ---------------------------------------------------------------------------
+__global__ void k_bcontrol(int nb, const GDesc *__restrict__ D, GState *__restrict__ S)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb) return;
+    GState s = S[q];
+    const GDesc &d = D[q];
+    if (s.st != G_ARN && s.st != G_RES && s.st != G_INIT) return;
+    double t = 0.0;
+    for (int64_t c = 0; c < d.nch; ++c) t += d.npart[c];
+    const double nr = sqrt(t);
+    const int m = d.m;
+    if (s.st == G_ARN) {
+        const int j = s.j;
+        double *Hj = d.H + int64_t(j) * (m + 1);
+        for (int i = 0; i <= j; ++i) Hj[i] = d.h1[i] + d.h2[i];
+        Hj[j + 1] = nr;
+        for (int i = 0; i < j; ++i) {
+            const double a = Hj[i], c = Hj[i + 1];
+            Hj[i] = d.cs[i] * a + d.sn[i] * c;
+            Hj[i + 1] = -d.sn[i] * a + d.cs[i] * c;
+        }
+        const double a = Hj[j], c = Hj[j + 1];
+        const double den = hypot(a, c);
+        d.cs[j] = a / den;
+        d.sn[j] = c / den;
+        Hj[j] = den;
+        Hj[j + 1] = 0.0;
+        d.g[j + 1] = -d.sn[j] * d.g[j];
+        d.g[j] = d.cs[j] * d.g[j];
+        s.j = j + 1;
+        s.total += 1;
+        s.hn = nr;
+        const double res = fabs(d.g[j + 1]);
+        if (!(res == res)) {
+            s.st = G_FAIL;
+            s.code = PBFB_ENAN;
+        } else if (res <= s.target || nr == 0.0 || s.j == m || s.total >= d.maxit) {
+            s.st = G_UPD;
+        }
+    } else {
+        if (s.st == G_INIT) s.target = d.tol * nr;
+        s.beta = nr;
+        if (!(nr == nr)) {
+            s.st = G_FAIL;
+            s.code = PBFB_ENAN;
+        } else if (nr <= s.target) {
+            s.st = G_DONE;
+        } else if (s.total >= d.maxit) {
+            s.st = G_FAIL;
+            s.code = PBFB_ENOTCONV;
+        } else {
+            for (int i = 0; i <= m; ++i) d.g[i] = 0.0;
+            d.g[0] = nr;
+            s.j = 0;
+            s.st = G_ARN;
+        }
+    }
+    S[q] = s;
+}
+
+// UPD: back substitution H y = g over the j columns of the cycle
+__global__ void k_bsolve(int nb, const GDesc *__restrict__ D, const GState *__restrict__ S)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb || S[q].st != G_UPD) return;
+    const GDesc &d = D[q];
+    const int j = S[q].j, m = d.m;
+    for (int i = j - 1; i >= 0; --i) {
+        double s = d.g[i];
+        for (int k = i + 1; k < j; ++k) s -= d.H[int64_t(k) * (m + 1) + i] * d.y[k];
+        d.y[i] = s / d.H[int64_t(i) * (m + 1) + i];
+    }
+}
+
+// UPD: x += D^{-1} (V y)
+__global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (s.st != G_UPD) return;
+    const GDesc &d = D[it.inst];
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) {
+        double v = 0.0;
+        for (int i = 0; i < s.j; ++i) v = fma(d.y[i], d.V[int64_t(i) * d.n + k], v);
+        d.x[k] += d.dinv[k] * v;
+    }
+}
+
+// UPD -> RES; count finished instances
+__global__ void k_badvance(int nb, GState *__restrict__ S, int *__restrict__ ndone)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        if (S[q].st == G_UPD) S[q].st = G_RES;
+        if (S[q].st == G_DONE || S[q].st == G_FAIL) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *ndone = cnt;
+}
+
+// ===========================================================================
+// host driver
+// ===========================================================================
+struct BatchBuffers {
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    int *pinned = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    ~BatchBuffers()
+    {
+        if (dev) (void)hipFree(dev);
+        if (pinned) (void)hipHostFree(pinned);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+static BatchBuffers &batch_buffers()
+{
+    static thread_local BatchBuffers B;
+    if (!B.pinned) {
+        PB_HIP(hipHostMalloc(reinterpret_cast<void **>(&B.pinned), 64 * sizeof(int), hipHostMallocDefault));
+        for (auto &e : B.ev) PB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    return B;
+}
+
+void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
+{
+    const int nb = int(jobs.size());
+    if (nb == 0) return;
+    std::vector<GDesc> desc(nb);
+    std::vector<GState> st(nb);
+    std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack;
+    int maxiter_host = 0;
+    for (int q = 0; q < nb; ++q) {
+        GmresJob &J = *jobs[q];
+        Problem &p = *J.p;
+        const int m = J.restart;
+        const int64_t n = p.n();
+        GDesc &d = desc[q];
+        d.Bm = p.surf[0].B;
+        d.Bs = p.surf[1].B;
+        d.nm = p.surf[0].nv;
+        d.ns = p.surf[1].nv;
+        d.ldm = bem_ld(d.nm);
+        d.lds = bem_ld(d.ns);
+        d.f32 = p.precision == PBFB_MIXED;
+        d.gm = p.surf[0].g;
+        d.gs = p.surf[1].g;
+        d.rowptr = p.d_rowptr;
+        d.col = p.d_col;
+        d.val = d.f32 ? static_cast<const void *>(p.d_val32) : static_cast<const void *>(p.d_val);
+        d.nn = p.nn;
+        d.n = n;
+        d.dinv = J.dinv;
+        d.V = scratch<double>(p, SCR_BASIS, size_t(m + 1) * n);
+        d.w = scratch<double>(p, SCR_G0, n);
+        d.xm = scratch<double>(p, SCR_XM, d.ldm);
+        d.xs = scratch<double>(p, SCR_XS, d.lds);
+        d.x = J.x;
+        d.b = J.b;
+        d.nch = (n + CH - 1) / CH;
+        double *kry = scratch<double>(p, SCR_HVEC, size_t(m) * (m + 1) + 3 * m + 3 * (m + 1) + 8);
+        d.H = kry;
+        d.cs = d.H + size_t(m) * (m + 1);
+        d.sn = d.cs + m;
+        d.y = d.sn + m;
+        d.g = d.y + m;
+        d.h1 = d.g + (m + 1);
+        d.h2 = d.h1 + (m + 1);
+        d.part = scratch<double>(p, SCR_HPART, size_t(d.nch) * (m + 1));
+        d.npart = scratch<double>(p, SCR_NRM, d.nch);
+        d.tol = J.tol;
+        d.m = m;
+        d.maxit = J.maxit;
+        st[q] = GState{G_INIT, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+        PB_HIP(hipMemsetAsync(J.x, 0, sizeof(double) * n, s));
+        for (int64_t c = 0; c < d.nch; ++c) wl_vec.push_back(WItem{q, int(c), c * CH});
+        for (int a = 0; a < 2; ++a) {
+            const int64_t nv = a == 0 ? d.nm : d.ns;
+            for (int64_t r = 0; r < nv; r += GROWS) wl_gemv.push_back(WItem{q, a, r});
+        }
+        for (int64_t r = 0; r < p.nn; r += SROWS) wl_spmv.push_back(WItem{q, 0, r});
+        for (int64_t k = 0; k < std::max(d.ldm, d.lds); k += CH) wl_pack.push_back(WItem{q, 0, k});
+        maxiter_host = std::max(maxiter_host, J.maxit + J.maxit / std::max(m, 1) + 4);
+    }
+    int maxm = 0;
+    for (auto *J : jobs) maxm = std::max(maxm, J->restart);
+    // device copies of descriptors, states and work lists
+    BatchBuffers &BB = batch_buffers();
+    const size_t bytes = sizeof(GDesc) * nb + sizeof(GState) * nb +
+                         sizeof(WItem) * (wl_vec.size() + wl_gemv.size() + wl_spmv.size() + wl_pack.size()) + 256;
+    if (BB.dev_bytes < bytes) {
+        if (BB.dev) PB_HIP(hipFree(BB.dev));
+        BB.dev = nullptr;
+        PB_HIP(hipMalloc(&BB.dev, bytes));
+        BB.dev_bytes = bytes;
+    }
+    char *cur = static_cast<char *>(BB.dev);
+    auto put = [&](const void *src, size_t b) {
+        char *d = cur;
+        PB_HIP(hipMemcpyAsync(d, src, b, hipMemcpyHostToDevice, s));
+        cur += (b + 15) / 16 * 16;
+        return static_cast<void *>(d);
+    };
+    GDesc *dD = static_cast<GDesc *>(put(desc.data(), sizeof(GDesc) * nb));
+    GState *dS = static_cast<GState *>(put(st.data(), sizeof(GState) * nb));
+    WItem *dvec = static_cast<WItem *>(put(wl_vec.data(), sizeof(WItem) * wl_vec.size()));
+    WItem *dgemv = static_cast<WItem *>(put(wl_gemv.data(), sizeof(WItem) * wl_gemv.size()));
+    WItem *dspmv = static_cast<WItem *>(put(wl_spmv.data(), sizeof(WItem) * wl_spmv.size()));
+    WItem *dpack = static_cast<WItem *>(put(wl_pack.data(), sizeof(WItem) * wl_pack.size()));
+    int *dcount = reinterpret_cast<int *>(cur);
+    const unsigned nvec = unsigned(wl_vec.size()), ngemv = unsigned(wl_gemv.size()),
+                   nspmv = unsigned(wl_spmv.size()), npack = unsigned(wl_pack.size());
+    const unsigned ngroups = unsigned((maxm + 1 + 7) / 8);
+    const unsigned tb = unsigned((nb + 63) / 64);
+
+    EventTimer *tm = nullptr;
+    for (auto *J : jobs)
+        if (J->p->timing) {
+            tm = &J->p->timer;
+            break;
+        }
+    // Enqueue iterations; poll a completion counter copied to pinned memory,
+    // blocking only on the copy from two polls back (bounded run-ahead).
+    const int POLL = 4;
+    int polls = 0;
+    bool finished = false;
+    for (int it = 0; it < maxiter_host && !finished; ++it) {
+        if (tm) tm->begin(T_APPLY, s);
+        hipLaunchKernelGGL(k_bpack, dim3(npack), dim3(256), 0, s, dpack, dD, dS);
+        if (tm) tm->begin(T_GEMV, s);
+        hipLaunchKernelGGL(k_bgemv, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
+        if (tm) {
+            tm->end(s);
+            tm->begin(T_SPMV, s);
+        }
+        hipLaunchKernelGGL(k_bspmv, dim3(nspmv), dim3(256), 0, s, dspmv, dD, dS);
+        if (tm) {
+            tm->end(s);
+            tm->end(s);
+        }
+        hipLaunchKernelGGL(k_bpost, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_bmdot, dim3(nvec, ngroups), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_bmsub, dim3(nvec), dim3(256), 0, s, dvec, dD, dS, 0);
+        hipLaunchKernelGGL(k_bmdot, dim3(nvec, ngroups), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_bmsub, dim3(nvec), dim3(256), 0, s, dvec, dD, dS, 1);
+        hipLaunchKernelGGL(k_bscale, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_bcontrol, dim3(tb), dim3(64), 0, s, nb, dD, dS);
+        hipLaunchKernelGGL(k_bsolve, dim3(tb), dim3(64), 0, s, nb, dD, dS);
+        hipLaunchKernelGGL(k_bupdx, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_badvance, dim3(1), dim3(256), 0, s, nb, dS, dcount);
+        PB_HIP(hipGetLastError());
+        if ((it + 1) % POLL == 0) {
+            const int slot = polls % 3;
+            PB_HIP(hipMemcpyAsync(BB.pinned + slot, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+            PB_HIP(hipEventRecord(BB.ev[slot], s));
+            ++polls;
+            if (polls >= 3) {
+                const int old = (polls - 3) % 3; // the copy two polls back
+                PB_HIP(hipEventSynchronize(BB.ev[old]));
+                if (BB.pinned[old] >= nb) finished = true;
+            }
+            // a newer copy may already be complete
+            for (int k = 1; k <= 2 && !finished && polls - k >= 0; ++k) {
+                const int sl = (polls - k) % 3;
+                if (hipEventQuery(BB.ev[sl]) == hipSuccess && BB.pinned[sl] >= nb) finished = true;
+            }
+        }
+    }
+    PB_HIP(hipMemcpyAsync(st.data(), dS, sizeof(GState) * nb, hipMemcpyDeviceToHost, s));
+    PB_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < nb; ++q) {
+        GmresJob &J = *jobs[q];
+        J.iters = st[q].total;
+        if (st[q].st == G_DONE) J.status = 0;
+        else if (st[q].st == G_FAIL) J.status = st[q].code;
+        else J.status = PBFB_ENOTCONV;
+    }
+}
+
+} // namespace pbfb

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -216,9 +217,37 @@ void dots(Problem &p, int k, const double *const *a, const double *const *b, int
 // energy
 void energy(Problem &p, const double *phi_lin, const double *phi_nl, double out[4], hipStream_t s);
 
-// solver
-int gmres(Problem &p, int scheme_for_diag, const double *u_for_diag, const double *b, double *x, double tol,
-          int restart, int maxit, int *iters, hipStream_t s);
+// batched GMRES (gmres_batched.hip): one linear system per job, all advanced together
+struct GmresJob {
+    Problem *p;
+    const double *b;
+    double *x;
+    const double *dinv;
+    double tol;
+    int restart, maxit;
+    int iters, status;
+};
+void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s);
+void build_precond(Problem &p, double *dinv, hipStream_t s);
+
+// Newton driver (solver.hip): one state machine per instance
+struct NewtonRun {
+    Problem *p;
+    pbfb_solve_opts o;
+    pbfb_result *res;
+    double *phi_out_dev;
+    int phase = 0, k = 0, sch = PBFB_HS, status = 0;
+    double tol = 0.0, omega_last = 1.0;
+    bool frozen = false;
+    double *phil = nullptr, *phinl = nullptr, *phi = nullptr, *c = nullptr, *d = nullptr, *D = nullptr;
+    double *pv = nullptr, *rv = nullptr, *rN = nullptr, *rJ = nullptr, *rH = nullptr, *dinv = nullptr;
+    GmresJob job{};
+    std::string message;
+    std::chrono::steady_clock::time_point t0, t1;
+    NewtonRun(Problem *p_, const pbfb_solve_opts &o_, pbfb_result *res_, double *out);
+};
+bool advance(NewtonRun &r, hipStream_t s);               // true: needs its linear solve
+void run_newton(std::vector<NewtonRun *> &runs, hipStream_t s);
 pbfb_status solve(Problem &p, const pbfb_solve_opts &o, pbfb_result &res, double *phi_out_dev, hipStream_t s);
 
 } // namespace pbfb

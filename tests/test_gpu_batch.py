@@ -1,0 +1,112 @@
+"""Batched solves and the continuous-batching server through the C ABI.
+
+Every instance's arithmetic (work lists, reduction orders, Krylov control) is
+independent of the rest of its batch, so a result must equal the solo
+result bit for bit, in a batch and when admitted mid-flight by the server.
+Solo results themselves are checked against the oracle.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import pbgen
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    dict(n=4, a=4.0, c=4.0, bump=False, t=4.0, L=6, helix=0, partials=0, kappa=0.125, center_charge=1.0),
+    dict(n=3, a=6.0, c=9.0, bump=True, t=3.0, L=3, helix=3, partials=5, kappa=0.2, seed=(9, 1)),
+    dict(n=1, a=4.0, c=4.0, bump=False, t=3.0, L=2, helix=0, partials=0, kappa=0.3, center_charge=-2.0),
+    dict(n=6, a=8.0, c=14.0, bump=True, t=5.0, L=5, helix=6, partials=20, kappa=0.05, seed=(9, 2)),
+    dict(n=5, a=5.0, c=5.0, bump=False, t=4.0, L=4, helix=0, partials=0, kappa=0.33, center_charge=3.0),
+]
+OPTS = dict(tol_nl=1e-9, tol_gr=1e-11, tol_gr0=1e-11, tol_omega=1e-8, l_e=0.0, max_gmres=20000)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2511_21713_amd as pb
+    ctx = pb.Context(0)
+    probs = [pbgen.make_problem(**s) for s in SPECS]
+    solo = []
+    for prob in probs:
+        g = pb.Problem.from_inputs(ctx, prob)
+        solo.append(g.solve(**OPTS))
+        g.close()
+    return pb, ctx, probs, solo
+
+
+def test_solo_matches_oracle(setup):
+    pb, ctx, probs, solo = setup
+    for prob, r in zip(probs[:3], solo[:3]):
+        ro, _, _ = oracle.Oracle.from_problem(prob).solve(**OPTS)
+        assert abs(r["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_solo_bitwise(setup, precision):
+    pb, ctx, probs, solo = setup
+    if precision == 1:
+        solo = []
+        for prob in probs:
+            g = pb.Problem.from_inputs(ctx, prob, precision=1)
+            solo.append(g.solve(**OPTS))
+            g.close()
+    gs = [pb.Problem.from_inputs(ctx, prob, precision=precision) for prob in probs]
+    code, res = pb.solve_batch(ctx, gs, **OPTS)
+    assert code == 0
+    for r, s in zip(res, solo):
+        print(f"  batch {r['total']!r} solo {s['total']!r} newton {r['newton_iters']} gmres {r['gmres_iters_total']}",
+              flush=True)
+        assert r["status"] == 0
+        assert r["total"] == s["total"] and r["lc"] == s["lc"] and r["nc"] == s["nc"]
+        assert r["newton_iters"] == s["newton_iters"] and r["gmres_iters"] == s["gmres_iters"]
+
+
+def test_batch_isolates_a_failing_instance(setup):
+    pb, ctx, probs, solo = setup
+    gs = [pb.Problem.from_inputs(ctx, prob) for prob in probs[:3]]
+    gs[1].set_charges(np.array([[0.0, 0.0, 100.0]]), np.array([1.0]))  # outside the solute
+    code, res = pb.solve_batch(ctx, gs, **OPTS)
+    assert code == pb.ECHARGE
+    assert res[1]["status"] == pb.ECHARGE
+    assert res[0]["status"] == 0 and res[0]["total"] == solo[0]["total"]
+    assert res[2]["status"] == 0 and res[2]["total"] == solo[2]["total"]
+
+
+def test_server_results_equal_solo(setup):
+    pb, ctx, probs, solo = setup
+    srv = pb.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=2)
+    tickets = []
+    gs = []
+    for i, prob in enumerate(probs):
+        g = pb.Problem.from_inputs(ctx, prob)
+        gs.append(g)
+        tickets.append(srv.submit(g, **OPTS))
+        time.sleep(0.01 * i)  # staggered arrivals join a running batch
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 120:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.005)
+    srv.close()
+    assert len(out) == len(tickets)
+    for t, s in zip(tickets, solo):
+        assert out[t]["status"] == 0
+        assert out[t]["total"] == s["total"], (out[t]["total"], s["total"])
+
+
+def test_server_rejects_oversized_request(setup):
+    pb, ctx, probs, solo = setup
+    srv = pb.Server(ctx, hbm_budget_bytes=1 << 20, max_slots=1)
+    g = pb.Problem.from_inputs(ctx, probs[0])
+    with pytest.raises(pb.PbfbError) as e:
+        srv.submit(g)
+    assert e.value.code == pb.ENOMEM
+    srv.close()
