@@ -36,8 +36,9 @@ struct GDesc {
     const double *dinv;
     double *V, *w, *xm, *xs, *x;
     const double *b;
-    double *H, *cs, *sn, *g, *y, *h1, *h2, *part, *npart;
-    int64_t nch;
+    double *H, *cs, *sn, *g, *y, *h1, *h2, *part, *npart, *nrm;
+    int *cnt; // completion counter of the x update (index 257)
+    int64_t nch, nchb;
     double tol;
     int m, maxit;
 };
@@ -52,7 +53,7 @@ struct WItem {
     int64_t b;
 };
 
-constexpr int CH = 2048;     // rows per reduction chunk (256 threads x 8)
+constexpr int CH = 256;      // rows per chunk: one per thread of a workgroup
 constexpr int GROWS = 16;    // GEMV rows per workgroup (4 wavefronts x 4 rows)
 constexpr int SROWS = 32;    // SpMV rows per workgroup (8 lanes per row)
 
@@ -208,22 +209,15 @@ __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, con
     if (sub == 0 && row < d.nn) d.w[row] = acc;
 }
 
-// RES: w = b - w;  INIT: w = b
-__global__ void __launch_bounds__(256) k_bpost(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
-                                               const GState *__restrict__ S)
-{
-    const WItem it = wl[blockIdx.x];
-    const int st = S[it.inst].st;
-    if (st != G_RES && st != G_INIT) return;
-    const GDesc &d = D[it.inst];
-    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256)
-        d.w[k] = st == G_RES ? d.b[k] - d.w[k] : d.b[k];
-}
+// ---------------------------------------------------------------------------
+// classical Gram-Schmidt pass: partial dot products V_i . w over 2048-row
+// chunks (work item: inst, a = chunk, b = first row; blockIdx.y = group of 8
+// coefficients), then one workgroup per (instance, group) sums the chunk
+// partials in chunk order, so every coefficient is deterministic.  Kernel
+// boundaries order the passes (no device-scope fences).
+// ---------------------------------------------------------------------------
+constexpr int CHB = 2048; // rows per dot-product chunk (8 per thread)
 
-// ---------------------------------------------------------------------------
-// classical Gram-Schmidt pass: partial dot products V_i . w per chunk
-// work item: inst, a = chunk index, b = first row; blockIdx.y = group of 8 i
-// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_bmdot(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S)
 {
@@ -238,7 +232,7 @@ __global__ void __launch_bounds__(256) k_bmdot(const WItem *__restrict__ wl, con
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) {
+    for (int64_t k = it.b + threadIdx.x; k < it.b + CHB && k < d.n; k += 256) {
         const double wk = d.w[k];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -256,10 +250,27 @@ __global__ void __launch_bounds__(256) k_bmdot(const WItem *__restrict__ wl, con
     if (threadIdx.x < kk) d.part[int64_t(it.a) * (d.m + 1) + i0 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// w -= sum_i h_i V_i with h_i summed from the chunk partials in a fixed order
-// (every workgroup gets the same h); the chunk-0 workgroup stores h.  With
-// with_norm, also the chunk's partial |w|^2 (for ARN after the update, and
-// for INIT/RES on the unmodified w).
+// h[i] = sum over chunks of part[c][i]; grid (instances, groups of 8)
+__global__ void __launch_bounds__(256) k_breduce(const GDesc *__restrict__ D, const GState *__restrict__ S, int pass)
+{
+    const int q = blockIdx.x;
+    const GState s = S[q];
+    if (s.st != G_ARN) return;
+    const int i0 = blockIdx.y * 8;
+    if (i0 > s.j) return;
+    const GDesc &d = D[q];
+    const int kk = min(8, s.j + 1 - i0);
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    if (g >= kk) return;
+    double t = 0.0;
+    for (int64_t c = lane; c < d.nchb; c += 32) t += d.part[c * (d.m + 1) + i0 + g];
+    for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off, 32);
+    if (lane == 0) (pass == 0 ? d.h1 : d.h2)[i0 + g] = t;
+}
+
+// First pass (second = 0): w -= sum_i h1_i V_i for ARN.
+// Second pass (second = 1): ARN: w -= sum_i h2_i V_i;  RES: w = b - w;
+// INIT: w = b; then |w|^2 per 256-row chunk into npart.
 __global__ void __launch_bounds__(256) k_bmsub(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S, int second)
 {
@@ -269,25 +280,24 @@ __global__ void __launch_bounds__(256) k_bmsub(const WItem *__restrict__ wl, con
     const GState s = S[it.inst];
     const GDesc &d = D[it.inst];
     const bool arn = s.st == G_ARN;
-    const bool nrm = second && (arn || s.st == G_RES || s.st == G_INIT);
-    if (!arn && !nrm) return;
+    if (!arn && !(second && (s.st == G_RES || s.st == G_INIT))) return;
     const int jj = arn ? s.j + 1 : 0;
-    for (int i = threadIdx.x; i < jj; i += 256) {
-        double h = 0.0;
-        for (int64_t c = 0; c < d.nch; ++c) h += d.part[c * (d.m + 1) + i];
-        hs[i] = h;
-        if (it.a == 0) (second ? d.h2 : d.h1)[i] = h;
-    }
+    const double *h = second ? d.h2 : d.h1;
+    for (int i = threadIdx.x; i < jj; i += 256) hs[i] = h[i];
     __syncthreads();
-    double sq = 0.0;
-    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) {
-        double v = d.w[k];
-        for (int i = 0; i < jj; ++i) v = fma(-hs[i], d.V[int64_t(i) * d.n + k], v);
-        if (arn) d.w[k] = v;
-        sq = fma(v, v, sq);
+    const int64_t k = it.b + threadIdx.x;
+    double v = 0.0;
+    if (k < d.n) {
+        if (s.st == G_INIT) v = d.b[k];
+        else if (s.st == G_RES) v = d.b[k] - d.w[k];
+        else {
+            v = d.w[k];
+            for (int i = 0; i < jj; ++i) v = fma(-hs[i], d.V[int64_t(i) * d.n + k], v);
+        }
+        d.w[k] = v;
     }
-    if (!nrm) return;
-    red[threadIdx.x] = sq;
+    if (!second) return;
+    red[threadIdx.x] = v * v;
     __syncthreads();
     for (int wd = 128; wd > 0; wd >>= 1) {
         if (threadIdx.x < wd) red[threadIdx.x] += red[threadIdx.x + wd];
@@ -296,130 +306,166 @@ __global__ void __launch_bounds__(256) k_bmsub(const WItem *__restrict__ wl, con
     if (threadIdx.x == 0) d.npart[it.a] = red[0];
 }
 
-// ARN: V_{j+1} = w / |w|;  INIT/RES: V_0 = w / |w|  (|w|^2 from the chunk partials)
+// |w|^2 = sum of the chunk partials, one workgroup per instance
+__global__ void __launch_bounds__(256) k_bnorm(const GDesc *__restrict__ D, const GState *__restrict__ S)
+{
+    __shared__ double red[256];
+    const int q = blockIdx.x;
+    const int st = S[q].st;
+    if (st != G_ARN && st != G_RES && st != G_INIT) return;
+    const GDesc &d = D[q];
+    double t = 0.0;
+    for (int64_t c = threadIdx.x; c < d.nch; c += 256) t += d.npart[c];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int wd = 128; wd > 0; wd >>= 1) {
+        if (threadIdx.x < wd) red[threadIdx.x] += red[threadIdx.x + wd];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *d.nrm = red[0];
+}
+
+// ARN: V_{j+1} = w / |w|;  INIT/RES: V_0 = w / |w|
 __global__ void __launch_bounds__(256) k_bscale(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                 const GState *__restrict__ S)
 {
-    __shared__ double nr;
     const WItem it = wl[blockIdx.x];
     const GState s = S[it.inst];
     if (s.st != G_ARN && s.st != G_RES && s.st != G_INIT) return;
     const GDesc &d = D[it.inst];
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int64_t c = 0; c < d.nch; ++c) t += d.npart[c];
-        nr = sqrt(t);
-    }
-    __syncthreads();
+    const double nr = sqrt(*d.nrm);
     const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
     double *dst = d.V + (s.st == G_ARN ? int64_t(s.j + 1) * d.n : 0);
-    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) dst[k] = d.w[k] * inv;
+    const int64_t k = it.b + threadIdx.x;
+    if (k < d.n) dst[k] = d.w[k] * inv;
 }
 
 // ---------------------------------------------------------------------------
-// control: one thread per instance
+// control: one wavefront per instance.  ARN: Hessenberg column, Givens chain
+// (in LDS, one lane), residual estimate, cycle end; at the end of a cycle the
+// triangular solve H y = g (column sweep across the lanes).  INIT/RES: true
+// residual test and cycle start.  Transitions to DONE/FAIL bump ndone.
 // ---------------------------------------------------------------------------
-__global__ void k_bcontrol(int nb, const GDesc *__restrict__ D, GState *__restrict__ S)
+__global__ void __launch_bounds__(64) k_bcontrol(const GDesc *__restrict__ D, GState *__restrict__ S,
+                                                 int *__restrict__ ndone)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nb) return;
-    GState s = S[q];
+    __shared__ double hc[1024], cs[1024], sn[1024], gl[1024];
+    __shared__ GState ss;
+    const int q = blockIdx.x, lane = threadIdx.x;
     const GDesc &d = D[q];
-    if (s.st != G_ARN && s.st != G_RES && s.st != G_INIT) return;
-    double t = 0.0;
-    for (int64_t c = 0; c < d.nch; ++c) t += d.npart[c];
-    const double nr = sqrt(t);
+    if (lane == 0) ss = S[q];
+    __syncthreads();
+    const int st0 = ss.st;
+    if (st0 != G_ARN && st0 != G_RES && st0 != G_INIT) return;
     const int m = d.m;
-    if (s.st == G_ARN) {
-        const int j = s.j;
+    const double nr = sqrt(*d.nrm);
+    if (st0 == G_ARN) {
+        const int j = ss.j;
+        for (int i = lane; i <= j; i += 64) {
+            hc[i] = d.h1[i] + d.h2[i];
+            if (i < j) {
+                cs[i] = d.cs[i];
+                sn[i] = d.sn[i];
+            }
+        }
+        __syncthreads();
+        if (lane == 0) {
+            double t = hc[0];
+            for (int i = 0; i < j; ++i) {
+                const double c2 = hc[i + 1];
+                hc[i] = cs[i] * t + sn[i] * c2;
+                t = -sn[i] * t + cs[i] * c2;
+            }
+            const double den = hypot(t, nr);
+            const double cj = t / den, sj = nr / den;
+            d.cs[j] = cj;
+            d.sn[j] = sj;
+            hc[j] = den;
+            const double gj = d.g[j];
+            d.g[j + 1] = -sj * gj;
+            d.g[j] = cj * gj;
+            ss.j = j + 1;
+            ss.total += 1;
+            ss.hn = nr;
+            const double res = fabs(d.g[j + 1]);
+            if (!(res == res)) {
+                ss.st = G_FAIL;
+                ss.code = PBFB_ENAN;
+                atomicAdd(ndone, 1);
+            } else if (res <= ss.target || nr == 0.0 || ss.j == m || ss.total >= d.maxit) {
+                ss.st = G_UPD;
+            }
+        }
+        __syncthreads();
         double *Hj = d.H + int64_t(j) * (m + 1);
-        for (int i = 0; i <= j; ++i) Hj[i] = d.h1[i] + d.h2[i];
-        Hj[j + 1] = nr;
-        for (int i = 0; i < j; ++i) {
-            const double a = Hj[i], c = Hj[i + 1];
-            Hj[i] = d.cs[i] * a + d.sn[i] * c;
-            Hj[i + 1] = -d.sn[i] * a + d.cs[i] * c;
+        for (int i = lane; i <= j; i += 64) Hj[i] = hc[i];
+        if (lane == 0) Hj[j + 1] = 0.0;
+        if (ss.st == G_UPD) {
+            // back substitution by columns: y_i = g_i / H_ii, then g_k -= H_ki y_i for k < i
+            const int jc = ss.j;
+            __threadfence_block();
+            for (int i = lane; i < jc; i += 64) gl[i] = d.g[i];
+            __syncthreads();
+            for (int i = jc - 1; i >= 0; --i) {
+                // column j (this step's) is taken from LDS, older columns from global memory
+                const double yi = gl[i] / (i == j ? hc[j] : d.H[int64_t(i) * (m + 1) + i]);
+                for (int k = lane; k < i; k += 64) gl[k] -= (i == j ? hc[k] : d.H[int64_t(i) * (m + 1) + k]) * yi;
+                if (lane == 0) d.y[i] = yi;
+                __syncthreads();
+            }
         }
-        const double a = Hj[j], c = Hj[j + 1];
-        const double den = hypot(a, c);
-        d.cs[j] = a / den;
-        d.sn[j] = c / den;
-        Hj[j] = den;
-        Hj[j + 1] = 0.0;
-        d.g[j + 1] = -d.sn[j] * d.g[j];
-        d.g[j] = d.cs[j] * d.g[j];
-        s.j = j + 1;
-        s.total += 1;
-        s.hn = nr;
-        const double res = fabs(d.g[j + 1]);
-        if (!(res == res)) {
-            s.st = G_FAIL;
-            s.code = PBFB_ENAN;
-        } else if (res <= s.target || nr == 0.0 || s.j == m || s.total >= d.maxit) {
-            s.st = G_UPD;
-        }
-    } else {
-        if (s.st == G_INIT) s.target = d.tol * nr;
-        s.beta = nr;
+    } else if (lane == 0) {
+        if (st0 == G_INIT) ss.target = d.tol * nr;
+        ss.beta = nr;
         if (!(nr == nr)) {
-            s.st = G_FAIL;
-            s.code = PBFB_ENAN;
-        } else if (nr <= s.target) {
-            s.st = G_DONE;
-        } else if (s.total >= d.maxit) {
-            s.st = G_FAIL;
-            s.code = PBFB_ENOTCONV;
+            ss.st = G_FAIL;
+            ss.code = PBFB_ENAN;
+            atomicAdd(ndone, 1);
+        } else if (nr <= ss.target) {
+            ss.st = G_DONE;
+            atomicAdd(ndone, 1);
+        } else if (ss.total >= d.maxit) {
+            ss.st = G_FAIL;
+            ss.code = PBFB_ENOTCONV;
+            atomicAdd(ndone, 1);
         } else {
             for (int i = 0; i <= m; ++i) d.g[i] = 0.0;
             d.g[0] = nr;
-            s.j = 0;
-            s.st = G_ARN;
+            ss.j = 0;
+            ss.st = G_ARN;
         }
     }
-    S[q] = s;
+    __syncthreads();
+    if (lane == 0) S[q] = ss;
 }
 
-// UPD: back substitution H y = g over the j columns of the cycle
-__global__ void k_bsolve(int nb, const GDesc *__restrict__ D, const GState *__restrict__ S)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nb || S[q].st != G_UPD) return;
-    const GDesc &d = D[q];
-    const int j = S[q].j, m = d.m;
-    for (int i = j - 1; i >= 0; --i) {
-        double s = d.g[i];
-        for (int k = i + 1; k < j; ++k) s -= d.H[int64_t(k) * (m + 1) + i] * d.y[k];
-        d.y[i] = s / d.H[int64_t(i) * (m + 1) + i];
-    }
-}
-
-// UPD: x += D^{-1} (V y)
+// UPD: x += D^{-1} (V y); the last workgroup of the instance moves it to RES
 __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
-                                               const GState *__restrict__ S)
+                                               GState *__restrict__ S)
 {
+    __shared__ double ys[1024];
+    __shared__ int last;
     const WItem it = wl[blockIdx.x];
     const GState s = S[it.inst];
     if (s.st != G_UPD) return;
     const GDesc &d = D[it.inst];
-    for (int64_t k = it.b + threadIdx.x; k < it.b + CH && k < d.n; k += 256) {
+    for (int i = threadIdx.x; i < s.j; i += 256) ys[i] = d.y[i];
+    __syncthreads();
+    const int64_t k = it.b + threadIdx.x;
+    if (k < d.n) {
         double v = 0.0;
-        for (int i = 0; i < s.j; ++i) v = fma(d.y[i], d.V[int64_t(i) * d.n + k], v);
+        for (int i = 0; i < s.j; ++i) v = fma(ys[i], d.V[int64_t(i) * d.n + k], v);
         d.x[k] += d.dinv[k] * v;
     }
-}
-
-// UPD -> RES; count finished instances
-__global__ void k_badvance(int nb, GState *__restrict__ S, int *__restrict__ ndone)
-{
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-        if (S[q].st == G_UPD) S[q].st = G_RES;
-        if (S[q].st == G_DONE || S[q].st == G_FAIL) atomicAdd(&cnt, 1);
+    if (threadIdx.x == 0) {
+        int *cnt = d.cnt + 257;
+        last = atomicAdd(cnt, 1) == int(d.nch) - 1;
+        if (last) {
+            *cnt = 0;
+            S[it.inst].st = G_RES;
+        }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) *ndone = cnt;
 }
 
 // ===========================================================================
@@ -455,7 +501,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     if (nb == 0) return;
     std::vector<GDesc> desc(nb);
     std::vector<GState> st(nb);
-    std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack;
+    std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack, wl_dot;
     int maxiter_host = 0;
     for (int q = 0; q < nb; ++q) {
         GmresJob &J = *jobs[q];
@@ -493,14 +539,19 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.g = d.y + m;
         d.h1 = d.g + (m + 1);
         d.h2 = d.h1 + (m + 1);
-        d.part = scratch<double>(p, SCR_HPART, size_t(d.nch) * (m + 1));
-        d.npart = scratch<double>(p, SCR_NRM, d.nch);
+        d.nchb = (n + CHB - 1) / CHB;
+        d.part = scratch<double>(p, SCR_HPART, size_t(d.nchb) * (m + 1));
+        d.npart = scratch<double>(p, SCR_NRM, d.nch + 1);
+        d.nrm = d.npart + d.nch;
+        d.cnt = scratch<int>(p, SCR_CNT, 258);
+        PB_HIP(hipMemsetAsync(d.cnt, 0, sizeof(int) * 258, s));
         d.tol = J.tol;
         d.m = m;
         d.maxit = J.maxit;
         st[q] = GState{G_INIT, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
         PB_HIP(hipMemsetAsync(J.x, 0, sizeof(double) * n, s));
         for (int64_t c = 0; c < d.nch; ++c) wl_vec.push_back(WItem{q, int(c), c * CH});
+        for (int64_t c = 0; c < d.nchb; ++c) wl_dot.push_back(WItem{q, int(c), c * CHB});
         for (int a = 0; a < 2; ++a) {
             const int64_t nv = a == 0 ? d.nm : d.ns;
             for (int64_t r = 0; r < nv; r += GROWS) wl_gemv.push_back(WItem{q, a, r});
@@ -514,7 +565,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     // device copies of descriptors, states and work lists
     BatchBuffers &BB = batch_buffers();
     const size_t bytes = sizeof(GDesc) * nb + sizeof(GState) * nb +
-                         sizeof(WItem) * (wl_vec.size() + wl_gemv.size() + wl_spmv.size() + wl_pack.size()) + 256;
+                         sizeof(WItem) * (wl_vec.size() + wl_gemv.size() + wl_spmv.size() + wl_pack.size() +
+                                          wl_dot.size()) + 512;
     if (BB.dev_bytes < bytes) {
         if (BB.dev) PB_HIP(hipFree(BB.dev));
         BB.dev = nullptr;
@@ -534,11 +586,13 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     WItem *dgemv = static_cast<WItem *>(put(wl_gemv.data(), sizeof(WItem) * wl_gemv.size()));
     WItem *dspmv = static_cast<WItem *>(put(wl_spmv.data(), sizeof(WItem) * wl_spmv.size()));
     WItem *dpack = static_cast<WItem *>(put(wl_pack.data(), sizeof(WItem) * wl_pack.size()));
+    WItem *ddot = static_cast<WItem *>(put(wl_dot.data(), sizeof(WItem) * wl_dot.size()));
     int *dcount = reinterpret_cast<int *>(cur);
+    PB_HIP(hipMemsetAsync(dcount, 0, sizeof(int), s));
     const unsigned nvec = unsigned(wl_vec.size()), ngemv = unsigned(wl_gemv.size()),
-                   nspmv = unsigned(wl_spmv.size()), npack = unsigned(wl_pack.size());
+                   nspmv = unsigned(wl_spmv.size()), npack = unsigned(wl_pack.size()),
+                   ndot = unsigned(wl_dot.size());
     const unsigned ngroups = unsigned((maxm + 1 + 7) / 8);
-    const unsigned tb = unsigned((nb + 63) / 64);
 
     EventTimer *tm = nullptr;
     for (auto *J : jobs)
@@ -565,16 +619,16 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             tm->end(s);
             tm->end(s);
         }
-        hipLaunchKernelGGL(k_bpost, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
-        hipLaunchKernelGGL(k_bmdot, dim3(nvec, ngroups), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_bmdot, dim3(ndot, ngroups), dim3(256), 0, s, ddot, dD, dS);
+        hipLaunchKernelGGL(k_breduce, dim3(unsigned(nb), ngroups), dim3(256), 0, s, dD, dS, 0);
         hipLaunchKernelGGL(k_bmsub, dim3(nvec), dim3(256), 0, s, dvec, dD, dS, 0);
-        hipLaunchKernelGGL(k_bmdot, dim3(nvec, ngroups), dim3(256), 0, s, dvec, dD, dS);
+        hipLaunchKernelGGL(k_bmdot, dim3(ndot, ngroups), dim3(256), 0, s, ddot, dD, dS);
+        hipLaunchKernelGGL(k_breduce, dim3(unsigned(nb), ngroups), dim3(256), 0, s, dD, dS, 1);
         hipLaunchKernelGGL(k_bmsub, dim3(nvec), dim3(256), 0, s, dvec, dD, dS, 1);
+        hipLaunchKernelGGL(k_bnorm, dim3(unsigned(nb)), dim3(256), 0, s, dD, dS);
         hipLaunchKernelGGL(k_bscale, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
-        hipLaunchKernelGGL(k_bcontrol, dim3(tb), dim3(64), 0, s, nb, dD, dS);
-        hipLaunchKernelGGL(k_bsolve, dim3(tb), dim3(64), 0, s, nb, dD, dS);
+        hipLaunchKernelGGL(k_bcontrol, dim3(unsigned(nb)), dim3(64), 0, s, dD, dS, dcount);
         hipLaunchKernelGGL(k_bupdx, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
-        hipLaunchKernelGGL(k_badvance, dim3(1), dim3(256), 0, s, nb, dS, dcount);
         PB_HIP(hipGetLastError());
         if ((it + 1) % POLL == 0) {
             const int slot = polls % 3;
