@@ -98,6 +98,103 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
     return out
 
 
+def batch_leg(pb, torch, count, steps, precision):
+    """Batched workload: `count` instances of the sphere-type and RNA-type
+    generators (triangles log-uniform over 320..38720, 4..60 helix charges,
+    kappa ~ U(0.03, 0.33)) solved by one pbfb_solve_batch per step, setup
+    included (operators reset before each step)."""
+    import pbgen
+    t0 = time.perf_counter()
+    probs = [pbgen.batch_instance(3, i) for i in range(count)]
+    progress(f"batch: generated {count} instances in {time.perf_counter() - t0:.1f} s "
+             f"({sum(p.tri_m.shape[0] for p in probs)} triangles per interface in total)")
+    ctx = pb.Context(0)
+    gs = [pb.Problem.from_inputs(ctx, p, precision=precision) for p in probs]
+    code, res = pb.solve_batch(ctx, gs)  # warm-up: topology, uploads, first assembly
+    walls, lat = [], []
+    for k in range(steps):
+        for g in gs:
+            g.reset_operators()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        code, res = pb.solve_batch(ctx, gs)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - ts)
+        lat += [r["t_setup_s"] + r["t_solve_s"] for r in res]
+        progress(f"batch: step {k}: {walls[-1]:.3f} s for {count} solves, status {code}, "
+                 f"newton {[r['newton_iters'] for r in res][:8]}...")
+    for g in gs:
+        g.close()
+    ctx.close()
+    wall = sum(walls) / len(walls)
+    return {"instances": count, "precision": "mixed" if precision == pb.MIXED else "fp64", "wall_s": wall,
+            "value": count / wall, "unit": "PB solves/s",
+            "completion_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
+            "status": code}
+
+
+def serve_leg(pb, torch, count, nmax, precision, load=0.8, seed=0):
+    """Serving workload: `count` requests (config-1 generator, triangles
+    log-uniform over 320..20 n_max^2, random kappa) arriving as a Poisson
+    process at `load` x the measured single-request service rate, submitted
+    to a continuous-batching server; latency = submit to completion."""
+    import numpy as np
+
+    import pbgen
+    t0 = time.perf_counter()
+    probs = [pbgen.serve_instance(i, n_hi=nmax) for i in range(count)]
+    progress(f"serve: generated {count} requests in {time.perf_counter() - t0:.1f} s")
+    ctx = pb.Context(0)
+    # service rate from solo solves of the first few requests
+    svc = []
+    for p in probs[:4]:
+        g = pb.Problem.from_inputs(ctx, p, precision=precision)
+        g.solve()
+        g.reset_operators()
+        ts = time.perf_counter()
+        g.solve()
+        svc.append(time.perf_counter() - ts)
+        g.close()
+    rate = load / (sum(svc) / len(svc))
+    rng = np.random.default_rng([4, seed])
+    gaps = rng.exponential(1.0 / rate, size=count)
+    srv = pb.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=16)
+    gs = [pb.Problem.from_inputs(ctx, p, precision=precision) for p in probs]
+    submit, done, res = {}, {}, {}
+    tickets = []
+    start = time.perf_counter()
+    next_t = start
+    i = 0
+    while len(done) < count:
+        now = time.perf_counter()
+        while i < count and now >= next_t:
+            t = srv.submit(gs[i])
+            tickets.append(t)
+            submit[t] = time.perf_counter()
+            next_t += gaps[i]
+            i += 1
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = time.perf_counter()
+                    res[t] = r
+        time.sleep(0.0005)
+    makespan = time.perf_counter() - start
+    srv.close()
+    for g in gs:
+        g.close()
+    ctx.close()
+    lat = [done[t] - submit[t] for t in tickets]
+    bad = sum(1 for t in tickets if res[t]["status"] != 0)
+    progress(f"serve ({'mixed' if precision == pb.MIXED else 'fp64'}): {count} requests in {makespan:.2f} s, "
+             f"p50 {percentile(lat, 0.5):.3f} s, p99 {percentile(lat, 0.99):.3f} s, failures {bad}")
+    return {"requests": count, "precision": "mixed" if precision == pb.MIXED else "fp64",
+            "arrival_rate_per_s": rate, "load": load, "value": count / makespan, "unit": "PB solves/s",
+            "latency_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)}, "failures": bad,
+            "max_triangles": 20 * nmax * nmax}
+
+
 def cpu_baseline(prob, applies_per_solve, seed=0):
     """Oracle timed on a bounded sample of the same workload, extrapolated to
     one solve: sampled dense Galerkin rows (assembly), the oracle's dense row
@@ -141,6 +238,9 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=32, help="instances of the batched leg (0: skip)")
+    ap.add_argument("--serve", type=int, default=48, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-nmax", type=int, default=20, help="largest icosphere frequency of served requests")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="run one device copy of this size first (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -227,6 +327,12 @@ def main():
             "gemv_gbs": gemv_bytes(nm, ns, 4) / (mg_ms * 1e-3) / 1e9 if mg_ms else None,
             "coupled_operator_gflops": flops / (mx["timing"]["apply"][0] * 1e-3) / 1e9 if mx["timing"]["apply"][0] else None,
         }
+    if args.batch > 0:
+        out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
+                          "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}
+    if args.serve > 0:
+        out["serving"] = {"mixed": serve_leg(pb, torch, args.serve, args.serve_nmax, pb.MIXED),
+                          "fp64": serve_leg(pb, torch, args.serve, args.serve_nmax, pb.FP64)}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle, bounded sample)")
         t0 = time.perf_counter()

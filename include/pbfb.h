@@ -140,7 +140,8 @@ typedef struct {
     int gmres_iters[64];
     double omega[64], e_k[64];
     int omega_iters[64];
-    double t_setup_s, t_solve_s;
+    double t_setup_s; /* from the start of the call (batch: of the batch; server: admission) to the end of setup */
+    double t_solve_s; /* from the end of setup to the result */
 } pbfb_result;
 
 /* Full solve: linear component Phi_L, Newton on Phi_NL, energy.  phi_out

@@ -53,6 +53,7 @@ NewtonRun::NewtonRun(Problem *p_, const pbfb_solve_opts &o_, pbfb_result *res_, 
     : p(p_), o(o_), res(res_), phi_out_dev(out)
 {
     *res = pbfb_result{};
+    t0 = std::chrono::steady_clock::now(); // batch start / admission time
 }
 
 static void finish(NewtonRun &r, hipStream_t s)
@@ -175,7 +176,6 @@ static bool advance_impl(NewtonRun &r, hipStream_t s)
     Problem &p = *r.p;
     const int64_t n = p.n(), nn = p.nn;
     if (r.phase == PH_START) {
-        r.t0 = std::chrono::steady_clock::now();
         ensure_all(p, s);
         PB_HIP(hipStreamSynchronize(s));
         r.t1 = std::chrono::steady_clock::now();

@@ -32,7 +32,7 @@ import math
 import numpy as np
 
 __all__ = ["Problem", "icosphere", "make_problem", "make_config", "config_params",
-           "point_mesh_distance", "validate", "batch_instance"]
+           "point_mesh_distance", "validate", "batch_instance", "serve_instance"]
 
 
 @dataclasses.dataclass
@@ -385,6 +385,20 @@ def batch_instance(cfg: int, instance: int, n_lo=4, n_hi=44):
     L = 10
     return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=L, helix=per, partials=0,
                         kappa=kappa, seed=(cfg, instance))
+
+
+def serve_instance(instance: int, n_lo=4, n_hi=64, cfg=4):
+    """One request of the serving workload: an RNA-like solute of the config-1
+    generator with a triangle count log-uniform over frequencies [n_lo, n_hi],
+    a helix of 4..60 charges and kappa ~ U(0.03, 0.33)."""
+    rng = np.random.default_rng([cfg, instance, 11])
+    n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+    kappa = float(rng.uniform(0.03, 0.33))
+    h = int(rng.integers(4, 61))
+    per = (h + 1) // 2
+    c = max(15.0, (per - 1) * 28.0 / 11.0 / 2.0 + 8.0)
+    return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=10, helix=per, partials=0, kappa=kappa,
+                        seed=(cfg, instance))
 
 
 # ----------------------------------------------------------------------------
