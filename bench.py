@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -30,14 +32,28 @@ HBM_PEAK_GBS = 8000.0
 # --pmc runs (FETCH_SIZE then WRITE_SIZE, each scaled by the factor the same
 # counter reads for a copy of known size), valid for the kernel source whose
 # hash is recorded with it; see profiles/gemv_f64_rna20k_hbm_counters.md.
-GEMV_TRAFFIC = {"config": 1, "src_sha256_16": "9547680e12ff9b82", "bytes": 3.4010e9 + 1.84e5}
+GEMV_TRAFFIC = {"config": 1, "src_sha256_16": "unmeasured", "bytes": None}
+# algorithmic flops per quadrature-point pair of the regular tiles, counting
+# add/mul/rsqrt/exp as 1 and FMA as 2: Laplace V and K 37, Yukawa 46
+FLOPS_QP = {"laplace": 37, "yukawa": 46}
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def gemv_source_hash():
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2511_21713_amd", "csrc", "kernels_la.hip")).read()
-    a, b = src.index("k_gemv_f64("), src.index("// FP32 storage, FP64 accumulation")
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    src = open(os.path.join(ROOT, "paper_2511_21713_amd", "csrc", "gemv_rows.hpp")).read()
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
+
+
+def regular_pairs(tri):
+    """Ordered triangle pairs of one surface that share no vertex (the pairs
+    the regular 6 x 6 rule integrates)."""
+    import numpy as np
+    import scipy.sparse as sp
+    nt = tri.shape[0]
+    T = sp.csr_matrix((np.ones(3 * nt), (np.repeat(np.arange(nt), 3), tri.ravel())))
+    return nt * nt - (T @ T.T).nnz
 
 
 def progress(msg):
@@ -72,7 +88,7 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
              f"device bytes {g.hbm() / 1e9:.2f} GB")
     for w in range(warmup):
         g.reset_operators()
-        r = g.solve(check=False, **opts)
+        r = g.solve(**opts)
         progress(f"{label}: warmup {w}: total {r['total']:.6f} kcal/mol, newton {r['newton_iters']}, "
                  f"gmres {r['gmres_iters_total']}, status {r['status']}, {r['t_setup_s'] + r['t_solve_s']:.3f} s")
     g.timing_enable(True)
@@ -83,7 +99,7 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
     for k in range(steps):
         ts = time.perf_counter()
         g.reset_operators()
-        res = g.solve(check=False, **opts)
+        res = g.solve(**opts)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         progress(f"{label}: step {k}: {lat[-1]:.3f} s (setup {res['t_setup_s']:.3f}, solve {res['t_solve_s']:.3f}), "
@@ -92,7 +108,13 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
     elapsed = time.perf_counter() - t_start
     tm = {name: g.timing(i) for i, name in enumerate(["apply", "gemv", "spmv", "assembly", "singular"])}
     g.timing_enable(False)
-    out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm())
+    # one more solve outside the timed region for the potential on Gamma_m
+    phi = torch.zeros(2 * g.n, dtype=torch.float64, device="cuda")
+    g.solve(phi_out=phi, **opts)
+    torch.cuda.synchronize()
+    phi = phi.cpu().numpy()
+    u_m = (phi[:g.n] + phi[g.n:])[np.unique(prob.tri_m)]
+    out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm(), u_m=u_m)
     g.close()
     ctx.close()
     return out
@@ -121,6 +143,8 @@ def batch_leg(pb, torch, count, steps, precision):
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - ts)
         lat += [r["t_setup_s"] + r["t_solve_s"] for r in res]
+        if code != 0:
+            raise RuntimeError(f"batched solve failed with status {code}: {pb.last_error()}")
         progress(f"batch: step {k}: {walls[-1]:.3f} s for {count} solves, status {code}, "
                  f"newton {[r['newton_iters'] for r in res][:8]}...")
     for g in gs:
@@ -187,6 +211,8 @@ def serve_leg(pb, torch, count, nmax, precision, load=0.8, seed=0):
     ctx.close()
     lat = [done[t] - submit[t] for t in tickets]
     bad = sum(1 for t in tickets if res[t]["status"] != 0)
+    if bad:
+        raise RuntimeError(f"{bad} served requests failed")
     progress(f"serve ({'mixed' if precision == pb.MIXED else 'fp64'}): {count} requests in {makespan:.2f} s, "
              f"p50 {percentile(lat, 0.5):.3f} s, p99 {percentile(lat, 0.99):.3f} s, failures {bad}")
     return {"requests": count, "precision": "mixed" if precision == pb.MIXED else "fp64",
@@ -303,7 +329,7 @@ def main():
                   "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"],
                   "omega": res["omega"], "status": res["status"], "coupled_applies_per_solve": applies},
         "kernel_ms": {"gemv": gemv_ms, "coupled_apply": apply_ms, "bem_assembly_launch": asm_ms},
-        "roofline": {"bound": "hbm", "kernel": "k_gemv_f64 (dense [K'|V'] GEMV, both interfaces)",
+        "roofline": {"bound": "hbm", "kernel": "k_bgemv / k_gemv (gemv_rows: dense [K'|V'] FP64 GEMV, both interfaces)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": (GEMV_TRAFFIC["bytes"] if (args.config == GEMV_TRAFFIC["config"] and
@@ -311,6 +337,19 @@ def main():
                                  else None),
                      "bytes_per_launch": gb},
     }
+    # regular BEM tiles: algorithmic flops per solve over the HIP-event time
+    # of the tile launches (both interfaces; touching pairs excluded)
+    asm_flops = 36 * (FLOPS_QP["laplace"] * regular_pairs(prob.tri_m) +
+                      FLOPS_QP["yukawa" if prob.kappa > 0 else "laplace"] * regular_pairs(prob.tri_s))
+
+    def asm_report(leg, peak):
+        ms, cnt = leg["timing"]["assembly"]
+        t = ms * cnt / K * 1e-3
+        return {"kernel": "k_bem_regular (6 x 6 rule, non-touching pairs)", "flops_per_solve": asm_flops,
+                "ms_per_solve": t * 1e3, "tflops": asm_flops / t / 1e12 if t else None, "peak_tflops": peak,
+                "frac": asm_flops / t / 1e12 / peak if t else None}
+
+    out["bem_assembly"] = {"fp64": asm_report(f64, FP64_PEAK_TFLOPS)}
     flops = apply_flops(nm, ns, 0)
     if apply_ms:
         out["coupled_operator_gflops"] = flops / (apply_ms * 1e-3) / 1e9
@@ -322,11 +361,15 @@ def main():
             "value": K / mx["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * mx["elapsed"] / K,
             "latency_s": {"p50": percentile(mx["lat"], 0.5), "p99": percentile(mx["lat"], 0.99)},
             "total_kcal_mol": rm["total"], "rel_energy_err_vs_fp64": abs(rm["total"] - res["total"]) / abs(res["total"]),
+            "rel_err_vs_fp64": {k: abs(rm[k] - res[k]) / abs(res[k]) for k in ("total", "lc", "nc", "dg_omega_i")},
+            "surface_potential_rel_err_vs_fp64": float(np.linalg.norm(mx["u_m"] - f64["u_m"]) /
+                                                       np.linalg.norm(f64["u_m"])),
             "newton_iters": rm["newton_iters"], "gmres_iters_total": rm["gmres_iters_total"],
             "gemv_ms": mg_ms,
             "gemv_gbs": gemv_bytes(nm, ns, 4) / (mg_ms * 1e-3) / 1e9 if mg_ms else None,
             "coupled_operator_gflops": flops / (mx["timing"]["apply"][0] * 1e-3) / 1e9 if mx["timing"]["apply"][0] else None,
         }
+        out["bem_assembly"]["mixed_fp32_eval"] = asm_report(mx, FP32_PEAK_TFLOPS)
     if args.batch > 0:
         out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
                           "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}

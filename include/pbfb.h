@@ -130,6 +130,9 @@ typedef struct {
     int max_omega_it;    /* 50 */
     int gmres_restart;   /* 200 */
     int max_gmres;       /* iterations per linear solve (2000) */
+    int krylov_fp32;     /* PBFB_MIXED only: 1 stores the GMRES basis in FP32, so every restart cycle
+                          * is an FP32-basis inner solve inside FP64 iterative refinement (half the
+                          * basis memory); 0 (default) keeps the basis FP64 */
 } pbfb_solve_opts;
 void pbfb_solve_opts_default(pbfb_solve_opts *o);
 

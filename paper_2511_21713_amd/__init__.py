@@ -40,7 +40,7 @@ class SolveOpts(C.Structure):
                 ("tol_omega", C.c_double), ("l_e", C.c_double), ("omega0_first", C.c_double),
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
-                ("max_gmres", C.c_int)]
+                ("max_gmres", C.c_int), ("krylov_fp32", C.c_int)]
 
 
 class Result(C.Structure):
@@ -111,6 +111,11 @@ def lib():
         L.pbfb_timing.argtypes = [P, C.c_int, C.POINTER(C.c_double), I64P, C.c_int]
         _lib = L
     return _lib
+
+
+def last_error():
+    """Message of the last failing library call on this thread."""
+    return lib().pbfb_last_error().decode()
 
 
 def _check(code):

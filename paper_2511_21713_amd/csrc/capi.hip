@@ -157,8 +157,6 @@ void release_all_scratch(Problem &p)
 // ---------------------------------------------------------------------------
 // event timers
 // ---------------------------------------------------------------------------
-static thread_local std::vector<int> g_open;
-
 void EventTimer::begin(int c, hipStream_t s)
 {
     if (size_t(2 * used + 2) > ev.size()) {
@@ -167,35 +165,50 @@ void EventTimer::begin(int c, hipStream_t s)
             ev.resize(std::max<size_t>(512, 2 * old));
             for (size_t i = old; i < ev.size(); ++i) PB_HIP(hipEventCreate(&ev[i]));
             cls.resize(ev.size() / 2);
+            closed.resize(ev.size() / 2);
         } else {
             drain();
         }
     }
     cls[used] = c;
+    closed[used] = 0;
     PB_HIP(hipEventRecord(ev[2 * used], s));
-    g_open.push_back(used);
+    open.push_back(used);
     ++used;
 }
 
 void EventTimer::end(hipStream_t s)
 {
-    int i = g_open.back();
-    g_open.pop_back();
+    const int i = open.back();
+    open.pop_back();
     PB_HIP(hipEventRecord(ev[2 * i + 1], s));
+    closed[i] = 1;
 }
 
 void EventTimer::drain()
 {
-    if (used == 0) return;
-    PB_HIP(hipEventSynchronize(ev[2 * (used - 1) + 1]));
+    int keep = 0;
     for (int i = 0; i < used; ++i) {
-        float ms = 0.f;
-        PB_HIP(hipEventSynchronize(ev[2 * i + 1]));
-        PB_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
-        sum_ms[cls[i]] += ms;
-        cnt[cls[i]] += 1;
+        if (closed[i]) {
+            float ms = 0.f;
+            PB_HIP(hipEventSynchronize(ev[2 * i + 1]));
+            PB_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+            sum_ms[cls[i]] += ms;
+            cnt[cls[i]] += 1;
+            continue;
+        }
+        // still open: move to the front, keeping its recorded start event
+        if (keep != i) {
+            std::swap(ev[2 * keep], ev[2 * i]);
+            std::swap(ev[2 * keep + 1], ev[2 * i + 1]);
+            cls[keep] = cls[i];
+            closed[keep] = 0;
+            for (int &o : open)
+                if (o == i) o = keep;
+        }
+        ++keep;
     }
-    used = 0;
+    used = keep;
 }
 
 void EventTimer::destroy()
@@ -203,6 +216,8 @@ void EventTimer::destroy()
     for (auto e : ev) (void)hipEventDestroy(e);
     ev.clear();
     cls.clear();
+    closed.clear();
+    open.clear();
     used = 0;
 }
 
@@ -469,6 +484,7 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->max_omega_it = 50;
     o->gmres_restart = 200;
     o->max_gmres = 2000;
+    o->krylov_fp32 = 0;
 }
 
 pbfb_status pbfb_solve(pbfb_problem *pp, const pbfb_solve_opts *o, pbfb_result *res, double *phi_out, int mem,
@@ -491,7 +507,9 @@ pbfb_status pbfb_solve(pbfb_problem *pp, const pbfb_solve_opts *o, pbfb_result *
         PB_HIP(hipMemcpyAsync(phi_out, dout, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
         PB_HIP(hipStreamSynchronize(s));
     }
-    if (st != PBFB_OK) set_error(st == PBFB_ENOTCONV ? "iteration limit reached" : "non-finite residual");
+    // other failures keep the message of the step that failed
+    if (st == PBFB_ENOTCONV) set_error("iteration limit reached");
+    else if (st == PBFB_ENAN) set_error("non-finite residual");
     return st;
     API_END
 }

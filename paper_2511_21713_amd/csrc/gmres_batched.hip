@@ -16,9 +16,16 @@
 //   UPD   -> y = H^{-1} g, x += D^{-1} V y                       -> RES
 //   RES   -> w = b - J x, beta = |w|: beta <= target -> DONE, else V_0 = w/beta -> ARN
 // which is the restarted GMRES of the oracle (true residual at every restart).
+//
+// Mixed precision may store the basis in FP32 (products, projections, norms,
+// Hessenberg, rotations, w and x stay FP64).  A restart cycle is then an
+// FP32-basis inner solve for the correction of the current iterate, and the
+// FP64 true residual b - J x that starts the next cycle is the outer
+// iterative refinement: the tolerance is always decided on that residual.
 #include <algorithm>
 #include <cmath>
 
+#include "gemv_rows.hpp"
 #include "pbfb_internal.hpp"
 
 namespace pbfb {
@@ -28,13 +35,15 @@ enum GSt { G_INIT = 0, G_ARN = 1, G_UPD = 2, G_RES = 3, G_DONE = 4, G_FAIL = 5 }
 struct GDesc {
     const void *Bm, *Bs;
     int64_t ldm, lds, nm, ns;
-    int f32;
+    int f32;  // operator values in FP32
+    int vf32; // Krylov basis stored in FP32
     const int32_t *gm, *gs;
     const int32_t *rowptr, *col;
     const void *val;
     int64_t nn, n;
     const double *dinv;
-    double *V, *w, *xm, *xs, *x;
+    void *V; // (m + 1) x n basis, FP64 or FP32 (vf32)
+    double *w, *xm, *xs, *x;
     const double *b;
     double *H, *cs, *sn, *g, *y, *h1, *h2, *part, *npart, *nrm;
     int *cnt; // completion counter of the x update (index 257)
@@ -54,13 +63,21 @@ struct WItem {
 };
 
 constexpr int CH = 256;      // rows per chunk: one per thread of a workgroup
-constexpr int GROWS = 16;    // GEMV rows per workgroup (4 wavefronts x 4 rows)
+constexpr int GROWS = 4 * GEMV_RW; // GEMV rows per workgroup (4 wavefronts)
 constexpr int SROWS = 32;    // SpMV rows per workgroup (8 lanes per row)
 
-typedef double dvec2 __attribute__((ext_vector_type(2)));
-typedef float fvec4 __attribute__((ext_vector_type(4)));
 
 __device__ inline bool applies(int st) { return st == G_ARN || st == G_RES; }
+
+// basis entry V_i[k], widened to FP64
+__device__ inline double vget(const GDesc &d, int64_t i, int64_t k)
+{
+    return d.vf32 ? double(static_cast<const float *>(d.V)[i * d.n + k]) : static_cast<const double *>(d.V)[i * d.n + k];
+}
+template <typename VT> __device__ inline const VT *vcol(const GDesc &d, int64_t i)
+{
+    return static_cast<const VT *>(d.V) + i * d.n;
+}
 
 // ---------------------------------------------------------------------------
 // apply: pack, dense GEMV, CSR SpMV on the current input of each instance
@@ -73,86 +90,22 @@ __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, con
     const GState s = S[it.inst];
     if (!applies(s.st)) return;
     const GDesc &d = D[it.inst];
-    const double *in = s.st == G_ARN ? d.V + int64_t(s.j) * d.n : d.x;
     const bool sc = s.st == G_ARN;
+    // ARN: D^{-1} V_j, RES: x
+    auto in = [&](int64_t r) { return sc ? vget(d, s.j, r) * d.dinv[r] : d.x[r]; };
     for (int64_t k = it.b + threadIdx.x; k < it.b + CH; k += 256) {
         if (k < d.ldm) {
             double v = 0.0;
-            if (k < d.nm) {
-                const int32_t r = d.gm[k];
-                v = sc ? in[r] * d.dinv[r] : in[r];
-            } else if (k < 2 * d.nm) {
-                const int64_t r = d.nn + (k - d.nm);
-                v = sc ? in[r] * d.dinv[r] : in[r];
-            }
+            if (k < d.nm) v = in(d.gm[k]);
+            else if (k < 2 * d.nm) v = in(d.nn + (k - d.nm));
             d.xm[k] = v;
         }
         if (k < d.lds) {
             double v = 0.0;
-            if (k < d.ns) {
-                const int32_t r = d.gs[k];
-                v = sc ? in[r] * d.dinv[r] : in[r];
-            } else if (k < 2 * d.ns) {
-                const int64_t r = d.nn + d.nm + (k - d.ns);
-                v = sc ? in[r] * d.dinv[r] : in[r];
-            }
+            if (k < d.ns) v = in(d.gs[k]);
+            else if (k < 2 * d.ns) v = in(d.nn + d.nm + (k - d.ns));
             d.xs[k] = v;
         }
-    }
-}
-
-template <typename MT>
-__device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
-                                 int64_t n, int64_t ld, int64_t r0, int lane)
-{
-    constexpr int RW = 4;
-    double acc[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) acc[r] = 0.0;
-    if constexpr (sizeof(MT) == 8) {
-        const dvec2 *xv = reinterpret_cast<const dvec2 *>(x);
-        const dvec2 *rows[RW];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) rows[r] = reinterpret_cast<const dvec2 *>(B + (r0 + r < n ? r0 + r : n - 1) * ld);
-        const int64_t nc = ld / 128;
-#pragma unroll 2
-        for (int64_t c = 0; c < nc; ++c) {
-            const dvec2 xx = xv[c * 64 + lane];
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const dvec2 bb = __builtin_nontemporal_load(rows[r] + c * 64 + lane);
-                acc[r] = fma(bb.x, xx.x, acc[r]);
-                acc[r] = fma(bb.y, xx.y, acc[r]);
-            }
-        }
-    } else {
-        const dvec2 *xv = reinterpret_cast<const dvec2 *>(x);
-        const fvec4 *rows[RW];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) rows[r] = reinterpret_cast<const fvec4 *>(B + (r0 + r < n ? r0 + r : n - 1) * ld);
-        const int64_t nc = ld / 256;
-#pragma unroll 2
-        for (int64_t c = 0; c < nc; ++c) {
-            const dvec2 xa = xv[(c * 64 + lane) * 2], xb = xv[(c * 64 + lane) * 2 + 1];
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const fvec4 bb = __builtin_nontemporal_load(rows[r] + c * 64 + lane);
-                acc[r] = fma(double(bb.x), xa.x, acc[r]);
-                acc[r] = fma(double(bb.y), xa.y, acc[r]);
-                acc[r] = fma(double(bb.z), xb.x, acc[r]);
-                acc[r] = fma(double(bb.w), xb.y, acc[r]);
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RW; ++r)
-        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
-    if (lane < RW && r0 + lane < n) {
-        double v = acc[0];
-#pragma unroll
-        for (int r = 1; r < RW; ++r)
-            if (lane == r) v = acc[r];
-        y[r0 + lane] = v;
     }
 }
 
@@ -164,7 +117,7 @@ __global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, con
     if (!applies(S[it.inst].st)) return;
     const GDesc &d = D[it.inst];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r0 = it.b + wv * 4;
+    const int64_t r0 = it.b + wv * GEMV_RW;
     const int64_t n = it.a == 0 ? d.nm : d.ns;
     if (r0 >= n) return;
     const int64_t ld = it.a == 0 ? d.ldm : d.lds;
@@ -184,23 +137,17 @@ __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, con
     const GDesc &d = D[it.inst];
     const int64_t row = it.b + (threadIdx.x >> 3);
     const int sub = threadIdx.x & 7;
-    const double *in = s.st == G_ARN ? d.V + int64_t(s.j) * d.n : d.x;
     const bool sc = s.st == G_ARN;
+    auto in = [&](int64_t r) { return sc ? vget(d, s.j, r) * d.dinv[r] : d.x[r]; };
     double acc = 0.0;
     if (row < d.nn) {
         const int32_t e = d.rowptr[row + 1];
         if (d.f32) {
             const float *val = static_cast<const float *>(d.val);
-            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) {
-                const int32_t c = d.col[k];
-                acc = fma(double(val[k]), sc ? in[c] * d.dinv[c] : in[c], acc);
-            }
+            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(double(val[k]), in(d.col[k]), acc);
         } else {
             const double *val = static_cast<const double *>(d.val);
-            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) {
-                const int32_t c = d.col[k];
-                acc = fma(val[k], sc ? in[c] * d.dinv[c] : in[c], acc);
-            }
+            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(val[k], in(d.col[k]), acc);
         }
     }
     acc += __shfl_xor(acc, 4);
@@ -232,12 +179,16 @@ __global__ void __launch_bounds__(256) k_bmdot(const WItem *__restrict__ wl, con
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int64_t k = it.b + threadIdx.x; k < it.b + CHB && k < d.n; k += 256) {
-        const double wk = d.w[k];
+    auto body = [&](auto *V0) {
+        for (int64_t k = it.b + threadIdx.x; k < it.b + CHB && k < d.n; k += 256) {
+            const double wk = d.w[k];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (q < kk) acc[q] = fma(d.V[int64_t(i0 + q) * d.n + k], wk, acc[q]);
-    }
+            for (int q = 0; q < 8; ++q)
+                if (q < kk) acc[q] = fma(double(V0[int64_t(q) * d.n + k]), wk, acc[q]);
+        }
+    };
+    if (d.vf32) body(vcol<float>(d, i0));
+    else body(vcol<double>(d, i0));
 #pragma unroll
     for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
     __syncthreads();
@@ -292,7 +243,13 @@ __global__ void __launch_bounds__(256) k_bmsub(const WItem *__restrict__ wl, con
         else if (s.st == G_RES) v = d.b[k] - d.w[k];
         else {
             v = d.w[k];
-            for (int i = 0; i < jj; ++i) v = fma(-hs[i], d.V[int64_t(i) * d.n + k], v);
+            if (d.vf32) {
+                const float *V0 = vcol<float>(d, 0);
+                for (int i = 0; i < jj; ++i) v = fma(-hs[i], double(V0[int64_t(i) * d.n + k]), v);
+            } else {
+                const double *V0 = vcol<double>(d, 0);
+                for (int i = 0; i < jj; ++i) v = fma(-hs[i], V0[int64_t(i) * d.n + k], v);
+            }
         }
         d.w[k] = v;
     }
@@ -335,9 +292,12 @@ __global__ void __launch_bounds__(256) k_bscale(const WItem *__restrict__ wl, co
     const GDesc &d = D[it.inst];
     const double nr = sqrt(*d.nrm);
     const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-    double *dst = d.V + (s.st == G_ARN ? int64_t(s.j + 1) * d.n : 0);
+    const int64_t off = (s.st == G_ARN ? int64_t(s.j + 1) * d.n : 0);
     const int64_t k = it.b + threadIdx.x;
-    if (k < d.n) dst[k] = d.w[k] * inv;
+    if (k < d.n) {
+        if (d.vf32) static_cast<float *>(d.V)[off + k] = float(d.w[k] * inv);
+        else static_cast<double *>(d.V)[off + k] = d.w[k] * inv;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -454,7 +414,13 @@ __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, con
     const int64_t k = it.b + threadIdx.x;
     if (k < d.n) {
         double v = 0.0;
-        for (int i = 0; i < s.j; ++i) v = fma(ys[i], d.V[int64_t(i) * d.n + k], v);
+        if (d.vf32) {
+            const float *V0 = vcol<float>(d, 0);
+            for (int i = 0; i < s.j; ++i) v = fma(ys[i], double(V0[int64_t(i) * d.n + k]), v);
+        } else {
+            const double *V0 = vcol<double>(d, 0);
+            for (int i = 0; i < s.j; ++i) v = fma(ys[i], V0[int64_t(i) * d.n + k], v);
+        }
         d.x[k] += d.dinv[k] * v;
     }
     __syncthreads();
@@ -524,7 +490,9 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.nn = p.nn;
         d.n = n;
         d.dinv = J.dinv;
-        d.V = scratch<double>(p, SCR_BASIS, size_t(m + 1) * n);
+        d.vf32 = J.basis32 && p.precision == PBFB_MIXED;
+        if (d.vf32) d.V = scratch<float>(p, SCR_BASIS32, size_t(m + 1) * n);
+        else d.V = scratch<double>(p, SCR_BASIS, size_t(m + 1) * n);
         d.w = scratch<double>(p, SCR_G0, n);
         d.xm = scratch<double>(p, SCR_XM, d.ldm);
         d.xs = scratch<double>(p, SCR_XS, d.lds);
@@ -640,10 +608,20 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
                 PB_HIP(hipEventSynchronize(BB.ev[old]));
                 if (BB.pinned[old] >= nb) finished = true;
             }
-            // a newer copy may already be complete
+            // a newer copy may already be complete.  A query of a pending
+            // event returns hipErrorNotReady and HIP also records that as the
+            // thread's last error, which the launch checks of the next
+            // iteration would report; it is cleared here (launch errors of
+            // this iteration were checked above).
             for (int k = 1; k <= 2 && !finished && polls - k >= 0; ++k) {
                 const int sl = (polls - k) % 3;
-                if (hipEventQuery(BB.ev[sl]) == hipSuccess && BB.pinned[sl] >= nb) finished = true;
+                const hipError_t q = hipEventQuery(BB.ev[sl]);
+                if (q == hipErrorNotReady) {
+                    (void)hipGetLastError();
+                    break;
+                }
+                PB_HIP(q);
+                if (BB.pinned[sl] >= nb) finished = true;
             }
         }
     }

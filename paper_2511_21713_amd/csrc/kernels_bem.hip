@@ -17,6 +17,15 @@
 //  3. touching pairs (identical, common edge, common vertex) are integrated
 //     with the Sauter-Schwab rules (one wavefront per pair) and added, with
 //     the 1/2 M term, by a row-owned scatter.
+//
+// In mixed precision the regular tiles evaluate the kernels in FP32: each
+// quadrature point is held as an FP32 offset from its triangle's centroid,
+// the centroid difference of a pair is formed in FP64 and rounded once, so
+// x - y never cancels large coordinates in FP32.  The 6-term sums over the
+// source points of a pair are FP32; everything from the pair's 3x3 blocks
+// upward (vertex tiles, gathers, the 1/2 M term) accumulates in FP64, and the
+// touching pairs stay FP64 throughout.  The result is rounded to FP32 once
+// for storage.
 #include <cmath>
 
 #include "pbfb_internal.hpp"
@@ -57,39 +66,70 @@ static inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / 
 constexpr double INV4PI = 0.079577471545947667884441881686257181;
 
 // Morton-ordered copies of the triangle data used by the regular assembly.
+// FP64 evaluation reads m_qp/m_nrm; FP32 evaluation reads m_cen/m_qf/m_nf
+// (whichever pointers are non-null are written).
 __global__ void k_tri_morton(int64_t nt, const int32_t *__restrict__ morton, const int32_t *__restrict__ tri,
                              const double *__restrict__ qp, const double *__restrict__ nrm,
-                             const double *__restrict__ area, int32_t *__restrict__ m_tri,
-                             double *__restrict__ m_qp, double *__restrict__ m_nrm, double *__restrict__ m_area)
+                             const double *__restrict__ area, const int32_t *__restrict__ g,
+                             const double *__restrict__ x, int32_t *__restrict__ m_tri, double *__restrict__ m_qp,
+                             double *__restrict__ m_nrm, double *__restrict__ m_area, double *__restrict__ m_cen,
+                             float *__restrict__ m_qf, float *__restrict__ m_nf)
 {
     int64_t m = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (m >= nt) return;
     int32_t t = morton[m];
-    for (int k = 0; k < 3; ++k) {
-        m_tri[3 * m + k] = tri[3 * t + k];
-        m_nrm[3 * m + k] = nrm[3 * t + k];
-    }
-    for (int k = 0; k < 18; ++k) m_qp[18 * m + k] = qp[18 * t + k];
+    for (int k = 0; k < 3; ++k) m_tri[3 * m + k] = tri[3 * t + k];
     m_area[m] = area[t];
+    if (m_qp) {
+        for (int k = 0; k < 3; ++k) m_nrm[3 * m + k] = nrm[3 * t + k];
+        for (int k = 0; k < 18; ++k) m_qp[18 * m + k] = qp[18 * t + k];
+    }
+    if (m_cen) {
+        double c[3];
+        for (int d = 0; d < 3; ++d)
+            c[d] = (x[3 * g[tri[3 * t]] + d] + x[3 * g[tri[3 * t + 1]] + d] + x[3 * g[tri[3 * t + 2]] + d]) / 3.0;
+        for (int d = 0; d < 3; ++d) {
+            m_cen[3 * m + d] = c[d];
+            m_nf[3 * m + d] = float(nrm[3 * t + d]);
+        }
+        for (int q = 0; q < 6; ++q)
+            for (int d = 0; d < 3; ++d) m_qf[18 * m + 3 * q + d] = float(qp[18 * t + 3 * q + d] - c[d]);
+    }
 }
-
 
 // ---------------------------------------------------------------------------
 // 1. regular tiles
 // ---------------------------------------------------------------------------
-template <bool YUK>
+// quadrature weights times barycentric values, w_q * b_q[k], in FP32
+struct QRule6F {
+    float wb[6][3];
+};
+static QRule6F q6farg()
+{
+    QRule6F r;
+    const Rules &R = rules();
+    for (int q = 0; q < 6; ++q)
+        for (int k = 0; k < 3; ++k) r.wb[q][k] = float(R.tri_w[q] * R.tri_bary[q][k]);
+    return r;
+}
+
+// RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
+// RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
+template <bool YUK, typename RT>
 __global__ void __launch_bounds__(256)
-    k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const double *__restrict__ m_qp,
-                  const double *__restrict__ m_nrm, const double *__restrict__ m_area,
+    k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
+                  const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
                   const int32_t *__restrict__ A_slots, const int32_t *__restrict__ B_pref,
                   const int32_t *__restrict__ B_nv, const int32_t *__restrict__ B_slots, int64_t bA0,
                   int64_t rowbase, double *__restrict__ EV, double *__restrict__ EK, int64_t ldE, double kappa,
-                  QRule6 R)
+                  QRule6 R, QRule6F RF)
 {
-    __shared__ double sX[BA][18];
-    __shared__ double sY[BB][18];
-    __shared__ double sN[BB][3];
+    constexpr bool F32 = sizeof(RT) == 4;
+    __shared__ RT sX[BA][18];
+    __shared__ RT sY[BB][18];
+    __shared__ RT sN[BB][3];
+    __shared__ double sCa[F32 ? BA : 1][3], sCb[F32 ? BB : 1][3];
     __shared__ double sAa[BA], sAb[BB];
     __shared__ int sVa[BA][3], sVb[BB][3];
     __shared__ int sSa[BA * 3][MAXS], sSb[BB * 3][MAXS];
@@ -104,23 +144,25 @@ __global__ void __launch_bounds__(256)
     for (int k = tid; k < BA * 18; k += 256) {
         int tl = k / 18, c = k % 18;
         int64_t m = bA * BA + tl;
-        sX[tl][c] = m < nt ? m_qp[18 * m + c] : 0.0;
+        sX[tl][c] = m < nt ? xq[18 * m + c] : RT(0);
     }
     for (int k = tid; k < BB * 18; k += 256) {
         int sl = k / 18, c = k % 18;
         int64_t m = bB * BB + sl;
-        sY[sl][c] = m < nt ? m_qp[18 * m + c] : 0.0;
+        sY[sl][c] = m < nt ? xq[18 * m + c] : RT(0);
     }
     if (tid < BB * 3) {
         int sl = tid / 3, c = tid % 3;
         int64_t m = bB * BB + sl;
-        sN[sl][c] = m < nt ? m_nrm[3 * m + c] : 0.0;
+        sN[sl][c] = m < nt ? nq[3 * m + c] : RT(0);
         sVb[sl][c] = m < nt ? m_tri[3 * m + c] : -1;
+        if constexpr (F32) sCb[sl][c] = m < nt ? cen[3 * m + c] : 0.0;
     }
     if (tid < BA * 3) {
         int tl = tid / 3, c = tid % 3;
         int64_t m = bA * BA + tl;
         sVa[tl][c] = m < nt ? m_tri[3 * m + c] : -2;
+        if constexpr (F32) sCa[tl][c] = m < nt ? cen[3 * m + c] : 0.0;
     }
     if (tid < BA) sAa[tid] = (bA * BA + tid) < nt ? m_area[bA * BA + tid] : 0.0;
     if (tid < BB) sAb[tid] = (bB * BB + tid) < nt ? m_area[bB * BB + tid] : 0.0;
@@ -146,28 +188,57 @@ __global__ void __launch_bounds__(256)
             for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
         bool valid = (sVa[tl][0] >= 0) && (sVb[sl][0] >= 0) && !touch;
         if (!valid) continue;
-        double SV[6][3], SK[6][3];
+        // target points relative to the source triangle's frame
+        RT xs[18];
+        if constexpr (F32) {
+            const float c0 = float(sCa[tl][0] - sCb[sl][0]), c1 = float(sCa[tl][1] - sCb[sl][1]),
+                        c2 = float(sCa[tl][2] - sCb[sl][2]);
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                xs[3 * p] = sX[tl][3 * p] + c0;
+                xs[3 * p + 1] = sX[tl][3 * p + 1] + c1;
+                xs[3 * p + 2] = sX[tl][3 * p + 2] + c2;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) xs[k] = sX[tl][k];
+        }
+        RT SV[6][3], SK[6][3];
 #pragma unroll
         for (int p = 0; p < 6; ++p)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) SV[p][b] = SK[p][b] = 0.0;
-        const double n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
+            for (int b = 0; b < 3; ++b) SV[p][b] = SK[p][b] = RT(0);
+        const RT n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
+        const RT kap = RT(kappa);
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const double y0 = sY[sl][3 * q], y1 = sY[sl][3 * q + 1], y2 = sY[sl][3 * q + 2];
-            const double wb0 = R.w[q] * R.b[q][0], wb1 = R.w[q] * R.b[q][1], wb2 = R.w[q] * R.b[q][2];
+            const RT y0 = sY[sl][3 * q], y1 = sY[sl][3 * q + 1], y2 = sY[sl][3 * q + 2];
+            RT wb0, wb1, wb2;
+            if constexpr (F32) {
+                wb0 = RF.wb[q][0];
+                wb1 = RF.wb[q][1];
+                wb2 = RF.wb[q][2];
+            } else {
+                wb0 = R.w[q] * R.b[q][0];
+                wb1 = R.w[q] * R.b[q][1];
+                wb2 = R.w[q] * R.b[q][2];
+            }
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
-                const double d0 = sX[tl][3 * p] - y0, d1 = sX[tl][3 * p + 1] - y1, d2 = sX[tl][3 * p + 2] - y2;
-                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                const double ri = rsqrt(r2);
-                const double dn = d0 * n0 + d1 * n1 + d2 * n2;
-                double gv, gk;
+                const RT d0 = xs[3 * p] - y0, d1 = xs[3 * p + 1] - y1, d2 = xs[3 * p + 2] - y2;
+                const RT r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                RT ri;
+                if constexpr (F32) ri = __builtin_amdgcn_rsqf(r2);
+                else ri = rsqrt(r2);
+                const RT dn = d0 * n0 + d1 * n1 + d2 * n2;
+                RT gv, gk;
                 if (YUK) {
-                    const double r = r2 * ri;
-                    const double e = exp(-kappa * r);
+                    const RT r = r2 * ri;
+                    RT e;
+                    if constexpr (F32) e = __builtin_amdgcn_exp2f(-1.44269504088896341f * kap * r);
+                    else e = exp(-kap * r);
                     gv = e * ri;
-                    gk = dn * (1.0 + kappa * r) * e * ri * ri * ri;
+                    gk = dn * (RT(1) + kap * r) * e * ri * ri * ri;
                 } else {
                     gv = ri;
                     gk = dn * ri * ri * ri;
@@ -188,8 +259,8 @@ __global__ void __launch_bounds__(256)
                 const double wa = sc * R.w[p] * R.b[p][a];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    Vl[h][3 * a + b] += wa * SV[p][b];
-                    Kl[h][3 * a + b] += wa * SK[p][b];
+                    Vl[h][3 * a + b] += wa * double(SV[p][b]);
+                    Kl[h][3 * a + b] += wa * double(SK[p][b]);
                 }
             }
         }
@@ -492,9 +563,17 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         A.release();
         S.B = nullptr;
         S.m_tri = A.alloc<int32_t>(3 * T.nt);
-        S.m_qp = A.alloc<double>(18 * T.nt);
-        S.m_nrm = A.alloc<double>(3 * T.nt);
         S.m_area = A.alloc<double>(T.nt);
+        S.m_qp = S.m_nrm = S.m_cen = nullptr;
+        S.m_qf = S.m_nf = nullptr;
+        if (p.precision == PBFB_MIXED) {
+            S.m_cen = A.alloc<double>(3 * T.nt);
+            S.m_qf = A.alloc<float>(18 * T.nt);
+            S.m_nf = A.alloc<float>(3 * T.nt);
+        } else {
+            S.m_qp = A.alloc<double>(18 * T.nt);
+            S.m_nrm = A.alloc<double>(3 * T.nt);
+        }
         S.morton = A.upload(T.morton, s);
         S.A_pref = A.upload(T.A_pref, s);
         S.A_nv = A.upload(T.A_nv, s);
@@ -527,7 +606,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     }
     int32_t *d_tptau = S.tp_tau;
     hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, S.morton, S.tri, S.qp, S.nrm,
-                       S.area, S.m_tri, S.m_qp, S.m_nrm, S.m_area);
+                       S.area, S.g, p.d_x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
 
     const int64_t nv = T.nv, ld = bem_ld(nv);
     // FP64 storage assembles in place; mixed precision assembles in an FP64
@@ -538,6 +617,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     // chunk the target blocks so that E stays within ~8 GB per operator
     const int64_t max_rows = std::max<int64_t>(BA * 3, (int64_t(1) << 30) / std::max<int64_t>(T.SB, 1));
     QRule6 R = q6arg();
+    QRule6F RF = q6farg();
     int64_t b0 = 0;
     bool first = true;
     while (b0 < T.nbA) {
@@ -549,14 +629,18 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         double *EK = scratch<double>(p, SCR_E1, rows * T.SB);
         dim3 grid(unsigned(T.nbB), unsigned(b1 - b0));
         if (p.timing) p.timer.begin(T_ASM, s);
-        if (yuk)
-            hipLaunchKernelGGL(k_bem_regular<true>, grid, dim3(256), 0, s, T.nt, S.m_tri, S.m_qp, S.m_nrm, S.m_area,
-                               S.A_pref, S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]),
-                               EV, EK, T.SB, kappa, R);
-        else
-            hipLaunchKernelGGL(k_bem_regular<false>, grid, dim3(256), 0, s, T.nt, S.m_tri, S.m_qp, S.m_nrm, S.m_area,
-                               S.A_pref, S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]),
-                               EV, EK, T.SB, kappa, R);
+#define PB_REGULAR(Y, RT, XQ, NQ, CEN)                                                                           \
+    hipLaunchKernelGGL((k_bem_regular<Y, RT>), grid, dim3(256), 0, s, T.nt, S.m_tri, XQ, NQ, CEN, S.m_area, S.A_pref, \
+                       S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]), EV, EK, T.SB,      \
+                       kappa, R, RF)
+        if (p.precision == PBFB_MIXED) {
+            if (yuk) PB_REGULAR(true, float, S.m_qf, S.m_nf, S.m_cen);
+            else PB_REGULAR(false, float, S.m_qf, S.m_nf, S.m_cen);
+        } else {
+            if (yuk) PB_REGULAR(true, double, S.m_qp, S.m_nrm, (const double *)nullptr);
+            else PB_REGULAR(false, double, S.m_qp, S.m_nrm, (const double *)nullptr);
+        }
+#undef PB_REGULAR
         if (p.timing) p.timer.end(s);
         PB_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_bem_pass1, dim3(nblk(T.SB, 256), unsigned(nv)), dim3(256), 0, s, nv, T.SB, S.LA_ptr,

@@ -1,17 +1,15 @@
-// Linear algebra of the coupled operator: surface packing, the dense
-// Galerkin GEMV (the bandwidth-bound hot kernel), the FEM CSR SpMV and the
-// vector kernels of GMRES.  Reductions use a fixed grid and a fixed tree, so
-// every result is bitwise reproducible run to run.
+// Linear algebra of the coupled operator outside GMRES (residuals, the
+// omega search, the C-ABI apply): surface packing, the dense Galerkin GEMV,
+// the FEM CSR SpMV and small vector kernels.  Reductions use a fixed grid
+// and a fixed tree, so every result is bitwise reproducible run to run.
 #include <cmath>
 
+#include "gemv_rows.hpp"
 #include "pbfb_internal.hpp"
 
 namespace pbfb {
 
 static inline unsigned nb_(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
-
-typedef double dvec2 __attribute__((ext_vector_type(2)));
-typedef float fvec4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // packing: x_w = [u(g_w) | lambda_w | 0 pad] for both surfaces
@@ -36,106 +34,20 @@ __global__ void k_pack(int64_t nn, int64_t nm, int64_t ns, int64_t ldm, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// dense GEMV over both surfaces in one launch.  A wavefront owns RW rows and
-// streams them with 16-byte loads; the packed input chunk is loaded once per
-// wavefront and reused for its RW rows.  Row sums are reduced across the
-// wavefront with xor shuffles.  Rows are padded to ld (multiple of 256).
+// dense GEMV over both surfaces in one launch (rows: gemv_rows.hpp)
 // ---------------------------------------------------------------------------
-template <int RW>
+template <typename MT>
 __global__ void __launch_bounds__(256)
-    k_gemv_f64(const double *__restrict__ B0, const double *__restrict__ x0, double *__restrict__ y0, int64_t n0,
-               int64_t ld0, int64_t nblk0, const double *__restrict__ B1, const double *__restrict__ x1,
-               double *__restrict__ y1, int64_t n1, int64_t ld1)
+    k_gemv(const MT *__restrict__ B0, const double *__restrict__ x0, double *__restrict__ y0, int64_t n0,
+           int64_t ld0, int64_t nblk0, const MT *__restrict__ B1, const double *__restrict__ x1,
+           double *__restrict__ y1, int64_t n1, int64_t ld1)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool s1 = blockIdx.x >= nblk0;
-    const double *B = s1 ? B1 : B0;
-    const double *x = s1 ? x1 : x0;
-    double *y = s1 ? y1 : y0;
-    const int64_t n = s1 ? n1 : n0, ld = s1 ? ld1 : ld0;
-    const int64_t r0 = ((s1 ? blockIdx.x - nblk0 : blockIdx.x) * 4 + wv) * RW;
+    const int64_t r0 = ((s1 ? blockIdx.x - nblk0 : blockIdx.x) * 4 + wv) * GEMV_RW;
+    const int64_t n = s1 ? n1 : n0;
     if (r0 >= n) return;
-    double acc[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) acc[r] = 0.0;
-    const dvec2 *xv = reinterpret_cast<const dvec2 *>(x);
-    const int64_t nchunk = ld / 128; // 64 lanes x 2 doubles
-    const dvec2 *rows[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int64_t rr = r0 + r < n ? r0 + r : n - 1;
-        rows[r] = reinterpret_cast<const dvec2 *>(B + rr * ld);
-    }
-#pragma unroll 2
-    for (int64_t c = 0; c < nchunk; ++c) {
-        const dvec2 xx = xv[c * 64 + lane];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            const dvec2 b = __builtin_nontemporal_load(rows[r] + c * 64 + lane);
-            acc[r] = fma(b.x, xx.x, acc[r]);
-            acc[r] = fma(b.y, xx.y, acc[r]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RW; ++r)
-        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
-    if (lane < RW && r0 + lane < n) {
-        double v = acc[0];
-#pragma unroll
-        for (int r = 1; r < RW; ++r)
-            if (lane == r) v = acc[r];
-        y[r0 + lane] = v;
-    }
-}
-
-// FP32 storage, FP64 accumulation (mixed precision)
-template <int RW>
-__global__ void __launch_bounds__(256)
-    k_gemv_f32(const float *__restrict__ B0, const double *__restrict__ x0, double *__restrict__ y0, int64_t n0,
-               int64_t ld0, int64_t nblk0, const float *__restrict__ B1, const double *__restrict__ x1,
-               double *__restrict__ y1, int64_t n1, int64_t ld1)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool s1 = blockIdx.x >= nblk0;
-    const float *B = s1 ? B1 : B0;
-    const double *x = s1 ? x1 : x0;
-    double *y = s1 ? y1 : y0;
-    const int64_t n = s1 ? n1 : n0, ld = s1 ? ld1 : ld0;
-    const int64_t r0 = ((s1 ? blockIdx.x - nblk0 : blockIdx.x) * 4 + wv) * RW;
-    if (r0 >= n) return;
-    double acc[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) acc[r] = 0.0;
-    const int64_t nchunk = ld / 256; // 64 lanes x 4 floats
-    const fvec4 *rows[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int64_t rr = r0 + r < n ? r0 + r : n - 1;
-        rows[r] = reinterpret_cast<const fvec4 *>(B + rr * ld);
-    }
-    const dvec2 *xv = reinterpret_cast<const dvec2 *>(x);
-#pragma unroll 2
-    for (int64_t c = 0; c < nchunk; ++c) {
-        const dvec2 xa = xv[(c * 64 + lane) * 2], xb = xv[(c * 64 + lane) * 2 + 1];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            const fvec4 b = __builtin_nontemporal_load(rows[r] + c * 64 + lane);
-            acc[r] = fma(double(b.x), xa.x, acc[r]);
-            acc[r] = fma(double(b.y), xa.y, acc[r]);
-            acc[r] = fma(double(b.z), xb.x, acc[r]);
-            acc[r] = fma(double(b.w), xb.y, acc[r]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RW; ++r)
-        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
-    if (lane < RW && r0 + lane < n) {
-        double v = acc[0];
-#pragma unroll
-        for (int r = 1; r < RW; ++r)
-            if (lane == r) v = acc[r];
-        y[r0 + lane] = v;
-    }
+    gemv_rows<MT>(s1 ? B1 : B0, s1 ? x1 : x0, s1 ? y1 : y0, n, s1 ? ld1 : ld0, r0, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,14 +83,6 @@ __global__ void k_mul(int64_t n, const double *__restrict__ a, const double *__r
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i < n) y[i] = a[i] * x[i];
-}
-__global__ void k_scale_dev(int64_t n, const double *__restrict__ num, const double *__restrict__ x,
-                            double *__restrict__ y)
-{
-    // y = x / sqrt(num[0]) (normalisation with a device-resident squared norm)
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    const double d = sqrt(num[0]);
-    if (i < n) y[i] = d > 0 ? x[i] / d : 0.0;
 }
 
 constexpr int RED_BLOCKS = 256;
@@ -223,55 +127,6 @@ __global__ void k_reduce_partial(int nb, int k, const double *__restrict__ parti
     if (threadIdx.x == 0) out[j] = red[0];
 }
 
-// h[j] = V_j . w for j < k (basis stored with stride ldv); partials per block
-// of rows: partial[b * kmax + j]
-__global__ void __launch_bounds__(256)
-    k_mdot_partial(int64_t n, int k, const double *__restrict__ Vb, int64_t ldv, const double *__restrict__ w,
-                   double *__restrict__ partial, int kmax)
-{
-    __shared__ double red[8][256];
-    const int j0 = blockIdx.y * 8;
-    const int kk = min(8, k - j0);
-    double s[8];
-    for (int j = 0; j < 8; ++j) s[j] = 0.0;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const double wi = w[i];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (j < kk) s[j] = fma(Vb[(j0 + j) * ldv + i], wi, s[j]);
-    }
-    for (int j = 0; j < 8; ++j) red[j][threadIdx.x] = s[j];
-    __syncthreads();
-    for (int wd = 128; wd > 0; wd >>= 1) {
-        if (threadIdx.x < wd)
-            for (int j = 0; j < 8; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + wd];
-        __syncthreads();
-    }
-    if (threadIdx.x < kk) partial[blockIdx.x * kmax + j0 + threadIdx.x] = red[threadIdx.x][0];
-}
-
-// w -= sum_j h[j] V_j ; hacc[j] += h[j] (thread 0 of block 0)
-__global__ void k_msub(int64_t n, int k, const double *__restrict__ Vb, int64_t ldv, const double *__restrict__ h,
-                       double *__restrict__ w)
-{
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (i >= n) return;
-    double s = w[i];
-    for (int j = 0; j < k; ++j) s = fma(-h[j], Vb[j * ldv + i], s);
-    w[i] = s;
-}
-
-// x += dinv .* (sum_j y_j V_j)
-__global__ void k_update(int64_t n, int k, const double *__restrict__ Vb, int64_t ldv, const double *__restrict__ y,
-                         const double *__restrict__ dinv, double *__restrict__ x)
-{
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int j = 0; j < k; ++j) s = fma(y[j], Vb[j * ldv + i], s);
-    x[i] += dinv[i] * s;
-}
-
 __global__ void k_add_vec(int64_t n, const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ y)
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -283,17 +138,17 @@ __global__ void k_add_vec(int64_t n, const double *__restrict__ a, const double 
 // ===========================================================================
 static void gemv_launch(Problem &p, const double *xm, const double *xs, double *y, hipStream_t s)
 {
-    constexpr int RW = 4;
+    constexpr int RW = GEMV_RW;
     const SurfaceDev &M = p.surf[0], &S = p.surf[1];
     const int64_t ldm = bem_ld(M.nv), lds = bem_ld(S.nv);
     const int64_t nb0 = (M.nv + 4 * RW - 1) / (4 * RW), nb1 = (S.nv + 4 * RW - 1) / (4 * RW);
     double *ym = y + p.nn, *ys = y + p.nn + M.nv;
     if (p.timing) p.timer.begin(T_GEMV, s);
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_gemv_f32<RW>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, (const float *)M.B, xm, ym,
+        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, (const float *)M.B, xm, ym,
                            M.nv, ldm, nb0, (const float *)S.B, xs, ys, S.nv, lds);
     else
-        hipLaunchKernelGGL(k_gemv_f64<RW>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, (const double *)M.B, xm, ym,
+        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, (const double *)M.B, xm, ym,
                            M.nv, ldm, nb0, (const double *)S.B, xs, ys, S.nv, lds);
     if (p.timing) p.timer.end(s);
 }
@@ -361,36 +216,6 @@ void vec_mul(int64_t n, const double *a, const double *x, double *y, hipStream_t
 void vec_add(int64_t n, const double *a, const double *b, double *y, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_vec, dim3(nb_(n, 256)), dim3(256), 0, s, n, a, b, y);
-}
-void vec_scale_dev(int64_t n, const double *num, const double *x, double *y, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scale_dev, dim3(nb_(n, 256)), dim3(256), 0, s, n, num, x, y);
-}
-// h[0..k) = V^T w into device array h (partials in part, size RED_BLOCKS * kmax)
-void basis_dots(int64_t n, int k, const double *Vb, int64_t ldv, const double *w, double *part, int kmax, double *h,
-                hipStream_t s)
-{
-    const int nbx = 128;
-    hipLaunchKernelGGL(k_mdot_partial, dim3(nbx, (k + 7) / 8), dim3(256), 0, s, n, k, Vb, ldv, w, part, kmax);
-    hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, nbx, kmax, part, h);
-}
-void basis_sub(int64_t n, int k, const double *Vb, int64_t ldv, const double *h, double *w, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_msub, dim3(nb_(n, 256)), dim3(256), 0, s, n, k, Vb, ldv, h, w);
-}
-void basis_update(int64_t n, int k, const double *Vb, int64_t ldv, const double *y, const double *dinv, double *x,
-                  hipStream_t s)
-{
-    hipLaunchKernelGGL(k_update, dim3(nb_(n, 256)), dim3(256), 0, s, n, k, Vb, ldv, y, dinv, x);
-}
-void sq_norm_dev(Problem &p, int64_t n, const double *x, double *out_dev, hipStream_t s)
-{
-    double *part = scratch<double>(p, SCR_NRM, RED_BLOCKS);
-    PtrTab T{};
-    T.a[0] = x;
-    T.b[0] = x;
-    hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, n, 1, T, part);
-    hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, s, RED_BLOCKS, 1, part, out_dev);
 }
 
 } // namespace pbfb

@@ -97,7 +97,9 @@ struct SurfaceDev {
     double *qp = nullptr, *nrm = nullptr, *area = nullptr; // original order: 18, 3, 1 per triangle
     // Morton-ordered triangle data for the regular assembly
     int32_t *m_tri = nullptr;
-    double *m_qp = nullptr, *m_nrm = nullptr, *m_area = nullptr;
+    double *m_qp = nullptr, *m_nrm = nullptr, *m_area = nullptr; // FP64 evaluation
+    double *m_cen = nullptr;                                     // FP32 evaluation: FP64 centroids,
+    float *m_qf = nullptr, *m_nf = nullptr;                      // FP32 offsets from them, FP32 normals
     int32_t *A_pref = nullptr, *A_nv = nullptr, *A_loc = nullptr, *A_slots = nullptr;
     int32_t *B_pref = nullptr, *B_nv = nullptr, *B_loc = nullptr, *B_slots = nullptr;
     int32_t *LA_ptr = nullptr, *LA = nullptr, *LA_blk = nullptr, *LB_ptr = nullptr, *LB = nullptr;
@@ -117,9 +119,14 @@ struct Ctx {
 
 enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_NCLASS = 5 };
 
+// HIP-event timing of launch ranges, accumulated per class.  Pairs may nest;
+// when the event pool is full the closed pairs are folded into the sums and
+// the open ones are kept.
 struct EventTimer {
     std::vector<hipEvent_t> ev;   // pairs
     std::vector<int> cls;         // class of each recorded pair
+    std::vector<char> closed;     // end recorded
+    std::vector<int> open;        // stack of open pair indices
     int used = 0;
     double sum_ms[T_NCLASS] = {0};
     int64_t cnt[T_NCLASS] = {0};
@@ -226,6 +233,7 @@ struct GmresJob {
     double tol;
     int restart, maxit;
     int iters, status;
+    int basis32; // Krylov basis in FP32 (mixed precision only)
 };
 void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s);
 void build_precond(Problem &p, double *dinv, hipStream_t s);

@@ -100,7 +100,7 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
     }
     fem_assemble_jacobian(p, r.sch, r.phi, s);
     build_precond(p, r.dinv, s);
-    r.job = GmresJob{&p, r.d, r.D, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0};
+    r.job = GmresJob{&p, r.d, r.D, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0, r.o.krylov_fp32};
     return true;
 }
 
@@ -197,7 +197,7 @@ static bool advance_impl(NewtonRun &r, hipStream_t s)
         // linear component: (A + eps_s kappa^2 M) Phi_L = b
         fem_assemble_jacobian(p, PBFB_LIN, r.phinl, s);
         build_precond(p, r.dinv, s);
-        r.job = GmresJob{&p, p.d_b, r.phil, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0};
+        r.job = GmresJob{&p, p.d_b, r.phil, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0, r.o.krylov_fp32};
         r.phase = PH_LINEAR;
         return true;
     }
@@ -261,7 +261,16 @@ void run_newton(std::vector<NewtonRun *> &runs, hipStream_t s)
         for (NewtonRun *r : runs)
             if (r->phase != PH_DONE && advance(*r, s)) jobs.push_back(&r->job);
         if (jobs.empty()) break;
-        batched_gmres(jobs, s);
+        try {
+            batched_gmres(jobs, s);
+        } catch (const Error &e) {
+            // a device error ends every instance of the batch with its code
+            for (NewtonRun *r : runs)
+                if (r->phase != PH_DONE) {
+                    r->job.status = e.code;
+                    r->message = e.msg;
+                }
+        }
     }
 }
 

@@ -134,6 +134,66 @@ def test_paper_tolerance_solve_iterates_like_oracle(case):
     assert abs(rg["total"] - ro["total"]) < 1e-6 * abs(ro["total"])
 
 
+def test_mixed_precision_matches_oracle(case, ctx):
+    """Mixed precision: regular panel pairs evaluated in FP32 (FP64 pair
+    blocks and gathers), operators stored in FP32, FP32 Krylov basis inside
+    FP64 restarts.  Bars: stored blocks within 1e-6 of the row maximum (FP32
+    rounding of kernel values and of the stored entry), energy and surface
+    potential of a tight solve within 1e-5 of the FP64 oracle."""
+    import paper_2511_21713_amd as pb
+    name, prob, o, g64 = case
+    gm = gpu_problem(ctx, prob, precision=pb.MIXED)
+    for surf in (0, 1):
+        V, K = o.bem_dense(surf)
+        nv = V.shape[0]
+        M = np.stack([o.surface_mass_apply(surf, e) for e in np.eye(nv)], 1)
+        Kp_ref = 0.5 * M + (K if surf == 0 else -K)
+        Vp_ref = -V if surf == 0 else V
+        Vp, Kp = gm.export_bem(surf)
+        for A, B in ((Vp, Vp_ref), (Kp, Kp_ref)):
+            err = (np.abs(A - B) / np.abs(B).max(1, keepdims=True)).max()
+            log(f"  {name} mixed surf {surf} entrywise rel err {err:.2e}")
+            assert err < 1e-6
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    ro, pl, pnl = o.solve(**kw)
+    gs = o.surface_nodes(0)
+    u_ora = (pl + pnl)[gs]
+    for basis32 in (0, 1):
+        phi = np.zeros(2 * o.n)
+        rm = gm.solve(phi_out=phi, krylov_fp32=basis32, **kw)
+        u_mix = (phi[:o.n] + phi[o.n:])[gs]
+        eE = abs(rm["total"] - ro["total"]) / abs(ro["total"])
+        eU = np.linalg.norm(u_mix - u_ora) / np.linalg.norm(u_ora)
+        log(f"  {name} mixed (FP32 basis {basis32}): total {rm['total']:.10f} vs {ro['total']:.10f}: "
+            f"energy {eE:.2e}, potential {eU:.2e}, gmres {rm['gmres_iters_total']}")
+        assert rm["status"] == 0
+        assert eE < 1e-5 and eU < 1e-5
+    gm.close()
+
+
+def test_timed_solves_repeat(ctx):
+    """Event timing on across several solves: the timer's event pool fills
+    and is folded while timed ranges are open; every solve must still end
+    normally with the same result."""
+    prob = pbgen.make_problem(**CASES["sphere_n4"])
+    g = gpu_problem(ctx, prob)
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    g.timing_enable(True)
+    g.timing(0, reset=True)
+    totals = []
+    for k in range(6):
+        g.reset_operators()
+        r = g.solve(**kw)
+        assert r["status"] == 0
+        totals.append(r["total"])
+    ms, cnt = g.timing(0)
+    log(f"  timed solves: {len(totals)} solves, {cnt} timed applies, {ms:.4f} ms each")
+    # three timed ranges per apply (apply, GEMV, SpMV): the 4096-pair pool fills several times
+    assert 3 * cnt > 2 * 4096 and ms > 0
+    assert all(t == totals[0] for t in totals)
+    g.close()
+
+
 def test_fixed_relaxation_sphere_config():
     # the charged-sphere workload: plain FP64 Newton with omega = 0.5
     import paper_2511_21713_amd as pb
