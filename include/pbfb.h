@@ -133,7 +133,17 @@ typedef struct {
     int krylov_fp32;     /* PBFB_MIXED only: 1 stores the GMRES basis in FP32, so every restart cycle
                           * is an FP32-basis inner solve inside FP64 iterative refinement (half the
                           * basis memory); 0 (default) keeps the basis FP64 */
+    int precond;         /* right preconditioner of GMRES (the paper leaves it open):
+                          * PBFB_PC_CHEB_SPAI (default): block diagonal; FEM block F = A + J_N(u):
+                          *   cheb_degree terms of the Jacobi-scaled Chebyshev iteration for F z = r
+                          *   from z = 0 on [lmax / cheb_ratio, lmax], lmax = max_i sum_j |F_ij| / F_ii;
+                          *   single-layer blocks: sparse approximate inverse on each vertex 1-ring
+                          *   (row i minimises || m^T V' - e_i^T ||_2);
+                          * PBFB_PC_DIAG: inverse of the diagonal of J */
+    int cheb_degree;     /* 8 (1..64) */
+    double cheb_ratio;   /* 30 (> 1) */
 } pbfb_solve_opts;
+enum { PBFB_PC_DIAG = 0, PBFB_PC_CHEB_SPAI = 1 };
 void pbfb_solve_opts_default(pbfb_solve_opts *o);
 
 typedef struct {
@@ -145,6 +155,8 @@ typedef struct {
     int omega_iters[64];
     double t_setup_s; /* from the start of the call (batch: of the batch; server: admission) to the end of setup */
     double t_solve_s; /* from the end of setup to the result */
+    int applies;      /* coupled-operator applications performed (Krylov steps, restart residuals, Newton residuals
+                       * and relaxation-search products) */
 } pbfb_result;
 
 /* Full solve: linear component Phi_L, Newton on Phi_NL, energy.  phi_out
@@ -201,7 +213,11 @@ pbfb_status pbfb_export_rhs(pbfb_problem *p, double *b);
  * event pair; pbfb_timing returns the average duration (ms) and the number
  * of launches since the last reset for: which = 0 coupled apply (dense GEMV +
  * FEM SpMV), 1 dense GEMV, 2 FEM SpMV, 3 regular BEM assembly, 4 touching-
- * panel integrals.  pbfb_timing synchronises the problem's last stream. */
+ * panel integrals, 5 GMRES preconditioner.  Batched GMRES launches its
+ * kernels for every iteration of the batch, so an instance that is between
+ * cycles or already converged is counted with a launch that returns at once;
+ * pbfb_result.applies counts the applications that did work.
+ * pbfb_timing synchronises the problem's last stream. */
 pbfb_status pbfb_timing_enable(pbfb_problem *p, int on);
 pbfb_status pbfb_timing(pbfb_problem *p, int which, double *avg_ms, int64_t *count, int reset);
 

@@ -24,7 +24,11 @@ class Opts(C.Structure):
                 ("tol_omega", C.c_double), ("l_e", C.c_double), ("omega0_first", C.c_double),
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
-                ("max_gmres", C.c_int)]
+                ("max_gmres", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
+                ("cheb_ratio", C.c_double)]
+
+
+PC_DIAG, PC_CHEB_SPAI = 0, 1
 
 
 class Result(C.Structure):
@@ -81,6 +85,14 @@ def lib():
         L.pbref_jacobian_rows.argtypes = [P, C.c_int, dp, dp, C.c_int64, lp, dp]
         L.pbref_opts_default.argtypes = [C.POINTER(Opts)]
         L.pbref_gmres.argtypes = [P, C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.pbref_gmres_pc.argtypes = [P, C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.c_double, C.POINTER(C.c_int)]
+        L.pbref_surface_ring.restype = C.c_int64
+        L.pbref_surface_ring.argtypes = [P, C.c_int, ip, ip]
+        L.pbref_spai_rows.argtypes = [C.c_int64, dp, ip, ip, dp]
+        L.pbref_fem_gershgorin.restype = C.c_double
+        L.pbref_fem_gershgorin.argtypes = [P, C.c_int, dp]
+        L.pbref_cheb_diag.argtypes = [C.c_int64, dp, dp, C.c_double, C.c_double, C.c_int, dp, dp]
         L.pbref_solve.argtypes = [P, C.POINTER(Opts), C.POINTER(Result), dp, dp]
         L.pbref_energy.argtypes = [P, dp, dp, dp]
         L.pbref_fd.argtypes = [P, C.c_int, dp, dp, C.c_double, dp]
@@ -132,6 +144,21 @@ def rule_tri_collapsed(m):
     b = np.zeros((m * m, 3)); w = np.zeros(m * m)
     lib().pbref_rule_tri_collapsed(m, _d(b), _d(w))
     return b, w
+
+
+def spai_rows(B, ptr, col):
+    """Rows of the sparse approximate inverse of the dense matrix B on the pattern (ptr, col)."""
+    B = _f64(B); ptr = np.ascontiguousarray(ptr, np.int32); col = np.ascontiguousarray(col, np.int32)
+    val = np.zeros(col.size)
+    st = lib().pbref_spai_rows(B.shape[0], _d(B), _i(ptr), _i(col), _d(val))
+    return val, st
+
+
+def cheb_diag(fdiag, dinv, lmax, ratio, k, r):
+    """The Chebyshev terms of the FEM-block preconditioner for a diagonal F."""
+    fdiag = _f64(fdiag); dinv = _f64(dinv); r = _f64(r); z = np.zeros(r.size)
+    lib().pbref_cheb_diag(r.size, _d(fdiag), _d(dinv), lmax, ratio, k, _d(r), _d(z))
+    return z
 
 
 def default_opts(**kw):
@@ -275,10 +302,22 @@ class Oracle:
         lib().pbref_jacobian_rows(self.h, scheme, _d(phi), _d(v), rows.size, _l(rows), _d(out))
         return out
 
-    def gmres(self, scheme, phi, b, tol=1e-10, restart=200, maxit=5000):
+    def gmres(self, scheme, phi, b, tol=1e-10, restart=200, maxit=5000, precond=PC_DIAG, cheb_degree=8,
+              cheb_ratio=30.0):
         phi = _f64(phi); b = _f64(b); x = np.zeros(self.n); it = C.c_int(0)
-        st = lib().pbref_gmres(self.h, scheme, _d(phi), _d(b), _d(x), tol, restart, maxit, C.byref(it))
+        st = lib().pbref_gmres_pc(self.h, scheme, _d(phi), _d(b), _d(x), tol, restart, maxit, precond,
+                                  cheb_degree, cheb_ratio, C.byref(it))
         return x, st, it.value
+
+    def surface_ring(self, surf):
+        nnz = lib().pbref_surface_ring(self.h, surf, None, None)
+        nv = len(self.surface_nodes(surf))
+        ptr = np.zeros(nv + 1, np.int32); col = np.zeros(nnz, np.int32)
+        lib().pbref_surface_ring(self.h, surf, _i(ptr), _i(col))
+        return ptr, col
+
+    def fem_gershgorin(self, scheme, u):
+        return lib().pbref_fem_gershgorin(self.h, scheme, _d(_f64(u)))
 
     def solve(self, **opts):
         o = default_opts(**opts)

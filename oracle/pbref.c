@@ -1147,16 +1147,298 @@ static void precond_diag(pbref *p, int scheme, const double *phi, double *dinv)
     for (int64_t i = 0; i < ns; ++i) dinv[nn + nm + i] = 1.0 / (p->s[1].V[i * ns + i]);
 }
 
-/* Solve J_scheme(phi) x = b to ||b - J x|| <= tol ||b||, x0 = 0. */
-int pbref_gmres(pbref *p, int scheme, const double *phi, const double *b, double *x, double tol, int restart,
-                int maxit, int *iters)
+/* The paper leaves the GMRES preconditioner open.  Two right preconditioners:
+ *
+ * PBREF_PC_DIAG: the inverse of the diagonal of J.
+ *
+ * PBREF_PC_CHEB_SPAI: block diagonal.
+ *   FEM block F = A + J_scheme(u): k terms of the Chebyshev iteration for
+ *   F z = r started from z = 0 with Jacobi scaling D = diag(F) (Saad,
+ *   Iterative Methods for Sparse Linear Systems, Chebyshev acceleration), on
+ *   the interval [lmax / ratio, lmax] with lmax the Gershgorin bound
+ *   max_i sum_j |F_ij| / F_ii of D^-1 F.  The k terms form a fixed polynomial
+ *   in D^-1 F, so the preconditioner is one linear operator.
+ *   Boundary blocks B (the single-layer blocks of the operator: -V0 on
+ *   Gamma_m, +Vk on Gamma_s): a sparse approximate inverse M whose row i is
+ *   supported on the vertex i and its triangle neighbours and minimises
+ *   || m^T B - e_i^T ||_2 (normal equations, Cholesky). */
+
+/* row i of the 1-ring pattern: i and every vertex sharing a triangle with it, ascending */
+int64_t pbref_surface_ring(const pbref *p, int surf, int32_t *ptr, int32_t *col)
+{
+    const surface *S = &p->s[surf];
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < S->nv; ++i) {
+        int32_t lst[256];
+        int m = 0;
+        lst[m++] = (int32_t)i;
+        for (int32_t e = S->v2t_ptr[i]; e < S->v2t_ptr[i + 1]; ++e) {
+            int64_t t = S->v2t[e];
+            for (int b = 0; b < 3; ++b) {
+                int32_t j = S->tri[3 * t + b];
+                int seen = 0;
+                for (int k = 0; k < m; ++k) seen |= lst[k] == j;
+                if (!seen && m < 256) lst[m++] = j;
+            }
+        }
+        for (int a = 1; a < m; ++a) /* insertion sort */
+            for (int b = a; b > 0 && lst[b - 1] > lst[b]; --b) {
+                int32_t t = lst[b];
+                lst[b] = lst[b - 1];
+                lst[b - 1] = t;
+            }
+        if (ptr) ptr[i] = (int32_t)nnz;
+        if (col) memcpy(col + nnz, lst, sizeof(int32_t) * m);
+        nnz += m;
+    }
+    if (ptr) ptr[S->nv] = (int32_t)nnz;
+    return nnz;
+}
+
+/* rows of the sparse approximate inverse of a dense n x n matrix B on the
+ * given pattern; returns 0, or -1 if a Gram matrix is not positive definite */
+int pbref_spai_rows(int64_t n, const double *B, const int32_t *ptr, const int32_t *col, double *val)
+{
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : err)
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *P = col + ptr[i];
+        int m = ptr[i + 1] - ptr[i];
+        double G[64][64], r[64];
+        if (m > 64) {
+            err |= 1;
+            continue;
+        }
+        for (int a = 0; a < m; ++a) {
+            r[a] = B[(int64_t)P[a] * n + i];
+            for (int b = 0; b <= a; ++b) {
+                double s = 0.0;
+                for (int64_t c = 0; c < n; ++c) s += B[(int64_t)P[a] * n + c] * B[(int64_t)P[b] * n + c];
+                G[a][b] = G[b][a] = s;
+            }
+        }
+        /* Cholesky G = L L^T in place (lower triangle), then two triangular solves */
+        for (int a = 0; a < m; ++a) {
+            double d = G[a][a];
+            for (int k = 0; k < a; ++k) d -= G[a][k] * G[a][k];
+            if (!(d > 0.0)) {
+                err |= 1;
+                break;
+            }
+            G[a][a] = sqrt(d);
+            for (int b = a + 1; b < m; ++b) {
+                double s = G[b][a];
+                for (int k = 0; k < a; ++k) s -= G[b][k] * G[a][k];
+                G[b][a] = s / G[a][a];
+            }
+        }
+        for (int a = 0; a < m; ++a) {
+            double s = r[a];
+            for (int k = 0; k < a; ++k) s -= G[a][k] * r[k];
+            r[a] = s / G[a][a];
+        }
+        for (int a = m - 1; a >= 0; --a) {
+            double s = r[a];
+            for (int k = a + 1; k < m; ++k) s -= G[k][a] * r[k];
+            r[a] = s / G[a][a];
+        }
+        for (int a = 0; a < m; ++a) val[ptr[i] + a] = r[a];
+    }
+    return err ? -1 : 0;
+}
+
+/* entries of row i of F = A + J_scheme(u), assembled from the tets at i */
+static int fem_row(const pbref *p, int scheme, const double *u, int64_t i, int32_t *cols, double *vals)
+{
+    double c = p->eps_s * p->kappa * p->kappa;
+    int m = 0;
+    for (int32_t e = p->n2t_ptr[i]; e < p->n2t_ptr[i + 1]; ++e) {
+        int64_t t = p->n2t[e];
+        const int32_t *T = p->tet + 4 * t;
+        int a = 0;
+        while (T[a] != i) ++a;
+        double G[4][3], vol;
+        tet_geom(p, t, G, &vol);
+        for (int b = 0; b < 4; ++b) {
+            double s = p->eps_s * vol * vdot(G[a], G[b]);
+            for (int q = 0; q < 27; ++q) {
+                const double *l = p->tq_b + 4 * q;
+                double uh = 0.0;
+                for (int k = 0; k < 4; ++k) uh += l[k] * u[T[k]];
+                s += c * vol * p->tq_w[q] * sch_d1(scheme, uh) * l[a] * l[b];
+            }
+            int k = 0;
+            while (k < m && cols[k] != T[b]) ++k;
+            if (k == m) {
+                if (m == 128) return -1;
+                cols[m] = T[b];
+                vals[m++] = 0.0;
+            }
+            vals[k] += s;
+        }
+    }
+    return m;
+}
+
+double pbref_fem_gershgorin(const pbref *p, int scheme, const double *u)
+{
+    double best = 0.0;
+    for (int64_t i = 0; i < p->nn; ++i) {
+        int32_t cols[128];
+        double vals[128], sum = 0.0, dg = 0.0;
+        int m = fem_row(p, scheme, u, i, cols, vals);
+        if (m < 0) return NAN;
+        for (int k = 0; k < m; ++k) {
+            sum += fabs(vals[k]);
+            if (cols[k] == i) dg = vals[k];
+        }
+        best = fmax(best, sum / dg);
+    }
+    return best;
+}
+
+typedef void (*lin_apply)(const void *ctx, const double *in, double *out);
+
+/* k terms of the Jacobi-scaled Chebyshev iteration for F z = r, z0 = 0 */
+static void cheb_terms(int64_t n, lin_apply F, const void *ctx, const double *dinv, double lmax, double ratio, int k,
+                       const double *r, double *z)
+{
+    double lo = lmax / ratio, theta = 0.5 * (lmax + lo), delta = 0.5 * (lmax - lo);
+    double sigma = theta / delta, rho = 1.0 / sigma;
+    double *d = malloc(sizeof(double) * n), *res = malloc(sizeof(double) * n);
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = dinv[i] * r[i] / theta;
+        z[i] = 0.0;
+    }
+    for (int s = 0; s < k; ++s) {
+        for (int64_t i = 0; i < n; ++i) z[i] += d[i];
+        if (s == k - 1) break;
+        F(ctx, z, res);
+        double rho1 = 1.0 / (2.0 * sigma - rho);
+        for (int64_t i = 0; i < n; ++i) d[i] = rho1 * rho * d[i] + 2.0 * rho1 / delta * dinv[i] * (r[i] - res[i]);
+        rho = rho1;
+    }
+    free(d);
+    free(res);
+}
+
+typedef struct {
+    int64_t n;
+    const double *f;
+} diag_ctx;
+static void diag_apply(const void *ctx, const double *in, double *out)
+{
+    const diag_ctx *c = ctx;
+    for (int64_t i = 0; i < c->n; ++i) out[i] = c->f[i] * in[i];
+}
+
+/* the Chebyshev terms for a diagonal F (test hook: the residual polynomial
+ * has a closed form there) */
+void pbref_cheb_diag(int64_t n, const double *fdiag, const double *dinv, double lmax, double ratio, int k,
+                     const double *r, double *z)
+{
+    diag_ctx c = {n, fdiag};
+    cheb_terms(n, diag_apply, &c, dinv, lmax, ratio, k, r, z);
+}
+
+typedef struct {
+    const pbref *p;
+    int scheme;
+    const double *u;
+    double *tmp;
+} fem_ctx;
+static void fem_block_apply(const void *ctx, const double *in, double *out)
+{
+    const fem_ctx *c = ctx;
+    stiffness_apply(c->p, in, out);
+    pbref_fem_jacobian(c->p, c->scheme, c->u, in, c->tmp);
+    for (int64_t i = 0; i < c->p->nn; ++i) out[i] += c->tmp[i];
+}
+
+typedef struct {
+    int mode, k;
+    double ratio, lmax;
+    int scheme;
+    const double *u;
+    double *dinv;
+    int32_t *sp_ptr[2], *sp_col[2];
+    double *sp_val[2];
+} precond;
+
+static int precond_build(pbref *p, int scheme, const double *phi, int mode, int k, double ratio, precond *P)
+{
+    memset(P, 0, sizeof *P);
+    int64_t n = nunk(p);
+    P->mode = mode;
+    P->k = k;
+    P->ratio = ratio;
+    P->scheme = scheme;
+    P->u = phi;
+    P->dinv = malloc(sizeof(double) * n);
+    precond_diag(p, scheme, phi, P->dinv);
+    if (mode == PBREF_PC_DIAG) return 0;
+    P->lmax = pbref_fem_gershgorin(p, scheme, phi);
+    if (!isfinite(P->lmax)) return -1;
+    for (int w = 0; w < 2; ++w) {
+        const surface *S = &p->s[w];
+        int64_t nnz = pbref_surface_ring(p, w, NULL, NULL);
+        P->sp_ptr[w] = malloc(sizeof(int32_t) * (S->nv + 1));
+        P->sp_col[w] = malloc(sizeof(int32_t) * nnz);
+        P->sp_val[w] = malloc(sizeof(double) * nnz);
+        pbref_surface_ring(p, w, P->sp_ptr[w], P->sp_col[w]);
+        if (pbref_spai_rows(S->nv, S->V, P->sp_ptr[w], P->sp_col[w], P->sp_val[w])) return -1;
+        if (w == 0) /* the Gamma_m block is -V0 */
+            for (int64_t e = 0; e < nnz; ++e) P->sp_val[w][e] = -P->sp_val[w][e];
+    }
+    return 0;
+}
+
+static void precond_free(precond *P)
+{
+    free(P->dinv);
+    for (int w = 0; w < 2; ++w) {
+        free(P->sp_ptr[w]);
+        free(P->sp_col[w]);
+        free(P->sp_val[w]);
+    }
+}
+
+/* z = P^-1 v */
+static void precond_apply(pbref *p, const precond *P, const double *v, double *z)
+{
+    int64_t n = nunk(p), nn = p->nn;
+    if (P->mode == PBREF_PC_DIAG) {
+        for (int64_t i = 0; i < n; ++i) z[i] = P->dinv[i] * v[i];
+        return;
+    }
+    fem_ctx c = {p, P->scheme, P->u, malloc(sizeof(double) * nn)};
+    cheb_terms(nn, fem_block_apply, &c, P->dinv, P->lmax, P->ratio, P->k, v, z);
+    free(c.tmp);
+    int64_t off = nn;
+    for (int w = 0; w < 2; ++w) {
+        const surface *S = &p->s[w];
+        for (int64_t i = 0; i < S->nv; ++i) {
+            double s = 0.0;
+            for (int32_t e = P->sp_ptr[w][i]; e < P->sp_ptr[w][i + 1]; ++e) s += P->sp_val[w][e] * v[off + P->sp_col[w][e]];
+            z[off + i] = s;
+        }
+        off += S->nv;
+    }
+}
+
+/* Solve J_scheme(phi) x = b to ||b - J x|| <= tol ||b||, x0 = 0, right preconditioned. */
+int pbref_gmres_pc(pbref *p, int scheme, const double *phi, const double *b, double *x, double tol, int restart,
+                   int maxit, int pc, int cheb_degree, double cheb_ratio, int *iters)
 {
     int r = need_dense(p);
     if (r) return r;
     int64_t n = nunk(p);
     int m = restart;
-    double *dinv = malloc(sizeof(double) * n);
-    precond_diag(p, scheme, phi, dinv);
+    precond P;
+    if (precond_build(p, scheme, phi, pc, cheb_degree, cheb_ratio, &P)) {
+        precond_free(&P);
+        return -7;
+    }
     double *Vb = malloc(sizeof(double) * n * (m + 1));
     double *H = calloc((size_t)(m + 1) * m, sizeof(double));
     double *cs = malloc(sizeof(double) * m), *sn = malloc(sizeof(double) * m), *g = malloc(sizeof(double) * (m + 1));
@@ -1187,7 +1469,7 @@ int pbref_gmres(pbref *p, int scheme, const double *phi, const double *b, double
         int j = 0;
         for (; j < m && total < maxit;) {
             double *vj = Vb + (size_t)j * n, *vn = Vb + (size_t)(j + 1) * n;
-            for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * vj[i];
+            precond_apply(p, &P, vj, z);
             pbref_apply_jacobian(p, scheme, phi, z, w);
             ++total;
             for (int i = 0; i <= j; ++i) { /* modified Gram-Schmidt */
@@ -1221,15 +1503,16 @@ int pbref_gmres(pbref *p, int scheme, const double *phi, const double *b, double
             for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * m + k] * y[k];
             y[i] = s / H[(size_t)i * m + i];
         }
-        memset(z, 0, sizeof(double) * n);
+        memset(res, 0, sizeof(double) * n);
         for (int i = 0; i < j; ++i)
-            for (int64_t k = 0; k < n; ++k) z[k] += y[i] * Vb[(size_t)i * n + k];
-        for (int64_t k = 0; k < n; ++k) x[k] += dinv[k] * z[k];
+            for (int64_t k = 0; k < n; ++k) res[k] += y[i] * Vb[(size_t)i * n + k];
+        precond_apply(p, &P, res, z);
+        for (int64_t k = 0; k < n; ++k) x[k] += z[k];
         free(y);
     }
 done:
     *iters = total;
-    free(dinv);
+    precond_free(&P);
     free(Vb);
     free(H);
     free(cs);
@@ -1248,6 +1531,12 @@ done:
 /* u_r(x) = int_{Gamma_m} [g0(x,y) lam_m(y) - dg0/dn_y(x,y) u(y)] dy, the
  * reaction potential of the interior representation formula (eq.
  * Potential_in_Omega_m), with the regular triangle rule. */
+int pbref_gmres(pbref *p, int scheme, const double *phi, const double *b, double *x, double tol, int restart,
+                int maxit, int *iters)
+{
+    return pbref_gmres_pc(p, scheme, phi, b, x, tol, restart, maxit, PBREF_PC_DIAG, 1, 1.0, iters);
+}
+
 int pbref_reaction_potential(const pbref *p, const double *phi, int64_t np, const double *pts, double *out)
 {
     const surface *S = &p->s[0];
@@ -1330,6 +1619,9 @@ void pbref_opts_default(pbref_opts *o)
     o->max_omega_it = 50;
     o->gmres_restart = 200;
     o->max_gmres = 2000;
+    o->precond = PBREF_PC_CHEB_SPAI;
+    o->cheb_degree = 8;
+    o->cheb_ratio = 30.0;
 }
 
 static int all_finite(int64_t n, const double *x)
@@ -1457,7 +1749,8 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
     /* 1. linear component: (A + eps_s kappa^2 M) Phi_L = b */
     double tol = o->tol_gr0;
     int it;
-    int st = pbref_gmres(p, PBREF_LIN, b /*unused for LIN*/, b, phi_lin, tol, o->gmres_restart, o->max_gmres, &it);
+    int st = pbref_gmres_pc(p, PBREF_LIN, b /*u: unused for LIN*/, b, phi_lin, tol, o->gmres_restart, o->max_gmres,
+                            o->precond, o->cheb_degree, o->cheb_ratio, &it);
     res->gmres_lin = it;
     res->gmres_iters_total = it;
     memset(phi_nl, 0, sizeof(double) * n);
@@ -1478,7 +1771,8 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
             break;
         }
         /* J_s(Phi) Delta = d */
-        st = pbref_gmres(p, s, phi, d, D, tol, o->gmres_restart, o->max_gmres, &it);
+        st = pbref_gmres_pc(p, s, phi, d, D, tol, o->gmres_restart, o->max_gmres, o->precond, o->cheb_degree,
+                            o->cheb_ratio, &it);
         int idx = k - 1 < 64 ? k - 1 : 63;
         res->gmres_iters[idx] = it;
         res->gmres_iters_total += it;

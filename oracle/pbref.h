@@ -72,7 +72,11 @@ typedef struct {
     double omega_fixed, tol_nl, tol_gr, tol_gr0, tol_omega, l_e, omega0_first, omega0_next,
         omega_min, omega_max;
     int max_newton, max_omega_it, gmres_restart, max_gmres;
+    int precond, cheb_degree; /* PBREF_PC_*, Chebyshev terms of the FEM block */
+    double cheb_ratio;        /* lmax / lower end of the Chebyshev interval */
 } pbref_opts;
+
+enum { PBREF_PC_DIAG = 0, PBREF_PC_CHEB_SPAI = 1 };
 
 typedef struct {
     int status; /* 0 ok, -6 not converged, -7 non-finite */
@@ -87,6 +91,17 @@ typedef struct {
 void pbref_opts_default(pbref_opts *);
 int pbref_gmres(pbref *, int scheme, const double *phi, const double *b, double *x, double tol,
                 int restart, int maxit, int *iters);
+int pbref_gmres_pc(pbref *, int scheme, const double *phi, const double *b, double *x, double tol,
+                   int restart, int maxit, int pc, int cheb_degree, double cheb_ratio, int *iters);
+/* preconditioner pieces: 1-ring pattern (returns nnz; ptr/col may be NULL),
+ * sparse approximate inverse rows of a dense n x n matrix on a pattern,
+ * Gershgorin bound of diag(F)^-1 F for the FEM block, and the Chebyshev
+ * terms for a diagonal F */
+int64_t pbref_surface_ring(const pbref *, int surf, int32_t *ptr, int32_t *col);
+int pbref_spai_rows(int64_t n, const double *B, const int32_t *ptr, const int32_t *col, double *val);
+double pbref_fem_gershgorin(const pbref *, int scheme, const double *u);
+void pbref_cheb_diag(int64_t n, const double *fdiag, const double *dinv, double lmax, double ratio, int k,
+                     const double *r, double *z);
 int pbref_solve(pbref *, const pbref_opts *, pbref_result *, double *phi_lin, double *phi_nl);
 /* f_d(omega) and f_d'(omega) for the step D at phi (out[0], out[1]) */
 int pbref_fd(pbref *, int scheme, const double *phi, const double *D, double omega, double out[2]);

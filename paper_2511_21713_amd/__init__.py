@@ -40,7 +40,8 @@ class SolveOpts(C.Structure):
                 ("tol_omega", C.c_double), ("l_e", C.c_double), ("omega0_first", C.c_double),
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
-                ("max_gmres", C.c_int), ("krylov_fp32", C.c_int)]
+                ("max_gmres", C.c_int), ("krylov_fp32", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
+                ("cheb_ratio", C.c_double)]
 
 
 class Result(C.Structure):
@@ -48,7 +49,7 @@ class Result(C.Structure):
                 ("dg_omega_i", C.c_double), ("newton_iters", C.c_int), ("gmres_iters_total", C.c_int),
                 ("gmres_lin", C.c_int), ("gmres_iters", C.c_int * 64), ("omega", C.c_double * 64),
                 ("e_k", C.c_double * 64), ("omega_iters", C.c_int * 64), ("t_setup_s", C.c_double),
-                ("t_solve_s", C.c_double)]
+                ("t_solve_s", C.c_double), ("applies", C.c_int)]
 
     def as_dict(self):
         k = min(self.newton_iters, 64)
@@ -56,7 +57,7 @@ class Result(C.Structure):
                     newton_iters=self.newton_iters, gmres_iters_total=self.gmres_iters_total,
                     gmres_lin=self.gmres_lin, gmres_iters=list(self.gmres_iters[:k]), omega=list(self.omega[:k]),
                     e_k=list(self.e_k[:k]), omega_iters=list(self.omega_iters[:k]), t_setup_s=self.t_setup_s,
-                    t_solve_s=self.t_solve_s)
+                    t_solve_s=self.t_solve_s, applies=self.applies)
 
 
 _lib = None

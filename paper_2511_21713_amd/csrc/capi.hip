@@ -485,7 +485,25 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->gmres_restart = 200;
     o->max_gmres = 2000;
     o->krylov_fp32 = 0;
+    o->precond = PBFB_PC_CHEB_SPAI;
+    o->cheb_degree = 8;
+    o->cheb_ratio = 30.0;
 }
+
+} // extern "C"
+
+namespace pbfb {
+void check_opts(const pbfb_solve_opts &O)
+{
+    PB_CHECK(O.gmres_restart >= 1 && O.gmres_restart <= 1000 && O.max_gmres >= 1, PBFB_EINVAL, "bad GMRES options");
+    PB_CHECK(O.tol_gr > 0 && O.tol_gr0 > 0 && O.tol_nl >= 0, PBFB_EINVAL, "bad tolerances");
+    PB_CHECK((O.precond == PBFB_PC_DIAG || O.precond == PBFB_PC_CHEB_SPAI) && O.cheb_degree >= 1 &&
+                 O.cheb_degree <= 64 && O.cheb_ratio > 1.0,
+             PBFB_EINVAL, "bad preconditioner options");
+}
+} // namespace pbfb
+
+extern "C" {
 
 pbfb_status pbfb_solve(pbfb_problem *pp, const pbfb_solve_opts *o, pbfb_result *res, double *phi_out, int mem,
                        void *stream)
@@ -495,8 +513,7 @@ pbfb_status pbfb_solve(pbfb_problem *pp, const pbfb_solve_opts *o, pbfb_result *
     pbfb_solve_opts def;
     pbfb_solve_opts_default(&def);
     const pbfb_solve_opts &O = o ? *o : def;
-    PB_CHECK(O.gmres_restart >= 1 && O.gmres_restart <= 1000 && O.max_gmres >= 1, PBFB_EINVAL, "bad GMRES options");
-    PB_CHECK(O.tol_gr > 0 && O.tol_gr0 > 0 && O.tol_nl >= 0, PBFB_EINVAL, "bad tolerances");
+    check_opts(O);
     Problem &p = pp->p;
     hipStream_t s = pick_stream(p, stream);
     const int64_t n = p.n();
@@ -522,7 +539,7 @@ pbfb_status pbfb_solve_batch(pbfb_ctx *ctx, int n, pbfb_problem *const *probs, c
     pbfb_solve_opts def;
     pbfb_solve_opts_default(&def);
     const pbfb_solve_opts &O = o ? *o : def;
-    PB_CHECK(O.gmres_restart >= 1 && O.gmres_restart <= 1000 && O.max_gmres >= 1, PBFB_EINVAL, "bad GMRES options");
+    check_opts(O);
     PB_HIP(hipSetDevice(ctx->c.device));
     hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->c.stream;
     std::vector<NewtonRun> runs;

@@ -10,12 +10,16 @@
 // per instance, so the host only enqueues iterations and polls a completion
 // counter asynchronously; nothing waits on the host between iterations.
 //
-// Per-instance state machine:
+// Per-instance state machine (P^-1 the right preconditioner):
 //   INIT  -> w = b, V_0 = b/|b|, target = tol |b|              -> ARN (or DONE if b = 0)
-//   ARN   -> w = J D^{-1} V_j, CGS2, V_{j+1}, Givens            -> UPD at convergence/restart/limit
-//   UPD   -> y = H^{-1} g, x += D^{-1} V y                       -> RES
-//   RES   -> w = b - J x, beta = |w|: beta <= target -> DONE, else V_0 = w/beta -> ARN
+//   ARN   -> z = P^-1 V_j, w = J z, CGS2, V_{j+1}, Givens       -> UPD at convergence/restart/limit
+//   UPD   -> y = H^{-1} g, t = V y                               -> RES
+//   RES   -> x += P^-1 t, w = b - J x, beta = |w|: beta <= target -> DONE, else V_0 = w/beta -> ARN
 // which is the restarted GMRES of the oracle (true residual at every restart).
+// P^-1 is either the inverse diagonal of J or the block preconditioner:
+// Jacobi-scaled Chebyshev terms on the FEM block (one SpMV launch per term
+// after the first) and a sparse approximate inverse on each single-layer
+// block.
 //
 // Mixed precision may store the basis in FP32 (products, projections, norms,
 // Hessenberg, rotations, w and x stay FP64).  A restart cycle is then an
@@ -50,11 +54,18 @@ struct GDesc {
     int64_t nch, nchb;
     double tol;
     int m, maxit;
+    // preconditioner
+    int pc, cheb_k;
+    double cheb_ratio;
+    const double *lmax;
+    const int32_t *sp_ptr[2], *sp_col[2];
+    const double *sp_val[2];
+    double *z, *zb, *dk, *t; // P^-1 input (full), Chebyshev ping-pong buffer and direction, V y
 };
 
 struct GState {
-    int st, j, total, code;
-    double beta, target, hn, pad;
+    int st, j, total, code, napply, pad;
+    double beta, target, hn;
 };
 
 struct WItem {
@@ -90,9 +101,8 @@ __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, con
     const GState s = S[it.inst];
     if (!applies(s.st)) return;
     const GDesc &d = D[it.inst];
-    const bool sc = s.st == G_ARN;
-    // ARN: D^{-1} V_j, RES: x
-    auto in = [&](int64_t r) { return sc ? vget(d, s.j, r) * d.dinv[r] : d.x[r]; };
+    const double *in0 = s.st == G_ARN ? d.z : d.x; // ARN: P^-1 V_j, RES: x
+    auto in = [&](int64_t r) { return in0[r]; };
     for (int64_t k = it.b + threadIdx.x; k < it.b + CH; k += 256) {
         if (k < d.ldm) {
             double v = 0.0;
@@ -107,6 +117,105 @@ __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, con
             d.xs[k] = v;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner stage: z = P^-1 src with src = V_j (ARN) or t = V y (RES,
+// which also adds the result to x).  Chebyshev term s (0-based) of the FEM
+// block is written to z when k - 1 - s is even and to zb otherwise, so the
+// last term always lands in z.
+// ---------------------------------------------------------------------------
+__device__ inline void cheb_params(const GDesc &d, double &theta, double &delta, double &sigma)
+{
+    const double hi = *d.lmax, lo = hi / d.cheb_ratio;
+    theta = 0.5 * (hi + lo);
+    delta = 0.5 * (hi - lo);
+    sigma = theta / delta;
+}
+
+__device__ inline double pc_src(const GDesc &d, const GState &s, int64_t r)
+{
+    return s.st == G_RES ? d.t[r] : vget(d, s.j, r);
+}
+
+// first term (FEM rows), the approximate inverse (surface rows) or the diagonal
+__global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                                const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (s.st != G_ARN && s.st != G_RES) return;
+    const GDesc &d = D[it.inst];
+    const int64_t k = it.b + threadIdx.x;
+    if (k >= d.n) return;
+    double zv;
+    bool last = true;
+    if (d.pc == PBFB_PC_DIAG) {
+        zv = d.dinv[k] * pc_src(d, s, k);
+        d.z[k] = zv;
+    } else if (k < d.nn) {
+        double theta, delta, sigma;
+        cheb_params(d, theta, delta, sigma);
+        zv = d.dinv[k] * pc_src(d, s, k) / theta;
+        d.dk[k] = zv;
+        ((d.cheb_k - 1) % 2 == 0 ? d.z : d.zb)[k] = zv;
+        last = d.cheb_k == 1;
+    } else {
+        const int w = k < d.nn + d.nm ? 0 : 1;
+        const int64_t off = d.nn + (w == 0 ? 0 : d.nm), i = k - off;
+        double acc = 0.0;
+        for (int32_t e = d.sp_ptr[w][i]; e < d.sp_ptr[w][i + 1]; ++e)
+            acc = fma(d.sp_val[w][e], pc_src(d, s, off + d.sp_col[w][e]), acc);
+        zv = acc;
+        d.z[k] = zv;
+    }
+    if (last && s.st == G_RES) d.x[k] += zv;
+}
+
+// Chebyshev term `step` >= 1 of the FEM block: 8 lanes per row
+__global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                               const GState *__restrict__ S, int step)
+{
+    const WItem it = wl[blockIdx.x];
+    const GState s = S[it.inst];
+    if (s.st != G_ARN && s.st != G_RES) return;
+    const GDesc &d = D[it.inst];
+    if (d.pc != PBFB_PC_CHEB_SPAI || step >= d.cheb_k) return;
+    const int64_t row = it.b + (threadIdx.x >> 3);
+    const int sub = threadIdx.x & 7;
+    const double *zp = ((d.cheb_k - step) % 2 == 0) ? d.z : d.zb; // term step - 1
+    double *zn = ((d.cheb_k - 1 - step) % 2 == 0) ? d.z : d.zb;
+    double acc = 0.0;
+    if (row < d.nn) {
+        const int32_t e = d.rowptr[row + 1];
+        if (d.f32) {
+            const float *val = static_cast<const float *>(d.val);
+            for (int32_t q = d.rowptr[row] + sub; q < e; q += 8) {
+                const int32_t c = d.col[q];
+                if (c < d.nn) acc = fma(double(val[q]), zp[c], acc);
+            }
+        } else {
+            const double *val = static_cast<const double *>(d.val);
+            for (int32_t q = d.rowptr[row] + sub; q < e; q += 8) {
+                const int32_t c = d.col[q];
+                if (c < d.nn) acc = fma(val[q], zp[c], acc);
+            }
+        }
+    }
+    acc += __shfl_xor(acc, 4);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 1);
+    if (sub != 0 || row >= d.nn) return;
+    double theta, delta, sigma;
+    cheb_params(d, theta, delta, sigma);
+    double rho0 = 1.0 / sigma;
+    for (int q = 1; q < step; ++q) rho0 = 1.0 / (2.0 * sigma - rho0);
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    const double dv = rho1 * rho0 * d.dk[row] + 2.0 * rho1 / delta * d.dinv[row] * (pc_src(d, s, row) - acc);
+    d.dk[row] = dv;
+    const double zv = zp[row] + dv;
+    zn[row] = zv;
+    if (step == d.cheb_k - 1 && s.st == G_RES) d.x[row] += zv;
 }
 
 // work item: inst, a = interface (0/1), b = first row of the workgroup
@@ -137,17 +246,16 @@ __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, con
     const GDesc &d = D[it.inst];
     const int64_t row = it.b + (threadIdx.x >> 3);
     const int sub = threadIdx.x & 7;
-    const bool sc = s.st == G_ARN;
-    auto in = [&](int64_t r) { return sc ? vget(d, s.j, r) * d.dinv[r] : d.x[r]; };
+    const double *in = s.st == G_ARN ? d.z : d.x;
     double acc = 0.0;
     if (row < d.nn) {
         const int32_t e = d.rowptr[row + 1];
         if (d.f32) {
             const float *val = static_cast<const float *>(d.val);
-            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(double(val[k]), in(d.col[k]), acc);
+            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(double(val[k]), in[d.col[k]], acc);
         } else {
             const double *val = static_cast<const double *>(d.val);
-            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(val[k], in(d.col[k]), acc);
+            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(val[k], in[d.col[k]], acc);
         }
     }
     acc += __shfl_xor(acc, 4);
@@ -346,6 +454,7 @@ __global__ void __launch_bounds__(64) k_bcontrol(const GDesc *__restrict__ D, GS
             d.g[j] = cj * gj;
             ss.j = j + 1;
             ss.total += 1;
+            ss.napply += 1;
             ss.hn = nr;
             const double res = fabs(d.g[j + 1]);
             if (!(res == res)) {
@@ -376,6 +485,7 @@ __global__ void __launch_bounds__(64) k_bcontrol(const GDesc *__restrict__ D, GS
         }
     } else if (lane == 0) {
         if (st0 == G_INIT) ss.target = d.tol * nr;
+        else ss.napply += 1; // RES: the true residual took one application
         ss.beta = nr;
         if (!(nr == nr)) {
             ss.st = G_FAIL;
@@ -399,7 +509,7 @@ __global__ void __launch_bounds__(64) k_bcontrol(const GDesc *__restrict__ D, GS
     if (lane == 0) S[q] = ss;
 }
 
-// UPD: x += D^{-1} (V y); the last workgroup of the instance moves it to RES
+// UPD: t = V y; the last workgroup of the instance moves it to RES
 __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                GState *__restrict__ S)
 {
@@ -421,7 +531,7 @@ __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, con
             const double *V0 = vcol<double>(d, 0);
             for (int i = 0; i < s.j; ++i) v = fma(ys[i], V0[int64_t(i) * d.n + k], v);
         }
-        d.x[k] += d.dinv[k] * v;
+        d.t[k] = v;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -468,7 +578,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     std::vector<GDesc> desc(nb);
     std::vector<GState> st(nb);
     std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack, wl_dot;
-    int maxiter_host = 0;
+    int maxiter_host = 0, kmax = 1;
     for (int q = 0; q < nb; ++q) {
         GmresJob &J = *jobs[q];
         Problem &p = *J.p;
@@ -490,6 +600,20 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.nn = p.nn;
         d.n = n;
         d.dinv = J.dinv;
+        d.pc = J.pc;
+        d.cheb_k = J.cheb_k;
+        d.cheb_ratio = J.cheb_ratio;
+        d.lmax = J.lmax;
+        for (int w = 0; w < 2; ++w) {
+            d.sp_ptr[w] = p.surf[w].ring_ptr;
+            d.sp_col[w] = p.surf[w].ring;
+            d.sp_val[w] = p.surf[w].spai;
+        }
+        d.z = scratch<double>(p, SCR_PZ, n);
+        d.t = scratch<double>(p, SCR_PT, n);
+        d.zb = scratch<double>(p, SCR_PZB, p.nn);
+        d.dk = scratch<double>(p, SCR_PDK, p.nn);
+        if (J.pc == PBFB_PC_CHEB_SPAI) kmax = std::max(kmax, J.cheb_k);
         d.vf32 = J.basis32 && p.precision == PBFB_MIXED;
         if (d.vf32) d.V = scratch<float>(p, SCR_BASIS32, size_t(m + 1) * n);
         else d.V = scratch<double>(p, SCR_BASIS, size_t(m + 1) * n);
@@ -516,7 +640,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.tol = J.tol;
         d.m = m;
         d.maxit = J.maxit;
-        st[q] = GState{G_INIT, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+        st[q] = GState{G_INIT, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
         PB_HIP(hipMemsetAsync(J.x, 0, sizeof(double) * n, s));
         for (int64_t c = 0; c < d.nch; ++c) wl_vec.push_back(WItem{q, int(c), c * CH});
         for (int64_t c = 0; c < d.nchb; ++c) wl_dot.push_back(WItem{q, int(c), c * CHB});
@@ -568,12 +692,19 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             tm = &J->p->timer;
             break;
         }
-    // Enqueue iterations; poll a completion counter copied to pinned memory,
-    // blocking only on the copy from two polls back (bounded run-ahead).
-    const int POLL = 4;
+    // Enqueue iterations; poll a completion counter copied to pinned memory
+    // every POLL iterations, blocking only on the copy of the previous poll:
+    // the device keeps 2 to 4 iterations queued, and at most that many launch
+    // rounds return at once after the last instance has finished.
+    const int POLL = 2;
     int polls = 0;
     bool finished = false;
     for (int it = 0; it < maxiter_host && !finished; ++it) {
+        if (tm) tm->begin(T_PREC, s);
+        hipLaunchKernelGGL(k_bprec0, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
+        for (int step = 1; step < kmax; ++step)
+            hipLaunchKernelGGL(k_bcheb, dim3(nspmv), dim3(256), 0, s, dspmv, dD, dS, step);
+        if (tm) tm->end(s);
         if (tm) tm->begin(T_APPLY, s);
         hipLaunchKernelGGL(k_bpack, dim3(npack), dim3(256), 0, s, dpack, dD, dS);
         if (tm) tm->begin(T_GEMV, s);
@@ -603,8 +734,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             PB_HIP(hipMemcpyAsync(BB.pinned + slot, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
             PB_HIP(hipEventRecord(BB.ev[slot], s));
             ++polls;
-            if (polls >= 3) {
-                const int old = (polls - 3) % 3; // the copy two polls back
+            if (polls >= 2) {
+                const int old = (polls - 2) % 3; // the copy of the previous poll
                 PB_HIP(hipEventSynchronize(BB.ev[old]));
                 if (BB.pinned[old] >= nb) finished = true;
             }
@@ -613,7 +744,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             // thread's last error, which the launch checks of the next
             // iteration would report; it is cleared here (launch errors of
             // this iteration were checked above).
-            for (int k = 1; k <= 2 && !finished && polls - k >= 0; ++k) {
+            for (int k = 1; k <= 1 && !finished && polls - k >= 0; ++k) {
                 const int sl = (polls - k) % 3;
                 const hipError_t q = hipEventQuery(BB.ev[sl]);
                 if (q == hipErrorNotReady) {
@@ -630,6 +761,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     for (int q = 0; q < nb; ++q) {
         GmresJob &J = *jobs[q];
         J.iters = st[q].total;
+        J.applies = st[q].napply;
         if (st[q].st == G_DONE) J.status = 0;
         else if (st[q].st == G_FAIL) J.status = st[q].code;
         else J.status = PBFB_ENOTCONV;

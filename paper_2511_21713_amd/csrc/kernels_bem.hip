@@ -544,6 +544,101 @@ __global__ void k_diag_and_narrow(int64_t nv, int64_t ld, int64_t ld_out, const 
     if (B32 && j < ld_out) B32[i * ld_out + j] = j < 2 * nv ? float(B64[i * ld + j]) : 0.0f;
 }
 
+// ---------------------------------------------------------------------------
+// sparse approximate inverse of the single-layer block (GMRES preconditioner)
+// ---------------------------------------------------------------------------
+// Row i minimises || m^T V' - e_i^T ||_2 over m supported on the 1-ring P(i)
+// of vertex i, V' = columns [nv, 2nv) of the stored rows (the signed
+// single-layer block of the operator).  Normal equations
+// (V'_P V'_P^T) m = V'_P e_i, solved by Cholesky.  One workgroup per row;
+// the Gram matrix accumulates over 64-column tiles of the rows P staged in
+// LDS, one thread per (a, b) pair, in a fixed order.
+template <typename MT>
+__global__ void __launch_bounds__(256)
+    k_spai(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ ring_ptr,
+           const int32_t *__restrict__ ring, double *__restrict__ val, int *__restrict__ bad)
+{
+    __shared__ double T[MAXRING][65];
+    __shared__ double G[MAXRING][MAXRING + 1];
+    __shared__ double rhs[MAXRING];
+    __shared__ int P[MAXRING];
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const int p0 = ring_ptr[i], m = ring_ptr[i + 1] - p0;
+    for (int a = tid; a < m; a += 256) P[a] = ring[p0 + a];
+    __syncthreads();
+    const int npair = m * (m + 1) / 2;
+    constexpr int PPT = (MAXRING * (MAXRING + 1) / 2 + 255) / 256; // pairs per thread
+    double acc[PPT];
+    int pa[PPT], pb[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        acc[q] = 0.0;
+        const int pr = tid + 256 * q;
+        int a = int((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+        while (a * (a + 1) / 2 > pr) --a;
+        while ((a + 1) * (a + 2) / 2 <= pr) ++a;
+        pa[q] = a;
+        pb[q] = pr - a * (a + 1) / 2;
+    }
+    for (int64_t c0 = 0; c0 < nv; c0 += 64) {
+        for (int k = tid; k < m * 64; k += 256) {
+            const int a = k >> 6, c = k & 63;
+            T[a][c] = c0 + c < nv ? double(B[int64_t(P[a]) * ld + nv + c0 + c]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (tid + 256 * q < npair) {
+                const int a = pa[q], b = pb[q];
+                double s = 0.0;
+                for (int c = 0; c < 64; ++c) s = fma(T[a][c], T[b][c], s);
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q)
+        if (tid + 256 * q < npair) G[pa[q]][pb[q]] = G[pb[q]][pa[q]] = acc[q];
+    for (int a = tid; a < m; a += 256) rhs[a] = double(B[int64_t(P[a]) * ld + nv + i]);
+    __syncthreads();
+    if (tid == 0) {
+        // Cholesky G = L L^T (lower triangle), then L y = rhs, L^T m = y
+        bool ok = true;
+        for (int a = 0; a < m && ok; ++a) {
+            double d = G[a][a];
+            for (int k = 0; k < a; ++k) d -= G[a][k] * G[a][k];
+            if (!(d > 0.0)) {
+                ok = false;
+                break;
+            }
+            G[a][a] = sqrt(d);
+            for (int b = a + 1; b < m; ++b) {
+                double s = G[b][a];
+                for (int k = 0; k < a; ++k) s -= G[b][k] * G[a][k];
+                G[b][a] = s / G[a][a];
+            }
+        }
+        if (!ok) {
+            atomicOr(bad, 4);
+            for (int a = 0; a < m; ++a) val[p0 + a] = 0.0;
+        } else {
+            for (int a = 0; a < m; ++a) {
+                double s = rhs[a];
+                for (int k = 0; k < a; ++k) s -= G[a][k] * rhs[k];
+                rhs[a] = s / G[a][a];
+            }
+            for (int a = m - 1; a >= 0; --a) {
+                double s = rhs[a];
+                for (int k = a + 1; k < m; ++k) s -= G[k][a] * rhs[k];
+                rhs[a] = s / G[a][a];
+            }
+            for (int a = 0; a < m; ++a) val[p0 + a] = rhs[a];
+        }
+    }
+}
+
 // ===========================================================================
 // host orchestration
 // ===========================================================================
@@ -597,6 +692,9 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         for (int64_t t = 0; t < T.nt; ++t)
             for (int32_t k = T.tp_ptr[t]; k < T.tp_ptr[t + 1]; ++k) tp_tau[k] = int32_t(t);
         S.tp_tau = A.upload(tp_tau, s);
+        S.ring_ptr = A.upload(T.ring_ptr, s);
+        S.ring = A.upload(T.ring, s);
+        S.spai = A.alloc<double>(T.ring.size());
         const int64_t ldt = bem_ld(T.nv);
         S.vdiag = A.alloc<double>(T.nv);
         if (p.precision == PBFB_MIXED) S.B = A.alloc<float>(T.nv * ldt);
@@ -687,6 +785,19 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     }
     PB_HIP(hipGetLastError());
     release_scratch(p, SCR_TPVAL);
+    // approximate inverse of the single-layer block, from the stored values
+    PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
+    if (p.precision == PBFB_MIXED)
+        hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const float *>(S.B), ld,
+                           S.ring_ptr, S.ring, S.spai, p.d_bad);
+    else
+        hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const double *>(S.B),
+                           ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+    PB_HIP(hipGetLastError());
+    int bad = 0;
+    PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    PB_HIP(hipStreamSynchronize(s));
+    PB_CHECK(!(bad & 4), PBFB_EMESH, "single-layer block not positive definite on a vertex 1-ring");
     p.bem_ready[w] = true;
 }
 

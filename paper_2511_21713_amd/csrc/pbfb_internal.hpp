@@ -73,6 +73,7 @@ struct Arena {
 constexpr int BA = 16;
 constexpr int BB = 32;
 constexpr int MAXS = 12; // slots per local vertex in a block (max triangles of a block at one vertex)
+constexpr int MAXRING = 64; // largest 1-ring (vertex and its neighbours) of the approximate inverse
 
 // host-side topology of one boundary surface
 struct SurfaceTopo {
@@ -89,6 +90,8 @@ struct SurfaceTopo {
     std::vector<int32_t> LB_ptr, LB;         // vertex -> expanded columns
     // touching pairs (tau, sigma) sharing at least one vertex, grouped by tau
     std::vector<int32_t> tp_ptr, tp_sig;
+    // 1-ring pattern of the sparse approximate inverse
+    std::vector<int32_t> ring_ptr, ring;
 };
 
 struct SurfaceDev {
@@ -110,6 +113,9 @@ struct SurfaceDev {
     // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
     void *B = nullptr;
     double *vdiag = nullptr; // diagonal of the signed single-layer block V'
+    // sparse approximate inverse of V' on the 1-ring pattern (GMRES preconditioner)
+    int32_t *ring_ptr = nullptr, *ring = nullptr;
+    double *spai = nullptr;
 };
 
 struct Ctx {
@@ -117,7 +123,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
 };
 
-enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_NCLASS = 5 };
+enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_PREC = 5, T_NCLASS = 6 };
 
 // HIP-event timing of launch ranges, accumulated per class.  Pairs may nest;
 // when the event pool is full the closed pairs are folded into the sums and
@@ -140,7 +146,8 @@ enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_E0, SCR_E1, SCR_W0, SCR_W1,
     SCR_TPVAL, SCR_B64, SCR_VX, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
-    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_N
+    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX,
+    SCR_N
 };
 
 struct ScratchBuf {
@@ -234,9 +241,15 @@ struct GmresJob {
     int restart, maxit;
     int iters, status;
     int basis32; // Krylov basis in FP32 (mixed precision only)
+    int pc, cheb_k;       // preconditioner (PBFB_PC_*), Chebyshev terms
+    double cheb_ratio;
+    const double *lmax;   // device scalar: Gershgorin bound of diag(F)^-1 F
+    int applies;          // out: operator applications that did work
 };
 void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s);
 void build_precond(Problem &p, double *dinv, hipStream_t s);
+void check_opts(const pbfb_solve_opts &o); // throws PBFB_EINVAL
+void fem_gershgorin(Problem &p, double *lmax_dev, hipStream_t s); // bound of diag(F)^-1 F, F = A + J_N
 
 // Newton driver (solver.hip): one state machine per instance
 struct NewtonRun {
@@ -249,6 +262,7 @@ struct NewtonRun {
     bool frozen = false;
     double *phil = nullptr, *phinl = nullptr, *phi = nullptr, *c = nullptr, *d = nullptr, *D = nullptr;
     double *pv = nullptr, *rv = nullptr, *rN = nullptr, *rJ = nullptr, *rH = nullptr, *dinv = nullptr;
+    double *lmax = nullptr; // Chebyshev bound (device) and its partial maxima
     GmresJob job{};
     std::string message;
     std::chrono::steady_clock::time_point t0, t1;

@@ -227,12 +227,18 @@ pbfb_status pbfb_server_submit(pbfb_server *sv, pbfb_problem *pp, const pbfb_sol
         Problem &p = pp->p;
         PB_CHECK(p.have_mesh && p.have_charges && p.have_params, PBFB_ESTATE, "problem not fully specified");
         PB_CHECK(p.ctx == sv->s.ctx, PBFB_EINVAL, "problem belongs to another context");
+        pbfb_solve_opts O;
+        if (o) O = *o;
+        else pbfb_solve_opts_default(&O);
+        check_opts(O);
+        size_t steady = 0, extra = 0;
+        footprint_estimate(p, O.gmres_restart, &steady, &extra);
+        PB_CHECK(steady + extra <= sv->s.budget, PBFB_ENOMEM, "request exceeds the server's HBM budget");
         auto *r = new Request;
-        if (o) r->o = *o;
-        else pbfb_solve_opts_default(&r->o);
+        r->o = O;
         r->p = &p;
-        footprint_estimate(p, r->o.gmres_restart, &r->steady, &r->extra);
-        PB_CHECK(r->steady + r->extra <= sv->s.budget, PBFB_ENOMEM, "request exceeds the server's HBM budget");
+        r->steady = steady;
+        r->extra = extra;
         std::lock_guard<std::mutex> lk(sv->s.mu);
         r->ticket = sv->s.next_ticket++;
         sv->s.all[r->ticket] = r;

@@ -157,6 +157,22 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
         }
         for (auto &e : vlB[i]) S.LB.push_back(e.first);
     }
+    // 1-ring of each vertex (itself and every vertex sharing a triangle), ascending
+    S.ring_ptr.assign(S.nv + 1, 0);
+    S.ring.clear();
+    {
+        std::vector<int32_t> r;
+        for (int64_t i = 0; i < S.nv; ++i) {
+            r.assign(1, int32_t(i));
+            for (int32_t e = S.v2t_ptr[i]; e < S.v2t_ptr[i + 1]; ++e)
+                for (int b = 0; b < 3; ++b) r.push_back(S.tri[3 * (S.v2t[e] / 3) + b]);
+            std::sort(r.begin(), r.end());
+            r.erase(std::unique(r.begin(), r.end()), r.end());
+            PB_CHECK(r.size() <= size_t(MAXRING), PBFB_EMESH, "surface vertex with more than 63 neighbours");
+            S.ring.insert(S.ring.end(), r.begin(), r.end());
+            S.ring_ptr[i + 1] = int32_t(S.ring.size());
+        }
+    }
     // touching pairs, grouped by the first triangle
     S.tp_ptr.assign(ntri + 1, 0);
     S.tp_sig.clear();

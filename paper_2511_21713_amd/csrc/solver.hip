@@ -47,7 +47,74 @@ void build_precond(Problem &p, double *dinv, hipStream_t s)
                        p.d_diag, p.surf[0].vdiag, p.surf[1].vdiag, dinv);
 }
 
+// Gershgorin bound of diag(F)^-1 F for the FEM block F = A + J_N (the upper
+// end of the Chebyshev interval): per-block maxima, then one block.  A
+// maximum does not depend on the order, so the bound is exact and
+// reproducible.
+__global__ void __launch_bounds__(256) k_gershgorin(int64_t nn, const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                    const int32_t *__restrict__ diag, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    double v = 0.0;
+    if (i < nn) {
+        double sum = 0.0;
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (col[e] < nn) sum += fabs(val[e]);
+        v = sum / val[diag[i]];
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_max_final(int64_t nb, const double *__restrict__ part,
+                                                   double *__restrict__ out)
+{
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) v = fmax(v, part[b]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// lmax_dev[0] = bound; lmax_dev[1 ..] partial maxima (1 + ceil(nn / 256) doubles)
+void fem_gershgorin(Problem &p, double *lmax_dev, hipStream_t s)
+{
+    const unsigned nb = nbk(p.nn, 256);
+    hipLaunchKernelGGL(k_gershgorin, dim3(nb), dim3(256), 0, s, p.nn, p.d_rowptr, p.d_col, p.d_val, p.d_diag,
+                       lmax_dev + 1);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, int64_t(nb), lmax_dev + 1, lmax_dev);
+    PB_HIP(hipGetLastError());
+}
+
 enum RunPhase { PH_START = 0, PH_LINEAR = 1, PH_NEWTON = 2, PH_DONE = 3 };
+
+// the linear-solve request of the current Newton matrix (its CSR values,
+// diagonal and Chebyshev bound are computed here)
+static GmresJob make_job(NewtonRun &r, const double *b, double *x, hipStream_t s)
+{
+    Problem &p = *r.p;
+    build_precond(p, r.dinv, s);
+    if (r.o.precond == PBFB_PC_CHEB_SPAI) fem_gershgorin(p, r.lmax, s);
+    GmresJob J{&p, b, x, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0, r.o.krylov_fp32};
+    J.pc = r.o.precond;
+    J.cheb_k = r.o.cheb_degree;
+    J.cheb_ratio = r.o.cheb_ratio;
+    J.lmax = r.lmax;
+    J.applies = 0;
+    return J;
+}
 
 NewtonRun::NewtonRun(Problem *p_, const pbfb_solve_opts &o_, pbfb_result *res_, double *out)
     : p(p_), o(o_), res(res_), phi_out_dev(out)
@@ -99,8 +166,8 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
         return false;
     }
     fem_assemble_jacobian(p, r.sch, r.phi, s);
-    build_precond(p, r.dinv, s);
-    r.job = GmresJob{&p, r.d, r.D, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0, r.o.krylov_fp32};
+    r.job = make_job(r, r.d, r.D, s);
+    r.res->applies += 1; // c = b - A Phi
     return true;
 }
 
@@ -121,6 +188,7 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
         omega = r.sch == PBFB_T3 ? o.omega0_first : o.omega0_next;
         // p = -A Delta
         coupled_apply_linear(p, r.D, r.pv, s);
+        r.res->applies += 1;
         vec_axpby(n, -1.0, r.pv, 0.0, r.pv, s);
         const double pp = dot(p, r.pv, r.pv, n, s);
         PB_HIP(hipMemcpyAsync(r.rv, r.c, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -195,15 +263,16 @@ static bool advance_impl(NewtonRun &r, hipStream_t s)
         r.tol = r.o.tol_gr0;
         PB_HIP(hipMemsetAsync(r.phinl, 0, sizeof(double) * n, s));
         // linear component: (A + eps_s kappa^2 M) Phi_L = b
+        r.lmax = scratch<double>(p, SCR_LMAX, 1 + nbk(nn, 256));
         fem_assemble_jacobian(p, PBFB_LIN, r.phinl, s);
-        build_precond(p, r.dinv, s);
-        r.job = GmresJob{&p, p.d_b, r.phil, r.dinv, r.tol, r.o.gmres_restart, r.o.max_gmres, 0, 0, r.o.krylov_fp32};
+        r.job = make_job(r, p.d_b, r.phil, s);
         r.phase = PH_LINEAR;
         return true;
     }
     if (r.phase == PH_LINEAR) {
         r.res->gmres_lin = r.job.iters;
         r.res->gmres_iters_total = r.job.iters;
+        r.res->applies += r.job.applies;
         if (r.job.status) {
             r.status = r.job.status;
             finish(r, s);
@@ -221,6 +290,7 @@ static bool advance_impl(NewtonRun &r, hipStream_t s)
         const int idx = std::min(r.k - 1, 63);
         r.res->gmres_iters[idx] = r.job.iters;
         r.res->gmres_iters_total += r.job.iters;
+        r.res->applies += r.job.applies;
         if (r.job.status) {
             r.status = r.job.status;
             finish(r, s);

@@ -105,13 +105,15 @@ def test_device_tensors_path(case):
     assert rel(out.cpu().numpy(), o.apply_jacobian(oracle.HS, phi, v)) < 1e-12
 
 
-def test_tight_solve_matches_oracle(case):
+@pytest.mark.parametrize("pc", [0, 1])
+def test_tight_solve_matches_oracle(case, pc):
+    # pc 0: inverse diagonal; 1: Chebyshev terms on the FEM block + approximate inverse of the single layers
     name, prob, o, g = case
-    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000, precond=pc)
     rg = g.solve(**kw)
     ro, pl, pnl = o.solve(**kw)
-    log(f"  {name}: gpu {rg['total']:.12f} ({rg['newton_iters']} it) oracle {ro['total']:.12f} "
-        f"({ro['newton_iters']} it)")
+    log(f"  {name} pc {pc}: gpu {rg['total']:.12f} ({rg['newton_iters']} it, gmres {rg['gmres_iters_total']}) "
+        f"oracle {ro['total']:.12f} ({ro['newton_iters']} it, gmres {ro['gmres_iters_total']})")
     assert rg["status"] == 0 and ro["status"] == 0
     assert abs(rg["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
     phi = np.zeros(2 * o.n)
@@ -122,11 +124,12 @@ def test_tight_solve_matches_oracle(case):
     assert np.linalg.norm(u_gpu - u_ora) < 1e-10 * np.linalg.norm(u_ora)
 
 
-def test_paper_tolerance_solve_iterates_like_oracle(case):
+@pytest.mark.parametrize("pc", [0, 1])
+def test_paper_tolerance_solve_iterates_like_oracle(case, pc):
     # Tol_NL = 1e-3, Tol_GR = 1e-6, adaptive Tol_GR0 = 1e-3, Tol_omega = 0.1, L_e = 0.35 (App. B settings)
     name, prob, o, g = case
-    rg = g.solve()
-    ro, _, _ = o.solve()
+    rg = g.solve(precond=pc)
+    ro, _, _ = o.solve(precond=pc)
     log(f"  {name}: gpu it {rg['newton_iters']} omega {rg['omega']} gmres {rg['gmres_iters']}; "
         f"oracle it {ro['newton_iters']} omega {ro['omega']} gmres {ro['gmres_iters']}")
     assert rg["newton_iters"] == ro["newton_iters"]
@@ -177,7 +180,7 @@ def test_timed_solves_repeat(ctx):
     normally with the same result."""
     prob = pbgen.make_problem(**CASES["sphere_n4"])
     g = gpu_problem(ctx, prob)
-    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000, precond=0)
     g.timing_enable(True)
     g.timing(0, reset=True)
     totals = []
@@ -188,8 +191,8 @@ def test_timed_solves_repeat(ctx):
         totals.append(r["total"])
     ms, cnt = g.timing(0)
     log(f"  timed solves: {len(totals)} solves, {cnt} timed applies, {ms:.4f} ms each")
-    # three timed ranges per apply (apply, GEMV, SpMV): the 4096-pair pool fills several times
-    assert 3 * cnt > 2 * 4096 and ms > 0
+    # four timed ranges per Krylov step (preconditioner, apply, GEMV, SpMV): the 4096-pair pool fills
+    assert 4 * cnt > 2 * 4096 and ms > 0
     assert all(t == totals[0] for t in totals)
     g.close()
 
