@@ -35,6 +35,7 @@ namespace pbfb {
 struct QRule6 {
     double b[6][3];
     double w[6];
+    double wb[6][3]; // w_q b_q[k]
 };
 struct GL4 {
     double x[4];
@@ -48,6 +49,7 @@ static QRule6 q6arg()
     for (int q = 0; q < 6; ++q) {
         for (int k = 0; k < 3; ++k) r.b[q][k] = R.tri_bary[q][k];
         r.w[q] = R.tri_w[q];
+        for (int k = 0; k < 3; ++k) r.wb[q][k] = R.tri_w[q] * R.tri_bary[q][k];
     }
     return r;
 }
@@ -113,10 +115,23 @@ static QRule6F q6farg()
     return r;
 }
 
+// 1/sqrt(x) for finite x > 0 (quadrature points of non-touching panels are
+// never coincident): the hardware estimate refined by one third-order step
+// y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
+__device__ inline double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+__device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
+
+constexpr int REG_THREADS = BA * BB; // one target x source triangle pair per thread
+
 // RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
 template <bool YUK, typename RT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(REG_THREADS, 4)
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
@@ -126,6 +141,7 @@ __global__ void __launch_bounds__(256)
                   QRule6 R, QRule6F RF)
 {
     constexpr bool F32 = sizeof(RT) == 4;
+    constexpr int NT = REG_THREADS;
     __shared__ RT sX[BA][18];
     __shared__ RT sY[BB][18];
     __shared__ RT sN[BB][3];
@@ -133,7 +149,7 @@ __global__ void __launch_bounds__(256)
     __shared__ double sAa[BA], sAb[BB];
     __shared__ int sVa[BA][3], sVb[BB][3];
     __shared__ int sSa[BA * 3][MAXS], sSb[BB * 3][MAXS];
-    __shared__ double acc[BA * 3][BB * 3 + 1];
+    __shared__ double acc[BA * 3 + 1][BB * 3 + 1]; // + a zero row and a zero column
 
     const int tid = threadIdx.x;
     const int64_t bB = blockIdx.x;
@@ -141,12 +157,12 @@ __global__ void __launch_bounds__(256)
     const int nA = A_nv[bA], nB = B_nv[bB];
     const int64_t pA = A_pref[bA], pB = B_pref[bB];
 
-    for (int k = tid; k < BA * 18; k += 256) {
+    for (int k = tid; k < BA * 18; k += NT) {
         int tl = k / 18, c = k % 18;
         int64_t m = bA * BA + tl;
         sX[tl][c] = m < nt ? xq[18 * m + c] : RT(0);
     }
-    for (int k = tid; k < BB * 18; k += 256) {
+    for (int k = tid; k < BB * 18; k += NT) {
         int sl = k / 18, c = k % 18;
         int64_t m = bB * BB + sl;
         sY[sl][c] = m < nt ? xq[18 * m + c] : RT(0);
@@ -166,70 +182,55 @@ __global__ void __launch_bounds__(256)
     }
     if (tid < BA) sAa[tid] = (bA * BA + tid) < nt ? m_area[bA * BA + tid] : 0.0;
     if (tid < BB) sAb[tid] = (bB * BB + tid) < nt ? m_area[bB * BB + tid] : 0.0;
-    for (int k = tid; k < BA * 3 * MAXS; k += 256) {
+    for (int k = tid; k < BA * 3 * MAXS; k += NT) {
         int r = k / MAXS, c = k % MAXS;
         sSa[r][c] = r < nA ? A_slots[(pA + r) * MAXS + c] : -1;
     }
-    for (int k = tid; k < BB * 3 * MAXS; k += 256) {
+    for (int k = tid; k < BB * 3 * MAXS; k += NT) {
         int r = k / MAXS, c = k % MAXS;
         sSb[r][c] = r < nB ? B_slots[(pB + r) * MAXS + c] : -1;
     }
     __syncthreads();
 
-    // two pairs per thread: (tl, sl) = (tid / 32 + 8 h, tid % 32)
-    double Vl[2][9], Kl[2][9];
+    // this thread's pair (target tl, source sl)
+    const int tl = tid / BB, sl = tid % BB;
+    double Vl[9], Kl[9];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int tl = tid / BB + 8 * h, sl = tid % BB;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Vl[h][k] = Kl[h][k] = 0.0;
-        bool touch = false;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
-        bool valid = (sVa[tl][0] >= 0) && (sVb[sl][0] >= 0) && !touch;
-        if (!valid) continue;
-        // target points relative to the source triangle's frame
-        RT xs[18];
+    for (int k = 0; k < 9; ++k) Vl[k] = Kl[k] = 0.0;
+    bool touch = false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
+    if ((sVa[tl][0] >= 0) && (sVb[sl][0] >= 0) && !touch) {
+        RT c0 = 0, c1 = 0, c2 = 0; // FP32: target frame relative to the source centroid
         if constexpr (F32) {
-            const float c0 = float(sCa[tl][0] - sCb[sl][0]), c1 = float(sCa[tl][1] - sCb[sl][1]),
-                        c2 = float(sCa[tl][2] - sCb[sl][2]);
-#pragma unroll
-            for (int p = 0; p < 6; ++p) {
-                xs[3 * p] = sX[tl][3 * p] + c0;
-                xs[3 * p + 1] = sX[tl][3 * p + 1] + c1;
-                xs[3 * p + 2] = sX[tl][3 * p + 2] + c2;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 18; ++k) xs[k] = sX[tl][k];
+            c0 = float(sCa[tl][0] - sCb[sl][0]);
+            c1 = float(sCa[tl][1] - sCb[sl][1]);
+            c2 = float(sCa[tl][2] - sCb[sl][2]);
         }
-        RT SV[6][3], SK[6][3];
-#pragma unroll
-        for (int p = 0; p < 6; ++p)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) SV[p][b] = SK[p][b] = RT(0);
         const RT n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
         const RT kap = RT(kappa);
+        const double sc = sAa[tl] * sAb[sl] * INV4PI;
+        // target point p outermost: 6-term source sums, then folded into the 3x3 blocks
+        // (not unrolled: the 6 source points of one target point are the unit of ILP)
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            const RT x0 = sX[tl][3 * p] + c0, x1 = sX[tl][3 * p + 1] + c1, x2 = sX[tl][3 * p + 2] + c2;
+            RT sv0 = 0, sv1 = 0, sv2 = 0, sk0 = 0, sk1 = 0, sk2 = 0;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const RT y0 = sY[sl][3 * q], y1 = sY[sl][3 * q + 1], y2 = sY[sl][3 * q + 2];
-            RT wb0, wb1, wb2;
-            if constexpr (F32) {
-                wb0 = RF.wb[q][0];
-                wb1 = RF.wb[q][1];
-                wb2 = RF.wb[q][2];
-            } else {
-                wb0 = R.w[q] * R.b[q][0];
-                wb1 = R.w[q] * R.b[q][1];
-                wb2 = R.w[q] * R.b[q][2];
-            }
-#pragma unroll
-            for (int p = 0; p < 6; ++p) {
-                const RT d0 = xs[3 * p] - y0, d1 = xs[3 * p + 1] - y1, d2 = xs[3 * p + 2] - y2;
+            for (int q = 0; q < 6; ++q) {
+                RT wb0, wb1, wb2;
+                if constexpr (F32) {
+                    wb0 = RF.wb[q][0];
+                    wb1 = RF.wb[q][1];
+                    wb2 = RF.wb[q][2];
+                } else {
+                    wb0 = R.wb[q][0];
+                    wb1 = R.wb[q][1];
+                    wb2 = R.wb[q][2];
+                }
+                const RT d0 = x0 - sY[sl][3 * q], d1 = x1 - sY[sl][3 * q + 1], d2 = x2 - sY[sl][3 * q + 2];
                 const RT r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                RT ri;
-                if constexpr (F32) ri = __builtin_amdgcn_rsqf(r2);
-                else ri = rsqrt(r2);
+                const RT ri = rsqrt_pos(r2);
                 const RT dn = d0 * n0 + d1 * n1 + d2 * n2;
                 RT gv, gk;
                 if (YUK) {
@@ -243,56 +244,89 @@ __global__ void __launch_bounds__(256)
                     gv = ri;
                     gk = dn * ri * ri * ri;
                 }
-                SV[p][0] += wb0 * gv;
-                SV[p][1] += wb1 * gv;
-                SV[p][2] += wb2 * gv;
-                SK[p][0] += wb0 * gk;
-                SK[p][1] += wb1 * gk;
-                SK[p][2] += wb2 * gk;
+                sv0 += wb0 * gv;
+                sv1 += wb1 * gv;
+                sv2 += wb2 * gv;
+                sk0 += wb0 * gk;
+                sk1 += wb1 * gk;
+                sk2 += wb2 * gk;
             }
-        }
-        const double sc = sAa[tl] * sAb[sl] * INV4PI;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double wa = sc * R.w[p] * R.b[p][a];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    Vl[h][3 * a + b] += wa * double(SV[p][b]);
-                    Kl[h][3 * a + b] += wa * double(SK[p][b]);
-                }
+                Vl[3 * a] += wa * double(sv0);
+                Vl[3 * a + 1] += wa * double(sv1);
+                Vl[3 * a + 2] += wa * double(sv2);
+                Kl[3 * a] += wa * double(sk0);
+                Kl[3 * a + 1] += wa * double(sk1);
+                Kl[3 * a + 2] += wa * double(sk2);
             }
         }
     }
 
-    // reduce both operators through the shared tile, V then K
+    // fold both operators onto the block's vertices through the shared tile,
+    // V then K: first the source corners of each source vertex (in place,
+    // row by row), then the target corners of each target vertex.  A thread
+    // owns one source vertex jb and a strided set of rows; the corner lists
+    // are read once into registers and every tile read is independent (an
+    // absent corner reads the zero row / column), so the reads pipeline.
+    const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+    const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
+    int cb[MAXS];
+#pragma unroll
+    for (int l = 0; l < MAXS; ++l) {
+        const int c = sSb[jb][l];
+        cb[l] = c < 0 ? BB * 3 : c;
+    }
+    for (int k = tid; k < BB * 3 + 1; k += NT) acc[BA * 3][k] = 0.0;
+    if (tid < BA * 3) acc[tid][BB * 3] = 0.0;
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int tl = tid / BB + 8 * h, sl = tid % BB;
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[3 * a + b] : Kl[3 * a + b];
+        __syncthreads();
+        constexpr int RMAX = BA * 3;
+        constexpr int RPT = (RMAX + NT / (BB * 3) - 1) / (NT / (BB * 3)); // rows per thread, nB <= BB * 3
+        double colsum[RPT];
+        int nrow = 0;
+        if (colthread) {
 #pragma unroll
-                for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[h][3 * a + b] : Kl[h][3 * a + b];
+            for (int r = 0; r < RPT; ++r) {
+                const int sa = r0 + r * rstep;
+                double t = 0.0;
+                if (sa < RMAX) {
+                    double v[MAXS];
+#pragma unroll
+                    for (int l = 0; l < MAXS; ++l) v[l] = acc[sa][cb[l]];
+#pragma unroll
+                    for (int l = 0; l < MAXS; ++l) t += v[l];
+                    nrow = r + 1;
+                }
+                colsum[r] = t;
+            }
         }
         __syncthreads();
+        if (colthread)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
+        __syncthreads();
         double *E = op == 0 ? EV : EK;
-        for (int o = tid; o < nA * nB; o += 256) {
-            const int ia = o / nB, jb = o % nB;
-            double s = 0.0;
-            for (int k = 0; k < MAXS; ++k) {
-                const int sa = sSa[ia][k];
-                if (sa < 0) break;
-                for (int l = 0; l < MAXS; ++l) {
-                    const int sb = sSb[jb][l];
-                    if (sb < 0) break;
-                    s += acc[sa][sb];
+        if (colthread)
+            for (int ia = r0; ia < nA; ia += rstep) {
+                double v[MAXS];
+#pragma unroll
+                for (int k = 0; k < MAXS; ++k) {
+                    const int ra = sSa[ia][k];
+                    v[k] = acc[ra < 0 ? BA * 3 : ra][jb];
                 }
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < MAXS; ++k) t += v[k];
+                E[(pA - rowbase + ia) * ldE + pB + jb] = t;
             }
-            E[(pA - rowbase + ia) * ldE + pB + jb] = s;
-        }
         __syncthreads();
     }
 }
@@ -728,7 +762,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         dim3 grid(unsigned(T.nbB), unsigned(b1 - b0));
         if (p.timing) p.timer.begin(T_ASM, s);
 #define PB_REGULAR(Y, RT, XQ, NQ, CEN)                                                                           \
-    hipLaunchKernelGGL((k_bem_regular<Y, RT>), grid, dim3(256), 0, s, T.nt, S.m_tri, XQ, NQ, CEN, S.m_area, S.A_pref, \
+    hipLaunchKernelGGL((k_bem_regular<Y, RT>), grid, dim3(REG_THREADS), 0, s, T.nt, S.m_tri, XQ, NQ, CEN, S.m_area, S.A_pref, \
                        S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]), EV, EK, T.SB,      \
                        kappa, R, RF)
         if (p.precision == PBFB_MIXED) {
