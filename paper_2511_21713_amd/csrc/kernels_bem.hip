@@ -581,6 +581,7 @@ __global__ void k_diag_and_narrow(int64_t nv, int64_t ld, int64_t ld_out, const 
 // ---------------------------------------------------------------------------
 // sparse approximate inverse of the single-layer block (GMRES preconditioner)
 // ---------------------------------------------------------------------------
+constexpr int SPAI_SMALL = 8; // largest 1-ring of the one-wavefront path
 // Row i minimises || m^T V' - e_i^T ||_2 over m supported on the 1-ring P(i)
 // of vertex i, V' = columns [nv, 2nv) of the stored rows (the signed
 // single-layer block of the operator).  Normal equations
@@ -599,6 +600,7 @@ __global__ void __launch_bounds__(256)
     const int tid = threadIdx.x;
     const int64_t i = blockIdx.x;
     const int p0 = ring_ptr[i], m = ring_ptr[i + 1] - p0;
+    if (m <= SPAI_SMALL) return; // handled by k_spai_small
     for (int a = tid; a < m; a += 256) P[a] = ring[p0 + a];
     __syncthreads();
     const int npair = m * (m + 1) / 2;
@@ -671,6 +673,96 @@ __global__ void __launch_bounds__(256)
             for (int a = 0; a < m; ++a) val[p0 + a] = rhs[a];
         }
     }
+}
+
+// Rows whose 1-ring has at most SPAI_SMALL vertices (every vertex of the
+// usual surface meshes): one wavefront per row, each lane streams whole
+// columns of the m rows and keeps the m (m + 1) / 2 Gram partial sums in
+// registers; a fixed xor-shuffle tree then sums them across the lanes.
+template <typename MT>
+__global__ void __launch_bounds__(256)
+    k_spai_small(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ ring_ptr,
+                 const int32_t *__restrict__ ring, double *__restrict__ val, int *__restrict__ bad)
+{
+    constexpr int NP = SPAI_SMALL * (SPAI_SMALL + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = blockIdx.x * int64_t(4) + (threadIdx.x >> 6);
+    if (i >= nv) return;
+    const int p0 = ring_ptr[i], m = ring_ptr[i + 1] - p0;
+    if (m > SPAI_SMALL) return; // handled by k_spai
+    const MT *rows[SPAI_SMALL];
+#pragma unroll
+    for (int a = 0; a < SPAI_SMALL; ++a) rows[a] = B + int64_t(ring[p0 + (a < m ? a : 0)]) * ld + nv;
+    double g[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) g[k] = 0.0;
+    for (int64_t c = lane; c < nv; c += 64) {
+        double x[SPAI_SMALL];
+#pragma unroll
+        for (int a = 0; a < SPAI_SMALL; ++a) x[a] = a < m ? double(rows[a][c]) : 0.0;
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < SPAI_SMALL; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++k) g[k] = fma(x[a], x[b], g[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off);
+    if (lane != 0) return;
+    // Cholesky in place on the packed lower triangle g[a (a + 1) / 2 + b]
+#define GP(a, b) g[(a) * ((a) + 1) / 2 + (b)]
+    double r[SPAI_SMALL];
+#pragma unroll
+    for (int a = 0; a < SPAI_SMALL; ++a) r[a] = a < m ? double(rows[a][i]) : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < SPAI_SMALL; ++a) {
+        if (a < m) {
+            double d = GP(a, a);
+#pragma unroll
+            for (int k = 0; k < a; ++k) d -= GP(a, k) * GP(a, k);
+            ok = ok && d > 0.0;
+            GP(a, a) = sqrt(d);
+#pragma unroll
+            for (int b = a + 1; b < SPAI_SMALL; ++b) {
+                if (b < m) {
+                    double t = GP(b, a);
+#pragma unroll
+                    for (int k = 0; k < a; ++k) t -= GP(b, k) * GP(a, k);
+                    GP(b, a) = t / GP(a, a);
+                }
+            }
+        }
+    }
+    if (!ok) {
+        atomicOr(bad, 4);
+        for (int a = 0; a < m; ++a) val[p0 + a] = 0.0;
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < SPAI_SMALL; ++a) {
+        if (a < m) {
+            double t = r[a];
+#pragma unroll
+            for (int k = 0; k < a; ++k) t -= GP(a, k) * r[k];
+            r[a] = t / GP(a, a);
+        }
+    }
+#pragma unroll
+    for (int a = SPAI_SMALL - 1; a >= 0; --a) {
+        if (a < m) {
+            double t = r[a];
+#pragma unroll
+            for (int k = a + 1; k < SPAI_SMALL; ++k)
+                if (k < m) t -= GP(k, a) * r[k];
+            r[a] = t / GP(a, a);
+        }
+    }
+#undef GP
+#pragma unroll
+    for (int a = 0; a < SPAI_SMALL; ++a)
+        if (a < m) val[p0 + a] = r[a];
 }
 
 // ===========================================================================
@@ -821,12 +913,19 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     release_scratch(p, SCR_TPVAL);
     // approximate inverse of the single-layer block, from the stored values
     PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
-    if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const float *>(S.B), ld,
-                           S.ring_ptr, S.ring, S.spai, p.d_bad);
-    else
-        hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const double *>(S.B),
-                           ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+    if (p.precision == PBFB_MIXED) {
+        hipLaunchKernelGGL(k_spai_small<float>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv,
+                           static_cast<const float *>(S.B), ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+        if (T.max_ring > SPAI_SMALL)
+            hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const float *>(S.B),
+                               ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+    } else {
+        hipLaunchKernelGGL(k_spai_small<double>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv,
+                           static_cast<const double *>(S.B), ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+        if (T.max_ring > SPAI_SMALL)
+            hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv,
+                               static_cast<const double *>(S.B), ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+    }
     PB_HIP(hipGetLastError());
     int bad = 0;
     PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -92,6 +92,7 @@ struct SurfaceTopo {
     std::vector<int32_t> tp_ptr, tp_sig;
     // 1-ring pattern of the sparse approximate inverse
     std::vector<int32_t> ring_ptr, ring;
+    int max_ring = 0;
 };
 
 struct SurfaceDev {

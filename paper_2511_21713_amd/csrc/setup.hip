@@ -160,6 +160,7 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
     // 1-ring of each vertex (itself and every vertex sharing a triangle), ascending
     S.ring_ptr.assign(S.nv + 1, 0);
     S.ring.clear();
+    S.max_ring = 0;
     {
         std::vector<int32_t> r;
         for (int64_t i = 0; i < S.nv; ++i) {
@@ -169,6 +170,7 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
             std::sort(r.begin(), r.end());
             r.erase(std::unique(r.begin(), r.end()), r.end());
             PB_CHECK(r.size() <= size_t(MAXRING), PBFB_EMESH, "surface vertex with more than 63 neighbours");
+            S.max_ring = std::max(S.max_ring, int(r.size()));
             S.ring.insert(S.ring.end(), r.begin(), r.end());
             S.ring_ptr[i + 1] = int32_t(S.ring.size());
         }
