@@ -154,6 +154,19 @@ void release_all_scratch(Problem &p)
     for (int i = 0; i < SCR_N; ++i) release_scratch(p, i);
 }
 
+double *Workspace::doubles(size_t n)
+{
+    const size_t want = sizeof(double) * (n ? n : 1);
+    if (bytes < want) {
+        if (ptr) PB_HIP(hipFree(ptr));
+        ptr = nullptr;
+        bytes = 0;
+        PB_HIP(hipMalloc(&ptr, want));
+        bytes = want;
+    }
+    return static_cast<double *>(ptr);
+}
+
 // ---------------------------------------------------------------------------
 // event timers
 // ---------------------------------------------------------------------------
@@ -292,6 +305,7 @@ void pbfb_ctx_destroy(pbfb_ctx *ctx)
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     (void)hipStreamDestroy(ctx->c.stream);
+    if (ctx->c.asm_ws.ptr) (void)hipFree(ctx->c.asm_ws.ptr);
     delete ctx;
 }
 

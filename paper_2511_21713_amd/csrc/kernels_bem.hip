@@ -833,24 +833,37 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
                        S.area, S.g, p.d_x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
 
     const int64_t nv = T.nv, ld = bem_ld(nv);
-    // FP64 storage assembles in place; mixed precision assembles in an FP64
-    // scratch copy and narrows at the end
-    double *B64 = p.precision == PBFB_MIXED ? scratch<double>(p, SCR_B64, nv * ld) : static_cast<double *>(S.B);
-    double *WV = scratch<double>(p, SCR_W0, nv * T.SB);
-    double *WK = scratch<double>(p, SCR_W1, nv * T.SB);
-    // chunk the target blocks so that E stays within ~8 GB per operator
+    // chunks of target blocks, so that E stays within 2^30 entries per operator
     const int64_t max_rows = std::max<int64_t>(BA * 3, (int64_t(1) << 30) / std::max<int64_t>(T.SB, 1));
-    QRule6 R = q6arg();
-    QRule6F RF = q6farg();
-    int64_t b0 = 0;
-    bool first = true;
-    while (b0 < T.nbA) {
+    std::vector<std::pair<int64_t, int64_t>> chunks;
+    int64_t chunk_rows = 0;
+    for (int64_t b0 = 0; b0 < T.nbA;) {
         int64_t b1 = b0;
         while (b1 < T.nbA && T.A_pref[b1 + 1] - T.A_pref[b0] <= max_rows) ++b1;
         if (b1 == b0) b1 = b0 + 1;
-        const int64_t rows = T.A_pref[b1] - T.A_pref[b0];
-        double *EV = scratch<double>(p, SCR_E0, rows * T.SB);
-        double *EK = scratch<double>(p, SCR_E1, rows * T.SB);
+        chunks.push_back({b0, b1});
+        chunk_rows = std::max<int64_t>(chunk_rows, T.A_pref[b1] - T.A_pref[b0]);
+        b0 = b1;
+    }
+    // the context's assembly workspace: E (V, K), W (V, K), FP64 staging
+    // (mixed precision assembles in FP64 and narrows at the end; FP64 storage
+    // assembles in place), vertex coordinates and touching-pair blocks
+    std::lock_guard<std::mutex> ws_lock(p.ctx->asm_ws.mu);
+    struct Drain { // on every exit the stream drains before the workspace is released
+        hipStream_t s;
+        ~Drain() { (void)hipStreamSynchronize(s); }
+    } drain{s};
+    const bool stage64 = p.precision == PBFB_MIXED;
+    const size_t nE = size_t(chunk_rows) * T.SB, nW = size_t(nv) * T.SB;
+    double *ws = p.ctx->asm_ws.doubles(2 * nE + 2 * nW + (stage64 ? size_t(nv) * ld : 0) + 3 * nv + 18 * S.ntp);
+    double *EV = ws, *EK = EV + nE, *WV = EK + nE, *WK = WV + nW;
+    double *B64 = stage64 ? WK + nW : static_cast<double *>(S.B);
+    double *vx = (stage64 ? B64 + size_t(nv) * ld : WK + nW), *tpv = vx + 3 * nv;
+    QRule6 R = q6arg();
+    QRule6F RF = q6farg();
+    bool first = true;
+    for (const auto &ch : chunks) {
+        const int64_t b0 = ch.first, b1 = ch.second;
         dim3 grid(unsigned(T.nbB), unsigned(b1 - b0));
         if (p.timing) p.timer.begin(T_ASM, s);
 #define PB_REGULAR(Y, RT, XQ, NQ, CEN)                                                                           \
@@ -871,21 +884,14 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
                            S.LA, S.LA_blk, b0, b1, int64_t(T.A_pref[b0]), EV, EK, WV, WK, first ? 1 : 0);
         PB_HIP(hipGetLastError());
         first = false;
-        b0 = b1;
     }
-    release_scratch(p, SCR_E0);
-    release_scratch(p, SCR_E1);
     const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
     PB_HIP(hipMemsetAsync(B64, 0, sizeof(double) * nv * ld, s));
     hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, T.SB, ld, S.LB_ptr, S.LB,
                        WV, WK, sV, sK, B64);
     PB_HIP(hipGetLastError());
-    release_scratch(p, SCR_W0);
-    release_scratch(p, SCR_W1);
     // touching pairs
-    double *vx = scratch<double>(p, SCR_VX, 3 * nv);
     hipLaunchKernelGGL(k_gather_coords, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, S.g, p.d_x, vx);
-    double *tpv = scratch<double>(p, SCR_TPVAL, 18 * S.ntp);
     GL4 G = gl4arg();
     if (p.timing) p.timer.begin(T_SING, s);
     if (yuk)
@@ -903,14 +909,11 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     if (p.precision == PBFB_MIXED) {
         hipLaunchKernelGGL(k_diag_and_narrow, dim3(nblk(ld, 256), unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64,
                            S.vdiag, static_cast<float *>(S.B));
-        PB_HIP(hipStreamSynchronize(s));
-        release_scratch(p, SCR_B64);
     } else {
         hipLaunchKernelGGL(k_diag_and_narrow, dim3(1, unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64, S.vdiag,
                            (float *)nullptr);
     }
     PB_HIP(hipGetLastError());
-    release_scratch(p, SCR_TPVAL);
     // approximate inverse of the single-layer block, from the stored values
     PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
     if (p.precision == PBFB_MIXED) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <mutex>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -119,9 +120,21 @@ struct SurfaceDev {
     double *spai = nullptr;
 };
 
+// Device workspace shared by the problems of a context for their dense
+// assembly (expanded tile matrices, gather buffers, FP64 staging): grown on
+// demand, never shrunk, freed with the context.  One assembly uses it at a
+// time (the mutex is held until the assembly's stream has drained).
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    std::mutex mu;
+    double *doubles(size_t n);
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    Workspace asm_ws;
 };
 
 enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_PREC = 5, T_NCLASS = 6 };
@@ -144,8 +157,7 @@ struct EventTimer {
 };
 
 enum ScratchSlot {
-    SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_E0, SCR_E1, SCR_W0, SCR_W1,
-    SCR_TPVAL, SCR_B64, SCR_VX, SCR_TPTAU,
+    SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
     SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX,
     SCR_N
