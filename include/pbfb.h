@@ -140,8 +140,8 @@ typedef struct {
                           *   single-layer blocks: sparse approximate inverse on each vertex 1-ring
                           *   (row i minimises || m^T V' - e_i^T ||_2);
                           * PBFB_PC_DIAG: inverse of the diagonal of J */
-    int cheb_degree;     /* 8 (1..64) */
-    double cheb_ratio;   /* 30 (> 1) */
+    int cheb_degree;     /* 16 (1..64) */
+    double cheb_ratio;   /* 200 (> 1) */
 } pbfb_solve_opts;
 enum { PBFB_PC_DIAG = 0, PBFB_PC_CHEB_SPAI = 1 };
 void pbfb_solve_opts_default(pbfb_solve_opts *o);

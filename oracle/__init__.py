@@ -302,8 +302,8 @@ class Oracle:
         lib().pbref_jacobian_rows(self.h, scheme, _d(phi), _d(v), rows.size, _l(rows), _d(out))
         return out
 
-    def gmres(self, scheme, phi, b, tol=1e-10, restart=200, maxit=5000, precond=PC_DIAG, cheb_degree=8,
-              cheb_ratio=30.0):
+    def gmres(self, scheme, phi, b, tol=1e-10, restart=200, maxit=5000, precond=PC_DIAG, cheb_degree=16,
+              cheb_ratio=200.0):
         phi = _f64(phi); b = _f64(b); x = np.zeros(self.n); it = C.c_int(0)
         st = lib().pbref_gmres_pc(self.h, scheme, _d(phi), _d(b), _d(x), tol, restart, maxit, precond,
                                   cheb_degree, cheb_ratio, C.byref(it))

@@ -1341,26 +1341,41 @@ void pbref_cheb_diag(int64_t n, const double *fdiag, const double *dinv, double 
     cheb_terms(n, diag_apply, &c, dinv, lmax, ratio, k, r, z);
 }
 
+/* the FEM block F = A + J_scheme(u) as rows (assembled once per GMRES call) */
 typedef struct {
-    const pbref *p;
-    int scheme;
-    const double *u;
-    double *tmp;
-} fem_ctx;
-static void fem_block_apply(const void *ctx, const double *in, double *out)
+    int64_t n;
+    int32_t *ptr, *col;
+    double *val;
+} csr;
+static int fem_block_csr(const pbref *p, int scheme, const double *u, csr *F)
 {
-    const fem_ctx *c = ctx;
-    stiffness_apply(c->p, in, out);
-    pbref_fem_jacobian(c->p, c->scheme, c->u, in, c->tmp);
-    for (int64_t i = 0; i < c->p->nn; ++i) out[i] += c->tmp[i];
+    F->n = p->nn;
+    F->ptr = malloc(sizeof(int32_t) * (p->nn + 1));
+    F->col = malloc(sizeof(int32_t) * 128 * p->nn);
+    F->val = malloc(sizeof(double) * 128 * p->nn);
+    F->ptr[0] = 0;
+    for (int64_t i = 0; i < p->nn; ++i) {
+        int m = fem_row(p, scheme, u, i, F->col + F->ptr[i], F->val + F->ptr[i]);
+        if (m < 0) return -1;
+        F->ptr[i + 1] = F->ptr[i] + m;
+    }
+    return 0;
+}
+static void csr_apply(const void *ctx, const double *in, double *out)
+{
+    const csr *F = ctx;
+    for (int64_t i = 0; i < F->n; ++i) {
+        double s = 0.0;
+        for (int32_t e = F->ptr[i]; e < F->ptr[i + 1]; ++e) s += F->val[e] * in[F->col[e]];
+        out[i] = s;
+    }
 }
 
 typedef struct {
     int mode, k;
     double ratio, lmax;
-    int scheme;
-    const double *u;
     double *dinv;
+    csr F;
     int32_t *sp_ptr[2], *sp_col[2];
     double *sp_val[2];
 } precond;
@@ -1372,13 +1387,12 @@ static int precond_build(pbref *p, int scheme, const double *phi, int mode, int 
     P->mode = mode;
     P->k = k;
     P->ratio = ratio;
-    P->scheme = scheme;
-    P->u = phi;
     P->dinv = malloc(sizeof(double) * n);
     precond_diag(p, scheme, phi, P->dinv);
     if (mode == PBREF_PC_DIAG) return 0;
     P->lmax = pbref_fem_gershgorin(p, scheme, phi);
     if (!isfinite(P->lmax)) return -1;
+    if (fem_block_csr(p, scheme, phi, &P->F)) return -1;
     for (int w = 0; w < 2; ++w) {
         const surface *S = &p->s[w];
         int64_t nnz = pbref_surface_ring(p, w, NULL, NULL);
@@ -1396,6 +1410,9 @@ static int precond_build(pbref *p, int scheme, const double *phi, int mode, int 
 static void precond_free(precond *P)
 {
     free(P->dinv);
+    free(P->F.ptr);
+    free(P->F.col);
+    free(P->F.val);
     for (int w = 0; w < 2; ++w) {
         free(P->sp_ptr[w]);
         free(P->sp_col[w]);
@@ -1411,9 +1428,7 @@ static void precond_apply(pbref *p, const precond *P, const double *v, double *z
         for (int64_t i = 0; i < n; ++i) z[i] = P->dinv[i] * v[i];
         return;
     }
-    fem_ctx c = {p, P->scheme, P->u, malloc(sizeof(double) * nn)};
-    cheb_terms(nn, fem_block_apply, &c, P->dinv, P->lmax, P->ratio, P->k, v, z);
-    free(c.tmp);
+    cheb_terms(nn, csr_apply, &P->F, P->dinv, P->lmax, P->ratio, P->k, v, z);
     int64_t off = nn;
     for (int w = 0; w < 2; ++w) {
         const surface *S = &p->s[w];
@@ -1620,8 +1635,8 @@ void pbref_opts_default(pbref_opts *o)
     o->gmres_restart = 200;
     o->max_gmres = 2000;
     o->precond = PBREF_PC_CHEB_SPAI;
-    o->cheb_degree = 8;
-    o->cheb_ratio = 30.0;
+    o->cheb_degree = 16;
+    o->cheb_ratio = 200.0;
 }
 
 static int all_finite(int64_t n, const double *x)

@@ -500,8 +500,8 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->max_gmres = 2000;
     o->krylov_fp32 = 0;
     o->precond = PBFB_PC_CHEB_SPAI;
-    o->cheb_degree = 8;
-    o->cheb_ratio = 30.0;
+    o->cheb_degree = 16;
+    o->cheb_ratio = 200.0;
 }
 
 } // extern "C"
