@@ -61,6 +61,7 @@ struct GDesc {
     const int32_t *sp_ptr[2], *sp_col[2];
     const double *sp_val[2];
     double *z, *zb, *dk, *t; // P^-1 input (full), Chebyshev ping-pong buffer and direction, V y
+    double *coef;            // Chebyshev coefficients: [0] = theta, [2s], [2s+1] = rho_s rho_{s-1}, 2 rho_s/delta
 };
 
 struct GState {
@@ -125,12 +126,25 @@ __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, con
 // block is written to z when k - 1 - s is even and to zb otherwise, so the
 // last term always lands in z.
 // ---------------------------------------------------------------------------
-__device__ inline void cheb_params(const GDesc &d, double &theta, double &delta, double &sigma)
+// the Chebyshev coefficients of every instance, from its bound lmax (one
+// thread per instance, once per batched solve)
+__global__ void k_cheb_coef(const GDesc *__restrict__ D, int nb)
 {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb) return;
+    const GDesc &d = D[q];
+    if (d.pc != PBFB_PC_CHEB_SPAI) return;
     const double hi = *d.lmax, lo = hi / d.cheb_ratio;
-    theta = 0.5 * (hi + lo);
-    delta = 0.5 * (hi - lo);
-    sigma = theta / delta;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    d.coef[0] = theta;
+    d.coef[1] = 0.0;
+    for (int s = 1; s < d.cheb_k; ++s) {
+        const double rho1 = 1.0 / (2.0 * sigma - rho);
+        d.coef[2 * s] = rho1 * rho;
+        d.coef[2 * s + 1] = 2.0 * rho1 / delta;
+        rho = rho1;
+    }
 }
 
 __device__ inline double pc_src(const GDesc &d, const GState &s, int64_t r)
@@ -154,9 +168,7 @@ __global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, co
         zv = d.dinv[k] * pc_src(d, s, k);
         d.z[k] = zv;
     } else if (k < d.nn) {
-        double theta, delta, sigma;
-        cheb_params(d, theta, delta, sigma);
-        zv = d.dinv[k] * pc_src(d, s, k) / theta;
+        zv = d.dinv[k] * pc_src(d, s, k) / d.coef[0];
         d.dk[k] = zv;
         ((d.cheb_k - 1) % 2 == 0 ? d.z : d.zb)[k] = zv;
         last = d.cheb_k == 1;
@@ -206,12 +218,7 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
     acc += __shfl_xor(acc, 2);
     acc += __shfl_xor(acc, 1);
     if (sub != 0 || row >= d.nn) return;
-    double theta, delta, sigma;
-    cheb_params(d, theta, delta, sigma);
-    double rho0 = 1.0 / sigma;
-    for (int q = 1; q < step; ++q) rho0 = 1.0 / (2.0 * sigma - rho0);
-    const double rho1 = 1.0 / (2.0 * sigma - rho0);
-    const double dv = rho1 * rho0 * d.dk[row] + 2.0 * rho1 / delta * d.dinv[row] * (pc_src(d, s, row) - acc);
+    const double dv = d.coef[2 * step] * d.dk[row] + d.coef[2 * step + 1] * d.dinv[row] * (pc_src(d, s, row) - acc);
     d.dk[row] = dv;
     const double zv = zp[row] + dv;
     zn[row] = zv;
@@ -613,6 +620,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.t = scratch<double>(p, SCR_PT, n);
         d.zb = scratch<double>(p, SCR_PZB, p.nn);
         d.dk = scratch<double>(p, SCR_PDK, p.nn);
+        d.coef = scratch<double>(p, SCR_PCOEF, 2 * 64 + 2);
         if (J.pc == PBFB_PC_CHEB_SPAI) kmax = std::max(kmax, J.cheb_k);
         d.vf32 = J.basis32 && p.precision == PBFB_MIXED;
         if (d.vf32) d.V = scratch<float>(p, SCR_BASIS32, size_t(m + 1) * n);
@@ -699,6 +707,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     const int POLL = 2;
     int polls = 0;
     bool finished = false;
+    hipLaunchKernelGGL(k_cheb_coef, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, dD, nb);
     for (int it = 0; it < maxiter_host && !finished; ++it) {
         if (tm) tm->begin(T_PREC, s);
         hipLaunchKernelGGL(k_bprec0, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
