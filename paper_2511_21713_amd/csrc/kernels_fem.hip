@@ -153,6 +153,36 @@ __global__ void k_surface_coupling(int64_t nv, const int32_t *__restrict__ v2t_p
 // ---------------------------------------------------------------------------
 // reaction terms: calN, calN', calN'' for LIN / T3 / HS
 // ---------------------------------------------------------------------------
+// sinh and cosh together: below 1/2 in magnitude from their Taylor series
+// (terms through t^15 and t^16, remainder below 1e-19 relative), above from
+// one exponential (cancellation in e - 1/e costs at most a factor 2.2 there)
+__device__ inline void sinh_cosh(double t, double &sh, double &ch)
+{
+    const double a = fabs(t);
+    if (a < 0.5) {
+        const double t2 = t * t;
+        sh = t * (1.0 + t2 * (1.0 / 6.0) *
+                            (1.0 + t2 * (1.0 / 20.0) *
+                                       (1.0 + t2 * (1.0 / 42.0) *
+                                                  (1.0 + t2 * (1.0 / 72.0) *
+                                                             (1.0 + t2 * (1.0 / 110.0) *
+                                                                        (1.0 + t2 * (1.0 / 156.0) *
+                                                                                   (1.0 + t2 * (1.0 / 210.0))))))));
+        ch = 1.0 + t2 * 0.5 *
+                       (1.0 + t2 * (1.0 / 12.0) *
+                                  (1.0 + t2 * (1.0 / 30.0) *
+                                             (1.0 + t2 * (1.0 / 56.0) *
+                                                        (1.0 + t2 * (1.0 / 90.0) *
+                                                                   (1.0 + t2 * (1.0 / 132.0) *
+                                                                              (1.0 + t2 * (1.0 / 182.0) *
+                                                                                         (1.0 + t2 * (1.0 / 240.0))))))));
+    } else {
+        const double e = exp(a), ei = 1.0 / e;
+        ch = 0.5 * (e + ei);
+        sh = copysign(0.5 * (e - ei), t);
+    }
+}
+
 __device__ inline void scheme_eval(int s, double t, double &f0, double &f1, double &f2)
 {
     if (s == PBFB_LIN) {
@@ -164,99 +194,105 @@ __device__ inline void scheme_eval(int s, double t, double &f0, double &f1, doub
         f1 = 1.0 + 0.5 * t * t;
         f2 = t;
     } else {
-        f0 = sinh(t);
-        f1 = cosh(t);
+        sinh_cosh(t, f0, f1);
         f2 = f0;
     }
 }
 
-// d_val = d_val0 + J_scheme(u) on the u columns of each FEM row
+// Element pass of the reaction terms: each tet evaluates the 27-point rule
+// once and leaves its contributions to its four nodes (row gathers below add
+// them up in a fixed order, so no atomics are needed).
+//   MODE_N: N_a           = c sum_q w_q |T| calN(u_h)  phi_a                 (4 per tet)
+//   MODE_W: N_a, J_a, H_a at u + omega D: calN, calN' D_h, calN'' D_h^2        (12 per tet)
+//   MODE_J: J_ab          = c sum_q w_q |T| calN'(u_h) phi_a phi_b           (16 per tet)
+enum { MODE_N = 0, MODE_W = 1, MODE_J = 2 };
+template <int MODE>
+__global__ void __launch_bounds__(128)
+    k_tet_reaction(int64_t ntet, const double *__restrict__ tg, const int32_t *__restrict__ tet,
+                   const double *__restrict__ u, const double *__restrict__ D, double omega, int scheme, double c,
+                   TetRuleArg R, double *__restrict__ out)
+{
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (t >= ntet) return;
+    const int32_t *T = tet + 4 * t;
+    double uk[4], dk[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+        if (MODE == MODE_W) dk[k] = D[T[k]];
+        uk[k] = u[T[k]] + (MODE == MODE_W ? omega * dk[k] : 0.0);
+    }
+    const double cv = c * tg[16 * t + 12];
+    constexpr int NO = MODE == MODE_N ? 4 : MODE == MODE_W ? 12 : 16;
+    double acc[NO];
+#pragma unroll
+    for (int k = 0; k < NO; ++k) acc[k] = 0.0;
+    for (int q = 0; q < 27; ++q) {
+        const double uh = R.b[q][0] * uk[0] + R.b[q][1] * uk[1] + R.b[q][2] * uk[2] + R.b[q][3] * uk[3];
+        double f0, f1, f2;
+        scheme_eval(scheme, uh, f0, f1, f2);
+        if (MODE == MODE_N) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a] += cv * R.w[q] * f0 * R.b[q][a];
+        } else if (MODE == MODE_W) {
+            const double dh = R.b[q][0] * dk[0] + R.b[q][1] * dk[1] + R.b[q][2] * dk[2] + R.b[q][3] * dk[3];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double w = cv * R.w[q] * R.b[q][a];
+                acc[a] += w * f0;
+                acc[4 + a] += w * f1 * dh;
+                acc[8 + a] += w * f2 * dh * dh;
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double wq = cv * R.w[q] * f1 * R.b[q][a];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[4 * a + b] += wq * R.b[q][b];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) out[NO * t + k] = acc[k];
+}
+
+// d_val = d_val0 + J_scheme(u) on the u columns of each FEM row, from the
+// element blocks (16 per tet), row by row
 __global__ void k_jacobian(int64_t nn, const int32_t *__restrict__ rowptr, const double *__restrict__ val0,
                            double *__restrict__ val, float *__restrict__ val32, const int32_t *__restrict__ n2t_ptr,
                            const int32_t *__restrict__ n2t, const int32_t *__restrict__ slot4,
-                           const double *__restrict__ tg, const int32_t *__restrict__ tet,
-                           const double *__restrict__ u, int scheme, double c, TetRuleArg R)
+                           const double *__restrict__ Jt)
 {
     int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (a >= nn) return;
     for (int32_t s = rowptr[a]; s < rowptr[a + 1]; ++s) val[s] = val0[s];
     for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
-        int32_t t = n2t[e] >> 2, la = n2t[e] & 3;
-        const int32_t *T = tet + 4 * int64_t(t);
-        double uk[4];
-        for (int k = 0; k < 4; ++k) uk[k] = u[T[k]];
-        double cv = c * tg[16 * int64_t(t) + 12];
-        double acc[4] = {0, 0, 0, 0};
-        for (int q = 0; q < 27; ++q) {
-            double uh = R.b[q][0] * uk[0] + R.b[q][1] * uk[1] + R.b[q][2] * uk[2] + R.b[q][3] * uk[3];
-            double f0, f1, f2;
-            scheme_eval(scheme, uh, f0, f1, f2);
-            double wq = cv * R.w[q] * f1 * R.b[q][la];
-            for (int b = 0; b < 4; ++b) acc[b] += wq * R.b[q][b];
-        }
-        for (int b = 0; b < 4; ++b) val[slot4[4 * int64_t(e) + b]] += acc[b];
+        const int64_t t = n2t[e] >> 2;
+        const int la = n2t[e] & 3;
+        for (int b = 0; b < 4; ++b) val[slot4[4 * int64_t(e) + b]] += Jt[16 * t + 4 * la + b];
     }
     if (val32)
         for (int32_t s = rowptr[a]; s < rowptr[a + 1]; ++s) val32[s] = float(val[s]);
 }
 
-// out_a = c int calN(u_h) phi_a
-__global__ void k_nonlinear(int64_t nn, const int32_t *__restrict__ n2t_ptr, const int32_t *__restrict__ n2t,
-                            const double *__restrict__ tg, const int32_t *__restrict__ tet,
-                            const double *__restrict__ u, int scheme, double c, TetRuleArg R, double *__restrict__ out)
+// out_k[a] = sum over the tets at node a of their contribution k to a (K per tet and node)
+template <int K>
+__global__ void k_node_gather(int64_t nn, const int32_t *__restrict__ n2t_ptr, const int32_t *__restrict__ n2t,
+                              const double *__restrict__ per_tet, double *__restrict__ o0, double *__restrict__ o1,
+                              double *__restrict__ o2)
 {
     int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (a >= nn) return;
-    double s = 0.0;
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
     for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
-        int32_t t = n2t[e] >> 2, la = n2t[e] & 3;
-        const int32_t *T = tet + 4 * int64_t(t);
-        double uk[4];
-        for (int k = 0; k < 4; ++k) uk[k] = u[T[k]];
-        double cv = c * tg[16 * int64_t(t) + 12];
-        for (int q = 0; q < 27; ++q) {
-            double uh = R.b[q][0] * uk[0] + R.b[q][1] * uk[1] + R.b[q][2] * uk[2] + R.b[q][3] * uk[3];
-            double f0, f1, f2;
-            scheme_eval(scheme, uh, f0, f1, f2);
-            s += cv * R.w[q] * f0 * R.b[q][la];
-        }
+        const int64_t t = n2t[e] >> 2;
+        const int la = n2t[e] & 3;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] += per_tet[4 * K * t + 4 * k + la];
     }
-    out[a] = s;
-}
-
-// Relaxation search terms at u + omega D: rN = N(.), rJ = J(.) D, rH = H(.)[D]
-__global__ void k_omega_terms(int64_t nn, const int32_t *__restrict__ n2t_ptr, const int32_t *__restrict__ n2t,
-                              const double *__restrict__ tg, const int32_t *__restrict__ tet,
-                              const double *__restrict__ u, const double *__restrict__ D, double omega, int scheme,
-                              double c, TetRuleArg R, double *__restrict__ rN, double *__restrict__ rJ,
-                              double *__restrict__ rH)
-{
-    int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (a >= nn) return;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
-        int32_t t = n2t[e] >> 2, la = n2t[e] & 3;
-        const int32_t *T = tet + 4 * int64_t(t);
-        double uk[4], dk[4];
-        for (int k = 0; k < 4; ++k) {
-            dk[k] = D[T[k]];
-            uk[k] = u[T[k]] + omega * dk[k];
-        }
-        double cv = c * tg[16 * int64_t(t) + 12];
-        for (int q = 0; q < 27; ++q) {
-            double uh = R.b[q][0] * uk[0] + R.b[q][1] * uk[1] + R.b[q][2] * uk[2] + R.b[q][3] * uk[3];
-            double dh = R.b[q][0] * dk[0] + R.b[q][1] * dk[1] + R.b[q][2] * dk[2] + R.b[q][3] * dk[3];
-            double f0, f1, f2;
-            scheme_eval(scheme, uh, f0, f1, f2);
-            double w = cv * R.w[q] * R.b[q][la];
-            s0 += w * f0;
-            s1 += w * f1 * dh;
-            s2 += w * f2 * dh * dh;
-        }
-    }
-    rN[a] = s0;
-    rJ[a] = s1;
-    rH[a] = s2;
+    o0[a] = s[0];
+    if (K > 1) o1[a] = s[1];
+    if (K > 2) o2[a] = s[2];
 }
 
 // per-tet integral of u sinh u - 2 cosh u + 2 for u = u_lin + u_nl (block partial sums)
@@ -574,26 +610,35 @@ void ensure_rhs(Problem &p, hipStream_t s)
 
 void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t s)
 {
-    double c = p.eps_s * p.kappa * p.kappa;
+    const double c = p.eps_s * p.kappa * p.kappa;
+    double *Jt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
+    hipLaunchKernelGGL(k_tet_reaction<MODE_J>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
+                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), Jt);
     hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_rowptr, p.d_val0, p.d_val,
-                       p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, p.d_tgeo, p.d_tet, u, scheme, c, tet_rule_arg());
+                       p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, Jt);
     PB_HIP(hipGetLastError());
 }
 
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s)
 {
-    double c = p.eps_s * p.kappa * p.kappa;
-    hipLaunchKernelGGL(k_nonlinear, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, p.d_tgeo,
-                       p.d_tet, u, scheme, c, tet_rule_arg(), out);
+    const double c = p.eps_s * p.kappa * p.kappa;
+    double *Nt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
+    hipLaunchKernelGGL(k_tet_reaction<MODE_N>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
+                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), Nt);
+    hipLaunchKernelGGL(k_node_gather<1>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Nt,
+                       out, (double *)nullptr, (double *)nullptr);
     PB_HIP(hipGetLastError());
 }
 
 void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN, double *rJ,
                      double *rH, hipStream_t s)
 {
-    double c = p.eps_s * p.kappa * p.kappa;
-    hipLaunchKernelGGL(k_omega_terms, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t,
-                       p.d_tgeo, p.d_tet, u, D, omega, scheme, c, tet_rule_arg(), rN, rJ, rH);
+    const double c = p.eps_s * p.kappa * p.kappa;
+    double *Wt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
+    hipLaunchKernelGGL(k_tet_reaction<MODE_W>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
+                       u, D, omega, scheme, c, tet_rule_arg(), Wt);
+    hipLaunchKernelGGL(k_node_gather<3>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Wt,
+                       rN, rJ, rH);
     PB_HIP(hipGetLastError());
 }
 
