@@ -142,6 +142,9 @@ typedef struct {
                           * PBFB_PC_DIAG: inverse of the diagonal of J */
     int cheb_degree;     /* 16 (1..64) */
     double cheb_ratio;   /* 200 (> 1) */
+    int hip_graph;       /* 1 (default): each Krylov step of a batch is captured once as a HIP graph and replayed;
+                          * 0: kernels launched one by one (also the case while kernel timing is enabled or on
+                          * a stream that cannot be captured).  Results are the same bit for bit */
 } pbfb_solve_opts;
 enum { PBFB_PC_DIAG = 0, PBFB_PC_CHEB_SPAI = 1 };
 void pbfb_solve_opts_default(pbfb_solve_opts *o);

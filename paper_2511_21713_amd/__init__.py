@@ -41,7 +41,7 @@ class SolveOpts(C.Structure):
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
                 ("max_gmres", C.c_int), ("krylov_fp32", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
-                ("cheb_ratio", C.c_double)]
+                ("cheb_ratio", C.c_double), ("hip_graph", C.c_int)]
 
 
 class Result(C.Structure):

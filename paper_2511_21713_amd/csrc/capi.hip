@@ -502,6 +502,7 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->precond = PBFB_PC_CHEB_SPAI;
     o->cheb_degree = 16;
     o->cheb_ratio = 200.0;
+    o->hip_graph = 1;
 }
 
 } // extern "C"

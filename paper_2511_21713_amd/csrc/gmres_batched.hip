@@ -554,11 +554,25 @@ __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, con
 // ===========================================================================
 // host driver
 // ===========================================================================
+// a captured Krylov step is valid for the same device buffer and launch shapes
+struct GraphKey {
+    void *dev = nullptr;
+    unsigned nvec = 0, ngemv = 0, nspmv = 0, npack = 0, ndot = 0, ngroups = 0, nb = 0;
+    int kmax = 0;
+    bool operator==(const GraphKey &o) const
+    {
+        return dev == o.dev && nvec == o.nvec && ngemv == o.ngemv && nspmv == o.nspmv && npack == o.npack &&
+               ndot == o.ndot && ngroups == o.ngroups && nb == o.nb && kmax == o.kmax;
+    }
+};
+
 struct BatchBuffers {
     void *dev = nullptr;
     size_t dev_bytes = 0;
     int *pinned = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t step = nullptr; // the captured Krylov step (left to process exit)
+    GraphKey key;
     ~BatchBuffers()
     {
         if (dev) (void)hipFree(dev);
@@ -668,6 +682,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
                          sizeof(WItem) * (wl_vec.size() + wl_gemv.size() + wl_spmv.size() + wl_pack.size() +
                                           wl_dot.size()) + 512;
     if (BB.dev_bytes < bytes) {
+        if (BB.step) PB_HIP(hipGraphExecDestroy(BB.step));
+        BB.step = nullptr;
         if (BB.dev) PB_HIP(hipFree(BB.dev));
         BB.dev = nullptr;
         PB_HIP(hipMalloc(&BB.dev, bytes));
@@ -708,7 +724,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     int polls = 0;
     bool finished = false;
     hipLaunchKernelGGL(k_cheb_coef, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, dD, nb);
-    for (int it = 0; it < maxiter_host && !finished; ++it) {
+    // one Krylov step of the whole batch
+    auto enqueue_step = [&]() {
         if (tm) tm->begin(T_PREC, s);
         hipLaunchKernelGGL(k_bprec0, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
         for (int step = 1; step < kmax; ++step)
@@ -737,6 +754,33 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         hipLaunchKernelGGL(k_bscale, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
         hipLaunchKernelGGL(k_bcontrol, dim3(unsigned(nb)), dim3(64), 0, s, dD, dS, dcount);
         hipLaunchKernelGGL(k_bupdx, dim3(nvec), dim3(256), 0, s, dvec, dD, dS);
+    };
+    // Without timers the step is captured once as a HIP graph (kernel nodes
+    // only) and replayed; the capture is reused while the buffer and launch
+    // shapes stay the same (the Newton steps of a solve, repeated solves).
+    bool graph = !tm;
+    for (auto *J : jobs) graph = graph && J->graph;
+    if (graph) {
+        const GraphKey key{BB.dev, nvec, ngemv, nspmv, npack, ndot, ngroups, unsigned(nb), kmax};
+        if (!(BB.step && BB.key == key)) {
+            if (BB.step) PB_HIP(hipGraphExecDestroy(BB.step));
+            BB.step = nullptr;
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                enqueue_step();
+                hipGraph_t g = nullptr;
+                PB_HIP(hipStreamEndCapture(s, &g));
+                PB_HIP(hipGraphInstantiate(&BB.step, g, nullptr, nullptr, 0));
+                PB_HIP(hipGraphDestroy(g));
+                BB.key = key;
+            } else {
+                (void)hipGetLastError(); // a stream that cannot be captured: launch one by one
+                graph = false;
+            }
+        }
+    }
+    for (int it = 0; it < maxiter_host && !finished; ++it) {
+        if (graph) PB_HIP(hipGraphLaunch(BB.step, s));
+        else enqueue_step();
         PB_HIP(hipGetLastError());
         if ((it + 1) % POLL == 0) {
             const int slot = polls % 3;

@@ -258,6 +258,7 @@ struct GmresJob {
     double cheb_ratio;
     const double *lmax;   // device scalar: Gershgorin bound of diag(F)^-1 F
     int applies;          // out: operator applications that did work
+    int graph;            // replay the Krylov step from a captured HIP graph
 };
 void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s);
 void build_precond(Problem &p, double *dinv, hipStream_t s);

@@ -113,6 +113,7 @@ static GmresJob make_job(NewtonRun &r, const double *b, double *x, hipStream_t s
     J.cheb_ratio = r.o.cheb_ratio;
     J.lmax = r.lmax;
     J.applies = 0;
+    J.graph = r.o.hip_graph;
     return J;
 }
 

@@ -65,6 +65,31 @@ def test_batch_equals_solo_bitwise(setup, precision):
         assert r["newton_iters"] == s["newton_iters"] and r["gmres_iters"] == s["gmres_iters"]
 
 
+def test_graph_replay_equals_eager_launches(setup):
+    """The Krylov step replayed from a captured HIP graph gives the same
+    results bit for bit as launching its kernels one by one, solo and in a
+    batch, across repeated solves (every replay reuses the capture)."""
+    pb, ctx, probs, solo = setup
+    for prec in (pb.FP64, pb.MIXED):
+        eager, graph = [], []
+        for prob in probs[:3]:
+            g = pb.Problem.from_inputs(ctx, prob, precision=prec)
+            eager.append(g.solve(hip_graph=0, **OPTS))
+            for _ in range(2):
+                r = g.solve(hip_graph=1, **OPTS)
+                assert r["total"] == eager[-1]["total"] and r["gmres_iters"] == eager[-1]["gmres_iters"]
+            graph.append(r)
+            g.close()
+        gs = [pb.Problem.from_inputs(ctx, prob, precision=prec) for prob in probs[:3]]
+        for rep in range(2):
+            code, res = pb.solve_batch(ctx, gs, hip_graph=1, **OPTS)
+            assert code == 0
+            for r, e in zip(res, eager):
+                assert r["total"] == e["total"] and r["gmres_iters"] == e["gmres_iters"]
+        for g in gs:
+            g.close()
+
+
 def test_batch_isolates_a_failing_instance(setup):
     pb, ctx, probs, solo = setup
     gs = [pb.Problem.from_inputs(ctx, prob) for prob in probs[:3]]
