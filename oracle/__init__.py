@@ -79,6 +79,8 @@ def lib():
         L.pbref_apply_A.argtypes = [P, dp, dp]
         L.pbref_dense_rows_apply.argtypes = [P, C.c_int, C.c_int64, dp, dp, dp, dp]
         L.pbref_rhs.argtypes = [P, dp]
+        L.pbref_set_rhs_extra.argtypes = [P, dp]
+        L.pbref_set_rhs_extra.restype = None
         L.pbref_residual.argtypes = [P, C.c_int, dp, dp]
         L.pbref_apply_jacobian.argtypes = [P, C.c_int, dp, dp, dp]
         L.pbref_residual_rows.argtypes = [P, C.c_int, dp, C.c_int64, lp, dp]
@@ -281,6 +283,14 @@ class Oracle:
         b = np.zeros(self.n)
         lib().pbref_rhs(self.h, _d(b))
         return b
+
+    def set_rhs_extra(self, e):
+        """Add e to the right-hand side of every later residual and solve (None clears)."""
+        if e is None:
+            lib().pbref_set_rhs_extra(self.h, None)
+        else:
+            self._extra = _f64(e)
+            lib().pbref_set_rhs_extra(self.h, _d(self._extra))
 
     def residual(self, scheme, phi):
         phi = _f64(phi); F = np.zeros(self.n)

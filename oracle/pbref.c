@@ -298,6 +298,7 @@ struct pbref {
     double *ss_x, *ss_w;
     int32_t *n2t_ptr, *n2t; /* FEM node -> tets */
     double *tgrad, *tvol;   /* per-tet barycentric gradients (4x3) and volume */
+    double *rhs_extra;      /* optional vector added to b (manufactured-solution tests) */
 };
 
 static int64_t nunk(const pbref *p) { return p->nn + p->s[0].nv + p->s[1].nv; }
@@ -439,6 +440,7 @@ pbref *pbref_create(int64_t n_nodes, const double *nodes, int64_t n_tets, const 
 void pbref_destroy(pbref *p)
 {
     if (!p) return;
+    free(p->rhs_extra);
     for (int w = 0; w < 2; ++w) {
         surface *S = &p->s[w];
         free(S->g);
@@ -987,7 +989,18 @@ int pbref_rhs(pbref *p, double *b)
 {
     memset(b, 0, sizeof(double) * nunk(p));
     pbref_coulomb_load(p, b + p->nn);
+    if (p->rhs_extra)
+        for (int64_t i = 0; i < nunk(p); ++i) b[i] += p->rhs_extra[i];
     return 0;
+}
+
+void pbref_set_rhs_extra(pbref *p, const double *e)
+{
+    free(p->rhs_extra);
+    p->rhs_extra = NULL;
+    if (!e) return;
+    p->rhs_extra = malloc(sizeof(double) * nunk(p));
+    memcpy(p->rhs_extra, e, sizeof(double) * nunk(p));
 }
 
 /* The Gamma rows of apply_A on a sample of rows, given those rows of the

@@ -60,6 +60,9 @@ int pbref_apply_A(pbref *, const double *phi, double *y);
 int pbref_dense_rows_apply(const pbref *, int surf, int64_t nrows, const double *V, const double *K,
                            const double *x, double *out);
 int pbref_rhs(pbref *, double *b);
+/* add a fixed vector to b in pbref_rhs, pbref_residual and pbref_solve (NULL clears);
+ * used to impose the volume source and interface jumps of manufactured solutions */
+void pbref_set_rhs_extra(pbref *, const double *e);
 int pbref_residual(pbref *, int scheme, const double *phi, double *F);
 int pbref_apply_jacobian(pbref *, int scheme, const double *phi, const double *v, double *Jv);
 /* selected rows of F or J v without dense assembly; rows are global unknown ids */
