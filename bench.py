@@ -75,6 +75,28 @@ def gemv_bytes(nm, ns, elem):
     return sum(n * 2 * n * elem + 2 * n * 8 + n * 8 for n in (nm, ns))
 
 
+def fem_nnz(prob):
+    """Nonzeros of the FEM block rows: node pairs sharing a tet, plus the
+    coupling columns of each interface node (its surface 1-ring)."""
+    import scipy.sparse as sp
+    nn = prob.nodes.shape[0]
+    T = prob.tets
+    r = np.repeat(T, 4, axis=1).ravel()
+    c = np.tile(T, (1, 4)).ravel()
+    nnz = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(nn, nn)).tocsr().nnz
+    for tri in (prob.tri_m, prob.tri_s):
+        r = np.repeat(tri, 3, axis=1).ravel()
+        c = np.tile(tri, (1, 3)).ravel()
+        nnz += sp.coo_matrix((np.ones(r.size), (r, c)), shape=(nn, nn)).tocsr().nnz
+    return nnz
+
+
+def spmv_bytes(nnz, nn, n, elem):
+    # algorithmic bytes of one FEM SpMV launch: values and 32-bit columns of
+    # the nonzeros, the FP64 input vector (all unknowns) once, FP64 output rows
+    return nnz * (elem + 4) + n * 8 + nn * 8
+
+
 def apply_flops(nm, ns, nnz):
     return 2 * (nm * 2 * nm + ns * 2 * ns) + 2 * nnz
 
@@ -306,7 +328,6 @@ def main():
     value = K / f64["elapsed"]
     ms_step = 1e3 * f64["elapsed"] / K
     nm, ns = f64["n_m"], f64["n_s"]
-    nnz_est = None
     gemv_ms, gemv_cnt = f64["timing"]["gemv"]
     apply_ms, apply_cnt = f64["timing"]["apply"]
     asm_ms, asm_cnt = f64["timing"]["assembly"]
@@ -357,7 +378,21 @@ def main():
                 "frac": asm_flops / t / 1e12 / peak if t else None}
 
     out["bem_assembly"] = {"fp64": asm_report(f64, FP64_PEAK_TFLOPS)}
-    flops = apply_flops(nm, ns, 0)
+    nnz = fem_nnz(prob)
+    nn = prob.nodes.shape[0]
+
+    def spmv_report(leg, elem):
+        ms, cnt = leg["timing"]["spmv"]
+        b = spmv_bytes(nnz, nn, leg["n"], elem)
+        gbs = b / (ms * 1e-3) / 1e9 if ms else None
+        return {"kernel": "k_bspmv / k_spmv (sell_part: sliced-ELL FEM rows)", "bound": "hbm",
+                "bytes_per_launch": b, "ms_per_launch": ms, "launches": cnt, "achieved": gbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                "nnz": nnz, "value_bytes": elem}
+
+    out["fem_spmv"] = {"fp64": spmv_report(f64, 8)}
+    out["kernel_ms"]["precond_per_solve"] = f64["timing"]["precond"][0] * f64["timing"]["precond"][1] / K
+    flops = apply_flops(nm, ns, nnz)
     if apply_ms:
         out["coupled_operator_gflops"] = flops / (apply_ms * 1e-3) / 1e9
     if not args.no_mixed:
@@ -377,6 +412,7 @@ def main():
             "coupled_operator_gflops": flops / (mx["timing"]["apply"][0] * 1e-3) / 1e9 if mx["timing"]["apply"][0] else None,
         }
         out["bem_assembly"]["mixed_fp32_eval"] = asm_report(mx, FP32_PEAK_TFLOPS)
+        out["fem_spmv"]["mixed_fp32_values"] = spmv_report(mx, 4)
     if args.batch > 0:
         out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
                           "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}

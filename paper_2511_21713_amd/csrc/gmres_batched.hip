@@ -31,6 +31,7 @@
 
 #include "gemv_rows.hpp"
 #include "pbfb_internal.hpp"
+#include "sell_slice.hpp"
 
 namespace pbfb {
 
@@ -42,7 +43,7 @@ struct GDesc {
     int f32;  // operator values in FP32
     int vf32; // Krylov basis stored in FP32
     const int32_t *gm, *gs;
-    const int32_t *rowptr, *col;
+    const int32_t *sptr, *col; // FEM rows, sliced ELL
     const void *val;
     int64_t nn, n;
     const double *dinv;
@@ -76,7 +77,6 @@ struct WItem {
 
 constexpr int CH = 256;      // rows per chunk: one per thread of a workgroup
 constexpr int GROWS = 4 * GEMV_RW; // GEMV rows per workgroup (4 wavefronts)
-constexpr int SROWS = 32;    // SpMV rows per workgroup (8 lanes per row)
 
 
 __device__ inline bool applies(int st) { return st == G_ARN || st == G_RES; }
@@ -92,7 +92,7 @@ template <typename VT> __device__ inline const VT *vcol(const GDesc &d, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// apply: pack, dense GEMV, CSR SpMV on the current input of each instance
+// apply: pack, dense GEMV, sliced-ELL SpMV on the current input of each instance
 // (ARN: D^{-1} V_j, RES: x)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
@@ -184,7 +184,8 @@ __global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, co
     if (last && s.st == G_RES) d.x[k] += zv;
 }
 
-// Chebyshev term `step` >= 1 of the FEM block: 8 lanes per row
+// Chebyshev term `step` >= 1 of the FEM block: one workgroup per 64-row
+// slice (work item: inst, b = first row of the slice)
 __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S, int step)
 {
@@ -193,31 +194,16 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
     if (s.st != G_ARN && s.st != G_RES) return;
     const GDesc &d = D[it.inst];
     if (d.pc != PBFB_PC_CHEB_SPAI || step >= d.cheb_k) return;
-    const int64_t row = it.b + (threadIdx.x >> 3);
-    const int sub = threadIdx.x & 7;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t q = it.b / SLICE, row = it.b + lane;
     const double *zp = ((d.cheb_k - step) % 2 == 0) ? d.z : d.zb; // term step - 1
     double *zn = ((d.cheb_k - 1 - step) % 2 == 0) ? d.z : d.zb;
-    double acc = 0.0;
-    if (row < d.nn) {
-        const int32_t e = d.rowptr[row + 1];
-        if (d.f32) {
-            const float *val = static_cast<const float *>(d.val);
-            for (int32_t q = d.rowptr[row] + sub; q < e; q += 8) {
-                const int32_t c = d.col[q];
-                if (c < d.nn) acc = fma(double(val[q]), zp[c], acc);
-            }
-        } else {
-            const double *val = static_cast<const double *>(d.val);
-            for (int32_t q = d.rowptr[row] + sub; q < e; q += 8) {
-                const int32_t c = d.col[q];
-                if (c < d.nn) acc = fma(val[q], zp[c], acc);
-            }
-        }
-    }
-    acc += __shfl_xor(acc, 4);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 1);
-    if (sub != 0 || row >= d.nn) return;
+    const double part = d.f32 ? sell_part<float, true>(d.sptr, d.col, static_cast<const float *>(d.val), zp, q,
+                                                       lane, wv, d.nn)
+                              : sell_part<double, true>(d.sptr, d.col, static_cast<const double *>(d.val), zp, q,
+                                                        lane, wv, d.nn);
+    const double acc = sell_reduce(part, lane, wv);
+    if (wv != 0 || row >= d.nn) return;
     const double dv = d.coef[2 * step] * d.dk[row] + d.coef[2 * step + 1] * d.dinv[row] * (pc_src(d, s, row) - acc);
     d.dk[row] = dv;
     const double zv = zp[row] + dv;
@@ -251,24 +237,15 @@ __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, con
     const GState s = S[it.inst];
     if (!applies(s.st)) return;
     const GDesc &d = D[it.inst];
-    const int64_t row = it.b + (threadIdx.x >> 3);
-    const int sub = threadIdx.x & 7;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t q = it.b / SLICE, row = it.b + lane;
     const double *in = s.st == G_ARN ? d.z : d.x;
-    double acc = 0.0;
-    if (row < d.nn) {
-        const int32_t e = d.rowptr[row + 1];
-        if (d.f32) {
-            const float *val = static_cast<const float *>(d.val);
-            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(double(val[k]), in[d.col[k]], acc);
-        } else {
-            const double *val = static_cast<const double *>(d.val);
-            for (int32_t k = d.rowptr[row] + sub; k < e; k += 8) acc = fma(val[k], in[d.col[k]], acc);
-        }
-    }
-    acc += __shfl_xor(acc, 4);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 1);
-    if (sub == 0 && row < d.nn) d.w[row] = acc;
+    const double part = d.f32 ? sell_part<float, false>(d.sptr, d.col, static_cast<const float *>(d.val), in, q,
+                                                        lane, wv, d.nn)
+                              : sell_part<double, false>(d.sptr, d.col, static_cast<const double *>(d.val), in, q,
+                                                         lane, wv, d.nn);
+    const double acc = sell_reduce(part, lane, wv);
+    if (wv == 0 && row < d.nn) d.w[row] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -615,7 +592,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.f32 = p.precision == PBFB_MIXED;
         d.gm = p.surf[0].g;
         d.gs = p.surf[1].g;
-        d.rowptr = p.d_rowptr;
+        d.sptr = p.d_sptr;
         d.col = p.d_col;
         d.val = d.f32 ? static_cast<const void *>(p.d_val32) : static_cast<const void *>(p.d_val);
         d.nn = p.nn;
@@ -670,7 +647,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             const int64_t nv = a == 0 ? d.nm : d.ns;
             for (int64_t r = 0; r < nv; r += GROWS) wl_gemv.push_back(WItem{q, a, r});
         }
-        for (int64_t r = 0; r < p.nn; r += SROWS) wl_spmv.push_back(WItem{q, 0, r});
+        for (int64_t r = 0; r < p.nn; r += SLICE) wl_spmv.push_back(WItem{q, 0, r});
         for (int64_t k = 0; k < std::max(d.ldm, d.lds); k += CH) wl_pack.push_back(WItem{q, 0, k});
         maxiter_host = std::max(maxiter_host, J.maxit + J.maxit / std::max(m, 1) + 4);
     }

@@ -255,22 +255,25 @@ __global__ void __launch_bounds__(128)
 }
 
 // d_val = d_val0 + J_scheme(u) on the u columns of each FEM row, from the
-// element blocks (16 per tet), row by row
-__global__ void k_jacobian(int64_t nn, const int32_t *__restrict__ rowptr, const double *__restrict__ val0,
+// element blocks (16 per tet), row by row; the copy covers the slice
+// padding (zero in d_val0) and is coalesced across the rows of a slice
+__global__ void k_jacobian(int64_t nn, const int32_t *__restrict__ sptr, const double *__restrict__ val0,
                            double *__restrict__ val, float *__restrict__ val32, const int32_t *__restrict__ n2t_ptr,
                            const int32_t *__restrict__ n2t, const int32_t *__restrict__ slot4,
                            const double *__restrict__ Jt)
 {
     int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (a >= nn) return;
-    for (int32_t s = rowptr[a]; s < rowptr[a + 1]; ++s) val[s] = val0[s];
+    const int64_t q = a / SLICE;
+    const int32_t b0 = sptr[q] + int32_t(a - q * SLICE), b1 = sptr[q + 1];
+    for (int32_t s = b0; s < b1; s += SLICE) val[s] = val0[s];
     for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
         const int64_t t = n2t[e] >> 2;
         const int la = n2t[e] & 3;
         for (int b = 0; b < 4; ++b) val[slot4[4 * int64_t(e) + b]] += Jt[16 * t + 4 * la + b];
     }
     if (val32)
-        for (int32_t s = rowptr[a]; s < rowptr[a + 1]; ++s) val32[s] = float(val[s]);
+        for (int32_t s = b0; s < b1; s += SLICE) val32[s] = float(val[s]);
 }
 
 // out_k[a] = sum over the tets at node a of their contribution k to a (K per tet and node)
@@ -509,10 +512,10 @@ void ensure_topology(Problem &p, hipStream_t s)
     A.release();
     p.d_x = A.upload(p.x, s);
     p.d_tet = A.upload(p.tet, s);
-    std::vector<int32_t> rowptr, col, n2t_ptr, n2t, slot4, diag, cslot[2];
-    build_fem_topology(p, rowptr, col, n2t_ptr, n2t, slot4, diag, cslot);
+    std::vector<int32_t> sptr, col, n2t_ptr, n2t, slot4, diag, cslot[2];
+    build_fem_topology(p, sptr, col, n2t_ptr, n2t, slot4, diag, cslot);
     p.nnz = int64_t(col.size());
-    p.d_rowptr = A.upload(rowptr, s);
+    p.d_sptr = A.upload(sptr, s);
     p.d_col = A.upload(col, s);
     p.d_n2t_ptr = A.upload(n2t_ptr, s);
     p.d_n2t = A.upload(n2t, s);
@@ -614,7 +617,7 @@ void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t 
     double *Jt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_J>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
                        u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), Jt);
-    hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_rowptr, p.d_val0, p.d_val,
+    hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_sptr, p.d_val0, p.d_val,
                        p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, Jt);
     PB_HIP(hipGetLastError());
 }

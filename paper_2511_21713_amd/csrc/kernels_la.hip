@@ -1,11 +1,12 @@
 // Linear algebra of the coupled operator outside GMRES (residuals, the
 // omega search, the C-ABI apply): surface packing, the dense Galerkin GEMV,
-// the FEM CSR SpMV and small vector kernels.  Reductions use a fixed grid
+// the FEM sliced-ELL SpMV and small vector kernels.  Reductions use a fixed grid
 // and a fixed tree, so every result is bitwise reproducible run to run.
 #include <cmath>
 
 #include "gemv_rows.hpp"
 #include "pbfb_internal.hpp"
+#include "sell_slice.hpp"
 
 namespace pbfb {
 
@@ -51,24 +52,19 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// FEM CSR SpMV over the shell rows, 8 lanes per row
+// FEM SpMV over the shell rows (sliced ELL): one workgroup per 64-row slice
 // ---------------------------------------------------------------------------
 template <typename VT>
 __global__ void __launch_bounds__(256)
-    k_spmv(int64_t nrows, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    k_spmv(int64_t nrows, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
            const VT *__restrict__ val, const double *__restrict__ x, double *__restrict__ y)
 {
-    const int64_t row = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) >> 3;
-    const int sub = threadIdx.x & 7;
-    double s = 0.0;
-    if (row < nrows) {
-        const int32_t e = rowptr[row + 1];
-        for (int32_t j = rowptr[row] + sub; j < e; j += 8) s = fma(double(val[j]), x[col[j]], s);
-    }
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
-    if (sub == 0 && row < nrows) y[row] = s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t q = blockIdx.x;
+    const double part = sell_part<VT, false>(sptr, col, val, x, q, lane, wv, nrows);
+    const double s = sell_reduce(part, lane, wv);
+    const int64_t row = q * SLICE + lane;
+    if (wv == 0 && row < nrows) y[row] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -164,13 +160,13 @@ static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hi
                        S.g, x, xm, xs);
     gemv_launch(p, xm, xs, y, s);
     if (p.timing) p.timer.begin(T_SPMV, s);
-    const unsigned g = nb_(p.nn * 8, 256);
+    const unsigned g = nb_(p.nn, SLICE);
     if (!with_jac)
-        hipLaunchKernelGGL(k_spmv<double>, dim3(g), dim3(256), 0, s, p.nn, p.d_rowptr, p.d_col, p.d_val0, x, y);
+        hipLaunchKernelGGL(k_spmv<double>, dim3(g), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val0, x, y);
     else if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_spmv<float>, dim3(g), dim3(256), 0, s, p.nn, p.d_rowptr, p.d_col, p.d_val32, x, y);
+        hipLaunchKernelGGL(k_spmv<float>, dim3(g), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val32, x, y);
     else
-        hipLaunchKernelGGL(k_spmv<double>, dim3(g), dim3(256), 0, s, p.nn, p.d_rowptr, p.d_col, p.d_val, x, y);
+        hipLaunchKernelGGL(k_spmv<double>, dim3(g), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val, x, y);
     if (p.timing) {
         p.timer.end(s); // spmv
         p.timer.end(s); // apply

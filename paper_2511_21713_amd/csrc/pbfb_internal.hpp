@@ -111,7 +111,7 @@ struct SurfaceDev {
     int64_t nbA = 0, nbB = 0, SA = 0, SB = 0;
     int32_t *tp_ptr = nullptr, *tp_sig = nullptr, *tp_tau = nullptr, *morton = nullptr;
     int64_t ntp = 0;
-    int32_t *cslot = nullptr; // CSR slot of the coupling entry per (v2t entry, b)
+    int32_t *cslot = nullptr; // FEM-row slot of the coupling entry per (v2t entry, b)
     // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
     void *B = nullptr;
     double *vdiag = nullptr; // diagonal of the signed single-layer block V'
@@ -186,10 +186,15 @@ struct Problem {
     ScratchBuf scr[SCR_N];
     double *d_x = nullptr, *d_tgeo = nullptr, *d_q = nullptr;
     int32_t *d_tet = nullptr, *d_n2t_ptr = nullptr, *d_n2t = nullptr, *d_slot4 = nullptr;
-    int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr;
+    // FEM rows in sliced ELL: slice q holds rows [64q, 64q + 64); its entry k
+    // of row 64q + l sits at d_sptr[q] + 64 k + l for k below the slice width
+    // (d_sptr[q + 1] - d_sptr[q]) / 64, in ascending column order; entries past
+    // a row's length hold column = the row itself and value 0.
+    int32_t *d_sptr = nullptr, *d_col = nullptr, *d_diag = nullptr;
     double *d_val0 = nullptr, *d_val = nullptr;
     float *d_val32 = nullptr;
-    int64_t nnz = 0;
+    int64_t nnz = 0;     // stored entries (with the slice padding)
+    int64_t nnz_row = 0; // nonzeros of the rows (without it)
     double *d_b = nullptr; // right-hand side, length n
     int *d_bad = nullptr;
     SurfaceDev surf[2];
@@ -211,7 +216,8 @@ void release_all_scratch(Problem &p);
 
 // host preprocessing (setup.hip)
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri);
-void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
+constexpr int SLICE = 64; // FEM rows per sliced-ELL slice: one wavefront
+void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int32_t> &col,
                         std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,
                         std::vector<int32_t> &diag, std::vector<int32_t> cslot[2]);
 

@@ -1,5 +1,5 @@
 // Host-side topology preprocessing: surfaces, adjacency, Morton blocks for the
-// regular boundary-element assembly, touching panel pairs and the FEM CSR
+// regular boundary-element assembly, touching panel pairs and the FEM sliced-ELL
 // pattern.  Integer work only; every floating-point quantity of the method is
 // computed on the device.
 #include <algorithm>
@@ -192,7 +192,7 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
     }
 }
 
-void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
+void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int32_t> &col,
                         std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,
                         std::vector<int32_t> &diag, std::vector<int32_t> cslot[2])
 {
@@ -213,8 +213,9 @@ void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<in
         for (int64_t i = 0; i < p.topo[w].nv; ++i) loc[w][p.topo[w].g[i]] = int32_t(i);
     }
     const int64_t off[2] = {nn, nn + p.topo[0].nv};
-    rowptr.assign(nn + 1, 0);
-    col.clear();
+    // row patterns: the nodes of the tets at the row node, then the
+    // coupling columns of the triangles at it (surface nodes), ascending
+    std::vector<int32_t> rowptr(nn + 1, 0), rc;
     std::vector<int32_t> cols;
     for (int64_t a = 0; a < nn; ++a) {
         cols.clear();
@@ -233,13 +234,43 @@ void build_fem_topology(Problem &p, std::vector<int32_t> &rowptr, std::vector<in
         }
         std::sort(cols.begin(), cols.end());
         cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-        col.insert(col.end(), cols.begin(), cols.end());
-        rowptr[a + 1] = int32_t(col.size());
+        rc.insert(rc.end(), cols.begin(), cols.end());
+        rowptr[a + 1] = int32_t(rc.size());
+    }
+    p.nnz_row = int64_t(rc.size());
+    // sliced ELL: slice width = longest row of the slice; entry k of row
+    // 64 q + l at sptr[q] + 64 k + l; padding: column = row, value 0
+    const int64_t nsl = (nn + SLICE - 1) / SLICE;
+    sptr.assign(nsl + 1, 0);
+    for (int64_t q = 0; q < nsl; ++q) {
+        int32_t w = 0;
+        for (int64_t a = q * SLICE; a < std::min(nn, (q + 1) * SLICE); ++a) w = std::max(w, rowptr[a + 1] - rowptr[a]);
+        PB_CHECK(int64_t(sptr[q]) + int64_t(SLICE) * w < (int64_t(1) << 31), PBFB_EINVAL,
+                 "FEM block too large for 32-bit slice offsets");
+        sptr[q + 1] = sptr[q] + SLICE * w;
+    }
+    col.assign(sptr[nsl], 0);
+    std::vector<int32_t> pos(rc.size()); // row-pattern index -> stored slot
+    for (int64_t q = 0; q < nsl; ++q) {
+        const int32_t w = (sptr[q + 1] - sptr[q]) / SLICE;
+        for (int l = 0; l < SLICE; ++l) {
+            const int64_t a = q * SLICE + l;
+            const int32_t len = a < nn ? rowptr[a + 1] - rowptr[a] : 0;
+            for (int32_t k = 0; k < w; ++k) {
+                const int64_t at = sptr[q] + int64_t(SLICE) * k + l;
+                if (k < len) {
+                    col[at] = rc[rowptr[a] + k];
+                    pos[rowptr[a] + k] = int32_t(at);
+                } else {
+                    col[at] = a < nn ? int32_t(a) : 0;
+                }
+            }
+        }
     }
     auto find = [&](int64_t row, int64_t c) {
-        auto b = col.begin() + rowptr[row], e = col.begin() + rowptr[row + 1];
+        auto b = rc.begin() + rowptr[row], e = rc.begin() + rowptr[row + 1];
         auto it = std::lower_bound(b, e, int32_t(c));
-        return int32_t(it - col.begin());
+        return pos[it - rc.begin()];
     };
     slot4.resize(4 * n2t.size());
     for (int64_t a = 0; a < nn; ++a)

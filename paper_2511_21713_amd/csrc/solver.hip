@@ -51,7 +51,7 @@ void build_precond(Problem &p, double *dinv, hipStream_t s)
 // end of the Chebyshev interval): per-block maxima, then one block.  A
 // maximum does not depend on the order, so the bound is exact and
 // reproducible.
-__global__ void __launch_bounds__(256) k_gershgorin(int64_t nn, const int32_t *__restrict__ rowptr,
+__global__ void __launch_bounds__(256) k_gershgorin(int64_t nn, const int32_t *__restrict__ sptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
                                                     const int32_t *__restrict__ diag, double *__restrict__ part)
 {
@@ -59,8 +59,9 @@ __global__ void __launch_bounds__(256) k_gershgorin(int64_t nn, const int32_t *_
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     double v = 0.0;
     if (i < nn) {
-        double sum = 0.0;
-        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+        const int64_t q = i / SLICE;
+        double sum = 0.0; // slice padding adds zeros
+        for (int32_t e = sptr[q] + int32_t(i - q * SLICE); e < sptr[q + 1]; e += SLICE)
             if (col[e] < nn) sum += fabs(val[e]);
         v = sum / val[diag[i]];
     }
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(256) k_max_final(int64_t nb, const double *__r
 void fem_gershgorin(Problem &p, double *lmax_dev, hipStream_t s)
 {
     const unsigned nb = nbk(p.nn, 256);
-    hipLaunchKernelGGL(k_gershgorin, dim3(nb), dim3(256), 0, s, p.nn, p.d_rowptr, p.d_col, p.d_val, p.d_diag,
+    hipLaunchKernelGGL(k_gershgorin, dim3(nb), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val, p.d_diag,
                        lmax_dev + 1);
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, int64_t(nb), lmax_dev + 1, lmax_dev);
     PB_HIP(hipGetLastError());
@@ -100,7 +101,7 @@ void fem_gershgorin(Problem &p, double *lmax_dev, hipStream_t s)
 
 enum RunPhase { PH_START = 0, PH_LINEAR = 1, PH_NEWTON = 2, PH_DONE = 3 };
 
-// the linear-solve request of the current Newton matrix (its CSR values,
+// the linear-solve request of the current Newton matrix (its FEM values,
 // diagonal and Chebyshev bound are computed here)
 static GmresJob make_job(NewtonRun &r, const double *b, double *x, hipStream_t s)
 {
