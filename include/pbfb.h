@@ -67,11 +67,14 @@ void pbfb_ctx_destroy(pbfb_ctx *ctx);
 const char *pbfb_last_error(void);
 
 /* ---- problem ------------------------------------------------------------ */
-/* precision PBFB_FP64: every operator stored and applied in FP64.
- * PBFB_MIXED: dense boundary operators and FEM matrix values stored in FP32
- * (integrated in FP64, rounded once), every product accumulated in FP64;
- * Krylov vectors, Newton update, relaxation search, orthogonalisation and
- * touching-panel integrals stay FP64. */
+/* precision PBFB_FP64: every operator evaluated, stored and applied in FP64.
+ * PBFB_MIXED: the regular (non-touching) boundary-element quadrature is
+ * evaluated in FP32 (point offsets from FP64 triangle centroids, FP32 kernel
+ * values and sums over the 6 source points) and accumulated in FP64; dense
+ * boundary operators and FEM matrix values are stored in FP32 (rounded once
+ * from their FP64 sums) and every product is accumulated in FP64.  Krylov
+ * vectors (unless krylov_fp32), Newton update, relaxation search,
+ * orthogonalisation and touching-panel integrals stay FP64. */
 pbfb_status pbfb_problem_create(pbfb_ctx *ctx, int precision, pbfb_problem **out);
 void pbfb_problem_destroy(pbfb_problem *p);
 
@@ -95,7 +98,7 @@ pbfb_status pbfb_set_params(pbfb_problem *p, double eps_in, double eps_out, doub
 /* sizes: FEM nodes, Gamma_m vertices, Gamma_s vertices, unknowns, device bytes held */
 pbfb_status pbfb_get_sizes(const pbfb_problem *p, int64_t *n_nodes, int64_t *n_m, int64_t *n_s,
                            int64_t *n_unknowns, int64_t *hbm_bytes);
-/* Device setup: geometry, CSR pattern, stiffness, surface masses, Coulomb
+/* Device setup: geometry, sparse pattern, stiffness, surface masses, Coulomb
  * load, dense boundary operators with touching-panel corrections.  Done
  * lazily by the first call that needs it. */
 pbfb_status pbfb_setup(pbfb_problem *p, void *hip_stream);

@@ -211,13 +211,18 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
     if (step == d.cheb_k - 1 && s.st == G_RES) d.x[row] += zv;
 }
 
-// work item: inst, a = interface (0/1), b = first row of the workgroup
+// work item: inst, a = interface (0/1), b = first row of the workgroup.  One
+// instantiation per storage type, each skipping the instances of the other:
+// a kernel holding both row routines would be register-allocated for their
+// union and run at half the occupancy of either.
+template <typename MT>
 __global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S)
 {
     const WItem it = wl[blockIdx.x];
     if (!applies(S[it.inst].st)) return;
     const GDesc &d = D[it.inst];
+    if (d.f32 != (sizeof(MT) == 4)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t r0 = it.b + wv * GEMV_RW;
     const int64_t n = it.a == 0 ? d.nm : d.ns;
@@ -225,9 +230,7 @@ __global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, con
     const int64_t ld = it.a == 0 ? d.ldm : d.lds;
     const double *x = it.a == 0 ? d.xm : d.xs;
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
-    const void *B = it.a == 0 ? d.Bm : d.Bs;
-    if (d.f32) gemv_rows<float>(static_cast<const float *>(B), x, y, n, ld, r0, lane);
-    else gemv_rows<double>(static_cast<const double *>(B), x, y, n, ld, r0, lane);
+    gemv_rows<MT>(static_cast<const MT *>(it.a == 0 ? d.Bm : d.Bs), x, y, n, ld, r0, lane);
 }
 
 __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
@@ -535,11 +538,11 @@ __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, con
 struct GraphKey {
     void *dev = nullptr;
     unsigned nvec = 0, ngemv = 0, nspmv = 0, npack = 0, ndot = 0, ngroups = 0, nb = 0;
-    int kmax = 0;
+    int kmax = 0, types = 0; // types: bit 0 FP64 operators present, bit 1 FP32
     bool operator==(const GraphKey &o) const
     {
         return dev == o.dev && nvec == o.nvec && ngemv == o.ngemv && nspmv == o.nspmv && npack == o.npack &&
-               ndot == o.ndot && ngroups == o.ngroups && nb == o.nb && kmax == o.kmax;
+               ndot == o.ndot && ngroups == o.ngroups && nb == o.nb && kmax == o.kmax && types == o.types;
     }
 };
 
@@ -701,6 +704,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     int polls = 0;
     bool finished = false;
     hipLaunchKernelGGL(k_cheb_coef, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, dD, nb);
+    int types = 0;
+    for (auto *J : jobs) types |= J->p->precision == PBFB_MIXED ? 2 : 1;
     // one Krylov step of the whole batch
     auto enqueue_step = [&]() {
         if (tm) tm->begin(T_PREC, s);
@@ -711,7 +716,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         if (tm) tm->begin(T_APPLY, s);
         hipLaunchKernelGGL(k_bpack, dim3(npack), dim3(256), 0, s, dpack, dD, dS);
         if (tm) tm->begin(T_GEMV, s);
-        hipLaunchKernelGGL(k_bgemv, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
+        if (types & 1) hipLaunchKernelGGL(k_bgemv<double>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
+        if (types & 2) hipLaunchKernelGGL(k_bgemv<float>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
         if (tm) {
             tm->end(s);
             tm->begin(T_SPMV, s);
@@ -738,7 +744,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     bool graph = !tm;
     for (auto *J : jobs) graph = graph && J->graph;
     if (graph) {
-        const GraphKey key{BB.dev, nvec, ngemv, nspmv, npack, ndot, ngroups, unsigned(nb), kmax};
+        const GraphKey key{BB.dev, nvec, ngemv, nspmv, npack, ndot, ngroups, unsigned(nb), kmax, types};
         if (!(BB.step && BB.key == key)) {
             if (BB.step) PB_HIP(hipGraphExecDestroy(BB.step));
             BB.step = nullptr;
