@@ -143,7 +143,9 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
     torch.cuda.synchronize()
     phi = phi.cpu().numpy()
     u_m = (phi[:g.n] + phi[g.n:])[np.unique(prob.tri_m)]
-    out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm(), u_m=u_m)
+    tiles = {"laplace_gamma_m": list(g.tile_shape(0)), "yukawa_gamma_s": list(g.tile_shape(1))}
+    out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm(), u_m=u_m,
+               tiles=tiles)
     g.close()
     ctx.close()
     return out
@@ -373,7 +375,8 @@ def main():
     def asm_report(leg, peak):
         ms, cnt = leg["timing"]["assembly"]
         t = ms * cnt / K * 1e-3
-        return {"kernel": "k_bem_regular (6 x 6 rule, non-touching pairs)", "flops_per_solve": asm_flops,
+        return {"kernel": "k_bem_regular (6 x 6 rule, non-touching pairs)", "tile_shapes_autotuned": leg["tiles"],
+                "flops_per_solve": asm_flops,
                 "ms_per_solve": t * 1e3, "tflops": asm_flops / t / 1e12 if t else None, "peak_tflops": peak,
                 "frac": asm_flops / t / 1e12 / peak if t else None}
 

@@ -203,6 +203,21 @@ pbfb_status pbfb_server_destroy(pbfb_server *s);
 pbfb_status pbfb_energy(pbfb_problem *p, const double *phi_lin, const double *phi_nl, double out[4], int mem,
                         void *hip_stream);
 
+/* ---- regular-assembly tile shape ---------------------------------------- */
+/* The non-touching triangle pairs of each interface are integrated in tiles
+ * of ta target x tb source triangles (Morton-ordered), one pair per GPU
+ * thread.  By default (ta = tb = 0) the shape is chosen by the library's
+ * autotuner: the first assembly of a (precision, kernel, size class) in a
+ * context times every candidate shape on a sample of that surface and keeps
+ * the fastest for the context's lifetime.  Candidates: 16x32, 8x32, 32x32,
+ * 8x64, 16x64.  pbfb_set_tile_shape pins one candidate for this problem
+ * (PBFB_EINVAL for any other pair) and marks its operators stale.  The shape
+ * changes only the order of floating-point sums, never the integrals. */
+pbfb_status pbfb_set_tile_shape(pbfb_problem *p, int ta, int tb);
+/* Shape used by the last assembly of surface `surf` (0 = Gamma_m, 1 =
+ * Gamma_s); 0, 0 before the first assembly. */
+pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *tb);
+
 /* ---- inspection --------------------------------------------------------- */
 /* Copy the two dense blocks stored for surface `surf` (0 = Gamma_m, Laplace;
  * 1 = Gamma_s, Yukawa) as row-major n x n host arrays (either may be NULL):

@@ -25,7 +25,7 @@ EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_probl
            "pbfb_reset_operators", "pbfb_residual",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
            "pbfb_server_submit", "pbfb_server_poll", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
-           "pbfb_export_rhs", "pbfb_timing_enable", "pbfb_timing"]
+           "pbfb_export_rhs", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
 
 
 class PbfbError(RuntimeError):
@@ -108,6 +108,8 @@ def lib():
         L.pbfb_server_destroy.argtypes = [P]
         L.pbfb_export_bem.argtypes = [P, C.c_int, P, P]
         L.pbfb_export_rhs.argtypes = [P, P]
+        L.pbfb_set_tile_shape.argtypes = [P, C.c_int, C.c_int]
+        L.pbfb_get_tile_shape.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pbfb_timing_enable.argtypes = [P, C.c_int]
         L.pbfb_timing.argtypes = [P, C.c_int, C.POINTER(C.c_double), I64P, C.c_int]
         _lib = L
@@ -335,6 +337,16 @@ class Problem:
         b = np.zeros(self.n)
         _check(lib().pbfb_export_rhs(self.h, b.ctypes.data))
         return b
+
+    def set_tile_shape(self, ta=0, tb=0):
+        """Pin the regular-assembly tile shape (ta x tb triangles); 0, 0 = tuned."""
+        _check(lib().pbfb_set_tile_shape(self.h, ta, tb))
+
+    def tile_shape(self, surf):
+        """Tile shape (ta, tb) of the last assembly of surface `surf`."""
+        ta, tb = C.c_int(), C.c_int()
+        _check(lib().pbfb_get_tile_shape(self.h, surf, C.byref(ta), C.byref(tb)))
+        return ta.value, tb.value
 
     def timing_enable(self, on=True):
         _check(lib().pbfb_timing_enable(self.h, 1 if on else 0))

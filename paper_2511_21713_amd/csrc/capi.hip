@@ -638,6 +638,33 @@ pbfb_status pbfb_reset_operators(pbfb_problem *pp)
     API_END
 }
 
+pbfb_status pbfb_set_tile_shape(pbfb_problem *pp, int ta, int tb)
+{
+    API_BEGIN
+    PB_CHECK(pp, PBFB_EINVAL, "null problem");
+    int k = -1;
+    if (!(ta == 0 && tb == 0)) {
+        k = tile_shape_index(ta, tb);
+        PB_CHECK(k >= 0, PBFB_EINVAL, "tile shape is not one of 16x32, 8x32, 32x32, 8x64, 16x64 (or 0x0 for tuned)");
+    }
+    Problem &p = pp->p;
+    if (k != p.tile_fixed) {
+        p.tile_fixed = k;
+        p.bem_ready[0] = p.bem_ready[1] = false;
+    }
+    API_END
+}
+
+pbfb_status pbfb_get_tile_shape(const pbfb_problem *pp, int surf, int *ta, int *tb)
+{
+    API_BEGIN
+    PB_CHECK(pp && (surf == 0 || surf == 1), PBFB_EINVAL, "bad argument");
+    const int k = pp->p.surf[surf].tile;
+    if (ta) *ta = k >= 0 ? TILE_SHAPES[k].ta : 0;
+    if (tb) *tb = k >= 0 ? TILE_SHAPES[k].tb : 0;
+    API_END
+}
+
 pbfb_status pbfb_timing_enable(pbfb_problem *pp, int on)
 {
     API_BEGIN

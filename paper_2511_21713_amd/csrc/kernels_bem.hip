@@ -126,12 +126,11 @@ __device__ inline double rsqrt_pos(double x)
 }
 __device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 
-constexpr int REG_THREADS = BA * BB; // one target x source triangle pair per thread
-
 // RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
-template <bool YUK, typename RT>
-__global__ void __launch_bounds__(REG_THREADS, 4)
+// TA x TB: target x source triangles of the tile, one pair per thread
+template <bool YUK, typename RT, int TA, int TB>
+__global__ void __launch_bounds__(TA * TB, 4)
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
@@ -141,15 +140,15 @@ __global__ void __launch_bounds__(REG_THREADS, 4)
                   QRule6 R, QRule6F RF)
 {
     constexpr bool F32 = sizeof(RT) == 4;
-    constexpr int NT = REG_THREADS;
-    __shared__ RT sX[BA][18];
-    __shared__ RT sY[BB][18];
-    __shared__ RT sN[BB][3];
-    __shared__ double sCa[F32 ? BA : 1][3], sCb[F32 ? BB : 1][3];
-    __shared__ double sAa[BA], sAb[BB];
-    __shared__ int sVa[BA][3], sVb[BB][3];
-    __shared__ int sSa[BA * 3][MAXS], sSb[BB * 3][MAXS];
-    __shared__ double acc[BA * 3 + 1][BB * 3 + 1]; // + a zero row and a zero column
+    constexpr int NT = TA * TB;
+    __shared__ RT sX[TA][18];
+    __shared__ RT sY[TB][18];
+    __shared__ RT sN[TB][3];
+    __shared__ double sCa[F32 ? TA : 1][3], sCb[F32 ? TB : 1][3];
+    __shared__ double sAa[TA], sAb[TB];
+    __shared__ int sVa[TA][3], sVb[TB][3];
+    __shared__ int sSa[TA * 3][MAXS], sSb[TB * 3][MAXS];
+    __shared__ double acc[TA * 3 + 1][TB * 3 + 1]; // + a zero row and a zero column
 
     const int tid = threadIdx.x;
     const int64_t bB = blockIdx.x;
@@ -157,43 +156,43 @@ __global__ void __launch_bounds__(REG_THREADS, 4)
     const int nA = A_nv[bA], nB = B_nv[bB];
     const int64_t pA = A_pref[bA], pB = B_pref[bB];
 
-    for (int k = tid; k < BA * 18; k += NT) {
+    for (int k = tid; k < TA * 18; k += NT) {
         int tl = k / 18, c = k % 18;
-        int64_t m = bA * BA + tl;
+        int64_t m = bA * TA + tl;
         sX[tl][c] = m < nt ? xq[18 * m + c] : RT(0);
     }
-    for (int k = tid; k < BB * 18; k += NT) {
+    for (int k = tid; k < TB * 18; k += NT) {
         int sl = k / 18, c = k % 18;
-        int64_t m = bB * BB + sl;
+        int64_t m = bB * TB + sl;
         sY[sl][c] = m < nt ? xq[18 * m + c] : RT(0);
     }
-    if (tid < BB * 3) {
+    if (tid < TB * 3) {
         int sl = tid / 3, c = tid % 3;
-        int64_t m = bB * BB + sl;
+        int64_t m = bB * TB + sl;
         sN[sl][c] = m < nt ? nq[3 * m + c] : RT(0);
         sVb[sl][c] = m < nt ? m_tri[3 * m + c] : -1;
         if constexpr (F32) sCb[sl][c] = m < nt ? cen[3 * m + c] : 0.0;
     }
-    if (tid < BA * 3) {
+    if (tid < TA * 3) {
         int tl = tid / 3, c = tid % 3;
-        int64_t m = bA * BA + tl;
+        int64_t m = bA * TA + tl;
         sVa[tl][c] = m < nt ? m_tri[3 * m + c] : -2;
         if constexpr (F32) sCa[tl][c] = m < nt ? cen[3 * m + c] : 0.0;
     }
-    if (tid < BA) sAa[tid] = (bA * BA + tid) < nt ? m_area[bA * BA + tid] : 0.0;
-    if (tid < BB) sAb[tid] = (bB * BB + tid) < nt ? m_area[bB * BB + tid] : 0.0;
-    for (int k = tid; k < BA * 3 * MAXS; k += NT) {
+    if (tid < TA) sAa[tid] = (bA * TA + tid) < nt ? m_area[bA * TA + tid] : 0.0;
+    if (tid < TB) sAb[tid] = (bB * TB + tid) < nt ? m_area[bB * TB + tid] : 0.0;
+    for (int k = tid; k < TA * 3 * MAXS; k += NT) {
         int r = k / MAXS, c = k % MAXS;
         sSa[r][c] = r < nA ? A_slots[(pA + r) * MAXS + c] : -1;
     }
-    for (int k = tid; k < BB * 3 * MAXS; k += NT) {
+    for (int k = tid; k < TB * 3 * MAXS; k += NT) {
         int r = k / MAXS, c = k % MAXS;
         sSb[r][c] = r < nB ? B_slots[(pB + r) * MAXS + c] : -1;
     }
     __syncthreads();
 
     // this thread's pair (target tl, source sl)
-    const int tl = tid / BB, sl = tid % BB;
+    const int tl = tid / TB, sl = tid % TB;
     double Vl[9], Kl[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Vl[k] = Kl[k] = 0.0;
@@ -276,10 +275,10 @@ __global__ void __launch_bounds__(REG_THREADS, 4)
 #pragma unroll
     for (int l = 0; l < MAXS; ++l) {
         const int c = sSb[jb][l];
-        cb[l] = c < 0 ? BB * 3 : c;
+        cb[l] = c < 0 ? TB * 3 : c;
     }
-    for (int k = tid; k < BB * 3 + 1; k += NT) acc[BA * 3][k] = 0.0;
-    if (tid < BA * 3) acc[tid][BB * 3] = 0.0;
+    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = 0.0;
+    if (tid < TA * 3) acc[tid][TB * 3] = 0.0;
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
 #pragma unroll
@@ -287,8 +286,8 @@ __global__ void __launch_bounds__(REG_THREADS, 4)
 #pragma unroll
             for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[3 * a + b] : Kl[3 * a + b];
         __syncthreads();
-        constexpr int RMAX = BA * 3;
-        constexpr int RPT = (RMAX + NT / (BB * 3) - 1) / (NT / (BB * 3)); // rows per thread, nB <= BB * 3
+        constexpr int RMAX = TA * 3;
+        constexpr int RPT = (RMAX + NT / (TB * 3) - 1) / (NT / (TB * 3)); // rows per thread, nB <= TB * 3
         double colsum[RPT];
         int nrow = 0;
         if (colthread) {
@@ -320,7 +319,7 @@ __global__ void __launch_bounds__(REG_THREADS, 4)
 #pragma unroll
                 for (int k = 0; k < MAXS; ++k) {
                     const int ra = sSa[ia][k];
-                    v[k] = acc[ra < 0 ? BA * 3 : ra][jb];
+                    v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
                 }
                 double t = 0.0;
 #pragma unroll
@@ -770,6 +769,133 @@ __global__ void __launch_bounds__(256)
 // ===========================================================================
 int64_t bem_ld(int64_t nv) { return ((2 * nv + 255) / 256) * 256; }
 
+// device copy of the block tables of block size bs (in the surface's arena)
+static const BlockSideDev &device_side(Problem &p, int w, int bs, hipStream_t s)
+{
+    SurfaceDev &S = p.surf[w];
+    auto it = S.sides.find(bs);
+    if (it != S.sides.end()) return it->second;
+    const BlockSide &H = block_side(p.topo[w], bs);
+    Arena &A = p.bem_arena[w];
+    BlockSideDev D;
+    D.bs = bs;
+    D.nb = H.nb;
+    D.S = H.S;
+    D.pref = A.upload(H.pref, s);
+    D.nvb = A.upload(H.nvb, s);
+    D.slots = A.upload(H.slots, s);
+    D.L_ptr = A.upload(H.L_ptr, s);
+    D.L = A.upload(H.L, s);
+    D.L_blk = A.upload(H.L_blk, s);
+    return S.sides.emplace(bs, D).first->second;
+}
+
+struct RegArgs {
+    int64_t nt = 0;
+    const int32_t *m_tri = nullptr;
+    const void *xq = nullptr, *nq = nullptr;
+    const double *cen = nullptr, *m_area = nullptr;
+    BlockSideDev A, B;
+    int64_t b0 = 0, b1 = 0, rowbase = 0;
+    double *EV = nullptr, *EK = nullptr;
+    double kappa = 0.0;
+    QRule6 R;
+    QRule6F RF;
+};
+
+template <int TA, int TB> static void launch_regular_t(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
+{
+    const dim3 grid(unsigned(a.B.nb), unsigned(a.b1 - a.b0));
+#define PB_REG(Y, RT)                                                                                              \
+    hipLaunchKernelGGL((k_bem_regular<Y, RT, TA, TB>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,                   \
+                       static_cast<const RT *>(a.xq), static_cast<const RT *>(a.nq), a.cen, a.m_area, a.A.pref,     \
+                       a.A.nvb, a.A.slots, a.B.pref, a.B.nvb, a.B.slots, a.b0, a.rowbase, a.EV, a.EK, a.B.S,         \
+                       a.kappa, a.R, a.RF)
+    if (f32) {
+        if (yuk) PB_REG(true, float);
+        else PB_REG(false, float);
+    } else {
+        if (yuk) PB_REG(true, double);
+        else PB_REG(false, double);
+    }
+#undef PB_REG
+}
+
+static_assert(N_TILE_SHAPES == 5, "one launch case per candidate tile shape");
+static void launch_regular(int shape, bool yuk, bool f32, const RegArgs &a, hipStream_t s)
+{
+    switch (shape) {
+    case 0: launch_regular_t<TILE_SHAPES[0].ta, TILE_SHAPES[0].tb>(yuk, f32, a, s); break;
+    case 1: launch_regular_t<TILE_SHAPES[1].ta, TILE_SHAPES[1].tb>(yuk, f32, a, s); break;
+    case 2: launch_regular_t<TILE_SHAPES[2].ta, TILE_SHAPES[2].tb>(yuk, f32, a, s); break;
+    case 3: launch_regular_t<TILE_SHAPES[3].ta, TILE_SHAPES[3].tb>(yuk, f32, a, s); break;
+    case 4: launch_regular_t<TILE_SHAPES[4].ta, TILE_SHAPES[4].tb>(yuk, f32, a, s); break;
+    default: PB_CHECK(false, PBFB_EINVAL, "unknown tile shape");
+    }
+}
+
+// cache key of the tuned shape: precision, kernel and size class (floor log2 of the triangle count)
+static int tile_key(int precision, bool yuk, int64_t nt)
+{
+    int c = 0;
+    while (c < 62 && (int64_t(2) << c) <= nt) ++c;
+    return (precision * 2 + (yuk ? 1 : 0)) * 64 + c;
+}
+
+// Autotuner: times the regular tile kernel of every candidate shape on the
+// same sample of this surface (the first min(nt, 256) Morton-ordered target
+// triangles against all source triangles; one warm-up launch, then the
+// faster of two timed launches) and returns the shape with the shortest time
+// per target triangle.  Runs with the context workspace held.
+static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream_t s)
+{
+    SurfaceTopo &T = p.topo[w];
+    const int64_t nsample = std::min<int64_t>(T.nt, 256);
+    size_t need = 0;
+    for (int k = 0; k < N_TILE_SHAPES; ++k) {
+        const BlockSide &HA = block_side(T, TILE_SHAPES[k].ta), &HB = block_side(T, TILE_SHAPES[k].tb);
+        const int64_t nbs = (nsample + HA.bs - 1) / HA.bs;
+        need = std::max(need, size_t(HA.pref[nbs]) * size_t(HB.S) * 2);
+    }
+    double *E = p.ctx->asm_ws.doubles(need);
+    hipEvent_t e0, e1;
+    PB_HIP(hipEventCreate(&e0));
+    PB_HIP(hipEventCreate(&e1));
+    int best = 0;
+    double best_t = 1e300;
+    for (int k = 0; k < N_TILE_SHAPES; ++k) {
+        const BlockSide &HA = block_side(T, TILE_SHAPES[k].ta), &HB = block_side(T, TILE_SHAPES[k].tb);
+        a.A = device_side(p, w, HA.bs, s);
+        a.B = device_side(p, w, HB.bs, s);
+        a.b0 = 0;
+        a.b1 = (nsample + HA.bs - 1) / HA.bs;
+        a.rowbase = 0;
+        a.EV = E;
+        a.EK = E + size_t(HA.pref[a.b1]) * size_t(HB.S);
+        const int64_t tris = std::min<int64_t>(a.b1 * HA.bs, T.nt);
+        launch_regular(k, yuk, f32, a, s);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            PB_HIP(hipEventRecord(e0, s));
+            launch_regular(k, yuk, f32, a, s);
+            PB_HIP(hipEventRecord(e1, s));
+            PB_HIP(hipEventSynchronize(e1));
+            float t = 0.0f;
+            PB_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
+        PB_HIP(hipGetLastError());
+        const double per = double(ms) / double(tris);
+        if (per < best_t) {
+            best_t = per;
+            best = k;
+        }
+    }
+    PB_HIP(hipEventDestroy(e0));
+    PB_HIP(hipEventDestroy(e1));
+    return best;
+}
+
 void ensure_bem(Problem &p, int w, hipStream_t s)
 {
     if (p.bem_ready[w]) return;
@@ -778,16 +904,20 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     SurfaceDev &S = p.surf[w];
     Arena &A = p.bem_arena[w];
     const bool yuk = (w == 1) && p.kappa > 0.0;
+    const bool f32 = p.precision == PBFB_MIXED;
     const double kappa = (w == 1) ? p.kappa : 0.0;
     if (!p.bem_topo_ready[w]) {
-        // block tables and Morton order: once per mesh
+        // Morton order and triangle data: once per mesh (block tables are
+        // uploaded per block size when a tile shape needs them)
         A.release();
+        S.sides.clear();
+        S.tile = -1;
         S.B = nullptr;
         S.m_tri = A.alloc<int32_t>(3 * T.nt);
         S.m_area = A.alloc<double>(T.nt);
         S.m_qp = S.m_nrm = S.m_cen = nullptr;
         S.m_qf = S.m_nf = nullptr;
-        if (p.precision == PBFB_MIXED) {
+        if (f32) {
             S.m_cen = A.alloc<double>(3 * T.nt);
             S.m_qf = A.alloc<float>(18 * T.nt);
             S.m_nf = A.alloc<float>(3 * T.nt);
@@ -796,23 +926,8 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
             S.m_nrm = A.alloc<double>(3 * T.nt);
         }
         S.morton = A.upload(T.morton, s);
-        S.A_pref = A.upload(T.A_pref, s);
-        S.A_nv = A.upload(T.A_nv, s);
-        S.A_slots = A.upload(T.A_slots, s);
-        S.B_pref = A.upload(T.B_pref, s);
-        S.B_nv = A.upload(T.B_nv, s);
-        S.B_slots = A.upload(T.B_slots, s);
-        S.LA_ptr = A.upload(T.LA_ptr, s);
-        S.LA = A.upload(T.LA, s);
-        S.LA_blk = A.upload(T.LA_blk, s);
-        S.LB_ptr = A.upload(T.LB_ptr, s);
-        S.LB = A.upload(T.LB, s);
         S.tp_ptr = A.upload(T.tp_ptr, s);
         S.tp_sig = A.upload(T.tp_sig, s);
-        S.nbA = T.nbA;
-        S.nbB = T.nbB;
-        S.SA = T.SA;
-        S.SB = T.SB;
         S.ntp = int64_t(T.tp_sig.size());
         std::vector<int32_t> tp_tau(S.ntp);
         for (int64_t t = 0; t < T.nt; ++t)
@@ -823,7 +938,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         S.spai = A.alloc<double>(T.ring.size());
         const int64_t ldt = bem_ld(T.nv);
         S.vdiag = A.alloc<double>(T.nv);
-        if (p.precision == PBFB_MIXED) S.B = A.alloc<float>(T.nv * ldt);
+        if (f32) S.B = A.alloc<float>(T.nv * ldt);
         else S.B = A.alloc<double>(T.nv * ldt);
         PB_HIP(hipStreamSynchronize(s));
         p.bem_topo_ready[w] = true;
@@ -832,19 +947,6 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, S.morton, S.tri, S.qp, S.nrm,
                        S.area, S.g, p.d_x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
 
-    const int64_t nv = T.nv, ld = bem_ld(nv);
-    // chunks of target blocks, so that E stays within 2^30 entries per operator
-    const int64_t max_rows = std::max<int64_t>(BA * 3, (int64_t(1) << 30) / std::max<int64_t>(T.SB, 1));
-    std::vector<std::pair<int64_t, int64_t>> chunks;
-    int64_t chunk_rows = 0;
-    for (int64_t b0 = 0; b0 < T.nbA;) {
-        int64_t b1 = b0;
-        while (b1 < T.nbA && T.A_pref[b1 + 1] - T.A_pref[b0] <= max_rows) ++b1;
-        if (b1 == b0) b1 = b0 + 1;
-        chunks.push_back({b0, b1});
-        chunk_rows = std::max<int64_t>(chunk_rows, T.A_pref[b1] - T.A_pref[b0]);
-        b0 = b1;
-    }
     // the context's assembly workspace: E (V, K), W (V, K), FP64 staging
     // (mixed precision assembles in FP64 and narrows at the end; FP64 storage
     // assembles in place), vertex coordinates and touching-pair blocks
@@ -853,41 +955,73 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         hipStream_t s;
         ~Drain() { (void)hipStreamSynchronize(s); }
     } drain{s};
-    const bool stage64 = p.precision == PBFB_MIXED;
-    const size_t nE = size_t(chunk_rows) * T.SB, nW = size_t(nv) * T.SB;
+    RegArgs ra;
+    ra.nt = T.nt;
+    ra.m_tri = S.m_tri;
+    ra.xq = f32 ? static_cast<const void *>(S.m_qf) : static_cast<const void *>(S.m_qp);
+    ra.nq = f32 ? static_cast<const void *>(S.m_nf) : static_cast<const void *>(S.m_nrm);
+    ra.cen = S.m_cen;
+    ra.m_area = S.m_area;
+    ra.kappa = kappa;
+    ra.R = q6arg();
+    ra.RF = q6farg();
+    // tile shape: forced, or tuned once per (precision, kernel, size class) and context
+    int shape = p.tile_fixed;
+    if (shape < 0) {
+        const int key = tile_key(p.precision, yuk, T.nt);
+        auto it = p.ctx->tile_choice.find(key);
+        if (it != p.ctx->tile_choice.end()) {
+            shape = it->second;
+        } else {
+            shape = tile_tune(p, w, ra, yuk, f32, s);
+            p.ctx->tile_choice[key] = shape;
+        }
+    }
+    S.tile = shape;
+    const BlockSide &HA = block_side(T, TILE_SHAPES[shape].ta);
+    const BlockSideDev &DA = device_side(p, w, TILE_SHAPES[shape].ta, s);
+    const BlockSideDev &DB = device_side(p, w, TILE_SHAPES[shape].tb, s);
+    ra.A = DA;
+    ra.B = DB;
+
+    const int64_t nv = T.nv, ld = bem_ld(nv);
+    // chunks of target blocks, so that E stays within 2^30 entries per operator
+    const int64_t max_rows = std::max<int64_t>(3 * HA.bs, (int64_t(1) << 30) / std::max<int64_t>(DB.S, 1));
+    std::vector<std::pair<int64_t, int64_t>> chunks;
+    int64_t chunk_rows = 0;
+    for (int64_t b0 = 0; b0 < HA.nb;) {
+        int64_t b1 = b0;
+        while (b1 < HA.nb && HA.pref[b1 + 1] - HA.pref[b0] <= max_rows) ++b1;
+        if (b1 == b0) b1 = b0 + 1;
+        chunks.push_back({b0, b1});
+        chunk_rows = std::max<int64_t>(chunk_rows, HA.pref[b1] - HA.pref[b0]);
+        b0 = b1;
+    }
+    const bool stage64 = f32;
+    const size_t nE = size_t(chunk_rows) * DB.S, nW = size_t(nv) * DB.S;
     double *ws = p.ctx->asm_ws.doubles(2 * nE + 2 * nW + (stage64 ? size_t(nv) * ld : 0) + 3 * nv + 18 * S.ntp);
     double *EV = ws, *EK = EV + nE, *WV = EK + nE, *WK = WV + nW;
     double *B64 = stage64 ? WK + nW : static_cast<double *>(S.B);
     double *vx = (stage64 ? B64 + size_t(nv) * ld : WK + nW), *tpv = vx + 3 * nv;
-    QRule6 R = q6arg();
-    QRule6F RF = q6farg();
     bool first = true;
     for (const auto &ch : chunks) {
-        const int64_t b0 = ch.first, b1 = ch.second;
-        dim3 grid(unsigned(T.nbB), unsigned(b1 - b0));
+        ra.b0 = ch.first;
+        ra.b1 = ch.second;
+        ra.rowbase = HA.pref[ch.first];
+        ra.EV = EV;
+        ra.EK = EK;
         if (p.timing) p.timer.begin(T_ASM, s);
-#define PB_REGULAR(Y, RT, XQ, NQ, CEN)                                                                           \
-    hipLaunchKernelGGL((k_bem_regular<Y, RT>), grid, dim3(REG_THREADS), 0, s, T.nt, S.m_tri, XQ, NQ, CEN, S.m_area, S.A_pref, \
-                       S.A_nv, S.A_slots, S.B_pref, S.B_nv, S.B_slots, b0, int64_t(T.A_pref[b0]), EV, EK, T.SB,      \
-                       kappa, R, RF)
-        if (p.precision == PBFB_MIXED) {
-            if (yuk) PB_REGULAR(true, float, S.m_qf, S.m_nf, S.m_cen);
-            else PB_REGULAR(false, float, S.m_qf, S.m_nf, S.m_cen);
-        } else {
-            if (yuk) PB_REGULAR(true, double, S.m_qp, S.m_nrm, (const double *)nullptr);
-            else PB_REGULAR(false, double, S.m_qp, S.m_nrm, (const double *)nullptr);
-        }
-#undef PB_REGULAR
+        launch_regular(shape, yuk, f32, ra, s);
         if (p.timing) p.timer.end(s);
         PB_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_bem_pass1, dim3(nblk(T.SB, 256), unsigned(nv)), dim3(256), 0, s, nv, T.SB, S.LA_ptr,
-                           S.LA, S.LA_blk, b0, b1, int64_t(T.A_pref[b0]), EV, EK, WV, WK, first ? 1 : 0);
+        hipLaunchKernelGGL(k_bem_pass1, dim3(nblk(DB.S, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, DA.L_ptr,
+                           DA.L, DA.L_blk, ra.b0, ra.b1, ra.rowbase, EV, EK, WV, WK, first ? 1 : 0);
         PB_HIP(hipGetLastError());
         first = false;
     }
     const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
     PB_HIP(hipMemsetAsync(B64, 0, sizeof(double) * nv * ld, s));
-    hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, T.SB, ld, S.LB_ptr, S.LB,
+    hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, ld, DB.L_ptr, DB.L,
                        WV, WK, sV, sK, B64);
     PB_HIP(hipGetLastError());
     // touching pairs

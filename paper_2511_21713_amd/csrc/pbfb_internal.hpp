@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <map>
 #include <mutex>
 #include <cstdint>
 #include <string>
@@ -70,11 +71,36 @@ struct Arena {
     ~Arena() { release(); }
 };
 
-// block sizes of the regular assembly (target x source triangles per workgroup)
-constexpr int BA = 16;
-constexpr int BB = 32;
+// Tile shapes of the regular assembly: ta target x tb source Morton-ordered
+// triangles per workgroup, one triangle pair per thread.  The shape of each
+// (precision, kernel, size class) is chosen at run time by timing every
+// candidate on a sample of the actual surface (tile_tune in kernels_bem.hip).
+struct TileShape {
+    int ta, tb;
+};
+constexpr TileShape TILE_SHAPES[] = {{16, 32}, {8, 32}, {32, 32}, {8, 64}, {16, 64}};
+constexpr int N_TILE_SHAPES = int(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
 constexpr int MAXS = 12; // slots per local vertex in a block (max triangles of a block at one vertex)
+int tile_shape_index(int ta, int tb); // -1 if not a candidate
 constexpr int MAXRING = 64; // largest 1-ring (vertex and its neighbours) of the approximate inverse
+
+// Blocks of `bs` consecutive Morton-ordered triangles (one side of a tile
+// shape): nb blocks, S = sum of their vertex counts (rows or columns of the
+// expanded tile matrix); per block its first expanded index and vertex
+// count; per expanded index the MAXS (triangle-in-block * 3 + corner) slots
+// touching that vertex (-1 padded); per surface vertex its expanded indices
+// and their blocks.
+struct BlockSide {
+    int bs = 0;
+    int64_t nb = 0, S = 0;
+    std::vector<int32_t> pref, nvb, slots;
+    std::vector<int32_t> L_ptr, L, L_blk;
+};
+struct BlockSideDev {
+    int bs = 0;
+    int64_t nb = 0, S = 0;
+    int32_t *pref = nullptr, *nvb = nullptr, *slots = nullptr, *L_ptr = nullptr, *L = nullptr, *L_blk = nullptr;
+};
 
 // host-side topology of one boundary surface
 struct SurfaceTopo {
@@ -83,12 +109,9 @@ struct SurfaceTopo {
     std::vector<int32_t> tri;          // 3*nt local vertex ids, original order
     std::vector<int32_t> v2t_ptr, v2t; // vertex -> (tri*3 + local index)
     std::vector<int32_t> morton;       // Morton position -> triangle id
-    // regular-assembly blocks (over Morton-ordered triangles)
-    int64_t nbA = 0, nbB = 0, SA = 0, SB = 0;
-    std::vector<int32_t> A_pref, A_nv, A_loc, A_slots; // A_loc: 3 per Morton position
-    std::vector<int32_t> B_pref, B_nv, B_loc, B_slots;
-    std::vector<int32_t> LA_ptr, LA, LA_blk; // vertex -> expanded rows (and their A block)
-    std::vector<int32_t> LB_ptr, LB;         // vertex -> expanded columns
+    // regular-assembly blocks of each block size in use (over Morton-ordered
+    // triangles), built on first use
+    std::map<int, BlockSide> sides;
     // touching pairs (tau, sigma) sharing at least one vertex, grouped by tau
     std::vector<int32_t> tp_ptr, tp_sig;
     // 1-ring pattern of the sparse approximate inverse
@@ -105,10 +128,8 @@ struct SurfaceDev {
     double *m_qp = nullptr, *m_nrm = nullptr, *m_area = nullptr; // FP64 evaluation
     double *m_cen = nullptr;                                     // FP32 evaluation: FP64 centroids,
     float *m_qf = nullptr, *m_nf = nullptr;                      // FP32 offsets from them, FP32 normals
-    int32_t *A_pref = nullptr, *A_nv = nullptr, *A_loc = nullptr, *A_slots = nullptr;
-    int32_t *B_pref = nullptr, *B_nv = nullptr, *B_loc = nullptr, *B_slots = nullptr;
-    int32_t *LA_ptr = nullptr, *LA = nullptr, *LA_blk = nullptr, *LB_ptr = nullptr, *LB = nullptr;
-    int64_t nbA = 0, nbB = 0, SA = 0, SB = 0;
+    std::map<int, BlockSideDev> sides; // device copies of the block tables in use (bem arena)
+    int tile = -1;                      // tile shape of the last assembly (index into TILE_SHAPES)
     int32_t *tp_ptr = nullptr, *tp_sig = nullptr, *tp_tau = nullptr, *morton = nullptr;
     int64_t ntp = 0;
     int32_t *cslot = nullptr; // FEM-row slot of the coupling entry per (v2t entry, b)
@@ -135,6 +156,8 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     Workspace asm_ws;
+    // tuned tile shape per (precision, kernel, size class); guarded by asm_ws.mu
+    std::map<int, int> tile_choice;
 };
 
 enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_PREC = 5, T_NCLASS = 6 };
@@ -174,6 +197,7 @@ struct Problem {
     bool have_mesh = false, have_charges = false, have_params = false;
     bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
     bool bem_topo_ready[2] = {false, false};
+    int tile_fixed = -1; // tile shape forced by pbfb_set_tile_shape (index), -1: tuned
     // host copies
     int64_t nn = 0, ntet = 0, nq = 0;
     std::vector<double> x;
@@ -216,6 +240,7 @@ void release_all_scratch(Problem &p);
 
 // host preprocessing (setup.hip)
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri);
+const BlockSide &block_side(SurfaceTopo &S, int bs); // built on first use
 constexpr int SLICE = 64; // FEM rows per sliced-ELL slice: one wavefront
 void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int32_t> &col,
                         std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,

@@ -31,10 +31,16 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
     const size_t elem = p.precision == PBFB_MIXED ? 4 : 8;
     size_t dense = 0, tmp = 0;
     for (int w = 0; w < 2; ++w) {
-        const SurfaceTopo &T = p.topo[w];
+        // block tables are a host-side cache filled on first use
+        SurfaceTopo &T = const_cast<SurfaceTopo &>(p.topo[w]);
         dense += size_t(T.nv) * bem_ld(T.nv) * elem;
-        tmp = std::max(tmp, size_t(T.SA) * T.SB * 16 + size_t(T.nv) * T.SB * 16 +
-                                (p.precision == PBFB_MIXED ? size_t(T.nv) * bem_ld(T.nv) * 8 : 0));
+        for (int k = 0; k < N_TILE_SHAPES; ++k) {
+            const size_t SA = size_t(block_side(T, TILE_SHAPES[k].ta).S), SB = size_t(block_side(T, TILE_SHAPES[k].tb).S);
+            const size_t rows = std::min(SA, std::max<size_t>(3 * TILE_SHAPES[k].ta, (size_t(1) << 30) / SB) +
+                                                  3 * TILE_SHAPES[k].ta); // one assembly chunk of E
+            tmp = std::max(tmp, rows * SB * 16 + size_t(T.nv) * SB * 16 +
+                                    (p.precision == PBFB_MIXED ? size_t(T.nv) * bem_ld(T.nv) * 8 : 0));
+        }
     }
     const size_t n = size_t(p.n());
     const size_t nnz_est = size_t(p.ntet) * 3 + size_t(p.nn) * 4; // generous: ~14 per row

@@ -22,20 +22,27 @@ static uint32_t spread10(uint32_t v)
     return v;
 }
 
-// Blocks of `bs` consecutive Morton-ordered triangles: unique local vertex
-// lists, each triangle corner's local index, and for every local vertex the
-// (triangle-in-block * 3 + corner) slots that touch it.
-static void make_blocks(const SurfaceTopo &S, int bs, int64_t &nb, int64_t &total, std::vector<int32_t> &pref,
-                        std::vector<int32_t> &nvb, std::vector<int32_t> &loc, std::vector<int32_t> &slots,
-                        std::vector<std::vector<std::pair<int32_t, int32_t>>> &vlist)
+int tile_shape_index(int ta, int tb)
 {
-    nb = (S.nt + bs - 1) / bs;
-    pref.assign(nb + 1, 0);
-    nvb.assign(nb, 0);
-    loc.assign(nb * bs * 3, -1);
-    vlist.assign(S.nv, {});
-    std::vector<std::vector<int32_t>> blk_verts(nb);
-    for (int64_t b = 0; b < nb; ++b) {
+    for (int k = 0; k < N_TILE_SHAPES; ++k)
+        if (TILE_SHAPES[k].ta == ta && TILE_SHAPES[k].tb == tb) return k;
+    return -1;
+}
+
+// Blocks of `bs` consecutive Morton-ordered triangles: unique local vertex
+// lists, and for every local vertex the (triangle-in-block * 3 + corner)
+// slots that touch it; per surface vertex its expanded indices.
+const BlockSide &block_side(SurfaceTopo &S, int bs)
+{
+    auto found = S.sides.find(bs);
+    if (found != S.sides.end()) return found->second;
+    BlockSide B;
+    B.bs = bs;
+    B.nb = (S.nt + bs - 1) / bs;
+    B.pref.assign(B.nb + 1, 0);
+    B.nvb.assign(B.nb, 0);
+    std::vector<std::vector<int32_t>> blk_verts(B.nb);
+    for (int64_t b = 0; b < B.nb; ++b) {
         std::vector<int32_t> vs;
         for (int k = 0; k < bs; ++k) {
             int64_t m = b * bs + k;
@@ -46,12 +53,13 @@ static void make_blocks(const SurfaceTopo &S, int bs, int64_t &nb, int64_t &tota
         std::sort(vs.begin(), vs.end());
         vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
         blk_verts[b] = vs;
-        nvb[b] = (int32_t)vs.size();
-        pref[b + 1] = pref[b] + nvb[b];
+        B.nvb[b] = (int32_t)vs.size();
+        B.pref[b + 1] = B.pref[b] + B.nvb[b];
     }
-    total = pref[nb];
-    slots.assign(total * MAXS, -1);
-    for (int64_t b = 0; b < nb; ++b) {
+    B.S = B.pref[B.nb];
+    B.slots.assign(B.S * MAXS, -1);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> vlist(S.nv);
+    for (int64_t b = 0; b < B.nb; ++b) {
         const auto &vs = blk_verts[b];
         std::vector<int> fill(vs.size(), 0);
         for (int k = 0; k < bs; ++k) {
@@ -61,13 +69,21 @@ static void make_blocks(const SurfaceTopo &S, int bs, int64_t &nb, int64_t &tota
             for (int a = 0; a < 3; ++a) {
                 int32_t v = S.tri[3 * t + a];
                 int32_t li = int32_t(std::lower_bound(vs.begin(), vs.end(), v) - vs.begin());
-                loc[m * 3 + a] = li;
                 PB_CHECK(fill[li] < MAXS, PBFB_EMESH, "vertex valence too high for the assembly blocks");
-                slots[(int64_t(pref[b]) + li) * MAXS + fill[li]++] = k * 3 + a;
+                B.slots[(int64_t(B.pref[b]) + li) * MAXS + fill[li]++] = k * 3 + a;
             }
         }
-        for (size_t li = 0; li < vs.size(); ++li) vlist[vs[li]].push_back({pref[b] + int32_t(li), int32_t(b)});
+        for (size_t li = 0; li < vs.size(); ++li) vlist[vs[li]].push_back({B.pref[b] + int32_t(li), int32_t(b)});
     }
+    B.L_ptr.assign(S.nv + 1, 0);
+    for (int64_t i = 0; i < S.nv; ++i) {
+        B.L_ptr[i + 1] = B.L_ptr[i] + int32_t(vlist[i].size());
+        for (auto &e : vlist[i]) {
+            B.L.push_back(e.first);
+            B.L_blk.push_back(e.second);
+        }
+    }
+    return S.sides.emplace(bs, std::move(B)).first->second;
 }
 
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
@@ -142,21 +158,10 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
         S.morton.resize(ntri);
         for (int64_t m = 0; m < ntri; ++m) S.morton[m] = key[m].second;
     }
-    // assembly blocks and vertex -> expanded row/column lists
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> vlA, vlB;
-    make_blocks(S, BA, S.nbA, S.SA, S.A_pref, S.A_nv, S.A_loc, S.A_slots, vlA);
-    make_blocks(S, BB, S.nbB, S.SB, S.B_pref, S.B_nv, S.B_loc, S.B_slots, vlB);
-    S.LA_ptr.assign(S.nv + 1, 0);
-    S.LB_ptr.assign(S.nv + 1, 0);
-    for (int64_t i = 0; i < S.nv; ++i) {
-        S.LA_ptr[i + 1] = S.LA_ptr[i] + int32_t(vlA[i].size());
-        S.LB_ptr[i + 1] = S.LB_ptr[i] + int32_t(vlB[i].size());
-        for (auto &e : vlA[i]) {
-            S.LA.push_back(e.first);
-            S.LA_blk.push_back(e.second);
-        }
-        for (auto &e : vlB[i]) S.LB.push_back(e.first);
-    }
+    // blocks of the default tile shape (other block sizes are built when a
+    // shape using them is timed or chosen)
+    block_side(S, TILE_SHAPES[0].ta);
+    block_side(S, TILE_SHAPES[0].tb);
     // 1-ring of each vertex (itself and every vertex sharing a triangle), ascending
     S.ring_ptr.assign(S.nv + 1, 0);
     S.ring.clear();

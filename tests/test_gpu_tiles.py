@@ -1,0 +1,110 @@
+"""Regular-assembly tile shapes and the autotuner, through the C ABI.
+
+Every candidate shape (ta target x tb source triangles per workgroup) must
+assemble the same Galerkin blocks as the oracle: the shape changes only the
+order of the floating-point sums.  The surface here (720 triangles, 362
+vertices) is not a multiple of any block size, so every shape has a ragged
+last block on both sides, and the Yukawa surface takes the kappa > 0 kernel.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import pbgen
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 32), (8, 32), (32, 32), (8, 64), (16, 64)]
+SPEC = dict(n=6, a=5.0, c=8.0, bump=True, t=3.0, L=2, helix=2, partials=4, kappa=0.15, seed=(9, 3))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tiles():
+    import paper_2511_21713_amd as pb
+    ctx = pb.Context(0)
+    prob = pbgen.make_problem(**SPEC)
+    o = oracle.Oracle.from_problem(prob)
+    refs = []
+    for surf in (0, 1):
+        V, K = o.bem_dense(surf)
+        nv = V.shape[0]
+        M = np.stack([o.surface_mass_apply(surf, e) for e in np.eye(nv)], 1)
+        refs.append((-V if surf == 0 else V, 0.5 * M + (K if surf == 0 else -K)))
+    return pb, ctx, prob, refs
+
+
+def rowrel(A, B):
+    return (np.abs(A - B) / np.abs(B).max(1, keepdims=True)).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_each_tile_shape_matches_oracle(tiles, shape, precision):
+    pb, ctx, prob, refs = tiles
+    g = pb.Problem.from_inputs(ctx, prob, precision=precision)
+    g.set_tile_shape(*shape)
+    bar = 1e-12 if precision == 0 else 1e-6
+    for surf in (0, 1):
+        Vp, Kp = g.export_bem(surf)
+        assert g.tile_shape(surf) == shape
+        eV, eK = rowrel(Vp, refs[surf][0]), rowrel(Kp, refs[surf][1])
+        log(f"  shape {shape} precision {precision} surf {surf}: V {eV:.2e} K {eK:.2e}")
+        assert eV < bar and eK < bar
+    g.close()
+
+
+def test_tuned_shape_is_a_candidate_and_sticks(tiles):
+    """Default mode: the autotuner picks a candidate; a second problem of the
+    same size class in the same context reuses the choice, and the operators
+    equal those of that shape pinned explicitly, bit for bit."""
+    pb, ctx, prob, refs = tiles
+    g = pb.Problem.from_inputs(ctx, prob)
+    Vt, Kt = g.export_bem(1)
+    shape = g.tile_shape(1)
+    log(f"  tuned shape (Yukawa, FP64, 720 triangles): {shape}")
+    assert shape in SHAPES
+    assert rowrel(Vt, refs[1][0]) < 1e-12 and rowrel(Kt, refs[1][1]) < 1e-12
+    g2 = pb.Problem.from_inputs(ctx, prob)
+    V2, K2 = g2.export_bem(1)
+    assert g2.tile_shape(1) == shape
+    assert np.array_equal(V2, Vt) and np.array_equal(K2, Kt)
+    g2.set_tile_shape(*shape)
+    V3, K3 = g2.export_bem(1)
+    assert np.array_equal(V3, Vt) and np.array_equal(K3, Kt)
+    g2.set_tile_shape(0, 0)
+    assert g2.tile_shape(1) == shape  # last assembly until the next one
+    g.close()
+    g2.close()
+
+
+def test_solve_with_pinned_shapes_agrees(tiles):
+    """Full solves with two different pinned shapes agree to rounding."""
+    pb, ctx, prob, refs = tiles
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    tot = []
+    for shape in ((8, 32), (16, 64)):
+        g = pb.Problem.from_inputs(ctx, prob)
+        g.set_tile_shape(*shape)
+        r = g.solve(**kw)
+        assert r["status"] == 0
+        tot.append(r["total"])
+        g.close()
+    log(f"  totals {tot[0]!r} {tot[1]!r}")
+    assert abs(tot[0] - tot[1]) < 1e-11 * abs(tot[0])
+
+
+def test_bad_tile_shape_rejected(tiles):
+    pb, ctx, prob, refs = tiles
+    g = pb.Problem.from_inputs(ctx, prob)
+    with pytest.raises(pb.PbfbError):
+        g.set_tile_shape(12, 32)
+    with pytest.raises(pb.PbfbError):
+        g.set_tile_shape(16, 0)
+    g.close()
