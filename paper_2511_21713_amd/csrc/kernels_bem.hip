@@ -126,10 +126,88 @@ __device__ inline double rsqrt_pos(double x)
 }
 __device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Fold of a tile's pair blocks onto the block's vertices through the shared
+// tile, V then K: first the source corners of each source vertex (in place,
+// row by row), then the target corners of each target vertex.  A thread owns
+// one source vertex jb and a strided set of rows; the corner lists are read
+// once into registers and every tile read is independent (an absent corner
+// reads the zero row / column), so the reads pipeline.  MS >= the largest
+// number of corners of any vertex of either block: the lists past it hold
+// only absent corners, whose +0 terms are skipped.
+template <int TA, int TB, int MS>
+__device__ inline void fold_tile(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
+                                 const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Vl,
+                                 const double *Kl, double *__restrict__ EV, double *__restrict__ EK, int64_t row0,
+                                 int64_t pB, int64_t ldE)
+{
+    constexpr int NT = TA * TB;
+    const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+    const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
+    int cb[MS];
+#pragma unroll
+    for (int l = 0; l < MS; ++l) {
+        const int c = sSb[jb][l];
+        cb[l] = c < 0 ? TB * 3 : c;
+    }
+    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = 0.0;
+    if (tid < TA * 3) acc[tid][TB * 3] = 0.0;
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[3 * a + b] : Kl[3 * a + b];
+        __syncthreads();
+        constexpr int RMAX = TA * 3;
+        constexpr int RPT = (RMAX + NT / (TB * 3) - 1) / (NT / (TB * 3)); // rows per thread, nB <= TB * 3
+        double colsum[RPT];
+        int nrow = 0;
+        if (colthread) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int sa = r0 + r * rstep;
+                double t = 0.0;
+                if (sa < RMAX) {
+                    double v[MS];
+#pragma unroll
+                    for (int l = 0; l < MS; ++l) v[l] = acc[sa][cb[l]];
+#pragma unroll
+                    for (int l = 0; l < MS; ++l) t += v[l];
+                    nrow = r + 1;
+                }
+                colsum[r] = t;
+            }
+        }
+        __syncthreads();
+        if (colthread)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
+        __syncthreads();
+        double *E = op == 0 ? EV : EK;
+        if (colthread)
+            for (int ia = r0; ia < nA; ia += rstep) {
+                double v[MS];
+#pragma unroll
+                for (int k = 0; k < MS; ++k) {
+                    const int ra = sSa[ia][k];
+                    v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
+                }
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < MS; ++k) t += v[k];
+                E[(row0 + ia) * ldE + pB + jb] = t;
+            }
+        __syncthreads();
+    }
+}
+
 // RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
-// TA x TB: target x source triangles of the tile, one pair per thread
-template <bool YUK, typename RT, int TA, int TB>
+// TA x TB: target x source triangles of the tile, one pair per thread; MS:
+// bound on the corners of one vertex in one block (6 for meshes of vertex
+// valence <= 6, else MAXS)
+template <bool YUK, typename RT, int TA, int TB, int MS>
 __global__ void __launch_bounds__(TA * TB, 4)
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
@@ -263,71 +341,7 @@ __global__ void __launch_bounds__(TA * TB, 4)
         }
     }
 
-    // fold both operators onto the block's vertices through the shared tile,
-    // V then K: first the source corners of each source vertex (in place,
-    // row by row), then the target corners of each target vertex.  A thread
-    // owns one source vertex jb and a strided set of rows; the corner lists
-    // are read once into registers and every tile read is independent (an
-    // absent corner reads the zero row / column), so the reads pipeline.
-    const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
-    const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
-    int cb[MAXS];
-#pragma unroll
-    for (int l = 0; l < MAXS; ++l) {
-        const int c = sSb[jb][l];
-        cb[l] = c < 0 ? TB * 3 : c;
-    }
-    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = 0.0;
-    if (tid < TA * 3) acc[tid][TB * 3] = 0.0;
-#pragma unroll
-    for (int op = 0; op < 2; ++op) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[3 * a + b] : Kl[3 * a + b];
-        __syncthreads();
-        constexpr int RMAX = TA * 3;
-        constexpr int RPT = (RMAX + NT / (TB * 3) - 1) / (NT / (TB * 3)); // rows per thread, nB <= TB * 3
-        double colsum[RPT];
-        int nrow = 0;
-        if (colthread) {
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int sa = r0 + r * rstep;
-                double t = 0.0;
-                if (sa < RMAX) {
-                    double v[MAXS];
-#pragma unroll
-                    for (int l = 0; l < MAXS; ++l) v[l] = acc[sa][cb[l]];
-#pragma unroll
-                    for (int l = 0; l < MAXS; ++l) t += v[l];
-                    nrow = r + 1;
-                }
-                colsum[r] = t;
-            }
-        }
-        __syncthreads();
-        if (colthread)
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
-        __syncthreads();
-        double *E = op == 0 ? EV : EK;
-        if (colthread)
-            for (int ia = r0; ia < nA; ia += rstep) {
-                double v[MAXS];
-#pragma unroll
-                for (int k = 0; k < MAXS; ++k) {
-                    const int ra = sSa[ia][k];
-                    v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
-                }
-                double t = 0.0;
-#pragma unroll
-                for (int k = 0; k < MAXS; ++k) t += v[k];
-                E[(pA - rowbase + ia) * ldE + pB + jb] = t;
-            }
-        __syncthreads();
-    }
+    fold_tile<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
 }
 
 // ---------------------------------------------------------------------------
@@ -799,15 +813,16 @@ struct RegArgs {
     int64_t b0 = 0, b1 = 0, rowbase = 0;
     double *EV = nullptr, *EK = nullptr;
     double kappa = 0.0;
+    int ms = MAXS; // largest corner count of a vertex in a block, both sides
     QRule6 R;
     QRule6F RF;
 };
 
-template <int TA, int TB> static void launch_regular_t(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
+template <int TA, int TB, int MS> static void launch_regular_ms(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
 {
     const dim3 grid(unsigned(a.B.nb), unsigned(a.b1 - a.b0));
 #define PB_REG(Y, RT)                                                                                              \
-    hipLaunchKernelGGL((k_bem_regular<Y, RT, TA, TB>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,                   \
+    hipLaunchKernelGGL((k_bem_regular<Y, RT, TA, TB, MS>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,               \
                        static_cast<const RT *>(a.xq), static_cast<const RT *>(a.nq), a.cen, a.m_area, a.A.pref,     \
                        a.A.nvb, a.A.slots, a.B.pref, a.B.nvb, a.B.slots, a.b0, a.rowbase, a.EV, a.EK, a.B.S,         \
                        a.kappa, a.R, a.RF)
@@ -819,6 +834,11 @@ template <int TA, int TB> static void launch_regular_t(bool yuk, bool f32, const
         else PB_REG(false, double);
     }
 #undef PB_REG
+}
+template <int TA, int TB> static void launch_regular_t(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
+{
+    if (a.ms <= 6) launch_regular_ms<TA, TB, 6>(yuk, f32, a, s);
+    else launch_regular_ms<TA, TB, MAXS>(yuk, f32, a, s);
 }
 
 static_assert(N_TILE_SHAPES == 5, "one launch case per candidate tile shape");
@@ -867,6 +887,7 @@ static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream
         const BlockSide &HA = block_side(T, TILE_SHAPES[k].ta), &HB = block_side(T, TILE_SHAPES[k].tb);
         a.A = device_side(p, w, HA.bs, s);
         a.B = device_side(p, w, HB.bs, s);
+        a.ms = std::max(HA.ms_max, HB.ms_max);
         a.b0 = 0;
         a.b1 = (nsample + HA.bs - 1) / HA.bs;
         a.rowbase = 0;
@@ -983,6 +1004,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     const BlockSideDev &DB = device_side(p, w, TILE_SHAPES[shape].tb, s);
     ra.A = DA;
     ra.B = DB;
+    ra.ms = std::max(HA.ms_max, block_side(T, TILE_SHAPES[shape].tb).ms_max);
 
     const int64_t nv = T.nv, ld = bem_ld(nv);
     // chunks of target blocks, so that E stays within 2^30 entries per operator

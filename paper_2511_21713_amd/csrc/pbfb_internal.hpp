@@ -88,10 +88,11 @@ constexpr int MAXRING = 64; // largest 1-ring (vertex and its neighbours) of the
 // shape): nb blocks, S = sum of their vertex counts (rows or columns of the
 // expanded tile matrix); per block its first expanded index and vertex
 // count; per expanded index the MAXS (triangle-in-block * 3 + corner) slots
-// touching that vertex (-1 padded); per surface vertex its expanded indices
-// and their blocks.
+// touching that vertex (-1 padded); ms_max = the largest slot count of any
+// vertex in any block; per surface vertex its expanded indices and their
+// blocks.
 struct BlockSide {
-    int bs = 0;
+    int bs = 0, ms_max = 0;
     int64_t nb = 0, S = 0;
     std::vector<int32_t> pref, nvb, slots;
     std::vector<int32_t> L_ptr, L, L_blk;
@@ -99,7 +100,8 @@ struct BlockSide {
 struct BlockSideDev {
     int bs = 0;
     int64_t nb = 0, S = 0;
-    int32_t *pref = nullptr, *nvb = nullptr, *slots = nullptr, *L_ptr = nullptr, *L = nullptr, *L_blk = nullptr;
+    int32_t *pref = nullptr, *nvb = nullptr, *slots = nullptr;
+    int32_t *L_ptr = nullptr, *L = nullptr, *L_blk = nullptr;
 };
 
 // host-side topology of one boundary surface

@@ -74,6 +74,7 @@ const BlockSide &block_side(SurfaceTopo &S, int bs)
             }
         }
         for (size_t li = 0; li < vs.size(); ++li) vlist[vs[li]].push_back({B.pref[b] + int32_t(li), int32_t(b)});
+        for (int f : fill) B.ms_max = std::max(B.ms_max, f);
     }
     B.L_ptr.assign(S.nv + 1, 0);
     for (int64_t i = 0; i < S.nv; ++i) {

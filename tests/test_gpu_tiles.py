@@ -108,3 +108,60 @@ def test_bad_tile_shape_rejected(tiles):
     with pytest.raises(pb.PbfbError):
         g.set_tile_shape(16, 0)
     g.close()
+
+
+def uv_sphere(nlon=9, nlat=6):
+    """Unit sphere triangulated by latitude rings: the two poles have valence
+    nlon (> 6), so some assembly block holds a vertex with more than 6 of its
+    triangles and the fold takes its full corner lists."""
+    verts = [(0.0, 0.0, 1.0)]
+    for i in range(1, nlat):
+        th = np.pi * i / nlat
+        for j in range(nlon):
+            ph = 2 * np.pi * (j + 0.5 * (i % 2)) / nlon
+            verts.append((np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)))
+    verts.append((0.0, 0.0, -1.0))
+    verts = np.array(verts)
+    ring = lambda i, j: 1 + (i - 1) * nlon + (j % nlon)
+    south = len(verts) - 1
+    tris = []
+    for j in range(nlon):
+        tris.append((0, ring(1, j), ring(1, j + 1)))
+        tris.append((south, ring(nlat - 1, j + 1), ring(nlat - 1, j)))
+    for i in range(1, nlat - 1):
+        for j in range(nlon):
+            a, b = ring(i, j), ring(i, j + 1)
+            c, d = ring(i + 1, j), ring(i + 1, j + 1)
+            if i % 2:
+                tris += [(a, c, d), (a, d, b)]
+            else:
+                tris += [(a, c, b), (b, c, d)]
+    tris = np.array(tris)
+    # outward orientation (normal along the position)
+    p = verts[tris]
+    n = np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0])
+    flip = np.einsum("ij,ij->i", n, p.sum(1)) < 0
+    tris[flip] = tris[flip][:, [0, 2, 1]]
+    return verts, tris
+
+
+def test_high_valence_mesh_matches_oracle(tiles):
+    pb, ctx, _, _ = tiles
+    unit, tris = uv_sphere()
+    nodes, tets, tri_m, tri_s = pbgen.shell_mesh(unit, tris, 4.0 * np.ones(unit.shape[0]), 3.0, 2)
+    prob = pbgen.Problem(nodes=nodes, tets=tets, tri_m=tri_m, tri_s=tri_s, q_xyz=np.zeros((1, 3)),
+                         q_z=np.array([1.0]), eps_in=4.0, eps_out=80.0, kappa=0.2, info={})
+    o = oracle.Oracle.from_problem(prob)
+    for shape in ((8, 32), (16, 64)):
+        g = pb.Problem.from_inputs(ctx, prob)
+        g.set_tile_shape(*shape)
+        for surf in (0, 1):
+            V, K = o.bem_dense(surf)
+            nv = V.shape[0]
+            M = np.stack([o.surface_mass_apply(surf, e) for e in np.eye(nv)], 1)
+            Vp, Kp = g.export_bem(surf)
+            eV = rowrel(Vp, -V if surf == 0 else V)
+            eK = rowrel(Kp, 0.5 * M + (K if surf == 0 else -K))
+            log(f"  valence-{9} mesh, shape {shape}, surf {surf}: V {eV:.2e} K {eK:.2e}")
+            assert eV < 1e-12 and eK < 1e-12
+        g.close()
