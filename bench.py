@@ -188,19 +188,24 @@ def batch_leg(pb, torch, count, steps, precision):
             "status": code}
 
 
-def serve_leg(pb, torch, count, nmax, precision, load=0.8, seed=0):
-    """Serving workload: `count` requests (config-1 generator, triangles
-    log-uniform over 320..20 n_max^2, random kappa) arriving as a Poisson
-    process at `load` x the measured single-request service rate, submitted
-    to a continuous-batching server; latency = submit to completion."""
-    import numpy as np
-
+def serve_requests(count, nmax):
     import pbgen
     t0 = time.perf_counter()
     probs = [pbgen.serve_instance(i, n_hi=nmax) for i in range(count)]
     progress(f"serve: generated {count} requests in {time.perf_counter() - t0:.1f} s")
+    return probs
+
+
+def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0):
+    """Serving workload: the requests `probs` (config-1 generator, triangles
+    log-uniform over 320..20 n_max^2, random kappa) arriving as a Poisson
+    process at `load` x the measured single-request service rate, submitted
+    to a continuous-batching server; latency = submit to completion.  One run
+    per load; the service rate comes from solo solves of the first requests."""
+    import numpy as np
+
+    count = len(probs)
     ctx = pb.Context(0)
-    # service rate from solo solves of the first few requests
     svc = []
     for p in probs[:4]:
         g = pb.Problem.from_inputs(ctx, p, precision=precision)
@@ -210,46 +215,51 @@ def serve_leg(pb, torch, count, nmax, precision, load=0.8, seed=0):
         g.solve()
         svc.append(time.perf_counter() - ts)
         g.close()
-    rate = load / (sum(svc) / len(svc))
-    rng = np.random.default_rng([4, seed])
-    gaps = rng.exponential(1.0 / rate, size=count)
-    srv = pb.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=16)
-    gs = [pb.Problem.from_inputs(ctx, p, precision=precision) for p in probs]
-    submit, done, res = {}, {}, {}
-    tickets = []
-    start = time.perf_counter()
-    next_t = start
-    i = 0
-    while len(done) < count:
-        now = time.perf_counter()
-        while i < count and now >= next_t:
-            t = srv.submit(gs[i])
-            tickets.append(t)
-            submit[t] = time.perf_counter()
-            next_t += gaps[i]
-            i += 1
-        for t in tickets:
-            if t not in done:
-                r = srv.poll(t)
-                if r is not None:
-                    done[t] = time.perf_counter()
-                    res[t] = r
-        time.sleep(0.0005)
-    makespan = time.perf_counter() - start
-    srv.close()
-    for g in gs:
-        g.close()
+    out = {}
+    for load in loads:
+        rate = load / (sum(svc) / len(svc))
+        rng = np.random.default_rng([4, seed])
+        gaps = rng.exponential(1.0 / rate, size=count)
+        srv = pb.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=16)
+        gs = [pb.Problem.from_inputs(ctx, p, precision=precision) for p in probs]
+        submit, done, res = {}, {}, {}
+        tickets = []
+        start = time.perf_counter()
+        next_t = start
+        i = 0
+        while len(done) < count:
+            now = time.perf_counter()
+            while i < count and now >= next_t:
+                t = srv.submit(gs[i])
+                tickets.append(t)
+                submit[t] = time.perf_counter()
+                next_t += gaps[i]
+                i += 1
+            for t in tickets:
+                if t not in done:
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[t] = time.perf_counter()
+                        res[t] = r
+            time.sleep(0.0005)
+        makespan = time.perf_counter() - start
+        srv.close()
+        for g in gs:
+            g.close()
+        lat = [done[t] - submit[t] for t in tickets]
+        bad = sum(1 for t in tickets if res[t]["status"] != 0)
+        if bad:
+            raise RuntimeError(f"{bad} served requests failed")
+        progress(f"serve ({'mixed' if precision == pb.MIXED else 'fp64'}, load {load}): {count} requests in "
+                 f"{makespan:.2f} s, p50 {percentile(lat, 0.5):.3f} s, p99 {percentile(lat, 0.99):.3f} s")
+        out[f"load_{load}"] = {"arrival_rate_per_s": rate, "load": load, "value": count / makespan,
+                               "unit": "PB solves/s",
+                               "latency_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
+                               "failures": bad}
     ctx.close()
-    lat = [done[t] - submit[t] for t in tickets]
-    bad = sum(1 for t in tickets if res[t]["status"] != 0)
-    if bad:
-        raise RuntimeError(f"{bad} served requests failed")
-    progress(f"serve ({'mixed' if precision == pb.MIXED else 'fp64'}): {count} requests in {makespan:.2f} s, "
-             f"p50 {percentile(lat, 0.5):.3f} s, p99 {percentile(lat, 0.99):.3f} s, failures {bad}")
-    return {"requests": count, "precision": "mixed" if precision == pb.MIXED else "fp64",
-            "arrival_rate_per_s": rate, "load": load, "value": count / makespan, "unit": "PB solves/s",
-            "latency_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)}, "failures": bad,
-            "max_triangles": 20 * nmax * nmax}
+    main = out["load_0.8"] if "load_0.8" in out else next(iter(out.values()))
+    return dict(main, requests=count, precision="mixed" if precision == pb.MIXED else "fp64",
+                max_triangles=20 * nmax * nmax, solo_service_s=sum(svc) / len(svc), by_load=out)
 
 
 def cpu_baseline(prob, applies_per_solve, seed=0):
@@ -420,8 +430,9 @@ def main():
         out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
                           "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}
     if args.serve > 0:
-        out["serving"] = {"mixed": serve_leg(pb, torch, args.serve, args.serve_nmax, pb.MIXED),
-                          "fp64": serve_leg(pb, torch, args.serve, args.serve_nmax, pb.FP64)}
+        reqs = serve_requests(args.serve, args.serve_nmax)
+        out["serving"] = {"mixed": serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED),
+                          "fp64": serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64)}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle, bounded sample)")
         t0 = time.perf_counter()

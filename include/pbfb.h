@@ -148,8 +148,21 @@ typedef struct {
     int hip_graph;       /* 1 (default): each Krylov step of a batch is captured once as a HIP graph and replayed;
                           * 0: kernels launched one by one (also the case while kernel timing is enabled or on
                           * a stream that cannot be captured).  Results are the same bit for bit */
+    int omega_method;    /* root finder of f_d (Sec. 2.5, the appendix on one-dimensional root finding):
+                          * PBFB_OMEGA_NEWTON (default): Newton-Raphson from omega0_first / omega0_next;
+                          * PBFB_OMEGA_BISECT: bisection of [omega_min, omega_max] (Newton from the
+                          *   start value when f_d keeps its sign over it);
+                          * PBFB_OMEGA_SECANT: secant from omega0 and omega0 + 1/8;
+                          * PBFB_OMEGA_BSEC: bisection in the first nonlinear iteration, secant after;
+                          * PBFB_OMEGA_NEWTON_BS: Newton, the first iteration starting from three
+                          *   bisection midpoints of [2, 3] and secant steps until two iterates differ
+                          *   by < 0.05 (the first-iteration start of the appendix on other
+                          *   optimisations).  pbfb_result.omega_iters counts f_d evaluations after
+                          *   the first */
 } pbfb_solve_opts;
 enum { PBFB_PC_DIAG = 0, PBFB_PC_CHEB_SPAI = 1 };
+enum { PBFB_OMEGA_NEWTON = 0, PBFB_OMEGA_BISECT = 1, PBFB_OMEGA_SECANT = 2, PBFB_OMEGA_BSEC = 3,
+       PBFB_OMEGA_NEWTON_BS = 4 };
 void pbfb_solve_opts_default(pbfb_solve_opts *o);
 
 typedef struct {

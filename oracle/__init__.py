@@ -25,10 +25,12 @@ class Opts(C.Structure):
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
                 ("max_gmres", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
-                ("cheb_ratio", C.c_double)]
+                ("cheb_ratio", C.c_double), ("omega_method", C.c_int)]
 
 
 PC_DIAG, PC_CHEB_SPAI = 0, 1
+OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS = 0, 1, 2, 3, 4
+FD_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double))
 
 
 class Result(C.Structure):
@@ -98,6 +100,9 @@ def lib():
         L.pbref_solve.argtypes = [P, C.POINTER(Opts), C.POINTER(Result), dp, dp]
         L.pbref_energy.argtypes = [P, dp, dp, dp]
         L.pbref_fd.argtypes = [P, C.c_int, dp, dp, C.c_double, dp]
+        L.pbref_root_find.argtypes = [C.c_int, C.c_int, C.c_double, FD_FN, P, C.POINTER(Opts),
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.pbref_root_find.restype = C.c_double
         L.pbref_omega_search.argtypes = [P, C.c_int, dp, dp, C.POINTER(Opts), dp, C.POINTER(C.c_int)]
         L.pbref_reaction_potential.argtypes = [P, dp, C.c_int64, dp, dp]
         L.pbref_rule_tri6.argtypes = [dp, dp]
@@ -169,6 +174,23 @@ def default_opts(**kw):
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def root_find(method, k, omega0, f, **opts):
+    """One root search of the oracle's f_d root finders on a Python function
+    f(omega) -> (f_d, f_d') (None for an undefined value).  Returns (omega,
+    evaluations, fallback)."""
+    def cb(_ctx, w, fd, dfd):
+        v = f(w)
+        if v is None:
+            return 1
+        fd[0], dfd[0] = float(v[0]), float(v[1])
+        return 0
+    fn = FD_FN(cb)
+    o = default_opts(**opts)
+    ev, fb = C.c_int(0), C.c_int(0)
+    w = lib().pbref_root_find(method, k, omega0, fn, None, C.byref(o), C.byref(ev), C.byref(fb))
+    return w, ev.value, fb.value
 
 
 class Oracle:

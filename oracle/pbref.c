@@ -1650,6 +1650,7 @@ void pbref_opts_default(pbref_opts *o)
     o->precond = PBREF_PC_CHEB_SPAI;
     o->cheb_degree = 16;
     o->cheb_ratio = 200.0;
+    o->omega_method = PBREF_OMEGA_NEWTON;
 }
 
 static int all_finite(int64_t n, const double *x)
@@ -1691,38 +1692,190 @@ static int fd_eval(const pbref *p, int s, const double *phi, const double *c, co
     return 0;
 }
 
-/* Newton iteration on f_d from the starting value in *omega; clamped to
- * [omega_min, omega_max]; stops at |f_d| < tol_omega or max_omega_it. */
-static void omega_search(pbref *p, int s, const double *phi, const double *c, const double *D, const pbref_opts *o,
-                         double *omega_io, int *iters, int *fallback)
+/* ---- one-dimensional root finders of f_d -------------------------------- */
+static double clamp_omega(double w, const pbref_opts *o)
+{
+    if (w < o->omega_min) w = o->omega_min;
+    if (w > o->omega_max) w = o->omega_max;
+    return w;
+}
+
+/* Newton-Raphson on f_d from w (iterates clamped); stops at |f_d| < tol */
+static double root_newton(pbref_fd_fn f, void *ctx, double w, const pbref_opts *o, int *ev, int *fb)
+{
+    for (int j = 0; *ev < o->max_omega_it; ++j) {
+        double fd, dfd;
+        ++*ev;
+        if (f(ctx, w, &fd, &dfd)) {
+            *fb = 1;
+            return 1.0;
+        }
+        if (fabs(fd) < o->tol_omega) return w;
+        if (dfd == 0.0 || !isfinite(dfd)) {
+            *fb = 1;
+            return 1.0;
+        }
+        w = clamp_omega(w - fd / dfd, o);
+    }
+    return w;
+}
+
+/* secant on f_d from the pair (w0, w1); stops at |f_d| < tol */
+static double root_secant(pbref_fd_fn f, void *ctx, double w0, double w1, const pbref_opts *o, int *ev, int *fb)
+{
+    double f0, f1, d;
+    ++*ev;
+    if (f(ctx, w0, &f0, &d)) {
+        *fb = 1;
+        return 1.0;
+    }
+    if (fabs(f0) < o->tol_omega) return w0;
+    ++*ev;
+    if (f(ctx, w1, &f1, &d)) {
+        *fb = 1;
+        return 1.0;
+    }
+    while (fabs(f1) >= o->tol_omega && *ev < o->max_omega_it) {
+        const double den = f0 - f1;
+        if (den == 0.0 || !isfinite(den)) {
+            *fb = 1;
+            return 1.0;
+        }
+        const double w2 = clamp_omega(w0 - (w0 - w1) * f0 / den, o);
+        w0 = w1;
+        f0 = f1;
+        w1 = w2;
+        ++*ev;
+        if (f(ctx, w1, &f1, &d)) {
+            *fb = 1;
+            return 1.0;
+        }
+    }
+    return w1;
+}
+
+/* bisection of [lo, hi]; without a sign change of f_d over it the search
+ * continues with Newton from w_start */
+static double root_bisect(pbref_fd_fn f, void *ctx, double lo, double hi, double w_start, const pbref_opts *o,
+                          int *ev, int *fb)
+{
+    double flo, fhi, fm, d;
+    ++*ev;
+    if (f(ctx, lo, &flo, &d)) {
+        *fb = 1;
+        return 1.0;
+    }
+    if (fabs(flo) < o->tol_omega) return lo;
+    ++*ev;
+    if (f(ctx, hi, &fhi, &d)) {
+        *fb = 1;
+        return 1.0;
+    }
+    if (fabs(fhi) < o->tol_omega) return hi;
+    if ((flo > 0.0) == (fhi > 0.0)) return root_newton(f, ctx, w_start, o, ev, fb);
+    double mid = 0.5 * (lo + hi);
+    while (*ev < o->max_omega_it) {
+        mid = 0.5 * (lo + hi);
+        ++*ev;
+        if (f(ctx, mid, &fm, &d)) {
+            *fb = 1;
+            return 1.0;
+        }
+        if (fabs(fm) < o->tol_omega) return mid;
+        if ((fm > 0.0) == (flo > 0.0)) {
+            lo = mid;
+            flo = fm;
+        } else {
+            hi = mid;
+        }
+    }
+    return mid;
+}
+
+/* start value of the first-iteration Newton search: three bisection
+ * midpoints of [2, 3] (f_d decreases through its root: a positive value
+ * moves the search up), then secant steps from the last two until two
+ * successive iterates differ by less than 0.05 */
+static double guess_bisect_secant(pbref_fd_fn f, void *ctx, const pbref_opts *o, int *ev, int *fb)
+{
+    double lo = 2.0, hi = 3.0, w[3], fv[3], d;
+    for (int i = 0; i < 3; ++i) {
+        w[i] = 0.5 * (lo + hi);
+        ++*ev;
+        if (f(ctx, w[i], &fv[i], &d)) {
+            *fb = 1;
+            return 1.0;
+        }
+        if (fv[i] > 0.0) lo = w[i];
+        else hi = w[i];
+    }
+    double w0 = w[1], f0 = fv[1], w1 = w[2], f1 = fv[2];
+    while (*ev < o->max_omega_it) {
+        const double den = f0 - f1;
+        if (den == 0.0 || !isfinite(den)) break;
+        const double w2 = clamp_omega(w0 - (w0 - w1) * f0 / den, o);
+        if (fabs(w2 - w1) < 0.05) return w2;
+        w0 = w1;
+        f0 = f1;
+        w1 = w2;
+        ++*ev;
+        if (f(ctx, w1, &f1, &d)) {
+            *fb = 1;
+            return 1.0;
+        }
+    }
+    return w1;
+}
+
+double pbref_root_find(int method, int k, double omega0, pbref_fd_fn f, void *ctx, const pbref_opts *o,
+                       int *evals, int *fallback)
+{
+    *evals = 0;
+    *fallback = 0;
+    switch (method) {
+    case PBREF_OMEGA_BISECT: return root_bisect(f, ctx, o->omega_min, o->omega_max, omega0, o, evals, fallback);
+    case PBREF_OMEGA_SECANT: return root_secant(f, ctx, omega0, omega0 + 0.125, o, evals, fallback);
+    case PBREF_OMEGA_BSEC:
+        if (k == 1) return root_bisect(f, ctx, o->omega_min, o->omega_max, omega0, o, evals, fallback);
+        return root_secant(f, ctx, omega0, omega0 + 0.125, o, evals, fallback);
+    case PBREF_OMEGA_NEWTON_BS:
+        if (k == 1) {
+            const double w = guess_bisect_secant(f, ctx, o, evals, fallback);
+            if (*fallback) return w;
+            return root_newton(f, ctx, w, o, evals, fallback);
+        }
+        return root_newton(f, ctx, omega0, o, evals, fallback);
+    default: return root_newton(f, ctx, omega0, o, evals, fallback);
+    }
+}
+
+struct fd_ctx {
+    pbref *p;
+    int s;
+    const double *phi, *c, *D, *pv;
+    double *work;
+};
+
+static int fd_cb(void *vc, double w, double *fd, double *dfd)
+{
+    struct fd_ctx *x = vc;
+    return fd_eval(x->p, x->s, x->phi, x->c, x->D, x->pv, w, fd, dfd, x->work);
+}
+
+/* root of f_d for the step D at phi with the method of o, from *omega_io;
+ * *iters = f_d evaluations after the first (the Newton updates, for NEWTON) */
+static void omega_search(pbref *p, int s, int k, const double *phi, const double *c, const double *D,
+                         const pbref_opts *o, double *omega_io, int *iters, int *fallback)
 {
     int64_t n = nunk(p), nn = p->nn;
     double *pv = malloc(sizeof(double) * n);
     double *work = malloc(sizeof(double) * (2 * nn + 3 * n));
     pbref_apply_A(p, D, pv);
     for (int64_t i = 0; i < n; ++i) pv[i] = -pv[i];
-    double omega = *omega_io;
-    int it;
-    *fallback = 0;
-    for (it = 0; it < o->max_omega_it; ++it) {
-        double fd, dfd;
-        if (fd_eval(p, s, phi, c, D, pv, omega, &fd, &dfd, work)) {
-            omega = 1.0;
-            *fallback = 1;
-            break;
-        }
-        if (fabs(fd) < o->tol_omega) break;
-        if (dfd == 0.0 || !isfinite(dfd)) {
-            omega = 1.0;
-            *fallback = 1;
-            break;
-        }
-        omega -= fd / dfd;
-        if (omega < o->omega_min) omega = o->omega_min;
-        if (omega > o->omega_max) omega = o->omega_max;
-    }
-    *omega_io = omega;
-    *iters = it;
+    struct fd_ctx x = {p, s, phi, c, D, pv, work};
+    int ev = 0;
+    *omega_io = pbref_root_find(o->omega_method, k, *omega_io, fd_cb, &x, o, &ev, fallback);
+    *iters = ev > 0 ? ev - 1 : 0;
     free(pv);
     free(work);
 }
@@ -1758,7 +1911,7 @@ int pbref_omega_search(pbref *p, int scheme, const double *phi, const double *D,
     pbref_apply_A(p, phi, c);
     for (int64_t i = 0; i < n; ++i) c[i] = b[i] - c[i];
     int fb = 0;
-    omega_search(p, scheme, phi, c, D, o, omega, iters, &fb);
+    omega_search(p, scheme, 1, phi, c, D, o, omega, iters, &fb);
     free(b);
     free(c);
     return fb;
@@ -1817,7 +1970,7 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
         } else {
             omega = (s == PBREF_T3) ? o->omega0_first : o->omega0_next;
             int fb = 0;
-            omega_search(p, s, phi, c, D, o, &omega, &oit, &fb);
+            omega_search(p, s, k, phi, c, D, o, &omega, &oit, &fb);
             res->omega_fallback += fb;
             omega_last = omega;
         }

@@ -77,7 +77,28 @@ typedef struct {
     int max_newton, max_omega_it, gmres_restart, max_gmres;
     int precond, cheb_degree; /* PBREF_PC_*, Chebyshev terms of the FEM block */
     double cheb_ratio;        /* lmax / lower end of the Chebyshev interval */
+    int omega_method;         /* PBREF_OMEGA_*: root finder of f_d */
 } pbref_opts;
+
+/* Root finders of f_d(omega) = 0 (Sec. 2.5 and the appendix on one-dimensional
+ * root finding; the comparison of Sec. 4 and the first-iteration guess of the
+ * appendix on other optimisations):
+ *   NEWTON   Newton-Raphson from omega0 (omega0_first in a T3 iteration, else omega0_next)
+ *   BISECT   bisection of [omega_min, omega_max]
+ *   SECANT   secant from omega0 and omega0 + 1/8
+ *   BSEC     bisection in the first nonlinear iteration, secant afterwards
+ *   NEWTON_BS  Newton whose first-iteration start comes from three bisection
+ *            midpoints in [2, 3] followed by secant steps until two iterates
+ *            differ by less than 0.05 */
+enum { PBREF_OMEGA_NEWTON = 0, PBREF_OMEGA_BISECT = 1, PBREF_OMEGA_SECANT = 2, PBREF_OMEGA_BSEC = 3,
+       PBREF_OMEGA_NEWTON_BS = 4 };
+/* f(ctx, omega, &f_d, &f_d') returns nonzero when f_d is undefined (beta = 0) */
+typedef int (*pbref_fd_fn)(void *ctx, double omega, double *fd, double *dfd);
+/* One root search with a caller-supplied f_d: method, nonlinear iteration k
+ * (1-based) and the start value omega0; returns omega; *evals = number of f_d
+ * evaluations; *fallback = 1 when the search fell back to omega = 1. */
+double pbref_root_find(int method, int k, double omega0, pbref_fd_fn f, void *ctx, const pbref_opts *o,
+                       int *evals, int *fallback);
 
 enum { PBREF_PC_DIAG = 0, PBREF_PC_CHEB_SPAI = 1 };
 

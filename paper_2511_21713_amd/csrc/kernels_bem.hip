@@ -32,10 +32,15 @@
 
 namespace pbfb {
 
+// The 6-point rule is two orbits of 3 points: point k of orbit o has
+// barycentric coordinate beta_o at index k and alpha_o at the other two.  A
+// sum s_j = sum_q w_q b_q[j] g_q is then A_0 G_0 + A_1 G_1 + D_0 g_{0,j} +
+// D_1 g_{1,j} with G_o the orbit's sum of g, A_o = w_o alpha_o and D_o =
+// w_o (beta_o - alpha_o) (12 operations for the three j instead of 18).
 struct QRule6 {
     double b[6][3];
     double w[6];
-    double wb[6][3]; // w_q b_q[k]
+    double oA[2], oD[2];
 };
 struct GL4 {
     double x[4];
@@ -49,7 +54,16 @@ static QRule6 q6arg()
     for (int q = 0; q < 6; ++q) {
         for (int k = 0; k < 3; ++k) r.b[q][k] = R.tri_bary[q][k];
         r.w[q] = R.tri_w[q];
-        for (int k = 0; k < 3; ++k) r.wb[q][k] = R.tri_w[q] * R.tri_bary[q][k];
+    }
+    for (int o = 0; o < 2; ++o) {
+        // the orbit structure the regular kernel relies on
+        const double al = R.tri_bary[3 * o][1], be = R.tri_bary[3 * o][0];
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j)
+                PB_CHECK(R.tri_bary[3 * o + k][j] == (j == k ? be : al) && R.tri_w[3 * o + k] == R.tri_w[3 * o],
+                         PBFB_EDEVICE, "triangle rule is not two 3-point orbits");
+        r.oA[o] = R.tri_w[3 * o] * al;
+        r.oD[o] = R.tri_w[3 * o] * (be - al);
     }
     return r;
 }
@@ -102,16 +116,18 @@ __global__ void k_tri_morton(int64_t nt, const int32_t *__restrict__ morton, con
 // ---------------------------------------------------------------------------
 // 1. regular tiles
 // ---------------------------------------------------------------------------
-// quadrature weights times barycentric values, w_q * b_q[k], in FP32
+// the orbit factors of the 6-point rule in FP32
 struct QRule6F {
-    float wb[6][3];
+    float oA[2], oD[2];
 };
 static QRule6F q6farg()
 {
+    const QRule6 R = q6arg();
     QRule6F r;
-    const Rules &R = rules();
-    for (int q = 0; q < 6; ++q)
-        for (int k = 0; k < 3; ++k) r.wb[q][k] = float(R.tri_w[q] * R.tri_bary[q][k]);
+    for (int o = 0; o < 2; ++o) {
+        r.oA[o] = float(R.oA[o]);
+        r.oD[o] = float(R.oD[o]);
+    }
     return r;
 }
 
@@ -288,46 +304,49 @@ __global__ void __launch_bounds__(TA * TB, 4)
         const RT kap = RT(kappa);
         const double sc = sAa[tl] * sAb[sl] * INV4PI;
         // target point p outermost: 6-term source sums, then folded into the 3x3 blocks
-        // (not unrolled: the 6 source points of one target point are the unit of ILP)
+        // (not unrolled: the 6 source points of one target point are the unit of ILP).
+        // The source points lie in the plane of the source triangle, so the
+        // normal distance (x - y_q).n is the same for all six: it is taken
+        // once per target point (from source point 0) and factored out of
+        // the double-layer sum.
 #pragma unroll 1
         for (int p = 0; p < 6; ++p) {
             const RT x0 = sX[tl][3 * p] + c0, x1 = sX[tl][3 * p + 1] + c1, x2 = sX[tl][3 * p + 2] + c2;
-            RT sv0 = 0, sv1 = 0, sv2 = 0, sk0 = 0, sk1 = 0, sk2 = 0;
+            const RT dn = (x0 - sY[sl][0]) * n0 + (x1 - sY[sl][1]) * n1 + (x2 - sY[sl][2]) * n2;
+            RT gv[6], hk[6]; // single-layer kernel, double-layer kernel / (x - y).n
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-                RT wb0, wb1, wb2;
-                if constexpr (F32) {
-                    wb0 = RF.wb[q][0];
-                    wb1 = RF.wb[q][1];
-                    wb2 = RF.wb[q][2];
-                } else {
-                    wb0 = R.wb[q][0];
-                    wb1 = R.wb[q][1];
-                    wb2 = R.wb[q][2];
-                }
                 const RT d0 = x0 - sY[sl][3 * q], d1 = x1 - sY[sl][3 * q + 1], d2 = x2 - sY[sl][3 * q + 2];
                 const RT r2 = d0 * d0 + d1 * d1 + d2 * d2;
                 const RT ri = rsqrt_pos(r2);
-                const RT dn = d0 * n0 + d1 * n1 + d2 * n2;
-                RT gv, gk;
+                const RT ri3 = ri * ri * ri;
                 if (YUK) {
                     const RT r = r2 * ri;
                     RT e;
                     if constexpr (F32) e = __builtin_amdgcn_exp2f(-1.44269504088896341f * kap * r);
                     else e = exp(-kap * r);
-                    gv = e * ri;
-                    gk = dn * (RT(1) + kap * r) * e * ri * ri * ri;
+                    gv[q] = e * ri;
+                    hk[q] = (RT(1) + kap * r) * e * ri3;
                 } else {
-                    gv = ri;
-                    gk = dn * ri * ri * ri;
+                    gv[q] = ri;
+                    hk[q] = ri3;
                 }
-                sv0 += wb0 * gv;
-                sv1 += wb1 * gv;
-                sv2 += wb2 * gv;
-                sk0 += wb0 * gk;
-                sk1 += wb1 * gk;
-                sk2 += wb2 * gk;
             }
+            RT oA0, oA1, oD0, oD1;
+            if constexpr (F32) {
+                oA0 = RF.oA[0], oA1 = RF.oA[1], oD0 = RF.oD[0], oD1 = RF.oD[1];
+            } else {
+                oA0 = R.oA[0], oA1 = R.oA[1], oD0 = R.oD[0], oD1 = R.oD[1];
+            }
+            const RT cv = oA0 * (gv[0] + gv[1] + gv[2]) + oA1 * (gv[3] + gv[4] + gv[5]);
+            const RT ck = oA0 * (hk[0] + hk[1] + hk[2]) + oA1 * (hk[3] + hk[4] + hk[5]);
+            const RT sv0 = cv + oD0 * gv[0] + oD1 * gv[3], sv1 = cv + oD0 * gv[1] + oD1 * gv[4],
+                     sv2 = cv + oD0 * gv[2] + oD1 * gv[5];
+            RT sk0 = ck + oD0 * hk[0] + oD1 * hk[3], sk1 = ck + oD0 * hk[1] + oD1 * hk[4],
+               sk2 = ck + oD0 * hk[2] + oD1 * hk[5];
+            sk0 *= dn;
+            sk1 *= dn;
+            sk2 *= dn;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double wa = sc * R.w[p] * R.b[p][a];

@@ -173,6 +173,163 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// root of f_d (Sec. 2.5; the appendix on one-dimensional root finding and
+// the first-iteration start of the appendix on other optimisations).
+// Every method stops at |f_d| < tol_omega or after max_omega_it
+// evaluations; iterates are clamped to [omega_min, omega_max]; an undefined
+// f_d (beta = 0) or a vanishing derivative / secant slope gives omega = 1.
+// ---------------------------------------------------------------------------
+static double clampw(double w, const pbfb_solve_opts &o) { return std::min(o.omega_max, std::max(o.omega_min, w)); }
+
+template <class F>
+static double omega_newton(const pbfb_solve_opts &o, F &f, double w, int &ev, bool &fb)
+{
+    while (ev < o.max_omega_it) {
+        double fd = 0.0, dfd = 0.0;
+        ++ev;
+        if (!f(w, fd, dfd)) {
+            fb = true;
+            return 1.0;
+        }
+        if (std::fabs(fd) < o.tol_omega) return w;
+        if (dfd == 0.0 || !std::isfinite(dfd)) {
+            fb = true;
+            return 1.0;
+        }
+        w = clampw(w - fd / dfd, o);
+    }
+    return w;
+}
+
+// secant from the pair (w0, w1)
+template <class F>
+static double omega_secant(const pbfb_solve_opts &o, F &f, double w0, double w1, int &ev, bool &fb)
+{
+    double f0 = 0.0, f1 = 0.0, d = 0.0;
+    ++ev;
+    if (!f(w0, f0, d)) {
+        fb = true;
+        return 1.0;
+    }
+    if (std::fabs(f0) < o.tol_omega) return w0;
+    ++ev;
+    if (!f(w1, f1, d)) {
+        fb = true;
+        return 1.0;
+    }
+    while (std::fabs(f1) >= o.tol_omega && ev < o.max_omega_it) {
+        const double slope = f0 - f1;
+        if (slope == 0.0 || !std::isfinite(slope)) {
+            fb = true;
+            return 1.0;
+        }
+        const double w2 = clampw(w0 - (w0 - w1) * f0 / slope, o);
+        w0 = w1;
+        f0 = f1;
+        w1 = w2;
+        ++ev;
+        if (!f(w1, f1, d)) {
+            fb = true;
+            return 1.0;
+        }
+    }
+    return w1;
+}
+
+// bisection of [lo, hi]; Newton from w_start when f_d keeps its sign over it
+template <class F>
+static double omega_bisect(const pbfb_solve_opts &o, F &f, double lo, double hi, double w_start, int &ev, bool &fb)
+{
+    double flo = 0.0, fhi = 0.0, d = 0.0;
+    ++ev;
+    if (!f(lo, flo, d)) {
+        fb = true;
+        return 1.0;
+    }
+    if (std::fabs(flo) < o.tol_omega) return lo;
+    ++ev;
+    if (!f(hi, fhi, d)) {
+        fb = true;
+        return 1.0;
+    }
+    if (std::fabs(fhi) < o.tol_omega) return hi;
+    if ((flo > 0.0) == (fhi > 0.0)) return omega_newton(o, f, w_start, ev, fb);
+    double mid = 0.5 * (lo + hi);
+    while (ev < o.max_omega_it) {
+        mid = 0.5 * (lo + hi);
+        double fm = 0.0;
+        ++ev;
+        if (!f(mid, fm, d)) {
+            fb = true;
+            return 1.0;
+        }
+        if (std::fabs(fm) < o.tol_omega) return mid;
+        if ((fm > 0.0) == (flo > 0.0)) {
+            lo = mid;
+            flo = fm;
+        } else {
+            hi = mid;
+        }
+    }
+    return mid;
+}
+
+// first-iteration start: three bisection midpoints of [2, 3] (a positive
+// f_d moves up: f_d decreases through its root), then secant steps from the
+// last two until successive iterates differ by less than 0.05
+template <class F> static double omega_start_bs(const pbfb_solve_opts &o, F &f, int &ev, bool &fb)
+{
+    double lo = 2.0, hi = 3.0, w[3], fv[3], d = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        w[i] = 0.5 * (lo + hi);
+        ++ev;
+        if (!f(w[i], fv[i], d)) {
+            fb = true;
+            return 1.0;
+        }
+        if (fv[i] > 0.0) lo = w[i];
+        else hi = w[i];
+    }
+    double w0 = w[1], f0 = fv[1], w1 = w[2], f1 = fv[2];
+    while (ev < o.max_omega_it) {
+        const double slope = f0 - f1;
+        if (slope == 0.0 || !std::isfinite(slope)) break;
+        const double w2 = clampw(w0 - (w0 - w1) * f0 / slope, o);
+        if (std::fabs(w2 - w1) < 0.05) return w2;
+        w0 = w1;
+        f0 = f1;
+        w1 = w2;
+        ++ev;
+        if (!f(w1, f1, d)) {
+            fb = true;
+            return 1.0;
+        }
+    }
+    return w1;
+}
+
+// the root finder of opts.omega_method at nonlinear iteration k (1-based)
+template <class F>
+static double omega_root(const pbfb_solve_opts &o, int k, double omega0, F &f, int &ev, bool &fb)
+{
+    switch (o.omega_method) {
+    case PBFB_OMEGA_BISECT: return omega_bisect(o, f, o.omega_min, o.omega_max, omega0, ev, fb);
+    case PBFB_OMEGA_SECANT: return omega_secant(o, f, omega0, omega0 + 0.125, ev, fb);
+    case PBFB_OMEGA_BSEC:
+        if (k == 1) return omega_bisect(o, f, o.omega_min, o.omega_max, omega0, ev, fb);
+        return omega_secant(o, f, omega0, omega0 + 0.125, ev, fb);
+    case PBFB_OMEGA_NEWTON_BS:
+        if (k == 1) {
+            const double w = omega_start_bs(o, f, ev, fb);
+            if (fb) return w;
+            return omega_newton(o, f, w, ev, fb);
+        }
+        return omega_newton(o, f, omega0, ev, fb);
+    default: return omega_newton(o, f, omega0, ev, fb);
+    }
+}
+
 // omega search and update after the Newton linear solve; true when converged
 static bool newton_post(NewtonRun &r, hipStream_t s)
 {
@@ -187,15 +344,16 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
     } else if (r.frozen) {
         omega = r.omega_last;
     } else {
-        omega = r.sch == PBFB_T3 ? o.omega0_first : o.omega0_next;
+        const double omega0 = r.sch == PBFB_T3 ? o.omega0_first : o.omega0_next;
         // p = -A Delta
         coupled_apply_linear(p, r.D, r.pv, s);
         r.res->applies += 1;
         vec_axpby(n, -1.0, r.pv, 0.0, r.pv, s);
         const double pp = dot(p, r.pv, r.pv, n, s);
         PB_HIP(hipMemcpyAsync(r.rv, r.c, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        for (oit = 0; oit < o.max_omega_it; ++oit) {
-            fem_omega_terms(p, r.sch, r.phi, r.D, omega, r.rN, r.rJ, r.rH, s);
+        // f_d(omega) and f_d'(omega) (eq. fd=0 and its derivative); false when beta = 0
+        auto fd_at = [&](double w, double &fd, double &dfd) {
+            fem_omega_terms(p, r.sch, r.phi, r.D, w, r.rN, r.rJ, r.rH, s);
             hipLaunchKernelGGL(k_sub_fem, dim3(nbk(nn, 256)), dim3(256), 0, s, nn, r.c, r.rN, r.rv);
             const double pr = dot(p, r.pv, r.rv, n, s);
             const double *A5[5] = {r.rJ, r.rJ, r.rJ, r.rv, r.pv};
@@ -203,22 +361,17 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
             double v5[5];
             dots(p, 5, A5, B5, nn, v5, s);
             // r' = -[rJ; 0; 0], r'' = -[rH; 0; 0]
-            const double a = pr - v5[0];     // (p + r').r
-            const double beta = pp - v5[1];  // (p + r').p
-            if (beta == 0.0) {
-                omega = 1.0;
-                break;
-            }
-            const double fd = -a / beta - omega;
-            if (std::fabs(fd) < o.tol_omega) break;
-            const double dfd = -(-v5[1] + v5[2] - v5[3]) / beta + a * (-v5[4]) / (beta * beta) - 1.0;
-            if (dfd == 0.0 || !std::isfinite(dfd)) {
-                omega = 1.0;
-                break;
-            }
-            omega -= fd / dfd;
-            omega = std::min(o.omega_max, std::max(o.omega_min, omega));
-        }
+            const double a = pr - v5[0];    // (p + r').r
+            const double beta = pp - v5[1]; // (p + r').p
+            if (beta == 0.0) return false;
+            fd = -a / beta - w;
+            dfd = -(-v5[1] + v5[2] - v5[3]) / beta + a * (-v5[4]) / (beta * beta) - 1.0;
+            return true;
+        };
+        int evals = 0;
+        bool fallback = false;
+        omega = omega_root(o, r.k, omega0, fd_at, evals, fallback);
+        oit = evals > 0 ? evals - 1 : 0;
         r.omega_last = omega;
     }
     vec_axpby(n, omega, r.D, 1.0, r.phinl, s);

@@ -137,6 +137,24 @@ def test_paper_tolerance_solve_iterates_like_oracle(case, pc):
     assert abs(rg["total"] - ro["total"]) < 1e-6 * abs(ro["total"])
 
 
+@pytest.mark.parametrize("method", [1, 2, 3, 4])
+def test_omega_root_finders_iterate_like_oracle(case, method):
+    """Bisection, secant, bisection-then-secant and the bisection/secant start
+    of the first Newton search for the relaxation factor, at the App. B
+    settings: the same Newton steps, the same number of f_d evaluations per
+    step and the same factors as the oracle."""
+    name, prob, o, g = case
+    rg = g.solve(omega_method=method)
+    ro, _, _ = o.solve(omega_method=method)
+    log(f"  {name} method {method}: gpu it {rg['newton_iters']} omega {rg['omega']} evals {rg['omega_iters']}; "
+        f"oracle omega {ro['omega']} evals {ro['omega_iters']}")
+    assert rg["status"] == 0 and ro["status"] == 0
+    assert rg["newton_iters"] == ro["newton_iters"]
+    assert rg["omega_iters"] == ro["omega_iters"]
+    assert np.allclose(rg["omega"], ro["omega"], atol=1e-6)
+    assert abs(rg["total"] - ro["total"]) < 1e-6 * abs(ro["total"])
+
+
 def test_mixed_precision_matches_oracle(case, ctx):
     """Mixed precision: regular panel pairs evaluated in FP32 (FP64 pair
     blocks and gathers), operators stored in FP32, FP32 Krylov basis inside
