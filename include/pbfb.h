@@ -157,12 +157,23 @@ typedef struct {
                           * PBFB_OMEGA_NEWTON_BS: Newton, the first iteration starting from three
                           *   bisection midpoints of [2, 3] and secant steps until two iterates differ
                           *   by < 0.05 (the first-iteration start of the appendix on other
-                          *   optimisations).  pbfb_result.omega_iters counts f_d evaluations after
+                          *   optimisations);
+                          * PBFB_OMEGA_BSEC_DF: bisection in the first nonlinear iteration, afterwards
+                          *   the direct secant formula omega = w0 / (1 - f_d(w0)), w0 = 1/8 (f_d(0) = 1
+                          *   in a Picard step).  pbfb_result.omega_iters counts f_d evaluations after
                           *   the first */
+    int nonlinear_method; /* PBFB_NEWTON (default): (A + J_N) Delta = d (eq. NR_main);
+                          * PBFB_PICARD: A Delta = d, Delta = intermediate estimate - Phi_NL
+                          *   (eqs. Ec_NL_Previo2, Ec_NL_Previo3); the paper searches omega in [0, 1]
+                          *   for Picard: set omega_max = 1 */
+    double r_e;          /* Picard: the relaxation factor is searched again only when e_{k-2}/e_{k-1} < r_e
+                          * (the norm-ratio rule of the section on reducing omega searches; 1.4; 0: every
+                          * step) */
 } pbfb_solve_opts;
 enum { PBFB_PC_DIAG = 0, PBFB_PC_CHEB_SPAI = 1 };
 enum { PBFB_OMEGA_NEWTON = 0, PBFB_OMEGA_BISECT = 1, PBFB_OMEGA_SECANT = 2, PBFB_OMEGA_BSEC = 3,
-       PBFB_OMEGA_NEWTON_BS = 4 };
+       PBFB_OMEGA_NEWTON_BS = 4, PBFB_OMEGA_BSEC_DF = 5 };
+enum { PBFB_NEWTON = 0, PBFB_PICARD = 1 };
 void pbfb_solve_opts_default(pbfb_solve_opts *o);
 
 typedef struct {

@@ -25,11 +25,14 @@ class Opts(C.Structure):
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
                 ("max_gmres", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
-                ("cheb_ratio", C.c_double), ("omega_method", C.c_int)]
+                ("cheb_ratio", C.c_double), ("omega_method", C.c_int), ("nonlinear_method", C.c_int),
+                ("r_e", C.c_double)]
 
 
 PC_DIAG, PC_CHEB_SPAI = 0, 1
-OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS = 0, 1, 2, 3, 4
+OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS, OMEGA_BSEC_DF = 0, 1, 2, 3, 4, 5
+NEWTON, PICARD = 0, 1
+NONE = 3  # scheme without reaction term (the Picard linear operator)
 FD_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double))
 
 

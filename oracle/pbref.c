@@ -809,16 +809,20 @@ static void tet_geom(const pbref *p, int64_t t, double grad[4][3], double *vol)
     *vol = p->tvol[t];
 }
 
-/* Scheme functions: N, N', N'' for LIN (t), T3 (t + t^3/6), HS (sinh t). */
+/* Scheme functions: N, N', N'' for LIN (t), T3 (t + t^3/6), HS (sinh t);
+ * NONE has no reaction term. */
 static double sch_f(int s, double t)
 {
-    return s == PBREF_LIN ? t : s == PBREF_T3 ? t + t * t * t / 6.0 : sinh(t);
+    return s == PBREF_NONE ? 0.0 : s == PBREF_LIN ? t : s == PBREF_T3 ? t + t * t * t / 6.0 : sinh(t);
 }
 static double sch_d1(int s, double t)
 {
-    return s == PBREF_LIN ? 1.0 : s == PBREF_T3 ? 1.0 + 0.5 * t * t : cosh(t);
+    return s == PBREF_NONE ? 0.0 : s == PBREF_LIN ? 1.0 : s == PBREF_T3 ? 1.0 + 0.5 * t * t : cosh(t);
 }
-static double sch_d2(int s, double t) { return s == PBREF_LIN ? 0.0 : s == PBREF_T3 ? t : sinh(t); }
+static double sch_d2(int s, double t)
+{
+    return s == PBREF_NONE ? 0.0 : s == PBREF_LIN ? 0.0 : s == PBREF_T3 ? t : sinh(t);
+}
 
 void pbref_stiffness_entries(const pbref *p, int32_t *rows, int32_t *cols, double *vals)
 {
@@ -1651,6 +1655,8 @@ void pbref_opts_default(pbref_opts *o)
     o->cheb_degree = 16;
     o->cheb_ratio = 200.0;
     o->omega_method = PBREF_OMEGA_NEWTON;
+    o->nonlinear_method = PBREF_NEWTON;
+    o->r_e = 1.4;
 }
 
 static int all_finite(int64_t n, const double *x)
@@ -1845,6 +1851,18 @@ double pbref_root_find(int method, int k, double omega0, pbref_fd_fn f, void *ct
             return root_newton(f, ctx, w, o, evals, fallback);
         }
         return root_newton(f, ctx, omega0, o, evals, fallback);
+    case PBREF_OMEGA_BSEC_DF:
+        if (k == 1) return root_bisect(f, ctx, o->omega_min, o->omega_max, omega0, o, evals, fallback);
+        {
+            const double w0 = 0.125;
+            double f0, d;
+            ++*evals;
+            if (f(ctx, w0, &f0, &d) || f0 == 1.0 || !isfinite(f0)) {
+                *fallback = 1;
+                return 1.0;
+            }
+            return clamp_omega(w0 / (1.0 - f0), o);
+        }
     default: return root_newton(f, ctx, omega0, o, evals, fallback);
     }
 }
@@ -1936,7 +1954,7 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
     res->gmres_iters_total = it;
     memset(phi_nl, 0, sizeof(double) * n);
     int frozen = 0, status = st;
-    double omega_last = 1.0;
+    double omega_last = 1.0, e_km1 = 0.0, e_km2 = 0.0; /* e of the two previous steps */
     int k;
     for (k = 1; k <= o->max_newton && status == 0; ++k) {
         int s = (k == 1 && o->scheme_first == PBREF_T3) ? PBREF_T3 : PBREF_HS;
@@ -1951,8 +1969,10 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
             status = -7;
             break;
         }
-        /* J_s(Phi) Delta = d */
-        st = pbref_gmres_pc(p, s, phi, d, D, tol, o->gmres_restart, o->max_gmres, o->precond, o->cheb_degree,
+        /* Newton: J_s(Phi) Delta = d (eq. NR_main); Picard: A Delta = d, Delta =
+         * the intermediate estimate minus Phi_NL (eq. Ec_NL_Previo2) */
+        const int lin = o->nonlinear_method == PBREF_PICARD ? PBREF_NONE : s;
+        st = pbref_gmres_pc(p, lin, phi, d, D, tol, o->gmres_restart, o->max_gmres, o->precond, o->cheb_degree,
                             o->cheb_ratio, &it);
         int idx = k - 1 < 64 ? k - 1 : 63;
         res->gmres_iters[idx] = it;
@@ -1967,6 +1987,8 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
             omega = o->omega_fixed;
         } else if (frozen) {
             omega = omega_last;
+        } else if (o->nonlinear_method == PBREF_PICARD && o->r_e > 0 && k >= 3 && e_km2 >= o->r_e * e_km1) {
+            omega = omega_last; /* e_{k-2} / e_{k-1} >= R_e: converging fast enough, reuse */
         } else {
             omega = (s == PBREF_T3) ? o->omega0_first : o->omega0_next;
             int fb = 0;
@@ -1979,6 +2001,8 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
         res->omega[idx] = omega;
         res->e_k[idx] = ek;
         res->omega_iters[idx] = oit;
+        e_km2 = e_km1;
+        e_km1 = ek;
         if (!isfinite(ek)) {
             status = -7;
             break;

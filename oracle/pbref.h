@@ -21,6 +21,8 @@ extern "C" {
 typedef struct pbref pbref;
 
 enum { PBREF_LIN = 0, PBREF_T3 = 1, PBREF_HS = 2 };
+/* no reaction term (N = J = H = 0): the linear operator A of the Picard step */
+enum { PBREF_NONE = 3 };
 
 /* quadrature rules (weights normalised to sum 1 over the reference cell) */
 int pbref_rule_tri6(double *bary /*6x3*/, double *w /*6*/);
@@ -78,7 +80,12 @@ typedef struct {
     int precond, cheb_degree; /* PBREF_PC_*, Chebyshev terms of the FEM block */
     double cheb_ratio;        /* lmax / lower end of the Chebyshev interval */
     int omega_method;         /* PBREF_OMEGA_*: root finder of f_d */
+    int nonlinear_method;     /* PBREF_NEWTON or PBREF_PICARD (Sec. 2.4.2) */
+    double r_e;               /* Picard: the relaxation factor is searched again only when
+                               * e_{k-2} / e_{k-1} < r_e (0: at every step) */
 } pbref_opts;
+
+enum { PBREF_NEWTON = 0, PBREF_PICARD = 1 };
 
 /* Root finders of f_d(omega) = 0 (Sec. 2.5 and the appendix on one-dimensional
  * root finding; the comparison of Sec. 4 and the first-iteration guess of the
@@ -89,9 +96,12 @@ typedef struct {
  *   BSEC     bisection in the first nonlinear iteration, secant afterwards
  *   NEWTON_BS  Newton whose first-iteration start comes from three bisection
  *            midpoints in [2, 3] followed by secant steps until two iterates
- *            differ by less than 0.05 */
+ *            differ by less than 0.05
+ *   BSEC_DF  bisection in the first nonlinear iteration, afterwards the
+ *            direct secant formula from omega = 0 (where f_d = 1 in a Picard
+ *            step) and omega = 1/8: omega0 / (1 - f_d(omega0)), one evaluation */
 enum { PBREF_OMEGA_NEWTON = 0, PBREF_OMEGA_BISECT = 1, PBREF_OMEGA_SECANT = 2, PBREF_OMEGA_BSEC = 3,
-       PBREF_OMEGA_NEWTON_BS = 4 };
+       PBREF_OMEGA_NEWTON_BS = 4, PBREF_OMEGA_BSEC_DF = 5 };
 /* f(ctx, omega, &f_d, &f_d') returns nonzero when f_d is undefined (beta = 0) */
 typedef int (*pbref_fd_fn)(void *ctx, double omega, double *fd, double *dfd);
 /* One root search with a caller-supplied f_d: method, nonlinear iteration k

@@ -18,7 +18,8 @@ OK, EINVAL, EMESH, ECHARGE, ENOMEM, EDEVICE, ENOTCONV, ENAN, ESTATE = 0, -1, -2,
 FP64, MIXED = 0, 1
 LIN, T3, HS = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
-OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS = 0, 1, 2, 3, 4
+OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS, OMEGA_BSEC_DF = 0, 1, 2, 3, 4, 5
+NEWTON, PICARD = 0, 1
 T_APPLY, T_GEMV, T_SPMV, T_ASM, T_SING = 0, 1, 2, 3, 4
 
 EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_problem_create", "pbfb_problem_destroy",
@@ -42,7 +43,8 @@ class SolveOpts(C.Structure):
                 ("omega0_next", C.c_double), ("omega_min", C.c_double), ("omega_max", C.c_double),
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
                 ("max_gmres", C.c_int), ("krylov_fp32", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
-                ("cheb_ratio", C.c_double), ("hip_graph", C.c_int), ("omega_method", C.c_int)]
+                ("cheb_ratio", C.c_double), ("hip_graph", C.c_int), ("omega_method", C.c_int),
+                ("nonlinear_method", C.c_int), ("r_e", C.c_double)]
 
 
 class Result(C.Structure):

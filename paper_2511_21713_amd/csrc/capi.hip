@@ -504,6 +504,8 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->cheb_ratio = 200.0;
     o->hip_graph = 1;
     o->omega_method = PBFB_OMEGA_NEWTON;
+    o->nonlinear_method = PBFB_NEWTON;
+    o->r_e = 1.4;
 }
 
 } // extern "C"
@@ -516,9 +518,11 @@ void check_opts(const pbfb_solve_opts &O)
     PB_CHECK((O.precond == PBFB_PC_DIAG || O.precond == PBFB_PC_CHEB_SPAI) && O.cheb_degree >= 1 &&
                  O.cheb_degree <= 64 && O.cheb_ratio > 1.0,
              PBFB_EINVAL, "bad preconditioner options");
-    PB_CHECK(O.omega_method >= PBFB_OMEGA_NEWTON && O.omega_method <= PBFB_OMEGA_NEWTON_BS &&
+    PB_CHECK(O.omega_method >= PBFB_OMEGA_NEWTON && O.omega_method <= PBFB_OMEGA_BSEC_DF &&
                  O.omega_min <= O.omega_max && O.max_omega_it >= 1,
              PBFB_EINVAL, "bad relaxation-search options");
+    PB_CHECK((O.nonlinear_method == PBFB_NEWTON || O.nonlinear_method == PBFB_PICARD) && O.r_e >= 0.0, PBFB_EINVAL,
+             "bad nonlinear-iteration options");
 }
 } // namespace pbfb
 

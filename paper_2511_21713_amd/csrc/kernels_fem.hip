@@ -255,8 +255,9 @@ __global__ void __launch_bounds__(128)
 }
 
 // d_val = d_val0 + J_scheme(u) on the u columns of each FEM row, from the
-// element blocks (16 per tet), row by row; the copy covers the slice
-// padding (zero in d_val0) and is coalesced across the rows of a slice
+// element blocks (16 per tet), row by row (Jt null: d_val = d_val0, the
+// operator without reaction term); the copy covers the slice padding (zero
+// in d_val0) and is coalesced across the rows of a slice
 __global__ void k_jacobian(int64_t nn, const int32_t *__restrict__ sptr, const double *__restrict__ val0,
                            double *__restrict__ val, float *__restrict__ val32, const int32_t *__restrict__ n2t_ptr,
                            const int32_t *__restrict__ n2t, const int32_t *__restrict__ slot4,
@@ -267,11 +268,12 @@ __global__ void k_jacobian(int64_t nn, const int32_t *__restrict__ sptr, const d
     const int64_t q = a / SLICE;
     const int32_t b0 = sptr[q] + int32_t(a - q * SLICE), b1 = sptr[q + 1];
     for (int32_t s = b0; s < b1; s += SLICE) val[s] = val0[s];
-    for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
-        const int64_t t = n2t[e] >> 2;
-        const int la = n2t[e] & 3;
-        for (int b = 0; b < 4; ++b) val[slot4[4 * int64_t(e) + b]] += Jt[16 * t + 4 * la + b];
-    }
+    if (Jt)
+        for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
+            const int64_t t = n2t[e] >> 2;
+            const int la = n2t[e] & 3;
+            for (int b = 0; b < 4; ++b) val[slot4[4 * int64_t(e) + b]] += Jt[16 * t + 4 * la + b];
+        }
     if (val32)
         for (int32_t s = b0; s < b1; s += SLICE) val32[s] = float(val[s]);
 }
@@ -619,6 +621,14 @@ void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t 
                        u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), Jt);
     hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_sptr, p.d_val0, p.d_val,
                        p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, Jt);
+    PB_HIP(hipGetLastError());
+}
+
+// FEM values of the coupled operator without reaction term (the Picard step)
+void fem_assemble_linear(Problem &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_sptr, p.d_val0, p.d_val,
+                       p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, (const double *)nullptr);
     PB_HIP(hipGetLastError());
 }
 

@@ -257,6 +257,7 @@ void ensure_all(Problem &p, hipStream_t s);
 
 // FEM element kernels (row gather over the tets around each node)
 void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t s); // d_val = A + J(u)
+void fem_assemble_linear(Problem &p, hipStream_t s);                                  // d_val = A
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s);
 void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN,
                      double *rJ, double *rH, hipStream_t s);
@@ -306,6 +307,7 @@ struct NewtonRun {
     double *phi_out_dev;
     int phase = 0, k = 0, sch = PBFB_HS, status = 0;
     double tol = 0.0, omega_last = 1.0;
+    double e_km1 = 0.0, e_km2 = 0.0; // e of the two previous nonlinear steps
     bool frozen = false;
     double *phil = nullptr, *phinl = nullptr, *phi = nullptr, *c = nullptr, *d = nullptr, *D = nullptr;
     double *pv = nullptr, *rv = nullptr, *rN = nullptr, *rJ = nullptr, *rH = nullptr, *dinv = nullptr;

@@ -167,7 +167,9 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
         r.status = PBFB_ENAN;
         return false;
     }
-    fem_assemble_jacobian(p, r.sch, r.phi, s);
+    // Newton: (A + J_N) Delta = d; Picard: A Delta = d
+    if (r.o.nonlinear_method == PBFB_PICARD) fem_assemble_linear(p, s);
+    else fem_assemble_jacobian(p, r.sch, r.phi, s);
     r.job = make_job(r, r.d, r.D, s);
     r.res->applies += 1; // c = b - A Phi
     return true;
@@ -326,6 +328,19 @@ static double omega_root(const pbfb_solve_opts &o, int k, double omega0, F &f, i
             return omega_newton(o, f, w, ev, fb);
         }
         return omega_newton(o, f, omega0, ev, fb);
+    case PBFB_OMEGA_BSEC_DF:
+        if (k == 1) return omega_bisect(o, f, o.omega_min, o.omega_max, omega0, ev, fb);
+        {
+            // the secant through (0, 1) and (w0, f_d(w0)): f_d(0) = 1 in a Picard step
+            const double w0 = 0.125;
+            double f0 = 0.0, d = 0.0;
+            ++ev;
+            if (!f(w0, f0, d) || f0 == 1.0 || !std::isfinite(f0)) {
+                fb = true;
+                return 1.0;
+            }
+            return clampw(w0 / (1.0 - f0), o);
+        }
     default: return omega_newton(o, f, omega0, ev, fb);
     }
 }
@@ -343,6 +358,8 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
         omega = o.omega_fixed;
     } else if (r.frozen) {
         omega = r.omega_last;
+    } else if (o.nonlinear_method == PBFB_PICARD && o.r_e > 0 && r.k >= 3 && r.e_km2 >= o.r_e * r.e_km1) {
+        omega = r.omega_last; // e_{k-2} / e_{k-1} >= R_e: converging fast enough, reuse
     } else {
         const double omega0 = r.sch == PBFB_T3 ? o.omega0_first : o.omega0_next;
         // p = -A Delta
@@ -379,6 +396,8 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
     r.res->omega[idx] = omega;
     r.res->e_k[idx] = ek;
     r.res->omega_iters[idx] = oit;
+    r.e_km2 = r.e_km1;
+    r.e_km1 = ek;
     if (!std::isfinite(ek)) {
         r.status = PBFB_ENAN;
         return true;

@@ -155,6 +155,27 @@ def test_omega_root_finders_iterate_like_oracle(case, method):
     assert abs(rg["total"] - ro["total"]) < 1e-6 * abs(ro["total"])
 
 
+def test_picard_iterates_like_oracle(case):
+    """Picard iteration (A Delta = d) with the direct-secant relaxation search
+    and the norm-ratio reuse rule, omega in [0, 1]: the same steps and factors
+    as the oracle at the App. B tolerances, and the same energy as Newton at
+    tight ones."""
+    name, prob, o, g = case
+    kw = dict(nonlinear_method=1, omega_method=5, omega_max=1.0, l_e=0.0, max_newton=200)
+    rg = g.solve(**kw)
+    ro, _, _ = o.solve(**kw)
+    log(f"  {name} picard: gpu it {rg['newton_iters']} omega {np.round(rg['omega'], 4)}; oracle it {ro['newton_iters']}")
+    assert rg["status"] == 0 and ro["status"] == 0
+    assert rg["newton_iters"] == ro["newton_iters"] and rg["omega_iters"] == ro["omega_iters"]
+    assert np.allclose(rg["omega"], ro["omega"], atol=1e-6)
+    tight = dict(kw, omega_method=1, tol_nl=1e-9, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, max_omega_it=200,
+                 max_gmres=20000)
+    rg = g.solve(**tight)
+    ro, _, _ = o.solve(**tight)
+    assert rg["status"] == 0
+    assert abs(rg["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
+
+
 def test_mixed_precision_matches_oracle(case, ctx):
     """Mixed precision: regular panel pairs evaluated in FP32 (FP64 pair
     blocks and gathers), operators stored in FP32, FP32 Krylov basis inside

@@ -125,3 +125,70 @@ def test_every_finder_reaches_the_same_solution():
         assert r["newton_iters"] == ref["newton_iters"], m
         assert np.allclose(r["omega"][:-1], ref["omega"][:-1], rtol=0, atol=1e-7), (m, r["omega"], ref["omega"])
         assert abs(r["total"] - ref["total"]) < 1e-9 * abs(ref["total"])
+
+
+# ---------------------------------------------------------------------------
+# Picard iteration (Sec. 2.4.2): A Delta = d, the same f_d, the R_e reuse rule
+# ---------------------------------------------------------------------------
+def test_direct_secant_formula():
+    # f_d(0) = 1 in a Picard step; on a linear f_d through (0, 1) the direct
+    # formula w0 / (1 - f_d(w0)) from w0 = 1/8 is the root, after one evaluation
+    g, seen = recorder(lambda w: (1.0 - w / 0.37, -1.0 / 0.37))
+    w, ev, fb = oracle.root_find(oracle.OMEGA_BSEC_DF, 2, 1.0, g)
+    assert seen == [0.125] and ev == 1 and fb == 0 and abs(w - 0.37) < 1e-15
+    g, seen = recorder(lambda w: (1.0 - w / 0.37, -1.0 / 0.37))
+    oracle.root_find(oracle.OMEGA_BSEC_DF, 1, 1.0, g, omega_max=1.0, tol_omega=1e-9, max_omega_it=200)
+    assert seen[:3] == [0.0, 1.0, 0.5]  # bisection of [0, 1] in the first iteration
+
+
+def test_picard_fd_at_zero_is_one():
+    """With Delta solving A Delta = d (the Picard step), p = -A Delta = -r(0),
+    so f_d(0) = -(p + r').r / ((p + r').p) = 1 exactly (derived from eq. fd=0)."""
+    prob = pbgen.make_problem(**SPEC)
+    o = oracle.Oracle.from_problem(prob)
+    rng = np.random.default_rng(5)
+    phi = 0.3 * rng.standard_normal(o.n)
+    d = -o.residual(oracle.HS, phi)
+    D, st, it = o.gmres(oracle.NONE, phi, d, tol=1e-13, maxit=20000, precond=oracle.PC_CHEB_SPAI)
+    assert st == 0
+    f0, _, st = o.fd(oracle.HS, phi, D, 0.0)
+    assert st == 0 and abs(f0 - 1.0) < 1e-9, f0
+    # Newton's step does not have this property
+    Dn, st, it = o.gmres(oracle.HS, phi, d, tol=1e-13, maxit=20000, precond=oracle.PC_CHEB_SPAI)
+    fn, _, _ = o.fd(oracle.HS, phi, Dn, 0.0)
+    assert abs(fn - 1.0) > 1e-3
+
+
+def test_picard_reaches_the_newton_solution_in_more_steps():
+    prob = pbgen.make_problem(**SPEC)
+    o = oracle.Oracle.from_problem(prob)
+    kw = dict(tol_nl=1e-9, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000, max_newton=200,
+              max_omega_it=200)
+    rn, _, _ = o.solve(**kw)
+    rp, _, _ = o.solve(nonlinear_method=oracle.PICARD, omega_method=oracle.OMEGA_BISECT, omega_max=1.0, **kw)
+    assert rn["status"] == 0 and rp["status"] == 0
+    assert abs(rp["total"] - rn["total"]) < 1e-10 * abs(rn["total"])
+    assert rp["newton_iters"] > 2 * rn["newton_iters"]
+    assert all(0.0 <= w <= 1.0 for w in rp["omega"])
+
+
+def test_picard_norm_ratio_rule():
+    """The relaxation factor is reused exactly when e_{k-2} / e_{k-1} >= R_e."""
+    prob = pbgen.make_problem(**SPEC)
+    o = oracle.Oracle.from_problem(prob)
+    r, _, _ = o.solve(nonlinear_method=oracle.PICARD, omega_method=oracle.OMEGA_BSEC_DF, omega_max=1.0, l_e=0.0,
+                      r_e=1.4)
+    assert r["status"] == 0
+    e, w = r["e_k"], r["omega"]
+    reused = 0
+    for k in range(2, len(w)):
+        if e[k - 2] >= 1.4 * e[k - 1]:
+            assert w[k] == w[k - 1]
+            reused += 1
+        else:
+            assert w[k] != w[k - 1]
+    assert reused > 0
+    # R_e = 0: a search at every step
+    r0, _, _ = o.solve(nonlinear_method=oracle.PICARD, omega_method=oracle.OMEGA_BSEC_DF, omega_max=1.0, l_e=0.0,
+                       r_e=0.0)
+    assert all(r0["omega"][k] != r0["omega"][k - 1] for k in range(1, len(r0["omega"])))
