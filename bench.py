@@ -305,6 +305,7 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-picard", action="store_true", help="skip the Picard comparison leg")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched leg (0: skip)")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-nmax", type=int, default=20, help="largest icosphere frequency of served requests")
@@ -426,6 +427,18 @@ def main():
         }
         out["bem_assembly"]["mixed_fp32_eval"] = asm_report(mx, FP32_PEAK_TFLOPS)
         out["fem_spmv"]["mixed_fp32_values"] = spmv_report(mx, 4)
+    if not args.no_picard:
+        # the paper's comparison path: Picard (A Delta = d) with the direct-secant
+        # relaxation search and the norm-ratio reuse rule, omega in [0, 1]
+        popts = dict(opts, nonlinear_method=pb.PICARD, omega_method=pb.OMEGA_BSEC_DF, omega_max=1.0, l_e=0.0,
+                     max_newton=200)
+        pc = run_leg(pb, torch, prob, pb.FP64, 1, 0, popts, "picard")
+        rp = pc["res"]
+        out["picard_fp64"] = {"value": 1.0 / pc["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * pc["elapsed"],
+                              "nonlinear_iters": rp["newton_iters"], "gmres_iters_total": rp["gmres_iters_total"],
+                              "total_kcal_mol": rp["total"],
+                              "rel_energy_diff_vs_newton": abs(rp["total"] - res["total"]) / abs(res["total"]),
+                              "newton_iters": res["newton_iters"], "status": rp["status"]}
     if args.batch > 0:
         out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
                           "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}
