@@ -233,8 +233,8 @@ pbfb_status pbfb_energy(pbfb_problem *p, const double *phi_lin, const double *ph
  * thread.  By default (ta = tb = 0) the shape is chosen by the library's
  * autotuner: the first assembly of a (precision, kernel, size class) in a
  * context times every candidate shape on a sample of that surface and keeps
- * the fastest for the context's lifetime.  Candidates: 16x32, 8x32, 32x32,
- * 8x64, 16x64.  pbfb_set_tile_shape pins one candidate for this problem
+ * the fastest for the context's lifetime.  Candidates: 16x32, 8x32, 8x64,
+ * 16x16, 8x16.  pbfb_set_tile_shape pins one candidate for this problem
  * (PBFB_EINVAL for any other pair) and marks its operators stale.  The shape
  * changes only the order of floating-point sums, never the integrals. */
 pbfb_status pbfb_set_tile_shape(pbfb_problem *p, int ta, int tb);

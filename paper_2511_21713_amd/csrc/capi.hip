@@ -653,7 +653,7 @@ pbfb_status pbfb_set_tile_shape(pbfb_problem *pp, int ta, int tb)
     int k = -1;
     if (!(ta == 0 && tb == 0)) {
         k = tile_shape_index(ta, tb);
-        PB_CHECK(k >= 0, PBFB_EINVAL, "tile shape is not one of 16x32, 8x32, 32x32, 8x64, 16x64 (or 0x0 for tuned)");
+        PB_CHECK(k >= 0, PBFB_EINVAL, "tile shape is not one of 16x32, 8x32, 8x64, 16x16, 8x16 (or 0x0 for tuned)");
     }
     Problem &p = pp->p;
     if (k != p.tile_fixed) {

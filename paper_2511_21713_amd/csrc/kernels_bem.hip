@@ -27,6 +27,7 @@
 // touching pairs stay FP64 throughout.  The result is rounded to FP32 once
 // for storage.
 #include <cmath>
+#include <type_traits>
 
 #include "pbfb_internal.hpp"
 
@@ -143,7 +144,8 @@ __device__ inline double rsqrt_pos(double x)
 __device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Fold of a tile's pair blocks onto the block's vertices through the shared
-// tile, V then K: first the source corners of each source vertex (in place,
+// tile (FP32 evaluation: one operator at a time, half the LDS of the paired
+// fold below, so more workgroups per CU), V then K: first the source corners of each source vertex (in place,
 // row by row), then the target corners of each target vertex.  A thread owns
 // one source vertex jb and a strided set of rows; the corner lists are read
 // once into registers and every tile read is independent (an absent corner
@@ -151,7 +153,7 @@ __device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 // number of corners of any vertex of either block: the lists past it hold
 // only absent corners, whose +0 terms are skipped.
 template <int TA, int TB, int MS>
-__device__ inline void fold_tile(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
+__device__ inline void fold_tile_single(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
                                  const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Vl,
                                  const double *Kl, double *__restrict__ EV, double *__restrict__ EK, int64_t row0,
                                  int64_t pB, int64_t ldE)
@@ -218,6 +220,89 @@ __device__ inline void fold_tile(int tid, int tl, int sl, int nA, int nB, const 
     }
 }
 
+// Fold of a tile's pair blocks onto the block's vertices through the shared
+// tile (FP64 evaluation), V and K together (each tile entry holds both, so one address and one
+// 16-byte LDS access serve the two operators): first the source corners of
+// each source vertex (in place, row by row), then the target corners of each
+// target vertex.  A thread owns one source vertex jb and a strided set of
+// rows; the corner lists are read once into registers and every tile read is
+// independent (an absent corner reads the zero row / column), so the reads
+// pipeline.  MS >= the largest number of corners of any vertex of either
+// block: the lists past it hold only absent corners, whose +0 terms are
+// skipped.
+typedef double dpair __attribute__((ext_vector_type(2))); // (V, K)
+
+template <int TA, int TB, int MS>
+__device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
+                                      const int (*sSb)[MAXS], dpair (*acc)[TB * 3 + 1], const double *Vl,
+                                 const double *Kl, double *__restrict__ EV, double *__restrict__ EK, int64_t row0,
+                                 int64_t pB, int64_t ldE)
+{
+    constexpr int NT = TA * TB;
+    const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+    const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
+    int cb[MS];
+#pragma unroll
+    for (int l = 0; l < MS; ++l) {
+        const int c = sSb[jb][l];
+        cb[l] = c < 0 ? TB * 3 : c;
+    }
+    const dpair zero = {0.0, 0.0};
+    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = zero;
+    if (tid < TA * 3) acc[tid][TB * 3] = zero;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = dpair{Vl[3 * a + b], Kl[3 * a + b]};
+    __syncthreads();
+    // source corners: rows r0, r0 + rstep, ... of each thread, in rounds of
+    // RC rows held in registers between the reads and the in-place writes
+    // (one round unless the source block has more than NT / (3 RC) vertices)
+    constexpr int RMAX = TA * 3, RC = 4;
+    const int rows_pt = (RMAX + rstep - 1) / rstep; // uniform
+    for (int rb = 0; rb < rows_pt; rb += RC) {
+        dpair colsum[RC];
+        int nrow = 0;
+        if (colthread) {
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+                const int sa = r0 + (rb + r) * rstep;
+                dpair t = zero;
+                if (sa < RMAX) {
+                    dpair v[MS];
+#pragma unroll
+                    for (int l = 0; l < MS; ++l) v[l] = acc[sa][cb[l]];
+#pragma unroll
+                    for (int l = 0; l < MS; ++l) t += v[l];
+                    nrow = r + 1;
+                }
+                colsum[r] = t;
+            }
+        }
+        __syncthreads();
+        if (colthread)
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+                if (r < nrow) acc[r0 + (rb + r) * rstep][jb] = colsum[r];
+        __syncthreads();
+    }
+    if (colthread)
+        for (int ia = r0; ia < nA; ia += rstep) {
+            dpair v[MS];
+#pragma unroll
+            for (int k = 0; k < MS; ++k) {
+                const int ra = sSa[ia][k];
+                v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
+            }
+            dpair t = zero;
+#pragma unroll
+            for (int k = 0; k < MS; ++k) t += v[k];
+            const int64_t at = (row0 + ia) * ldE + pB + jb;
+            EV[at] = t.x;
+            EK[at] = t.y;
+        }
+}
+
 // RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
 // TA x TB: target x source triangles of the tile, one pair per thread; MS:
@@ -242,7 +327,8 @@ __global__ void __launch_bounds__(TA * TB, 4)
     __shared__ double sAa[TA], sAb[TB];
     __shared__ int sVa[TA][3], sVb[TB][3];
     __shared__ int sSa[TA * 3][MAXS], sSb[TB * 3][MAXS];
-    __shared__ double acc[TA * 3 + 1][TB * 3 + 1]; // + a zero row and a zero column
+    // the tile: (V, K) pairs (FP64) or one operator at a time (FP32); + a zero row and a zero column
+    __shared__ std::conditional_t<F32, double, dpair> acc[TA * 3 + 1][TB * 3 + 1];
 
     const int tid = threadIdx.x;
     const int64_t bB = blockIdx.x;
@@ -360,7 +446,8 @@ __global__ void __launch_bounds__(TA * TB, 4)
         }
     }
 
-    fold_tile<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
+    if constexpr (F32) fold_tile_single<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
+    else fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
 }
 
 // ---------------------------------------------------------------------------
@@ -882,14 +969,14 @@ static int tile_key(int precision, bool yuk, int64_t nt)
 }
 
 // Autotuner: times the regular tile kernel of every candidate shape on the
-// same sample of this surface (the first min(nt, 256) Morton-ordered target
+// same sample of this surface (the first min(nt, 512) Morton-ordered target
 // triangles against all source triangles; one warm-up launch, then the
-// faster of two timed launches) and returns the shape with the shortest time
-// per target triangle.  Runs with the context workspace held.
+// fastest of three timed launches) and returns the shape with the shortest
+// time per target triangle.  Runs with the context workspace held.
 static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream_t s)
 {
     SurfaceTopo &T = p.topo[w];
-    const int64_t nsample = std::min<int64_t>(T.nt, 256);
+    const int64_t nsample = std::min<int64_t>(T.nt, 512);
     size_t need = 0;
     for (int k = 0; k < N_TILE_SHAPES; ++k) {
         const BlockSide &HA = block_side(T, TILE_SHAPES[k].ta), &HB = block_side(T, TILE_SHAPES[k].tb);
@@ -915,7 +1002,7 @@ static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream
         const int64_t tris = std::min<int64_t>(a.b1 * HA.bs, T.nt);
         launch_regular(k, yuk, f32, a, s);
         float ms = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             PB_HIP(hipEventRecord(e0, s));
             launch_regular(k, yuk, f32, a, s);
             PB_HIP(hipEventRecord(e1, s));

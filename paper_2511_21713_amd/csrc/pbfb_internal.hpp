@@ -78,7 +78,7 @@ struct Arena {
 struct TileShape {
     int ta, tb;
 };
-constexpr TileShape TILE_SHAPES[] = {{16, 32}, {8, 32}, {32, 32}, {8, 64}, {16, 64}};
+constexpr TileShape TILE_SHAPES[] = {{16, 32}, {8, 32}, {8, 64}, {16, 16}, {8, 16}};
 constexpr int N_TILE_SHAPES = int(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
 constexpr int MAXS = 12; // slots per local vertex in a block (max triangles of a block at one vertex)
 int tile_shape_index(int ta, int tb); // -1 if not a candidate

@@ -16,7 +16,7 @@ import pbgen
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 32), (8, 32), (32, 32), (8, 64), (16, 64)]
+SHAPES = [(16, 32), (8, 32), (8, 64), (16, 16), (8, 16)]
 SPEC = dict(n=6, a=5.0, c=8.0, bump=True, t=3.0, L=2, helix=2, partials=4, kappa=0.15, seed=(9, 3))
 
 
@@ -89,7 +89,7 @@ def test_solve_with_pinned_shapes_agrees(tiles):
     pb, ctx, prob, refs = tiles
     kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
     tot = []
-    for shape in ((8, 32), (16, 64)):
+    for shape in ((8, 32), (16, 16)):
         g = pb.Problem.from_inputs(ctx, prob)
         g.set_tile_shape(*shape)
         r = g.solve(**kw)
@@ -152,7 +152,7 @@ def test_high_valence_mesh_matches_oracle(tiles):
     prob = pbgen.Problem(nodes=nodes, tets=tets, tri_m=tri_m, tri_s=tri_s, q_xyz=np.zeros((1, 3)),
                          q_z=np.array([1.0]), eps_in=4.0, eps_out=80.0, kappa=0.2, info={})
     o = oracle.Oracle.from_problem(prob)
-    for shape in ((8, 32), (16, 64)):
+    for shape in ((8, 32), (8, 64)):
         g = pb.Problem.from_inputs(ctx, prob)
         g.set_tile_shape(*shape)
         for surf in (0, 1):
