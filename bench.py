@@ -101,9 +101,11 @@ def apply_flops(nm, ns, nnz):
     return 2 * (nm * 2 * nm + ns * 2 * ns) + 2 * nnz
 
 
-def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
+def run_leg(pb, torch, prob, precision, steps, warmup, opts, label, bem_mode=None, potential=True):
     ctx = pb.Context(0)
     g = pb.Problem.from_inputs(ctx, prob, precision=precision)
+    if bem_mode is not None:
+        g.set_bem_mode(bem_mode)
     t0 = time.perf_counter()
     g.setup()
     progress(f"{label}: first setup (topology + upload + assembly) {time.perf_counter() - t0:.2f} s, "
@@ -137,12 +139,14 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label):
         ms, cnt = tm[name]
         tm[name] = (ms * cnt / real if real else 0.0, real)
     g.timing_enable(False)
-    # one more solve outside the timed region for the potential on Gamma_m
-    phi = torch.zeros(2 * g.n, dtype=torch.float64, device="cuda")
-    g.solve(phi_out=phi, **opts)
-    torch.cuda.synchronize()
-    phi = phi.cpu().numpy()
-    u_m = (phi[:g.n] + phi[g.n:])[np.unique(prob.tri_m)]
+    u_m = None
+    if potential:
+        # one more solve outside the timed region for the potential on Gamma_m
+        phi = torch.zeros(2 * g.n, dtype=torch.float64, device="cuda")
+        g.solve(phi_out=phi, **opts)
+        torch.cuda.synchronize()
+        phi = phi.cpu().numpy()
+        u_m = (phi[:g.n] + phi[g.n:])[np.unique(prob.tri_m)]
     tiles = {"laplace_gamma_m": list(g.tile_shape(0)), "yukawa_gamma_s": list(g.tile_shape(1))}
     out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm(), u_m=u_m,
                tiles=tiles)
@@ -306,6 +310,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard comparison leg")
+    ap.add_argument("--no-matrix-free", action="store_true", help="skip the matrix-free boundary-element leg")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched leg (0: skip)")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-nmax", type=int, default=20, help="largest icosphere frequency of served requests")
@@ -439,6 +444,27 @@ def main():
                               "total_kcal_mol": rp["total"],
                               "rel_energy_diff_vs_newton": abs(rp["total"] - res["total"]) / abs(res["total"]),
                               "newton_iters": res["newton_iters"], "status": rp["status"]}
+    if not args.no_matrix_free:
+        # nothing dense stored: every coupled apply evaluates the regular
+        # quadrature-point pairs again (the same flops as one assembly)
+        mf = {}
+        for name, prec, peak in (("fp64", pb.FP64, FP64_PEAK_TFLOPS), ("mixed_fp32_eval", pb.MIXED, FP32_PEAK_TFLOPS)):
+            if prec == pb.MIXED and args.no_mixed:
+                continue
+            lg = run_leg(pb, torch, prob, prec, 1, 0, opts, f"matrix-free {name}", bem_mode=pb.BEM_MATRIX_FREE,
+                         potential=False)
+            r = lg["res"]
+            ams, acnt = lg["timing"]["gemv"]
+            mf[name] = {"value": 1.0 / lg["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * lg["elapsed"],
+                        "device_bytes": lg["hbm"], "newton_iters": r["newton_iters"],
+                        "gmres_iters_total": r["gmres_iters_total"], "coupled_applies": r["applies"],
+                        "total_kcal_mol": r["total"],
+                        "rel_energy_diff_vs_dense_fp64": abs(r["total"] - res["total"]) / abs(res["total"]),
+                        "bem_apply_ms": ams, "bem_apply_flops": asm_flops,
+                        "tflops": asm_flops / (ams * 1e-3) / 1e12 if ams else None, "peak_tflops": peak,
+                        "frac": asm_flops / (ams * 1e-3) / 1e12 / peak if ams else None, "status": r["status"]}
+        mf["dense_fp64_device_bytes"] = f64["hbm"]
+        out["matrix_free"] = mf
     if args.batch > 0:
         out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
                           "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}

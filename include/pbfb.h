@@ -242,6 +242,23 @@ pbfb_status pbfb_set_tile_shape(pbfb_problem *p, int ta, int tb);
  * Gamma_s); 0, 0 before the first assembly. */
 pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *tb);
 
+/* ---- boundary operator storage ------------------------------------------ */
+/* PBFB_BEM_DENSE (default): the four Galerkin blocks are assembled once per
+ * setup and stored (n x 2n per interface, FP64 or FP32), every apply is a
+ * dense GEMV.  PBFB_BEM_MATRIX_FREE: nothing dense is stored; every apply
+ * evaluates the regular quadrature-point pairs on the fly (about 36 N_t^2
+ * kernel evaluations per interface) and adds the touching-pair blocks and
+ * 1/2 M kept from setup: for instances whose dense blocks would not fit
+ * (the paper switches to a fast multipole method above 90k vertices for the
+ * same reason).  The single-layer blocks of the GMRES preconditioner are
+ * then their inverse diagonal (the approximate inverse needs dense rows), so
+ * Krylov iteration counts are higher.  Results equal the dense mode's to
+ * rounding.  With PBFB_MIXED the FP32 evaluation rounds each apply's source
+ * strengths, so the apply is linear to ~1e-7 only and GMRES tolerances below
+ * that are not reached.  Marks the operators stale. */
+enum { PBFB_BEM_DENSE = 0, PBFB_BEM_MATRIX_FREE = 1 };
+pbfb_status pbfb_set_bem_mode(pbfb_problem *p, int mode);
+
 /* ---- inspection --------------------------------------------------------- */
 /* Copy the two dense blocks stored for surface `surf` (0 = Gamma_m, Laplace;
  * 1 = Gamma_s, Yukawa) as row-major n x n host arrays (either may be NULL):
@@ -249,7 +266,8 @@ pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *t
  *   Gamma_s: Kp = 1/2 M_s - Kk_s,  Vp = +Vk_s
  * i.e. the Galerkin blocks of the second and third block rows above, with
  * M the P1 surface mass, V/K the single/double layer (Sec. 2.2, eq. KV).
- * In mixed precision the FP32 stored values are widened. */
+ * In mixed precision the FP32 stored values are widened.  PBFB_ESTATE in
+ * matrix-free mode (nothing is stored). */
 pbfb_status pbfb_export_bem(pbfb_problem *p, int surf, double *Vp, double *Kp);
 /* Right-hand side b = [0 | f_m | 0] (host array of length n_unknowns). */
 pbfb_status pbfb_export_rhs(pbfb_problem *p, double *b);

@@ -20,6 +20,7 @@ LIN, T3, HS = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS, OMEGA_BSEC_DF = 0, 1, 2, 3, 4, 5
 NEWTON, PICARD = 0, 1
+BEM_DENSE, BEM_MATRIX_FREE = 0, 1
 T_APPLY, T_GEMV, T_SPMV, T_ASM, T_SING = 0, 1, 2, 3, 4
 
 EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_problem_create", "pbfb_problem_destroy",
@@ -27,7 +28,7 @@ EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_probl
            "pbfb_reset_operators", "pbfb_residual",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
            "pbfb_server_submit", "pbfb_server_poll", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
-           "pbfb_export_rhs", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
+           "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
 
 
 class PbfbError(RuntimeError):
@@ -112,6 +113,7 @@ def lib():
         L.pbfb_export_bem.argtypes = [P, C.c_int, P, P]
         L.pbfb_export_rhs.argtypes = [P, P]
         L.pbfb_set_tile_shape.argtypes = [P, C.c_int, C.c_int]
+        L.pbfb_set_bem_mode.argtypes = [P, C.c_int]
         L.pbfb_get_tile_shape.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pbfb_timing_enable.argtypes = [P, C.c_int]
         L.pbfb_timing.argtypes = [P, C.c_int, C.POINTER(C.c_double), I64P, C.c_int]
@@ -340,6 +342,10 @@ class Problem:
         b = np.zeros(self.n)
         _check(lib().pbfb_export_rhs(self.h, b.ctypes.data))
         return b
+
+    def set_bem_mode(self, mode):
+        """BEM_DENSE (stored Galerkin blocks) or BEM_MATRIX_FREE (evaluated at every apply)."""
+        _check(lib().pbfb_set_bem_mode(self.h, mode))
 
     def set_tile_shape(self, ta=0, tb=0):
         """Pin the regular-assembly tile shape (ta x tb triangles); 0, 0 = tuned."""

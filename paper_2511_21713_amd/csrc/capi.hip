@@ -606,6 +606,7 @@ pbfb_status pbfb_export_bem(pbfb_problem *pp, int surf, double *V, double *K)
     API_BEGIN
     PB_CHECK(pp && (surf == 0 || surf == 1), PBFB_EINVAL, "bad argument");
     Problem &p = pp->p;
+    PB_CHECK(!p.bem_mf, PBFB_ESTATE, "matrix-free mode stores no boundary operator");
     hipStream_t s = pick_stream(p, nullptr);
     ensure_bem(p, surf, s);
     const int64_t nv = p.topo[surf].nv, ld = bem_ld(nv);
@@ -643,6 +644,20 @@ pbfb_status pbfb_reset_operators(pbfb_problem *pp)
     API_BEGIN
     PB_CHECK(pp, PBFB_EINVAL, "null problem");
     invalidate_geometry(pp->p);
+    API_END
+}
+
+pbfb_status pbfb_set_bem_mode(pbfb_problem *pp, int mode)
+{
+    API_BEGIN
+    PB_CHECK(pp && (mode == PBFB_BEM_DENSE || mode == PBFB_BEM_MATRIX_FREE), PBFB_EINVAL, "bad boundary-operator mode");
+    Problem &p = pp->p;
+    const bool mf = mode == PBFB_BEM_MATRIX_FREE;
+    if (mf != p.bem_mf) {
+        p.bem_mf = mf;
+        p.bem_ready[0] = p.bem_ready[1] = false;
+        p.bem_topo_ready[0] = p.bem_topo_ready[1] = false;
+    }
     API_END
 }
 

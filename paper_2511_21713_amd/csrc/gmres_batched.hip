@@ -35,13 +35,13 @@
 
 namespace pbfb {
 
-enum GSt { G_INIT = 0, G_ARN = 1, G_UPD = 2, G_RES = 3, G_DONE = 4, G_FAIL = 5 };
 
 struct GDesc {
     const void *Bm, *Bs;
     int64_t ldm, lds, nm, ns;
     int f32;  // operator values in FP32
     int vf32; // Krylov basis stored in FP32
+    int mf;   // boundary operators applied matrix-free (no dense GEMV)
     const int32_t *gm, *gs;
     const int32_t *sptr, *col; // FEM rows, sliced ELL
     const void *val;
@@ -175,10 +175,14 @@ __global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, co
     } else {
         const int w = k < d.nn + d.nm ? 0 : 1;
         const int64_t off = d.nn + (w == 0 ? 0 : d.nm), i = k - off;
-        double acc = 0.0;
-        for (int32_t e = d.sp_ptr[w][i]; e < d.sp_ptr[w][i + 1]; ++e)
-            acc = fma(d.sp_val[w][e], pc_src(d, s, off + d.sp_col[w][e]), acc);
-        zv = acc;
+        if (!d.sp_ptr[w]) {
+            zv = d.dinv[k] * pc_src(d, s, k); // matrix-free: no dense rows for the approximate inverse
+        } else {
+            double acc = 0.0;
+            for (int32_t e = d.sp_ptr[w][i]; e < d.sp_ptr[w][i + 1]; ++e)
+                acc = fma(d.sp_val[w][e], pc_src(d, s, off + d.sp_col[w][e]), acc);
+            zv = acc;
+        }
         d.z[k] = zv;
     }
     if (last && s.st == G_RES) d.x[k] += zv;
@@ -222,7 +226,7 @@ __global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, con
     const WItem it = wl[blockIdx.x];
     if (!applies(S[it.inst].st)) return;
     const GDesc &d = D[it.inst];
-    if (d.f32 != (sizeof(MT) == 4)) return;
+    if (d.mf || d.f32 != (sizeof(MT) == 4)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t r0 = it.b + wv * GEMV_RW;
     const int64_t n = it.a == 0 ? d.nm : d.ns;
@@ -593,6 +597,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.ldm = bem_ld(d.nm);
         d.lds = bem_ld(d.ns);
         d.f32 = p.precision == PBFB_MIXED;
+        d.mf = p.bem_mf ? 1 : 0;
         d.gm = p.surf[0].g;
         d.gs = p.surf[1].g;
         d.sptr = p.d_sptr;
@@ -606,7 +611,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.cheb_ratio = J.cheb_ratio;
         d.lmax = J.lmax;
         for (int w = 0; w < 2; ++w) {
-            d.sp_ptr[w] = p.surf[w].ring_ptr;
+            d.sp_ptr[w] = p.bem_mf ? nullptr : p.surf[w].ring_ptr; // null: inverse diagonal
             d.sp_col[w] = p.surf[w].ring;
             d.sp_val[w] = p.surf[w].spai;
         }
@@ -705,7 +710,11 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     bool finished = false;
     hipLaunchKernelGGL(k_cheb_coef, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, dD, nb);
     int types = 0;
-    for (auto *J : jobs) types |= J->p->precision == PBFB_MIXED ? 2 : 1;
+    bool any_mf = false;
+    for (auto *J : jobs) {
+        if (J->p->bem_mf) any_mf = true;
+        else types |= J->p->precision == PBFB_MIXED ? 2 : 1;
+    }
     // one Krylov step of the whole batch
     auto enqueue_step = [&]() {
         if (tm) tm->begin(T_PREC, s);
@@ -718,6 +727,14 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         if (tm) tm->begin(T_GEMV, s);
         if (types & 1) hipLaunchKernelGGL(k_bgemv<double>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
         if (types & 2) hipLaunchKernelGGL(k_bgemv<float>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
+        // matrix-free instances: their own launches, gated by their state word
+        for (size_t q = 0; q < jobs.size() && any_mf; ++q) {
+            Problem &pq = *jobs[q]->p;
+            if (!pq.bem_mf) continue;
+            const int *stq = reinterpret_cast<const int *>(dS + q);
+            mf_apply(pq, 0, desc[q].xm, desc[q].w + pq.nn, stq, s);
+            mf_apply(pq, 1, desc[q].xs, desc[q].w + pq.nn + pq.surf[0].nv, stq, s);
+        }
         if (tm) {
             tm->end(s);
             tm->begin(T_SPMV, s);
@@ -741,7 +758,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     // Without timers the step is captured once as a HIP graph (kernel nodes
     // only) and replayed; the capture is reused while the buffer and launch
     // shapes stay the same (the Newton steps of a solve, repeated solves).
-    bool graph = !tm;
+    bool graph = !tm && !any_mf; // matrix-free launches carry per-instance pointers: not captured
     for (auto *J : jobs) graph = graph && J->graph;
     if (graph) {
         const GraphKey key{BB.dev, nvec, ngemv, nspmv, npack, ndot, ngroups, unsigned(nb), kmax, types};

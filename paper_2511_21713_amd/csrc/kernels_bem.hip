@@ -29,45 +29,16 @@
 #include <cmath>
 #include <type_traits>
 
+#include "bem_quad.hpp"
 #include "pbfb_internal.hpp"
 
 namespace pbfb {
 
-// The 6-point rule is two orbits of 3 points: point k of orbit o has
-// barycentric coordinate beta_o at index k and alpha_o at the other two.  A
-// sum s_j = sum_q w_q b_q[j] g_q is then A_0 G_0 + A_1 G_1 + D_0 g_{0,j} +
-// D_1 g_{1,j} with G_o the orbit's sum of g, A_o = w_o alpha_o and D_o =
-// w_o (beta_o - alpha_o) (12 operations for the three j instead of 18).
-struct QRule6 {
-    double b[6][3];
-    double w[6];
-    double oA[2], oD[2];
-};
 struct GL4 {
     double x[4];
     double w[4];
 };
 
-static QRule6 q6arg()
-{
-    QRule6 r;
-    const Rules &R = rules();
-    for (int q = 0; q < 6; ++q) {
-        for (int k = 0; k < 3; ++k) r.b[q][k] = R.tri_bary[q][k];
-        r.w[q] = R.tri_w[q];
-    }
-    for (int o = 0; o < 2; ++o) {
-        // the orbit structure the regular kernel relies on
-        const double al = R.tri_bary[3 * o][1], be = R.tri_bary[3 * o][0];
-        for (int k = 0; k < 3; ++k)
-            for (int j = 0; j < 3; ++j)
-                PB_CHECK(R.tri_bary[3 * o + k][j] == (j == k ? be : al) && R.tri_w[3 * o + k] == R.tri_w[3 * o],
-                         PBFB_EDEVICE, "triangle rule is not two 3-point orbits");
-        r.oA[o] = R.tri_w[3 * o] * al;
-        r.oD[o] = R.tri_w[3 * o] * (be - al);
-    }
-    return r;
-}
 static GL4 gl4arg()
 {
     GL4 r;
@@ -80,7 +51,7 @@ static GL4 gl4arg()
 
 static inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
-constexpr double INV4PI = 0.079577471545947667884441881686257181;
+
 
 // Morton-ordered copies of the triangle data used by the regular assembly.
 // FP64 evaluation reads m_qp/m_nrm; FP32 evaluation reads m_cen/m_qf/m_nf
@@ -117,31 +88,7 @@ __global__ void k_tri_morton(int64_t nt, const int32_t *__restrict__ morton, con
 // ---------------------------------------------------------------------------
 // 1. regular tiles
 // ---------------------------------------------------------------------------
-// the orbit factors of the 6-point rule in FP32
-struct QRule6F {
-    float oA[2], oD[2];
-};
-static QRule6F q6farg()
-{
-    const QRule6 R = q6arg();
-    QRule6F r;
-    for (int o = 0; o < 2; ++o) {
-        r.oA[o] = float(R.oA[o]);
-        r.oD[o] = float(R.oD[o]);
-    }
-    return r;
-}
 
-// 1/sqrt(x) for finite x > 0 (quadrature points of non-touching panels are
-// never coincident): the hardware estimate refined by one third-order step
-// y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
-__device__ inline double rsqrt_pos(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-__device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Fold of a tile's pair blocks onto the block's vertices through the shared
 // tile (FP32 evaluation: one operator at a time, half the LDS of the paired
@@ -1060,13 +1007,25 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         for (int64_t t = 0; t < T.nt; ++t)
             for (int32_t k = T.tp_ptr[t]; k < T.tp_ptr[t + 1]; ++k) tp_tau[k] = int32_t(t);
         S.tp_tau = A.upload(tp_tau, s);
-        S.ring_ptr = A.upload(T.ring_ptr, s);
-        S.ring = A.upload(T.ring, s);
-        S.spai = A.alloc<double>(T.ring.size());
-        const int64_t ldt = bem_ld(T.nv);
         S.vdiag = A.alloc<double>(T.nv);
-        if (f32) S.B = A.alloc<float>(T.nv * ldt);
-        else S.B = A.alloc<double>(T.nv * ldt);
+        S.tpv = nullptr;
+        S.mpos = nullptr;
+        S.ring_ptr = S.ring = nullptr;
+        S.spai = nullptr;
+        if (p.bem_mf) {
+            // matrix-free: resident touching-pair blocks and the Morton position of each triangle
+            S.tpv = A.alloc<double>(18 * S.ntp);
+            std::vector<int32_t> mpos(T.nt);
+            for (int64_t m = 0; m < T.nt; ++m) mpos[T.morton[m]] = int32_t(m);
+            S.mpos = A.upload(mpos, s);
+        } else {
+            S.ring_ptr = A.upload(T.ring_ptr, s);
+            S.ring = A.upload(T.ring, s);
+            S.spai = A.alloc<double>(T.ring.size());
+            const int64_t ldt = bem_ld(T.nv);
+            if (f32) S.B = A.alloc<float>(T.nv * ldt);
+            else S.B = A.alloc<double>(T.nv * ldt);
+        }
         PB_HIP(hipStreamSynchronize(s));
         p.bem_topo_ready[w] = true;
     }
@@ -1082,6 +1041,26 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         hipStream_t s;
         ~Drain() { (void)hipStreamSynchronize(s); }
     } drain{s};
+    if (p.bem_mf) {
+        // matrix-free: only the touching-pair blocks (kept) and the diagonal of V'
+        double *vxm = p.ctx->asm_ws.doubles(3 * T.nv);
+        hipLaunchKernelGGL(k_gather_coords, dim3(nblk(T.nv, 256)), dim3(256), 0, s, T.nv, S.g, p.d_x, vxm);
+        GL4 G = gl4arg();
+        if (p.timing) p.timer.begin(T_SING, s);
+        if (yuk)
+            hipLaunchKernelGGL(k_bem_singular<true>, dim3(nblk(S.ntp * 64, 256)), dim3(256), 0, s, S.ntp, d_tptau,
+                               S.tp_sig, S.tri, vxm, S.nrm, S.area, kappa, G, S.tpv);
+        else
+            hipLaunchKernelGGL(k_bem_singular<false>, dim3(nblk(S.ntp * 64, 256)), dim3(256), 0, s, S.ntp, d_tptau,
+                               S.tp_sig, S.tri, vxm, S.nrm, S.area, kappa, G, S.tpv);
+        if (p.timing) p.timer.end(s);
+        PB_HIP(hipGetLastError());
+        mf_vdiag(p, w, s);
+        PB_HIP(hipStreamSynchronize(s));
+        S.tile = -1;
+        p.bem_ready[w] = true;
+        return;
+    }
     RegArgs ra;
     ra.nt = T.nt;
     ra.m_tri = S.m_tri;

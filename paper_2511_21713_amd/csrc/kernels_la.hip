@@ -158,7 +158,14 @@ static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hi
     if (p.timing) p.timer.begin(T_APPLY, s);
     hipLaunchKernelGGL(k_pack, dim3(nb_(std::max(ldm, lds), 256)), dim3(256), 0, s, p.nn, M.nv, S.nv, ldm, lds, M.g,
                        S.g, x, xm, xs);
-    gemv_launch(p, xm, xs, y, s);
+    if (p.bem_mf) {
+        if (p.timing) p.timer.begin(T_GEMV, s);
+        mf_apply(p, 0, xm, y + p.nn, nullptr, s);
+        mf_apply(p, 1, xs, y + p.nn + p.surf[0].nv, nullptr, s);
+        if (p.timing) p.timer.end(s);
+    } else {
+        gemv_launch(p, xm, xs, y, s);
+    }
     if (p.timing) p.timer.begin(T_SPMV, s);
     const unsigned g = nb_(p.nn, SLICE);
     if (!with_jac)

@@ -132,6 +132,10 @@ struct SurfaceDev {
     float *m_qf = nullptr, *m_nf = nullptr;                      // FP32 offsets from them, FP32 normals
     std::map<int, BlockSideDev> sides; // device copies of the block tables in use (bem arena)
     int tile = -1;                      // tile shape of the last assembly (index into TILE_SHAPES)
+    // matrix-free mode: touching-pair blocks kept resident (18 per pair: V then K),
+    // Morton position of each triangle
+    double *tpv = nullptr;
+    int32_t *mpos = nullptr;
     int32_t *tp_ptr = nullptr, *tp_sig = nullptr, *tp_tau = nullptr, *morton = nullptr;
     int64_t ntp = 0;
     int32_t *cslot = nullptr; // FEM-row slot of the coupling entry per (v2t entry, b)
@@ -184,7 +188,7 @@ struct EventTimer {
 enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
-    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR,
+    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1,
     SCR_N
 };
 
@@ -200,6 +204,7 @@ struct Problem {
     bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
     bool bem_topo_ready[2] = {false, false};
     int tile_fixed = -1; // tile shape forced by pbfb_set_tile_shape (index), -1: tuned
+    bool bem_mf = false; // boundary operators applied matrix-free (no dense storage)
     // host copies
     int64_t nn = 0, ntet = 0, nq = 0;
     std::vector<double> x;
@@ -244,6 +249,8 @@ void release_all_scratch(Problem &p);
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri);
 const BlockSide &block_side(SurfaceTopo &S, int bs); // built on first use
 constexpr int SLICE = 64; // FEM rows per sliced-ELL slice: one wavefront
+// Krylov state of a batched GMRES instance (the state word every batched kernel reads)
+enum GSt { G_INIT = 0, G_ARN = 1, G_UPD = 2, G_RES = 3, G_DONE = 4, G_FAIL = 5 };
 void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int32_t> &col,
                         std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,
                         std::vector<int32_t> &diag, std::vector<int32_t> cslot[2]);
@@ -258,6 +265,11 @@ void ensure_all(Problem &p, hipStream_t s);
 // FEM element kernels (row gather over the tets around each node)
 void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t s); // d_val = A + J(u)
 void fem_assemble_linear(Problem &p, hipStream_t s);                                  // d_val = A
+// matrix-free boundary rows of surface w: y = [K'|V'] x for the packed x =
+// [u on the surface | lambda]; st (nullable): Krylov state word, the kernels
+// return at once unless it is G_ARN or G_RES
+void mf_apply(Problem &p, int w, const double *x, double *y, const int *st, hipStream_t s);
+void mf_vdiag(Problem &p, int w, hipStream_t s); // diagonal of V' from the resident touching-pair blocks
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s);
 void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN,
                      double *rJ, double *rH, hipStream_t s);
