@@ -311,6 +311,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard comparison leg")
     ap.add_argument("--no-matrix-free", action="store_true", help="skip the matrix-free boundary-element leg")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the Taylor-schedule comparison leg")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched leg (0: skip)")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-nmax", type=int, default=20, help="largest icosphere frequency of served requests")
@@ -444,6 +445,21 @@ def main():
                               "total_kcal_mol": rp["total"],
                               "rel_energy_diff_vs_newton": abs(rp["total"] - res["total"]) / abs(res["total"]),
                               "newton_iters": res["newton_iters"], "status": rp["status"]}
+    if not args.no_schemes:
+        # the reaction term raised through Taylor orders over the first
+        # iterations (T3-HS is the default leg above)
+        sch = {}
+        for label, sched in (("T3-T5-HS", [pb.T3, pb.T5]), ("T3-T5-T7-T7-HS", [pb.T3, pb.T5, pb.T7, pb.T7])):
+            lg = run_leg(pb, torch, prob, pb.FP64, 2, 0, dict(opts, schedule=sched), f"schedule {label}",
+                         potential=False)
+            r = lg["res"]
+            sch[label] = {"value": 2 / lg["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * lg["elapsed"] / 2,
+                          "newton_iters": r["newton_iters"], "gmres_iters_total": r["gmres_iters_total"],
+                          "omega": r["omega"], "total_kcal_mol": r["total"],
+                          "rel_energy_diff_vs_t3_hs": abs(r["total"] - res["total"]) / abs(res["total"]),
+                          "status": r["status"]}
+        sch["T3-HS"] = {"value": value, "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"]}
+        out["scheme_schedules_fp64"] = sch
     if not args.no_matrix_free:
         # nothing dense stored: every coupled apply evaluates the regular
         # quadrature-point pairs again (the same flops as one assembly)

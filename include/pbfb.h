@@ -58,7 +58,10 @@ typedef enum {
 
 typedef enum { PBFB_FP64 = 0, PBFB_MIXED = 1 } pbfb_precision;
 /* nonlinearity of the shell reaction term: N(u) = u, u + u^3/6, sinh(u) */
-typedef enum { PBFB_LIN = 0, PBFB_T3 = 1, PBFB_HS = 2 } pbfb_scheme;
+/* Reaction term of the FEM rows (Sec. 2.4.2; the schemes of Sec. 3.3.1 that raise
+ * the Taylor order of sinh as the iterations advance): LIN t, T3 t + t^3/3!,
+ * T5 through t^5/5!, T7 through t^7/7!, HS sinh t */
+typedef enum { PBFB_LIN = 0, PBFB_T3 = 1, PBFB_HS = 2, PBFB_T5 = 3, PBFB_T7 = 4 } pbfb_scheme;
 enum { PBFB_MEM_HOST = 0, PBFB_MEM_DEVICE = 1 };
 
 /* ---- context ------------------------------------------------------------ */
@@ -118,10 +121,10 @@ pbfb_status pbfb_apply_jacobian(pbfb_problem *p, int scheme, const double *phi, 
 
 /* ---- Newton solve (Sec. 2.4.2, 2.5, App. A, App. B) --------------------- */
 typedef struct {
-    int scheme_first;    /* PBFB_T3 (cubic start, default) or PBFB_HS */
+    int scheme_first;    /* PBFB_T3 (cubic start, default) or PBFB_HS; ignored when n_schedule > 0 */
     int omega_auto;      /* 1: relaxation factor from the root of f_d; 0: omega_fixed */
     double omega_fixed;  /* constant relaxation factor when omega_auto == 0 */
-    double tol_nl;       /* stop when omega ||Delta||_2 < tol_nl (1e-3) */
+    double tol_nl;       /* stop when omega ||Delta||_2 < tol_nl (1e-3) after a PBFB_HS step */
     double tol_gr;       /* final GMRES relative tolerance (1e-6) */
     double tol_gr0;      /* initial GMRES tolerance (1e-3); == tol_gr disables adaptivity */
     double tol_omega;    /* |f_d| tolerance of the omega search (0.1) */
@@ -169,6 +172,11 @@ typedef struct {
     double r_e;          /* Picard: the relaxation factor is searched again only when e_{k-2}/e_{k-1} < r_e
                           * (the norm-ratio rule of the section on reducing omega searches; 1.4; 0: every
                           * step) */
+    int n_schedule;      /* 0 (default): the scheme_first rule.  1..8: nonlinear iteration k <= n_schedule
+                          * uses schedule[k-1] (PBFB_T3, PBFB_T5, PBFB_T7 or PBFB_HS), later ones PBFB_HS:
+                          * the T3-T5-HS and T3-T5-T7-T7-HS sequences of Sec. 3.3.1.  The omega search
+                          * starts from omega0_first in a T3 iteration, from omega0_next otherwise */
+    int schedule[8];
 } pbfb_solve_opts;
 enum { PBFB_PC_DIAG = 0, PBFB_PC_CHEB_SPAI = 1 };
 enum { PBFB_OMEGA_NEWTON = 0, PBFB_OMEGA_BISECT = 1, PBFB_OMEGA_SECANT = 2, PBFB_OMEGA_BSEC = 3,

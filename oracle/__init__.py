@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpbref.so")
 
-LIN, T3, HS = 0, 1, 2
+LIN, T3, HS, T5, T7 = 0, 1, 2, 3, 4
 
 _lib = None
 
@@ -26,13 +26,13 @@ class Opts(C.Structure):
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
                 ("max_gmres", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("omega_method", C.c_int), ("nonlinear_method", C.c_int),
-                ("r_e", C.c_double)]
+                ("r_e", C.c_double), ("n_schedule", C.c_int), ("schedule", C.c_int * 8)]
 
 
 PC_DIAG, PC_CHEB_SPAI = 0, 1
 OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS, OMEGA_BSEC_DF = 0, 1, 2, 3, 4, 5
 NEWTON, PICARD = 0, 1
-NONE = 3  # scheme without reaction term (the Picard linear operator)
+NONE = 7  # scheme without reaction term (the Picard linear operator)
 FD_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double))
 
 
@@ -172,9 +172,18 @@ def cheb_diag(fdiag, dinv, lmax, ratio, k, r):
 
 
 def default_opts(**kw):
+    """Options with the defaults of pbref_opts_default; schedule=[T3, T5, ...]
+    sets the per-iteration schemes (n_schedule and schedule)."""
     o = Opts()
     lib().pbref_opts_default(C.byref(o))
     for k, v in kw.items():
+        if k == "schedule":
+            v = list(v)
+            assert len(v) <= 8
+            o.n_schedule = len(v)
+            for i, x in enumerate(v):
+                o.schedule[i] = x
+            continue
         setattr(o, k, v)
     return o
 

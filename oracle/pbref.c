@@ -809,19 +809,42 @@ static void tet_geom(const pbref *p, int64_t t, double grad[4][3], double *vol)
     *vol = p->tvol[t];
 }
 
-/* Scheme functions: N, N', N'' for LIN (t), T3 (t + t^3/6), HS (sinh t);
+/* Scheme functions: N, N', N'' for LIN (t), the Taylor schemes T3 / T5 / T7
+ * (sinh t = sum over odd j of t^j / j!, cut after j = 3, 5, 7), HS (sinh t);
  * NONE has no reaction term. */
+static int taylor_order(int s)
+{
+    return s == PBREF_T3 ? 3 : s == PBREF_T5 ? 5 : s == PBREF_T7 ? 7 : 0;
+}
+/* sum of t^j / j! over j <= m with j of the parity of m */
+static double series(int m, double t)
+{
+    double sum = 0.0, term = (m % 2) ? t : 1.0;
+    for (int j = m % 2; j <= m; j += 2) {
+        sum += term;
+        term *= t * t / ((j + 1.0) * (j + 2.0));
+    }
+    return sum;
+}
 static double sch_f(int s, double t)
 {
-    return s == PBREF_NONE ? 0.0 : s == PBREF_LIN ? t : s == PBREF_T3 ? t + t * t * t / 6.0 : sinh(t);
+    if (s == PBREF_NONE) return 0.0;
+    if (s == PBREF_LIN) return t;
+    if (s == PBREF_HS) return sinh(t);
+    return series(taylor_order(s), t);
 }
 static double sch_d1(int s, double t)
 {
-    return s == PBREF_NONE ? 0.0 : s == PBREF_LIN ? 1.0 : s == PBREF_T3 ? 1.0 + 0.5 * t * t : cosh(t);
+    if (s == PBREF_NONE) return 0.0;
+    if (s == PBREF_LIN) return 1.0;
+    if (s == PBREF_HS) return cosh(t);
+    return series(taylor_order(s) - 1, t);
 }
 static double sch_d2(int s, double t)
 {
-    return s == PBREF_NONE ? 0.0 : s == PBREF_LIN ? 0.0 : s == PBREF_T3 ? t : sinh(t);
+    if (s == PBREF_NONE || s == PBREF_LIN) return 0.0;
+    if (s == PBREF_HS) return sinh(t);
+    return series(taylor_order(s) - 2, t);
 }
 
 void pbref_stiffness_entries(const pbref *p, int32_t *rows, int32_t *cols, double *vals)
@@ -1657,6 +1680,8 @@ void pbref_opts_default(pbref_opts *o)
     o->omega_method = PBREF_OMEGA_NEWTON;
     o->nonlinear_method = PBREF_NEWTON;
     o->r_e = 1.4;
+    o->n_schedule = 0;
+    for (int k = 0; k < 8; ++k) o->schedule[k] = PBREF_HS;
 }
 
 static int all_finite(int64_t n, const double *x)
@@ -1957,7 +1982,9 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
     double omega_last = 1.0, e_km1 = 0.0, e_km2 = 0.0; /* e of the two previous steps */
     int k;
     for (k = 1; k <= o->max_newton && status == 0; ++k) {
-        int s = (k == 1 && o->scheme_first == PBREF_T3) ? PBREF_T3 : PBREF_HS;
+        int s;
+        if (o->n_schedule > 0) s = k <= o->n_schedule ? o->schedule[k - 1] : PBREF_HS;
+        else s = (k == 1 && o->scheme_first == PBREF_T3) ? PBREF_T3 : PBREF_HS;
         for (int64_t i = 0; i < n; ++i) phi[i] = phi_lin[i] + phi_nl[i];
         /* c = b - A Phi ; d = c - N_s(u) */
         pbref_apply_A(p, phi, c);
@@ -2009,7 +2036,7 @@ int pbref_solve(pbref *p, const pbref_opts *o, pbref_result *res, double *phi_li
         }
         if (o->l_e > 0 && ek < o->l_e) frozen = 1;
         if (o->tol_gr0 > o->tol_gr && ek < 1250.0 * tol) tol = fmax(o->tol_gr, 0.1 * tol);
-        if (ek < o->tol_nl) {
+        if (ek < o->tol_nl && s == PBREF_HS) { /* a Taylor step solves another equation */
             ++k;
             break;
         }

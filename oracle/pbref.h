@@ -20,9 +20,11 @@ extern "C" {
 
 typedef struct pbref pbref;
 
-enum { PBREF_LIN = 0, PBREF_T3 = 1, PBREF_HS = 2 };
+/* reaction term N(t): LIN t, T3 / T5 / T7 the sinh series through t^3/3!,
+ * t^5/5!, t^7/7! (the schemes of Sec. 3.3.1), HS sinh t */
+enum { PBREF_LIN = 0, PBREF_T3 = 1, PBREF_HS = 2, PBREF_T5 = 3, PBREF_T7 = 4 };
 /* no reaction term (N = J = H = 0): the linear operator A of the Picard step */
-enum { PBREF_NONE = 3 };
+enum { PBREF_NONE = 7 };
 
 /* quadrature rules (weights normalised to sum 1 over the reference cell) */
 int pbref_rule_tri6(double *bary /*6x3*/, double *w /*6*/);
@@ -83,6 +85,9 @@ typedef struct {
     int nonlinear_method;     /* PBREF_NEWTON or PBREF_PICARD (Sec. 2.4.2) */
     double r_e;               /* Picard: the relaxation factor is searched again only when
                                * e_{k-2} / e_{k-1} < r_e (0: at every step) */
+    int n_schedule;           /* > 0: iteration k <= n_schedule uses schedule[k-1], later ones HS
+                               * (T3-T5-HS and the like, Sec. 3.3.1); 0: the scheme_first rule */
+    int schedule[8];
 } pbref_opts;
 
 enum { PBREF_NEWTON = 0, PBREF_PICARD = 1 };

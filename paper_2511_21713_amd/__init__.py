@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpbfb.so")
 
 OK, EINVAL, EMESH, ECHARGE, ENOMEM, EDEVICE, ENOTCONV, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
-LIN, T3, HS = 0, 1, 2
+LIN, T3, HS, T5, T7 = 0, 1, 2, 3, 4
 MEM_HOST, MEM_DEVICE = 0, 1
 OMEGA_NEWTON, OMEGA_BISECT, OMEGA_SECANT, OMEGA_BSEC, OMEGA_NEWTON_BS, OMEGA_BSEC_DF = 0, 1, 2, 3, 4, 5
 NEWTON, PICARD = 0, 1
@@ -45,7 +45,8 @@ class SolveOpts(C.Structure):
                 ("max_newton", C.c_int), ("max_omega_it", C.c_int), ("gmres_restart", C.c_int),
                 ("max_gmres", C.c_int), ("krylov_fp32", C.c_int), ("precond", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("hip_graph", C.c_int), ("omega_method", C.c_int),
-                ("nonlinear_method", C.c_int), ("r_e", C.c_double)]
+                ("nonlinear_method", C.c_int), ("r_e", C.c_double), ("n_schedule", C.c_int),
+                ("schedule", C.c_int * 8)]
 
 
 class Result(C.Structure):
@@ -132,11 +133,21 @@ def _check(code):
 
 
 def default_opts(**kw):
+    """pbfb_solve_opts with the library defaults; schedule=[T3, T5, ...] sets
+    n_schedule and the schedule entries."""
     o = SolveOpts()
     lib().pbfb_solve_opts_default(C.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "schedule":
+            v = list(v)
+            if len(v) > 8:
+                raise ValueError("at most 8 scheduled iterations")
+            o.n_schedule = len(v)
+            for i, x in enumerate(v):
+                o.schedule[i] = x
+            continue
         setattr(o, k, v)
     return o
 

@@ -442,7 +442,7 @@ pbfb_status pbfb_residual(pbfb_problem *pp, int scheme, const double *phi, doubl
 {
     API_BEGIN
     PB_CHECK(pp && phi && F, PBFB_EINVAL, "null argument");
-    PB_CHECK(scheme >= PBFB_LIN && scheme <= PBFB_HS, PBFB_EINVAL, "unknown scheme");
+    PB_CHECK(scheme >= PBFB_LIN && scheme <= PBFB_T7, PBFB_EINVAL, "unknown scheme");
     Problem &p = pp->p;
     hipStream_t s = pick_stream(p, stream);
     ensure_all(p, s);
@@ -464,7 +464,7 @@ pbfb_status pbfb_apply_jacobian(pbfb_problem *pp, int scheme, const double *phi,
 {
     API_BEGIN
     PB_CHECK(pp && phi && v && Jv, PBFB_EINVAL, "null argument");
-    PB_CHECK(scheme >= PBFB_LIN && scheme <= PBFB_HS, PBFB_EINVAL, "unknown scheme");
+    PB_CHECK(scheme >= PBFB_LIN && scheme <= PBFB_T7, PBFB_EINVAL, "unknown scheme");
     Problem &p = pp->p;
     hipStream_t s = pick_stream(p, stream);
     ensure_all(p, s);
@@ -506,6 +506,8 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->omega_method = PBFB_OMEGA_NEWTON;
     o->nonlinear_method = PBFB_NEWTON;
     o->r_e = 1.4;
+    o->n_schedule = 0;
+    for (int k = 0; k < 8; ++k) o->schedule[k] = PBFB_HS;
 }
 
 } // extern "C"
@@ -523,6 +525,12 @@ void check_opts(const pbfb_solve_opts &O)
              PBFB_EINVAL, "bad relaxation-search options");
     PB_CHECK((O.nonlinear_method == PBFB_NEWTON || O.nonlinear_method == PBFB_PICARD) && O.r_e >= 0.0, PBFB_EINVAL,
              "bad nonlinear-iteration options");
+    PB_CHECK(O.scheme_first == PBFB_T3 || O.scheme_first == PBFB_HS, PBFB_EINVAL, "bad scheme_first");
+    PB_CHECK(O.n_schedule >= 0 && O.n_schedule <= 8, PBFB_EINVAL, "bad n_schedule");
+    for (int k = 0; k < O.n_schedule; ++k)
+        PB_CHECK(O.schedule[k] == PBFB_T3 || O.schedule[k] == PBFB_T5 || O.schedule[k] == PBFB_T7 ||
+                     O.schedule[k] == PBFB_HS,
+                 PBFB_EINVAL, "schedule entries must be PBFB_T3, PBFB_T5, PBFB_T7 or PBFB_HS");
 }
 } // namespace pbfb
 

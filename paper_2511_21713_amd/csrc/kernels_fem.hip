@@ -151,7 +151,7 @@ __global__ void k_surface_coupling(int64_t nv, const int32_t *__restrict__ v2t_p
 }
 
 // ---------------------------------------------------------------------------
-// reaction terms: calN, calN', calN'' for LIN / T3 / HS
+// reaction terms: calN, calN', calN'' for LIN / T3 / T5 / T7 / HS
 // ---------------------------------------------------------------------------
 // sinh and cosh together: below 1/2 in magnitude from their Taylor series
 // (terms through t^15 and t^16, remainder below 1e-19 relative), above from
@@ -189,10 +189,16 @@ __device__ inline void scheme_eval(int s, double t, double &f0, double &f1, doub
         f0 = t;
         f1 = 1.0;
         f2 = 0.0;
-    } else if (s == PBFB_T3) {
-        f0 = t + t * t * t * (1.0 / 6.0);
-        f1 = 1.0 + 0.5 * t * t;
-        f2 = t;
+    } else if (s == PBFB_T3 || s == PBFB_T5 || s == PBFB_T7) {
+        // truncated sinh series: f0 through t^o / o!, f1 = f0' through
+        // t^(o-1) / (o-1)!, f2 = f0'' through t^(o-2) / (o-2)!  (o = 3, 5, 7)
+        const bool o5 = s != PBFB_T3, o7 = s == PBFB_T7;
+        const double t2 = t * t;
+        const double a5 = o5 ? t2 * (1.0 / 20.0) * (1.0 + (o7 ? t2 * (1.0 / 42.0) : 0.0)) : 0.0;
+        f0 = t * (1.0 + t2 * (1.0 / 6.0) * (1.0 + a5));
+        const double a4 = o5 ? t2 * (1.0 / 12.0) * (1.0 + (o7 ? t2 * (1.0 / 30.0) : 0.0)) : 0.0;
+        f1 = 1.0 + t2 * 0.5 * (1.0 + a4);
+        f2 = t * (1.0 + (o5 ? t2 * (1.0 / 6.0) * (1.0 + (o7 ? t2 * (1.0 / 20.0) : 0.0)) : 0.0));
     } else {
         sinh_cosh(t, f0, f1);
         f2 = f0;

@@ -6,7 +6,8 @@
 // Newton: Phi = Phi_L + Phi_NL, c = b - A Phi, d = c - N(u); solve
 // (A + J) Delta = d; Phi_NL += omega Delta; stop when omega ||Delta||_2 <
 // Tol_NL.  The first step uses the cubic Taylor scheme (T3), later steps
-// sinh (HS).  omega is the root of f_d (eq. fd=0) found by Newton's method
+// sinh (HS), unless a schedule of Taylor orders is given (T3-T5-HS and the
+// like of Sec. 3.3.1).  omega is the root of f_d (eq. fd=0) found by Newton's method
 // with the derivative of App. A (second derivative r'' = -H[Delta], the
 // minus sign the printed formula drops), started at 2 in the T3 step and 1
 // afterwards, each iterate clamped to [omega_min, omega_max]; it is frozen
@@ -155,7 +156,8 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
 {
     Problem &p = *r.p;
     const int64_t n = p.n(), nn = p.nn;
-    r.sch = (r.k == 1 && r.o.scheme_first == PBFB_T3) ? PBFB_T3 : PBFB_HS;
+    if (r.o.n_schedule > 0) r.sch = r.k <= r.o.n_schedule ? r.o.schedule[r.k - 1] : PBFB_HS;
+    else r.sch = (r.k == 1 && r.o.scheme_first == PBFB_T3) ? PBFB_T3 : PBFB_HS;
     vec_add(n, r.phil, r.phinl, r.phi, s);
     coupled_apply_linear(p, r.phi, r.c, s);
     vec_axpby(n, 1.0, p.d_b, -1.0, r.c, s);
@@ -404,7 +406,8 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
     }
     if (o.l_e > 0 && ek < o.l_e) r.frozen = true;
     if (o.tol_gr0 > o.tol_gr && ek < 1250.0 * r.tol) r.tol = std::max(o.tol_gr, 0.1 * r.tol);
-    if (ek < o.tol_nl) return true;
+    // only a sinh step ends the iteration: a Taylor step solves another equation
+    if (ek < o.tol_nl && r.sch == PBFB_HS) return true;
     if (r.k >= o.max_newton) {
         r.status = PBFB_ENOTCONV;
         return true;

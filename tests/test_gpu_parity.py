@@ -79,7 +79,7 @@ def test_rhs_matches_oracle(case):
     assert rel(b, o.rhs()) < 1e-12
 
 
-@pytest.mark.parametrize("scheme", [oracle.LIN, oracle.T3, oracle.HS])
+@pytest.mark.parametrize("scheme", [oracle.LIN, oracle.T3, oracle.T5, oracle.T7, oracle.HS])
 def test_residual_and_jacobian_match_oracle(case, scheme):
     name, prob, o, g = case
     rng = np.random.default_rng(11 + scheme)
@@ -171,6 +171,26 @@ def test_picard_iterates_like_oracle(case):
     tight = dict(kw, omega_method=1, tol_nl=1e-9, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, max_omega_it=200,
                  max_gmres=20000)
     rg = g.solve(**tight)
+    ro, _, _ = o.solve(**tight)
+    assert rg["status"] == 0
+    assert abs(rg["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
+
+
+@pytest.mark.parametrize("sched", [(1, 3), (1, 3, 4, 4)])
+def test_scheme_schedule_iterates_like_oracle(case, sched):
+    """T3-T5-HS and T3-T5-T7-T7-HS (Sec. 3.3.1) at the App. B settings: the
+    same steps and relaxation factors as the oracle, and at tight tolerances
+    the same energy as T3-HS."""
+    name, prob, o, g = case
+    rg = g.solve(schedule=sched)
+    ro, _, _ = o.solve(schedule=sched)
+    log(f"  {name} schedule {sched}: gpu it {rg['newton_iters']} omega {np.round(rg['omega'], 4)}; "
+        f"oracle it {ro['newton_iters']}")
+    assert rg["status"] == 0 and ro["status"] == 0
+    assert rg["newton_iters"] == ro["newton_iters"] and rg["omega_iters"] == ro["omega_iters"]
+    assert np.allclose(rg["omega"], ro["omega"], atol=1e-6)
+    tight = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    rg = g.solve(schedule=sched, **tight)
     ro, _, _ = o.solve(**tight)
     assert rg["status"] == 0
     assert abs(rg["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
@@ -290,6 +310,10 @@ def test_error_codes(ctx):
     with pytest.raises(pb.PbfbError) as e:
         g.solve()
     assert e.value.code == pb.ECHARGE
+    for bad_opts in (dict(schedule=[0]), dict(schedule=[1, 7]), dict(n_schedule=9), dict(scheme_first=0)):
+        with pytest.raises(pb.PbfbError) as e:
+            g.solve(**bad_opts)
+        assert e.value.code == pb.EINVAL
     bad = prob.tri_m[1:]  # open surface
     g2 = pb.Problem(ctx)
     with pytest.raises(pb.PbfbError) as e:

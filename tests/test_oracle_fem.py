@@ -6,6 +6,8 @@ which is how a reaction term is tested):
   N(u)_a = eps_s kappa^2 int calN(u_h) phi_a,  J(u) v = eps_s kappa^2 int calN'(u_h) v_h phi_a,
   H(u)[v]_a = eps_s kappa^2 int calN''(u_h) v_h^2 phi_a
 """
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -77,7 +79,7 @@ def test_mass_closed_form_and_volume(cfg0):
     assert abs(one @ (M @ one) - vol.sum()) <= 1e-13 * vol.sum()
 
 
-@pytest.mark.parametrize("scheme", [oracle.LIN, oracle.T3, oracle.HS])
+@pytest.mark.parametrize("scheme", [oracle.LIN, oracle.T3, oracle.T5, oracle.T7, oracle.HS])
 def test_jacobian_at_zero_is_scaled_mass(cfg0, scheme):
     p, o = cfg0
     M = coo(p, o.mass_entries(p.tets.shape[0]))
@@ -98,9 +100,37 @@ def test_nonlinear_on_constant_field(cfg0):
     assert np.allclose(o.fem_nonlinear(oracle.HS, u), k2 * np.sinh(c) * lumped, rtol=1e-13)
     assert np.allclose(o.fem_nonlinear(oracle.T3, u), k2 * (c + c ** 3 / 6) * lumped, rtol=1e-13)
     assert np.allclose(o.fem_nonlinear(oracle.LIN, u), k2 * c * lumped, rtol=1e-13)
+    # the Taylor schemes of Sec. 3.3.1: sinh cut after the 5th and 7th powers
+    assert np.allclose(o.fem_nonlinear(oracle.T5, u), k2 * (c + c ** 3 / 6 + c ** 5 / 120) * lumped, rtol=1e-13)
+    assert np.allclose(o.fem_nonlinear(oracle.T7, u),
+                       k2 * (c + c ** 3 / 6 + c ** 5 / 120 + c ** 7 / 5040) * lumped, rtol=1e-13)
+    # and their derivatives, the cosh and sinh series cut one and two orders lower
+    one = np.ones(p.n_nodes)
+    for s_, d1, d2 in ((oracle.T5, 1 + c ** 2 / 2 + c ** 4 / 24, c + c ** 3 / 6),
+                       (oracle.T7, 1 + c ** 2 / 2 + c ** 4 / 24 + c ** 6 / 720, c + c ** 3 / 6 + c ** 5 / 120)):
+        assert np.allclose(o.fem_jacobian(s_, u, one), k2 * d1 * lumped, rtol=1e-13)
+        assert np.allclose(o.fem_hessian(s_, u, one), k2 * d2 * lumped, rtol=1e-13)
 
 
-@pytest.mark.parametrize("scheme", [oracle.T3, oracle.HS])
+def test_taylor_schemes_approach_sinh():
+    """On a constant field the gap between a Taylor scheme and sinh is the
+    series remainder, bounded by cosh(c) c^(o+2) / (o+2)!; each order closes
+    most of the gap of the one before."""
+    p = cached_config(0)
+    o = oracle.Oracle.from_problem(p)
+    for c in (0.5, 1.5, 3.0):
+        u = np.full(p.n_nodes, c)
+        hs = o.fem_nonlinear(oracle.HS, u)
+        gaps = []
+        for s_, order in ((oracle.T3, 3), (oracle.T5, 5), (oracle.T7, 7)):
+            gap = np.abs(o.fem_nonlinear(s_, u) - hs).max() / np.abs(hs).max()
+            bound = np.cosh(c) * c ** (order + 2) / math.factorial(order + 2) / np.sinh(c)
+            assert 0 < gap <= bound * (1 + 1e-9)
+            gaps.append(gap)
+        assert gaps[0] > gaps[1] > gaps[2]
+
+
+@pytest.mark.parametrize("scheme", [oracle.T3, oracle.T5, oracle.T7, oracle.HS])
 def test_jacobian_and_hessian_by_central_differences(cfg0, scheme):
     p, o = cfg0
     rng = np.random.default_rng(2)
