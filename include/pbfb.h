@@ -258,10 +258,11 @@ pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *t
  * kernel evaluations per interface) and adds the touching-pair blocks and
  * 1/2 M kept from setup: for instances whose dense blocks would not fit
  * (the paper switches to a fast multipole method above 90k vertices for the
- * same reason).  The single-layer blocks of the GMRES preconditioner are
- * then their inverse diagonal (the approximate inverse needs dense rows), so
- * Krylov iteration counts are higher.  Results equal the dense mode's to
- * rounding.  With PBFB_MIXED the FP32 evaluation rounds each apply's source
+ * same reason).  The 1-ring approximate inverse of the single layers (the
+ * GMRES preconditioner) is then built from the near field of V' (for each
+ * row, the columns within three rings of its vertex) instead of full rows,
+ * so Krylov iteration counts differ a little from dense mode.  Results equal
+ * the dense mode's to rounding.  With PBFB_MIXED the FP32 evaluation rounds each apply's source
  * strengths, so the apply is linear to ~1e-7 only and GMRES tolerances below
  * that are not reached.  Marks the operators stale. */
 enum { PBFB_BEM_DENSE = 0, PBFB_BEM_MATRIX_FREE = 1 };

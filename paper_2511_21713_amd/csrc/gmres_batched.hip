@@ -175,14 +175,10 @@ __global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, co
     } else {
         const int w = k < d.nn + d.nm ? 0 : 1;
         const int64_t off = d.nn + (w == 0 ? 0 : d.nm), i = k - off;
-        if (!d.sp_ptr[w]) {
-            zv = d.dinv[k] * pc_src(d, s, k); // matrix-free: no dense rows for the approximate inverse
-        } else {
-            double acc = 0.0;
-            for (int32_t e = d.sp_ptr[w][i]; e < d.sp_ptr[w][i + 1]; ++e)
-                acc = fma(d.sp_val[w][e], pc_src(d, s, off + d.sp_col[w][e]), acc);
-            zv = acc;
-        }
+        double acc = 0.0;
+        for (int32_t e = d.sp_ptr[w][i]; e < d.sp_ptr[w][i + 1]; ++e)
+            acc = fma(d.sp_val[w][e], pc_src(d, s, off + d.sp_col[w][e]), acc);
+        zv = acc;
         d.z[k] = zv;
     }
     if (last && s.st == G_RES) d.x[k] += zv;
@@ -611,7 +607,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.cheb_ratio = J.cheb_ratio;
         d.lmax = J.lmax;
         for (int w = 0; w < 2; ++w) {
-            d.sp_ptr[w] = p.bem_mf ? nullptr : p.surf[w].ring_ptr; // null: inverse diagonal
+            d.sp_ptr[w] = p.surf[w].ring_ptr;
             d.sp_col[w] = p.surf[w].ring;
             d.sp_val[w] = p.surf[w].spai;
         }

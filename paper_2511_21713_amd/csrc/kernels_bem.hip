@@ -1010,18 +1010,29 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         S.vdiag = A.alloc<double>(T.nv);
         S.tpv = nullptr;
         S.mpos = nullptr;
-        S.ring_ptr = S.ring = nullptr;
-        S.spai = nullptr;
+        S.nf_ptr = S.nf_col = S.nf_row = nullptr;
+        S.nf_val = nullptr;
+        S.nf_nnz = 0;
+        S.ring_ptr = A.upload(T.ring_ptr, s);
+        S.ring = A.upload(T.ring, s);
+        S.spai = A.alloc<double>(T.ring.size());
         if (p.bem_mf) {
-            // matrix-free: resident touching-pair blocks and the Morton position of each triangle
+            // matrix-free: resident touching-pair blocks, the Morton position of
+            // each triangle and the near-field rows of the preconditioner
             S.tpv = A.alloc<double>(18 * S.ntp);
             std::vector<int32_t> mpos(T.nt);
             for (int64_t m = 0; m < T.nt; ++m) mpos[T.morton[m]] = int32_t(m);
             S.mpos = A.upload(mpos, s);
+            near_pattern(T);
+            S.nf_nnz = int64_t(T.nf_col.size());
+            std::vector<int32_t> nf_row(S.nf_nnz);
+            for (int64_t i = 0; i < T.nv; ++i)
+                for (int32_t k = T.nf_ptr[i]; k < T.nf_ptr[i + 1]; ++k) nf_row[k] = int32_t(i);
+            S.nf_ptr = A.upload(T.nf_ptr, s);
+            S.nf_col = A.upload(T.nf_col, s);
+            S.nf_row = A.upload(nf_row, s);
+            S.nf_val = A.alloc<double>(S.nf_nnz);
         } else {
-            S.ring_ptr = A.upload(T.ring_ptr, s);
-            S.ring = A.upload(T.ring, s);
-            S.spai = A.alloc<double>(T.ring.size());
             const int64_t ldt = bem_ld(T.nv);
             if (f32) S.B = A.alloc<float>(T.nv * ldt);
             else S.B = A.alloc<double>(T.nv * ldt);
@@ -1056,6 +1067,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         if (p.timing) p.timer.end(s);
         PB_HIP(hipGetLastError());
         mf_vdiag(p, w, s);
+        mf_spai(p, w, s);
         PB_HIP(hipStreamSynchronize(s));
         S.tile = -1;
         p.bem_ready[w] = true;

@@ -269,4 +269,150 @@ void mf_vdiag(Problem &p, int w, hipStream_t s)
     PB_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// preconditioner of the single layers without stored rows: the 1-ring
+// sparse approximate inverse (row i minimises || m^T V' - e_i^T ||_2 over m
+// on the 1-ring P(i)) built from the near field of V' instead of its full
+// rows.  The near field keeps, for every row a, the columns within three
+// rings of a, each entry the same Galerkin integral as the dense operator
+// (touching pairs from the resident blocks, the others by the 6 x 6 rule).
+// ---------------------------------------------------------------------------
+// entry e = (a, c): sum over triangles tau at a and sigma at c (one thread per entry)
+template <bool YUK>
+__global__ void k_mf_near(int64_t nnz, const int32_t *__restrict__ nf_row, const int32_t *__restrict__ nf_col,
+                          const int32_t *__restrict__ v2t_ptr, const int32_t *__restrict__ v2t,
+                          const int32_t *__restrict__ tp_ptr, const int32_t *__restrict__ tp_sig,
+                          const double *__restrict__ tpv, const double *__restrict__ qp,
+                          const double *__restrict__ area, double kappa, double sV, QRule6 R,
+                          double *__restrict__ nf_val)
+{
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t a = nf_row[e], c = nf_col[e];
+    double acc = 0.0;
+    for (int32_t ea = v2t_ptr[a]; ea < v2t_ptr[a + 1]; ++ea) {
+        const int32_t ta = v2t[ea] / 3, la = v2t[ea] % 3;
+        for (int32_t ec = v2t_ptr[c]; ec < v2t_ptr[c + 1]; ++ec) {
+            const int32_t sc = v2t[ec] / 3, lc = v2t[ec] % 3;
+            int32_t pp = -1;
+            for (int32_t k = tp_ptr[ta]; k < tp_ptr[ta + 1]; ++k)
+                if (tp_sig[k] == sc) {
+                    pp = k;
+                    break;
+                }
+            if (pp >= 0) { // touching pair: the resident V block
+                acc += tpv[18 * int64_t(pp) + 3 * la + lc];
+                continue;
+            }
+            const double *X = qp + 18 * int64_t(ta), *Y = qp + 18 * int64_t(sc);
+            double sum = 0.0;
+            for (int p = 0; p < 6; ++p) {
+                double sp = 0.0;
+                for (int q = 0; q < 6; ++q) {
+                    const double d0 = X[3 * p] - Y[3 * q], d1 = X[3 * p + 1] - Y[3 * q + 1],
+                                 d2 = X[3 * p + 2] - Y[3 * q + 2];
+                    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    const double g = YUK ? exp(-kappa * r) / r : 1.0 / r;
+                    sp += R.w[q] * R.b[q][lc] * g;
+                }
+                sum += R.w[p] * R.b[p][la] * sp;
+            }
+            acc += area[ta] * area[sc] * INV4PI * sum;
+        }
+    }
+    nf_val[e] = sV * acc;
+}
+
+// one 64-thread workgroup per row i: lanes take the (a, b) pairs of the Gram
+// matrix of the near-field rows P(i), each a merge of two ascending sparse
+// rows; lane 0 solves the normal equations by Cholesky
+__global__ void __launch_bounds__(64)
+    k_mf_spai(int64_t nv, const int32_t *__restrict__ ring_ptr, const int32_t *__restrict__ ring,
+              const int32_t *__restrict__ nf_ptr, const int32_t *__restrict__ nf_col,
+              const double *__restrict__ nf_val, double *__restrict__ val, int *__restrict__ bad)
+{
+    __shared__ double G[MAXRING][MAXRING + 1];
+    __shared__ double rhs[MAXRING];
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (i >= nv) return;
+    const int p0 = ring_ptr[i], m = ring_ptr[i + 1] - p0;
+    const int npair = m * (m + 1) / 2;
+    for (int pr = lane; pr < npair; pr += 64) {
+        int a = int((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+        while (a * (a + 1) / 2 > pr) --a;
+        while ((a + 1) * (a + 2) / 2 <= pr) ++a;
+        const int b = pr - a * (a + 1) / 2;
+        const int32_t ra = ring[p0 + a], rb = ring[p0 + b];
+        int32_t ka = nf_ptr[ra], kb = nf_ptr[rb];
+        const int32_t ea = nf_ptr[ra + 1], eb = nf_ptr[rb + 1];
+        double sum = 0.0;
+        while (ka < ea && kb < eb) {
+            const int32_t ca = nf_col[ka], cb = nf_col[kb];
+            if (ca == cb) sum = fma(nf_val[ka++], nf_val[kb++], sum);
+            else if (ca < cb) ++ka;
+            else ++kb;
+        }
+        G[a][b] = G[b][a] = sum;
+    }
+    for (int a = lane; a < m; a += 64) {
+        const int32_t ra = ring[p0 + a];
+        double v = 0.0; // V'(P_a, i): i is in the 1-ring of P_a, hence in its pattern
+        for (int32_t k = nf_ptr[ra]; k < nf_ptr[ra + 1]; ++k)
+            if (nf_col[k] == int32_t(i)) v = nf_val[k];
+        rhs[a] = v;
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    bool ok = true;
+    for (int a = 0; a < m && ok; ++a) {
+        double d = G[a][a];
+        for (int k = 0; k < a; ++k) d -= G[a][k] * G[a][k];
+        if (!(d > 0.0)) {
+            ok = false;
+            break;
+        }
+        G[a][a] = sqrt(d);
+        for (int b = a + 1; b < m; ++b) {
+            double t = G[b][a];
+            for (int k = 0; k < a; ++k) t -= G[b][k] * G[a][k];
+            G[b][a] = t / G[a][a];
+        }
+    }
+    if (!ok) {
+        atomicOr(bad, 4);
+        for (int a = 0; a < m; ++a) val[p0 + a] = 0.0;
+        return;
+    }
+    for (int a = 0; a < m; ++a) {
+        double t = rhs[a];
+        for (int k = 0; k < a; ++k) t -= G[a][k] * rhs[k];
+        rhs[a] = t / G[a][a];
+    }
+    for (int a = m - 1; a >= 0; --a) {
+        double t = rhs[a];
+        for (int k = a + 1; k < m; ++k) t -= G[k][a] * rhs[k];
+        rhs[a] = t / G[a][a];
+    }
+    for (int a = 0; a < m; ++a) val[p0 + a] = rhs[a];
+}
+
+void mf_spai(Problem &p, int w, hipStream_t s)
+{
+    const SurfaceDev &S = p.surf[w];
+    const bool yuk = (w == 1) && p.kappa > 0.0;
+    const double kappa = (w == 1) ? p.kappa : 0.0, sV = (w == 0) ? -1.0 : 1.0;
+    const QRule6 R = q6arg();
+    const dim3 g(nbk_(S.nf_nnz, 256));
+    if (yuk)
+        hipLaunchKernelGGL(k_mf_near<true>, g, dim3(256), 0, s, S.nf_nnz, S.nf_row, S.nf_col, S.v2t_ptr, S.v2t,
+                           S.tp_ptr, S.tp_sig, S.tpv, S.qp, S.area, kappa, sV, R, S.nf_val);
+    else
+        hipLaunchKernelGGL(k_mf_near<false>, g, dim3(256), 0, s, S.nf_nnz, S.nf_row, S.nf_col, S.v2t_ptr, S.v2t,
+                           S.tp_ptr, S.tp_sig, S.tpv, S.qp, S.area, kappa, sV, R, S.nf_val);
+    hipLaunchKernelGGL(k_mf_spai, dim3(unsigned(S.nv)), dim3(64), 0, s, S.nv, S.ring_ptr, S.ring, S.nf_ptr, S.nf_col,
+                       S.nf_val, S.spai, p.d_bad);
+    PB_HIP(hipGetLastError());
+}
+
 } // namespace pbfb

@@ -119,6 +119,8 @@ struct SurfaceTopo {
     // 1-ring pattern of the sparse approximate inverse
     std::vector<int32_t> ring_ptr, ring;
     int max_ring = 0;
+    // 3-ring pattern of the near-field single layer (matrix-free mode), built on first use
+    std::vector<int32_t> nf_ptr, nf_col;
 };
 
 struct SurfaceDev {
@@ -139,6 +141,10 @@ struct SurfaceDev {
     int32_t *tp_ptr = nullptr, *tp_sig = nullptr, *tp_tau = nullptr, *morton = nullptr;
     int64_t ntp = 0;
     int32_t *cslot = nullptr; // FEM-row slot of the coupling entry per (v2t entry, b)
+    // matrix-free mode: near-field V' on the 3-ring pattern (rows ascending)
+    int32_t *nf_ptr = nullptr, *nf_col = nullptr, *nf_row = nullptr;
+    double *nf_val = nullptr;
+    int64_t nf_nnz = 0;
     // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
     void *B = nullptr;
     double *vdiag = nullptr; // diagonal of the signed single-layer block V'
@@ -270,6 +276,9 @@ void fem_assemble_linear(Problem &p, hipStream_t s);                            
 // return at once unless it is G_ARN or G_RES
 void mf_apply(Problem &p, int w, const double *x, double *y, const int *st, hipStream_t s);
 void mf_vdiag(Problem &p, int w, hipStream_t s); // diagonal of V' from the resident touching-pair blocks
+// near-field V' on the 3-ring pattern and the 1-ring approximate inverse from it
+void mf_spai(Problem &p, int w, hipStream_t s);
+void near_pattern(SurfaceTopo &S); // host: the 3-ring pattern (nf_ptr, nf_col), once
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s);
 void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN,
                      double *rJ, double *rH, hipStream_t s);

@@ -31,9 +31,10 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
     const size_t elem = p.precision == PBFB_MIXED ? 4 : 8;
     size_t dense = 0, tmp = 0;
     for (int w = 0; w < 2 && p.bem_mf; ++w) {
-        // matrix-free: touching-pair blocks and the apply's strength buffers
+        // matrix-free: touching-pair blocks, the apply's strength buffers and
+        // the near-field rows of the preconditioner (~40 per vertex)
         const SurfaceTopo &T = p.topo[w];
-        dense += T.tp_sig.size() * 18 * 8 + size_t(T.nt) * 15 * 8;
+        dense += T.tp_sig.size() * 18 * 8 + size_t(T.nt) * 15 * 8 + size_t(T.nv) * 40 * 16;
     }
     for (int w = 0; w < 2 && !p.bem_mf; ++w) {
         // block tables are a host-side cache filled on first use

@@ -297,4 +297,34 @@ void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int3
     }
 }
 
+// 3-ring of each vertex (vertices within three edges of a triangle path,
+// itself included), ascending: the pattern of the near-field single layer
+// from which the matrix-free preconditioner is built
+void near_pattern(SurfaceTopo &S)
+{
+    if (!S.nf_ptr.empty()) return;
+    std::vector<int32_t> mark(S.nv, -1), cur, next;
+    S.nf_ptr.assign(S.nv + 1, 0);
+    S.nf_col.clear();
+    for (int64_t i = 0; i < S.nv; ++i) {
+        cur.assign(1, int32_t(i));
+        mark[i] = int32_t(i);
+        for (int depth = 0; depth < 3; ++depth) {
+            next = cur;
+            for (int32_t j : cur)
+                for (int32_t e = S.ring_ptr[j]; e < S.ring_ptr[j + 1]; ++e) {
+                    const int32_t k = S.ring[e];
+                    if (mark[k] != int32_t(i)) {
+                        mark[k] = int32_t(i);
+                        next.push_back(k);
+                    }
+                }
+            cur.swap(next);
+        }
+        std::sort(cur.begin(), cur.end());
+        S.nf_col.insert(S.nf_col.end(), cur.begin(), cur.end());
+        S.nf_ptr[i + 1] = int32_t(S.nf_col.size());
+    }
+}
+
 } // namespace pbfb
