@@ -100,10 +100,9 @@ __global__ void k_tri_morton(int64_t nt, const int32_t *__restrict__ morton, con
 // number of corners of any vertex of either block: the lists past it hold
 // only absent corners, whose +0 terms are skipped.
 template <int TA, int TB, int MS>
-__device__ inline void fold_tile_single(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
-                                 const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Vl,
-                                 const double *Kl, double *__restrict__ EV, double *__restrict__ EK, int64_t row0,
-                                 int64_t pB, int64_t ldE)
+__device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
+                                     const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Xl,
+                                     double *__restrict__ E, int64_t row0, int64_t pB, int64_t ldE)
 {
     constexpr int NT = TA * TB;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -117,54 +116,60 @@ __device__ inline void fold_tile_single(int tid, int tl, int sl, int nA, int nB,
     for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = 0.0;
     if (tid < TA * 3) acc[tid][TB * 3] = 0.0;
 #pragma unroll
-    for (int op = 0; op < 2; ++op) {
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = Xl[3 * a + b];
+    __syncthreads();
+    constexpr int RMAX = TA * 3;
+    constexpr int RPT = (RMAX + NT / (TB * 3) - 1) / (NT / (TB * 3)); // rows per thread, nB <= TB * 3
+    double colsum[RPT];
+    int nrow = 0;
+    if (colthread) {
 #pragma unroll
-            for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = op == 0 ? Vl[3 * a + b] : Kl[3 * a + b];
-        __syncthreads();
-        constexpr int RMAX = TA * 3;
-        constexpr int RPT = (RMAX + NT / (TB * 3) - 1) / (NT / (TB * 3)); // rows per thread, nB <= TB * 3
-        double colsum[RPT];
-        int nrow = 0;
-        if (colthread) {
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int sa = r0 + r * rstep;
-                double t = 0.0;
-                if (sa < RMAX) {
-                    double v[MS];
-#pragma unroll
-                    for (int l = 0; l < MS; ++l) v[l] = acc[sa][cb[l]];
-#pragma unroll
-                    for (int l = 0; l < MS; ++l) t += v[l];
-                    nrow = r + 1;
-                }
-                colsum[r] = t;
-            }
-        }
-        __syncthreads();
-        if (colthread)
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
-        __syncthreads();
-        double *E = op == 0 ? EV : EK;
-        if (colthread)
-            for (int ia = r0; ia < nA; ia += rstep) {
+        for (int r = 0; r < RPT; ++r) {
+            const int sa = r0 + r * rstep;
+            double t = 0.0;
+            if (sa < RMAX) {
                 double v[MS];
 #pragma unroll
-                for (int k = 0; k < MS; ++k) {
-                    const int ra = sSa[ia][k];
-                    v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
-                }
-                double t = 0.0;
+                for (int l = 0; l < MS; ++l) v[l] = acc[sa][cb[l]];
 #pragma unroll
-                for (int k = 0; k < MS; ++k) t += v[k];
-                E[(row0 + ia) * ldE + pB + jb] = t;
+                for (int l = 0; l < MS; ++l) t += v[l];
+                nrow = r + 1;
             }
-        __syncthreads();
+            colsum[r] = t;
+        }
     }
+    __syncthreads();
+    if (colthread)
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
+    __syncthreads();
+    if (colthread)
+        for (int ia = r0; ia < nA; ia += rstep) {
+            double v[MS];
+#pragma unroll
+            for (int k = 0; k < MS; ++k) {
+                const int ra = sSa[ia][k];
+                v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < MS; ++k) t += v[k];
+            E[(row0 + ia) * ldE + pB + jb] = t;
+        }
+    __syncthreads();
+}
+
+template <int TA, int TB, int MS>
+__device__ inline void fold_tile_single(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
+                                        const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Vl,
+                                        const double *Kl, double *__restrict__ EV, double *__restrict__ EK,
+                                        int64_t row0, int64_t pB, int64_t ldE)
+{
+    fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, EV, row0, pB, ldE);
+    fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Kl, EK, row0, pB, ldE);
 }
 
 // Fold of a tile's pair blocks onto the block's vertices through the shared
@@ -254,22 +259,34 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
 // TA x TB: target x source triangles of the tile, one pair per thread; MS:
 // bound on the corners of one vertex in one block (6 for meshes of vertex
-// valence <= 6, else MAXS)
-template <bool YUK, typename RT, int TA, int TB, int MS>
+// valence <= 6, else MAXS).
+// SYM (square tiles): each unordered pair is evaluated once.  Only tiles
+// with source block >= target block run, and in a diagonal tile only pairs
+// with the source after the target.  Besides V and K of (tau, sigma) a pair
+// also yields K of (sigma, tau): the kernel values are shared, only the
+// normal distance changes ((y_q - x).n_tau, the same for the six target
+// points, which lie in the plane of tau).  It is stored transposed, as
+// Kt[a][b] = K_{sigma tau}[b][a], in EKt with the layout of EK; V of
+// (sigma, tau) is the transpose of V of (tau, sigma).  The gather then
+// completes the operator: V = U_V + U_V^T, K = U_K + U_Kt^T.
+template <bool YUK, typename RT, int TA, int TB, int MS, bool SYM>
 __global__ void __launch_bounds__(TA * TB, 4)
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
                   const int32_t *__restrict__ A_slots, const int32_t *__restrict__ B_pref,
                   const int32_t *__restrict__ B_nv, const int32_t *__restrict__ B_slots, int64_t bA0,
-                  int64_t rowbase, double *__restrict__ EV, double *__restrict__ EK, int64_t ldE, double kappa,
-                  QRule6 R, QRule6F RF)
+                  int64_t rowbase, double *__restrict__ EV, double *__restrict__ EK, double *__restrict__ EKt,
+                  int64_t ldE, double kappa, QRule6 R, QRule6F RF)
 {
+    static_assert(!SYM || TA == TB, "symmetric evaluation needs square tiles");
     constexpr bool F32 = sizeof(RT) == 4;
     constexpr int NT = TA * TB;
+    if (SYM && int64_t(blockIdx.x) < bA0 + int64_t(blockIdx.y)) return; // lower tile: from its mirror
     __shared__ RT sX[TA][18];
     __shared__ RT sY[TB][18];
     __shared__ RT sN[TB][3];
+    __shared__ RT sNa[SYM ? TA : 1][3];
     __shared__ double sCa[F32 ? TA : 1][3], sCb[F32 ? TB : 1][3];
     __shared__ double sAa[TA], sAb[TB];
     __shared__ int sVa[TA][3], sVb[TB][3];
@@ -305,6 +322,7 @@ __global__ void __launch_bounds__(TA * TB, 4)
         int64_t m = bA * TA + tl;
         sVa[tl][c] = m < nt ? m_tri[3 * m + c] : -2;
         if constexpr (F32) sCa[tl][c] = m < nt ? cen[3 * m + c] : 0.0;
+        if constexpr (SYM) sNa[tl][c] = m < nt ? nq[3 * m + c] : RT(0);
     }
     if (tid < TA) sAa[tid] = (bA * TA + tid) < nt ? m_area[bA * TA + tid] : 0.0;
     if (tid < TB) sAb[tid] = (bB * TB + tid) < nt ? m_area[bB * TB + tid] : 0.0;
@@ -320,12 +338,15 @@ __global__ void __launch_bounds__(TA * TB, 4)
 
     // this thread's pair (target tl, source sl)
     const int tl = tid / TB, sl = tid % TB;
-    double Vl[9], Kl[9];
+    double Vl[9], Kl[9], Ktl[SYM ? 9 : 1];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Vl[k] = Kl[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < (SYM ? 9 : 1); ++k) Ktl[k] = 0.0;
     bool touch = false;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
+    if (SYM && bA == bB && sl <= tl) touch = true; // the mirror pair carries it
     if ((sVa[tl][0] >= 0) && (sVb[sl][0] >= 0) && !touch) {
         RT c0 = 0, c1 = 0, c2 = 0; // FP32: target frame relative to the source centroid
         if constexpr (F32) {
@@ -334,6 +355,14 @@ __global__ void __launch_bounds__(TA * TB, 4)
             c2 = float(sCa[tl][2] - sCb[sl][2]);
         }
         const RT n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
+        RT dm[SYM ? 6 : 1]; // (y_q - x).n_tau, the same for every target point x
+        if constexpr (SYM) {
+            const RT m0 = sNa[tl][0], m1 = sNa[tl][1], m2 = sNa[tl][2];
+            const RT xa0 = sX[tl][0] + c0, xa1 = sX[tl][1] + c1, xa2 = sX[tl][2] + c2;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                dm[q] = (sY[sl][3 * q] - xa0) * m0 + (sY[sl][3 * q + 1] - xa1) * m1 + (sY[sl][3 * q + 2] - xa2) * m2;
+        }
         const RT kap = RT(kappa);
         const double sc = sAa[tl] * sAb[sl] * INV4PI;
         // target point p outermost: 6-term source sums, then folded into the 3x3 blocks
@@ -380,6 +409,16 @@ __global__ void __launch_bounds__(TA * TB, 4)
             sk0 *= dn;
             sk1 *= dn;
             sk2 *= dn;
+            RT st0 = 0, st1 = 0, st2 = 0; // K of (sigma, tau): normal distance inside the source sum
+            if constexpr (SYM) {
+                RT hm[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hm[q] = hk[q] * dm[q];
+                const RT cm = oA0 * (hm[0] + hm[1] + hm[2]) + oA1 * (hm[3] + hm[4] + hm[5]);
+                st0 = cm + oD0 * hm[0] + oD1 * hm[3];
+                st1 = cm + oD0 * hm[1] + oD1 * hm[4];
+                st2 = cm + oD0 * hm[2] + oD1 * hm[5];
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double wa = sc * R.w[p] * R.b[p][a];
@@ -389,42 +428,60 @@ __global__ void __launch_bounds__(TA * TB, 4)
                 Kl[3 * a] += wa * double(sk0);
                 Kl[3 * a + 1] += wa * double(sk1);
                 Kl[3 * a + 2] += wa * double(sk2);
+                if constexpr (SYM) {
+                    Ktl[3 * a] += wa * double(st0);
+                    Ktl[3 * a + 1] += wa * double(st1);
+                    Ktl[3 * a + 2] += wa * double(st2);
+                }
             }
         }
     }
 
     if constexpr (F32) fold_tile_single<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
     else fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
+    if constexpr (SYM) {
+        __syncthreads();
+        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, reinterpret_cast<double (*)[TB * 3 + 1]>(acc), Ktl,
+                                  EKt, pA - rowbase, pB, ldE);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // 2. gather passes
 // ---------------------------------------------------------------------------
-// W[i][c] (+)= sum of E rows of vertex i that belong to target blocks [bA0, bA1)
+// W[i][c] (+)= sum of E rows of vertex i that belong to target blocks [bA0, bA1).
+// Symmetric evaluation (c_blk non-null): only E entries of tiles whose source
+// block (that of column c) is not below the target block were written, and
+// EKt / WKt carry the third operator.
 __global__ void k_bem_pass1(int64_t nv, int64_t SB, const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA,
                             const int32_t *__restrict__ LA_blk, int64_t bA0, int64_t bA1, int64_t rowbase,
-                            const double *__restrict__ EV, const double *__restrict__ EK, double *__restrict__ WV,
-                            double *__restrict__ WK, int first)
+                            const double *__restrict__ EV, const double *__restrict__ EK,
+                            const double *__restrict__ EKt, const int32_t *__restrict__ c_blk,
+                            double *__restrict__ WV, double *__restrict__ WK, double *__restrict__ WKt, int first)
 {
     const int64_t i = blockIdx.y;
     const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (c >= SB) return;
-    double sv = 0.0, sk = 0.0;
+    const int32_t cb = c_blk ? c_blk[c] : INT32_MAX;
+    double sv = 0.0, sk = 0.0, st = 0.0;
     bool any = false;
     for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) {
         const int32_t b = LA_blk[e];
-        if (b < bA0 || b >= bA1) continue;
+        if (b < bA0 || b >= bA1 || b > cb) continue;
         const int64_t r = LA[e] - rowbase;
         sv += EV[r * SB + c];
         sk += EK[r * SB + c];
+        if (c_blk) st += EKt[r * SB + c];
         any = true;
     }
     if (first) {
         WV[i * SB + c] = sv;
         WK[i * SB + c] = sk;
+        if (c_blk) WKt[i * SB + c] = st;
     } else if (any) {
         WV[i * SB + c] += sv;
         WK[i * SB + c] += sk;
+        if (c_blk) WKt[i * SB + c] += st;
     }
 }
 
@@ -443,6 +500,54 @@ __global__ void k_bem_pass2(int64_t nv, int64_t SB, int64_t ld, const int32_t *_
     }
     Bo[i * ld + j] = sK * k;
     Bo[i * ld + nv + j] = sV * v;
+}
+
+// T[i][j] = sc * sum W[i][cols of j] (the mirrored double layer, ld nv)
+__global__ void k_bem_pass2_one(int64_t nv, int64_t SB, const int32_t *__restrict__ LB_ptr,
+                                const int32_t *__restrict__ LB, const double *__restrict__ W, double sc,
+                                double *__restrict__ T)
+{
+    const int64_t i = blockIdx.y;
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j >= nv) return;
+    double v = 0.0;
+    for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) v += W[i * SB + LB[e]];
+    T[i * nv + j] = sc * v;
+}
+
+// Completion of a symmetric evaluation on 32 x 32 tiles (I <= J, both
+// mirror tiles handled by one workgroup): V(i, j) = U_V(i, j) + U_V(j, i)
+// and K(i, j) = U_K(i, j) + T(j, i), where B holds [U_K | U_V] per row.
+constexpr int SYMT = 32;
+__global__ void __launch_bounds__(256) k_bem_symm(int64_t nv, int64_t ld, double *__restrict__ B,
+                                                  const double *__restrict__ T)
+{
+    const int64_t I = blockIdx.y, J = blockIdx.x;
+    if (J < I) return;
+    __shared__ double a[SYMT][SYMT + 1], b[SYMT][SYMT + 1], t1[SYMT][SYMT + 1], t2[SYMT][SYMT + 1];
+    const int tx = threadIdx.x % SYMT, ty = threadIdx.x / SYMT;
+    for (int r = ty; r < SYMT; r += 256 / SYMT) {
+        const int64_t i = I * SYMT + r, j = J * SYMT + tx;   // tile (I, J)
+        const int64_t i2 = J * SYMT + r, j2 = I * SYMT + tx; // tile (J, I)
+        const bool in1 = i < nv && j < nv, in2 = i2 < nv && j2 < nv;
+        a[r][tx] = in1 ? B[i * ld + nv + j] : 0.0;
+        t2[r][tx] = in1 ? T[i * nv + j] : 0.0;
+        b[r][tx] = in2 ? B[i2 * ld + nv + j2] : 0.0;
+        t1[r][tx] = in2 ? T[i2 * nv + j2] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < SYMT; r += 256 / SYMT) {
+        const int64_t i = I * SYMT + r, j = J * SYMT + tx;
+        if (i < nv && j < nv) {
+            B[i * ld + nv + j] = a[r][tx] + b[tx][r];
+            B[i * ld + j] += t1[tx][r];
+        }
+        const int64_t i2 = J * SYMT + r, j2 = I * SYMT + tx;
+        if (I != J && i2 < nv && j2 < nv) {
+            B[i2 * ld + nv + j2] = b[r][tx] + a[tx][r];
+            B[i2 * ld + j2] += t2[tx][r];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -854,6 +959,7 @@ static const BlockSideDev &device_side(Problem &p, int w, int bs, hipStream_t s)
     D.L_ptr = A.upload(H.L_ptr, s);
     D.L = A.upload(H.L, s);
     D.L_blk = A.upload(H.L_blk, s);
+    D.slot_blk = A.upload(H.slot_blk, s);
     return S.sides.emplace(bs, D).first->second;
 }
 
@@ -864,21 +970,24 @@ struct RegArgs {
     const double *cen = nullptr, *m_area = nullptr;
     BlockSideDev A, B;
     int64_t b0 = 0, b1 = 0, rowbase = 0;
-    double *EV = nullptr, *EK = nullptr;
+    double *EV = nullptr, *EK = nullptr, *EKt = nullptr; // EKt: square (symmetric) shapes only
     double kappa = 0.0;
     int ms = MAXS; // largest corner count of a vertex in a block, both sides
     QRule6 R;
     QRule6F RF;
 };
 
+// square shapes evaluate each unordered pair once (SYM)
+template <int TA, int TB> constexpr bool shape_sym() { return TA == TB; }
 template <int TA, int TB, int MS> static void launch_regular_ms(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
 {
     const dim3 grid(unsigned(a.B.nb), unsigned(a.b1 - a.b0));
+    constexpr bool SYM = shape_sym<TA, TB>();
 #define PB_REG(Y, RT)                                                                                              \
-    hipLaunchKernelGGL((k_bem_regular<Y, RT, TA, TB, MS>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,               \
+    hipLaunchKernelGGL((k_bem_regular<Y, RT, TA, TB, MS, SYM>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,          \
                        static_cast<const RT *>(a.xq), static_cast<const RT *>(a.nq), a.cen, a.m_area, a.A.pref,     \
-                       a.A.nvb, a.A.slots, a.B.pref, a.B.nvb, a.B.slots, a.b0, a.rowbase, a.EV, a.EK, a.B.S,         \
-                       a.kappa, a.R, a.RF)
+                       a.A.nvb, a.A.slots, a.B.pref, a.B.nvb, a.B.slots, a.b0, a.rowbase, a.EV, a.EK, a.EKt,        \
+                       a.B.S, a.kappa, a.R, a.RF)
     if (f32) {
         if (yuk) PB_REG(true, float);
         else PB_REG(false, float);
@@ -916,10 +1025,18 @@ static int tile_key(int precision, bool yuk, int64_t nt)
 }
 
 // Autotuner: times the regular tile kernel of every candidate shape on the
-// same sample of this surface (the first min(nt, 512) Morton-ordered target
-// triangles against all source triangles; one warm-up launch, then the
-// fastest of three timed launches) and returns the shape with the shortest
-// time per target triangle.  Runs with the context workspace held.
+// same sample of this surface (min(nt, 512) Morton-ordered target triangles
+// from the middle of the order against all source triangles, so that a
+// symmetric shape, which skips the source blocks below the target block,
+// does the average share of its work; one warm-up launch, then the fastest
+// of three timed launches) and returns the shape with the shortest time per
+// target triangle.  Runs with the context workspace held.
+static void tune_range(const BlockSide &HA, int64_t nsample, int64_t &b0, int64_t &b1)
+{
+    const int64_t nbs = std::min<int64_t>((nsample + HA.bs - 1) / HA.bs, HA.nb);
+    b0 = (HA.nb - nbs) / 2;
+    b1 = b0 + nbs;
+}
 static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream_t s)
 {
     SurfaceTopo &T = p.topo[w];
@@ -927,8 +1044,9 @@ static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream
     size_t need = 0;
     for (int k = 0; k < N_TILE_SHAPES; ++k) {
         const BlockSide &HA = block_side(T, TILE_SHAPES[k].ta), &HB = block_side(T, TILE_SHAPES[k].tb);
-        const int64_t nbs = (nsample + HA.bs - 1) / HA.bs;
-        need = std::max(need, size_t(HA.pref[nbs]) * size_t(HB.S) * 2);
+        int64_t b0, b1;
+        tune_range(HA, nsample, b0, b1);
+        need = std::max(need, size_t(HA.pref[b1] - HA.pref[b0]) * size_t(HB.S) * 3);
     }
     double *E = p.ctx->asm_ws.doubles(need);
     hipEvent_t e0, e1;
@@ -941,12 +1059,13 @@ static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream
         a.A = device_side(p, w, HA.bs, s);
         a.B = device_side(p, w, HB.bs, s);
         a.ms = std::max(HA.ms_max, HB.ms_max);
-        a.b0 = 0;
-        a.b1 = (nsample + HA.bs - 1) / HA.bs;
-        a.rowbase = 0;
+        tune_range(HA, nsample, a.b0, a.b1);
+        a.rowbase = HA.pref[a.b0];
+        const size_t nEs = size_t(HA.pref[a.b1] - HA.pref[a.b0]) * size_t(HB.S);
         a.EV = E;
-        a.EK = E + size_t(HA.pref[a.b1]) * size_t(HB.S);
-        const int64_t tris = std::min<int64_t>(a.b1 * HA.bs, T.nt);
+        a.EK = E + nEs;
+        a.EKt = E + 2 * nEs;
+        const int64_t tris = std::min<int64_t>(a.b1 * HA.bs, T.nt) - a.b0 * HA.bs;
         launch_regular(k, yuk, f32, a, s);
         float ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1117,11 +1236,19 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         b0 = b1;
     }
     const bool stage64 = f32;
+    // square shapes evaluate each unordered pair once: a third operator
+    // (mirrored double layer) goes through E, W and an nv x nv matrix T
+    const bool sym = TILE_SHAPES[shape].ta == TILE_SHAPES[shape].tb;
+    const int nops = sym ? 3 : 2;
     const size_t nE = size_t(chunk_rows) * DB.S, nW = size_t(nv) * DB.S;
-    double *ws = p.ctx->asm_ws.doubles(2 * nE + 2 * nW + (stage64 ? size_t(nv) * ld : 0) + 3 * nv + 18 * S.ntp);
-    double *EV = ws, *EK = EV + nE, *WV = EK + nE, *WK = WV + nW;
-    double *B64 = stage64 ? WK + nW : static_cast<double *>(S.B);
-    double *vx = (stage64 ? B64 + size_t(nv) * ld : WK + nW), *tpv = vx + 3 * nv;
+    const size_t nT = sym && nE < size_t(nv) * nv ? size_t(nv) * nv : 0; // else T reuses EV after the gather
+    double *ws = p.ctx->asm_ws.doubles(nops * (nE + nW) + nT + (stage64 ? size_t(nv) * ld : 0) + 3 * nv +
+                                       18 * S.ntp);
+    double *EV = ws, *EK = EV + nE, *EKt = sym ? EK + nE : nullptr, *WV = EV + nops * nE, *WK = WV + nW;
+    double *WKt = sym ? WK + nW : nullptr;
+    double *Tm = nT ? WV + nops * nW : (sym ? EV : nullptr);
+    double *B64 = stage64 ? WV + nops * nW + nT : static_cast<double *>(S.B);
+    double *vx = (stage64 ? B64 + size_t(nv) * ld : WV + nops * nW + nT), *tpv = vx + 3 * nv;
     bool first = true;
     for (const auto &ch : chunks) {
         ra.b0 = ch.first;
@@ -1129,12 +1256,14 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         ra.rowbase = HA.pref[ch.first];
         ra.EV = EV;
         ra.EK = EK;
+        ra.EKt = EKt;
         if (p.timing) p.timer.begin(T_ASM, s);
         launch_regular(shape, yuk, f32, ra, s);
         if (p.timing) p.timer.end(s);
         PB_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_bem_pass1, dim3(nblk(DB.S, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, DA.L_ptr,
-                           DA.L, DA.L_blk, ra.b0, ra.b1, ra.rowbase, EV, EK, WV, WK, first ? 1 : 0);
+                           DA.L, DA.L_blk, ra.b0, ra.b1, ra.rowbase, EV, EK, EKt,
+                           sym ? static_cast<const int32_t *>(DB.slot_blk) : nullptr, WV, WK, WKt, first ? 1 : 0);
         PB_HIP(hipGetLastError());
         first = false;
     }
@@ -1143,6 +1272,13 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, ld, DB.L_ptr, DB.L,
                        WV, WK, sV, sK, B64);
     PB_HIP(hipGetLastError());
+    if (sym) {
+        hipLaunchKernelGGL(k_bem_pass2_one, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, DB.L_ptr,
+                           DB.L, WKt, sK, Tm);
+        const unsigned nbt = unsigned((nv + SYMT - 1) / SYMT);
+        hipLaunchKernelGGL(k_bem_symm, dim3(nbt, nbt), dim3(256), 0, s, nv, ld, B64, Tm);
+        PB_HIP(hipGetLastError());
+    }
     // touching pairs
     hipLaunchKernelGGL(k_gather_coords, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, S.g, p.d_x, vx);
     GL4 G = gl4arg();

@@ -96,12 +96,14 @@ struct BlockSide {
     int64_t nb = 0, S = 0;
     std::vector<int32_t> pref, nvb, slots;
     std::vector<int32_t> L_ptr, L, L_blk;
+    std::vector<int32_t> slot_blk; // block of each slot
 };
 struct BlockSideDev {
     int bs = 0;
     int64_t nb = 0, S = 0;
     int32_t *pref = nullptr, *nvb = nullptr, *slots = nullptr;
     int32_t *L_ptr = nullptr, *L = nullptr, *L_blk = nullptr;
+    int32_t *slot_blk = nullptr;
 };
 
 // host-side topology of one boundary surface

@@ -44,7 +44,10 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
             const size_t SA = size_t(block_side(T, TILE_SHAPES[k].ta).S), SB = size_t(block_side(T, TILE_SHAPES[k].tb).S);
             const size_t rows = std::min(SA, std::max<size_t>(3 * TILE_SHAPES[k].ta, (size_t(1) << 30) / SB) +
                                                   3 * TILE_SHAPES[k].ta); // one assembly chunk of E
-            tmp = std::max(tmp, rows * SB * 16 + size_t(T.nv) * SB * 16 +
+            // square shapes: a third operator in E and W, and an nv x nv matrix
+            const size_t ops = TILE_SHAPES[k].ta == TILE_SHAPES[k].tb ? 3 : 2;
+            const size_t tm = ops == 3 ? size_t(T.nv) * T.nv * 8 : 0;
+            tmp = std::max(tmp, rows * SB * 8 * ops + size_t(T.nv) * SB * 8 * ops + tm +
                                     (p.precision == PBFB_MIXED ? size_t(T.nv) * bem_ld(T.nv) * 8 : 0));
         }
     }

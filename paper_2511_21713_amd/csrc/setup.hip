@@ -57,6 +57,9 @@ const BlockSide &block_side(SurfaceTopo &S, int bs)
         B.pref[b + 1] = B.pref[b] + B.nvb[b];
     }
     B.S = B.pref[B.nb];
+    B.slot_blk.resize(B.S);
+    for (int64_t b = 0; b < B.nb; ++b)
+        for (int32_t k = B.pref[b]; k < B.pref[b + 1]; ++k) B.slot_blk[k] = int32_t(b);
     B.slots.assign(B.S * MAXS, -1);
     std::vector<std::vector<std::pair<int32_t, int32_t>>> vlist(S.nv);
     for (int64_t b = 0; b < B.nb; ++b) {
