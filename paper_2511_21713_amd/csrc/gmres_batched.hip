@@ -66,7 +66,7 @@ struct GDesc {
 };
 
 struct GState {
-    int st, j, total, code, napply, pad;
+    int st, j, total, code, napply, fin; // fin: the cycle ended on the residual estimate
     double beta, target, hn;
 };
 
@@ -149,7 +149,7 @@ __global__ void k_cheb_coef(const GDesc *__restrict__ D, int nb)
 
 __device__ inline double pc_src(const GDesc &d, const GState &s, int64_t r)
 {
-    return s.st == G_RES ? d.t[r] : vget(d, s.j, r);
+    return (s.st == G_RES || s.st == G_FIN) ? d.t[r] : vget(d, s.j, r);
 }
 
 // first term (FEM rows), the approximate inverse (surface rows) or the diagonal
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, co
 {
     const WItem it = wl[blockIdx.x];
     const GState s = S[it.inst];
-    if (s.st != G_ARN && s.st != G_RES) return;
+    if (s.st != G_ARN && s.st != G_RES && s.st != G_FIN) return;
     const GDesc &d = D[it.inst];
     const int64_t k = it.b + threadIdx.x;
     if (k >= d.n) return;
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) k_bprec0(const WItem *__restrict__ wl, co
         zv = acc;
         d.z[k] = zv;
     }
-    if (last && s.st == G_RES) d.x[k] += zv;
+    if (last && (s.st == G_RES || s.st == G_FIN)) d.x[k] += zv;
 }
 
 // Chebyshev term `step` >= 1 of the FEM block: one workgroup per 64-row
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
 {
     const WItem it = wl[blockIdx.x];
     const GState s = S[it.inst];
-    if (s.st != G_ARN && s.st != G_RES) return;
+    if (s.st != G_ARN && s.st != G_RES && s.st != G_FIN) return;
     const GDesc &d = D[it.inst];
     if (d.pc != PBFB_PC_CHEB_SPAI || step >= d.cheb_k) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
     d.dk[row] = dv;
     const double zv = zp[row] + dv;
     zn[row] = zv;
-    if (step == d.cheb_k - 1 && s.st == G_RES) d.x[row] += zv;
+    if (step == d.cheb_k - 1 && (s.st == G_RES || s.st == G_FIN)) d.x[row] += zv;
 }
 
 // work item: inst, a = interface (0/1), b = first row of the workgroup.  One
@@ -411,6 +411,13 @@ __global__ void __launch_bounds__(64) k_bcontrol(const GDesc *__restrict__ D, GS
     if (lane == 0) ss = S[q];
     __syncthreads();
     const int st0 = ss.st;
+    if (st0 == G_FIN) {
+        if (lane == 0) {
+            S[q].st = G_DONE;
+            atomicAdd(ndone, 1);
+        }
+        return;
+    }
     if (st0 != G_ARN && st0 != G_RES && st0 != G_INIT) return;
     const int m = d.m;
     const double nr = sqrt(*d.nrm);
@@ -450,6 +457,9 @@ __global__ void __launch_bounds__(64) k_bcontrol(const GDesc *__restrict__ D, GS
                 atomicAdd(ndone, 1);
             } else if (res <= ss.target || nr == 0.0 || ss.j == m || ss.total >= d.maxit) {
                 ss.st = G_UPD;
+                // converged on the estimate: no true-residual check, except with an
+                // FP32 basis, whose restarts are refinement steps that need it
+                ss.fin = (res <= ss.target || nr == 0.0) && !d.vf32;
             }
         }
         __syncthreads();
@@ -526,7 +536,7 @@ __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, con
         last = atomicAdd(cnt, 1) == int(d.nch) - 1;
         if (last) {
             *cnt = 0;
-            S[it.inst].st = G_RES;
+            S[it.inst].st = s.fin ? G_FIN : G_RES;
         }
     }
 }

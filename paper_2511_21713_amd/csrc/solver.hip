@@ -159,8 +159,12 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
     if (r.o.n_schedule > 0) r.sch = r.k <= r.o.n_schedule ? r.o.schedule[r.k - 1] : PBFB_HS;
     else r.sch = (r.k == 1 && r.o.scheme_first == PBFB_T3) ? PBFB_T3 : PBFB_HS;
     vec_add(n, r.phil, r.phinl, r.phi, s);
-    coupled_apply_linear(p, r.phi, r.c, s);
-    vec_axpby(n, 1.0, p.d_b, -1.0, r.c, s);
+    if (!r.c_ready) { // else c was carried over from the last step's omega search
+        coupled_apply_linear(p, r.phi, r.c, s);
+        vec_axpby(n, 1.0, p.d_b, -1.0, r.c, s);
+        r.res->applies += 1; // c = b - A Phi
+    }
+    r.c_ready = false;
     fem_nonlinear(p, r.sch, r.phi, r.rN, s);
     PB_HIP(hipMemcpyAsync(r.d, r.c, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_sub_fem, dim3(nbk(nn, 256)), dim3(256), 0, s, nn, r.c, r.rN, r.d);
@@ -173,7 +177,6 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
     if (r.o.nonlinear_method == PBFB_PICARD) fem_assemble_linear(p, s);
     else fem_assemble_jacobian(p, r.sch, r.phi, s);
     r.job = make_job(r, r.d, r.D, s);
-    r.res->applies += 1; // c = b - A Phi
     return true;
 }
 
@@ -356,6 +359,7 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
     const int idx = std::min(r.k - 1, 63);
     double omega;
     int oit = 0;
+    bool searched = false; // r.pv = -A Delta was formed
     if (!o.omega_auto) {
         omega = o.omega_fixed;
     } else if (r.frozen) {
@@ -367,6 +371,7 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
         // p = -A Delta
         coupled_apply_linear(p, r.D, r.pv, s);
         r.res->applies += 1;
+        searched = true;
         vec_axpby(n, -1.0, r.pv, 0.0, r.pv, s);
         const double pp = dot(p, r.pv, r.pv, n, s);
         PB_HIP(hipMemcpyAsync(r.rv, r.c, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -394,6 +399,11 @@ static bool newton_post(NewtonRun &r, hipStream_t s)
         r.omega_last = omega;
     }
     vec_axpby(n, omega, r.D, 1.0, r.phinl, s);
+    if (searched) {
+        // A (Phi + omega Delta) = A Phi - omega p: the next c = b - A Phi without an apply
+        vec_axpby(n, omega, r.pv, 1.0, r.c, s);
+        r.c_ready = true;
+    }
     const double ek = omega * std::sqrt(dot(p, r.D, r.D, n, s));
     r.res->omega[idx] = omega;
     r.res->e_k[idx] = ek;
