@@ -66,6 +66,9 @@ enum { PBFB_MEM_HOST = 0, PBFB_MEM_DEVICE = 1 };
 
 /* ---- context ------------------------------------------------------------ */
 pbfb_status pbfb_ctx_create(int device, pbfb_ctx **out);
+/* Problems of the context should be destroyed first.  Any that are still
+ * alive are detached: every later call on them returns PBFB_ESTATE except
+ * pbfb_problem_destroy, which still releases their device memory. */
 void pbfb_ctx_destroy(pbfb_ctx *ctx);
 const char *pbfb_last_error(void);
 
@@ -227,7 +230,8 @@ pbfb_status pbfb_server_create(pbfb_ctx *ctx, size_t hbm_budget_bytes, int max_s
 pbfb_status pbfb_server_submit(pbfb_server *s, pbfb_problem *p, const pbfb_solve_opts *o, uint64_t *ticket);
 /* done = 1 once the request finished; res (nullable) then receives its result */
 pbfb_status pbfb_server_poll(pbfb_server *s, uint64_t ticket, int *done, pbfb_result *res);
-/* drains every submitted request, then stops the threads and frees the server */
+/* drains every submitted request, then stops the threads and frees the server;
+ * a server must be destroyed before its context */
 pbfb_status pbfb_server_destroy(pbfb_server *s);
 
 /* Energy split {Total, LC, NC, dG_Omega_i} (kcal/mol) of given Phi_L, Phi_NL

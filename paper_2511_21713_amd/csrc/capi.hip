@@ -258,6 +258,15 @@ using namespace pbfb;
     }                                                                                                  \
     return PBFB_OK;
 
+// a problem whose context was destroyed is detached: only pbfb_problem_destroy accepts it
+static Problem &live(pbfb_problem *pp)
+{
+    PB_CHECK(pp, PBFB_EINVAL, "null problem");
+    PB_CHECK(pp->p.ctx, PBFB_ESTATE, "the problem's context was destroyed");
+    return pp->p;
+}
+static const Problem &live(const pbfb_problem *pp) { return live(const_cast<pbfb_problem *>(pp)); }
+
 static hipStream_t pick_stream(Problem &p, void *s)
 {
     hipStream_t st = s ? static_cast<hipStream_t>(s) : p.ctx->stream;
@@ -302,6 +311,12 @@ pbfb_status pbfb_ctx_create(int device, pbfb_ctx **out)
 void pbfb_ctx_destroy(pbfb_ctx *ctx)
 {
     if (!ctx) return;
+    {
+        // problems still alive are detached (they keep their own device memory)
+        std::lock_guard<std::mutex> lk(ctx->c.live_mu);
+        for (Problem *q : ctx->c.live) q->ctx = nullptr;
+        ctx->c.live.clear();
+    }
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     (void)hipStreamDestroy(ctx->c.stream);
@@ -316,7 +331,12 @@ pbfb_status pbfb_problem_create(pbfb_ctx *ctx, int precision, pbfb_problem **out
     PB_CHECK(precision == PBFB_FP64 || precision == PBFB_MIXED, PBFB_EINVAL, "unknown precision");
     auto *p = new pbfb_problem;
     p->p.ctx = &ctx->c;
+    p->p.device = ctx->c.device;
     p->p.precision = precision;
+    {
+        std::lock_guard<std::mutex> lk(ctx->c.live_mu);
+        ctx->c.live.insert(&p->p);
+    }
     *out = p;
     API_END
 }
@@ -325,7 +345,11 @@ void pbfb_problem_destroy(pbfb_problem *pp)
 {
     if (!pp) return;
     Problem &p = pp->p;
-    (void)hipSetDevice(p.ctx->device);
+    if (p.ctx) {
+        std::lock_guard<std::mutex> lk(p.ctx->live_mu);
+        p.ctx->live.erase(&p);
+    }
+    (void)hipSetDevice(p.device);
     (void)hipDeviceSynchronize();
     p.timer.destroy();
     release_all_scratch(p);
@@ -348,7 +372,7 @@ pbfb_status pbfb_set_mesh(pbfb_problem *pp, int64_t n_nodes, const double *nodes
     PB_CHECK(pp && nodes && tets && tri_m && tri_s, PBFB_EINVAL, "null argument");
     PB_CHECK(n_nodes >= 4 && n_tets >= 1 && n_tri_m >= 4 && n_tri_s >= 4, PBFB_EINVAL, "mesh too small");
     PB_CHECK(n_nodes < (int64_t(1) << 31) && 4 * n_tets < (int64_t(1) << 31), PBFB_EINVAL, "mesh too large");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     PB_HIP(hipSetDevice(p.ctx->device));
     (void)hipDeviceSynchronize();
     invalidate_geometry(p);
@@ -370,7 +394,7 @@ pbfb_status pbfb_set_charges(pbfb_problem *pp, int64_t n, const double *xyz, con
 {
     API_BEGIN
     PB_CHECK(pp && n >= 0 && (n == 0 || (xyz && z)), PBFB_EINVAL, "bad charge arguments");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     p.nq = n;
     p.q.resize(4 * n);
     for (int64_t k = 0; k < n; ++k) {
@@ -390,7 +414,7 @@ pbfb_status pbfb_set_params(pbfb_problem *pp, double eps_in, double eps_out, dou
     PB_CHECK(eps_in > 0 && eps_out > 0, PBFB_EINVAL, "permittivities must be positive");
     PB_CHECK(kappa >= 0 && std::isfinite(kappa), PBFB_EINVAL, "kappa must be >= 0");
     PB_CHECK(temperature_K > 0, PBFB_EINVAL, "temperature must be positive");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     const bool geo = p.eps_m != eps_in || p.eps_s != eps_out;
     const bool kap = p.kappa != kappa;
     p.eps_m = eps_in;
@@ -413,7 +437,7 @@ pbfb_status pbfb_get_sizes(const pbfb_problem *pp, int64_t *n_nodes, int64_t *n_
 {
     API_BEGIN
     PB_CHECK(pp, PBFB_EINVAL, "null problem");
-    const Problem &p = pp->p;
+    const Problem &p = live(pp);
     PB_CHECK(p.have_mesh, PBFB_ESTATE, "no mesh");
     if (n_nodes) *n_nodes = p.nn;
     if (n_m) *n_m = p.topo[0].nv;
@@ -431,7 +455,7 @@ pbfb_status pbfb_setup(pbfb_problem *pp, void *stream)
 {
     API_BEGIN
     PB_CHECK(pp, PBFB_EINVAL, "null problem");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     hipStream_t s = pick_stream(p, stream);
     ensure_all(p, s);
     PB_HIP(hipStreamSynchronize(s));
@@ -443,7 +467,7 @@ pbfb_status pbfb_residual(pbfb_problem *pp, int scheme, const double *phi, doubl
     API_BEGIN
     PB_CHECK(pp && phi && F, PBFB_EINVAL, "null argument");
     PB_CHECK(scheme >= PBFB_LIN && scheme <= PBFB_T7, PBFB_EINVAL, "unknown scheme");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     hipStream_t s = pick_stream(p, stream);
     ensure_all(p, s);
     const int64_t n = p.n();
@@ -465,7 +489,7 @@ pbfb_status pbfb_apply_jacobian(pbfb_problem *pp, int scheme, const double *phi,
     API_BEGIN
     PB_CHECK(pp && phi && v && Jv, PBFB_EINVAL, "null argument");
     PB_CHECK(scheme >= PBFB_LIN && scheme <= PBFB_T7, PBFB_EINVAL, "unknown scheme");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     hipStream_t s = pick_stream(p, stream);
     ensure_all(p, s);
     const int64_t n = p.n();
@@ -545,7 +569,7 @@ pbfb_status pbfb_solve(pbfb_problem *pp, const pbfb_solve_opts *o, pbfb_result *
     pbfb_solve_opts_default(&def);
     const pbfb_solve_opts &O = o ? *o : def;
     check_opts(O);
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     hipStream_t s = pick_stream(p, stream);
     const int64_t n = p.n();
     double *dout = nullptr;
@@ -599,7 +623,7 @@ pbfb_status pbfb_energy(pbfb_problem *pp, const double *phi_lin, const double *p
 {
     API_BEGIN
     PB_CHECK(pp && phi_lin && out, PBFB_EINVAL, "null argument");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     hipStream_t s = pick_stream(p, stream);
     ensure_rhs(p, s);
     const int64_t n = p.n();
@@ -613,7 +637,7 @@ pbfb_status pbfb_export_bem(pbfb_problem *pp, int surf, double *V, double *K)
 {
     API_BEGIN
     PB_CHECK(pp && (surf == 0 || surf == 1), PBFB_EINVAL, "bad argument");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     PB_CHECK(!p.bem_mf, PBFB_ESTATE, "matrix-free mode stores no boundary operator");
     hipStream_t s = pick_stream(p, nullptr);
     ensure_bem(p, surf, s);
@@ -639,7 +663,7 @@ pbfb_status pbfb_export_rhs(pbfb_problem *pp, double *b)
 {
     API_BEGIN
     PB_CHECK(pp && b, PBFB_EINVAL, "null argument");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     hipStream_t s = pick_stream(p, nullptr);
     ensure_rhs(p, s);
     PB_HIP(hipMemcpyAsync(b, p.d_b, sizeof(double) * p.n(), hipMemcpyDeviceToHost, s));
@@ -659,7 +683,7 @@ pbfb_status pbfb_set_bem_mode(pbfb_problem *pp, int mode)
 {
     API_BEGIN
     PB_CHECK(pp && (mode == PBFB_BEM_DENSE || mode == PBFB_BEM_MATRIX_FREE), PBFB_EINVAL, "bad boundary-operator mode");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     const bool mf = mode == PBFB_BEM_MATRIX_FREE;
     if (mf != p.bem_mf) {
         p.bem_mf = mf;
@@ -678,7 +702,7 @@ pbfb_status pbfb_set_tile_shape(pbfb_problem *pp, int ta, int tb)
         k = tile_shape_index(ta, tb);
         PB_CHECK(k >= 0, PBFB_EINVAL, "tile shape is not one of 16x32, 8x32, 8x64, 16x16, 8x16 (or 0x0 for tuned)");
     }
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     if (k != p.tile_fixed) {
         p.tile_fixed = k;
         p.bem_ready[0] = p.bem_ready[1] = false;
@@ -708,7 +732,7 @@ pbfb_status pbfb_timing(pbfb_problem *pp, int which, double *avg_ms, int64_t *co
 {
     API_BEGIN
     PB_CHECK(pp && which >= 0 && which < T_NCLASS, PBFB_EINVAL, "bad argument");
-    Problem &p = pp->p;
+    Problem &p = live(pp);
     PB_HIP(hipSetDevice(p.ctx->device));
     p.timer.drain();
     const int64_t c = p.timer.cnt[which];

@@ -5,6 +5,7 @@
 
 #include <chrono>
 #include <map>
+#include <set>
 #include <mutex>
 #include <cstdint>
 #include <string>
@@ -166,12 +167,16 @@ struct Workspace {
     double *doubles(size_t n);
 };
 
+struct Problem;
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     Workspace asm_ws;
     // tuned tile shape per (precision, kernel, size class); guarded by asm_ws.mu
     std::map<int, int> tile_choice;
+    // problems created in this context and not yet destroyed
+    std::mutex live_mu;
+    std::set<Problem *> live;
 };
 
 enum TimerClass { T_APPLY = 0, T_GEMV = 1, T_SPMV = 2, T_ASM = 3, T_SING = 4, T_PREC = 5, T_NCLASS = 6 };
@@ -206,7 +211,8 @@ struct ScratchBuf {
 };
 
 struct Problem {
-    Ctx *ctx = nullptr;
+    Ctx *ctx = nullptr; // null once the context is destroyed (detached problem)
+    int device = 0;     // the context's device, kept for the problem's own release
     int precision = PBFB_FP64;
     bool have_mesh = false, have_charges = false, have_params = false;
     bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
@@ -258,7 +264,9 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
 const BlockSide &block_side(SurfaceTopo &S, int bs); // built on first use
 constexpr int SLICE = 64; // FEM rows per sliced-ELL slice: one wavefront
 // Krylov state of a batched GMRES instance (the state word every batched kernel reads)
-enum GSt { G_INIT = 0, G_ARN = 1, G_UPD = 2, G_RES = 3, G_DONE = 4, G_FAIL = 5 };
+// FIN: the cycle ended on the residual estimate; the step only adds the
+// preconditioned update to x (no true-residual apply) and the solve is done
+enum GSt { G_INIT = 0, G_ARN = 1, G_UPD = 2, G_RES = 3, G_DONE = 4, G_FAIL = 5, G_FIN = 6 };
 void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int32_t> &col,
                         std::vector<int32_t> &n2t_ptr, std::vector<int32_t> &n2t, std::vector<int32_t> &slot4,
                         std::vector<int32_t> &diag, std::vector<int32_t> cslot[2]);
@@ -332,6 +340,7 @@ struct NewtonRun {
     double tol = 0.0, omega_last = 1.0;
     double e_km1 = 0.0, e_km2 = 0.0; // e of the two previous nonlinear steps
     bool frozen = false;
+    bool c_ready = false; // c already holds b - A Phi for the next step
     double *phil = nullptr, *phinl = nullptr, *phi = nullptr, *c = nullptr, *d = nullptr, *D = nullptr;
     double *pv = nullptr, *rv = nullptr, *rN = nullptr, *rJ = nullptr, *rH = nullptr, *dinv = nullptr;
     double *lmax = nullptr; // Chebyshev bound (device) and its partial maxima

@@ -240,6 +240,7 @@ pbfb_status pbfb_server_submit(pbfb_server *sv, pbfb_problem *pp, const pbfb_sol
     try {
         PB_CHECK(sv && pp && ticket, PBFB_EINVAL, "null argument");
         Problem &p = pp->p;
+        PB_CHECK(p.ctx, PBFB_ESTATE, "the problem's context was destroyed");
         PB_CHECK(p.have_mesh && p.have_charges && p.have_params, PBFB_ESTATE, "problem not fully specified");
         PB_CHECK(p.ctx == sv->s.ctx, PBFB_EINVAL, "problem belongs to another context");
         pbfb_solve_opts O;

@@ -326,3 +326,25 @@ def test_error_codes(ctx):
     with pytest.raises(pb.PbfbError) as e:
         g3.setup()
     assert e.value.code == pb.EMESH
+
+
+def test_problem_outliving_its_context():
+    """A context destroyed before its problems detaches them: calls on them
+    fail with PBFB_ESTATE, destroying them still works, and a new context is
+    unaffected (finalizers of garbage cycles may run in any order)."""
+    import paper_2511_21713_amd as pb
+    prob = cached_config(0)
+    c2 = pb.Context(0)
+    g = pb.Problem.from_inputs(c2, prob)
+    g.setup()
+    c2.close()
+    with pytest.raises(pb.PbfbError) as e:
+        g.residual(oracle.HS, np.zeros(g.n))
+    assert e.value.code == pb.ESTATE
+    g.close()
+    c3 = pb.Context(0)
+    g3 = pb.Problem.from_inputs(c3, prob)
+    g3.setup()
+    g3.close()
+    c3.close()
+
