@@ -69,9 +69,14 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def gemv_bytes(nm, ns, elem):
-    # algorithmic bytes of one dense launch: both [K'|V'] operators (n x 2n),
-    # their packed FP64 inputs (2n) and FP64 outputs (n)
+def gemv_bytes(nm, ns, elem, sym=False):
+    # algorithmic bytes of one dense apply: both [K'|V'] operators (n x 2n),
+    # their packed FP64 inputs (2n) and FP64 outputs (n).  With the symmetric
+    # use of the stored single layer (square-tile assembly) only K' and the
+    # lower triangle of V' with its diagonal are read (the sparse Delta rows,
+    # ~0.1 % of the bytes, are left out)
+    if sym:
+        return sum(n * n * elem + n * (n + 1) // 2 * elem + 2 * n * 8 + n * 8 for n in (nm, ns))
     return sum(n * 2 * n * elem + 2 * n * 8 + n * 8 for n in (nm, ns))
 
 
@@ -350,7 +355,8 @@ def main():
     gemv_ms, gemv_cnt = f64["timing"]["gemv"]
     apply_ms, apply_cnt = f64["timing"]["apply"]
     asm_ms, asm_cnt = f64["timing"]["assembly"]
-    gb = gemv_bytes(nm, ns, 8)
+    sym = all(a == b for a, b in f64["tiles"].values())  # square tiles: symmetric use of V'
+    gb = gemv_bytes(nm, ns, 8, sym)
     achieved = gb / (gemv_ms * 1e-3) / 1e9 if gemv_ms else None
     res = f64["res"]
     applies = res["applies"]
@@ -376,7 +382,9 @@ def main():
                   "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"],
                   "omega": res["omega"], "status": res["status"], "coupled_applies_per_solve": applies},
         "kernel_ms": {"gemv": gemv_ms, "coupled_apply": apply_ms, "bem_assembly_launch": asm_ms},
-        "roofline": {"bound": "hbm", "kernel": "k_bgemv / k_gemv (gemv_rows: dense [K'|V'] FP64 GEMV, both interfaces)",
+        "roofline": {"bound": "hbm", "kernel": ("k_bgemv + k_bgemv_fin / k_gemv + k_gemv_fin (gemv_rows_sym: K' and the "
+                                                "lower triangle of V', FP64, both interfaces)" if sym else
+                                                "k_bgemv / k_gemv (gemv_rows: dense [K'|V'] FP64 GEMV, both interfaces)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": (GEMV_TRAFFIC["bytes"] if (args.config == GEMV_TRAFFIC["config"] and
@@ -428,7 +436,8 @@ def main():
                                                        np.linalg.norm(f64["u_m"])),
             "newton_iters": rm["newton_iters"], "gmres_iters_total": rm["gmres_iters_total"],
             "gemv_ms": mg_ms,
-            "gemv_gbs": gemv_bytes(nm, ns, 4) / (mg_ms * 1e-3) / 1e9 if mg_ms else None,
+            "gemv_gbs": gemv_bytes(nm, ns, 4, all(a == b for a, b in mx["tiles"].values())) / (mg_ms * 1e-3) / 1e9
+            if mg_ms else None,
             "coupled_operator_gflops": flops / (mx["timing"]["apply"][0] * 1e-3) / 1e9 if mx["timing"]["apply"][0] else None,
         }
         out["bem_assembly"]["mixed_fp32_eval"] = asm_report(mx, FP32_PEAK_TFLOPS)

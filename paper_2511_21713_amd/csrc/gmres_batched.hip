@@ -42,6 +42,11 @@ struct GDesc {
     int f32;  // operator values in FP32
     int vf32; // Krylov basis stored in FP32
     int mf;   // boundary operators applied matrix-free (no dense GEMV)
+    // symmetric use of the stored single layer, per surface: column partials, Delta rows
+    int symm[2];
+    double *symP[2];
+    const int32_t *dl_ptr[2], *dl_col[2];
+    const double *dl_val[2];
     const int32_t *gm, *gs;
     const int32_t *sptr, *col; // FEM rows, sliced ELL
     const void *val;
@@ -216,7 +221,7 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
 // a kernel holding both row routines would be register-allocated for their
 // union and run at half the occupancy of either.
 template <typename MT>
-__global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+__global__ void __launch_bounds__(256, 4) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S)
 {
     const WItem it = wl[blockIdx.x];
@@ -224,13 +229,31 @@ __global__ void __launch_bounds__(256) k_bgemv(const WItem *__restrict__ wl, con
     const GDesc &d = D[it.inst];
     if (d.mf || d.f32 != (sizeof(MT) == 4)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r0 = it.b + wv * GEMV_RW;
     const int64_t n = it.a == 0 ? d.nm : d.ns;
-    if (r0 >= n) return;
     const int64_t ld = it.a == 0 ? d.ldm : d.lds;
     const double *x = it.a == 0 ? d.xm : d.xs;
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
-    gemv_rows<MT>(static_cast<const MT *>(it.a == 0 ? d.Bm : d.Bs), x, y, n, ld, r0, lane);
+    const MT *B = static_cast<const MT *>(it.a == 0 ? d.Bm : d.Bs);
+    if (d.symm[it.a]) {
+        gemv_rows_sym<MT>(B, x, y, d.symP[it.a], n, ld, it.b, threadIdx.x);
+    } else {
+        const int64_t r0 = it.b + wv * GEMV_RW;
+        if (r0 < n) gemv_rows<MT>(B, x, y, n, ld, r0, lane);
+    }
+}
+
+// second stage of the symmetric use (work item: inst, a = surface, b = first of GFIN_ROWS rows)
+__global__ void __launch_bounds__(256) k_bgemv_fin(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+                                                   const GState *__restrict__ S)
+{
+    const WItem it = wl[blockIdx.x];
+    if (!applies(S[it.inst].st)) return;
+    const GDesc &d = D[it.inst];
+    if (d.mf || !d.symm[it.a]) return;
+    const int64_t n = it.a == 0 ? d.nm : d.ns;
+    const double *x = it.a == 0 ? d.xm : d.xs;
+    double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
+    gemv_sym_finish(n, d.symP[it.a], d.dl_ptr[it.a], d.dl_col[it.a], d.dl_val[it.a], x, y, it.b, threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
@@ -547,12 +570,13 @@ __global__ void __launch_bounds__(256) k_bupdx(const WItem *__restrict__ wl, con
 // a captured Krylov step is valid for the same device buffer and launch shapes
 struct GraphKey {
     void *dev = nullptr;
-    unsigned nvec = 0, ngemv = 0, nspmv = 0, npack = 0, ndot = 0, ngroups = 0, nb = 0;
+    unsigned nvec = 0, ngemv = 0, nspmv = 0, npack = 0, ndot = 0, ngroups = 0, nb = 0, nfin = 0;
     int kmax = 0, types = 0; // types: bit 0 FP64 operators present, bit 1 FP32
     bool operator==(const GraphKey &o) const
     {
         return dev == o.dev && nvec == o.nvec && ngemv == o.ngemv && nspmv == o.nspmv && npack == o.npack &&
-               ndot == o.ndot && ngroups == o.ngroups && nb == o.nb && kmax == o.kmax && types == o.types;
+               ndot == o.ndot && ngroups == o.ngroups && nb == o.nb && nfin == o.nfin && kmax == o.kmax &&
+               types == o.types;
     }
 };
 
@@ -588,7 +612,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     if (nb == 0) return;
     std::vector<GDesc> desc(nb);
     std::vector<GState> st(nb);
-    std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack, wl_dot;
+    std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack, wl_dot, wl_fin;
     int maxiter_host = 0, kmax = 1;
     for (int q = 0; q < nb; ++q) {
         GmresJob &J = *jobs[q];
@@ -620,6 +644,14 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             d.sp_ptr[w] = p.surf[w].ring_ptr;
             d.sp_col[w] = p.surf[w].ring;
             d.sp_val[w] = p.surf[w].spai;
+            const SurfaceDev &SD = p.surf[w];
+            d.symm[w] = (!p.bem_mf && SD.sym) ? 1 : 0;
+            d.symP[w] = d.symm[w] ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP1,
+                                                    size_t((SD.nv + GSYM - 1) / GSYM) * SD.nv)
+                                  : nullptr;
+            d.dl_ptr[w] = SD.d_ptr;
+            d.dl_col[w] = SD.d_col;
+            d.dl_val[w] = SD.d_val;
         }
         d.z = scratch<double>(p, SCR_PZ, n);
         d.t = scratch<double>(p, SCR_PT, n);
@@ -657,9 +689,15 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         PB_HIP(hipMemsetAsync(J.x, 0, sizeof(double) * n, s));
         for (int64_t c = 0; c < d.nch; ++c) wl_vec.push_back(WItem{q, int(c), c * CH});
         for (int64_t c = 0; c < d.nchb; ++c) wl_dot.push_back(WItem{q, int(c), c * CHB});
+        static_assert(GROWS == GSYM, "GEMV work items are the symmetric routine's row blocks");
         for (int a = 0; a < 2; ++a) {
             const int64_t nv = a == 0 ? d.nm : d.ns;
-            for (int64_t r = 0; r < nv; r += GROWS) wl_gemv.push_back(WItem{q, a, r});
+            if (d.symm[a]) { // the last rows read the most: dispatched first
+                for (int64_t r = (nv - 1) / GROWS * GROWS; r >= 0; r -= GROWS) wl_gemv.push_back(WItem{q, a, r});
+                for (int64_t r = 0; r < nv; r += GFIN_ROWS) wl_fin.push_back(WItem{q, a, r});
+            } else {
+                for (int64_t r = 0; r < nv; r += GROWS) wl_gemv.push_back(WItem{q, a, r});
+            }
         }
         for (int64_t r = 0; r < p.nn; r += SLICE) wl_spmv.push_back(WItem{q, 0, r});
         for (int64_t k = 0; k < std::max(d.ldm, d.lds); k += CH) wl_pack.push_back(WItem{q, 0, k});
@@ -671,7 +709,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     BatchBuffers &BB = batch_buffers();
     const size_t bytes = sizeof(GDesc) * nb + sizeof(GState) * nb +
                          sizeof(WItem) * (wl_vec.size() + wl_gemv.size() + wl_spmv.size() + wl_pack.size() +
-                                          wl_dot.size()) + 512;
+                                          wl_dot.size() + wl_fin.size()) + 512;
     if (BB.dev_bytes < bytes) {
         if (BB.step) PB_HIP(hipGraphExecDestroy(BB.step));
         BB.step = nullptr;
@@ -694,11 +732,12 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     WItem *dspmv = static_cast<WItem *>(put(wl_spmv.data(), sizeof(WItem) * wl_spmv.size()));
     WItem *dpack = static_cast<WItem *>(put(wl_pack.data(), sizeof(WItem) * wl_pack.size()));
     WItem *ddot = static_cast<WItem *>(put(wl_dot.data(), sizeof(WItem) * wl_dot.size()));
+    WItem *dfin = static_cast<WItem *>(put(wl_fin.data(), sizeof(WItem) * wl_fin.size()));
     int *dcount = reinterpret_cast<int *>(cur);
     PB_HIP(hipMemsetAsync(dcount, 0, sizeof(int), s));
     const unsigned nvec = unsigned(wl_vec.size()), ngemv = unsigned(wl_gemv.size()),
                    nspmv = unsigned(wl_spmv.size()), npack = unsigned(wl_pack.size()),
-                   ndot = unsigned(wl_dot.size());
+                   ndot = unsigned(wl_dot.size()), nfin = unsigned(wl_fin.size());
     const unsigned ngroups = unsigned((maxm + 1 + 7) / 8);
 
     EventTimer *tm = nullptr;
@@ -733,6 +772,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         if (tm) tm->begin(T_GEMV, s);
         if (types & 1) hipLaunchKernelGGL(k_bgemv<double>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
         if (types & 2) hipLaunchKernelGGL(k_bgemv<float>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
+        if (nfin) hipLaunchKernelGGL(k_bgemv_fin, dim3(nfin), dim3(256), 0, s, dfin, dD, dS);
         // matrix-free instances: their own launches, gated by their state word
         for (size_t q = 0; q < jobs.size() && any_mf; ++q) {
             Problem &pq = *jobs[q]->p;
@@ -767,7 +807,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     bool graph = !tm && !any_mf; // matrix-free launches carry per-instance pointers: not captured
     for (auto *J : jobs) graph = graph && J->graph;
     if (graph) {
-        const GraphKey key{BB.dev, nvec, ngemv, nspmv, npack, ndot, ngroups, unsigned(nb), kmax, types};
+        const GraphKey key{BB.dev, nvec, ngemv, nspmv, npack, ndot, ngroups, unsigned(nb), nfin, kmax, types};
         if (!(BB.step && BB.key == key)) {
             if (BB.step) PB_HIP(hipGraphExecDestroy(BB.step));
             BB.step = nullptr;

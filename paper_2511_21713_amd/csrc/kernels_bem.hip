@@ -936,6 +936,20 @@ __global__ void __launch_bounds__(256)
         if (a < m) val[p0 + a] = r[a];
 }
 
+// Delta_ij = V'_ij - V'_ji on the upper two-ring pattern, from the stored
+// operator (one thread per row)
+template <typename MT>
+__global__ void k_sym_delta(int64_t nv, int64_t ld, const MT *__restrict__ B, const int32_t *__restrict__ dptr,
+                            const int32_t *__restrict__ dcol, double *__restrict__ dval)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    for (int32_t e = dptr[i]; e < dptr[i + 1]; ++e) {
+        const int64_t j = dcol[e];
+        dval[e] = double(B[i * ld + nv + j]) - double(B[j * ld + nv + i]);
+    }
+}
+
 // ===========================================================================
 // host orchestration
 // ===========================================================================
@@ -1132,6 +1146,9 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         S.nf_ptr = S.nf_col = S.nf_row = nullptr;
         S.nf_val = nullptr;
         S.nf_nnz = 0;
+        S.d_ptr = S.d_col = nullptr;
+        S.d_val = nullptr;
+        S.sym = false;
         S.ring_ptr = A.upload(T.ring_ptr, s);
         S.ring = A.upload(T.ring, s);
         S.spai = A.alloc<double>(T.ring.size());
@@ -1155,6 +1172,10 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
             const int64_t ldt = bem_ld(T.nv);
             if (f32) S.B = A.alloc<float>(T.nv * ldt);
             else S.B = A.alloc<double>(T.nv * ldt);
+            delta_pattern(T);
+            S.d_ptr = A.upload(T.d2_ptr, s);
+            S.d_col = A.upload(T.d2_col, s);
+            S.d_val = A.alloc<double>(std::max<size_t>(T.d2_col.size(), 1));
         }
         PB_HIP(hipStreamSynchronize(s));
         p.bem_topo_ready[w] = true;
@@ -1303,6 +1324,17 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
                            (float *)nullptr);
     }
     PB_HIP(hipGetLastError());
+    // symmetric storage use (square-tile assembly): Delta from the stored values
+    S.sym = sym;
+    if (sym) {
+        if (p.precision == PBFB_MIXED)
+            hipLaunchKernelGGL(k_sym_delta<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld,
+                               static_cast<const float *>(S.B), S.d_ptr, S.d_col, S.d_val);
+        else
+            hipLaunchKernelGGL(k_sym_delta<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld,
+                               static_cast<const double *>(S.B), S.d_ptr, S.d_col, S.d_val);
+        PB_HIP(hipGetLastError());
+    }
     // approximate inverse of the single-layer block, from the stored values
     PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
     if (p.precision == PBFB_MIXED) {

@@ -37,18 +37,44 @@ __global__ void k_pack(int64_t nn, int64_t nm, int64_t ns, int64_t ldm, int64_t 
 // ---------------------------------------------------------------------------
 // dense GEMV over both surfaces in one launch (rows: gemv_rows.hpp)
 // ---------------------------------------------------------------------------
+// one surface's operator as the GEMV sees it
+struct GemvSurf {
+    const void *B;
+    const double *x;
+    double *y, *P; // P: column partials of the symmetric storage use
+    int64_t n, ld;
+    int sym;
+    const int32_t *dptr, *dcol;
+    const double *dval;
+};
+
 template <typename MT>
-__global__ void __launch_bounds__(256)
-    k_gemv(const MT *__restrict__ B0, const double *__restrict__ x0, double *__restrict__ y0, int64_t n0,
-           int64_t ld0, int64_t nblk0, const MT *__restrict__ B1, const double *__restrict__ x1,
-           double *__restrict__ y1, int64_t n1, int64_t ld1)
+__global__ void __launch_bounds__(256, 4) k_gemv(GemvSurf S0, GemvSurf S1, int64_t nblk0)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool s1 = blockIdx.x >= nblk0;
-    const int64_t r0 = ((s1 ? blockIdx.x - nblk0 : blockIdx.x) * 4 + wv) * GEMV_RW;
-    const int64_t n = s1 ? n1 : n0;
-    if (r0 >= n) return;
-    gemv_rows<MT>(s1 ? B1 : B0, s1 ? x1 : x0, s1 ? y1 : y0, n, s1 ? ld1 : ld0, r0, lane);
+    const GemvSurf &S = s1 ? S1 : S0;
+    const int64_t bi = s1 ? blockIdx.x - nblk0 : blockIdx.x;
+    const int64_t nb = (S.n + GSYM - 1) / GSYM;
+    // symmetric use: the last rows read the most, so they are dispatched first
+    const int64_t r0 = (S.sym ? nb - 1 - bi : bi) * int64_t(GSYM);
+    const MT *B = static_cast<const MT *>(S.B);
+    if (S.sym) {
+        gemv_rows_sym<MT>(B, S.x, S.y, S.P, S.n, S.ld, r0, threadIdx.x);
+    } else {
+        const int64_t rw = r0 + wv * GEMV_RW;
+        if (rw < S.n) gemv_rows<MT>(B, S.x, S.y, S.n, S.ld, rw, lane);
+    }
+}
+
+// second stage of the symmetric use: transposed column partials and Delta
+__global__ void __launch_bounds__(256) k_gemv_fin(GemvSurf S0, GemvSurf S1, int64_t nb0)
+{
+    const bool s1 = blockIdx.x >= nb0;
+    const GemvSurf &S = s1 ? S1 : S0;
+    if (!S.sym) return;
+    const int64_t i0 = (s1 ? blockIdx.x - nb0 : blockIdx.x) * int64_t(GFIN_ROWS);
+    gemv_sym_finish(S.n, S.P, S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,20 +158,38 @@ __global__ void k_add_vec(int64_t n, const double *__restrict__ a, const double 
 // ===========================================================================
 // host wrappers
 // ===========================================================================
+static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y)
+{
+    const SurfaceDev &D = p.surf[w];
+    GemvSurf G{};
+    G.B = D.B;
+    G.x = x;
+    G.y = y;
+    G.n = D.nv;
+    G.ld = bem_ld(D.nv);
+    G.sym = D.sym ? 1 : 0;
+    G.P = D.sym ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP1, size_t((D.nv + GSYM - 1) / GSYM) * D.nv)
+                : nullptr;
+    G.dptr = D.d_ptr;
+    G.dcol = D.d_col;
+    G.dval = D.d_val;
+    return G;
+}
+
 static void gemv_launch(Problem &p, const double *xm, const double *xs, double *y, hipStream_t s)
 {
-    constexpr int RW = GEMV_RW;
     const SurfaceDev &M = p.surf[0], &S = p.surf[1];
-    const int64_t ldm = bem_ld(M.nv), lds = bem_ld(S.nv);
-    const int64_t nb0 = (M.nv + 4 * RW - 1) / (4 * RW), nb1 = (S.nv + 4 * RW - 1) / (4 * RW);
-    double *ym = y + p.nn, *ys = y + p.nn + M.nv;
+    const int64_t nb0 = (M.nv + GSYM - 1) / GSYM, nb1 = (S.nv + GSYM - 1) / GSYM;
+    const GemvSurf G0 = gemv_surf(p, 0, xm, y + p.nn), G1 = gemv_surf(p, 1, xs, y + p.nn + M.nv);
     if (p.timing) p.timer.begin(T_GEMV, s);
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, (const float *)M.B, xm, ym,
-                           M.nv, ldm, nb0, (const float *)S.B, xs, ys, S.nv, lds);
+        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, G0, G1, nb0);
     else
-        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, (const double *)M.B, xm, ym,
-                           M.nv, ldm, nb0, (const double *)S.B, xs, ys, S.nv, lds);
+        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, G0, G1, nb0);
+    if (G0.sym || G1.sym) {
+        const int64_t f0 = (M.nv + GFIN_ROWS - 1) / GFIN_ROWS, f1 = (S.nv + GFIN_ROWS - 1) / GFIN_ROWS;
+        hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0 + f1)), dim3(256), 0, s, G0, G1, f0);
+    }
     if (p.timing) p.timer.end(s);
 }
 

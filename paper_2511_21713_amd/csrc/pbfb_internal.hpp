@@ -124,6 +124,8 @@ struct SurfaceTopo {
     int max_ring = 0;
     // 3-ring pattern of the near-field single layer (matrix-free mode), built on first use
     std::vector<int32_t> nf_ptr, nf_col;
+    // pairs j > i within two rings (where touching-pair blocks can make V' unsymmetric)
+    std::vector<int32_t> d2_ptr, d2_col;
 };
 
 struct SurfaceDev {
@@ -151,6 +153,11 @@ struct SurfaceDev {
     // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
     void *B = nullptr;
     double *vdiag = nullptr; // diagonal of the signed single-layer block V'
+    // symmetric storage use: the regular part of V' is bitwise symmetric, and
+    // Delta_ij = V'_ij - V'_ji (j > i, two-ring pattern) carries the rest
+    bool sym = false;
+    int32_t *d_ptr = nullptr, *d_col = nullptr;
+    double *d_val = nullptr;
     // sparse approximate inverse of V' on the 1-ring pattern (GMRES preconditioner)
     int32_t *ring_ptr = nullptr, *ring = nullptr;
     double *spai = nullptr;
@@ -201,7 +208,7 @@ struct EventTimer {
 enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
-    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1,
+    SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1, SCR_SYMP0, SCR_SYMP1,
     SCR_N
 };
 
@@ -289,6 +296,7 @@ void mf_vdiag(Problem &p, int w, hipStream_t s); // diagonal of V' from the resi
 // near-field V' on the 3-ring pattern and the 1-ring approximate inverse from it
 void mf_spai(Problem &p, int w, hipStream_t s);
 void near_pattern(SurfaceTopo &S); // host: the 3-ring pattern (nf_ptr, nf_col), once
+void delta_pattern(SurfaceTopo &S); // host: the upper two-ring pattern (d2_ptr, d2_col), once
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s);
 void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN,
                      double *rJ, double *rH, hipStream_t s);

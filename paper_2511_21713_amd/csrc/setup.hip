@@ -330,4 +330,31 @@ void near_pattern(SurfaceTopo &S)
     }
 }
 
+// vertices j > i within two rings of i, ascending: every pair (i, j) whose
+// entry can receive a touching-pair block (j on a triangle that shares a
+// vertex with a triangle at i)
+void delta_pattern(SurfaceTopo &S)
+{
+    if (!S.d2_ptr.empty()) return;
+    std::vector<int32_t> mark(S.nv, -1), cur;
+    S.d2_ptr.assign(S.nv + 1, 0);
+    S.d2_col.clear();
+    for (int64_t i = 0; i < S.nv; ++i) {
+        cur.clear();
+        for (int32_t e = S.ring_ptr[i]; e < S.ring_ptr[i + 1]; ++e) {
+            const int32_t a = S.ring[e];
+            for (int32_t f = S.ring_ptr[a]; f < S.ring_ptr[a + 1]; ++f) {
+                const int32_t b = S.ring[f];
+                if (b > i && mark[b] != int32_t(i)) {
+                    mark[b] = int32_t(i);
+                    cur.push_back(b);
+                }
+            }
+        }
+        std::sort(cur.begin(), cur.end());
+        S.d2_col.insert(S.d2_col.end(), cur.begin(), cur.end());
+        S.d2_ptr[i + 1] = int32_t(S.d2_col.size());
+    }
+}
+
 } // namespace pbfb
