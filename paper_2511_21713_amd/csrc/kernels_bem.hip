@@ -463,6 +463,11 @@ __global__ void k_bem_pass1(int64_t nv, int64_t SB, const int32_t *__restrict__ 
     const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (c >= SB) return;
     const int32_t cb = c_blk ? c_blk[c] : INT32_MAX;
+    if (c_blk) { // a column below every block of vertex i never receives anything: left unwritten
+        int32_t bmin = INT32_MAX;
+        for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) bmin = min(bmin, LA_blk[e]);
+        if (cb < bmin) return;
+    }
     double sv = 0.0, sk = 0.0, st = 0.0;
     bool any = false;
     for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) {
@@ -485,33 +490,55 @@ __global__ void k_bem_pass1(int64_t nv, int64_t SB, const int32_t *__restrict__ 
     }
 }
 
+// smallest target block holding vertex i (symmetric evaluation: W[i][c] is
+// written only for columns c of blocks not below it)
+__device__ inline int32_t row_bmin(const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA_blk,
+                                   int64_t i)
+{
+    int32_t bmin = INT32_MAX;
+    for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) bmin = min(bmin, LA_blk[e]);
+    return bmin;
+}
+
 // B64[i][j] = sK * sum W_K[i][cols of j],  B64[i][nv + j] = sV * sum W_V[i][cols of j]
+// (c_blk non-null: symmetric evaluation, columns below row i's blocks skipped)
 __global__ void k_bem_pass2(int64_t nv, int64_t SB, int64_t ld, const int32_t *__restrict__ LB_ptr,
-                            const int32_t *__restrict__ LB, const double *__restrict__ WV,
-                            const double *__restrict__ WK, double sV, double sK, double *__restrict__ Bo)
+                            const int32_t *__restrict__ LB, const int32_t *__restrict__ c_blk,
+                            const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA_blk,
+                            const double *__restrict__ WV, const double *__restrict__ WK, double sV, double sK,
+                            double *__restrict__ Bo)
 {
     const int64_t i = blockIdx.y;
     const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (j >= nv) return;
+    const int32_t bmin = c_blk ? row_bmin(LA_ptr, LA_blk, i) : INT32_MIN;
     double v = 0.0, k = 0.0;
     for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) {
-        v += WV[i * SB + LB[e]];
-        k += WK[i * SB + LB[e]];
+        const int32_t c = LB[e];
+        if (c_blk && c_blk[c] < bmin) continue;
+        v += WV[i * SB + c];
+        k += WK[i * SB + c];
     }
     Bo[i * ld + j] = sK * k;
     Bo[i * ld + nv + j] = sV * v;
 }
 
-// T[i][j] = sc * sum W[i][cols of j] (the mirrored double layer, ld nv)
+// T[i][j] = sc * sum W[i][cols of j] (the mirrored double layer, ld nv;
+// columns below row i's blocks were never written)
 __global__ void k_bem_pass2_one(int64_t nv, int64_t SB, const int32_t *__restrict__ LB_ptr,
-                                const int32_t *__restrict__ LB, const double *__restrict__ W, double sc,
-                                double *__restrict__ T)
+                                const int32_t *__restrict__ LB, const int32_t *__restrict__ c_blk,
+                                const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA_blk,
+                                const double *__restrict__ W, double sc, double *__restrict__ T)
 {
     const int64_t i = blockIdx.y;
     const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (j >= nv) return;
+    const int32_t bmin = row_bmin(LA_ptr, LA_blk, i);
     double v = 0.0;
-    for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) v += W[i * SB + LB[e]];
+    for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) {
+        const int32_t c = LB[e];
+        if (c_blk[c] >= bmin) v += W[i * SB + c];
+    }
     T[i * nv + j] = sc * v;
 }
 
@@ -1290,12 +1317,13 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     }
     const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
     PB_HIP(hipMemsetAsync(B64, 0, sizeof(double) * nv * ld, s));
+    const int32_t *cblk = sym ? static_cast<const int32_t *>(DB.slot_blk) : nullptr;
     hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, ld, DB.L_ptr, DB.L,
-                       WV, WK, sV, sK, B64);
+                       cblk, DA.L_ptr, DA.L_blk, WV, WK, sV, sK, B64);
     PB_HIP(hipGetLastError());
     if (sym) {
         hipLaunchKernelGGL(k_bem_pass2_one, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, DB.L_ptr,
-                           DB.L, WKt, sK, Tm);
+                           DB.L, cblk, DA.L_ptr, DA.L_blk, WKt, sK, Tm);
         const unsigned nbt = unsigned((nv + SYMT - 1) / SYMT);
         hipLaunchKernelGGL(k_bem_symm, dim3(nbt, nbt), dim3(256), 0, s, nv, ld, B64, Tm);
         PB_HIP(hipGetLastError());
