@@ -100,6 +100,34 @@ def test_solve_with_pinned_shapes_agrees(tiles):
     assert abs(tot[0] - tot[1]) < 1e-11 * abs(tot[0])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_symmetric_apply_matches_full_rows(tiles, precision):
+    """A square shape stores the regular single layer bitwise symmetric and
+    the apply reads K' and only the lower triangle of V' (plus the two-ring
+    difference left by the touching blocks); a rectangular shape applies
+    full rows.  The residual and Jacobian products of the two agree to
+    rounding, and (FP64) match the oracle's."""
+    pb, ctx, prob, refs = tiles
+    o = oracle.Oracle.from_problem(prob)
+    rng = np.random.default_rng(31 + precision)
+    phi = rng.standard_normal(o.n)
+    v = rng.standard_normal(o.n)
+    out = {}
+    for shape in ((16, 32), (16, 16)):
+        g = pb.Problem.from_inputs(ctx, prob, precision=precision)
+        g.set_tile_shape(*shape)
+        out[shape] = (g.residual(oracle.HS, phi), g.apply_jacobian(oracle.HS, phi, v))
+        assert g.tile_shape(0) == shape
+        g.close()
+    (Ff, Jf), (Fs, Js) = out[(16, 32)], out[(16, 16)]
+    eF, eJ = rowrel(Fs[None, :], Ff[None, :]), rowrel(Js[None, :], Jf[None, :])
+    log(f"  precision {precision}: symmetric vs full rows F {eF:.2e} Jv {eJ:.2e}")
+    bar = 1e-13 if precision == 0 else 1e-6
+    assert eF < bar and eJ < bar
+    if precision == 0:
+        assert rowrel(Js[None, :], o.apply_jacobian(oracle.HS, phi, v)[None, :]) < 1e-12
+
+
 def test_bad_tile_shape_rejected(tiles):
     pb, ctx, prob, refs = tiles
     g = pb.Problem.from_inputs(ctx, prob)
