@@ -1363,21 +1363,14 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
                                static_cast<const double *>(S.B), S.d_ptr, S.d_col, S.d_val);
         PB_HIP(hipGetLastError());
     }
-    // approximate inverse of the single-layer block, from the stored values
+    // approximate inverse of the single-layer block, from the FP64 values (with
+    // FP32 storage: the staging copy, still in the workspace)
     PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
-    if (p.precision == PBFB_MIXED) {
-        hipLaunchKernelGGL(k_spai_small<float>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv,
-                           static_cast<const float *>(S.B), ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
-        if (T.max_ring > SPAI_SMALL)
-            hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const float *>(S.B),
-                               ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
-    } else {
-        hipLaunchKernelGGL(k_spai_small<double>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv,
-                           static_cast<const double *>(S.B), ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
-        if (T.max_ring > SPAI_SMALL)
-            hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv,
-                               static_cast<const double *>(S.B), ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
-    }
+    hipLaunchKernelGGL(k_spai_small<double>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv, static_cast<const double *>(B64),
+                       ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+    if (T.max_ring > SPAI_SMALL)
+        hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const double *>(B64),
+                           ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
     PB_HIP(hipGetLastError());
     int bad = 0;
     PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
