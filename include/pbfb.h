@@ -250,6 +250,14 @@ pbfb_status pbfb_energy(pbfb_problem *p, const double *phi_lin, const double *ph
  * (PBFB_EINVAL for any other pair) and marks its operators stale.  The shape
  * changes only the order of floating-point sums, never the integrals. */
 pbfb_status pbfb_set_tile_shape(pbfb_problem *p, int ta, int tb);
+/* Cap of the assembly workspace: the expanded tile matrix of the regular
+ * assembly is built in chunks of target blocks of at most max_entries
+ * entries per operator (0: the default 2^30; at least one block of rows is
+ * always taken).  Smaller chunks bound the per-context workspace (which
+ * holds three such chunks and the gather buffers) at the cost of more
+ * launches; the operators differ only in the order of floating-point sums.
+ * Marks the boundary operators stale. */
+pbfb_status pbfb_set_assembly_chunk(pbfb_problem *p, int64_t max_entries);
 /* Shape used by the last assembly of surface `surf` (0 = Gamma_m, 1 =
  * Gamma_s); 0, 0 before the first assembly. */
 pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *tb);

@@ -28,7 +28,7 @@ EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_probl
            "pbfb_reset_operators", "pbfb_residual",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
            "pbfb_server_submit", "pbfb_server_poll", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
-           "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
+           "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_assembly_chunk", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
 
 
 class PbfbError(RuntimeError):
@@ -114,6 +114,7 @@ def lib():
         L.pbfb_export_bem.argtypes = [P, C.c_int, P, P]
         L.pbfb_export_rhs.argtypes = [P, P]
         L.pbfb_set_tile_shape.argtypes = [P, C.c_int, C.c_int]
+        L.pbfb_set_assembly_chunk.argtypes = [P, C.c_int64]
         L.pbfb_set_bem_mode.argtypes = [P, C.c_int]
         L.pbfb_get_tile_shape.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pbfb_timing_enable.argtypes = [P, C.c_int]
@@ -357,6 +358,10 @@ class Problem:
     def set_bem_mode(self, mode):
         """BEM_DENSE (stored Galerkin blocks) or BEM_MATRIX_FREE (evaluated at every apply)."""
         _check(lib().pbfb_set_bem_mode(self.h, mode))
+
+    def set_assembly_chunk(self, max_entries=0):
+        """Largest expanded-matrix chunk per operator in entries (0: default 2^30)."""
+        _check(lib().pbfb_set_assembly_chunk(self.h, max_entries))
 
     def set_tile_shape(self, ta=0, tb=0):
         """Pin the regular-assembly tile shape (ta x tb triangles); 0, 0 = tuned."""

@@ -693,6 +693,20 @@ pbfb_status pbfb_set_bem_mode(pbfb_problem *pp, int mode)
     API_END
 }
 
+pbfb_status pbfb_set_assembly_chunk(pbfb_problem *pp, int64_t max_entries)
+{
+    API_BEGIN
+    PB_CHECK(pp, PBFB_EINVAL, "null problem");
+    PB_CHECK(max_entries >= 0, PBFB_EINVAL, "max_entries must be >= 0");
+    Problem &p = live(pp);
+    const int64_t v = max_entries == 0 ? (int64_t(1) << 30) : max_entries;
+    if (v != p.asm_chunk) {
+        p.asm_chunk = v;
+        p.bem_ready[0] = p.bem_ready[1] = false;
+    }
+    API_END
+}
+
 pbfb_status pbfb_set_tile_shape(pbfb_problem *pp, int ta, int tb)
 {
     API_BEGIN

@@ -1271,8 +1271,9 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     ra.ms = std::max(HA.ms_max, block_side(T, TILE_SHAPES[shape].tb).ms_max);
 
     const int64_t nv = T.nv, ld = bem_ld(nv);
-    // chunks of target blocks, so that E stays within 2^30 entries per operator
-    const int64_t max_rows = std::max<int64_t>(3 * HA.bs, (int64_t(1) << 30) / std::max<int64_t>(DB.S, 1));
+    // chunks of target blocks, so that E stays within p.asm_chunk entries per
+    // operator (2^30 unless capped; at least one block of rows)
+    const int64_t max_rows = std::max<int64_t>(3 * HA.bs, p.asm_chunk / std::max<int64_t>(DB.S, 1));
     std::vector<std::pair<int64_t, int64_t>> chunks;
     int64_t chunk_rows = 0;
     for (int64_t b0 = 0; b0 < HA.nb;) {

@@ -225,6 +225,7 @@ struct Problem {
     bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
     bool bem_topo_ready[2] = {false, false};
     int tile_fixed = -1; // tile shape forced by pbfb_set_tile_shape (index), -1: tuned
+    int64_t asm_chunk = int64_t(1) << 30; // largest expanded-matrix chunk per operator (entries)
     bool bem_mf = false; // boundary operators applied matrix-free (no dense storage)
     // host copies
     int64_t nn = 0, ntet = 0, nq = 0;

@@ -43,7 +43,7 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
         dense += size_t((T.nv + 15) / 16) * T.nv * 8 + size_t(T.nv) * 20 * 12; // symmetric use: partials, Delta
         for (int k = 0; k < N_TILE_SHAPES; ++k) {
             const size_t SA = size_t(block_side(T, TILE_SHAPES[k].ta).S), SB = size_t(block_side(T, TILE_SHAPES[k].tb).S);
-            const size_t rows = std::min(SA, std::max<size_t>(3 * TILE_SHAPES[k].ta, (size_t(1) << 30) / SB) +
+            const size_t rows = std::min(SA, std::max<size_t>(3 * TILE_SHAPES[k].ta, size_t(p.asm_chunk) / SB) +
                                                   3 * TILE_SHAPES[k].ta); // one assembly chunk of E
             // square shapes: a third operator in E and W, and an nv x nv matrix
             const size_t ops = TILE_SHAPES[k].ta == TILE_SHAPES[k].tb ? 3 : 2;

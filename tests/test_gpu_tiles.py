@@ -128,6 +128,27 @@ def test_symmetric_apply_matches_full_rows(tiles, precision):
         assert rowrel(Js[None, :], o.apply_jacobian(oracle.HS, phi, v)[None, :]) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(16, 16), (16, 32)])
+def test_chunked_assembly_matches(tiles, shape):
+    """A tiny workspace cap builds the expanded matrix in many chunks (one
+    block of target rows each), the path large surfaces take: the operators
+    equal the one-chunk ones to rounding and the oracle's, for the symmetric
+    square shape and a rectangular one."""
+    pb, ctx, prob, refs = tiles
+    g = pb.Problem.from_inputs(ctx, prob)
+    g.set_tile_shape(*shape)
+    one = [g.export_bem(s) for s in (0, 1)]
+    g.set_assembly_chunk(1)
+    many = [g.export_bem(s) for s in (0, 1)]
+    for s in (0, 1):
+        for a, b, r in zip(many[s], one[s], refs[s]):
+            e1, e2 = rowrel(a, b), rowrel(a, r)
+            log(f"  shape {shape} surf {s}: chunked vs one chunk {e1:.2e}, vs oracle {e2:.2e}")
+            assert e1 < 1e-14 and e2 < 1e-12
+    g.set_assembly_chunk(0)
+    g.close()
+
+
 def test_bad_tile_shape_rejected(tiles):
     pb, ctx, prob, refs = tiles
     g = pb.Problem.from_inputs(ctx, prob)
