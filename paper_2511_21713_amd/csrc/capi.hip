@@ -361,7 +361,7 @@ void pbfb_problem_destroy(pbfb_problem *pp)
 
 static void invalidate_geometry(Problem &p)
 {
-    p.geom_ready = p.fm_ready = p.bem_ready[0] = p.bem_ready[1] = false;
+    p.geom_ready = p.val_ready = p.fm_ready = p.bem_ready[0] = p.bem_ready[1] = false;
 }
 
 pbfb_status pbfb_set_mesh(pbfb_problem *pp, int64_t n_nodes, const double *nodes, int64_t n_tets,
@@ -415,7 +415,7 @@ pbfb_status pbfb_set_params(pbfb_problem *pp, double eps_in, double eps_out, dou
     PB_CHECK(kappa >= 0 && std::isfinite(kappa), PBFB_EINVAL, "kappa must be >= 0");
     PB_CHECK(temperature_K > 0, PBFB_EINVAL, "temperature must be positive");
     Problem &p = live(pp);
-    const bool geo = p.eps_m != eps_in || p.eps_s != eps_out;
+    const bool perm = p.eps_m != eps_in || p.eps_s != eps_out;
     const bool kap = p.kappa != kappa;
     p.eps_m = eps_in;
     p.eps_s = eps_out;
@@ -425,7 +425,7 @@ pbfb_status pbfb_set_params(pbfb_problem *pp, double eps_in, double eps_out, dou
     const double e = 1.602176634e-19, eps0 = 8.8541878128e-12, kB = 1.380649e-23, NA = 6.02214076e23;
     p.lB = e * e / (4.0 * M_PI * eps0 * kB * temperature_K) * 1e10; // Angstrom
     p.kT = kB * temperature_K * NA / 4184.0;                         // kcal/mol
-    if (geo) invalidate_geometry(p); // stiffness and coupling values carry eps
+    if (perm) p.val_ready = false; // stiffness and coupling values carry eps (the boundary operators do not)
     if (kap) p.bem_ready[1] = false;
     p.fm_ready = false;
     p.have_params = true;

@@ -1383,6 +1383,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
 void ensure_all(Problem &p, hipStream_t s)
 {
     ensure_geometry(p, s);
+    ensure_values(p, s);
     ensure_rhs(p, s);
     ensure_bem(p, 0, s);
     ensure_bem(p, 1, s);

@@ -552,7 +552,7 @@ void ensure_topology(Problem &p, hipStream_t s)
     p.topo_ready = true;
 }
 
-// Geometry and FEM values from the device-resident mesh.
+// Geometry of the tets and surface triangles from the device-resident mesh.
 void ensure_geometry(Problem &p, hipStream_t s)
 {
     if (p.geom_ready) return;
@@ -572,7 +572,15 @@ void ensure_geometry(Problem &p, hipStream_t s)
     PB_HIP(hipStreamSynchronize(s));
     PB_CHECK(!(bad & 1), PBFB_EMESH, "degenerate (zero-volume) tetrahedron");
     PB_CHECK(!(bad & 2), PBFB_EMESH, "degenerate (zero-area) surface triangle");
-    // stiffness + surface coupling values
+    p.geom_ready = true;
+}
+
+// Stiffness and surface-coupling values of the FEM rows (they carry the
+// permittivities; the boundary operators do not).
+void ensure_values(Problem &p, hipStream_t s)
+{
+    if (p.val_ready) return;
+    ensure_geometry(p, s);
     PB_HIP(hipMemsetAsync(p.d_val0, 0, sizeof(double) * p.nnz, s));
     hipLaunchKernelGGL(k_stiffness, dim3(nblocks(p.nn, 256)), dim3(256), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t,
                        p.d_slot4, p.d_tgeo, p.eps_s, p.d_val0);
@@ -583,7 +591,7 @@ void ensure_geometry(Problem &p, hipStream_t s)
                            S.area, S.cslot, coef, p.d_val0);
     }
     PB_HIP(hipGetLastError());
-    p.geom_ready = true;
+    p.val_ready = true;
 }
 
 void ensure_rhs(Problem &p, hipStream_t s)

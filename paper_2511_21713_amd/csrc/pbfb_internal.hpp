@@ -223,6 +223,7 @@ struct Problem {
     int precision = PBFB_FP64;
     bool have_mesh = false, have_charges = false, have_params = false;
     bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
+    bool val_ready = false; // FEM stiffness and coupling values (depend on the permittivities)
     bool bem_topo_ready[2] = {false, false};
     int tile_fixed = -1; // tile shape forced by pbfb_set_tile_shape (index), -1: tuned
     int64_t asm_chunk = int64_t(1) << 30; // largest expanded-matrix chunk per operator (entries)
@@ -282,6 +283,7 @@ void build_fem_topology(Problem &p, std::vector<int32_t> &sptr, std::vector<int3
 // device setup and operators (kernels_*.hip, solver.hip)
 void ensure_topology(Problem &p, hipStream_t s);
 void ensure_geometry(Problem &p, hipStream_t s);
+void ensure_values(Problem &p, hipStream_t s);
 void ensure_rhs(Problem &p, hipStream_t s);
 void ensure_bem(Problem &p, int surf, hipStream_t s);
 void ensure_all(Problem &p, hipStream_t s);

@@ -348,3 +348,31 @@ def test_problem_outliving_its_context():
     g3.close()
     c3.close()
 
+
+def test_parameter_changes_recompute_what_depends_on_them(ctx):
+    """After a setup, new permittivities recompute the FEM values and the
+    load (not the boundary operators, which do not depend on them) and a new
+    kappa the Yukawa operators: the products then match an oracle built with
+    the new values, and the Laplace operators are left as they were."""
+    import dataclasses
+
+    import paper_2511_21713_amd as pb
+    prob = cached_config(0)
+    g = pb.Problem.from_inputs(ctx, prob)
+    g.setup()
+    Vm0, Km0 = g.export_bem(0)
+    rng = np.random.default_rng(41)
+    phi = 0.5 * rng.standard_normal(g.n)
+    v = rng.standard_normal(g.n)
+    for eps_in, eps_out, kappa in ((2.0, 80.0, prob.kappa), (2.0, 60.0, prob.kappa), (2.0, 60.0, 0.3)):
+        g.set_params(eps_in, eps_out, kappa)
+        q = dataclasses.replace(prob, eps_in=eps_in, eps_out=eps_out, kappa=kappa)
+        o = oracle.Oracle.from_problem(q)
+        eF = rel(g.residual(oracle.HS, phi), o.residual(oracle.HS, phi))
+        eJ = rel(g.apply_jacobian(oracle.HS, phi, v), o.apply_jacobian(oracle.HS, phi, v))
+        log(f"  eps {eps_in}/{eps_out} kappa {kappa}: F {eF:.2e} Jv {eJ:.2e}")
+        assert eF < 1e-12 and eJ < 1e-12
+        Vm, Km = g.export_bem(0)
+        assert np.array_equal(Vm, Vm0) and np.array_equal(Km, Km0)
+    g.close()
+
