@@ -376,3 +376,24 @@ def test_parameter_changes_recompute_what_depends_on_them(ctx):
         assert np.array_equal(Vm, Vm0) and np.array_equal(Km, Km0)
     g.close()
 
+
+def test_iteration_limit_returns_the_last_iterate(case):
+    """Stopped by max_newton: PBFB_ENOTCONV, with the result and phi_out
+    holding the last iterate, which equals the oracle's after the same
+    steps."""
+    import paper_2511_21713_amd as pb
+    name, prob, o, g = case
+    kw = dict(max_newton=2, tol_nl=1e-14, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    phi = np.zeros(2 * o.n)
+    rg = g.solve(phi_out=phi, check=False, **kw)
+    ro, pl, pnl = o.solve(**kw)
+    log(f"  {name}: status {rg['status']} (oracle {ro['status']}), newton {rg['newton_iters']}, "
+        f"total {rg['total']:.10f} vs {ro['total']:.10f}")
+    assert rg["status"] == pb.ENOTCONV and ro["status"] == pb.ENOTCONV
+    assert rg["newton_iters"] == 2 and len(rg["omega"]) == 2
+    assert abs(rg["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
+    assert np.linalg.norm(phi[o.n:] - pnl) < 1e-9 * np.linalg.norm(pnl)
+    with pytest.raises(pb.PbfbError) as e:
+        g.solve(**kw)
+    assert e.value.code == pb.ENOTCONV
+
