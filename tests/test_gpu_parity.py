@@ -397,3 +397,39 @@ def test_iteration_limit_returns_the_last_iterate(case):
         g.solve(**kw)
     assert e.value.code == pb.ENOTCONV
 
+
+def test_degenerate_inputs(ctx):
+    """Edge cases of the method: no charges (b = 0: the solve returns at
+    once with Phi = 0 and zero energy), kappa = 0 (no ions: the shell
+    equation is linear, Gamma_s carries the Laplace kernel, and the
+    nonlinear part vanishes), and an empty batch."""
+    import dataclasses
+
+    import paper_2511_21713_amd as pb
+    prob = cached_config(0)
+    # no charges
+    g = pb.Problem.from_inputs(ctx, prob)
+    g.set_charges(np.zeros((0, 3)), np.zeros(0))
+    phi = np.ones(2 * g.n)
+    r = g.solve(phi_out=phi)
+    log(f"  no charges: status {r['status']}, total {r['total']!r}, newton {r['newton_iters']}")
+    assert r["status"] == 0 and r["total"] == 0.0 and not np.any(phi)
+    g.close()
+    # kappa = 0
+    q = dataclasses.replace(prob, kappa=0.0)
+    o = oracle.Oracle.from_problem(q)
+    g = pb.Problem.from_inputs(ctx, q)
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    rg = g.solve(**kw)
+    ro, _, _ = o.solve(**kw)
+    log(f"  kappa 0: total {rg['total']!r} vs {ro['total']!r}, nc {rg['nc']:.3e}")
+    assert rg["status"] == 0 and abs(rg["total"] - ro["total"]) < 1e-10 * abs(ro["total"])
+    assert rg["nc"] == 0.0 or abs(rg["nc"]) < 1e-12 * abs(rg["total"])
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(o.n)
+    assert rel(g.residual(oracle.HS, x), o.residual(oracle.HS, x)) < 1e-12
+    g.close()
+    # an empty batch
+    code, res = pb.solve_batch(ctx, [])
+    assert code == 0 and res == []
+
