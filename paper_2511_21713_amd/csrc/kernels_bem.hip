@@ -7,13 +7,18 @@
 // so the Galerkin rows of the coupled operator are one dense GEMV each.
 //
 // Assembly, deterministic and free of atomics:
-//  1. regular tiles: a workgroup takes 16 target x 32 source Morton-ordered
-//     triangles, evaluates the 6 x 6 product rule for every non-touching pair,
-//     reduces the 3x3 pair blocks to the block's local vertex tile in LDS and
-//     stores it in an expanded matrix E whose rows are (target block, local
-//     vertex) and whose columns are (source block, local vertex);
+//  1. regular tiles: a workgroup takes TA target x TB source Morton-ordered
+//     triangles (shape chosen by an autotuner), evaluates the 6 x 6 product
+//     rule for every non-touching pair, reduces the 3x3 pair blocks to the
+//     block's local vertex tile in LDS and stores it in an expanded matrix E
+//     whose rows are (target block, local vertex) and whose columns are
+//     (source block, local vertex).  Square shapes evaluate each unordered
+//     pair once (tiles with source block >= target block) and also store the
+//     double layer of the mirrored pair;
 //  2. two coalesced gather passes fold the duplicated rows and columns of E
-//     back onto surface vertices;
+//     back onto surface vertices (square shapes: the mirrored double layer
+//     into an N_v x N_v matrix, then a transpose-add completes V and K, with
+//     the regular part of V bitwise symmetric);
 //  3. touching pairs (identical, common edge, common vertex) are integrated
 //     with the Sauter-Schwab rules (one wavefront per pair) and added, with
 //     the 1/2 M term, by a row-owned scatter.
