@@ -275,7 +275,7 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
 // (sigma, tau) is the transpose of V of (tau, sigma).  The gather then
 // completes the operator: V = U_V + U_V^T, K = U_K + U_Kt^T.
 template <bool YUK, typename RT, int TA, int TB, int MS, bool SYM>
-__global__ void __launch_bounds__(TA * TB, 4)
+__global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)))
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
