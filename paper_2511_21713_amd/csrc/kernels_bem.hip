@@ -636,7 +636,7 @@ __device__ inline double ss_jac(int kind, int r, double xi, double e1, double e2
 // regions x n^4 Gauss points; the 3x3 V and K blocks (in the triangles' own
 // vertex order) go to out[18 * pair].
 template <bool YUK>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     k_bem_singular(int64_t ntp, const int32_t *__restrict__ tp_tau, const int32_t *__restrict__ tp_sig,
                    const int32_t *__restrict__ tri, const double *__restrict__ vx, const double *__restrict__ nrm,
                    const double *__restrict__ area, double kappa, GL4 G, double *__restrict__ out)
