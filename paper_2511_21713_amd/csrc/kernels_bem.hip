@@ -1322,7 +1322,11 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         first = false;
     }
     const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
-    PB_HIP(hipMemsetAsync(B64, 0, sizeof(double) * nv * ld, s));
+    // every entry of [K' | V'] is written below; only the row padding past 2 nv
+    // (read by the dense apply against zero inputs) is cleared, and only
+    // where it is the stored operator (FP32 storage pads when narrowing)
+    if (!stage64 && ld > 2 * nv)
+        PB_HIP(hipMemset2DAsync(B64 + 2 * nv, sizeof(double) * ld, 0, sizeof(double) * (ld - 2 * nv), nv, s));
     const int32_t *cblk = sym ? static_cast<const int32_t *>(DB.slot_blk) : nullptr;
     hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, ld, DB.L_ptr, DB.L,
                        cblk, DA.L_ptr, DA.L_blk, WV, WK, sV, sK, B64);
