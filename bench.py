@@ -469,6 +469,18 @@ def main():
                           "status": r["status"]}
         sch["T3-HS"] = {"value": value, "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"]}
         out["scheme_schedules_fp64"] = sch
+        # the root finders of f_d for the relaxation factor (Newton is the default leg above)
+        om = {}
+        for label, m in (("bisection", pb.OMEGA_BISECT), ("secant", pb.OMEGA_SECANT),
+                         ("bisection_then_secant", pb.OMEGA_BSEC), ("newton_bisection_secant_start", pb.OMEGA_NEWTON_BS)):
+            lg = run_leg(pb, torch, prob, pb.FP64, 2, 0, dict(opts, omega_method=m), f"omega {label}", potential=False)
+            r = lg["res"]
+            om[label] = {"value": 2 / lg["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * lg["elapsed"] / 2,
+                         "newton_iters": r["newton_iters"], "fd_evaluations_after_the_first": r["omega_iters"],
+                         "omega": r["omega"], "rel_energy_diff_vs_newton": abs(r["total"] - res["total"]) / abs(res["total"]),
+                         "status": r["status"]}
+        om["newton"] = {"value": value, "newton_iters": res["newton_iters"], "omega": res["omega"]}
+        out["omega_root_finders_fp64"] = om
     if not args.no_matrix_free:
         # nothing dense stored: every coupled apply evaluates the regular
         # quadrature-point pairs again (the same flops as one assembly)
