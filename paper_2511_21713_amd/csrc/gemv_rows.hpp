@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 namespace pbfb {
 
@@ -92,18 +93,22 @@ __device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restr
 // groups of gsym_g chunks of the row stream), blk = r0 / 16.  Rows past n
 // contribute nothing.  Reads n + r0 + 16 entries of each row instead of 2 n.
 constexpr int GSYM = 4 * GEMV_RW;
-// chunks per LDS exchange: 32 KB of column partials per workgroup
-template <typename MT> constexpr int gsym_g() { return sizeof(MT) == 8 ? 8 : 4; }
+// chunks per LDS exchange: 32 KB of column partials per workgroup.  The
+// partials are kept in the storage precision: FP32 storage already rounds
+// every entry of V' to FP32, and its column partials are rounded once more.
+template <typename MT> constexpr int gsym_g() { return 8; }
+template <typename MT> using sym_part_t = std::conditional_t<sizeof(MT) == 8, double, float>;
 
 template <typename MT>
 __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
-                                     double *__restrict__ P, int64_t n, int64_t ld, int64_t r0, int tid)
+                                     sym_part_t<MT> *__restrict__ P, int64_t n, int64_t ld, int64_t r0, int tid)
 {
+    using PT = sym_part_t<MT>;
     constexpr int RW = GEMV_RW;
     constexpr int EL = sizeof(MT) == 8 ? 2 : 4; // entries per lane per chunk
     constexpr int CW = 64 * EL;                 // columns per chunk
     constexpr int GSYM_G = gsym_g<MT>();
-    __shared__ double part[4][GSYM_G * CW];
+    __shared__ PT part[4][GSYM_G * CW];
     const int lane = tid & 63, wv = tid >> 6;
     const int64_t rw = r0 + RW * wv; // this wavefront's first row
     const int64_t blk = r0 / GSYM;
@@ -201,13 +206,13 @@ __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__r
                 }
             }
 #pragma unroll
-            for (int e = 0; e < EL; ++e) part[wv][g * CW + lane * EL + e] = t[e];
+            for (int e = 0; e < EL; ++e) part[wv][g * CW + lane * EL + e] = PT(t[e]);
         }
         __syncthreads();
         for (int k = tid; k < GSYM_G * CW; k += 256) {
             const int64_t col = g0 * CW + k, j = col - n;
             if (j >= 0 && j < n && col < cend)
-                P[blk * n + j] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+                P[blk * n + j] = PT((double(part[0][k]) + double(part[1][k])) + (double(part[2][k]) + double(part[3][k])));
         }
         __syncthreads();
     }
@@ -228,7 +233,8 @@ __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__r
 // the blocks ty, ty + GFIN_NY, ... for row i0 + tx, and the GFIN_NY partial
 // sums are then added in ty order (fixed, so the result is reproducible).
 constexpr int GFIN_ROWS = 32, GFIN_NY = 256 / GFIN_ROWS;
-__device__ inline void gemv_sym_finish(int64_t n, const double *__restrict__ P, const int32_t *__restrict__ dptr,
+template <typename PT>
+__device__ inline void gemv_sym_finish(int64_t n, const PT *__restrict__ P, const int32_t *__restrict__ dptr,
                                        const int32_t *__restrict__ dcol, const double *__restrict__ dval,
                                        const double *__restrict__ x, double *__restrict__ y, int64_t i0, int tid)
 {
@@ -239,7 +245,7 @@ __device__ inline void gemv_sym_finish(int64_t n, const double *__restrict__ P, 
     double s = 0.0;
     if (i < n) {
 #pragma unroll 4
-        for (int64_t b = i / GSYM + ty; b < nblk; b += GFIN_NY) s += P[b * n + i];
+        for (int64_t b = i / GSYM + ty; b < nblk; b += GFIN_NY) s += double(P[b * n + i]);
     }
     red[ty][tx] = s;
     __syncthreads();

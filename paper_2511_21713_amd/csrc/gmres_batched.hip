@@ -44,7 +44,7 @@ struct GDesc {
     int mf;   // boundary operators applied matrix-free (no dense GEMV)
     // symmetric use of the stored single layer, per surface: column partials, Delta rows
     int symm[2];
-    double *symP[2];
+    void *symP[2]; // in the storage precision
     const int32_t *dl_ptr[2], *dl_col[2];
     const double *dl_val[2];
     const int32_t *gm, *gs;
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256, 4) k_bgemv(const WItem *__restrict__ wl, 
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
     const MT *B = static_cast<const MT *>(it.a == 0 ? d.Bm : d.Bs);
     if (d.symm[it.a]) {
-        gemv_rows_sym<MT>(B, x, y, d.symP[it.a], n, ld, it.b, threadIdx.x);
+        gemv_rows_sym<MT>(B, x, y, static_cast<sym_part_t<MT> *>(d.symP[it.a]), n, ld, it.b, threadIdx.x);
     } else {
         const int64_t r0 = it.b + wv * GEMV_RW;
         if (r0 < n) gemv_rows<MT>(B, x, y, n, ld, r0, lane);
@@ -253,7 +253,12 @@ __global__ void __launch_bounds__(256) k_bgemv_fin(const WItem *__restrict__ wl,
     const int64_t n = it.a == 0 ? d.nm : d.ns;
     const double *x = it.a == 0 ? d.xm : d.xs;
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
-    gemv_sym_finish(n, d.symP[it.a], d.dl_ptr[it.a], d.dl_col[it.a], d.dl_val[it.a], x, y, it.b, threadIdx.x);
+    if (d.f32)
+        gemv_sym_finish(n, static_cast<const float *>(d.symP[it.a]), d.dl_ptr[it.a], d.dl_col[it.a], d.dl_val[it.a], x,
+                        y, it.b, threadIdx.x);
+    else
+        gemv_sym_finish(n, static_cast<const double *>(d.symP[it.a]), d.dl_ptr[it.a], d.dl_col[it.a],
+                        d.dl_val[it.a], x, y, it.b, threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,

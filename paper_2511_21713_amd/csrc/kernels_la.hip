@@ -41,9 +41,10 @@ __global__ void k_pack(int64_t nn, int64_t nm, int64_t ns, int64_t ldm, int64_t 
 struct GemvSurf {
     const void *B;
     const double *x;
-    double *y, *P; // P: column partials of the symmetric storage use
+    double *y;
+    void *P; // column partials of the symmetric use, in the storage precision
     int64_t n, ld;
-    int sym;
+    int sym, f32;
     const int32_t *dptr, *dcol;
     const double *dval;
 };
@@ -60,7 +61,7 @@ __global__ void __launch_bounds__(256, 4) k_gemv(GemvSurf S0, GemvSurf S1, int64
     const int64_t r0 = (S.sym ? nb - 1 - bi : bi) * int64_t(GSYM);
     const MT *B = static_cast<const MT *>(S.B);
     if (S.sym) {
-        gemv_rows_sym<MT>(B, S.x, S.y, S.P, S.n, S.ld, r0, threadIdx.x);
+        gemv_rows_sym<MT>(B, S.x, S.y, static_cast<sym_part_t<MT> *>(S.P), S.n, S.ld, r0, threadIdx.x);
     } else {
         const int64_t rw = r0 + wv * GEMV_RW;
         if (rw < S.n) gemv_rows<MT>(B, S.x, S.y, S.n, S.ld, rw, lane);
@@ -74,7 +75,8 @@ __global__ void __launch_bounds__(256) k_gemv_fin(GemvSurf S0, GemvSurf S1, int6
     const GemvSurf &S = s1 ? S1 : S0;
     if (!S.sym) return;
     const int64_t i0 = (s1 ? blockIdx.x - nb0 : blockIdx.x) * int64_t(GFIN_ROWS);
-    gemv_sym_finish(S.n, S.P, S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
+    if (S.f32) gemv_sym_finish(S.n, static_cast<const float *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
+    else gemv_sym_finish(S.n, static_cast<const double *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -168,6 +170,7 @@ static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y)
     G.n = D.nv;
     G.ld = bem_ld(D.nv);
     G.sym = D.sym ? 1 : 0;
+    G.f32 = p.precision == PBFB_MIXED ? 1 : 0;
     G.P = D.sym ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP1, size_t((D.nv + GSYM - 1) / GSYM) * D.nv)
                 : nullptr;
     G.dptr = D.d_ptr;
