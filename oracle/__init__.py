@@ -108,6 +108,8 @@ def lib():
         L.pbref_root_find.restype = C.c_double
         L.pbref_omega_search.argtypes = [P, C.c_int, dp, dp, C.POINTER(Opts), dp, C.POINTER(C.c_int)]
         L.pbref_reaction_potential.argtypes = [P, dp, C.c_int64, dp, dp]
+        L.pbref_set_two_field.argtypes = [P, C.c_int64]
+        L.pbref_lambda_m.argtypes = [P, dp, C.c_int, dp]
         L.pbref_rule_tri6.argtypes = [dp, dp]
         L.pbref_rule_tet27.argtypes = [dp, dp]
         L.pbref_rule_gauss01.argtypes = [C.c_int, dp, dp]
@@ -209,7 +211,7 @@ class Oracle:
     """One oracle problem instance built from mesh, charges and parameters."""
 
     def __init__(self, nodes, tets, tri_m, tri_s, q_xyz, q_z, eps_in, eps_out, kappa,
-                 temperature=298.15, reg_order=0, n_ss=4):
+                 temperature=298.15, reg_order=0, n_ss=4, n_tets_m=0):
         L = lib()
         self._keep = [_f64(nodes), np.ascontiguousarray(tets, np.int32), np.ascontiguousarray(tri_m, np.int32),
                       np.ascontiguousarray(tri_s, np.int32), _f64(np.reshape(q_xyz, (-1, 3))), _f64(q_z)]
@@ -219,6 +221,9 @@ class Oracle:
                                 reg_order, n_ss)
         if not self.h:
             raise ValueError("oracle rejected the mesh")
+        self.two_field = n_tets_m > 0
+        if self.two_field and L.pbref_set_two_field(self.h, int(n_tets_m)) != 0:
+            raise ValueError("bad solute tet count")
         s = np.zeros(4, np.int64)
         L.pbref_sizes(self.h, _l(s))
         self.n_nodes, self.n_m, self.n_s, self.n = (int(v) for v in s)
@@ -228,6 +233,7 @@ class Oracle:
 
     @classmethod
     def from_problem(cls, p, **kw):
+        kw.setdefault("n_tets_m", getattr(p, "n_tets_m", 0))
         return cls(p.nodes, p.tets, p.tri_m, p.tri_s, p.q_xyz, p.q_z, p.eps_in, p.eps_out, p.kappa, **kw)
 
     def __del__(self):
@@ -387,6 +393,14 @@ class Oracle:
         pn = _f64(phi_nl) if phi_nl is not None else None
         lib().pbref_energy(self.h, _d(pl), _d(pn) if pn is not None else None, _d(out))
         return dict(total=out[0], lc=out[1], nc=out[2], dg_omega_i=out[3])
+
+    def lambda_m(self, u, with_load=True):
+        """lam_m from the trace of u on Gamma_m (Sec. 2.3.1), by a dense solve."""
+        u = _f64(u)
+        out = np.zeros(self.n_m)
+        if lib().pbref_lambda_m(self.h, _d(u), int(bool(with_load)), _d(out)) != 0:
+            raise RuntimeError("singular single layer")
+        return out
 
     def reaction_potential(self, phi, pts):
         phi = _f64(phi); pts = _f64(np.reshape(pts, (-1, 3))); out = np.zeros(pts.shape[0])

@@ -299,7 +299,16 @@ struct pbref {
     int32_t *n2t_ptr, *n2t; /* FEM node -> tets */
     double *tgrad, *tvol;   /* per-tet barycentric gradients (4x3) and volume */
     double *rhs_extra;      /* optional vector added to b (manufactured-solution tests) */
+    /* two-field form (Sec. 2.3, eq. fembem_matrix): the tets from nt_i on fill
+     * the solute, where the permittivity is eps_m and there is no reaction
+     * term; otherwise nt_i = nt and every tet is in the shell */
+    int64_t nt_i;
+    int two_field;
 };
+
+/* permittivity and reaction coefficient eps kappa^2 of tet t */
+static double tet_eps(const pbref *p, int64_t t) { return t < p->nt_i ? p->eps_s : p->eps_m; }
+static double tet_react(const pbref *p, int64_t t) { return t < p->nt_i ? p->eps_s * p->kappa * p->kappa : 0.0; }
 
 static int64_t nunk(const pbref *p) { return p->nn + p->s[0].nv + p->s[1].nv; }
 static void compute_tet_geom(const pbref *p, int64_t t, double grad[4][3], double *vol);
@@ -377,6 +386,7 @@ pbref *pbref_create(int64_t n_nodes, const double *nodes, int64_t n_tets, const 
     pbref *p = calloc(1, sizeof(pbref));
     p->nn = n_nodes;
     p->nt = n_tets;
+    p->nt_i = n_tets;
     p->nq = n_q;
     p->x = malloc(sizeof(double) * 3 * n_nodes);
     memcpy(p->x, nodes, sizeof(double) * 3 * n_nodes);
@@ -857,7 +867,7 @@ void pbref_stiffness_entries(const pbref *p, int32_t *rows, int32_t *cols, doubl
                 int64_t e = 16 * t + 4 * a + b;
                 rows[e] = p->tet[4 * t + a];
                 cols[e] = p->tet[4 * t + b];
-                vals[e] = p->eps_s * vol * vdot(G[a], G[b]);
+                vals[e] = tet_eps(p, t) * vol * vdot(G[a], G[b]);
             }
     }
 }
@@ -884,15 +894,19 @@ void pbref_mass_entries(const pbref *p, int32_t *rows, int32_t *cols, double *va
  *   mode 0: out_a += c int N(u_h) phi_a
  *   mode 1: out_a += c int N'(u_h) v_h phi_a
  *   mode 2: out_a += c int N''(u_h) v_h^2 phi_a
- * with c = eps_s kappa^2 and the 27-point tet rule. */
+ * with c = eps_s kappa^2 (0 in a solute tet of the two-field form) and the
+ * 27-point tet rule. */
 static void tet_reaction(const pbref *p, int64_t t, int scheme, int mode, const double *u, const double *v,
                          double out[4])
 {
     double G[4][3], vol;
     tet_geom(p, t, G, &vol);
     const int32_t *T = p->tet + 4 * t;
-    double c = p->eps_s * p->kappa * p->kappa;
+    double c = tet_react(p, t);
     for (int a = 0; a < 4; ++a) out[a] = 0.0;
+    /* a solute tet has no reaction term; its N(u) is never evaluated (the
+     * potential at a point charge's node is far outside sinh's range) */
+    if (c == 0.0) return;
     for (int q = 0; q < 27; ++q) {
         const double *l = p->tq_b + 4 * q;
         double uh = 0.0, vh = 0.0;
@@ -936,7 +950,7 @@ static void stiffness_apply(const pbref *p, const double *v, double *y)
         tet_geom(p, t, G, &vol);
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b)
-                y[p->tet[4 * t + a]] += p->eps_s * vol * vdot(G[a], G[b]) * v[p->tet[4 * t + b]];
+                y[p->tet[4 * t + a]] += tet_eps(p, t) * vol * vdot(G[a], G[b]) * v[p->tet[4 * t + b]];
     }
 }
 
@@ -944,14 +958,14 @@ static void stiffness_apply(const pbref *p, const double *v, double *y)
 static void fem_diag(const pbref *p, int scheme, const double *u, double *dg)
 {
     memset(dg, 0, sizeof(double) * p->nn);
-    double c = p->eps_s * p->kappa * p->kappa;
     for (int64_t t = 0; t < p->nt; ++t) {
         double G[4][3], vol;
         tet_geom(p, t, G, &vol);
         const int32_t *T = p->tet + 4 * t;
+        const double c = tet_react(p, t);
         for (int a = 0; a < 4; ++a) {
-            double s = p->eps_s * vol * vdot(G[a], G[a]);
-            for (int q = 0; q < 27; ++q) {
+            double s = tet_eps(p, t) * vol * vdot(G[a], G[a]);
+            for (int q = 0; q < 27 && c != 0.0; ++q) {
                 const double *l = p->tq_b + 4 * q;
                 double uh = 0.0;
                 for (int k = 0; k < 4; ++k) uh += l[k] * u[T[k]];
@@ -980,14 +994,18 @@ int pbref_apply_A(pbref *p, const double *phi, double *y)
     int64_t nn = p->nn, nm = p->s[0].nv, ns = p->s[1].nv;
     const double *u = phi, *lm = phi + nn, *ls = phi + nn + nm;
     double *yu = y, *ym = y + nn, *ys = y + nn + nm;
-    /* FEM row: A u + eps_m T_m^T M_m lam_m - eps_s T_s^T M_s lam_s */
+    /* FEM row: A u + eps_m T_m^T M_m lam_m - eps_s T_s^T M_s lam_s; in the
+     * two-field form Gamma_m is inside the FEM domain: no lam_m term */
     stiffness_apply(p, u, yu);
     double *tmp = malloc(sizeof(double) * (nm > ns ? nm : ns));
     pbref_surface_mass_apply(p, 0, lm, tmp);
-    for (int64_t i = 0; i < nm; ++i) yu[p->s[0].g[i]] += p->eps_m * tmp[i];
+    if (!p->two_field)
+        for (int64_t i = 0; i < nm; ++i) yu[p->s[0].g[i]] += p->eps_m * tmp[i];
     pbref_surface_mass_apply(p, 1, ls, tmp);
     for (int64_t i = 0; i < ns; ++i) yu[p->s[1].g[i]] -= p->eps_s * tmp[i];
-    /* Gamma_m row: (1/2 M_m + K0_m) u_m - V0_m lam_m */
+    /* Gamma_m row: (1/2 M_m + K0_m) u_m - V0_m lam_m; in the two-field form
+     * lam_m is not an unknown of the solve (it is recovered afterwards) and
+     * its row is the identity, so it stays zero */
     double *um = malloc(sizeof(double) * nm), *us = malloc(sizeof(double) * ns);
     for (int64_t i = 0; i < nm; ++i) um[i] = u[p->s[0].g[i]];
     for (int64_t i = 0; i < ns; ++i) us[i] = u[p->s[1].g[i]];
@@ -996,7 +1014,7 @@ int pbref_apply_A(pbref *p, const double *phi, double *y)
     for (int64_t i = 0; i < nm; ++i) {
         double s = 0.5 * tmp[i];
         for (int64_t j = 0; j < nm; ++j) s += p->s[0].K[i * nm + j] * um[j] - p->s[0].V[i * nm + j] * lm[j];
-        ym[i] = s;
+        ym[i] = p->two_field ? lm[i] : s;
     }
     /* Gamma_s row: (1/2 M_s - Kk_s) u_s + Vk_s lam_s */
     pbref_surface_mass_apply(p, 1, us, tmp);
@@ -1012,10 +1030,54 @@ int pbref_apply_A(pbref *p, const double *phi, double *y)
     return 0;
 }
 
+/* Point-charge load of the two-field form (Sec. 2.3: rho_c = sum_k Q_k delta_k
+ * tested with the P1 basis): b_a = sum_k Q_k phi_a(x_k), Q_k = 4 pi l_B z_k,
+ * with phi_a(x_k) the barycentric coordinates of x_k in the solute tet that
+ * holds it (the one whose smallest coordinate is largest). */
+static int point_load(const pbref *p, double *b)
+{
+    memset(b, 0, sizeof(double) * p->nn);
+    for (int64_t k = 0; k < p->nq; ++k) {
+        const double *xk = p->qx + 3 * k;
+        int64_t best = -1;
+        double bmin = -1e300, bb[4] = {0, 0, 0, 0};
+        for (int64_t t = p->nt_i; t < p->nt; ++t) {
+            double G[4][3], vol, l[4], d[3], lo = 1e300;
+            tet_geom(p, t, G, &vol);
+            vsub(xk, p->x + 3 * p->tet[4 * t], d);
+            for (int a = 0; a < 4; ++a) {
+                l[a] = (a == 0 ? 1.0 : 0.0) + vdot(G[a], d);
+                if (l[a] < lo) lo = l[a];
+            }
+            if (lo > bmin) {
+                bmin = lo;
+                best = t;
+                memcpy(bb, l, sizeof bb);
+            }
+        }
+        if (best < 0 || bmin < -1e-10) return -3;
+        for (int a = 0; a < 4; ++a) b[p->tet[4 * best + a]] += 4.0 * PI * p->lB * p->qz[k] * bb[a];
+    }
+    return 0;
+}
+
+int pbref_set_two_field(pbref *p, int64_t n_tets_m)
+{
+    if (n_tets_m <= 0 || n_tets_m >= p->nt) return -1;
+    p->nt_i = p->nt - n_tets_m;
+    p->two_field = 1;
+    return 0;
+}
+
 int pbref_rhs(pbref *p, double *b)
 {
     memset(b, 0, sizeof(double) * nunk(p));
-    pbref_coulomb_load(p, b + p->nn);
+    if (p->two_field) {
+        int r = point_load(p, b);
+        if (r) return r;
+    } else {
+        pbref_coulomb_load(p, b + p->nn);
+    }
     if (p->rhs_extra)
         for (int64_t i = 0; i < nunk(p); ++i) b[i] += p->rhs_extra[i];
     return 0;
@@ -1084,10 +1146,18 @@ static int coupled_rows(pbref *p, int scheme, int mode, const double *phi, const
 {
     int64_t nn = p->nn, nm = p->s[0].nv, ns = p->s[1].nv;
     const double *x = mode == 0 ? phi : v;
-    double *fm = NULL;
+    double *fm = NULL, *bu = NULL;
     if (mode == 0) {
         fm = malloc(sizeof(double) * nm);
         pbref_coulomb_load(p, fm);
+        if (p->two_field) {
+            bu = malloc(sizeof(double) * nn);
+            if (point_load(p, bu)) {
+                free(fm);
+                free(bu);
+                return -3;
+            }
+        }
     }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1102,13 +1172,14 @@ static int coupled_rows(pbref *p, int scheme, int mode, const double *phi, const
                 tet_geom(p, t, G, &vol);
                 int a = 0;
                 while (p->tet[4 * t + a] != row) ++a;
-                for (int b = 0; b < 4; ++b) s += p->eps_s * vol * vdot(G[a], G[b]) * x[p->tet[4 * t + b]];
+                for (int b = 0; b < 4; ++b) s += tet_eps(p, t) * vol * vdot(G[a], G[b]) * x[p->tet[4 * t + b]];
                 double loc[4];
                 tet_reaction(p, t, scheme, mode == 0 ? 0 : 1, phi, mode == 0 ? NULL : v, loc);
                 s += loc[a];
             }
+            if (bu) s -= bu[row];
             /* surface mass couplings */
-            for (int w = 0; w < 2; ++w) {
+            for (int w = p->two_field ? 1 : 0; w < 2; ++w) {
                 const surface *S = &p->s[w];
                 int32_t i = p->loc[w][row];
                 if (i < 0) continue;
@@ -1122,6 +1193,8 @@ static int coupled_rows(pbref *p, int scheme, int mode, const double *phi, const
                     }
                 }
             }
+        } else if (p->two_field && row < nn + nm) {
+            s = x[row]; /* identity row of lam_m */
         } else if (row < nn + nm + ns) {
             int w = row < nn + nm ? 0 : 1;
             const surface *S = &p->s[w];
@@ -1154,6 +1227,7 @@ static int coupled_rows(pbref *p, int scheme, int mode, const double *phi, const
         out[r] = s;
     }
     free(fm);
+    free(bu);
     return err;
 }
 
@@ -1288,9 +1362,12 @@ int pbref_spai_rows(int64_t n, const double *B, const int32_t *ptr, const int32_
 }
 
 /* entries of row i of F = A + J_scheme(u), assembled from the tets at i */
+/* distinct neighbours of node i (itself included) are at most 3 per tet + 1 */
+static int64_t row_cap(const pbref *p, int64_t i) { return 3 * (int64_t)(p->n2t_ptr[i + 1] - p->n2t_ptr[i]) + 1; }
+
 static int fem_row(const pbref *p, int scheme, const double *u, int64_t i, int32_t *cols, double *vals)
 {
-    double c = p->eps_s * p->kappa * p->kappa;
+    const int64_t cap = row_cap(p, i);
     int m = 0;
     for (int32_t e = p->n2t_ptr[i]; e < p->n2t_ptr[i + 1]; ++e) {
         int64_t t = p->n2t[e];
@@ -1299,9 +1376,10 @@ static int fem_row(const pbref *p, int scheme, const double *u, int64_t i, int32
         while (T[a] != i) ++a;
         double G[4][3], vol;
         tet_geom(p, t, G, &vol);
+        const double c = tet_react(p, t);
         for (int b = 0; b < 4; ++b) {
-            double s = p->eps_s * vol * vdot(G[a], G[b]);
-            for (int q = 0; q < 27; ++q) {
+            double s = tet_eps(p, t) * vol * vdot(G[a], G[b]);
+            for (int q = 0; q < 27 && c != 0.0; ++q) {
                 const double *l = p->tq_b + 4 * q;
                 double uh = 0.0;
                 for (int k = 0; k < 4; ++k) uh += l[k] * u[T[k]];
@@ -1310,7 +1388,7 @@ static int fem_row(const pbref *p, int scheme, const double *u, int64_t i, int32
             int k = 0;
             while (k < m && cols[k] != T[b]) ++k;
             if (k == m) {
-                if (m == 128) return -1;
+                if (m == cap) return -1;
                 cols[m] = T[b];
                 vals[m++] = 0.0;
             }
@@ -1323,17 +1401,26 @@ static int fem_row(const pbref *p, int scheme, const double *u, int64_t i, int32
 double pbref_fem_gershgorin(const pbref *p, int scheme, const double *u)
 {
     double best = 0.0;
+    int64_t mx = 1;
+    for (int64_t i = 0; i < p->nn; ++i)
+        if (row_cap(p, i) > mx) mx = row_cap(p, i);
+    int32_t *cols = malloc(sizeof(int32_t) * mx);
+    double *vals = malloc(sizeof(double) * mx);
     for (int64_t i = 0; i < p->nn; ++i) {
-        int32_t cols[128];
-        double vals[128], sum = 0.0, dg = 0.0;
+        double sum = 0.0, dg = 0.0;
         int m = fem_row(p, scheme, u, i, cols, vals);
-        if (m < 0) return NAN;
+        if (m < 0) {
+            best = NAN;
+            break;
+        }
         for (int k = 0; k < m; ++k) {
             sum += fabs(vals[k]);
             if (cols[k] == i) dg = vals[k];
         }
         best = fmax(best, sum / dg);
     }
+    free(cols);
+    free(vals);
     return best;
 }
 
@@ -1391,8 +1478,8 @@ static int fem_block_csr(const pbref *p, int scheme, const double *u, csr *F)
 {
     F->n = p->nn;
     F->ptr = malloc(sizeof(int32_t) * (p->nn + 1));
-    F->col = malloc(sizeof(int32_t) * 128 * p->nn);
-    F->val = malloc(sizeof(double) * 128 * p->nn);
+    F->col = malloc(sizeof(int32_t) * (12 * p->nt + p->nn));
+    F->val = malloc(sizeof(double) * (12 * p->nt + p->nn));
     F->ptr[0] = 0;
     for (int64_t i = 0; i < p->nn; ++i) {
         int m = fem_row(p, scheme, u, i, F->col + F->ptr[i], F->val + F->ptr[i]);
@@ -1619,11 +1706,94 @@ int pbref_reaction_potential(const pbref *p, const double *phi, int64_t np, cons
     return 0;
 }
 
+/* Solve A x = r for a dense n x n A (row-major, overwritten) by Gaussian
+ * elimination with partial pivoting; r is overwritten by x. */
+static int dense_solve(int64_t n, double *A, double *r)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t piv = k;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (A[piv * n + k] == 0.0) return -1;
+        if (piv != k) {
+            for (int64_t j = 0; j < n; ++j) {
+                double t = A[k * n + j];
+                A[k * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            double t = r[k];
+            r[k] = r[piv];
+            r[piv] = t;
+        }
+#pragma omp parallel for
+        for (int64_t i = k + 1; i < n; ++i) {
+            double f = A[i * n + k] / A[k * n + k];
+            for (int64_t j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            r[i] -= f * r[k];
+        }
+    }
+    for (int64_t k = n - 1; k >= 0; --k) {
+        double s = r[k];
+        for (int64_t j = k + 1; j < n; ++j) s -= A[k * n + j] * r[j];
+        r[k] = s / A[k * n + k];
+    }
+    return 0;
+}
+
+/* Normal derivative on Gamma_m from the trace of u (Sec. 2.3.1, the limit
+ * of the representation formula on Gamma_m): V0 lam_m = (1/2 M_m + K0_m) u_m
+ * - f_m, with f_m the Coulomb load when with_load is set (the linear part
+ * Phi_L carries the charges; the correction Phi_NL does not). */
+int pbref_lambda_m(pbref *p, const double *u, int with_load, double *lam)
+{
+    int r = pbref_bem_dense(p, 0);
+    if (r) return r;
+    const surface *S = &p->s[0];
+    int64_t nm = S->nv;
+    double *um = malloc(sizeof(double) * nm), *fm = malloc(sizeof(double) * nm);
+    double *A = malloc(sizeof(double) * nm * nm);
+    for (int64_t i = 0; i < nm; ++i) um[i] = u[S->g[i]];
+    pbref_surface_mass_apply(p, 0, um, lam);
+    if (with_load) pbref_coulomb_load(p, fm);
+    for (int64_t i = 0; i < nm; ++i) {
+        double s = 0.5 * lam[i];
+        for (int64_t j = 0; j < nm; ++j) s += S->K[i * nm + j] * um[j];
+        lam[i] = s - (with_load ? fm[i] : 0.0);
+    }
+    for (int64_t i = 0; i < nm * nm; ++i) A[i] = S->V[i];
+    r = dense_solve(nm, A, lam);
+    free(um);
+    free(fm);
+    free(A);
+    return r;
+}
+
 /* out = {Total, LC, NC, dG_Omega_i} in kcal/mol (eqs. Esolv, Esolv_Lineal):
  * LC, NC = 1/2 kT sum_k z_k u_r[Phi_L or Phi_NL](x_k);
  * dG = kT/(4 pi l_B) * 1/2 eps_s kappa^2 int (u sinh u - 2 cosh u + 2). */
 int pbref_energy(pbref *p, const double *phi_lin, const double *phi_nl, double out[4])
 {
+    double *pl = NULL, *pn = NULL;
+    if (p->two_field) {
+        /* the reaction potential needs lam_m: recover it from the trace of u
+         * for each part (Sec. 2.3.1) */
+        const int64_t n = nunk(p);
+        pl = malloc(sizeof(double) * n);
+        memcpy(pl, phi_lin, sizeof(double) * n);
+        int r = pbref_lambda_m(p, phi_lin, 1, pl + p->nn);
+        if (!r && phi_nl) {
+            pn = malloc(sizeof(double) * n);
+            memcpy(pn, phi_nl, sizeof(double) * n);
+            r = pbref_lambda_m(p, phi_nl, 0, pn + p->nn);
+        }
+        if (r) {
+            free(pl);
+            free(pn);
+            return r;
+        }
+        phi_lin = pl;
+        if (phi_nl) phi_nl = pn;
+    }
     double *ur = malloc(sizeof(double) * (p->nq > 0 ? p->nq : 1));
     double lc = 0.0, nc = 0.0;
     pbref_reaction_potential(p, phi_lin, p->nq, p->qx, ur);
@@ -1633,7 +1803,7 @@ int pbref_energy(pbref *p, const double *phi_lin, const double *phi_nl, double o
         for (int64_t k = 0; k < p->nq; ++k) nc += 0.5 * p->kT * p->qz[k] * ur[k];
     }
     double integral = 0.0;
-    for (int64_t t = 0; t < p->nt; ++t) {
+    for (int64_t t = 0; t < p->nt_i; ++t) { /* Omega_i only */
         double G[4][3], vol;
         tet_geom(p, t, G, &vol);
         const int32_t *T = p->tet + 4 * t;
@@ -1650,6 +1820,8 @@ int pbref_energy(pbref *p, const double *phi_lin, const double *phi_nl, double o
     out[2] = nc;
     out[3] = dg;
     free(ur);
+    free(pl);
+    free(pn);
     return 0;
 }
 

@@ -1,5 +1,5 @@
 /* pbref -- plain FP64 CPU oracle for the three-region FEM-BEM nonlinear
- * Poisson-Boltzmann problem.  TEST INFRASTRUCTURE ONLY: it exists to check the
+ * Poisson-Boltzmann problem (and its two-field form, pbref_set_two_field).  TEST INFRASTRUCTURE ONLY: it exists to check the
  * HIP library, it is slow on purpose, and no product code may link or call it.
  *
  * Unknowns: Phi = [u (FEM nodes) | lambda_m (Gamma_m vertices) | lambda_s
@@ -64,6 +64,14 @@ int pbref_apply_A(pbref *, const double *phi, double *y);
 int pbref_dense_rows_apply(const pbref *, int surf, int64_t nrows, const double *V, const double *K,
                            const double *x, double *out);
 int pbref_rhs(pbref *, double *b);
+/* Two-field form (Sec. 2.3, eq. fembem_matrix): the last n_tets_m tets fill
+ * the solute (eps_m, no reaction term), the load is the point charges in the
+ * FEM rows, the FEM rows lose their lam_m term and the lam_m rows become the
+ * identity (lam_m is recovered after the solve by pbref_lambda_m, and
+ * pbref_energy does so itself).  Returns -1 unless 0 < n_tets_m < n_tets. */
+int pbref_set_two_field(pbref *, int64_t n_tets_m);
+/* lam = V0^-1 ((1/2 M_m + K0_m) u|Gamma_m - [with_load] f_m) (Sec. 2.3.1) */
+int pbref_lambda_m(pbref *, const double *u, int with_load, double *lam);
 /* add a fixed vector to b in pbref_rhs, pbref_residual and pbref_solve (NULL clears);
  * used to impose the volume source and interface jumps of manufactured solutions */
 void pbref_set_rhs_extra(pbref *, const double *e);

@@ -47,6 +47,7 @@ class Problem:
     eps_out: float
     kappa: float
     info: dict
+    n_tets_m: int = 0      # > 0: the last n_tets_m tets fill the solute (two-field form)
 
     @property
     def n_nodes(self):
@@ -173,6 +174,44 @@ def shell_mesh(unit, tris, r_in, thickness, layers):
     tri_m = tris.astype(np.int64)
     tri_s = tris.astype(np.int64) + L * nv
     return nodes, tets.astype(np.int32), tri_m.astype(np.int32), tri_s.astype(np.int32)
+
+
+def solute_mesh(unit, tris, r_m, layers, first_id):
+    """Tets filling the star-shaped solute inside r_m(x) x: `layers` scaled
+    copies of Gamma_m at radial fractions 1 - k/(layers+1), prisms between
+    neighbouring copies split as in the shell, and a cone from the innermost
+    copy to the centre.  New nodes are numbered from `first_id`; Gamma_m keeps
+    ids 0..nv-1, so the shell part of the mesh is unchanged."""
+    nv = unit.shape[0]
+    L = int(layers)
+    nodes = np.concatenate([(r_m * (1.0 - k / (L + 1.0)))[:, None] * unit for k in range(1, L + 1)]
+                           + [np.zeros((1, 3))])
+    t = np.sort(tris.astype(np.int64), axis=1)
+    a, b, c = t[:, 0], t[:, 1], t[:, 2]
+
+    def layer(k):  # global id offset of copy k (0 = Gamma_m)
+        return 0 if k == 0 else first_id + (k - 1) * nv
+
+    tets = []
+    for k in range(L):
+        lo, hi = layer(k), layer(k + 1)
+        A, B, C = a + lo, b + lo, c + lo
+        A2, B2, C2 = a + hi, b + hi, c + hi
+        tets.append(np.stack([A, B, C, C2], 1))
+        tets.append(np.stack([A, B, B2, C2], 1))
+        tets.append(np.stack([A, A2, B2, C2], 1))
+    centre = first_id + L * nv
+    inner = layer(L)
+    tets.append(np.stack([a + inner, b + inner, c + inner, np.full_like(a, centre)], 1))
+    return nodes, np.concatenate(tets)
+
+
+def _orient(nodes, tets):
+    p = nodes[tets]
+    vol = np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
+    neg = vol < 0
+    tets[neg] = tets[neg][:, [0, 2, 1, 3]]
+    return tets
 
 
 # ----------------------------------------------------------------------------
@@ -331,12 +370,22 @@ def config_params(cfg: int):
 
 
 def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
-                 eps_in=4.0, eps_out=80.0, clearance=1.5, center_charge=None):
+                 eps_in=4.0, eps_out=80.0, clearance=1.5, center_charge=None, solute_layers=0):
+    """solute_layers > 0 adds the tets of the solute (Sec. 2.3's FEM domain
+    Omega_m u Omega_i): they follow the shell tets, their new nodes follow the
+    shell nodes, and Problem.n_tets_m counts them."""
     rng = np.random.default_rng(list(seed))
     unit, tris = icosphere(n)
     r, amp = radial_surface(unit, a, c, rng if bump else None)
     nodes, tets, tri_m, tri_s = shell_mesh(unit, tris, r, t, L)
-    log = dict(n=n, a=a, c=c, amp=amp, t=t, L=L, seed=list(seed))
+    n_tets_m = 0
+    if solute_layers:
+        inodes, itets = solute_mesh(unit, tris, r, solute_layers, nodes.shape[0])
+        nodes = np.concatenate([nodes, inodes])
+        itets = _orient(nodes, itets)
+        n_tets_m = int(itets.shape[0])
+        tets = np.concatenate([tets, itets.astype(np.int32)])
+    log = dict(n=n, a=a, c=c, amp=amp, t=t, L=L, seed=list(seed), solute_layers=int(solute_layers))
     gm = nodes[: unit.shape[0]]
     qx, qz = [], []
     if center_charge is not None:
@@ -356,7 +405,7 @@ def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
                    tri_m=np.ascontiguousarray(tri_m), tri_s=np.ascontiguousarray(tri_s),
                    q_xyz=np.ascontiguousarray(q_xyz, dtype=np.float64),
                    q_z=np.ascontiguousarray(q_z, dtype=np.float64),
-                   eps_in=eps_in, eps_out=eps_out, kappa=kappa, info=log)
+                   eps_in=eps_in, eps_out=eps_out, kappa=kappa, info=log, n_tets_m=n_tets_m)
 
 
 def make_config(cfg: int, instance: int = 0, **override):
