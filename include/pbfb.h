@@ -280,6 +280,24 @@ pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *t
 enum { PBFB_BEM_DENSE = 0, PBFB_BEM_MATRIX_FREE = 1 };
 pbfb_status pbfb_set_bem_mode(pbfb_problem *p, int mode);
 
+/* The two-field form of Sec. 2.3 (eq. fembem_matrix): the FEM domain is the
+ * solute and the shell, and the last n_tets_m tets of the mesh fill the
+ * solute (Gamma_m is then an interface inside the FEM mesh; the solute's
+ * nodes may be numbered anywhere).  There the permittivity is eps_in and
+ * there is no reaction term; the charges load the FEM rows as point sources
+ * (b_a = sum_k 4 pi l_B z_k phi_a(x_k), each charge in the solute tet that
+ * holds it, else PBFB_ECHARGE at setup); the FEM rows have no lambda_m term
+ * and the lambda_m rows are the identity, so lambda_m stays zero through
+ * the Newton solve and Phi = [u | 0 | lambda_s].  The energy (pbfb_energy,
+ * pbfb_solve's result) recovers lambda_m first from the trace of u with the
+ * Laplace operators of Gamma_m (Sec. 2.3.1: V0 lambda_m = (1/2 M_m + K0_m)
+ * u - f_m, by conjugate gradients to 1e-13, PBFB_ENOTCONV otherwise).
+ * n_tets_m = 0 returns to the shell-only form above.  Needs dense boundary
+ * operators (PBFB_EINVAL in matrix-free mode, and set_bem_mode refuses
+ * matrix-free while it is on); PBFB_ESTATE before set_mesh, PBFB_EINVAL
+ * unless 0 <= n_tets_m < n_tets.  set_mesh resets it to 0. */
+pbfb_status pbfb_set_two_field(pbfb_problem *p, int64_t n_tets_m);
+
 /* ---- inspection --------------------------------------------------------- */
 /* Copy the two dense blocks stored for surface `surf` (0 = Gamma_m, Laplace;
  * 1 = Gamma_s, Yukawa) as row-major n x n host arrays (either may be NULL):
@@ -290,7 +308,8 @@ pbfb_status pbfb_set_bem_mode(pbfb_problem *p, int mode);
  * In mixed precision the FP32 stored values are widened.  PBFB_ESTATE in
  * matrix-free mode (nothing is stored). */
 pbfb_status pbfb_export_bem(pbfb_problem *p, int surf, double *Vp, double *Kp);
-/* Right-hand side b = [0 | f_m | 0] (host array of length n_unknowns). */
+/* Right-hand side b = [0 | f_m | 0] (host array of length n_unknowns); in
+ * the two-field form b = [point-charge load | 0 | 0]. */
 pbfb_status pbfb_export_rhs(pbfb_problem *p, double *b);
 /* Kernel timing with HIP events recorded on the stream each kernel runs on.
  * While enabled, every launch of the timed kernel classes is bracketed by an

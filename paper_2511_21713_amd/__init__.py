@@ -28,7 +28,7 @@ EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_probl
            "pbfb_reset_operators", "pbfb_residual",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
            "pbfb_server_submit", "pbfb_server_poll", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
-           "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_assembly_chunk", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
+           "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_two_field", "pbfb_set_assembly_chunk", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
 
 
 class PbfbError(RuntimeError):
@@ -116,6 +116,7 @@ def lib():
         L.pbfb_set_tile_shape.argtypes = [P, C.c_int, C.c_int]
         L.pbfb_set_assembly_chunk.argtypes = [P, C.c_int64]
         L.pbfb_set_bem_mode.argtypes = [P, C.c_int]
+        L.pbfb_set_two_field.argtypes = [P, C.c_int64]
         L.pbfb_get_tile_shape.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pbfb_timing_enable.argtypes = [P, C.c_int]
         L.pbfb_timing.argtypes = [P, C.c_int, C.POINTER(C.c_double), I64P, C.c_int]
@@ -255,6 +256,8 @@ class Problem:
         self.set_mesh(prob.nodes, prob.tets, prob.tri_m, prob.tri_s)
         self.set_charges(prob.q_xyz, prob.q_z)
         self.set_params(prob.eps_in, prob.eps_out, prob.kappa, temperature)
+        if getattr(prob, "n_tets_m", 0):
+            self.set_two_field(prob.n_tets_m)
         return self
 
     def close(self):
@@ -358,6 +361,10 @@ class Problem:
     def set_bem_mode(self, mode):
         """BEM_DENSE (stored Galerkin blocks) or BEM_MATRIX_FREE (evaluated at every apply)."""
         _check(lib().pbfb_set_bem_mode(self.h, mode))
+
+    def set_two_field(self, n_tets_m):
+        """Two-field form: the last n_tets_m tets fill the solute (0: shell-only form)."""
+        _check(lib().pbfb_set_two_field(self.h, int(n_tets_m)))
 
     def set_assembly_chunk(self, max_entries=0):
         """Largest expanded-matrix chunk per operator in entries (0: default 2^30)."""

@@ -380,6 +380,7 @@ pbfb_status pbfb_set_mesh(pbfb_problem *pp, int64_t n_nodes, const double *nodes
     p.have_mesh = false;
     p.nn = n_nodes;
     p.ntet = n_tets;
+    p.ntet_m = 0;
     p.x.assign(nodes, nodes + 3 * n_nodes);
     for (double v : p.x) PB_CHECK(std::isfinite(v), PBFB_EINVAL, "non-finite node coordinate");
     p.tet.assign(tets, tets + 4 * n_tets);
@@ -685,10 +686,27 @@ pbfb_status pbfb_set_bem_mode(pbfb_problem *pp, int mode)
     PB_CHECK(pp && (mode == PBFB_BEM_DENSE || mode == PBFB_BEM_MATRIX_FREE), PBFB_EINVAL, "bad boundary-operator mode");
     Problem &p = live(pp);
     const bool mf = mode == PBFB_BEM_MATRIX_FREE;
+    PB_CHECK(!(mf && p.two_field()), PBFB_EINVAL, "the two-field form needs dense boundary operators");
     if (mf != p.bem_mf) {
         p.bem_mf = mf;
         p.bem_ready[0] = p.bem_ready[1] = false;
         p.bem_topo_ready[0] = p.bem_topo_ready[1] = false;
+    }
+    API_END
+}
+
+pbfb_status pbfb_set_two_field(pbfb_problem *pp, int64_t n_tets_m)
+{
+    API_BEGIN
+    PB_CHECK(pp, PBFB_EINVAL, "null problem");
+    Problem &p = live(pp);
+    PB_CHECK(p.have_mesh, PBFB_ESTATE, "set_mesh must precede set_two_field");
+    PB_CHECK(n_tets_m >= 0 && n_tets_m < p.ntet, PBFB_EINVAL, "n_tets_m must be in [0, n_tets)");
+    PB_CHECK(!(n_tets_m > 0 && p.bem_mf), PBFB_EINVAL, "the two-field form needs dense boundary operators");
+    if (n_tets_m != p.ntet_m) {
+        p.ntet_m = n_tets_m;
+        p.val_ready = false; // permittivity per tet and the Gamma_m coupling
+        p.fm_ready = false;  // the load
     }
     API_END
 }

@@ -42,6 +42,7 @@ struct GDesc {
     int f32;  // operator values in FP32
     int vf32; // Krylov basis stored in FP32
     int mf;   // boundary operators applied matrix-free (no dense GEMV)
+    int two_field; // lambda_m is not an unknown (two-field form): identity row, no Gamma_m GEMV
     // symmetric use of the stored single layer, per surface: column partials, Delta rows
     int symm[2];
     void *symP[2]; // in the storage precision
@@ -110,7 +111,9 @@ __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, con
     const double *in0 = s.st == G_ARN ? d.z : d.x; // ARN: P^-1 V_j, RES: x
     auto in = [&](int64_t r) { return in0[r]; };
     for (int64_t k = it.b + threadIdx.x; k < it.b + CH; k += 256) {
-        if (k < d.ldm) {
+        if (d.two_field) {
+            if (k < d.nm) d.w[d.nn + k] = in(d.nn + k); // identity row of lambda_m
+        } else if (k < d.ldm) {
             double v = 0.0;
             if (k < d.nm) v = in(d.gm[k]);
             else if (k < 2 * d.nm) v = in(d.nn + (k - d.nm));
@@ -633,6 +636,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.lds = bem_ld(d.ns);
         d.f32 = p.precision == PBFB_MIXED;
         d.mf = p.bem_mf ? 1 : 0;
+        d.two_field = p.two_field() ? 1 : 0;
         d.gm = p.surf[0].g;
         d.gs = p.surf[1].g;
         d.sptr = p.d_sptr;
@@ -695,7 +699,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         for (int64_t c = 0; c < d.nch; ++c) wl_vec.push_back(WItem{q, int(c), c * CH});
         for (int64_t c = 0; c < d.nchb; ++c) wl_dot.push_back(WItem{q, int(c), c * CHB});
         static_assert(GROWS == GSYM, "GEMV work items are the symmetric routine's row blocks");
-        for (int a = 0; a < 2; ++a) {
+        for (int a = d.two_field ? 1 : 0; a < 2; ++a) {
             const int64_t nv = a == 0 ? d.nm : d.ns;
             if (d.symm[a]) { // the last rows read the most: dispatched first
                 for (int64_t r = (nv - 1) / GROWS * GROWS; r >= 0; r -= GROWS) wl_gemv.push_back(WItem{q, a, r});

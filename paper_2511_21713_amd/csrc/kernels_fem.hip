@@ -120,17 +120,17 @@ __global__ void k_tri_geom(int64_t nt, const double *__restrict__ x, const int32
 // ---------------------------------------------------------------------------
 __global__ void k_stiffness(int64_t nn, const int32_t *__restrict__ n2t_ptr, const int32_t *__restrict__ n2t,
                             const int32_t *__restrict__ slot4, const double *__restrict__ tg, double eps_s,
-                            double *__restrict__ val0)
+                            int64_t nt_i, double eps_m, double *__restrict__ val0)
 {
     int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (a >= nn) return;
     for (int32_t e = n2t_ptr[a]; e < n2t_ptr[a + 1]; ++e) {
         int32_t t = n2t[e] >> 2, la = n2t[e] & 3;
         const double *G = tg + 16 * int64_t(t);
-        double vol = G[12];
+        const double vol = G[12], eps = t < nt_i ? eps_s : eps_m; // tets from nt_i on: solute
         for (int b = 0; b < 4; ++b) {
             double gg = G[3 * la] * G[3 * b] + G[3 * la + 1] * G[3 * b + 1] + G[3 * la + 2] * G[3 * b + 2];
-            val0[slot4[4 * int64_t(e) + b]] += eps_s * vol * gg;
+            val0[slot4[4 * int64_t(e) + b]] += eps * vol * gg;
         }
     }
 }
@@ -216,10 +216,16 @@ template <int MODE>
 __global__ void __launch_bounds__(128)
     k_tet_reaction(int64_t ntet, const double *__restrict__ tg, const int32_t *__restrict__ tet,
                    const double *__restrict__ u, const double *__restrict__ D, double omega, int scheme, double c,
-                   TetRuleArg R, double *__restrict__ out)
+                   TetRuleArg R, int64_t nt_i, double *__restrict__ out)
 {
     const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (t >= ntet) return;
+    constexpr int NZ = MODE == MODE_N ? 4 : MODE == MODE_W ? 12 : 16;
+    if (t >= nt_i) { // solute tet: no reaction term, and calN is never evaluated there
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) out[NZ * t + k] = 0.0;
+        return;
+    }
     const int32_t *T = tet + 4 * t;
     double uk[4], dk[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) {
@@ -344,6 +350,67 @@ __global__ void k_energy_integral(int64_t nt, const double *__restrict__ tg, con
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Point-charge load of the two-field form (Sec. 2.3): b_a = sum_k Q_k phi_a(x_k),
+// Q_k = 4 pi l_B z_k.  One workgroup per charge finds the solute tet whose
+// smallest barycentric coordinate of x_k is largest (ties: the lower tet id);
+// one thread then adds the charges in order, so the sum is deterministic.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_point_locate(int64_t nt0, int64_t nt, const double *__restrict__ x,
+                                                      const int32_t *__restrict__ tet, const double *__restrict__ tg,
+                                                      const double *__restrict__ q, double *__restrict__ loc)
+{
+    __shared__ double sv[256];
+    __shared__ int64_t st[256];
+    const int64_t k = blockIdx.x;
+    const double xk[3] = {q[4 * k], q[4 * k + 1], q[4 * k + 2]};
+    double best = -1e300;
+    int64_t bt = -1;
+    for (int64_t t = nt0 + threadIdx.x; t < nt; t += 256) {
+        const double *G = tg + 16 * t, *x0 = x + 3 * int64_t(tet[4 * t]);
+        const double d[3] = {xk[0] - x0[0], xk[1] - x0[1], xk[2] - x0[2]};
+        double lo = 1e300;
+        for (int a = 0; a < 4; ++a)
+            lo = fmin(lo, (a == 0 ? 1.0 : 0.0) + G[3 * a] * d[0] + G[3 * a + 1] * d[1] + G[3 * a + 2] * d[2]);
+        if (lo > best) { best = lo; bt = t; }
+    }
+    sv[threadIdx.x] = best;
+    st[threadIdx.x] = bt;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double o = sv[threadIdx.x + w];
+            const int64_t ot = st[threadIdx.x + w];
+            if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && ot >= 0 && (st[threadIdx.x] < 0 || ot < st[threadIdx.x]))) {
+                sv[threadIdx.x] = o;
+                st[threadIdx.x] = ot;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t t = st[0];
+        loc[6 * k] = double(t);
+        loc[6 * k + 1] = sv[0];
+        if (t >= 0) {
+            const double *G = tg + 16 * t, *x0 = x + 3 * int64_t(tet[4 * t]);
+            const double d[3] = {xk[0] - x0[0], xk[1] - x0[1], xk[2] - x0[2]};
+            for (int a = 0; a < 4; ++a)
+                loc[6 * k + 2 + a] = (a == 0 ? 1.0 : 0.0) + G[3 * a] * d[0] + G[3 * a + 1] * d[1] + G[3 * a + 2] * d[2];
+        }
+    }
+}
+
+__global__ void k_point_scatter(int64_t nq, const int32_t *__restrict__ tet, const double *__restrict__ q,
+                                const double *__restrict__ loc, double qscale, double *__restrict__ b)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int64_t k = 0; k < nq; ++k) {
+        const int64_t t = int64_t(loc[6 * k]);
+        for (int a = 0; a < 4; ++a) b[tet[4 * t + a]] += qscale * q[4 * k + 3] * loc[6 * k + 2 + a];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -583,8 +650,9 @@ void ensure_values(Problem &p, hipStream_t s)
     ensure_geometry(p, s);
     PB_HIP(hipMemsetAsync(p.d_val0, 0, sizeof(double) * p.nnz, s));
     hipLaunchKernelGGL(k_stiffness, dim3(nblocks(p.nn, 256)), dim3(256), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t,
-                       p.d_slot4, p.d_tgeo, p.eps_s, p.d_val0);
-    for (int w = 0; w < 2; ++w) {
+                       p.d_slot4, p.d_tgeo, p.eps_s, p.ntet_i(), p.eps_m, p.d_val0);
+    // the two-field form has Gamma_m inside the FEM domain: no lambda_m columns
+    for (int w = p.two_field() ? 1 : 0; w < 2; ++w) {
         SurfaceDev &S = p.surf[w];
         double coef = w == 0 ? p.eps_m : -p.eps_s;
         hipLaunchKernelGGL(k_surface_coupling, dim3(nblocks(S.nv, 256)), dim3(256), 0, s, S.nv, S.v2t_ptr, S.v2t,
@@ -618,10 +686,26 @@ void ensure_rhs(Problem &p, hipStream_t s)
                      "charge " + std::to_string(k) + " is closer than 1 A to Gamma_m");
         }
         double *trif = scratch<double>(p, SCR_TRIF, 3 * S.nt);
+        // the Coulomb load f_m: the Gamma_m rows of b, or (two-field form) kept
+        // for the recovery of lambda_m while the point charges load the FEM rows
+        double *fm = p.two_field() ? scratch<double>(p, SCR_FM, S.nv) : p.d_b + p.nn;
         hipLaunchKernelGGL(k_coulomb_tri, dim3(nblocks(S.nt, 128)), dim3(128), 0, s, S.nt, S.qp, S.area, p.d_q, p.nq,
                            p.lB / p.eps_m, tri_rule_arg(), trif);
         hipLaunchKernelGGL(k_gather_vertex, dim3(nblocks(S.nv, 256)), dim3(256), 0, s, S.nv, S.v2t_ptr, S.v2t, trif,
-                           p.d_b + p.nn);
+                           fm);
+        if (p.two_field()) {
+            double *loc = scratch<double>(p, SCR_PLOC, 6 * p.nq);
+            hipLaunchKernelGGL(k_point_locate, dim3(unsigned(p.nq)), dim3(256), 0, s, p.ntet_i(), p.ntet, p.d_x,
+                               p.d_tet, p.d_tgeo, p.d_q, loc);
+            std::vector<double> h(6 * p.nq);
+            PB_HIP(hipMemcpyAsync(h.data(), loc, sizeof(double) * 6 * p.nq, hipMemcpyDeviceToHost, s));
+            PB_HIP(hipStreamSynchronize(s));
+            for (int64_t k = 0; k < p.nq; ++k)
+                PB_CHECK(h[6 * k] >= 0 && h[6 * k + 1] >= -1e-10, PBFB_ECHARGE,
+                         "charge " + std::to_string(k) + " lies in no solute tet");
+            hipLaunchKernelGGL(k_point_scatter, dim3(1), dim3(64), 0, s, p.nq, p.d_tet, p.d_q, loc,
+                               4.0 * M_PI * p.lB, p.d_b);
+        }
         PB_HIP(hipGetLastError());
     }
     p.fm_ready = true;
@@ -632,7 +716,7 @@ void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t 
     const double c = p.eps_s * p.kappa * p.kappa;
     double *Jt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_J>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
-                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), Jt);
+                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Jt);
     hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_sptr, p.d_val0, p.d_val,
                        p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, Jt);
     PB_HIP(hipGetLastError());
@@ -651,7 +735,7 @@ void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStre
     const double c = p.eps_s * p.kappa * p.kappa;
     double *Nt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_N>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
-                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), Nt);
+                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Nt);
     hipLaunchKernelGGL(k_node_gather<1>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Nt,
                        out, (double *)nullptr, (double *)nullptr);
     PB_HIP(hipGetLastError());
@@ -663,7 +747,7 @@ void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, d
     const double c = p.eps_s * p.kappa * p.kappa;
     double *Wt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_W>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
-                       u, D, omega, scheme, c, tet_rule_arg(), Wt);
+                       u, D, omega, scheme, c, tet_rule_arg(), p.ntet_i(), Wt);
     hipLaunchKernelGGL(k_node_gather<3>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Wt,
                        rN, rJ, rH);
     PB_HIP(hipGetLastError());
@@ -673,8 +757,8 @@ double fem_energy_integral(Problem &p, const double *ul, const double *unl, hipS
 {
     const int nb = 512;
     double *part = scratch<double>(p, SCR_EPART, nb);
-    hipLaunchKernelGGL(k_energy_integral, dim3(nb), dim3(256), 0, s, p.ntet, p.d_tgeo, p.d_tet, ul, unl,
-                       tet_rule_arg(), part);
+    hipLaunchKernelGGL(k_energy_integral, dim3(nb), dim3(256), 0, s, p.ntet_i(), p.d_tgeo, p.d_tet, ul, unl,
+                       tet_rule_arg(), part); // Omega_i: the shell tets come first
     std::vector<double> h(nb);
     PB_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
     PB_HIP(hipStreamSynchronize(s));
@@ -686,6 +770,21 @@ double fem_energy_integral(Problem &p, const double *ul, const double *unl, hipS
 void energy(Problem &p, const double *phi_lin, const double *phi_nl, double out[4], hipStream_t s)
 {
     ensure_rhs(p, s);
+    if (p.two_field()) {
+        // the reaction potential needs lambda_m: recovered from the trace of u,
+        // with the Coulomb load for the linear part only (Sec. 2.3.1)
+        const int64_t n = p.n();
+        double *pl = scratch<double>(p, SCR_PL, n);
+        PB_HIP(hipMemcpyAsync(pl, phi_lin, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        lambda_m_recover(p, phi_lin, true, pl + p.nn, s);
+        phi_lin = pl;
+        if (phi_nl) {
+            double *pn = scratch<double>(p, SCR_PN, n);
+            PB_HIP(hipMemcpyAsync(pn, phi_nl, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            lambda_m_recover(p, phi_nl, false, pn + p.nn, s);
+            phi_nl = pn;
+        }
+    }
     double lc = 0.0, nc = 0.0;
     if (p.nq > 0) {
         SurfaceDev &S = p.surf[0];

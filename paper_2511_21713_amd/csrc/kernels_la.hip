@@ -179,10 +179,11 @@ static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y)
     return G;
 }
 
-static void gemv_launch(Problem &p, const double *xm, const double *xs, double *y, hipStream_t s)
+// both surfaces' rows in one launch; skip_m leaves out Gamma_m (two-field form)
+static void gemv_launch(Problem &p, const double *xm, const double *xs, double *y, hipStream_t s, bool skip_m)
 {
     const SurfaceDev &M = p.surf[0], &S = p.surf[1];
-    const int64_t nb0 = (M.nv + GSYM - 1) / GSYM, nb1 = (S.nv + GSYM - 1) / GSYM;
+    const int64_t nb0 = skip_m ? 0 : (M.nv + GSYM - 1) / GSYM, nb1 = (S.nv + GSYM - 1) / GSYM;
     const GemvSurf G0 = gemv_surf(p, 0, xm, y + p.nn), G1 = gemv_surf(p, 1, xs, y + p.nn + M.nv);
     if (p.timing) p.timer.begin(T_GEMV, s);
     if (p.precision == PBFB_MIXED)
@@ -190,7 +191,7 @@ static void gemv_launch(Problem &p, const double *xm, const double *xs, double *
     else
         hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, G0, G1, nb0);
     if (G0.sym || G1.sym) {
-        const int64_t f0 = (M.nv + GFIN_ROWS - 1) / GFIN_ROWS, f1 = (S.nv + GFIN_ROWS - 1) / GFIN_ROWS;
+        const int64_t f0 = skip_m ? 0 : (M.nv + GFIN_ROWS - 1) / GFIN_ROWS, f1 = (S.nv + GFIN_ROWS - 1) / GFIN_ROWS;
         hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0 + f1)), dim3(256), 0, s, G0, G1, f0);
     }
     if (p.timing) p.timer.end(s);
@@ -211,8 +212,11 @@ static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hi
         mf_apply(p, 1, xs, y + p.nn + p.surf[0].nv, nullptr, s);
         if (p.timing) p.timer.end(s);
     } else {
-        gemv_launch(p, xm, xs, y, s);
+        gemv_launch(p, xm, xs, y, s, p.two_field());
     }
+    // two-field form: lambda_m is not an unknown of the solve; its row is the identity
+    if (p.two_field())
+        PB_HIP(hipMemcpyAsync(y + p.nn, x + p.nn, sizeof(double) * M.nv, hipMemcpyDeviceToDevice, s));
     if (p.timing) p.timer.begin(T_SPMV, s);
     const unsigned g = nb_(p.nn, SLICE);
     if (!with_jac)
@@ -229,6 +233,92 @@ static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hi
 }
 
 void coupled_apply(Problem &p, const double *x, double *y, hipStream_t s) { apply_impl(p, x, y, true, s); }
+
+// ---------------------------------------------------------------------------
+// lambda_m from the trace of u (two-field form, Sec. 2.3.1):
+// V0 lam = (1/2 M_m + K0_m) u_m - [with_load] f_m, with the stored Gamma_m
+// rows [K' | V'] = [1/2 M_m + K0_m | -V0]: the right-hand side is the row
+// product with [u_m | 0], and V0 p = -(row product with [0 | p]).  V0 is
+// symmetric positive definite, so conjugate gradients with its diagonal as
+// preconditioner.
+// ---------------------------------------------------------------------------
+__global__ void k_pack_m(int64_t nm, int64_t ldm, const int32_t *__restrict__ gm, const double *__restrict__ u,
+                         const double *__restrict__ lam, double *__restrict__ xm)
+{
+    const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (k >= ldm) return;
+    double v = 0.0;
+    if (k < nm) v = u ? u[gm[k]] : 0.0;
+    else if (k < 2 * nm) v = lam ? lam[k - nm] : 0.0;
+    xm[k] = v;
+}
+
+template <typename MT>
+__global__ void k_vdiag_inv(int64_t nm, int64_t ld, const MT *__restrict__ B, double *__restrict__ dinv)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < nm) dinv[i] = -1.0 / double(B[i * ld + nm + i]);
+}
+
+static void gemv_m(Problem &p, const double *xm, double *y, hipStream_t s)
+{
+    const GemvSurf G = gemv_surf(p, 0, xm, y);
+    const int64_t nb0 = (G.n + GSYM - 1) / GSYM, f0 = (G.n + GFIN_ROWS - 1) / GFIN_ROWS;
+    if (p.precision == PBFB_MIXED)
+        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0)), dim3(256), 0, s, G, G, nb0);
+    else
+        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0)), dim3(256), 0, s, G, G, nb0);
+    if (G.sym) hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0)), dim3(256), 0, s, G, G, f0);
+}
+
+void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam, hipStream_t s)
+{
+    PB_CHECK(!p.bem_mf, PBFB_ESTATE, "the two-field form needs the dense Gamma_m operator");
+    ensure_rhs(p, s);
+    const SurfaceDev &M = p.surf[0];
+    const int64_t nm = M.nv, ldm = bem_ld(nm);
+    double *xm = scratch<double>(p, SCR_CGX, ldm);
+    double *wv = scratch<double>(p, SCR_CGV, 5 * nm);
+    double *r = wv, *z = wv + nm, *d = wv + 2 * nm, *q = wv + 3 * nm, *dinv = wv + 4 * nm;
+    const unsigned g = nb_(ldm, 256), gn = nb_(nm, 256);
+    hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, phi, (const double *)nullptr, xm);
+    gemv_m(p, xm, r, s);
+    if (with_load && p.nq > 0) vec_axpby(nm, -1.0, scratch<double>(p, SCR_FM, nm), 1.0, r, s);
+    if (p.precision == PBFB_MIXED)
+        hipLaunchKernelGGL(k_vdiag_inv<float>, dim3(gn), dim3(256), 0, s, nm, ldm, static_cast<const float *>(M.B), dinv);
+    else
+        hipLaunchKernelGGL(k_vdiag_inv<double>, dim3(gn), dim3(256), 0, s, nm, ldm, static_cast<const double *>(M.B),
+                           dinv);
+    PB_HIP(hipMemsetAsync(lam, 0, sizeof(double) * nm, s));
+    vec_mul(nm, dinv, r, z, s);
+    PB_HIP(hipMemcpyAsync(d, z, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
+    double h[2];
+    {
+        const double *a[2] = {r, r}, *b[2] = {z, r};
+        dots(p, 2, a, b, nm, h, s);
+    }
+    double rz = h[0];
+    const double r0 = std::sqrt(h[1]), tol = 1e-13 * r0;
+    if (r0 == 0.0) return;
+    const int maxit = int(std::min<int64_t>(20 * nm + 100, 20000));
+    bool done = false;
+    for (int it = 0; it < maxit && !done; ++it) {
+        hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, (const double *)nullptr, d, xm);
+        gemv_m(p, xm, q, s); // q = V' d = -V0 d
+        const double alpha = -rz / dot(p, d, q, nm, s);
+        vec_axpby(nm, alpha, d, 1.0, lam, s);
+        vec_axpby(nm, alpha, q, 1.0, r, s); // r -= alpha V0 d
+        vec_mul(nm, dinv, r, z, s);
+        const double *a[2] = {r, r}, *b[2] = {z, r};
+        dots(p, 2, a, b, nm, h, s);
+        PB_CHECK(std::isfinite(h[0]) && std::isfinite(h[1]), PBFB_ENAN, "non-finite lambda_m recovery");
+        if (std::sqrt(h[1]) <= tol) done = true;
+        const double beta = h[0] / rz;
+        rz = h[0];
+        vec_axpby(nm, 1.0, z, beta, d, s);
+    }
+    PB_CHECK(done, PBFB_ENOTCONV, "lambda_m recovery did not converge");
+}
 void coupled_apply_linear(Problem &p, const double *x, double *y, hipStream_t s) { apply_impl(p, x, y, false, s); }
 
 void dots(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out, hipStream_t s)

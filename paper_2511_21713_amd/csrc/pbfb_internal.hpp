@@ -209,6 +209,7 @@ enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
     SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1, SCR_SYMP0, SCR_SYMP1,
+    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC,
     SCR_N
 };
 
@@ -230,6 +231,12 @@ struct Problem {
     bool bem_mf = false; // boundary operators applied matrix-free (no dense storage)
     // host copies
     int64_t nn = 0, ntet = 0, nq = 0;
+    // two-field form (Sec. 2.3): the last ntet_m tets fill the solute (eps_m,
+    // no reaction term), the load is the point charges, lambda_m is recovered
+    // after the solve; 0: the shell-only form
+    int64_t ntet_m = 0;
+    int64_t ntet_i() const { return ntet - ntet_m; }
+    bool two_field() const { return ntet_m > 0; }
     std::vector<double> x;
     std::vector<int32_t> tet;
     std::vector<double> q; // 4 per charge: x, y, z, valence
@@ -319,6 +326,10 @@ void dots(Problem &p, int k, const double *const *a, const double *const *b, int
 
 // energy
 void energy(Problem &p, const double *phi_lin, const double *phi_nl, double out[4], hipStream_t s);
+// two-field form: lam = V0^-1 ((1/2 M_m + K0_m) u|Gamma_m - [with_load] f_m) by
+// conjugate gradients on the stored Gamma_m operator (V0 is symmetric positive
+// definite); phi and lam are device vectors
+void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam, hipStream_t s);
 
 // batched GMRES (gmres_batched.hip): one linear system per job, all advanced together
 struct GmresJob {

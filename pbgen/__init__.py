@@ -70,13 +70,9 @@ def _icosahedron():
     return v, f
 
 
-def icosphere(n: int):
-    """Class-I geodesic subdivision of frequency n, projected to the unit sphere.
-
-    Returns (verts (10n^2+2, 3), tris (20n^2, 3) int32, outward oriented).
-    Grid points are keyed exactly by their integer barycentric weights on the
-    icosahedron corners, so points on shared edges are merged exactly.
-    """
+def _icosphere_keyed(n: int):
+    """icosphere(n) plus each vertex's key: its integer barycentric weights on
+    the icosahedron corners, as a sorted tuple of (corner, weight)."""
     if n < 1:
         raise ValueError("frequency must be >= 1")
     V, F = _icosahedron()
@@ -111,7 +107,21 @@ def icosphere(n: int):
     flip = np.einsum("ij,ij->i", nrm, a + b + c) < 0
     tris[flip] = tris[flip][:, [0, 2, 1]]
     assert verts.shape[0] == 10 * n * n + 2 and tris.shape[0] == 20 * n * n
-    return verts, tris.astype(np.int32)
+    keys = [None] * len(pts)
+    for k, i in key_to_id.items():
+        keys[i] = k
+    return verts, tris.astype(np.int32), keys
+
+
+def icosphere(n: int):
+    """Class-I geodesic subdivision of frequency n, projected to the unit sphere.
+
+    Returns (verts (10n^2+2, 3), tris (20n^2, 3) int32, outward oriented).
+    Grid points are keyed exactly by their integer barycentric weights on the
+    icosahedron corners, so points on shared edges are merged exactly.
+    """
+    v, t, _ = _icosphere_keyed(n)
+    return v, t
 
 
 def _real_sph_harm(lmax, xyz):
@@ -176,34 +186,103 @@ def shell_mesh(unit, tris, r_in, thickness, layers):
     return nodes, tets.astype(np.int32), tri_m.astype(np.int32), tri_s.astype(np.int32)
 
 
-def solute_mesh(unit, tris, r_m, layers, first_id):
-    """Tets filling the star-shaped solute inside r_m(x) x: `layers` scaled
-    copies of Gamma_m at radial fractions 1 - k/(layers+1), prisms between
-    neighbouring copies split as in the shell, and a cone from the innermost
-    copy to the centre.  New nodes are numbered from `first_id`; Gamma_m keeps
-    ids 0..nv-1, so the shell part of the mesh is unchanged."""
-    nv = unit.shape[0]
-    L = int(layers)
-    nodes = np.concatenate([(r_m * (1.0 - k / (L + 1.0)))[:, None] * unit for k in range(1, L + 1)]
-                           + [np.zeros((1, 3))])
+def solute_mesh(n, radial, layers, first_id):
+    """Tets filling the star-shaped solute inside Gamma_m = radial(unit) unit
+    (Gamma_m: the frequency-n icosphere, node ids 0..10n^2+1).
+
+    From Gamma_m inwards: `layers` scaled copies of Gamma_m joined by prisms
+    split into 3 tets (as in the shell); then, while the frequency is even,
+    a transition to the frequency-f/2 sphere, whose points are every other
+    lattice point of the frequency-f one: each coarse triangle's slab (the 4
+    fine triangles above it, the coarse one below, each side split at the
+    fine edge midpoint) is coned to a point inside it, 14 tets; finally a cone
+    from the coarsest sphere to the centre.  Every node then has a bounded
+    number of neighbours (a cone from the fine sphere would join the centre
+    to all of its vertices).  Copies sit at equal radial steps.  New nodes
+    are numbered from first_id, so the shell part of the mesh is unchanged."""
+    freqs = [n]
+    while freqs[-1] % 2 == 0:
+        freqs.append(freqs[-1] // 2)
+    L, T = int(layers), len(freqs) - 1
+    steps = L + T + 1
+    nodes, tets = [], []
+    next_id = [first_id]
+
+    def add(x):
+        i0 = next_id[0]
+        nodes.append(x)
+        next_id[0] += x.shape[0]
+        return i0
+
+    unit, tris, keys = _icosphere_keyed(n)
+    r = radial(unit)
+    gm_x = r[:, None] * unit  # Gamma_m, node ids 0..nv-1
+    cur = np.arange(unit.shape[0])  # ids of the current (outermost remaining) copy
+    k = 0
     t = np.sort(tris.astype(np.int64), axis=1)
-    a, b, c = t[:, 0], t[:, 1], t[:, 2]
+    for _ in range(L):
+        k += 1
+        base = add((r * (1.0 - k / steps))[:, None] * unit)
+        inner = base + np.arange(unit.shape[0])
+        A, B, C = cur[t[:, 0]], cur[t[:, 1]], cur[t[:, 2]]
+        A2, B2, C2 = inner[t[:, 0]], inner[t[:, 1]], inner[t[:, 2]]
+        tets += [np.stack([A, B, C, C2], 1), np.stack([A, B, B2, C2], 1), np.stack([A, A2, B2, C2], 1)]
+        cur = inner
+    f = n
+    for _ in range(T):
+        k += 1
+        fine_id = {kk: i for i, kk in enumerate(keys)}
+        cu, ct, ck = _icosphere_keyed(f // 2)
+        cr = radial(cu)
+        base = add((cr * (1.0 - k / steps))[:, None] * cu)
+        cids = base + np.arange(cu.shape[0])
 
-    def layer(k):  # global id offset of copy k (0 = Gamma_m)
-        return 0 if k == 0 else first_id + (k - 1) * nv
+        def fine_of(*ks):  # fine vertex id of a sum of coarse keys (weights double on the finer lattice)
+            w = {}
+            for kk in ks:
+                for c, v in kk:
+                    w[c] = w.get(c, 0) + v
+            return int(cur[fine_id[tuple(sorted(w.items()))]])
 
-    tets = []
-    for k in range(L):
-        lo, hi = layer(k), layer(k + 1)
-        A, B, C = a + lo, b + lo, c + lo
-        A2, B2, C2 = a + hi, b + hi, c + hi
-        tets.append(np.stack([A, B, C, C2], 1))
-        tets.append(np.stack([A, B, B2, C2], 1))
-        tets.append(np.stack([A, A2, B2, C2], 1))
-    centre = first_id + L * nv
-    inner = layer(L)
-    tets.append(np.stack([a + inner, b + inner, c + inner, np.full_like(a, centre)], 1))
-    return nodes, np.concatenate(tets)
+        faces = []
+        for (ia, ib, ic) in ct:
+            X = [int(cids[ia]), int(cids[ib]), int(cids[ic])]
+            kx = [ck[ia], ck[ib], ck[ic]]
+            corner = [fine_of(kx[0], kx[0]), fine_of(kx[1], kx[1]), fine_of(kx[2], kx[2])]
+            mid = {(0, 1): fine_of(kx[0], kx[1]), (1, 2): fine_of(kx[1], kx[2]), (0, 2): fine_of(kx[0], kx[2])}
+            m01, m12, m02 = mid[(0, 1)], mid[(1, 2)], mid[(0, 2)]
+            fc = [(corner[0], m01, m02), (corner[1], m12, m01), (corner[2], m02, m12), (m01, m12, m02),
+                  (X[0], X[1], X[2])]
+            for (i, j) in ((0, 1), (1, 2), (0, 2)):
+                m = mid[(i, j)]
+                fc += [(X[i], corner[i], m), (X[i], m, X[j]), (X[j], m, corner[j])]
+            faces.append(fc)
+        faces = np.array(faces, dtype=np.int64)  # (n_coarse_tri, 14, 3)
+        # Steiner point: centroid of the slab's 9 vertices
+        newx = np.concatenate(nodes)
+
+        def pos(ids):
+            return np.where((ids < first_id)[:, None], gm_x[np.minimum(ids, gm_x.shape[0] - 1)],
+                            newx[np.maximum(ids - first_id, 0)])
+
+        cen = np.stack([pos(np.unique(fc.ravel())).mean(0) for fc in faces])
+        sb = add(cen)
+        sid = sb + np.arange(faces.shape[0])
+        tets.append(np.concatenate([np.concatenate([np.full((14, 1), sid[q]), faces[q]], 1)
+                                    for q in range(faces.shape[0])]))
+        cur, keys, f = cids, ck, f // 2
+    # cone from the coarsest copy to the centre
+    centre = add(np.zeros((1, 3)))
+    ct = np.sort(_icosphere_keyed(f)[1].astype(np.int64), axis=1)
+    tets.append(np.stack([cur[ct[:, 0]], cur[ct[:, 1]], cur[ct[:, 2]], np.full(ct.shape[0], centre)], 1))
+    return np.concatenate(nodes), np.concatenate(tets)
+
+
+def _radial_eval(u, unit, r):
+    """r at the unit vectors u, each of which is one of `unit` (exact match
+    of the lattice point's coordinates)."""
+    idx = {tuple(x): i for i, x in enumerate(unit)}
+    return np.array([r[idx[tuple(x)]] for x in u])
 
 
 def _orient(nodes, tets):
@@ -380,7 +459,7 @@ def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
     nodes, tets, tri_m, tri_s = shell_mesh(unit, tris, r, t, L)
     n_tets_m = 0
     if solute_layers:
-        inodes, itets = solute_mesh(unit, tris, r, solute_layers, nodes.shape[0])
+        inodes, itets = solute_mesh(n, lambda u: _radial_eval(u, unit, r), solute_layers, nodes.shape[0])
         nodes = np.concatenate([nodes, inodes])
         itets = _orient(nodes, itets)
         n_tets_m = int(itets.shape[0])
