@@ -271,53 +271,145 @@ static void gemv_m(Problem &p, const double *xm, double *y, hipStream_t s)
     if (G.sym) hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0)), dim3(256), 0, s, G, G, f0);
 }
 
+// CG scalars kept on the device (sc[0] = r.z, sc[1] = alpha, sc[2] = beta,
+// sc[3] = r.r): no host round trip per step
+__global__ void k_cg_alpha(const double *__restrict__ pq, double *__restrict__ sc)
+{
+    if (threadIdx.x == 0) sc[1] = pq[0] != 0.0 ? -sc[0] / pq[0] : 0.0; // q = -V0 d
+}
+__global__ void k_cg_beta(const double *__restrict__ red, double *__restrict__ sc)
+{
+    if (threadIdx.x == 0) {
+        sc[2] = sc[0] != 0.0 ? red[0] / sc[0] : 0.0;
+        sc[0] = red[0];
+        sc[3] = red[1];
+    }
+}
+__global__ void k_cg_dir(int64_t n, const double *__restrict__ sc, const double *__restrict__ z, double *__restrict__ d)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < n) d[i] = z[i] + sc[2] * d[i];
+}
+
+// z = -1/2 (S + S^T) r with S the 1-ring approximate inverse of V' = -V0 (the
+// GMRES preconditioner's block; the 1-ring pattern is symmetric, tslot[e] is
+// the slot of the transposed entry): a symmetric approximation of V0^-1
+__global__ void k_cg_spai(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                          const double *__restrict__ val, const int32_t *__restrict__ tslot,
+                          const double *__restrict__ r, double *__restrict__ z)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) acc += (val[e] + val[tslot[e]]) * r[col[e]];
+    z[i] = -0.5 * acc;
+}
+__global__ void k_cg_update_spai(int64_t n, const double *__restrict__ sc, const double *__restrict__ d,
+                                 const double *__restrict__ q, double *__restrict__ lam, double *__restrict__ r)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    const double a = sc[1];
+    lam[i] += a * d[i];
+    r[i] += a * q[i];
+}
+
 void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam, hipStream_t s)
 {
     PB_CHECK(!p.bem_mf, PBFB_ESTATE, "the two-field form needs the dense Gamma_m operator");
     ensure_rhs(p, s);
     const SurfaceDev &M = p.surf[0];
+    const SurfaceTopo &TM = p.topo[0];
     const int64_t nm = M.nv, ldm = bem_ld(nm);
     double *xm = scratch<double>(p, SCR_CGX, ldm);
-    double *wv = scratch<double>(p, SCR_CGV, 5 * nm);
-    double *r = wv, *z = wv + nm, *d = wv + 2 * nm, *q = wv + 3 * nm, *dinv = wv + 4 * nm;
+    double *wv = scratch<double>(p, SCR_CGV, 6 * nm + 8);
+    double *b = wv, *r = wv + nm, *z = wv + 2 * nm, *d = wv + 3 * nm, *q = wv + 4 * nm, *dinv = wv + 5 * nm,
+           *sc = wv + 6 * nm;
+    double *part = scratch<double>(p, SCR_DOT, RED_BLOCKS * 8 + 8), *red = part + RED_BLOCKS * 8;
     const unsigned g = nb_(ldm, 256), gn = nb_(nm, 256);
+    auto dev_dots = [&](int k, const double *a0, const double *b0, const double *a1, const double *b1) {
+        PtrTab T{};
+        T.a[0] = a0;
+        T.b[0] = b0;
+        T.a[1] = a1;
+        T.b[1] = b1;
+        hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, nm, k, T, part);
+        hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, red);
+    };
     hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, phi, (const double *)nullptr, xm);
-    gemv_m(p, xm, r, s);
-    if (with_load && p.nq > 0) vec_axpby(nm, -1.0, scratch<double>(p, SCR_FM, nm), 1.0, r, s);
+    gemv_m(p, xm, b, s);
+    if (with_load && p.nq > 0) vec_axpby(nm, -1.0, scratch<double>(p, SCR_FM, nm), 1.0, b, s);
     if (p.precision == PBFB_MIXED)
         hipLaunchKernelGGL(k_vdiag_inv<float>, dim3(gn), dim3(256), 0, s, nm, ldm, static_cast<const float *>(M.B), dinv);
     else
         hipLaunchKernelGGL(k_vdiag_inv<double>, dim3(gn), dim3(256), 0, s, nm, ldm, static_cast<const double *>(M.B),
                            dinv);
+    // transposed slots of the approximate inverse's 1-ring pattern (host, from the topology)
+    int32_t *tslot = nullptr;
+    if (M.spai && !TM.ring_ptr.empty()) {
+        std::vector<int32_t> ts(TM.ring.size(), -1);
+        bool ok = true;
+        for (int64_t i = 0; i < nm && ok; ++i)
+            for (int32_t e = TM.ring_ptr[i]; e < TM.ring_ptr[i + 1] && ok; ++e) {
+                const int32_t j = TM.ring[e];
+                for (int32_t f = TM.ring_ptr[j]; f < TM.ring_ptr[j + 1]; ++f)
+                    if (TM.ring[f] == i) ts[e] = f;
+                ok = ts[e] >= 0;
+            }
+        if (ok) {
+            tslot = scratch<int32_t>(p, SCR_TSLOT, ts.size());
+            PB_HIP(hipMemcpyAsync(tslot, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice, s));
+        }
+    }
+    auto precond = [&](const double *rr, double *zz) {
+        if (tslot)
+            hipLaunchKernelGGL(k_cg_spai, dim3(gn), dim3(256), 0, s, nm, M.ring_ptr, M.ring, M.spai, tslot, rr, zz);
+        else
+            vec_mul(nm, dinv, rr, zz, s);
+    };
+    double h[4];
+    dev_dots(1, b, b, nullptr, nullptr);
+    PB_HIP(hipMemcpyAsync(h, red, sizeof(double), hipMemcpyDeviceToHost, s));
+    PB_HIP(hipStreamSynchronize(s));
+    const double b0 = std::sqrt(h[0]), tol = 1e-13 * b0;
     PB_HIP(hipMemsetAsync(lam, 0, sizeof(double) * nm, s));
-    vec_mul(nm, dinv, r, z, s);
-    PB_HIP(hipMemcpyAsync(d, z, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
-    double h[2];
-    {
-        const double *a[2] = {r, r}, *b[2] = {z, r};
-        dots(p, 2, a, b, nm, h, s);
-    }
-    double rz = h[0];
-    const double r0 = std::sqrt(h[1]), tol = 1e-13 * r0;
-    if (r0 == 0.0) return;
+    if (b0 == 0.0) return;
+    // one CG run from lam = 0; false if the preconditioner lost definiteness or
+    // the step budget ran out.  Convergence is read back every CHECK steps.
+    auto run = [&](int maxit) -> bool {
+        PB_HIP(hipMemsetAsync(lam, 0, sizeof(double) * nm, s));
+        PB_HIP(hipMemcpyAsync(r, b, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
+        precond(r, z);
+        PB_HIP(hipMemcpyAsync(d, z, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
+        dev_dots(2, r, z, r, r);
+        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, red, sc); // sc[0] = r.z, sc[3] = r.r
+        PB_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+        PB_HIP(hipStreamSynchronize(s));
+        if (!(h[0] > 0.0)) return false;
+        constexpr int CHECK = 8;
+        for (int it = 0; it < maxit;) {
+            for (int k = 0; k < CHECK; ++k, ++it) {
+                hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, (const double *)nullptr, d, xm);
+                gemv_m(p, xm, q, s); // q = V' d = -V0 d
+                dev_dots(1, d, q, nullptr, nullptr);
+                hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, red, sc);
+                hipLaunchKernelGGL(k_cg_update_spai, dim3(gn), dim3(256), 0, s, nm, sc, d, q, lam, r);
+                precond(r, z);
+                dev_dots(2, r, z, r, r);
+                hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, red, sc);
+                hipLaunchKernelGGL(k_cg_dir, dim3(gn), dim3(256), 0, s, nm, sc, z, d);
+            }
+            PB_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+            PB_HIP(hipStreamSynchronize(s));
+            if (!std::isfinite(h[0]) || !std::isfinite(h[3]) || !(h[0] > 0.0)) return std::sqrt(h[3]) <= tol;
+            if (std::sqrt(h[3]) <= tol) return true;
+        }
+        return false;
+    };
     const int maxit = int(std::min<int64_t>(20 * nm + 100, 20000));
-    bool done = false;
-    for (int it = 0; it < maxit && !done; ++it) {
-        hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, (const double *)nullptr, d, xm);
-        gemv_m(p, xm, q, s); // q = V' d = -V0 d
-        const double alpha = -rz / dot(p, d, q, nm, s);
-        vec_axpby(nm, alpha, d, 1.0, lam, s);
-        vec_axpby(nm, alpha, q, 1.0, r, s); // r -= alpha V0 d
-        vec_mul(nm, dinv, r, z, s);
-        const double *a[2] = {r, r}, *b[2] = {z, r};
-        dots(p, 2, a, b, nm, h, s);
-        PB_CHECK(std::isfinite(h[0]) && std::isfinite(h[1]), PBFB_ENAN, "non-finite lambda_m recovery");
-        if (std::sqrt(h[1]) <= tol) done = true;
-        const double beta = h[0] / rz;
-        rz = h[0];
-        vec_axpby(nm, 1.0, z, beta, d, s);
-    }
-    PB_CHECK(done, PBFB_ENOTCONV, "lambda_m recovery did not converge");
+    if (tslot && run(std::min(maxit, 2000))) return;
+    tslot = nullptr; // the diagonal of V0 instead
+    PB_CHECK(run(maxit), PBFB_ENOTCONV, "lambda_m recovery did not converge");
 }
 void coupled_apply_linear(Problem &p, const double *x, double *y, hipStream_t s) { apply_impl(p, x, y, false, s); }
 
