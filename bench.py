@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # --pmc runs (FETCH_SIZE then WRITE_SIZE, each scaled by the factor the same
 # counter reads for a copy of known size), valid for the kernel source whose
 # hash is recorded with it; see profiles/gemv_f64_rna20k_hbm_counters.md.
-GEMV_TRAFFIC = {"config": 1, "src_sha256_16": "a80a65ce3e167ef4", "bytes": 2.53424e9 + 7.9254e7 + 5.3112e7}
+GEMV_TRAFFIC = {"config": 1, "src_sha256_16": "d9c2eb2ba90cdfa6", "bytes": 2.53424e9 + 7.9254e7 + 5.3112e7}
 # algorithmic flops per quadrature-point pair of the regular tiles, counting
 # add/mul/rsqrt/exp as 1 and FMA as 2: Laplace V and K 37, Yukawa 46
 FLOPS_QP = {"laplace": 37, "yukawa": 46}

@@ -94,10 +94,11 @@ __device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restr
 // contribute nothing.  Reads n + r0 + 16 entries of each row instead of 2 n.
 constexpr int GSYM = 4 * GEMV_RW;
 // chunks per LDS exchange: 32 KB of column partials per workgroup.  The
-// partials are kept in the storage precision: FP32 storage already rounds
-// every entry of V' to FP32, and its column partials are rounded once more.
-template <typename MT> constexpr int gsym_g() { return 8; }
-template <typename MT> using sym_part_t = std::conditional_t<sizeof(MT) == 8, double, float>;
+// partials are FP64 for both storage precisions: with FP32 partials the
+// apply is linear only to FP32 rounding of the partial sums, which left
+// strongly charged instances short of the Newton tolerance in mixed mode.
+template <typename MT> constexpr int gsym_g() { return sizeof(MT) == 8 ? 8 : 4; }
+template <typename MT> using sym_part_t = double;
 
 template <typename MT>
 __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,

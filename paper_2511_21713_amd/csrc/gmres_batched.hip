@@ -45,7 +45,7 @@ struct GDesc {
     int two_field; // lambda_m is not an unknown (two-field form): identity row, no Gamma_m GEMV
     // symmetric use of the stored single layer, per surface: column partials, Delta rows
     int symm[2];
-    void *symP[2]; // in the storage precision
+    void *symP[2]; // FP64 column partials
     const int32_t *dl_ptr[2], *dl_col[2];
     const double *dl_val[2];
     const int32_t *gm, *gs;
@@ -256,12 +256,8 @@ __global__ void __launch_bounds__(256) k_bgemv_fin(const WItem *__restrict__ wl,
     const int64_t n = it.a == 0 ? d.nm : d.ns;
     const double *x = it.a == 0 ? d.xm : d.xs;
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
-    if (d.f32)
-        gemv_sym_finish(n, static_cast<const float *>(d.symP[it.a]), d.dl_ptr[it.a], d.dl_col[it.a], d.dl_val[it.a], x,
-                        y, it.b, threadIdx.x);
-    else
-        gemv_sym_finish(n, static_cast<const double *>(d.symP[it.a]), d.dl_ptr[it.a], d.dl_col[it.a],
-                        d.dl_val[it.a], x, y, it.b, threadIdx.x);
+    gemv_sym_finish(n, static_cast<const double *>(d.symP[it.a]), d.dl_ptr[it.a], d.dl_col[it.a], d.dl_val[it.a], x, y,
+                    it.b, threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_bspmv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,

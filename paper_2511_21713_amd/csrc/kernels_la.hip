@@ -42,7 +42,7 @@ struct GemvSurf {
     const void *B;
     const double *x;
     double *y;
-    void *P; // column partials of the symmetric use, in the storage precision
+    void *P; // FP64 column partials of the symmetric use
     int64_t n, ld;
     int sym, f32;
     const int32_t *dptr, *dcol;
@@ -75,8 +75,7 @@ __global__ void __launch_bounds__(256) k_gemv_fin(GemvSurf S0, GemvSurf S1, int6
     const GemvSurf &S = s1 ? S1 : S0;
     if (!S.sym) return;
     const int64_t i0 = (s1 ? blockIdx.x - nb0 : blockIdx.x) * int64_t(GFIN_ROWS);
-    if (S.f32) gemv_sym_finish(S.n, static_cast<const float *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
-    else gemv_sym_finish(S.n, static_cast<const double *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
+    gemv_sym_finish(S.n, static_cast<const double *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
