@@ -335,7 +335,7 @@ def main():
                     help="run one device copy of this size first (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU row-block sharding is a design, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
