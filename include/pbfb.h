@@ -47,7 +47,7 @@ typedef struct pbfb_problem pbfb_problem;
 typedef enum {
     PBFB_OK = 0,
     PBFB_EINVAL = -1,   /* bad argument (null pointer, eps <= 0, kappa < 0, size) */
-    PBFB_EMESH = -2,    /* inverted/degenerate tet, open or non-manifold surface */
+    PBFB_EMESH = -2,    /* degenerate tet, open, non-manifold or inward-oriented surface */
     PBFB_ECHARGE = -3,  /* charge outside Gamma_m or closer than 1 A to it */
     PBFB_ENOMEM = -4,   /* device allocation failed */
     PBFB_EDEVICE = -5,  /* HIP runtime error */
@@ -89,8 +89,11 @@ void pbfb_problem_destroy(pbfb_problem *p);
  * tri_m[3*n_tri_m] / tri_s[3*n_tri_s]: Gamma_m / Gamma_s triangles over FEM
  * node ids, oriented so that the right-hand normal points away from the
  * solute.  The surface unknowns are numbered by ascending FEM node id.
- * Errors: EINVAL (sizes / ids out of range), EMESH (degenerate tet,
- * zero-area triangle, surface not closed). */
+ * Errors: EINVAL (sizes / ids out of range), EMESH (surface not closed or
+ * not consistently oriented here; at setup, where the geometry is computed on
+ * the device: degenerate tet, zero-area triangle, or a surface whose
+ * right-hand normals enclose a negative volume, i.e. oriented towards the
+ * solute; the double layer's sign depends on the orientation). */
 pbfb_status pbfb_set_mesh(pbfb_problem *p, int64_t n_nodes, const double *nodes, int64_t n_tets,
                           const int32_t *tets, int64_t n_tri_m, const int32_t *tri_m, int64_t n_tri_s,
                           const int32_t *tri_s);

@@ -115,6 +115,32 @@ __global__ void k_tri_geom(int64_t nt, const double *__restrict__ x, const int32
             qp[18 * t + 3 * q + d] = R.b[q][0] * P[0][d] + R.b[q][1] * P[1][d] + R.b[q][2] * P[2][d];
 }
 
+// Signed volume enclosed by a closed surface, (1/3) sum_t |t| n_t . c_t (the
+// divergence theorem for the field x / 3; c_t the centroid): positive when
+// every right-hand normal points away from the enclosed region.  One
+// workgroup, strided partial sums added in a fixed tree.
+__global__ void __launch_bounds__(256) k_enclosed_volume(int64_t nt, const double *__restrict__ x,
+                                                         const int32_t *__restrict__ g, const int32_t *__restrict__ tri,
+                                                         const double *__restrict__ nrm, const double *__restrict__ area,
+                                                         double *__restrict__ vol)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < nt; t += 256) {
+        double c[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) c[d] += x[3 * g[tri[3 * t + a]] + d];
+        s += area[t] * (nrm[3 * t] * c[0] + nrm[3 * t + 1] * c[1] + nrm[3 * t + 2] * c[2]) / 9.0;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *vol = red[0];
+}
+
 // ---------------------------------------------------------------------------
 // stiffness and coupling values (row gather)
 // ---------------------------------------------------------------------------
@@ -629,16 +655,26 @@ void ensure_geometry(Problem &p, hipStream_t s)
     hipLaunchKernelGGL(k_tet_geom, dim3(nblocks(p.ntet, 256)), dim3(256), 0, s, p.ntet, p.d_x, p.d_tet, p.d_tgeo,
                        p.d_bad);
     TriRuleArg TR = tri_rule_arg();
+    double *d_vol = scratch<double>(p, SCR_VOL, 2);
     for (int w = 0; w < 2; ++w) {
         SurfaceDev &S = p.surf[w];
         hipLaunchKernelGGL(k_tri_geom, dim3(nblocks(S.nt, 256)), dim3(256), 0, s, S.nt, p.d_x, S.g, S.tri, TR, S.qp,
                            S.nrm, S.area, p.d_bad);
+        hipLaunchKernelGGL(k_enclosed_volume, dim3(1), dim3(256), 0, s, S.nt, p.d_x, S.g, S.tri, S.nrm, S.area,
+                           d_vol + w);
     }
     int bad = 0;
+    double vol[2] = {0.0, 0.0};
     PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    PB_HIP(hipMemcpyAsync(vol, d_vol, sizeof(vol), hipMemcpyDeviceToHost, s));
     PB_HIP(hipStreamSynchronize(s));
     PB_CHECK(!(bad & 1), PBFB_EMESH, "degenerate (zero-volume) tetrahedron");
     PB_CHECK(!(bad & 2), PBFB_EMESH, "degenerate (zero-area) surface triangle");
+    // the formulation's normals point away from the solute on both interfaces
+    // (the sign of the double layer depends on it): the right-hand normals must
+    // enclose a positive volume
+    PB_CHECK(vol[0] > 0.0, PBFB_EMESH, "Gamma_m is oriented inward (its right-hand normals enclose a negative volume)");
+    PB_CHECK(vol[1] > 0.0, PBFB_EMESH, "Gamma_s is oriented inward (its right-hand normals enclose a negative volume)");
     p.geom_ready = true;
 }
 

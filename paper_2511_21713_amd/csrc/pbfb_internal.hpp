@@ -209,7 +209,7 @@ enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
     SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1, SCR_SYMP0, SCR_SYMP1,
-    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC, SCR_TSLOT,
+    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC, SCR_TSLOT, SCR_VOL,
     SCR_N
 };
 

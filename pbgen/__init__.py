@@ -27,6 +27,7 @@ Gamma_m nodes are 0..Nv-1 and the Gamma_s nodes are L*Nv..(L+1)*Nv-1.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 
 import numpy as np
@@ -73,6 +74,12 @@ def _icosahedron():
 def _icosphere_keyed(n: int):
     """icosphere(n) plus each vertex's key: its integer barycentric weights on
     the icosahedron corners, as a sorted tuple of (corner, weight)."""
+    v, t, k = _icosphere_keyed_cached(int(n))
+    return v.copy(), t.copy(), list(k)
+
+
+@functools.lru_cache(maxsize=None)
+def _icosphere_keyed_cached(n: int):
     if n < 1:
         raise ValueError("frequency must be >= 1")
     V, F = _icosahedron()
@@ -124,8 +131,22 @@ def icosphere(n: int):
     return v, t
 
 
+_SPH_CACHE = {}
+
+
 def _real_sph_harm(lmax, xyz):
-    """Real spherical harmonics Y_lm for l = 1..lmax (m = -l..l) at unit vectors."""
+    """Real spherical harmonics Y_lm for l = 1..lmax (m = -l..l) at unit vectors
+    (tables of the point sets seen before are reused)."""
+    import hashlib
+    key = (int(lmax), xyz.shape, hashlib.sha1(np.ascontiguousarray(xyz).tobytes()).hexdigest())
+    if key not in _SPH_CACHE:
+        if len(_SPH_CACHE) > 64:
+            _SPH_CACHE.clear()
+        _SPH_CACHE[key] = _real_sph_harm_eval(lmax, xyz)
+    return _SPH_CACHE[key]
+
+
+def _real_sph_harm_eval(lmax, xyz):
     from scipy import special
     theta = np.arccos(np.clip(xyz[:, 2], -1.0, 1.0))
     phi = np.arctan2(xyz[:, 1], xyz[:, 0])
@@ -298,13 +319,105 @@ def _orient(nodes, tets):
 # ----------------------------------------------------------------------------
 def point_mesh_distance(p, verts, tris):
     """Exact Euclidean distance from each point p (k,3) to a triangle mesh."""
-    A = verts[tris[:, 0]]
-    B = verts[tris[:, 1]]
-    C = verts[tris[:, 2]]
-    out = np.empty(p.shape[0])
-    for i, x in enumerate(np.atleast_2d(p)):
-        out[i] = np.sqrt(np.min(_pt_tri_dist2(x, A, B, C)))
-    return out
+    return MeshQuery(verts, tris).distance(p)
+
+
+class MeshQuery:
+    """Exact distance and star-shaped inside queries against one triangle mesh.
+
+    Both restrict the exact per-triangle tests to candidate sets that provably
+    hold every triangle that can matter:
+    * distance: with c_t the centroid and rho_t the largest centroid-to-vertex
+      distance of triangle t, dist(x, t) >= |x - c_t| - rho_t, and dist(x,
+      mesh) <= |x - v| for the nearest vertex v, so only triangles with
+      |x - c_t| <= |x - v| + max rho need the exact test;
+    * inside (ray from the origin): the directions of a triangle's points form
+      the spherical triangle of its vertex directions, inside the cap around
+      its normalised centroid that reaches the farthest vertex direction; the
+      ray's direction must lie in that cap (with a margin for the hit test's
+      tolerance)."""
+
+    def __init__(self, verts, tris):
+        from scipy.spatial import cKDTree
+        self.A = verts[tris[:, 0]]
+        self.B = verts[tris[:, 1]]
+        self.C = verts[tris[:, 2]]
+        self.E1 = self.B - self.A
+        self.E2 = self.C - self.A
+        self.small = tris.shape[0] <= 512
+        if self.small:
+            return
+        cen = (self.A + self.B + self.C) / 3.0
+        rho = np.max(np.stack([np.linalg.norm(V - cen, axis=1) for V in (self.A, self.B, self.C)]), axis=0)
+        self.vtree = cKDTree(verts[np.unique(tris)])
+        self.ctree = cKDTree(cen)
+        self.slack = float(rho.max()) * (1.0 + 1e-9) + 1e-9
+        cd = cen / np.linalg.norm(cen, axis=1)[:, None]
+        chord = np.max(np.stack([np.linalg.norm(V / np.linalg.norm(V, axis=1)[:, None] - cd, axis=1)
+                                 for V in (self.A, self.B, self.C)]), axis=0)
+        self.dtree = cKDTree(cd)
+        self.reach = float(chord.max()) * 1.01 + 1e-6
+
+    def _pairs(self, tree, q, radii):
+        """Flattened (point, candidate triangle) pairs of the ball queries."""
+        lists = tree.query_ball_point(q, radii)
+        cnt = np.fromiter((len(c) for c in lists), dtype=np.int64, count=len(lists))
+        tri = np.fromiter((t for c in lists for t in c), dtype=np.int64, count=int(cnt.sum()))
+        pt = np.repeat(np.arange(len(lists)), cnt)
+        return pt, tri, cnt
+
+    def distance(self, p):
+        p = np.atleast_2d(np.asarray(p, dtype=np.float64))
+        out = np.empty(p.shape[0])
+        if p.shape[0] == 0:
+            return out
+        if self.small:
+            for i, x in enumerate(p):
+                out[i] = np.sqrt(np.min(_pt_tri_dist2(x, self.A, self.B, self.C)))
+            return out
+        dv, _ = self.vtree.query(p)
+        pt, tri, cnt = self._pairs(self.ctree, p, dv * (1.0 + 1e-9) + self.slack)
+        d2 = _pt_tri_dist2(p[pt], self.A[tri], self.B[tri], self.C[tri])
+        start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        return np.sqrt(np.minimum.reduceat(d2, start))
+
+    def inside(self, p):
+        p = np.atleast_2d(np.asarray(p, dtype=np.float64))
+        res = np.zeros(p.shape[0], dtype=bool)
+        if p.shape[0] == 0:
+            return res
+        rn = np.linalg.norm(p, axis=1)
+        zero = rn == 0
+        res[zero] = True
+        idx = np.nonzero(~zero)[0]
+        if idx.size == 0:
+            return res
+        d = p[idx] / rn[idx][:, None]
+        if self.small:
+            pt = np.repeat(np.arange(idx.size), self.A.shape[0])
+            tri = np.tile(np.arange(self.A.shape[0]), idx.size)
+            cnt = np.full(idx.size, self.A.shape[0])
+        else:
+            pt, tri, cnt = self._pairs(self.dtree, d, self.reach)
+        dd = d[pt]
+        a, e1, e2 = self.A[tri], self.E1[tri], self.E2[tri]
+        h = np.cross(dd, e2)
+        det = np.einsum("ij,ij->i", e1, h)
+        ok = np.abs(det) > 1e-14
+        inv = np.where(ok, 1.0 / np.where(ok, det, 1.0), 0.0)
+        s = -a
+        u = np.einsum("ij,ij->i", s, h) * inv
+        qv = np.cross(s, e1)
+        v = np.einsum("ij,ij->i", qv, dd) * inv
+        t = np.einsum("ij,ij->i", e2, qv) * inv
+        hit = ok & (u >= -1e-12) & (v >= -1e-12) & (u + v <= 1 + 1e-12) & (t > 0)
+        tmin = np.where(hit, t, np.inf)
+        start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        has = cnt > 0
+        first = np.full(idx.size, np.inf)
+        first[has] = np.minimum.reduceat(tmin, start[has])
+        res[idx] = np.isfinite(first) & (rn[idx] < first)
+        return res
 
 
 def _pt_tri_dist2(x, A, B, C):
@@ -355,28 +468,7 @@ def _pt_tri_dist2(x, A, B, C):
 
 def inside_star(p, verts, tris):
     """Inside test for a surface star-shaped about the origin (ray from origin)."""
-    A = verts[tris[:, 0]]
-    E1 = verts[tris[:, 1]] - A
-    E2 = verts[tris[:, 2]] - A
-    res = np.zeros(p.shape[0], dtype=bool)
-    for i, x in enumerate(p):
-        rn = np.linalg.norm(x)
-        if rn == 0:
-            res[i] = True
-            continue
-        d = x / rn
-        h = np.cross(d, E2)
-        det = np.einsum("ij,ij->i", E1, h)
-        ok = np.abs(det) > 1e-14
-        inv = np.where(ok, 1.0 / np.where(ok, det, 1.0), 0.0)
-        s = -A
-        u = np.einsum("ij,ij->i", s, h) * inv
-        qv = np.cross(s, E1)
-        v = (qv @ d) * inv
-        t = np.einsum("ij,ij->i", E2, qv) * inv
-        hit = ok & (u >= -1e-12) & (v >= -1e-12) & (u + v <= 1 + 1e-12) & (t > 0)
-        res[i] = bool(np.any(hit)) and rn < np.min(t[hit])
-    return res
+    return MeshQuery(verts, tris).inside(p)
 
 
 def _place_helix(n_per_strand, radius, verts, tris, clearance, log):
@@ -388,31 +480,45 @@ def _place_helix(n_per_strand, radius, verts, tris, clearance, log):
             z = (k - (n_per_strand - 1) / 2.0) * rise
             pts.append([radius * math.cos(th), radius * math.sin(th), z])
     pts = np.array(pts)
+    mq = MeshQuery(verts, tris)
+
+    def ok(x, sc):  # every point x[i] scaled by sc[i] inside, with the clearance
+        y = x * sc[:, None]
+        good = mq.inside(y)
+        if np.any(good):
+            good[good] = mq.distance(y[good]) >= clearance
+        return good
+
+    # charges that violate the clearance move towards the origin: scale factors
+    # 0.95, 0.90, ... until one is feasible (0 ends the search), then 16
+    # bisections between it and the last infeasible one
+    bad = ~ok(pts, np.ones(len(pts)))
+    idx = np.nonzero(bad)[0]
+    x = pts[idx]
+    s_hi = np.ones(idx.size)
+    step = np.ones(idx.size)
+    active = np.ones(idx.size, dtype=bool)
+    while np.any(active):
+        step[active] = np.maximum(0.0, step[active] - 0.05)
+        a_idx = np.nonzero(active)[0]
+        zero = step[a_idx] == 0.0
+        done = zero.copy()
+        rest = a_idx[~zero]
+        if rest.size:
+            done[~zero] = ok(x[rest], step[rest])
+        for j, dn in zip(a_idx, done):
+            if not dn:
+                s_hi[j] = step[j]
+        active[a_idx[done]] = False
+    s_lo = step.copy()
+    for _ in range(16):
+        mid = 0.5 * (s_lo + s_hi)
+        g = ok(x, mid) if idx.size else np.zeros(0, dtype=bool)
+        s_lo = np.where(g, mid, s_lo)
+        s_hi = np.where(g, s_hi, mid)
     out = pts.copy()
-    tapered = 0
-    for i, x in enumerate(pts):
-        def ok(s):
-            y = x * s
-            return inside_star(y[None], verts, tris)[0] and point_mesh_distance(y[None], verts, tris)[0] >= clearance
-        if ok(1.0):
-            continue
-        tapered += 1
-        s_hi = 1.0
-        step = 1.0
-        while True:
-            step = max(0.0, step - 0.05)
-            if step == 0.0 or ok(step):
-                break
-            s_hi = step
-        s_lo = step
-        for _ in range(16):  # bisect towards the feasible boundary
-            mid = 0.5 * (s_lo + s_hi)
-            if ok(mid):
-                s_lo = mid
-            else:
-                s_hi = mid
-        out[i] = x * s_lo
-    log["helix_tapered"] = tapered
+    out[idx] = x * s_lo[:, None]
+    log["helix_tapered"] = int(idx.size)
     return out
 
 
@@ -420,12 +526,13 @@ def _place_partials(count, sigma, rng, verts, tris, clearance):
     lo = verts.min(0)
     hi = verts.max(0)
     acc = []
+    mq = MeshQuery(verts, tris)
     while len(acc) < count:
         cand = rng.uniform(lo, hi, size=(max(64, 2 * (count - len(acc))), 3))
-        ins = inside_star(cand, verts, tris)
+        ins = mq.inside(cand)
         cand = cand[ins]
         if cand.size:
-            d = point_mesh_distance(cand, verts, tris)
+            d = mq.distance(cand)
             cand = cand[d >= clearance]
         for c in cand:
             if len(acc) < count:
@@ -497,9 +604,10 @@ def make_config(cfg: int, instance: int = 0, **override):
 
 
 def batch_instance(cfg: int, instance: int, n_lo=4, n_hi=44):
-    """One instance of the batched / serving workloads: triangle count log-uniform
-    over frequencies [n_lo, n_hi], kappa ~ U(0.03, 0.33), half sphere-type
-    (central +1 charge) and half RNA-type (helix of 4..60 charges)."""
+    """One instance of the batched workload: triangle count log-uniform over
+    frequencies [n_lo, n_hi], kappa ~ U(0.03, 0.33), half sphere-type (the
+    charged-sphere generator: central +1 charge) and half RNA-type (the
+    RNA-like generator: helix of 4..60 charges plus its 400 partial charges)."""
     rng = np.random.default_rng([cfg, instance, 7])
     n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
     kappa = float(rng.uniform(0.03, 0.33))
@@ -511,21 +619,22 @@ def batch_instance(cfg: int, instance: int, n_lo=4, n_hi=44):
     span = (per - 1) * 28.0 / 11.0
     c = max(15.0, span / 2.0 + 8.0)
     L = 10
-    return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=L, helix=per, partials=0,
+    return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=L, helix=per, partials=400,
                         kappa=kappa, seed=(cfg, instance))
 
 
 def serve_instance(instance: int, n_lo=4, n_hi=64, cfg=4):
-    """One request of the serving workload: an RNA-like solute of the config-1
-    generator with a triangle count log-uniform over frequencies [n_lo, n_hi],
-    a helix of 4..60 charges and kappa ~ U(0.03, 0.33)."""
+    """One request of the serving workload: an RNA-like solute of the
+    RNA-like generator with a triangle count log-uniform over frequencies
+    [n_lo, n_hi], a helix of 4..60 charges, its 400 partial charges and
+    kappa ~ U(0.03, 0.33)."""
     rng = np.random.default_rng([cfg, instance, 11])
     n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
     kappa = float(rng.uniform(0.03, 0.33))
     h = int(rng.integers(4, 61))
     per = (h + 1) // 2
     c = max(15.0, (per - 1) * 28.0 / 11.0 / 2.0 + 8.0)
-    return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=10, helix=per, partials=0, kappa=kappa,
+    return make_problem(n=n, a=10.0, c=c, bump=True, t=6.0, L=10, helix=per, partials=400, kappa=kappa,
                         seed=(cfg, instance))
 
 

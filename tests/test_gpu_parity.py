@@ -328,6 +328,34 @@ def test_error_codes(ctx):
     assert e.value.code == pb.EMESH
 
 
+def test_inward_oriented_surfaces_are_refused(ctx):
+    """A surface oriented consistently but towards the solute (every
+    triangle flipped) is closed and manifold, yet flips the sign of its double
+    layer: setup refuses it with PBFB_EMESH from the negative enclosed volume,
+    for Gamma_m and for Gamma_s, with and without charges."""
+    import paper_2511_21713_amd as pb
+    prob = cached_config(0)
+    for which in ("m", "s"):
+        for charged in (True, False):
+            tm = prob.tri_m[:, [0, 2, 1]].copy() if which == "m" else prob.tri_m
+            ts = prob.tri_s[:, [0, 2, 1]].copy() if which == "s" else prob.tri_s
+            g = pb.Problem(ctx)
+            g.set_mesh(prob.nodes, prob.tets, tm, ts)
+            g.set_params(prob.eps_in, prob.eps_out, prob.kappa)
+            if charged:
+                g.set_charges(prob.q_xyz, prob.q_z)
+            else:
+                g.set_charges(np.zeros((0, 3)), np.zeros(0))
+            with pytest.raises(pb.PbfbError) as e:
+                g.setup()
+            log(f"  flipped Gamma_{which}, charges {charged}: {pb.last_error()}")
+            assert e.value.code == pb.EMESH
+            g.close()
+    g = pb.Problem.from_inputs(ctx, prob)  # the outward-oriented mesh is accepted
+    g.setup()
+    g.close()
+
+
 def test_problem_outliving_its_context():
     """A context destroyed before its problems detaches them: calls on them
     fail with PBFB_ESTATE, destroying them still works, and a new context is

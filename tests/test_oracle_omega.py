@@ -192,3 +192,32 @@ def test_picard_norm_ratio_rule():
     r0, _, _ = o.solve(nonlinear_method=oracle.PICARD, omega_method=oracle.OMEGA_BSEC_DF, omega_max=1.0, l_e=0.0,
                        r_e=0.0)
     assert all(r0["omega"][k] != r0["omega"][k - 1] for k in range(1, len(r0["omega"])))
+
+
+@pytest.mark.parametrize("r_e", [1.4, 3.0, 4.5])
+def test_picard_first_reuse_from_a_run_without_the_rule(r_e):
+    """The norm-ratio rule (the section on reducing omega searches: search
+    again only when the ratio of the two latest step norms falls below R_e),
+    checked against a run that never applies it.  Until the rule first
+    reuses a factor, a run with R_e and one with R_e = 0 take identical steps,
+    so the step norms e_1, e_2, ... of the R_e = 0 run, which the rule played
+    no part in producing, fix the first reuse: the smallest k >= 3 with
+    e_{k-2} >= R_e e_{k-1}.  The three thresholds put it at three different
+    steps of the same sequence, so using other step norms (e_{k-3}/e_{k-2},
+    the inverse ratio), another first step or the opposite comparison moves
+    it and fails."""
+    prob = pbgen.make_problem(**SPEC)
+    o = oracle.Oracle.from_problem(prob)
+    kw = dict(nonlinear_method=oracle.PICARD, omega_method=oracle.OMEGA_BSEC_DF, omega_max=1.0, l_e=0.0)
+    r0, _, _ = o.solve(r_e=0.0, **kw)
+    e0, w0 = r0["e_k"], r0["omega"]
+    kstar = next(k for k in range(3, len(e0) + 1) if e0[k - 3] >= r_e * e0[k - 2])
+    assert all(w0[j] != w0[j - 1] for j in range(1, len(w0)))  # R_e = 0: a new factor at every step
+    r, _, _ = o.solve(r_e=r_e, **kw)
+    assert r["status"] == 0
+    e, w = r["e_k"], r["omega"]
+    for j in range(kstar - 1):  # steps 1 .. k* - 1 as without the rule
+        assert w[j] == pytest.approx(w0[j], rel=1e-12, abs=0.0)
+        assert e[j] == pytest.approx(e0[j], rel=1e-12, abs=0.0)
+    assert w[kstar - 1] == w[kstar - 2]  # step k* reuses the factor of step k* - 1
+    assert w0[kstar - 1] != pytest.approx(w0[kstar - 2], rel=1e-6)
