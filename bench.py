@@ -1,18 +1,22 @@
 #!/usr/bin/env python
 """Benchmark of the nonlinear Poisson-Boltzmann FEM-BEM hot path on one MI355X.
 
-One step = one complete solve of the RNA-like workload (20480 triangles per
-interface, 614400 shell tets, 48 helix + 400 partial charges, kappa = 0.125):
-device setup from the resident mesh (geometry, FEM values, Coulomb load, dense
-Laplace and Yukawa Galerkin operators with touching-panel integrals), the
-linear solve, cubic-start Newton with the self-adjusted relaxation factor,
-and the energy.  The host-side mesh topology and the mesh upload happen
-before the timed region (inputs resident in HBM).
+One step = one complete solve of the large RNA-like workload (81920 triangles
+per interface, 2949120 shell tets, 120 helix + 400 partial charges, kappa =
+0.125) in its mixed-precision form: device setup from the resident mesh
+(geometry, FEM values, Coulomb load, dense Laplace and Yukawa Galerkin
+operators with FP32 evaluation of the regular pairs, FP64 touching-panel
+integrals, FP32 storage), the linear solve, cubic-start Newton with the
+self-adjusted relaxation factor, GMRES with an FP32 Krylov basis inside FP64
+iterative refinement, and the energy.  The host-side mesh topology and the
+mesh upload happen before the timed region (inputs resident in HBM).
 
-Prints one JSON line: PB solves/s (FP64 path, the workload's precision),
-coupled-operator GFLOP/s, step latency p50/p99, the mixed-precision leg and
-its energy error against the FP64 path, the roofline of the dense GEMV (the
-dominant kernel) from HIP events, and the CPU oracle baseline.
+Prints one JSON line: PB solves/s of that path (`value`), the FP64 path on
+the same workload and the relative energy / surface-potential error between
+them, coupled-operator GFLOP/s, step latency p50/p99, the roofline of the
+dense GEMV (the dominant kernel) from HIP events, the CPU oracle baseline, and
+further legs (the RNA-like 20k-triangle workload's variants, batched and
+served solves).
 """
 import argparse
 import json
@@ -32,10 +36,22 @@ HBM_PEAK_GBS = 8000.0
 # --pmc runs (FETCH_SIZE then WRITE_SIZE, each scaled by the factor the same
 # counter reads for a copy of known size), valid for the kernel source whose
 # hash is recorded with it; see profiles/gemv_f64_rna20k_hbm_counters.md.
-GEMV_TRAFFIC = {"config": 1, "src_sha256_16": "d9c2eb2ba90cdfa6", "bytes": 2.53424e9 + 7.9254e7 + 5.3112e7}
+GEMV_TRAFFIC = {
+    "rna20k_f64": {"src_sha256_16": "d9c2eb2ba90cdfa6", "bytes": 2.53424e9 + 7.9254e7 + 5.3112e7},
+}
+
+
+def gemv_traffic_key(cfg, elem):
+    return {1: "rna20k", 2: "rna80k"}.get(cfg, f"config{cfg}") + ("_f64" if elem == 8 else "_f32")
 # algorithmic flops per quadrature-point pair of the regular tiles, counting
 # add/mul/rsqrt/exp as 1 and FMA as 2: Laplace V and K 37, Yukawa 46
 FLOPS_QP = {"laplace": 37, "yukawa": 46}
+# the same for the matrix-free apply's k_mf_pot (one potential pair per
+# quadrature pair): 3 sub, 5 for r^2, rsqrt, 2 mul r^-3, 2 FMA for the two
+# strength sums = 15, plus the per-target-point normal distance and FP64
+# accumulation (11 flops over the 6 source points) = 17; Yukawa adds r = r^2
+# r^-1, the exponent (2 mul), exp, e r^-1, (1 + kappa r) (FMA), 2 mul = 9
+MF_FLOPS_QP = {"laplace": 17, "yukawa": 26}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
@@ -162,7 +178,7 @@ def run_leg(pb, torch, prob, precision, steps, warmup, opts, label, bem_mode=Non
         u_m = (phi[:g.n] + phi[g.n:])[np.unique(prob.tri_m)]
     tiles = {"laplace_gamma_m": list(g.tile_shape(0)), "yukawa_gamma_s": list(g.tile_shape(1))}
     out = dict(elapsed=elapsed, lat=lat, res=res, timing=tm, n=g.n, n_m=g.n_m, n_s=g.n_s, hbm=g.hbm(), u_m=u_m,
-               tiles=tiles)
+               tiles=tiles, steps=steps)
     if potential and time_energy:
         out["energy_ms"] = energy_ms
     g.close()
@@ -211,22 +227,26 @@ def serve_requests(count, nmax):
     import pbgen
     t0 = time.perf_counter()
     probs = [pbgen.serve_instance(i, n_hi=nmax) for i in range(count)]
-    progress(f"serve: generated {count} requests in {time.perf_counter() - t0:.1f} s")
+    tris = sorted(p.tri_m.shape[0] for p in probs)
+    progress(f"serve: generated {count} requests in {time.perf_counter() - t0:.1f} s, triangles per interface "
+             f"{tris[0]}..{tris[-1]} (median {tris[len(tris) // 2]})")
     return probs
 
 
-def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0):
-    """Serving workload: the requests `probs` (config-1 generator, triangles
-    log-uniform over 320..20 n_max^2, random kappa) arriving as a Poisson
-    process at `load` x the measured single-request service rate, submitted
-    to a continuous-batching server; latency = submit to completion.  One run
-    per load; the service rate comes from solo solves of the first requests."""
+def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0, budget=48 << 30, slots=16):
+    """Serving workload: the requests `probs` (RNA-like generator with its
+    partial charges, triangles log-uniform over 320..20 n_max^2, random kappa)
+    arriving as a Poisson process at `load` x the measured service rate,
+    submitted to a continuous-batching server with an HBM budget that binds
+    (requests wait for admission); latency = submit to completion, admission
+    wait = submit to admission.  The service rate is the mean solo solve time
+    of every fifth request (setup included)."""
     import numpy as np
 
     count = len(probs)
     ctx = pb.Context(0)
     svc = []
-    for p in probs[:4]:
+    for p in probs[::5]:
         g = pb.Problem.from_inputs(ctx, p, precision=precision)
         g.solve()
         g.reset_operators()
@@ -235,23 +255,32 @@ def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0):
         svc.append(time.perf_counter() - ts)
         g.close()
     out = {}
+    prec = "mixed" if precision == pb.MIXED else "fp64"
     for load in loads:
         rate = load / (sum(svc) / len(svc))
         rng = np.random.default_rng([4, seed])
         gaps = rng.exponential(1.0 / rate, size=count)
-        srv = pb.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=16)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        low = free0
+        srv = pb.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
         gs = [pb.Problem.from_inputs(ctx, p, precision=precision) for p in probs]
         submit, done, res = {}, {}, {}
-        tickets = []
+        tickets, rejected = [], 0
         start = time.perf_counter()
         next_t = start
         i = 0
-        while len(done) < count:
+        while len(done) < len(tickets) or i < count:
             now = time.perf_counter()
             while i < count and now >= next_t:
-                t = srv.submit(gs[i])
-                tickets.append(t)
-                submit[t] = time.perf_counter()
+                try:
+                    t = srv.submit(gs[i])
+                    tickets.append(t)
+                    submit[t] = time.perf_counter()
+                except pb.PbfbError as e:
+                    if e.code != pb.ENOMEM:
+                        raise
+                    rejected += 1
                 next_t += gaps[i]
                 i += 1
             for t in tickets:
@@ -260,60 +289,111 @@ def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0):
                     if r is not None:
                         done[t] = time.perf_counter()
                         res[t] = r
+            low = min(low, torch.cuda.mem_get_info()[0])
             time.sleep(0.0005)
         makespan = time.perf_counter() - start
         srv.close()
         for g in gs:
             g.close()
         lat = [done[t] - submit[t] for t in tickets]
+        waits = [res[t]["t_wait_s"] for t in tickets]
         bad = sum(1 for t in tickets if res[t]["status"] != 0)
         if bad:
             raise RuntimeError(f"{bad} served requests failed")
-        progress(f"serve ({'mixed' if precision == pb.MIXED else 'fp64'}, load {load}): {count} requests in "
-                 f"{makespan:.2f} s, p50 {percentile(lat, 0.5):.3f} s, p99 {percentile(lat, 0.99):.3f} s")
-        out[f"load_{load}"] = {"arrival_rate_per_s": rate, "load": load, "value": count / makespan,
+        progress(f"serve ({prec}, load {load}): {len(tickets)} requests in {makespan:.2f} s, p50 "
+                 f"{percentile(lat, 0.5):.3f} s, p99 {percentile(lat, 0.99):.3f} s, admission wait p99 "
+                 f"{percentile(waits, 0.99):.3f} s, peak device use {(free0 - low) / 2**30:.1f} GiB, {rejected} rejected")
+        out[f"load_{load}"] = {"arrival_rate_per_s": rate, "load": load, "value": len(tickets) / makespan,
                                "unit": "PB solves/s",
                                "latency_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
-                               "failures": bad}
+                               "admission_wait_s": {"p50": percentile(waits, 0.5), "p99": percentile(waits, 0.99),
+                                                    "waited": sum(1 for w in waits if w > 1e-3)},
+                               "peak_device_bytes": free0 - low, "failures": bad,
+                               "rejected_over_budget": rejected}
     ctx.close()
     main = out["load_0.8"] if "load_0.8" in out else next(iter(out.values()))
-    return dict(main, requests=count, precision="mixed" if precision == pb.MIXED else "fp64",
-                max_triangles=20 * nmax * nmax, solo_service_s=sum(svc) / len(svc), by_load=out)
+    return dict(main, requests=count, precision=prec, max_triangles=int(max(p.tri_m.shape[0] for p in probs)),
+                hbm_budget_bytes=budget, max_slots=slots, solo_service_s=sum(svc) / len(svc), by_load=out)
 
 
-def cpu_baseline(prob, applies_per_solve, seed=0):
-    """Oracle timed on a bounded sample of the same workload, extrapolated to
-    one solve: sampled dense Galerkin rows (assembly), the oracle's dense row
-    loop on those rows, and its matrix-free FEM products."""
+def host_info():
+    """CPU model, logical CPUs and memory of the host the bench runs on."""
+    model, mem = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = float(line.split()[1]) * 1024 / 2**30
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_gib": mem}
+
+
+def cpu_baseline(prob, applies_per_solve, seed=0, budget_s=12.0):
+    """The oracle timed on a bounded sample of the same workload and
+    extrapolated to one solve (labelled so): sampled dense Galerkin rows of
+    both interfaces (assembly), the oracle's dense row products on those rows,
+    and its matrix-free FEM Jacobian product; solve time = assembly of every
+    row + applies_per_solve (the GPU FP64 run's count) x (dense rows + FEM
+    product).  Measured with all host threads and with one."""
     import numpy as np
 
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = oracle.Oracle.from_problem(prob)
     rng = np.random.default_rng(seed)
-    nrows = 32 * max(1, threads)
-    t_asm = t_dense = 0.0
     x = rng.standard_normal(o.n)
-    for surf, nv in ((0, o.n_m), (1, o.n_s)):
-        rows = np.sort(rng.choice(nv, size=nrows, replace=False))
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {}
+    for label, threads in (("all", all_threads), ("one", 1)):
+        oracle.set_threads(threads)
+        nrows = max(2, 2 * threads) if prob.tri_m.shape[0] > 40000 else 8 * threads
+        t_asm = t_dense = 0.0
+        for surf, nv in ((0, o.n_m), (1, o.n_s)):
+            rows = np.sort(rng.choice(nv, size=nrows, replace=False))
+            t0 = time.perf_counter()
+            V, K = o.bem_rows(surf, rows)
+            t_asm += (time.perf_counter() - t0) * nv / nrows
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                o.dense_rows_apply(surf, V, K, x)
+            t_dense += (time.perf_counter() - t0) / reps * nv / nrows
         t0 = time.perf_counter()
-        V, K = o.bem_rows(surf, rows)
-        t_asm += (time.perf_counter() - t0) * nv / nrows
-        reps = 20
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            o.dense_rows_apply(surf, V, K, x)
-        t_dense += (time.perf_counter() - t0) / reps * nv / nrows
-    t0 = time.perf_counter()
-    for _ in range(3):
         o.fem_jacobian(oracle.HS, x, x)
-    t_fem = (time.perf_counter() - t0) / 3
-    t_solve = t_asm + applies_per_solve * (t_dense + t_fem)
-    sample = (f"{nrows} Galerkin rows per interface assembled, their dense row products x20, 3 FEM Jacobian "
-              f"products; extrapolated to one solve = assembly of all rows + {applies_per_solve} coupled applies "
-              f"(the GPU run's count); assembly {t_asm:.1f} s, dense apply {t_dense * 1e3:.1f} ms, "
-              f"FEM product {t_fem * 1e3:.1f} ms")
-    return dict(value=1.0 / t_solve, unit="PB solves/s", cores=threads, kind="oracle", sample=sample)
+        t_fem = time.perf_counter() - t0
+        t_solve = t_asm + applies_per_solve * (t_dense + t_fem)
+        out[label] = dict(threads=int(threads), rows_per_interface=int(nrows), t_assembly_s=t_asm,
+                          t_dense_apply_s=t_dense, t_fem_product_s=t_fem, t_solve_s=t_solve)
+    oracle.set_threads(all_threads)
+    a, one = out["all"], out["one"]
+    sample = (f"extrapolated: {a['rows_per_interface']} Galerkin rows per interface assembled by the oracle, their "
+              f"dense row products x5, 1 FEM Jacobian product, scaled to one solve = assembly of every row + "
+              f"{applies_per_solve} coupled applies (the GPU FP64 run's count); {a['threads']} threads: assembly "
+              f"{a['t_assembly_s']:.1f} s, dense apply {a['t_dense_apply_s']:.3f} s, FEM product "
+              f"{a['t_fem_product_s'] * 1e3:.1f} ms; 1 thread: {1.0 / one['t_solve_s']:.3g} solves/s")
+    return dict(value=1.0 / a["t_solve_s"], unit="PB solves/s", cores=a["threads"], kind="oracle", sample=sample,
+                extrapolated=True, single_core={"value": 1.0 / one["t_solve_s"], "unit": "PB solves/s",
+                                                "t_solve_s": one["t_solve_s"]},
+                host=host_info(), detail=out)
+
+
+def leg_summary(leg, K, ref=None, u_ref=None):
+    r = leg["res"]
+    d = {"value": K / leg["elapsed"], "unit": "PB solves/s", "steps": K, "ms_per_step": 1e3 * leg["elapsed"] / K,
+         "latency_s": {"p50": percentile(leg["lat"], 0.5), "p99": percentile(leg["lat"], 0.99)},
+         "total_kcal_mol": r["total"], "lc": r["lc"], "nc": r["nc"], "dg_omega_i": r["dg_omega_i"],
+         "newton_iters": r["newton_iters"], "gmres_iters_total": r["gmres_iters_total"], "omega": r["omega"],
+         "coupled_applies_per_solve": r["applies"], "device_bytes": leg["hbm"], "status": r["status"],
+         "setup_s": r["t_setup_s"], "solve_s": r["t_solve_s"]}
+    if ref is not None:
+        d["rel_err_vs_fp64"] = {k: abs(r[k] - ref[k]) / abs(ref[k]) for k in ("total", "lc", "nc", "dg_omega_i")}
+    if u_ref is not None and leg["u_m"] is not None:
+        d["surface_potential_rel_err_vs_fp64"] = float(np.linalg.norm(leg["u_m"] - u_ref) / np.linalg.norm(u_ref))
+    return d
 
 
 def main():
@@ -321,16 +401,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2,
+                    help="workload of the headline line: 2 = large RNA-like (mixed precision, the default), "
+                         "1 = RNA-like (FP64), 0 = charged sphere (FP64)")
+    ap.add_argument("--cmp-steps", type=int, default=5, help="timed steps of the comparison legs at the workload")
+    ap.add_argument("--side-config", type=int, default=1, help="workload of the variant legs (Picard, schedules, "
+                                                               "root finders, matrix-free, two-field)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard comparison leg")
     ap.add_argument("--no-matrix-free", action="store_true", help="skip the matrix-free boundary-element leg")
     ap.add_argument("--no-schemes", action="store_true", help="skip the Taylor-schedule comparison leg")
     ap.add_argument("--no-two-field", action="store_true", help="skip the two-field form leg")
+    ap.add_argument("--no-side", action="store_true", help="skip every variant leg")
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched leg (0: skip)")
-    ap.add_argument("--serve", type=int, default=48, help="requests of the serving leg (0: skip)")
-    ap.add_argument("--serve-nmax", type=int, default=20, help="largest icosphere frequency of served requests")
+    ap.add_argument("--serve", type=int, default=40, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-nmax", type=int, default=64, help="largest icosphere frequency of served requests")
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="HBM budget of the serving leg")
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,1.0")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="run one device copy of this size first (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -351,108 +439,164 @@ def main():
         torch.cuda.synchronize()
         del a, b
         progress(f"calibration copy of {n * 8 / 1e9:.3f} GB done")
-    t0 = time.perf_counter()
-    prob = pbgen.make_config(args.config)
-    progress(f"generated workload {args.config} in {time.perf_counter() - t0:.1f} s: {prob.nodes.shape[0]} nodes, "
-             f"{prob.tets.shape[0]} tets, {prob.tri_m.shape[0]} triangles per interface, {prob.q_z.size} charges")
-    opts = dict()  # cubic start, self-adjusted omega, App. B settings (library defaults)
-    if args.config == 0:
-        opts = dict(omega_auto=0, omega_fixed=0.5)
-    f64 = run_leg(pb, torch, prob, pb.FP64, args.steps, args.warmup, opts, "fp64")
     K = args.steps
-    value = K / f64["elapsed"]
-    ms_step = 1e3 * f64["elapsed"] / K
-    nm, ns = f64["n_m"], f64["n_s"]
-    gemv_ms, gemv_cnt = f64["timing"]["gemv"]
-    apply_ms, apply_cnt = f64["timing"]["apply"]
-    asm_ms, asm_cnt = f64["timing"]["assembly"]
-    sym = all(a == b for a, b in f64["tiles"].values())  # square tiles: symmetric use of V'
-    gb = gemv_bytes(nm, ns, 8, sym)
+    cfg = args.config
+    t0 = time.perf_counter()
+    prob = pbgen.make_config(cfg)
+    progress(f"generated workload {cfg} in {time.perf_counter() - t0:.1f} s: {prob.nodes.shape[0]} nodes, "
+             f"{prob.tets.shape[0]} tets, {prob.tri_m.shape[0]} triangles per interface, {prob.q_z.size} charges")
+    base_opts = dict()  # cubic start, self-adjusted omega, App. B settings (library defaults)
+    if cfg == 0:
+        base_opts = dict(omega_auto=0, omega_fixed=0.5)
+    mixed_head = cfg == 2 and not args.no_mixed
+    head_prec = pb.MIXED if mixed_head else pb.FP64
+    head_opts = dict(base_opts, krylov_fp32=1) if mixed_head else dict(base_opts)
+    head = run_leg(pb, torch, prob, head_prec, K, args.warmup, head_opts,
+                   "mixed (fp32 krylov basis)" if mixed_head else "fp64")
+    if mixed_head:
+        f64 = run_leg(pb, torch, prob, pb.FP64, args.cmp_steps, 1, base_opts, "fp64")
+    else:
+        f64 = head
+    res64 = f64["res"]
+    nm, ns = head["n_m"], head["n_s"]
+    elem = 4 if mixed_head else 8
+    gemv_ms, gemv_cnt = head["timing"]["gemv"]
+    apply_ms, apply_cnt = head["timing"]["apply"]
+    sym = all(a == b for a, b in head["tiles"].values())  # square tiles: symmetric use of V'
+    gb = gemv_bytes(nm, ns, elem, sym)
     achieved = gb / (gemv_ms * 1e-3) / 1e9 if gemv_ms else None
-    res = f64["res"]
-    applies = res["applies"]
+    res = head["res"]
+    nnz = fem_nnz(prob)
+    nn = prob.nodes.shape[0]
+    flops = apply_flops(nm, ns, nnz)
+    kname = ("k_bgemv + k_bgemv_fin / k_gemv + k_gemv_fin (gemv_rows_sym: K' and the lower triangle of V', "
+             f"{'FP32' if elem == 4 else 'FP64'} storage, FP64 accumulation, both interfaces)" if sym else
+             f"k_bgemv / k_gemv (gemv_rows: dense [K'|V'] {'FP32' if elem == 4 else 'FP64'} GEMV, both interfaces)")
+    tkey = gemv_traffic_key(cfg, elem)
+    workload = (f"RNA-like solute, large: {prob.tri_m.shape[0]} triangles per interface, {prob.tets.shape[0]} shell "
+                f"tets, {prob.q_z.size} charges, kappa {prob.kappa}; " if cfg == 2 else
+                f"RNA-like solute: {prob.tri_m.shape[0]} triangles per interface, {prob.tets.shape[0]} shell tets, "
+                f"{prob.q_z.size} charges, kappa {prob.kappa}; " if cfg == 1 else
+                f"charged sphere: {prob.tri_m.shape[0]} triangles per interface, {prob.tets.shape[0]} shell tets; ")
+    workload += ("mixed precision (FP32 BEM evaluation and storage, FP32 FEM values, FP64 accumulation; GMRES with "
+                 "an FP32 Krylov basis inside FP64 iterative refinement); cubic-start Newton with self-adjusted "
+                 "relaxation" if mixed_head else "FP64; cubic-start Newton with self-adjusted relaxation")
     out = {
         "metric": "PB solves/s + coupled-operator GFLOP/s, mixed vs FP64 at <=1e-5 rel energy; p50/p99",
-        "value": value,
+        "value": K / head["elapsed"],
         "unit": "PB solves/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": 1e3 * head["elapsed"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64 mixed" if mixed_head else "f64",
         "data": "synthetic",
-        "config": {"workload": f"RNA-like solute (config {args.config}): {prob.tri_m.shape[0]} triangles per "
-                               f"interface, {prob.tets.shape[0]} shell tets, {prob.q_z.size} charges, kappa "
-                               f"{prob.kappa}, cubic-start Newton with self-adjusted relaxation, FP64",
-                   "unknowns": f64["n"], "parallelism": "single GPU"},
-        "latency_s": {"p50": percentile(f64["lat"], 0.5), "p99": percentile(f64["lat"], 0.99)},
+        "config": {"workload": workload, "unknowns": head["n"], "parallelism": "single GPU"},
+        "latency_s": {"p50": percentile(head["lat"], 0.5), "p99": percentile(head["lat"], 0.99)},
         "solve": {"total_kcal_mol": res["total"], "lc": res["lc"], "nc": res["nc"], "dg_omega_i": res["dg_omega_i"],
                   "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"],
-                  "omega": res["omega"], "status": res["status"], "coupled_applies_per_solve": applies},
-        "kernel_ms": {"gemv": gemv_ms, "coupled_apply": apply_ms, "bem_assembly_launch": asm_ms},
-        "roofline": {"bound": "hbm", "kernel": ("k_bgemv + k_bgemv_fin / k_gemv + k_gemv_fin (gemv_rows_sym: K' and the "
-                                                "lower triangle of V', FP64, both interfaces)" if sym else
-                                                "k_bgemv / k_gemv (gemv_rows: dense [K'|V'] FP64 GEMV, both interfaces)"),
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "omega": res["omega"], "status": res["status"], "coupled_applies_per_solve": res["applies"],
+                  "device_bytes": head["hbm"]},
+        "kernel_ms": {"gemv": gemv_ms, "coupled_apply": apply_ms},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": (GEMV_TRAFFIC["bytes"] if (args.config == GEMV_TRAFFIC["config"] and
-                                                           gemv_source_hash() == GEMV_TRAFFIC["src_sha256_16"])
-                                 else None),
+                     "traffic": (GEMV_TRAFFIC[tkey]["bytes"] if tkey in GEMV_TRAFFIC and
+                                 gemv_source_hash() == GEMV_TRAFFIC[tkey]["src_sha256_16"] else None),
                      "bytes_per_launch": gb},
     }
+    if mixed_head:
+        out["rel_energy_err_vs_fp64"] = abs(res["total"] - res64["total"]) / abs(res64["total"])
+        out["surface_potential_rel_err_vs_fp64"] = float(np.linalg.norm(head["u_m"] - f64["u_m"]) /
+                                                         np.linalg.norm(f64["u_m"]))
+        out["fp64"] = leg_summary(f64, args.cmp_steps)
+        g64_ms = f64["timing"]["gemv"][0]
+        gb64 = gemv_bytes(nm, ns, 8, all(a == b for a, b in f64["tiles"].values()))
+        out["fp64"]["gemv"] = {"ms": g64_ms, "bytes_per_launch": gb64,
+                               "achieved_gbs": gb64 / (g64_ms * 1e-3) / 1e9 if g64_ms else None,
+                               "frac": gb64 / (g64_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if g64_ms else None}
+        out["mixed_speedup_vs_fp64"] = out["value"] / out["fp64"]["value"]
+        # the same mixed path with an FP64 Krylov basis
+        mx64 = run_leg(pb, torch, prob, pb.MIXED, args.cmp_steps, 1, base_opts, "mixed (fp64 krylov basis)")
+        out["mixed_fp64_krylov"] = leg_summary(mx64, args.cmp_steps, res64, f64["u_m"])
+        out["mixed_fp64_krylov"]["coupled_operator_gflops"] = (flops / (mx64["timing"]["apply"][0] * 1e-3) / 1e9
+                                                               if mx64["timing"]["apply"][0] else None)
+
     # regular BEM tiles: algorithmic flops per solve over the HIP-event time
     # of the tile launches (both interfaces; touching pairs excluded)
     asm_flops = 36 * (FLOPS_QP["laplace"] * regular_pairs(prob.tri_m) +
                       FLOPS_QP["yukawa" if prob.kappa > 0 else "laplace"] * regular_pairs(prob.tri_s))
 
-    def asm_report(leg, peak):
+    def asm_report(leg, peak, steps):
         ms, cnt = leg["timing"]["assembly"]
-        t = ms * cnt / K * 1e-3
+        t = ms * cnt / steps * 1e-3
         return {"kernel": "k_bem_regular (6 x 6 rule, non-touching pairs)", "tile_shapes_autotuned": leg["tiles"],
                 "flops_per_solve": asm_flops,
                 "ms_per_solve": t * 1e3, "tflops": asm_flops / t / 1e12 if t else None, "peak_tflops": peak,
                 "frac": asm_flops / t / 1e12 / peak if t else None}
 
-    out["bem_assembly"] = {"fp64": asm_report(f64, FP64_PEAK_TFLOPS)}
-    nnz = fem_nnz(prob)
-    nn = prob.nodes.shape[0]
-
-    def spmv_report(leg, elem):
+    def spmv_report(leg, e):
         ms, cnt = leg["timing"]["spmv"]
-        b = spmv_bytes(nnz, nn, leg["n"], elem)
+        b = spmv_bytes(nnz, nn, leg["n"], e)
         gbs = b / (ms * 1e-3) / 1e9 if ms else None
         return {"kernel": "k_bspmv / k_spmv (sell_part: sliced-ELL FEM rows)", "bound": "hbm",
-                "bytes_per_launch": b, "ms_per_launch": ms, "launches": cnt, "achieved": gbs,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
-                "nnz": nnz, "value_bytes": elem}
+                "bytes_per_launch": b, "working_set_bytes": b, "ms_per_launch": ms, "launches": cnt,
+                "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                "nnz": nnz, "value_bytes": e,
+                "cache_note": (f"each launch follows the dense apply of the same coupled apply, which streams "
+                               f"{gemv_bytes(nm, ns, e, sym) / 1e9:.1f} GB through the 256 MB Infinity Cache")}
 
+    out["bem_assembly"] = {"fp64": asm_report(f64, FP64_PEAK_TFLOPS, f64["steps"])}
     out["fem_spmv"] = {"fp64": spmv_report(f64, 8)}
-    out["kernel_ms"]["precond_per_solve"] = f64["timing"]["precond"][0] * f64["timing"]["precond"][1] / K
-    flops = apply_flops(nm, ns, nnz)
+    out["kernel_ms"]["precond_per_solve"] = head["timing"]["precond"][0] * head["timing"]["precond"][1] / K
     if apply_ms:
         out["coupled_operator_gflops"] = flops / (apply_ms * 1e-3) / 1e9
-    if not args.no_mixed:
-        mx = run_leg(pb, torch, prob, pb.MIXED, K, args.warmup, opts, "mixed")
-        rm = mx["res"]
-        mg_ms = mx["timing"]["gemv"][0]
-        out["mixed"] = {
-            "value": K / mx["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * mx["elapsed"] / K,
-            "latency_s": {"p50": percentile(mx["lat"], 0.5), "p99": percentile(mx["lat"], 0.99)},
-            "total_kcal_mol": rm["total"], "rel_energy_err_vs_fp64": abs(rm["total"] - res["total"]) / abs(res["total"]),
-            "rel_err_vs_fp64": {k: abs(rm[k] - res[k]) / abs(res[k]) for k in ("total", "lc", "nc", "dg_omega_i")},
-            "surface_potential_rel_err_vs_fp64": float(np.linalg.norm(mx["u_m"] - f64["u_m"]) /
-                                                       np.linalg.norm(f64["u_m"])),
-            "newton_iters": rm["newton_iters"], "gmres_iters_total": rm["gmres_iters_total"],
-            "gemv_ms": mg_ms,
-            "gemv_gbs": gemv_bytes(nm, ns, 4, all(a == b for a, b in mx["tiles"].values())) / (mg_ms * 1e-3) / 1e9
-            if mg_ms else None,
-            "coupled_operator_gflops": flops / (mx["timing"]["apply"][0] * 1e-3) / 1e9 if mx["timing"]["apply"][0] else None,
-        }
-        out["bem_assembly"]["mixed_fp32_eval"] = asm_report(mx, FP32_PEAK_TFLOPS)
+    if f64["timing"]["apply"][0]:
+        out["coupled_operator_gflops_fp64"] = flops / (f64["timing"]["apply"][0] * 1e-3) / 1e9
+    if mixed_head:
+        out["bem_assembly"]["mixed_fp32_eval"] = asm_report(head, FP32_PEAK_TFLOPS, K)
+        out["fem_spmv"]["mixed_fp32_values"] = spmv_report(head, 4)
+    elif not args.no_mixed:
+        mx = run_leg(pb, torch, prob, pb.MIXED, args.cmp_steps, 1, dict(base_opts, krylov_fp32=1), "mixed")
+        out["mixed"] = leg_summary(mx, args.cmp_steps, res64, f64["u_m"])
+        out["bem_assembly"]["mixed_fp32_eval"] = asm_report(mx, FP32_PEAK_TFLOPS, args.cmp_steps)
         out["fem_spmv"]["mixed_fp32_values"] = spmv_report(mx, 4)
+    cpu_applies = max(res64["applies"], 1)
+
+    if not args.no_side:
+        side_legs(pb, torch, pbgen, args, out)
+    if args.batch > 0:
+        out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
+                          "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}
+    if args.serve > 0:
+        reqs = serve_requests(args.serve, args.serve_nmax)
+        loads = tuple(float(x) for x in args.serve_loads.split(","))
+        out["serving"] = {"mixed": serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED, loads,
+                                             budget=int(args.serve_budget_gb * 2**30)),
+                          "fp64": serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64, (0.8,),
+                                            budget=int(args.serve_budget_gb * 2**30))}
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle, bounded sample, extrapolated)")
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(prob, cpu_applies)
+        progress(f"cpu baseline took {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+def side_legs(pb, torch, pbgen, args, out):
+    """Variants of the method on the RNA-like 20k-triangle workload, each
+    compared with an FP64 Newton solve of that workload."""
+    cfg = args.side_config
+    prob = pbgen.make_config(cfg)
+    opts = dict(omega_auto=0, omega_fixed=0.5) if cfg == 0 else dict()
+    base = run_leg(pb, torch, prob, pb.FP64, 3, 1, opts, f"side fp64 (workload {cfg})")
+    res = base["res"]
+    side = {"workload": f"RNA-like solute (config {cfg}): {prob.tri_m.shape[0]} triangles per interface, "
+                        f"{prob.tets.shape[0]} shell tets, {prob.q_z.size} charges",
+            "fp64_newton": leg_summary(base, 3)}
+    value = side["fp64_newton"]["value"]
     if not args.no_picard:
         # the paper's comparison path: Picard (A Delta = d) with the direct-secant
         # relaxation search and the norm-ratio reuse rule, omega in [0, 1]
@@ -460,14 +604,12 @@ def main():
                      max_newton=200)
         pc = run_leg(pb, torch, prob, pb.FP64, 1, 0, popts, "picard")
         rp = pc["res"]
-        out["picard_fp64"] = {"value": 1.0 / pc["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * pc["elapsed"],
-                              "nonlinear_iters": rp["newton_iters"], "gmres_iters_total": rp["gmres_iters_total"],
-                              "total_kcal_mol": rp["total"],
-                              "rel_energy_diff_vs_newton": abs(rp["total"] - res["total"]) / abs(res["total"]),
-                              "newton_iters": res["newton_iters"], "status": rp["status"]}
+        side["picard_fp64"] = {"value": 1.0 / pc["elapsed"], "unit": "PB solves/s", "ms_per_step": 1e3 * pc["elapsed"],
+                               "nonlinear_iters": rp["newton_iters"], "gmres_iters_total": rp["gmres_iters_total"],
+                               "total_kcal_mol": rp["total"],
+                               "rel_energy_diff_vs_newton": abs(rp["total"] - res["total"]) / abs(res["total"]),
+                               "newton_iters": res["newton_iters"], "status": rp["status"]}
     if not args.no_schemes:
-        # the reaction term raised through Taylor orders over the first
-        # iterations (T3-HS is the default leg above)
         sch = {}
         for label, sched in (("T3-T5-HS", [pb.T3, pb.T5]), ("T3-T5-T7-T7-HS", [pb.T3, pb.T5, pb.T7, pb.T7])):
             lg = run_leg(pb, torch, prob, pb.FP64, 2, 0, dict(opts, schedule=sched), f"schedule {label}",
@@ -479,8 +621,7 @@ def main():
                           "rel_energy_diff_vs_t3_hs": abs(r["total"] - res["total"]) / abs(res["total"]),
                           "status": r["status"]}
         sch["T3-HS"] = {"value": value, "newton_iters": res["newton_iters"], "gmres_iters_total": res["gmres_iters_total"]}
-        out["scheme_schedules_fp64"] = sch
-        # the root finders of f_d for the relaxation factor (Newton is the default leg above)
+        side["scheme_schedules_fp64"] = sch
         om = {}
         for label, m in (("bisection", pb.OMEGA_BISECT), ("secant", pb.OMEGA_SECANT),
                          ("bisection_then_secant", pb.OMEGA_BSEC), ("newton_bisection_secant_start", pb.OMEGA_NEWTON_BS)):
@@ -491,10 +632,12 @@ def main():
                          "omega": r["omega"], "rel_energy_diff_vs_newton": abs(r["total"] - res["total"]) / abs(res["total"]),
                          "status": r["status"]}
         om["newton"] = {"value": value, "newton_iters": res["newton_iters"], "omega": res["omega"]}
-        out["omega_root_finders_fp64"] = om
+        side["omega_root_finders_fp64"] = om
     if not args.no_matrix_free:
         # nothing dense stored: every coupled apply evaluates the regular
-        # quadrature-point pairs again (the same flops as one assembly)
+        # quadrature-point pairs of both interfaces again (k_mf_pot)
+        mf_flops = 36 * (MF_FLOPS_QP["laplace"] * regular_pairs(prob.tri_m) +
+                         MF_FLOPS_QP["yukawa" if prob.kappa > 0 else "laplace"] * regular_pairs(prob.tri_s))
         mf = {}
         for name, prec, peak in (("fp64", pb.FP64, FP64_PEAK_TFLOPS), ("mixed_fp32_eval", pb.MIXED, FP32_PEAK_TFLOPS)):
             if prec == pb.MIXED and args.no_mixed:
@@ -508,16 +651,17 @@ def main():
                         "gmres_iters_total": r["gmres_iters_total"], "coupled_applies": r["applies"],
                         "total_kcal_mol": r["total"],
                         "rel_energy_diff_vs_dense_fp64": abs(r["total"] - res["total"]) / abs(res["total"]),
-                        "bem_apply_ms": ams, "bem_apply_flops": asm_flops,
-                        "tflops": asm_flops / (ams * 1e-3) / 1e12 if ams else None, "peak_tflops": peak,
-                        "frac": asm_flops / (ams * 1e-3) / 1e12 / peak if ams else None, "status": r["status"]}
-        mf["dense_fp64_device_bytes"] = f64["hbm"]
-        out["matrix_free"] = mf
+                        "bem_apply_ms": ams, "bem_apply_flops": mf_flops,
+                        "flops_per_quadrature_pair": MF_FLOPS_QP,
+                        "tflops": mf_flops / (ams * 1e-3) / 1e12 if ams else None, "peak_tflops": peak,
+                        "frac": mf_flops / (ams * 1e-3) / 1e12 / peak if ams else None, "status": r["status"]}
+        mf["dense_fp64_device_bytes"] = base["hbm"]
+        side["matrix_free"] = mf
     if not args.no_two_field:
         # the paper's two-field form on the same surfaces: FEM also fills the
         # solute (three inner copies of Gamma_m, then coarsening layers), the
         # charges load the FEM rows, lambda_m is recovered for the energy
-        ptf = pbgen.make_config(args.config, solute_layers=3)
+        ptf = pbgen.make_config(cfg, solute_layers=3)
         tf = {"solute_tets": int(ptf.n_tets_m), "shell_tets": int(len(ptf.tets) - ptf.n_tets_m)}
         for name, prec in (("fp64", pb.FP64), ("mixed", pb.MIXED)):
             if prec == pb.MIXED and args.no_mixed:
@@ -530,20 +674,8 @@ def main():
                         "energy_with_lambda_m_recovery_ms": lg["energy_ms"],
                         "rel_energy_diff_vs_shell_only_fp64": abs(r["total"] - res["total"]) / abs(res["total"]),
                         "status": r["status"]}
-        out["two_field"] = tf
-    if args.batch > 0:
-        out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
-                          "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}
-    if args.serve > 0:
-        reqs = serve_requests(args.serve, args.serve_nmax)
-        out["serving"] = {"mixed": serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED),
-                          "fp64": serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64)}
-    if not args.no_cpu_baseline:
-        progress("cpu baseline (oracle, bounded sample)")
-        t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(prob, max(applies, 1))
-        progress(f"cpu baseline took {time.perf_counter() - t0:.1f} s")
-    print(json.dumps(out), flush=True)
+        side["two_field"] = tf
+    out["variants"] = side
 
 
 if __name__ == "__main__":

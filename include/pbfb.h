@@ -201,6 +201,7 @@ typedef struct {
     double t_solve_s; /* from the end of setup to the result */
     int applies;      /* coupled-operator applications performed (Krylov steps, restart residuals, Newton residuals
                        * and relaxation-search products) */
+    double t_wait_s;  /* server: from submission to admission (waiting for a slot or for HBM budget); 0 otherwise */
 } pbfb_result;
 
 /* Full solve: linear component Phi_L, Newton on Phi_NL, energy.  phi_out
@@ -226,11 +227,22 @@ pbfb_status pbfb_solve_batch(pbfb_ctx *ctx, int n, pbfb_problem *const *probs, c
  * running set at the next Newton-step boundary and leave it when done.  The
  * problem is borrowed from submit until poll reports done (the caller must
  * not touch it meanwhile and destroys it afterwards); the budget counts a
- * request from admission to completion.  ENOMEM at submit: the request alone
- * exceeds the budget. */
+ * request from admission to completion, plus the context's assembly
+ * workspace (shared by the context's problems, grown to the largest
+ * assembly it has served and kept).  A completed request's device memory is
+ * released (the problem keeps its mesh, charges and parameters; a later call
+ * on it sets it up again), so a finished request holds no budget.  ENOMEM at
+ * submit: the request alone exceeds the budget; otherwise a request that does
+ * not fit waits until running ones complete. */
 typedef struct pbfb_server pbfb_server;
 pbfb_status pbfb_server_create(pbfb_ctx *ctx, size_t hbm_budget_bytes, int max_slots, pbfb_server **out);
 pbfb_status pbfb_server_submit(pbfb_server *s, pbfb_problem *p, const pbfb_solve_opts *o, uint64_t *ticket);
+/* The device bytes the server charges for a request: steady (held from
+ * admission to completion) and setup (the context's assembly workspace the
+ * request's setup needs; charged once per context, see above).  A budget of
+ * at least steady + setup admits the request. */
+pbfb_status pbfb_request_footprint(const pbfb_problem *p, const pbfb_solve_opts *o, size_t *steady_bytes,
+                                   size_t *setup_bytes);
 /* done = 1 once the request finished; res (nullable) then receives its result */
 pbfb_status pbfb_server_poll(pbfb_server *s, uint64_t ticket, int *done, pbfb_result *res);
 /* drains every submitted request, then stops the threads and frees the server;
@@ -253,14 +265,6 @@ pbfb_status pbfb_energy(pbfb_problem *p, const double *phi_lin, const double *ph
  * (PBFB_EINVAL for any other pair) and marks its operators stale.  The shape
  * changes only the order of floating-point sums, never the integrals. */
 pbfb_status pbfb_set_tile_shape(pbfb_problem *p, int ta, int tb);
-/* Cap of the assembly workspace: the expanded tile matrix of the regular
- * assembly is built in chunks of target blocks of at most max_entries
- * entries per operator (0: the default 2^30; at least one block of rows is
- * always taken).  Smaller chunks bound the per-context workspace (which
- * holds three such chunks and the gather buffers) at the cost of more
- * launches; the operators differ only in the order of floating-point sums.
- * Marks the boundary operators stale. */
-pbfb_status pbfb_set_assembly_chunk(pbfb_problem *p, int64_t max_entries);
 /* Shape used by the last assembly of surface `surf` (0 = Gamma_m, 1 =
  * Gamma_s); 0, 0 before the first assembly. */
 pbfb_status pbfb_get_tile_shape(const pbfb_problem *p, int surf, int *ta, int *tb);
@@ -311,6 +315,13 @@ pbfb_status pbfb_set_two_field(pbfb_problem *p, int64_t n_tets_m);
  * In mixed precision the FP32 stored values are widened.  PBFB_ESTATE in
  * matrix-free mode (nothing is stored). */
 pbfb_status pbfb_export_bem(pbfb_problem *p, int surf, double *Vp, double *Kp);
+/* The same blocks for the listed rows only: rows[n_rows] (0-based surface
+ * vertex ids, any order, repeats allowed) and row-major n_rows x n host
+ * arrays Vp, Kp (either may be NULL), row r of each holding row rows[r] of
+ * the block.  For large surfaces, where the full blocks would not fit on the
+ * host.  EINVAL for a row out of range; ESTATE in matrix-free mode. */
+pbfb_status pbfb_export_bem_rows(pbfb_problem *p, int surf, int64_t n_rows, const int64_t *rows, double *Vp,
+                                 double *Kp);
 /* Right-hand side b = [0 | f_m | 0] (host array of length n_unknowns); in
  * the two-field form b = [point-charge load | 0 | 0]. */
 pbfb_status pbfb_export_rhs(pbfb_problem *p, double *b);

@@ -118,6 +118,18 @@ def lib():
     return _lib
 
 
+def set_threads(n):
+    """OpenMP threads of the oracle's parallel loops in this process (the
+    calling thread's setting, which every later oracle call inherits)."""
+    lib()
+    C.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def get_threads():
+    lib()
+    return int(C.CDLL("libgomp.so.1").omp_get_max_threads())
+
+
 def _d(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 

@@ -27,8 +27,8 @@ EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_probl
            "pbfb_set_mesh", "pbfb_set_charges", "pbfb_set_params", "pbfb_get_sizes", "pbfb_setup",
            "pbfb_reset_operators", "pbfb_residual",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
-           "pbfb_server_submit", "pbfb_server_poll", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
-           "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_two_field", "pbfb_set_assembly_chunk", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
+           "pbfb_server_submit", "pbfb_server_poll", "pbfb_request_footprint", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
+           "pbfb_export_bem_rows", "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_two_field", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
 
 
 class PbfbError(RuntimeError):
@@ -54,7 +54,7 @@ class Result(C.Structure):
                 ("dg_omega_i", C.c_double), ("newton_iters", C.c_int), ("gmres_iters_total", C.c_int),
                 ("gmres_lin", C.c_int), ("gmres_iters", C.c_int * 64), ("omega", C.c_double * 64),
                 ("e_k", C.c_double * 64), ("omega_iters", C.c_int * 64), ("t_setup_s", C.c_double),
-                ("t_solve_s", C.c_double), ("applies", C.c_int)]
+                ("t_solve_s", C.c_double), ("applies", C.c_int), ("t_wait_s", C.c_double)]
 
     def as_dict(self):
         k = min(self.newton_iters, 64)
@@ -62,7 +62,7 @@ class Result(C.Structure):
                     newton_iters=self.newton_iters, gmres_iters_total=self.gmres_iters_total,
                     gmres_lin=self.gmres_lin, gmres_iters=list(self.gmres_iters[:k]), omega=list(self.omega[:k]),
                     e_k=list(self.e_k[:k]), omega_iters=list(self.omega_iters[:k]), t_setup_s=self.t_setup_s,
-                    t_solve_s=self.t_solve_s, applies=self.applies)
+                    t_solve_s=self.t_solve_s, applies=self.applies, t_wait_s=self.t_wait_s)
 
 
 _lib = None
@@ -110,11 +110,12 @@ def lib():
         L.pbfb_server_create.argtypes = [P, C.c_size_t, C.c_int, PP]
         L.pbfb_server_submit.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(C.c_uint64)]
         L.pbfb_server_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(Result)]
+        L.pbfb_request_footprint.argtypes = [P, C.POINTER(SolveOpts), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.pbfb_server_destroy.argtypes = [P]
         L.pbfb_export_bem.argtypes = [P, C.c_int, P, P]
+        L.pbfb_export_bem_rows.argtypes = [P, C.c_int, I64, P, P, P]
         L.pbfb_export_rhs.argtypes = [P, P]
         L.pbfb_set_tile_shape.argtypes = [P, C.c_int, C.c_int]
-        L.pbfb_set_assembly_chunk.argtypes = [P, C.c_int64]
         L.pbfb_set_bem_mode.argtypes = [P, C.c_int]
         L.pbfb_set_two_field.argtypes = [P, C.c_int64]
         L.pbfb_get_tile_shape.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -353,6 +354,22 @@ class Problem:
         _check(lib().pbfb_export_bem(self.h, surf, Vp.ctypes.data, Kp.ctypes.data))
         return Vp, Kp
 
+    def footprint(self, **opts):
+        """(steady, setup) device bytes a server charges for solving this problem."""
+        o = default_opts(**opts)
+        a, b = C.c_size_t(), C.c_size_t()
+        _check(lib().pbfb_request_footprint(self.h, C.byref(o), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def export_bem_rows(self, surf, rows):
+        """Rows `rows` of the stored blocks (V', K') of surface `surf`."""
+        nv = self.n_m if surf == 0 else self.n_s
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        Vp = np.zeros((rows.size, nv))
+        Kp = np.zeros((rows.size, nv))
+        _check(lib().pbfb_export_bem_rows(self.h, surf, rows.size, rows.ctypes.data, Vp.ctypes.data, Kp.ctypes.data))
+        return Vp, Kp
+
     def export_rhs(self):
         b = np.zeros(self.n)
         _check(lib().pbfb_export_rhs(self.h, b.ctypes.data))
@@ -365,10 +382,6 @@ class Problem:
     def set_two_field(self, n_tets_m):
         """Two-field form: the last n_tets_m tets fill the solute (0: shell-only form)."""
         _check(lib().pbfb_set_two_field(self.h, int(n_tets_m)))
-
-    def set_assembly_chunk(self, max_entries=0):
-        """Largest expanded-matrix chunk per operator in entries (0: default 2^30)."""
-        _check(lib().pbfb_set_assembly_chunk(self.h, max_entries))
 
     def set_tile_shape(self, ta=0, tb=0):
         """Pin the regular-assembly tile shape (ta x tb triangles); 0, 0 = tuned."""

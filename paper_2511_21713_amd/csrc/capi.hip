@@ -154,6 +154,22 @@ void release_all_scratch(Problem &p)
     for (int i = 0; i < SCR_N; ++i) release_scratch(p, i);
 }
 
+void release_device_state(Problem &p)
+{
+    release_all_scratch(p);
+    p.mesh_arena.release();
+    for (int w = 0; w < 2; ++w) {
+        p.bem_arena[w].release();
+        p.surf[w].sides.clear();
+        p.surf[w].tile = -1;
+        p.bem_topo_ready[w] = false;
+        p.bem_ready[w] = false;
+    }
+    p.topo_ready = p.geom_ready = p.val_ready = p.fm_ready = false;
+    p.d_b = nullptr;
+    p.d_q = nullptr;
+}
+
 double *Workspace::doubles(size_t n)
 {
     const size_t want = sizeof(double) * (n ? n : 1);
@@ -161,8 +177,10 @@ double *Workspace::doubles(size_t n)
         if (ptr) PB_HIP(hipFree(ptr));
         ptr = nullptr;
         bytes = 0;
+        held.store(0);
         PB_HIP(hipMalloc(&ptr, want));
         bytes = want;
+        held.store(want);
     }
     return static_cast<double *>(ptr);
 }
@@ -273,6 +291,29 @@ static hipStream_t pick_stream(Problem &p, void *s)
     PB_HIP(hipSetDevice(p.ctx->device));
     p.last_stream = st;
     return st;
+}
+
+// row i (ascending vertex order) of the stored [K' | V'] of surface w, widened
+// to FP64 and put back into the ascending column order (the device stores
+// rows and columns in the Morton vertex order)
+static void copy_bem_row(Problem &p, int w, int64_t i, double *K, double *V)
+{
+    const SurfaceTopo &T = p.topo[w];
+    const int64_t nv = T.nv, ld = bem_ld(nv), k = T.minv[i];
+    std::vector<double> row(ld);
+    if (p.precision == PBFB_MIXED) {
+        std::vector<float> rowf(ld);
+        PB_HIP(hipMemcpy(rowf.data(), static_cast<const float *>(p.surf[w].B) + k * ld, sizeof(float) * ld,
+                         hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < ld; ++j) row[j] = rowf[j];
+    } else {
+        PB_HIP(hipMemcpy(row.data(), static_cast<const double *>(p.surf[w].B) + k * ld, sizeof(double) * ld,
+                         hipMemcpyDeviceToHost));
+    }
+    for (int64_t j = 0; j < nv; ++j) {
+        if (K) K[j] = row[T.minv[j]];
+        if (V) V[j] = row[nv + T.minv[j]];
+    }
 }
 
 // copy an FP64 vector argument to the device if it lives on the host
@@ -642,21 +683,24 @@ pbfb_status pbfb_export_bem(pbfb_problem *pp, int surf, double *V, double *K)
     PB_CHECK(!p.bem_mf, PBFB_ESTATE, "matrix-free mode stores no boundary operator");
     hipStream_t s = pick_stream(p, nullptr);
     ensure_bem(p, surf, s);
-    const int64_t nv = p.topo[surf].nv, ld = bem_ld(nv);
-    std::vector<double> row(ld);
-    std::vector<float> rowf(ld);
-    for (int64_t i = 0; i < nv; ++i) {
-        if (p.precision == PBFB_MIXED) {
-            PB_HIP(hipMemcpy(rowf.data(), static_cast<const float *>(p.surf[surf].B) + i * ld, sizeof(float) * ld,
-                             hipMemcpyDeviceToHost));
-            for (int64_t j = 0; j < ld; ++j) row[j] = rowf[j];
-        } else {
-            PB_HIP(hipMemcpy(row.data(), static_cast<const double *>(p.surf[surf].B) + i * ld, sizeof(double) * ld,
-                             hipMemcpyDeviceToHost));
-        }
-        if (K) std::memcpy(K + i * nv, row.data(), sizeof(double) * nv);
-        if (V) std::memcpy(V + i * nv, row.data() + nv, sizeof(double) * nv);
-    }
+    const int64_t nv = p.topo[surf].nv;
+    for (int64_t i = 0; i < nv; ++i)
+        copy_bem_row(p, surf, i, K ? K + i * nv : nullptr, V ? V + i * nv : nullptr);
+    API_END
+}
+
+pbfb_status pbfb_export_bem_rows(pbfb_problem *pp, int surf, int64_t n_rows, const int64_t *rows, double *V,
+                                 double *K)
+{
+    API_BEGIN
+    PB_CHECK(pp && (surf == 0 || surf == 1) && n_rows >= 0 && (rows || n_rows == 0), PBFB_EINVAL, "bad argument");
+    Problem &p = live(pp);
+    PB_CHECK(!p.bem_mf, PBFB_ESTATE, "matrix-free mode stores no boundary operator");
+    const int64_t nv = p.topo[surf].nv;
+    for (int64_t r = 0; r < n_rows; ++r) PB_CHECK(rows[r] >= 0 && rows[r] < nv, PBFB_EINVAL, "row out of range");
+    hipStream_t s = pick_stream(p, nullptr);
+    ensure_bem(p, surf, s);
+    for (int64_t r = 0; r < n_rows; ++r) copy_bem_row(p, surf, rows[r], K ? K + r * nv : nullptr, V ? V + r * nv : nullptr);
     API_END
 }
 
@@ -707,20 +751,6 @@ pbfb_status pbfb_set_two_field(pbfb_problem *pp, int64_t n_tets_m)
         p.ntet_m = n_tets_m;
         p.val_ready = false; // permittivity per tet and the Gamma_m coupling
         p.fm_ready = false;  // the load
-    }
-    API_END
-}
-
-pbfb_status pbfb_set_assembly_chunk(pbfb_problem *pp, int64_t max_entries)
-{
-    API_BEGIN
-    PB_CHECK(pp, PBFB_EINVAL, "null problem");
-    PB_CHECK(max_entries >= 0, PBFB_EINVAL, "max_entries must be >= 0");
-    Problem &p = live(pp);
-    const int64_t v = max_entries == 0 ? (int64_t(1) << 30) : max_entries;
-    if (v != p.asm_chunk) {
-        p.asm_chunk = v;
-        p.bem_ready[0] = p.bem_ready[1] = false;
     }
     API_END
 }

@@ -1,5 +1,5 @@
-// Dense Galerkin GEMV rows: y[r] = sum_c B[r][c] x[c] for the rows owned by
-// one wavefront.  B is a surface operator [K' | V'] stored row-major with a
+// Dense Galerkin GEMV rows: y[oidx[r]] = sum_c B[r][c] x[c] for the rows owned
+// by one wavefront (oidx: the output position of operator row r).  B is a surface operator [K' | V'] stored row-major with a
 // padded row length ld (a multiple of 256 entries, zero past 2n); x is the
 // packed FP64 input of the same length.  A wavefront owns RW consecutive
 // rows and streams them with 16-byte non-temporal loads (the operator is
@@ -27,7 +27,7 @@ constexpr int GEMV_RW = 4; // rows per wavefront
 
 template <typename MT>
 __device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
-                                 int64_t n, int64_t ld, int64_t r0, int lane)
+                                 const int32_t *__restrict__ oidx, int64_t n, int64_t ld, int64_t r0, int lane)
 {
     constexpr int RW = GEMV_RW;
     double acc[RW];
@@ -76,7 +76,7 @@ __device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restr
 #pragma unroll
         for (int r = 1; r < RW; ++r)
             if (lane == r) v = acc[r];
-        y[r0 + lane] = v;
+        y[oidx[r0 + lane]] = v;
     }
 }
 
@@ -102,7 +102,8 @@ template <typename MT> using sym_part_t = double;
 
 template <typename MT>
 __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
-                                     sym_part_t<MT> *__restrict__ P, int64_t n, int64_t ld, int64_t r0, int tid)
+                                     const int32_t *__restrict__ oidx, sym_part_t<MT> *__restrict__ P, int64_t n,
+                                     int64_t ld, int64_t r0, int tid)
 {
     using PT = sym_part_t<MT>;
     constexpr int RW = GEMV_RW;
@@ -225,7 +226,7 @@ __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__r
 #pragma unroll
         for (int r = 1; r < RW; ++r)
             if (lane == r) v = acc[r];
-        y[rw + lane] = v;
+        y[oidx[rw + lane]] = v;
     }
 }
 
@@ -237,7 +238,8 @@ constexpr int GFIN_ROWS = 32, GFIN_NY = 256 / GFIN_ROWS;
 template <typename PT>
 __device__ inline void gemv_sym_finish(int64_t n, const PT *__restrict__ P, const int32_t *__restrict__ dptr,
                                        const int32_t *__restrict__ dcol, const double *__restrict__ dval,
-                                       const double *__restrict__ x, double *__restrict__ y, int64_t i0, int tid)
+                                       const double *__restrict__ x, double *__restrict__ y,
+                                       const int32_t *__restrict__ oidx, int64_t i0, int tid)
 {
     __shared__ double red[GFIN_NY][GFIN_ROWS];
     const int tx = tid % GFIN_ROWS, ty = tid / GFIN_ROWS;
@@ -255,7 +257,7 @@ __device__ inline void gemv_sym_finish(int64_t n, const PT *__restrict__ P, cons
 #pragma unroll
         for (int k = 1; k < GFIN_NY; ++k) t += red[k][tx];
         for (int32_t e = dptr[i]; e < dptr[i + 1]; ++e) t = fma(dval[e], x[n + dcol[e]], t);
-        y[i] += t;
+        y[oidx[i]] += t;
     }
 }
 

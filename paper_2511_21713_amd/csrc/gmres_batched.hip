@@ -48,7 +48,9 @@ struct GDesc {
     void *symP[2]; // FP64 column partials
     const int32_t *dl_ptr[2], *dl_col[2];
     const double *dl_val[2];
-    const int32_t *gm, *gs;
+    // packing maps: operator index -> FEM node, and -> surface vertex (Morton
+    // vertex order of the stored operators; matrix-free: ascending, mv null)
+    const int32_t *gm, *gs, *mvm, *mvs;
     const int32_t *sptr, *col; // FEM rows, sliced ELL
     const void *val;
     int64_t nn, n;
@@ -116,13 +118,13 @@ __global__ void __launch_bounds__(256) k_bpack(const WItem *__restrict__ wl, con
         } else if (k < d.ldm) {
             double v = 0.0;
             if (k < d.nm) v = in(d.gm[k]);
-            else if (k < 2 * d.nm) v = in(d.nn + (k - d.nm));
+            else if (k < 2 * d.nm) v = in(d.nn + (d.mvm ? d.mvm[k - d.nm] : k - d.nm));
             d.xm[k] = v;
         }
         if (k < d.lds) {
             double v = 0.0;
             if (k < d.ns) v = in(d.gs[k]);
-            else if (k < 2 * d.ns) v = in(d.nn + d.nm + (k - d.ns));
+            else if (k < 2 * d.ns) v = in(d.nn + d.nm + (d.mvs ? d.mvs[k - d.ns] : k - d.ns));
             d.xs[k] = v;
         }
     }
@@ -238,10 +240,11 @@ __global__ void __launch_bounds__(256, 4) k_bgemv(const WItem *__restrict__ wl, 
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
     const MT *B = static_cast<const MT *>(it.a == 0 ? d.Bm : d.Bs);
     if (d.symm[it.a]) {
-        gemv_rows_sym<MT>(B, x, y, static_cast<sym_part_t<MT> *>(d.symP[it.a]), n, ld, it.b, threadIdx.x);
+        gemv_rows_sym<MT>(B, x, y, it.a == 0 ? d.mvm : d.mvs, static_cast<sym_part_t<MT> *>(d.symP[it.a]), n, ld,
+                          it.b, threadIdx.x);
     } else {
         const int64_t r0 = it.b + wv * GEMV_RW;
-        if (r0 < n) gemv_rows<MT>(B, x, y, n, ld, r0, lane);
+        if (r0 < n) gemv_rows<MT>(B, x, y, it.a == 0 ? d.mvm : d.mvs, n, ld, r0, lane);
     }
 }
 
@@ -257,6 +260,7 @@ __global__ void __launch_bounds__(256) k_bgemv_fin(const WItem *__restrict__ wl,
     const double *x = it.a == 0 ? d.xm : d.xs;
     double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
     gemv_sym_finish(n, static_cast<const double *>(d.symP[it.a]), d.dl_ptr[it.a], d.dl_col[it.a], d.dl_val[it.a], x, y,
+                    it.a == 0 ? d.mvm : d.mvs,
                     it.b, threadIdx.x);
 }
 
@@ -633,8 +637,10 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         d.f32 = p.precision == PBFB_MIXED;
         d.mf = p.bem_mf ? 1 : 0;
         d.two_field = p.two_field() ? 1 : 0;
-        d.gm = p.surf[0].g;
-        d.gs = p.surf[1].g;
+        d.gm = p.bem_mf ? p.surf[0].g : p.surf[0].gmv;
+        d.gs = p.bem_mf ? p.surf[1].g : p.surf[1].gmv;
+        d.mvm = p.bem_mf ? nullptr : p.surf[0].mvert;
+        d.mvs = p.bem_mf ? nullptr : p.surf[1].mvert;
         d.sptr = p.d_sptr;
         d.col = p.d_col;
         d.val = d.f32 ? static_cast<const void *>(p.d_val32) : static_cast<const void *>(p.d_val);

@@ -6,19 +6,23 @@
 //   Gamma_s: K' = 1/2 M - Kk,  V' = +Vk   (exterior Yukawa equation)
 // so the Galerkin rows of the coupled operator are one dense GEMV each.
 //
-// Assembly, deterministic and free of atomics:
+// Rows and columns follow the Morton vertex order (first appearance along
+// the Morton-ordered triangles; SurfaceTopo::mvert), so the vertices of a
+// block of consecutive triangles are nearby rows and columns.
+//
+// Assembly, deterministic and free of atomics, straight into that storage:
 //  1. regular tiles: a workgroup takes TA target x TB source Morton-ordered
 //     triangles (shape chosen by an autotuner), evaluates the 6 x 6 product
 //     rule for every non-touching pair, reduces the 3x3 pair blocks to the
-//     block's local vertex tile in LDS and stores it in an expanded matrix E
-//     whose rows are (target block, local vertex) and whose columns are
-//     (source block, local vertex).  Square shapes evaluate each unordered
-//     pair once (tiles with source block >= target block) and also store the
-//     double layer of the mirrored pair;
-//  2. two coalesced gather passes fold the duplicated rows and columns of E
-//     back onto surface vertices (square shapes: the mirrored double layer
-//     into an N_v x N_v matrix, then a transpose-add completes V and K, with
-//     the regular part of V bitwise symmetric);
+//     blocks' vertices in LDS and adds the result into the stored operator.
+//     The triangle blocks are coloured so that blocks of one colour share no
+//     vertex; one launch per colour pair then has tiles that touch disjoint
+//     entries, and the launches run one after the other, so every entry
+//     receives its contributions in a fixed order.  Square shapes evaluate
+//     each unordered pair once and also add the double layer of the
+//     mirrored pair to an nv x nv matrix T (the only workspace);
+//  2. square shapes: a transpose pass completes V' = U + U^T and K' += T^T
+//     (the regular part of V' bitwise symmetric);
 //  3. touching pairs (identical, common edge, common vertex) are integrated
 //     with the Sauter-Schwab rules (one wavefront per pair) and added, with
 //     the 1/2 M term, by a row-owned scatter.
@@ -28,9 +32,10 @@
 // the centroid difference of a pair is formed in FP64 and rounded once, so
 // x - y never cancels large coordinates in FP32.  The 6-term sums over the
 // source points of a pair are FP32; everything from the pair's 3x3 blocks
-// upward (vertex tiles, gathers, the 1/2 M term) accumulates in FP64, and the
-// touching pairs stay FP64 throughout.  The result is rounded to FP32 once
-// for storage.
+// upward (the pair blocks and their fold onto a tile's vertices) accumulates
+// in FP64, and the touching pairs stay FP64 throughout; each tile's sum is
+// added to the FP32 stored entry in FP64 and rounded (an entry receives one
+// tile's sum for each pair of blocks holding its two vertices).
 #include <cmath>
 #include <type_traits>
 
@@ -95,19 +100,31 @@ __global__ void k_tri_morton(int64_t nt, const int32_t *__restrict__ morton, con
 // ---------------------------------------------------------------------------
 
 
-// Fold of a tile's pair blocks onto the block's vertices through the shared
-// tile (FP32 evaluation: one operator at a time, half the LDS of the paired
-// fold below, so more workgroups per CU), V then K: first the source corners of each source vertex (in place,
-// row by row), then the target corners of each target vertex.  A thread owns
-// one source vertex jb and a strided set of rows; the corner lists are read
-// once into registers and every tile read is independent (an absent corner
-// reads the zero row / column), so the reads pipeline.  MS >= the largest
-// number of corners of any vertex of either block: the lists past it hold
-// only absent corners, whose +0 terms are skipped.
-template <int TA, int TB, int MS>
-__device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
-                                     const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Xl,
-                                     double *__restrict__ E, int64_t row0, int64_t pB, int64_t ldE)
+// Read-modify-write of one folded operator entry into the stored operator
+// (FP64 or FP32 storage; the sum is formed in FP64 and rounded once).  No
+// other thread of the launch touches the same entry (the launch's tiles have
+// vertex-disjoint target blocks and vertex-disjoint source blocks).
+template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int64_t at, double v)
+{
+    U[at] = MT(double(U[at]) + v);
+}
+
+// Fold of a tile's pair blocks onto the blocks' vertices through the shared
+// tile (one operator; FP32 evaluation folds V then K one at a time in half
+// the LDS of the paired fold below, so more workgroups fit per CU): first
+// the source corners of each source vertex (in place, row by row), then the
+// target corners of each target vertex, added into U at row vA[ia], column
+// off + vB[jb] with factor sc.  A thread owns one source vertex jb and a
+// strided set of rows; the corner lists are read once into registers and
+// every tile read is independent (an absent corner reads the zero row /
+// column), so the reads pipeline.  MS >= the largest number of corners of
+// any vertex of either block: the lists past it hold only absent corners,
+// whose +0 terms are skipped.
+template <int TA, int TB, int MS, typename MT>
+__device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
+                                     const int (*sSb)[MS], double (*acc)[TB * 3 + 1], const double *Xl,
+                                     const int *vA, const int *vB, MT *__restrict__ U, int64_t ld, int64_t off,
+                                     double sc)
 {
     constexpr int NT = TA * TB;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -151,7 +168,8 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
         for (int r = 0; r < RPT; ++r)
             if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
     __syncthreads();
-    if (colthread)
+    if (colthread) {
+        const int64_t col = off + vB[jb];
         for (int ia = r0; ia < nA; ia += rstep) {
             double v[MS];
 #pragma unroll
@@ -162,38 +180,23 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
             double t = 0.0;
 #pragma unroll
             for (int k = 0; k < MS; ++k) t += v[k];
-            E[(row0 + ia) * ldE + pB + jb] = t;
+            add_entry(U, int64_t(vA[ia]) * ld + col, sc * t);
         }
+    }
     __syncthreads();
 }
 
-template <int TA, int TB, int MS>
-__device__ inline void fold_tile_single(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
-                                        const int (*sSb)[MAXS], double (*acc)[TB * 3 + 1], const double *Vl,
-                                        const double *Kl, double *__restrict__ EV, double *__restrict__ EK,
-                                        int64_t row0, int64_t pB, int64_t ldE)
-{
-    fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, EV, row0, pB, ldE);
-    fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Kl, EK, row0, pB, ldE);
-}
-
-// Fold of a tile's pair blocks onto the block's vertices through the shared
-// tile (FP64 evaluation), V and K together (each tile entry holds both, so one address and one
-// 16-byte LDS access serve the two operators): first the source corners of
-// each source vertex (in place, row by row), then the target corners of each
-// target vertex.  A thread owns one source vertex jb and a strided set of
-// rows; the corner lists are read once into registers and every tile read is
-// independent (an absent corner reads the zero row / column), so the reads
-// pipeline.  MS >= the largest number of corners of any vertex of either
-// block: the lists past it hold only absent corners, whose +0 terms are
-// skipped.
+// Fold of a tile's pair blocks (FP64 evaluation), V and K together: each
+// tile entry holds both, so one address and one 16-byte LDS access serve the
+// two operators; then V goes to column nv + vB[jb] with factor sV and K to
+// column vB[jb] with factor sK of row vA[ia].  Otherwise as fold_tile_one.
 typedef double dpair __attribute__((ext_vector_type(2))); // (V, K)
 
-template <int TA, int TB, int MS>
-__device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MAXS],
-                                      const int (*sSb)[MAXS], dpair (*acc)[TB * 3 + 1], const double *Vl,
-                                 const double *Kl, double *__restrict__ EV, double *__restrict__ EK, int64_t row0,
-                                 int64_t pB, int64_t ldE)
+template <int TA, int TB, int MS, typename MT>
+__device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
+                                      const int (*sSb)[MS], dpair (*acc)[TB * 3 + 1], const double *Vl,
+                                      const double *Kl, const int *vA, const int *vB, MT *__restrict__ U, int64_t ld,
+                                      int64_t nv, double sV, double sK)
 {
     constexpr int NT = TA * TB;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -243,7 +246,8 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
                 if (r < nrow) acc[r0 + (rb + r) * rstep][jb] = colsum[r];
         __syncthreads();
     }
-    if (colthread)
+    if (colthread) {
+        const int64_t col = vB[jb];
         for (int ia = r0; ia < nA; ia += rstep) {
             dpair v[MS];
 #pragma unroll
@@ -254,40 +258,49 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
             dpair t = zero;
 #pragma unroll
             for (int k = 0; k < MS; ++k) t += v[k];
-            const int64_t at = (row0 + ia) * ldE + pB + jb;
-            EV[at] = t.x;
-            EK[at] = t.y;
+            const int64_t row = int64_t(vA[ia]) * ld;
+            add_entry(U, row + nv + col, sV * t.x);
+            add_entry(U, row + col, sK * t.y);
         }
+    }
 }
 
 // RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
+// MT: storage of the operator (double, or float in mixed precision)
 // TA x TB: target x source triangles of the tile, one pair per thread; MS:
-// bound on the corners of one vertex in one block (6 for meshes of vertex
-// valence <= 6, else MAXS).
-// SYM (square tiles): each unordered pair is evaluated once.  Only tiles
-// with source block >= target block run, and in a diagonal tile only pairs
-// with the source after the target.  Besides V and K of (tau, sigma) a pair
-// also yields K of (sigma, tau): the kernel values are shared, only the
-// normal distance changes ((y_q - x).n_tau, the same for the six target
-// points, which lie in the plane of tau).  It is stored transposed, as
-// Kt[a][b] = K_{sigma tau}[b][a], in EKt with the layout of EK; V of
-// (sigma, tau) is the transpose of V of (tau, sigma).  The gather then
-// completes the operator: V = U_V + U_V^T, K = U_K + U_Kt^T.
-template <bool YUK, typename RT, int TA, int TB, int MS, bool SYM>
+// bound on the corners of one vertex in one block (6, 12 or MAXS).  The
+// tile of workgroup (x, y) is target block listA[y] x source block listB[x]
+// (skip_lower: tiles whose source block precedes the target block return).
+// The tile's V and K blocks are folded onto its vertices and added into the
+// stored operator U (rows: [K' | V'] in the Morton vertex order, sK K and sV
+// V) -- the launch's tiles touch disjoint entries, see BlockSide.
+// SYM (square tiles): each unordered pair is evaluated once (the launches
+// cover each unordered block pair once, in either orientation, and a
+// diagonal tile only its pairs with the source after the target).  Besides
+// V and K of (tau, sigma) a pair also yields K of (sigma, tau): the kernel
+// values are shared, only the normal distance changes ((y_q - x).n_tau, the
+// same for the six target points, which lie in the plane of tau).  It is
+// added, transposed, to T (nv x nv: T[i][j] collects sK K(j, i)); V of
+// (sigma, tau) is the transpose of V of (tau, sigma).  k_bem_symm then
+// completes the operator: V' = U_V + U_V^T, K' = U_K + T^T.
+template <bool YUK, typename RT, typename MT, int TA, int TB, int MS, bool SYM>
 __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)))
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
-                  const int32_t *__restrict__ A_slots, const int32_t *__restrict__ B_pref,
-                  const int32_t *__restrict__ B_nv, const int32_t *__restrict__ B_slots, int64_t bA0,
-                  int64_t rowbase, double *__restrict__ EV, double *__restrict__ EK, double *__restrict__ EKt,
-                  int64_t ldE, double kappa, QRule6 R, QRule6F RF)
+                  const int32_t *__restrict__ A_slots, const int32_t *__restrict__ A_vid,
+                  const int32_t *__restrict__ B_pref, const int32_t *__restrict__ B_nv,
+                  const int32_t *__restrict__ B_slots, const int32_t *__restrict__ B_vid,
+                  const int32_t *__restrict__ listA, const int32_t *__restrict__ listB, int skip_lower,
+                  MT *__restrict__ U, MT *__restrict__ T, int64_t ld, int64_t nv, double sV, double sK,
+                  double kappa, QRule6 R, QRule6F RF)
 {
     static_assert(!SYM || TA == TB, "symmetric evaluation needs square tiles");
     constexpr bool F32 = sizeof(RT) == 4;
     constexpr int NT = TA * TB;
-    if (SYM && int64_t(blockIdx.x) < bA0 + int64_t(blockIdx.y)) return; // lower tile: from its mirror
+    const int64_t bA = listA[blockIdx.y], bB = listB[blockIdx.x];
+    if (SYM && skip_lower && bB < bA) return; // evaluated as (bB, bA)
     __shared__ RT sX[TA][18];
     __shared__ RT sY[TB][18];
     __shared__ RT sN[TB][3];
@@ -295,13 +308,12 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ double sCa[F32 ? TA : 1][3], sCb[F32 ? TB : 1][3];
     __shared__ double sAa[TA], sAb[TB];
     __shared__ int sVa[TA][3], sVb[TB][3];
-    __shared__ int sSa[TA * 3][MAXS], sSb[TB * 3][MAXS];
+    __shared__ int sSa[TA * 3][MS], sSb[TB * 3][MS];
+    __shared__ int sIa[TA * 3], sIb[TB * 3]; // operator index of each block vertex
     // the tile: (V, K) pairs (FP64) or one operator at a time (FP32); + a zero row and a zero column
     __shared__ std::conditional_t<F32, double, dpair> acc[TA * 3 + 1][TB * 3 + 1];
 
     const int tid = threadIdx.x;
-    const int64_t bB = blockIdx.x;
-    const int64_t bA = bA0 + blockIdx.y;
     const int nA = A_nv[bA], nB = B_nv[bB];
     const int64_t pA = A_pref[bA], pB = B_pref[bB];
 
@@ -321,6 +333,7 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
         sN[sl][c] = m < nt ? nq[3 * m + c] : RT(0);
         sVb[sl][c] = m < nt ? m_tri[3 * m + c] : -1;
         if constexpr (F32) sCb[sl][c] = m < nt ? cen[3 * m + c] : 0.0;
+        sIb[tid] = tid < nB ? B_vid[pB + tid] : 0;
     }
     if (tid < TA * 3) {
         int tl = tid / 3, c = tid % 3;
@@ -328,15 +341,16 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
         sVa[tl][c] = m < nt ? m_tri[3 * m + c] : -2;
         if constexpr (F32) sCa[tl][c] = m < nt ? cen[3 * m + c] : 0.0;
         if constexpr (SYM) sNa[tl][c] = m < nt ? nq[3 * m + c] : RT(0);
+        sIa[tid] = tid < nA ? A_vid[pA + tid] : 0;
     }
     if (tid < TA) sAa[tid] = (bA * TA + tid) < nt ? m_area[bA * TA + tid] : 0.0;
     if (tid < TB) sAb[tid] = (bB * TB + tid) < nt ? m_area[bB * TB + tid] : 0.0;
-    for (int k = tid; k < TA * 3 * MAXS; k += NT) {
-        int r = k / MAXS, c = k % MAXS;
+    for (int k = tid; k < TA * 3 * MS; k += NT) {
+        int r = k / MS, c = k % MS;
         sSa[r][c] = r < nA ? A_slots[(pA + r) * MAXS + c] : -1;
     }
-    for (int k = tid; k < TB * 3 * MAXS; k += NT) {
-        int r = k / MAXS, c = k % MAXS;
+    for (int k = tid; k < TB * 3 * MS; k += NT) {
+        int r = k / MS, c = k % MS;
         sSb[r][c] = r < nB ? B_slots[(pB + r) * MAXS + c] : -1;
     }
     __syncthreads();
@@ -442,117 +456,29 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
         }
     }
 
-    if constexpr (F32) fold_tile_single<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
-    else fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, EV, EK, pA - rowbase, pB, ldE);
+    if constexpr (F32) {
+        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, sIa, sIb, U, ld, nv, sV);
+        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Kl, sIa, sIb, U, ld, 0, sK);
+    } else {
+        fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, sIa, sIb, U, ld, nv, sV, sK);
+    }
     if constexpr (SYM) {
         __syncthreads();
         fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, reinterpret_cast<double (*)[TB * 3 + 1]>(acc), Ktl,
-                                  EKt, pA - rowbase, pB, ldE);
+                                  sIa, sIb, T, nv, 0, sK);
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2. gather passes
+// 2. completion of a symmetric evaluation
 // ---------------------------------------------------------------------------
-// W[i][c] (+)= sum of E rows of vertex i that belong to target blocks [bA0, bA1).
-// Symmetric evaluation (c_blk non-null): only E entries of tiles whose source
-// block (that of column c) is not below the target block were written, and
-// EKt / WKt carry the third operator.
-__global__ void k_bem_pass1(int64_t nv, int64_t SB, const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA,
-                            const int32_t *__restrict__ LA_blk, int64_t bA0, int64_t bA1, int64_t rowbase,
-                            const double *__restrict__ EV, const double *__restrict__ EK,
-                            const double *__restrict__ EKt, const int32_t *__restrict__ c_blk,
-                            double *__restrict__ WV, double *__restrict__ WK, double *__restrict__ WKt, int first)
-{
-    const int64_t i = blockIdx.y;
-    const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (c >= SB) return;
-    const int32_t cb = c_blk ? c_blk[c] : INT32_MAX;
-    if (c_blk) { // a column below every block of vertex i never receives anything: left unwritten
-        int32_t bmin = INT32_MAX;
-        for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) bmin = min(bmin, LA_blk[e]);
-        if (cb < bmin) return;
-    }
-    double sv = 0.0, sk = 0.0, st = 0.0;
-    bool any = false;
-    for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) {
-        const int32_t b = LA_blk[e];
-        if (b < bA0 || b >= bA1 || b > cb) continue;
-        const int64_t r = LA[e] - rowbase;
-        sv += EV[r * SB + c];
-        sk += EK[r * SB + c];
-        if (c_blk) st += EKt[r * SB + c];
-        any = true;
-    }
-    if (first) {
-        WV[i * SB + c] = sv;
-        WK[i * SB + c] = sk;
-        if (c_blk) WKt[i * SB + c] = st;
-    } else if (any) {
-        WV[i * SB + c] += sv;
-        WK[i * SB + c] += sk;
-        if (c_blk) WKt[i * SB + c] += st;
-    }
-}
-
-// smallest target block holding vertex i (symmetric evaluation: W[i][c] is
-// written only for columns c of blocks not below it)
-__device__ inline int32_t row_bmin(const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA_blk,
-                                   int64_t i)
-{
-    int32_t bmin = INT32_MAX;
-    for (int32_t e = LA_ptr[i]; e < LA_ptr[i + 1]; ++e) bmin = min(bmin, LA_blk[e]);
-    return bmin;
-}
-
-// B64[i][j] = sK * sum W_K[i][cols of j],  B64[i][nv + j] = sV * sum W_V[i][cols of j]
-// (c_blk non-null: symmetric evaluation, columns below row i's blocks skipped)
-__global__ void k_bem_pass2(int64_t nv, int64_t SB, int64_t ld, const int32_t *__restrict__ LB_ptr,
-                            const int32_t *__restrict__ LB, const int32_t *__restrict__ c_blk,
-                            const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA_blk,
-                            const double *__restrict__ WV, const double *__restrict__ WK, double sV, double sK,
-                            double *__restrict__ Bo)
-{
-    const int64_t i = blockIdx.y;
-    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (j >= nv) return;
-    const int32_t bmin = c_blk ? row_bmin(LA_ptr, LA_blk, i) : INT32_MIN;
-    double v = 0.0, k = 0.0;
-    for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) {
-        const int32_t c = LB[e];
-        if (c_blk && c_blk[c] < bmin) continue;
-        v += WV[i * SB + c];
-        k += WK[i * SB + c];
-    }
-    Bo[i * ld + j] = sK * k;
-    Bo[i * ld + nv + j] = sV * v;
-}
-
-// T[i][j] = sc * sum W[i][cols of j] (the mirrored double layer, ld nv;
-// columns below row i's blocks were never written)
-__global__ void k_bem_pass2_one(int64_t nv, int64_t SB, const int32_t *__restrict__ LB_ptr,
-                                const int32_t *__restrict__ LB, const int32_t *__restrict__ c_blk,
-                                const int32_t *__restrict__ LA_ptr, const int32_t *__restrict__ LA_blk,
-                                const double *__restrict__ W, double sc, double *__restrict__ T)
-{
-    const int64_t i = blockIdx.y;
-    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (j >= nv) return;
-    const int32_t bmin = row_bmin(LA_ptr, LA_blk, i);
-    double v = 0.0;
-    for (int32_t e = LB_ptr[j]; e < LB_ptr[j + 1]; ++e) {
-        const int32_t c = LB[e];
-        if (c_blk[c] >= bmin) v += W[i * SB + c];
-    }
-    T[i * nv + j] = sc * v;
-}
-
-// Completion of a symmetric evaluation on 32 x 32 tiles (I <= J, both
-// mirror tiles handled by one workgroup): V(i, j) = U_V(i, j) + U_V(j, i)
-// and K(i, j) = U_K(i, j) + T(j, i), where B holds [U_K | U_V] per row.
+// On 32 x 32 tiles (I <= J, both mirror tiles handled by one workgroup):
+// V'(i, j) = U_V(i, j) + U_V(j, i) and K'(i, j) = U_K(i, j) + T(j, i), where
+// B holds [U_K | U_V] per row (signed; the regular part of V' comes out
+// bitwise symmetric).
 constexpr int SYMT = 32;
-__global__ void __launch_bounds__(256) k_bem_symm(int64_t nv, int64_t ld, double *__restrict__ B,
-                                                  const double *__restrict__ T)
+template <typename MT>
+__global__ void __launch_bounds__(256) k_bem_symm(int64_t nv, int64_t ld, MT *__restrict__ B, const MT *__restrict__ T)
 {
     const int64_t I = blockIdx.y, J = blockIdx.x;
     if (J < I) return;
@@ -562,22 +488,22 @@ __global__ void __launch_bounds__(256) k_bem_symm(int64_t nv, int64_t ld, double
         const int64_t i = I * SYMT + r, j = J * SYMT + tx;   // tile (I, J)
         const int64_t i2 = J * SYMT + r, j2 = I * SYMT + tx; // tile (J, I)
         const bool in1 = i < nv && j < nv, in2 = i2 < nv && j2 < nv;
-        a[r][tx] = in1 ? B[i * ld + nv + j] : 0.0;
-        t2[r][tx] = in1 ? T[i * nv + j] : 0.0;
-        b[r][tx] = in2 ? B[i2 * ld + nv + j2] : 0.0;
-        t1[r][tx] = in2 ? T[i2 * nv + j2] : 0.0;
+        a[r][tx] = in1 ? double(B[i * ld + nv + j]) : 0.0;
+        t2[r][tx] = in1 ? double(T[i * nv + j]) : 0.0;
+        b[r][tx] = in2 ? double(B[i2 * ld + nv + j2]) : 0.0;
+        t1[r][tx] = in2 ? double(T[i2 * nv + j2]) : 0.0;
     }
     __syncthreads();
     for (int r = ty; r < SYMT; r += 256 / SYMT) {
         const int64_t i = I * SYMT + r, j = J * SYMT + tx;
         if (i < nv && j < nv) {
-            B[i * ld + nv + j] = a[r][tx] + b[tx][r];
-            B[i * ld + j] += t1[tx][r];
+            B[i * ld + nv + j] = MT(a[r][tx] + b[tx][r]);
+            add_entry(B, i * ld + j, t1[tx][r]);
         }
         const int64_t i2 = J * SYMT + r, j2 = I * SYMT + tx;
         if (I != J && i2 < nv && j2 < nv) {
-            B[i2 * ld + nv + j2] = b[r][tx] + a[tx][r];
-            B[i2 * ld + j2] += t2[tx][r];
+            B[i2 * ld + nv + j2] = MT(b[r][tx] + a[tx][r]);
+            add_entry(B, i2 * ld + j2, t2[tx][r]);
         }
     }
 }
@@ -739,28 +665,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     }
 }
 
-// Row-owned scatter of the touching-pair blocks and of the 1/2 M term.
-__global__ void k_bem_scatter(int64_t nv, int64_t ld, const int32_t *__restrict__ v2t_ptr,
-                              const int32_t *__restrict__ v2t, const int32_t *__restrict__ tri,
-                              const int32_t *__restrict__ tp_ptr, const int32_t *__restrict__ tp_sig,
-                              const double *__restrict__ tpv, const double *__restrict__ area, double sV, double sK,
-                              double *__restrict__ Bo)
+// Row-owned scatter of the touching-pair blocks and of the 1/2 M term into
+// the stored operator (Morton vertex order: vertex i is row minv[i]).
+template <typename MT>
+__global__ void k_bem_scatter(int64_t nv, int64_t ld, const int32_t *__restrict__ minv,
+                              const int32_t *__restrict__ v2t_ptr, const int32_t *__restrict__ v2t,
+                              const int32_t *__restrict__ tri, const int32_t *__restrict__ tp_ptr,
+                              const int32_t *__restrict__ tp_sig, const double *__restrict__ tpv,
+                              const double *__restrict__ area, double sV, double sK, MT *__restrict__ Bo)
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= nv) return;
-    double *row = Bo + i * ld;
+    MT *row = Bo + int64_t(minv[i]) * ld;
     for (int32_t e = v2t_ptr[i]; e < v2t_ptr[i + 1]; ++e) {
         const int32_t ta = v2t[e] / 3, a = v2t[e] % 3;
         for (int32_t pp = tp_ptr[ta]; pp < tp_ptr[ta + 1]; ++pp) {
             const int32_t sb = tp_sig[pp];
             const double *blk = tpv + 18 * int64_t(pp);
             for (int b = 0; b < 3; ++b) {
-                const int32_t j = tri[3 * sb + b];
-                row[nv + j] += sV * blk[3 * a + b];
-                row[j] += sK * blk[9 + 3 * a + b];
+                const int64_t j = minv[tri[3 * sb + b]];
+                add_entry(row, nv + j, sV * blk[3 * a + b]);
+                add_entry(row, j, sK * blk[9 + 3 * a + b]);
             }
         }
-        for (int b = 0; b < 3; ++b) row[tri[3 * ta + b]] += 0.5 * area[ta] * (a == b ? 2.0 : 1.0) / 12.0;
+        for (int b = 0; b < 3; ++b)
+            add_entry(row, minv[tri[3 * ta + b]], 0.5 * area[ta] * (a == b ? 2.0 : 1.0) / 12.0);
     }
 }
 
@@ -772,13 +701,13 @@ __global__ void k_gather_coords(int64_t nv, const int32_t *__restrict__ g, const
     for (int d = 0; d < 3; ++d) vx[3 * i + d] = x[3 * g[i] + d];
 }
 
-__global__ void k_diag_and_narrow(int64_t nv, int64_t ld, int64_t ld_out, const double *__restrict__ B64,
-                                  double *__restrict__ vdiag, float *__restrict__ B32)
+// diagonal of V' in the ascending vertex order
+template <typename MT>
+__global__ void k_vdiag(int64_t nv, int64_t ld, const int32_t *__restrict__ mvert, const MT *__restrict__ B,
+                        double *__restrict__ vdiag)
 {
-    const int64_t i = blockIdx.y;
-    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (j == 0) vdiag[i] = B64[i * ld + nv + i];
-    if (B32 && j < ld_out) B32[i * ld_out + j] = j < 2 * nv ? float(B64[i * ld + j]) : 0.0f;
+    const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (k < nv) vdiag[mvert[k]] = double(B[k * ld + nv + k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -787,14 +716,15 @@ __global__ void k_diag_and_narrow(int64_t nv, int64_t ld, int64_t ld_out, const 
 constexpr int SPAI_SMALL = 8; // largest 1-ring of the one-wavefront path
 // Row i minimises || m^T V' - e_i^T ||_2 over m supported on the 1-ring P(i)
 // of vertex i, V' = columns [nv, 2nv) of the stored rows (the signed
-// single-layer block of the operator).  Normal equations
+// single-layer block of the operator; vertex v is row / column minv[v]).  Normal equations
 // (V'_P V'_P^T) m = V'_P e_i, solved by Cholesky.  One workgroup per row;
 // the Gram matrix accumulates over 64-column tiles of the rows P staged in
 // LDS, one thread per (a, b) pair, in a fixed order.
 template <typename MT>
 __global__ void __launch_bounds__(256)
-    k_spai(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ ring_ptr,
-           const int32_t *__restrict__ ring, double *__restrict__ val, int *__restrict__ bad)
+    k_spai(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ minv,
+           const int32_t *__restrict__ ring_ptr, const int32_t *__restrict__ ring, double *__restrict__ val,
+           int *__restrict__ bad)
 {
     __shared__ double T[MAXRING][65];
     __shared__ double G[MAXRING][MAXRING + 1];
@@ -804,7 +734,7 @@ __global__ void __launch_bounds__(256)
     const int64_t i = blockIdx.x;
     const int p0 = ring_ptr[i], m = ring_ptr[i + 1] - p0;
     if (m <= SPAI_SMALL) return; // handled by k_spai_small
-    for (int a = tid; a < m; a += 256) P[a] = ring[p0 + a];
+    for (int a = tid; a < m; a += 256) P[a] = minv[ring[p0 + a]];
     __syncthreads();
     const int npair = m * (m + 1) / 2;
     constexpr int PPT = (MAXRING * (MAXRING + 1) / 2 + 255) / 256; // pairs per thread
@@ -840,7 +770,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int q = 0; q < PPT; ++q)
         if (tid + 256 * q < npair) G[pa[q]][pb[q]] = G[pb[q]][pa[q]] = acc[q];
-    for (int a = tid; a < m; a += 256) rhs[a] = double(B[int64_t(P[a]) * ld + nv + i]);
+    for (int a = tid; a < m; a += 256) rhs[a] = double(B[int64_t(P[a]) * ld + nv + minv[i]]);
     __syncthreads();
     if (tid == 0) {
         // Cholesky G = L L^T (lower triangle), then L y = rhs, L^T m = y
@@ -884,8 +814,9 @@ __global__ void __launch_bounds__(256)
 // registers; a fixed xor-shuffle tree then sums them across the lanes.
 template <typename MT>
 __global__ void __launch_bounds__(256)
-    k_spai_small(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ ring_ptr,
-                 const int32_t *__restrict__ ring, double *__restrict__ val, int *__restrict__ bad)
+    k_spai_small(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ minv,
+                 const int32_t *__restrict__ ring_ptr, const int32_t *__restrict__ ring, double *__restrict__ val,
+                 int *__restrict__ bad)
 {
     constexpr int NP = SPAI_SMALL * (SPAI_SMALL + 1) / 2;
     const int lane = threadIdx.x & 63;
@@ -895,7 +826,7 @@ __global__ void __launch_bounds__(256)
     if (m > SPAI_SMALL) return; // handled by k_spai
     const MT *rows[SPAI_SMALL];
 #pragma unroll
-    for (int a = 0; a < SPAI_SMALL; ++a) rows[a] = B + int64_t(ring[p0 + (a < m ? a : 0)]) * ld + nv;
+    for (int a = 0; a < SPAI_SMALL; ++a) rows[a] = B + int64_t(minv[ring[p0 + (a < m ? a : 0)]]) * ld + nv;
     double g[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) g[k] = 0.0;
@@ -916,8 +847,9 @@ __global__ void __launch_bounds__(256)
     // Cholesky in place on the packed lower triangle g[a (a + 1) / 2 + b]
 #define GP(a, b) g[(a) * ((a) + 1) / 2 + (b)]
     double r[SPAI_SMALL];
+    const int64_t ci = minv[i];
 #pragma unroll
-    for (int a = 0; a < SPAI_SMALL; ++a) r[a] = a < m ? double(rows[a][i]) : 0.0;
+    for (int a = 0; a < SPAI_SMALL; ++a) r[a] = a < m ? double(rows[a][ci]) : 0.0;
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < SPAI_SMALL; ++a) {
@@ -968,8 +900,8 @@ __global__ void __launch_bounds__(256)
         if (a < m) val[p0 + a] = r[a];
 }
 
-// Delta_ij = V'_ij - V'_ji on the upper two-ring pattern, from the stored
-// operator (one thread per row)
+// Delta_kl = V'_kl - V'_lk on the upper two-ring pattern of the Morton vertex
+// order, from the stored operator (one thread per row)
 template <typename MT>
 __global__ void k_sym_delta(int64_t nv, int64_t ld, const MT *__restrict__ B, const int32_t *__restrict__ dptr,
                             const int32_t *__restrict__ dcol, double *__restrict__ dval)
@@ -1002,10 +934,11 @@ static const BlockSideDev &device_side(Problem &p, int w, int bs, hipStream_t s)
     D.pref = A.upload(H.pref, s);
     D.nvb = A.upload(H.nvb, s);
     D.slots = A.upload(H.slots, s);
-    D.L_ptr = A.upload(H.L_ptr, s);
-    D.L = A.upload(H.L, s);
-    D.L_blk = A.upload(H.L_blk, s);
-    D.slot_blk = A.upload(H.slot_blk, s);
+    D.vid = A.upload(H.vid, s);
+    // the blocks of each colour, then every block in order (the tuner's lists)
+    std::vector<int32_t> lists(H.col_blk);
+    for (int64_t b = 0; b < H.nb; ++b) lists.push_back(int32_t(b));
+    D.col_blk = A.upload(lists, s);
     return S.sides.emplace(bs, D).first->second;
 }
 
@@ -1015,8 +948,12 @@ struct RegArgs {
     const void *xq = nullptr, *nq = nullptr;
     const double *cen = nullptr, *m_area = nullptr;
     BlockSideDev A, B;
-    int64_t b0 = 0, b1 = 0, rowbase = 0;
-    double *EV = nullptr, *EK = nullptr, *EKt = nullptr; // EKt: square (symmetric) shapes only
+    const int32_t *listA = nullptr, *listB = nullptr; // device block lists of the launch
+    int64_t nA = 0, nB = 0;                            // their lengths
+    int skip_lower = 0;
+    void *U = nullptr, *T = nullptr; // operator rows [K' | V'] and the mirrored double layer (square shapes)
+    int64_t ld = 0, nv = 0;
+    double sV = 0.0, sK = 0.0;
     double kappa = 0.0;
     int ms = MAXS; // largest corner count of a vertex in a block, both sides
     QRule6 R;
@@ -1027,13 +964,15 @@ struct RegArgs {
 template <int TA, int TB> constexpr bool shape_sym() { return TA == TB; }
 template <int TA, int TB, int MS> static void launch_regular_ms(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
 {
-    const dim3 grid(unsigned(a.B.nb), unsigned(a.b1 - a.b0));
+    if (a.nA == 0 || a.nB == 0) return;
+    const dim3 grid(unsigned(a.nB), unsigned(a.nA));
     constexpr bool SYM = shape_sym<TA, TB>();
 #define PB_REG(Y, RT)                                                                                              \
-    hipLaunchKernelGGL((k_bem_regular<Y, RT, TA, TB, MS, SYM>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,          \
+    hipLaunchKernelGGL((k_bem_regular<Y, RT, RT, TA, TB, MS, SYM>), grid, dim3(TA * TB), 0, s, a.nt, a.m_tri,      \
                        static_cast<const RT *>(a.xq), static_cast<const RT *>(a.nq), a.cen, a.m_area, a.A.pref,     \
-                       a.A.nvb, a.A.slots, a.B.pref, a.B.nvb, a.B.slots, a.b0, a.rowbase, a.EV, a.EK, a.EKt,        \
-                       a.B.S, a.kappa, a.R, a.RF)
+                       a.A.nvb, a.A.slots, a.A.vid, a.B.pref, a.B.nvb, a.B.slots, a.B.vid, a.listA, a.listB,        \
+                       a.skip_lower, static_cast<RT *>(a.U), static_cast<RT *>(a.T), a.ld, a.nv, a.sV, a.sK,        \
+                       a.kappa, a.R, a.RF)
     if (f32) {
         if (yuk) PB_REG(true, float);
         else PB_REG(false, float);
@@ -1046,6 +985,7 @@ template <int TA, int TB, int MS> static void launch_regular_ms(bool yuk, bool f
 template <int TA, int TB> static void launch_regular_t(bool yuk, bool f32, const RegArgs &a, hipStream_t s)
 {
     if (a.ms <= 6) launch_regular_ms<TA, TB, 6>(yuk, f32, a, s);
+    else if (a.ms <= 12) launch_regular_ms<TA, TB, 12>(yuk, f32, a, s);
     else launch_regular_ms<TA, TB, MAXS>(yuk, f32, a, s);
 }
 
@@ -1060,6 +1000,29 @@ static void launch_regular(int shape, bool yuk, bool f32, const RegArgs &a, hipS
     case 4: launch_regular_t<TILE_SHAPES[4].ta, TILE_SHAPES[4].tb>(yuk, f32, a, s); break;
     default: PB_CHECK(false, PBFB_EINVAL, "unknown tile shape");
     }
+}
+
+// Every tile of the assembly, one launch per pair of colours so that no two
+// tiles of a launch touch the same operator entry; launches follow each other
+// on the stream, so every entry receives its contributions in a fixed order.
+// Square shapes: launch (c1, c2), c1 < c2, takes every target block of colour
+// c1 against every source block of colour c2 (one orientation per unordered
+// block pair); launch (c, c) the pairs with source block >= target block.
+// Rectangular shapes (target and source blocks coloured separately): every
+// colour pair, every tile.
+static void launch_all_tiles(int shape, bool yuk, bool f32, RegArgs a, const BlockSide &HA, const BlockSide &HB,
+                             hipStream_t s)
+{
+    const bool sym = TILE_SHAPES[shape].ta == TILE_SHAPES[shape].tb;
+    for (int c1 = 0; c1 < HA.ncolor; ++c1)
+        for (int c2 = sym ? c1 : 0; c2 < HB.ncolor; ++c2) {
+            a.listA = a.A.col_blk + HA.col_ptr[c1];
+            a.nA = HA.col_ptr[c1 + 1] - HA.col_ptr[c1];
+            a.listB = a.B.col_blk + HB.col_ptr[c2];
+            a.nB = HB.col_ptr[c2 + 1] - HB.col_ptr[c2];
+            a.skip_lower = sym && c1 == c2 ? 1 : 0;
+            launch_regular(shape, yuk, f32, a, s);
+        }
 }
 
 // cache key of the tuned shape: precision, kernel and size class (floor log2 of the triangle count)
@@ -1085,16 +1048,11 @@ static void tune_range(const BlockSide &HA, int64_t nsample, int64_t &b0, int64_
 }
 static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream_t s)
 {
+    // the timed launches add into the operator and T (a.U, a.T), which are
+    // cleared before the assembly proper; their tiles are not coloured (the
+    // values are discarded, so unordered additions do not matter here)
     SurfaceTopo &T = p.topo[w];
     const int64_t nsample = std::min<int64_t>(T.nt, 512);
-    size_t need = 0;
-    for (int k = 0; k < N_TILE_SHAPES; ++k) {
-        const BlockSide &HA = block_side(T, TILE_SHAPES[k].ta), &HB = block_side(T, TILE_SHAPES[k].tb);
-        int64_t b0, b1;
-        tune_range(HA, nsample, b0, b1);
-        need = std::max(need, size_t(HA.pref[b1] - HA.pref[b0]) * size_t(HB.S) * 3);
-    }
-    double *E = p.ctx->asm_ws.doubles(need);
     hipEvent_t e0, e1;
     PB_HIP(hipEventCreate(&e0));
     PB_HIP(hipEventCreate(&e1));
@@ -1105,13 +1063,14 @@ static int tile_tune(Problem &p, int w, RegArgs a, bool yuk, bool f32, hipStream
         a.A = device_side(p, w, HA.bs, s);
         a.B = device_side(p, w, HB.bs, s);
         a.ms = std::max(HA.ms_max, HB.ms_max);
-        tune_range(HA, nsample, a.b0, a.b1);
-        a.rowbase = HA.pref[a.b0];
-        const size_t nEs = size_t(HA.pref[a.b1] - HA.pref[a.b0]) * size_t(HB.S);
-        a.EV = E;
-        a.EK = E + nEs;
-        a.EKt = E + 2 * nEs;
-        const int64_t tris = std::min<int64_t>(a.b1 * HA.bs, T.nt) - a.b0 * HA.bs;
+        int64_t b0, b1;
+        tune_range(HA, nsample, b0, b1);
+        a.listA = a.A.col_blk + HA.nb + b0; // blocks b0 .. b1 - 1 of the in-order list
+        a.nA = b1 - b0;
+        a.listB = a.B.col_blk + HB.nb;
+        a.nB = HB.nb;
+        a.skip_lower = TILE_SHAPES[k].ta == TILE_SHAPES[k].tb ? 1 : 0;
+        const int64_t tris = std::min<int64_t>(b1 * HA.bs, T.nt) - b0 * HA.bs;
         launch_regular(k, yuk, f32, a, s);
         float ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1216,9 +1175,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, S.morton, S.tri, S.qp, S.nrm,
                        S.area, S.g, p.d_x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
 
-    // the context's assembly workspace: E (V, K), W (V, K), FP64 staging
-    // (mixed precision assembles in FP64 and narrows at the end; FP64 storage
-    // assembles in place), vertex coordinates and touching-pair blocks
+    // the context's assembly workspace (see below) is used by one assembly at a time
     std::lock_guard<std::mutex> ws_lock(p.ctx->asm_ws.mu);
     struct Drain { // on every exit the stream drains before the workspace is released
         hipStream_t s;
@@ -1245,6 +1202,9 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         p.bem_ready[w] = true;
         return;
     }
+    const int64_t nv = T.nv, ld = bem_ld(nv);
+    const size_t elem = f32 ? sizeof(float) : sizeof(double);
+    const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
     RegArgs ra;
     ra.nt = T.nt;
     ra.m_tri = S.m_tri;
@@ -1255,6 +1215,19 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     ra.kappa = kappa;
     ra.R = q6arg();
     ra.RF = q6farg();
+    ra.U = S.B;
+    ra.ld = ld;
+    ra.nv = nv;
+    ra.sV = sV;
+    ra.sK = sK;
+    // the context's assembly workspace: the mirrored double layer T of a
+    // square-tile assembly (nv x nv in the storage precision), vertex
+    // coordinates and the touching-pair blocks
+    const size_t tbytes = (size_t(nv) * nv * elem + 255) / 256 * 256;
+    double *ws = p.ctx->asm_ws.doubles((tbytes + 8 * (3 * size_t(nv) + 18 * size_t(S.ntp))) / 8 + 1);
+    void *Tm = ws;
+    double *vx = reinterpret_cast<double *>(static_cast<char *>(Tm) + tbytes), *tpv = vx + 3 * nv;
+    ra.T = Tm;
     // tile shape: forced, or tuned once per (precision, kernel, size class) and context
     int shape = p.tile_fixed;
     if (shape < 0) {
@@ -1268,74 +1241,27 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         }
     }
     S.tile = shape;
-    const BlockSide &HA = block_side(T, TILE_SHAPES[shape].ta);
-    const BlockSideDev &DA = device_side(p, w, TILE_SHAPES[shape].ta, s);
-    const BlockSideDev &DB = device_side(p, w, TILE_SHAPES[shape].tb, s);
-    ra.A = DA;
-    ra.B = DB;
-    ra.ms = std::max(HA.ms_max, block_side(T, TILE_SHAPES[shape].tb).ms_max);
-
-    const int64_t nv = T.nv, ld = bem_ld(nv);
-    // chunks of target blocks, so that E stays within p.asm_chunk entries per
-    // operator (2^30 unless capped; at least one block of rows)
-    const int64_t max_rows = std::max<int64_t>(3 * HA.bs, p.asm_chunk / std::max<int64_t>(DB.S, 1));
-    std::vector<std::pair<int64_t, int64_t>> chunks;
-    int64_t chunk_rows = 0;
-    for (int64_t b0 = 0; b0 < HA.nb;) {
-        int64_t b1 = b0;
-        while (b1 < HA.nb && HA.pref[b1 + 1] - HA.pref[b0] <= max_rows) ++b1;
-        if (b1 == b0) b1 = b0 + 1;
-        chunks.push_back({b0, b1});
-        chunk_rows = std::max<int64_t>(chunk_rows, HA.pref[b1] - HA.pref[b0]);
-        b0 = b1;
-    }
-    const bool stage64 = f32;
-    // square shapes evaluate each unordered pair once: a third operator
-    // (mirrored double layer) goes through E, W and an nv x nv matrix T
+    const BlockSide &HA = block_side(T, TILE_SHAPES[shape].ta), &HB = block_side(T, TILE_SHAPES[shape].tb);
+    ra.A = device_side(p, w, TILE_SHAPES[shape].ta, s);
+    ra.B = device_side(p, w, TILE_SHAPES[shape].tb, s);
+    ra.ms = std::max(HA.ms_max, HB.ms_max);
     const bool sym = TILE_SHAPES[shape].ta == TILE_SHAPES[shape].tb;
-    const int nops = sym ? 3 : 2;
-    const size_t nE = size_t(chunk_rows) * DB.S, nW = size_t(nv) * DB.S;
-    const size_t nT = sym && nE < size_t(nv) * nv ? size_t(nv) * nv : 0; // else T reuses EV after the gather
-    double *ws = p.ctx->asm_ws.doubles(nops * (nE + nW) + nT + (stage64 ? size_t(nv) * ld : 0) + 3 * nv +
-                                       18 * S.ntp);
-    double *EV = ws, *EK = EV + nE, *EKt = sym ? EK + nE : nullptr, *WV = EV + nops * nE, *WK = WV + nW;
-    double *WKt = sym ? WK + nW : nullptr;
-    double *Tm = nT ? WV + nops * nW : (sym ? EV : nullptr);
-    double *B64 = stage64 ? WV + nops * nW + nT : static_cast<double *>(S.B);
-    double *vx = (stage64 ? B64 + size_t(nv) * ld : WV + nops * nW + nT), *tpv = vx + 3 * nv;
-    bool first = true;
-    for (const auto &ch : chunks) {
-        ra.b0 = ch.first;
-        ra.b1 = ch.second;
-        ra.rowbase = HA.pref[ch.first];
-        ra.EV = EV;
-        ra.EK = EK;
-        ra.EKt = EKt;
-        if (p.timing) p.timer.begin(T_ASM, s);
-        launch_regular(shape, yuk, f32, ra, s);
-        if (p.timing) p.timer.end(s);
-        PB_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_bem_pass1, dim3(nblk(DB.S, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, DA.L_ptr,
-                           DA.L, DA.L_blk, ra.b0, ra.b1, ra.rowbase, EV, EK, EKt,
-                           sym ? static_cast<const int32_t *>(DB.slot_blk) : nullptr, WV, WK, WKt, first ? 1 : 0);
-        PB_HIP(hipGetLastError());
-        first = false;
-    }
-    const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
-    // every entry of [K' | V'] is written below; only the row padding past 2 nv
-    // (read by the dense apply against zero inputs) is cleared, and only
-    // where it is the stored operator (FP32 storage pads when narrowing)
-    if (!stage64 && ld > 2 * nv)
-        PB_HIP(hipMemset2DAsync(B64 + 2 * nv, sizeof(double) * ld, 0, sizeof(double) * (ld - 2 * nv), nv, s));
-    const int32_t *cblk = sym ? static_cast<const int32_t *>(DB.slot_blk) : nullptr;
-    hipLaunchKernelGGL(k_bem_pass2, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, ld, DB.L_ptr, DB.L,
-                       cblk, DA.L_ptr, DA.L_blk, WV, WK, sV, sK, B64);
+    // every tile adds into the operator: start from zero (the row padding
+    // past 2 nv, read by the dense apply against zero inputs, stays zero)
+    PB_HIP(hipMemsetAsync(S.B, 0, size_t(nv) * ld * elem, s));
+    if (sym) PB_HIP(hipMemsetAsync(Tm, 0, size_t(nv) * nv * elem, s));
+    if (p.timing) p.timer.begin(T_ASM, s);
+    launch_all_tiles(shape, yuk, f32, ra, HA, HB, s);
+    if (p.timing) p.timer.end(s);
     PB_HIP(hipGetLastError());
     if (sym) {
-        hipLaunchKernelGGL(k_bem_pass2_one, dim3(nblk(nv, 256), unsigned(nv)), dim3(256), 0, s, nv, DB.S, DB.L_ptr,
-                           DB.L, cblk, DA.L_ptr, DA.L_blk, WKt, sK, Tm);
         const unsigned nbt = unsigned((nv + SYMT - 1) / SYMT);
-        hipLaunchKernelGGL(k_bem_symm, dim3(nbt, nbt), dim3(256), 0, s, nv, ld, B64, Tm);
+        if (f32)
+            hipLaunchKernelGGL(k_bem_symm<float>, dim3(nbt, nbt), dim3(256), 0, s, nv, ld, static_cast<float *>(S.B),
+                               static_cast<const float *>(Tm));
+        else
+            hipLaunchKernelGGL(k_bem_symm<double>, dim3(nbt, nbt), dim3(256), 0, s, nv, ld,
+                               static_cast<double *>(S.B), static_cast<const double *>(Tm));
         PB_HIP(hipGetLastError());
     }
     // touching pairs
@@ -1350,37 +1276,40 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
                            S.tp_sig, S.tri, vx, S.nrm, S.area, kappa, G, tpv);
     if (p.timing) p.timer.end(s);
     PB_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_bem_scatter, dim3(nblk(nv, 64)), dim3(64), 0, s, nv, ld, S.v2t_ptr, S.v2t, S.tri, S.tp_ptr,
-                       S.tp_sig, tpv, S.area, sV, sK, B64);
+    if (f32)
+        hipLaunchKernelGGL(k_bem_scatter<float>, dim3(nblk(nv, 64)), dim3(64), 0, s, nv, ld, S.minv, S.v2t_ptr, S.v2t,
+                           S.tri, S.tp_ptr, S.tp_sig, tpv, S.area, sV, sK, static_cast<float *>(S.B));
+    else
+        hipLaunchKernelGGL(k_bem_scatter<double>, dim3(nblk(nv, 64)), dim3(64), 0, s, nv, ld, S.minv, S.v2t_ptr,
+                           S.v2t, S.tri, S.tp_ptr, S.tp_sig, tpv, S.area, sV, sK, static_cast<double *>(S.B));
     PB_HIP(hipGetLastError());
-    // final storage
-    if (p.precision == PBFB_MIXED) {
-        hipLaunchKernelGGL(k_diag_and_narrow, dim3(nblk(ld, 256), unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64,
-                           S.vdiag, static_cast<float *>(S.B));
-    } else {
-        hipLaunchKernelGGL(k_diag_and_narrow, dim3(1, unsigned(nv)), dim3(256), 0, s, nv, ld, ld, B64, S.vdiag,
-                           (float *)nullptr);
-    }
-    PB_HIP(hipGetLastError());
-    // symmetric storage use (square-tile assembly): Delta from the stored values
+    // diagonal of V', symmetric storage use (Delta from the stored values),
+    // approximate inverse of the single-layer block (from the stored values)
     S.sym = sym;
-    if (sym) {
-        if (p.precision == PBFB_MIXED)
-            hipLaunchKernelGGL(k_sym_delta<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld,
-                               static_cast<const float *>(S.B), S.d_ptr, S.d_col, S.d_val);
-        else
-            hipLaunchKernelGGL(k_sym_delta<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld,
-                               static_cast<const double *>(S.B), S.d_ptr, S.d_col, S.d_val);
-        PB_HIP(hipGetLastError());
-    }
-    // approximate inverse of the single-layer block, from the FP64 values (with
-    // FP32 storage: the staging copy, still in the workspace)
     PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_spai_small<double>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv, static_cast<const double *>(B64),
-                       ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
-    if (T.max_ring > SPAI_SMALL)
-        hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, static_cast<const double *>(B64),
-                           ld, S.ring_ptr, S.ring, S.spai, p.d_bad);
+    if (f32) {
+        const float *Bf = static_cast<const float *>(S.B);
+        hipLaunchKernelGGL(k_vdiag<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, S.mvert, Bf, S.vdiag);
+        if (sym)
+            hipLaunchKernelGGL(k_sym_delta<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, Bf, S.d_ptr, S.d_col,
+                               S.d_val);
+        hipLaunchKernelGGL(k_spai_small<float>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv, S.ring_ptr,
+                           S.ring, S.spai, p.d_bad);
+        if (T.max_ring > SPAI_SMALL)
+            hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, Bf, ld, S.minv, S.ring_ptr,
+                               S.ring, S.spai, p.d_bad);
+    } else {
+        const double *Bd = static_cast<const double *>(S.B);
+        hipLaunchKernelGGL(k_vdiag<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, S.mvert, Bd, S.vdiag);
+        if (sym)
+            hipLaunchKernelGGL(k_sym_delta<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, Bd, S.d_ptr,
+                               S.d_col, S.d_val);
+        hipLaunchKernelGGL(k_spai_small<double>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv, S.ring_ptr,
+                           S.ring, S.spai, p.d_bad);
+        if (T.max_ring > SPAI_SMALL)
+            hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, Bd, ld, S.minv, S.ring_ptr,
+                               S.ring, S.spai, p.d_bad);
+    }
     PB_HIP(hipGetLastError());
     int bad = 0;
     PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -633,6 +633,9 @@ void ensure_topology(Problem &p, hipStream_t s)
         S.nv = T.nv;
         S.nt = T.nt;
         S.g = A.upload(T.g, s);
+        S.mvert = A.upload(T.mvert, s);
+        S.minv = A.upload(T.minv, s);
+        S.gmv = A.upload(T.gmv, s);
         S.tri = A.upload(T.tri, s);
         S.v2t_ptr = A.upload(T.v2t_ptr, s);
         S.v2t = A.upload(T.v2t, s);
@@ -768,8 +771,12 @@ void fem_assemble_linear(Problem &p, hipStream_t s)
 
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s)
 {
+    fem_nonlinear_buf(p, scheme, u, out, scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet)), s);
+}
+
+void fem_nonlinear_buf(Problem &p, int scheme, const double *u, double *out, double *Nt, hipStream_t s)
+{
     const double c = p.eps_s * p.kappa * p.kappa;
-    double *Nt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_N>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
                        u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Nt);
     hipLaunchKernelGGL(k_node_gather<1>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Nt,

@@ -13,23 +13,26 @@ namespace pbfb {
 static inline unsigned nb_(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------------------
-// packing: x_w = [u(g_w) | lambda_w | 0 pad] for both surfaces
+// packing: x_w = [u(g_w) | lambda_w | 0 pad] for both surfaces, in the
+// Morton vertex order of the stored operators (gmv: FEM node, mv: surface
+// vertex of each operator index; matrix-free: g and mv null, ascending order)
 // ---------------------------------------------------------------------------
-__global__ void k_pack(int64_t nn, int64_t nm, int64_t ns, int64_t ldm, int64_t lds, const int32_t *__restrict__ gm,
-                       const int32_t *__restrict__ gs, const double *__restrict__ x, double *__restrict__ xm,
+__global__ void k_pack(int64_t nn, int64_t nm, int64_t ns, int64_t ldm, int64_t lds, const int32_t *__restrict__ gmm,
+                       const int32_t *__restrict__ mvm, const int32_t *__restrict__ gms,
+                       const int32_t *__restrict__ mvs, const double *__restrict__ x, double *__restrict__ xm,
                        double *__restrict__ xs)
 {
     const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (k < ldm) {
         double v = 0.0;
-        if (k < nm) v = x[gm[k]];
-        else if (k < 2 * nm) v = x[nn + (k - nm)];
+        if (k < nm) v = x[gmm[k]];
+        else if (k < 2 * nm) v = x[nn + (mvm ? mvm[k - nm] : k - nm)];
         xm[k] = v;
     }
     if (k < lds) {
         double v = 0.0;
-        if (k < ns) v = x[gs[k]];
-        else if (k < 2 * ns) v = x[nn + nm + (k - ns)];
+        if (k < ns) v = x[gms[k]];
+        else if (k < 2 * ns) v = x[nn + nm + (mvs ? mvs[k - ns] : k - ns)];
         xs[k] = v;
     }
 }
@@ -42,6 +45,7 @@ struct GemvSurf {
     const void *B;
     const double *x;
     double *y;
+    const int32_t *oidx; // output position of each operator row (its vertex)
     void *P; // FP64 column partials of the symmetric use
     int64_t n, ld;
     int sym, f32;
@@ -61,10 +65,10 @@ __global__ void __launch_bounds__(256, 4) k_gemv(GemvSurf S0, GemvSurf S1, int64
     const int64_t r0 = (S.sym ? nb - 1 - bi : bi) * int64_t(GSYM);
     const MT *B = static_cast<const MT *>(S.B);
     if (S.sym) {
-        gemv_rows_sym<MT>(B, S.x, S.y, static_cast<sym_part_t<MT> *>(S.P), S.n, S.ld, r0, threadIdx.x);
+        gemv_rows_sym<MT>(B, S.x, S.y, S.oidx, static_cast<sym_part_t<MT> *>(S.P), S.n, S.ld, r0, threadIdx.x);
     } else {
         const int64_t rw = r0 + wv * GEMV_RW;
-        if (rw < S.n) gemv_rows<MT>(B, S.x, S.y, S.n, S.ld, rw, lane);
+        if (rw < S.n) gemv_rows<MT>(B, S.x, S.y, S.oidx, S.n, S.ld, rw, lane);
     }
 }
 
@@ -75,7 +79,7 @@ __global__ void __launch_bounds__(256) k_gemv_fin(GemvSurf S0, GemvSurf S1, int6
     const GemvSurf &S = s1 ? S1 : S0;
     if (!S.sym) return;
     const int64_t i0 = (s1 ? blockIdx.x - nb0 : blockIdx.x) * int64_t(GFIN_ROWS);
-    gemv_sym_finish(S.n, static_cast<const double *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, i0, threadIdx.x);
+    gemv_sym_finish(S.n, static_cast<const double *>(S.P), S.dptr, S.dcol, S.dval, S.x, S.y, S.oidx, i0, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,19 +163,22 @@ __global__ void k_add_vec(int64_t n, const double *__restrict__ a, const double 
 // ===========================================================================
 // host wrappers
 // ===========================================================================
-static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y)
+// column partials of the symmetric use: ((nv + GSYM - 1) / GSYM) x nv FP64
+int64_t sym_partials_doubles(int64_t nv) { return ((nv + GSYM - 1) / GSYM) * nv; }
+
+static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y, double *P)
 {
     const SurfaceDev &D = p.surf[w];
     GemvSurf G{};
     G.B = D.B;
     G.x = x;
     G.y = y;
+    G.oidx = D.mvert;
     G.n = D.nv;
     G.ld = bem_ld(D.nv);
     G.sym = D.sym ? 1 : 0;
     G.f32 = p.precision == PBFB_MIXED ? 1 : 0;
-    G.P = D.sym ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP1, size_t((D.nv + GSYM - 1) / GSYM) * D.nv)
-                : nullptr;
+    G.P = D.sym ? P : nullptr;
     G.dptr = D.d_ptr;
     G.dcol = D.d_col;
     G.dval = D.d_val;
@@ -179,12 +186,12 @@ static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y)
 }
 
 // both surfaces' rows in one launch; skip_m leaves out Gamma_m (two-field form)
-static void gemv_launch(Problem &p, const double *xm, const double *xs, double *y, hipStream_t s, bool skip_m)
+static void gemv_launch(Problem &p, const ApplyBufs &bf, double *y, hipStream_t s, bool skip_m, bool timed)
 {
     const SurfaceDev &M = p.surf[0], &S = p.surf[1];
     const int64_t nb0 = skip_m ? 0 : (M.nv + GSYM - 1) / GSYM, nb1 = (S.nv + GSYM - 1) / GSYM;
-    const GemvSurf G0 = gemv_surf(p, 0, xm, y + p.nn), G1 = gemv_surf(p, 1, xs, y + p.nn + M.nv);
-    if (p.timing) p.timer.begin(T_GEMV, s);
+    const GemvSurf G0 = gemv_surf(p, 0, bf.xm, y + p.nn, bf.P[0]), G1 = gemv_surf(p, 1, bf.xs, y + p.nn + M.nv, bf.P[1]);
+    if (timed) p.timer.begin(T_GEMV, s);
     if (p.precision == PBFB_MIXED)
         hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, G0, G1, nb0);
     else
@@ -193,30 +200,45 @@ static void gemv_launch(Problem &p, const double *xm, const double *xs, double *
         const int64_t f0 = skip_m ? 0 : (M.nv + GFIN_ROWS - 1) / GFIN_ROWS, f1 = (S.nv + GFIN_ROWS - 1) / GFIN_ROWS;
         hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0 + f1)), dim3(256), 0, s, G0, G1, f0);
     }
-    if (p.timing) p.timer.end(s);
+    if (timed) p.timer.end(s);
 }
 
-static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hipStream_t s)
+// bufs: caller-provided work buffers (no allocation, no timing), else the
+// problem's scratch
+static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hipStream_t s,
+                       const ApplyBufs *bufs = nullptr)
 {
     const SurfaceDev &M = p.surf[0], &S = p.surf[1];
     const int64_t ldm = bem_ld(M.nv), lds = bem_ld(S.nv);
-    double *xm = scratch<double>(p, SCR_XM, ldm);
-    double *xs = scratch<double>(p, SCR_XS, lds);
-    if (p.timing) p.timer.begin(T_APPLY, s);
-    hipLaunchKernelGGL(k_pack, dim3(nb_(std::max(ldm, lds), 256)), dim3(256), 0, s, p.nn, M.nv, S.nv, ldm, lds, M.g,
-                       S.g, x, xm, xs);
-    if (p.bem_mf) {
-        if (p.timing) p.timer.begin(T_GEMV, s);
-        mf_apply(p, 0, xm, y + p.nn, nullptr, s);
-        mf_apply(p, 1, xs, y + p.nn + p.surf[0].nv, nullptr, s);
-        if (p.timing) p.timer.end(s);
+    ApplyBufs bf;
+    if (bufs) {
+        bf = *bufs;
     } else {
-        gemv_launch(p, xm, xs, y, s, p.two_field());
+        bf.xm = scratch<double>(p, SCR_XM, ldm);
+        bf.xs = scratch<double>(p, SCR_XS, lds);
+        for (int w = 0; w < 2; ++w)
+            bf.P[w] = p.surf[w].sym ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP1,
+                                                      sym_partials_doubles(p.surf[w].nv))
+                                    : nullptr;
+    }
+    const bool timed = p.timing && !bufs;
+    if (timed) p.timer.begin(T_APPLY, s);
+    hipLaunchKernelGGL(k_pack, dim3(nb_(std::max(ldm, lds), 256)), dim3(256), 0, s, p.nn, M.nv, S.nv, ldm, lds,
+                       p.bem_mf ? M.g : M.gmv, p.bem_mf ? nullptr : M.mvert, p.bem_mf ? S.g : S.gmv,
+                       p.bem_mf ? nullptr : S.mvert, x, bf.xm, bf.xs);
+    if (p.bem_mf) {
+        PB_CHECK(!bufs, PBFB_EINVAL, "matrix-free boundary operators need the problem's own work buffers");
+        if (timed) p.timer.begin(T_GEMV, s);
+        mf_apply(p, 0, bf.xm, y + p.nn, nullptr, s);
+        mf_apply(p, 1, bf.xs, y + p.nn + p.surf[0].nv, nullptr, s);
+        if (timed) p.timer.end(s);
+    } else {
+        gemv_launch(p, bf, y, s, p.two_field(), timed);
     }
     // two-field form: lambda_m is not an unknown of the solve; its row is the identity
     if (p.two_field())
         PB_HIP(hipMemcpyAsync(y + p.nn, x + p.nn, sizeof(double) * M.nv, hipMemcpyDeviceToDevice, s));
-    if (p.timing) p.timer.begin(T_SPMV, s);
+    if (timed) p.timer.begin(T_SPMV, s);
     const unsigned g = nb_(p.nn, SLICE);
     if (!with_jac)
         hipLaunchKernelGGL(k_spmv<double>, dim3(g), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val0, x, y);
@@ -224,7 +246,7 @@ static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hi
         hipLaunchKernelGGL(k_spmv<float>, dim3(g), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val32, x, y);
     else
         hipLaunchKernelGGL(k_spmv<double>, dim3(g), dim3(256), 0, s, p.nn, p.d_sptr, p.d_col, p.d_val, x, y);
-    if (p.timing) {
+    if (timed) {
         p.timer.end(s); // spmv
         p.timer.end(s); // apply
     }
@@ -232,6 +254,10 @@ static void apply_impl(Problem &p, const double *x, double *y, bool with_jac, hi
 }
 
 void coupled_apply(Problem &p, const double *x, double *y, hipStream_t s) { apply_impl(p, x, y, true, s); }
+void coupled_apply_linear_bufs(Problem &p, const double *x, double *y, hipStream_t s, const ApplyBufs &bufs)
+{
+    apply_impl(p, x, y, false, s, &bufs);
+}
 
 // ---------------------------------------------------------------------------
 // lambda_m from the trace of u (two-field form, Sec. 2.3.1):
@@ -241,27 +267,32 @@ void coupled_apply(Problem &p, const double *x, double *y, hipStream_t s) { appl
 // symmetric positive definite, so conjugate gradients with its diagonal as
 // preconditioner.
 // ---------------------------------------------------------------------------
-__global__ void k_pack_m(int64_t nm, int64_t ldm, const int32_t *__restrict__ gm, const double *__restrict__ u,
-                         const double *__restrict__ lam, double *__restrict__ xm)
+// packed Gamma_m input in the operator's Morton vertex order (gmv: FEM node,
+// mv: surface vertex of each operator index)
+__global__ void k_pack_m(int64_t nm, int64_t ldm, const int32_t *__restrict__ gmv, const int32_t *__restrict__ mv,
+                         const double *__restrict__ u, const double *__restrict__ lam, double *__restrict__ xm)
 {
     const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (k >= ldm) return;
     double v = 0.0;
-    if (k < nm) v = u ? u[gm[k]] : 0.0;
-    else if (k < 2 * nm) v = lam ? lam[k - nm] : 0.0;
+    if (k < nm) v = u ? u[gmv[k]] : 0.0;
+    else if (k < 2 * nm) v = lam ? lam[mv[k - nm]] : 0.0;
     xm[k] = v;
 }
 
 template <typename MT>
-__global__ void k_vdiag_inv(int64_t nm, int64_t ld, const MT *__restrict__ B, double *__restrict__ dinv)
+__global__ void k_vdiag_inv(int64_t nm, int64_t ld, const int32_t *__restrict__ mv, const MT *__restrict__ B,
+                            double *__restrict__ dinv)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (i < nm) dinv[i] = -1.0 / double(B[i * ld + nm + i]);
+    const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (k < nm) dinv[mv[k]] = -1.0 / double(B[k * ld + nm + k]);
 }
 
 static void gemv_m(Problem &p, const double *xm, double *y, hipStream_t s)
 {
-    const GemvSurf G = gemv_surf(p, 0, xm, y);
+    const GemvSurf G = gemv_surf(p, 0, xm, y,
+                                 p.surf[0].sym ? scratch<double>(p, SCR_SYMP0, sym_partials_doubles(p.surf[0].nv))
+                                               : nullptr);
     const int64_t nb0 = (G.n + GSYM - 1) / GSYM, f0 = (G.n + GFIN_ROWS - 1) / GFIN_ROWS;
     if (p.precision == PBFB_MIXED)
         hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0)), dim3(256), 0, s, G, G, nb0);
@@ -335,14 +366,15 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
         hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, nm, k, T, part);
         hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, red);
     };
-    hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, phi, (const double *)nullptr, xm);
+    hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.gmv, M.mvert, phi, (const double *)nullptr, xm);
     gemv_m(p, xm, b, s);
     if (with_load && p.nq > 0) vec_axpby(nm, -1.0, scratch<double>(p, SCR_FM, nm), 1.0, b, s);
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_vdiag_inv<float>, dim3(gn), dim3(256), 0, s, nm, ldm, static_cast<const float *>(M.B), dinv);
+        hipLaunchKernelGGL(k_vdiag_inv<float>, dim3(gn), dim3(256), 0, s, nm, ldm, M.mvert,
+                           static_cast<const float *>(M.B), dinv);
     else
-        hipLaunchKernelGGL(k_vdiag_inv<double>, dim3(gn), dim3(256), 0, s, nm, ldm, static_cast<const double *>(M.B),
-                           dinv);
+        hipLaunchKernelGGL(k_vdiag_inv<double>, dim3(gn), dim3(256), 0, s, nm, ldm, M.mvert,
+                           static_cast<const double *>(M.B), dinv);
     // transposed slots of the approximate inverse's 1-ring pattern (host, from the topology)
     int32_t *tslot = nullptr;
     if (M.spai && !TM.ring_ptr.empty()) {
@@ -388,7 +420,8 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
         constexpr int CHECK = 8;
         for (int it = 0; it < maxit;) {
             for (int k = 0; k < CHECK; ++k, ++it) {
-                hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.g, (const double *)nullptr, d, xm);
+                hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.gmv, M.mvert, (const double *)nullptr, d,
+                                   xm);
                 gemv_m(p, xm, q, s); // q = V' d = -V0 d
                 dev_dots(1, d, q, nullptr, nullptr);
                 hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, red, sc);

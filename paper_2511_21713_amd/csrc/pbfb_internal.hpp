@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <map>
 #include <set>
@@ -81,30 +82,34 @@ struct TileShape {
 };
 constexpr TileShape TILE_SHAPES[] = {{16, 32}, {8, 32}, {8, 64}, {16, 16}, {8, 16}};
 constexpr int N_TILE_SHAPES = int(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
-constexpr int MAXS = 12; // slots per local vertex in a block (max triangles of a block at one vertex)
+constexpr int MAXS = 24; // slots per local vertex in a block (max triangles of a block at one vertex)
 int tile_shape_index(int ta, int tb); // -1 if not a candidate
 constexpr int MAXRING = 64; // largest 1-ring (vertex and its neighbours) of the approximate inverse
 
 // Blocks of `bs` consecutive Morton-ordered triangles (one side of a tile
-// shape): nb blocks, S = sum of their vertex counts (rows or columns of the
-// expanded tile matrix); per block its first expanded index and vertex
-// count; per expanded index the MAXS (triangle-in-block * 3 + corner) slots
-// touching that vertex (-1 padded); ms_max = the largest slot count of any
-// vertex in any block; per surface vertex its expanded indices and their
-// blocks.
+// shape): nb blocks, S = sum of their vertex counts; per block its first
+// local-vertex index and vertex count; per local vertex (block, k) its
+// operator index (vid: the surface vertex's position in the Morton vertex
+// order, the row / column of the stored operator; ascending within a block)
+// and the MAXS (triangle-in-block * 3 + corner) slots touching it (-1
+// padded); ms_max = the largest slot count of any vertex in any block.
+// A greedy colouring of the blocks such that two blocks of one colour share
+// no vertex: col_blk[col_ptr[c] .. col_ptr[c + 1]) lists the blocks of
+// colour c, ascending.  Tiles whose target blocks share one colour and whose
+// source blocks share one colour touch disjoint operator entries, so such a
+// set of tiles can add into the operator in one launch without atomics.
 struct BlockSide {
     int bs = 0, ms_max = 0;
     int64_t nb = 0, S = 0;
-    std::vector<int32_t> pref, nvb, slots;
-    std::vector<int32_t> L_ptr, L, L_blk;
-    std::vector<int32_t> slot_blk; // block of each slot
+    std::vector<int32_t> pref, nvb, slots, vid;
+    int ncolor = 0;
+    std::vector<int32_t> col_ptr, col_blk;
 };
 struct BlockSideDev {
     int bs = 0;
     int64_t nb = 0, S = 0;
-    int32_t *pref = nullptr, *nvb = nullptr, *slots = nullptr;
-    int32_t *L_ptr = nullptr, *L = nullptr, *L_blk = nullptr;
-    int32_t *slot_blk = nullptr;
+    int32_t *pref = nullptr, *nvb = nullptr, *slots = nullptr, *vid = nullptr;
+    int32_t *col_blk = nullptr;
 };
 
 // host-side topology of one boundary surface
@@ -114,6 +119,10 @@ struct SurfaceTopo {
     std::vector<int32_t> tri;          // 3*nt local vertex ids, original order
     std::vector<int32_t> v2t_ptr, v2t; // vertex -> (tri*3 + local index)
     std::vector<int32_t> morton;       // Morton position -> triangle id
+    // Morton vertex order (first appearance along the Morton triangle order):
+    // the row / column order of the stored dense operator.  mvert[k] = local
+    // vertex at position k, minv = its inverse, gmv[k] = g[mvert[k]]
+    std::vector<int32_t> mvert, minv, gmv;
     // regular-assembly blocks of each block size in use (over Morton-ordered
     // triangles), built on first use
     std::map<int, BlockSide> sides;
@@ -124,13 +133,15 @@ struct SurfaceTopo {
     int max_ring = 0;
     // 3-ring pattern of the near-field single layer (matrix-free mode), built on first use
     std::vector<int32_t> nf_ptr, nf_col;
-    // pairs j > i within two rings (where touching-pair blocks can make V' unsymmetric)
+    // in the Morton vertex order: pairs k' > k within two rings (where
+    // touching-pair blocks can make the stored V' unsymmetric)
     std::vector<int32_t> d2_ptr, d2_col;
 };
 
 struct SurfaceDev {
     int64_t nv = 0, nt = 0;
     int32_t *g = nullptr, *tri = nullptr, *v2t_ptr = nullptr, *v2t = nullptr;
+    int32_t *mvert = nullptr, *minv = nullptr, *gmv = nullptr; // Morton vertex order (SurfaceTopo)
     double *qp = nullptr, *nrm = nullptr, *area = nullptr; // original order: 18, 3, 1 per triangle
     // Morton-ordered triangle data for the regular assembly
     int32_t *m_tri = nullptr;
@@ -150,11 +161,12 @@ struct SurfaceDev {
     int32_t *nf_ptr = nullptr, *nf_col = nullptr, *nf_row = nullptr;
     double *nf_val = nullptr;
     int64_t nf_nnz = 0;
-    // assembled dense operator: row i = [K'_i (nv) | V'_i (nv)], FP64 or FP32
+    // assembled dense operator in the Morton vertex order: row k (vertex
+    // mvert[k]) = [K'_k (nv) | V'_k (nv)], columns in the same order, FP64 or FP32
     void *B = nullptr;
-    double *vdiag = nullptr; // diagonal of the signed single-layer block V'
+    double *vdiag = nullptr; // diagonal of the signed single-layer block V' (ascending vertex order)
     // symmetric storage use: the regular part of V' is bitwise symmetric, and
-    // Delta_ij = V'_ij - V'_ji (j > i, two-ring pattern) carries the rest
+    // Delta_kl = V'_kl - V'_lk (l > k in the Morton order, two-ring pattern) carries the rest
     bool sym = false;
     int32_t *d_ptr = nullptr, *d_col = nullptr;
     double *d_val = nullptr;
@@ -170,6 +182,7 @@ struct SurfaceDev {
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
+    std::atomic<size_t> held{0}; // bytes, readable without the mutex (admission by HBM footprint)
     std::mutex mu;
     double *doubles(size_t n);
 };
@@ -227,7 +240,6 @@ struct Problem {
     bool val_ready = false; // FEM stiffness and coupling values (depend on the permittivities)
     bool bem_topo_ready[2] = {false, false};
     int tile_fixed = -1; // tile shape forced by pbfb_set_tile_shape (index), -1: tuned
-    int64_t asm_chunk = int64_t(1) << 30; // largest expanded-matrix chunk per operator (entries)
     bool bem_mf = false; // boundary operators applied matrix-free (no dense storage)
     // host copies
     int64_t nn = 0, ntet = 0, nq = 0;
@@ -274,6 +286,10 @@ template <class T> T *scratch(Problem &p, int slot, size_t n)
 }
 void release_scratch(Problem &p, int slot);
 void release_all_scratch(Problem &p);
+// frees every device allocation of the problem (arenas and scratch) and marks
+// all device state stale; the host copies (mesh, charges, parameters) stay,
+// so the next call sets the problem up again
+void release_device_state(Problem &p);
 
 // host preprocessing (setup.hip)
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri);
@@ -314,6 +330,18 @@ double fem_energy_integral(Problem &p, const double *u_lin, const double *u_nl, 
 
 // coupled operator y = J x with the current CSR values (pack + GEMV + SpMV)
 void coupled_apply(Problem &p, const double *x, double *y, hipStream_t s);
+// work buffers of one apply: packed surface inputs (bem_ld(nv) each) and the
+// FP64 column partials of the symmetric use (sym_partials_doubles(nv) each,
+// null where a surface is not stored symmetric)
+struct ApplyBufs {
+    double *xm = nullptr, *xs = nullptr;
+    double *P[2] = {nullptr, nullptr};
+};
+int64_t sym_partials_doubles(int64_t nv);
+// A only (no J_N), with caller-provided buffers (no allocation, no timing)
+void coupled_apply_linear_bufs(Problem &p, const double *x, double *y, hipStream_t s, const ApplyBufs &bufs);
+// N_scheme(u) into out (FEM rows) with a caller-provided element buffer of 4 ntet doubles
+void fem_nonlinear_buf(Problem &p, int scheme, const double *u, double *out, double *Nt, hipStream_t s);
 void coupled_apply_linear(Problem &p, const double *x, double *y, hipStream_t s); // A only (no J_N)
 
 // vector helpers

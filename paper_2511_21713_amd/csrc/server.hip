@@ -12,6 +12,8 @@
 // and budget.  The per-instance arithmetic (work lists, reduction orders) does
 // not depend on the other members of the batch, so a request's result is the
 // same bit for bit alone or in any mix.
+#include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -24,8 +26,10 @@ namespace pbfb {
 
 int64_t bem_ld(int64_t nv);
 
-// Device bytes an instance holds while solving, and the extra it needs while
-// its dense operators are assembled (expanded tile matrix and gather buffer).
+// Device bytes an instance holds while solving, and the assembly workspace it
+// needs while its dense operators are assembled (the mirrored double layer of
+// a square-tile assembly, nv x nv in the storage precision, vertex
+// coordinates and touching-pair blocks).
 void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *setup_extra)
 {
     const size_t elem = p.precision == PBFB_MIXED ? 4 : 8;
@@ -35,22 +39,15 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
         // the near-field rows of the preconditioner (~40 per vertex)
         const SurfaceTopo &T = p.topo[w];
         dense += T.tp_sig.size() * 18 * 8 + size_t(T.nt) * 15 * 8 + size_t(T.nv) * 40 * 16;
+        tmp = std::max(tmp, size_t(T.nv) * 3 * 8);
     }
     for (int w = 0; w < 2 && !p.bem_mf; ++w) {
-        // block tables are a host-side cache filled on first use
-        SurfaceTopo &T = const_cast<SurfaceTopo &>(p.topo[w]);
+        const SurfaceTopo &T = p.topo[w];
         dense += size_t(T.nv) * bem_ld(T.nv) * elem;
         dense += size_t((T.nv + 15) / 16) * T.nv * 8 + size_t(T.nv) * 20 * 12; // symmetric use: partials, Delta
-        for (int k = 0; k < N_TILE_SHAPES; ++k) {
-            const size_t SA = size_t(block_side(T, TILE_SHAPES[k].ta).S), SB = size_t(block_side(T, TILE_SHAPES[k].tb).S);
-            const size_t rows = std::min(SA, std::max<size_t>(3 * TILE_SHAPES[k].ta, size_t(p.asm_chunk) / SB) +
-                                                  3 * TILE_SHAPES[k].ta); // one assembly chunk of E
-            // square shapes: a third operator in E and W, and an nv x nv matrix
-            const size_t ops = TILE_SHAPES[k].ta == TILE_SHAPES[k].tb ? 3 : 2;
-            const size_t tm = ops == 3 ? size_t(T.nv) * T.nv * 8 : 0;
-            tmp = std::max(tmp, rows * SB * 8 * ops + size_t(T.nv) * SB * 8 * ops + tm +
-                                    (p.precision == PBFB_MIXED ? size_t(T.nv) * bem_ld(T.nv) * 8 : 0));
-        }
+        dense += size_t(T.nt) * 18 * 8 * 2 + size_t(T.nv) * (8 * 8 + 16 * 4);  // Morton copies, block tables, rings
+        tmp = std::max(tmp, (size_t(T.nv) * T.nv * elem + 255) / 256 * 256 + size_t(T.nv) * 3 * 8 +
+                                T.tp_sig.size() * 18 * 8 + 64);
     }
     const size_t n = size_t(p.n());
     const size_t nnz_est = size_t(p.ntet) * 3 + size_t(p.nn) * 4; // generous: ~14 per row
@@ -70,11 +67,15 @@ struct Request {
     NewtonRun *run = nullptr;
     bool done = false;
     std::string message;
+    std::chrono::steady_clock::time_point t_submit, t_admit;
 };
 
 struct Server {
     Ctx *ctx = nullptr;
-    size_t budget = 0, used = 0;
+    // used: steady footprints of the admitted, unfinished requests; ws_need: the
+    // largest assembly workspace any admitted request needs (the context's
+    // workspace grows to it and is kept, so it is charged once, never released)
+    size_t budget = 0, used = 0, ws_need = 0;
     int max_slots = 1;
     hipStream_t s_solve = nullptr, s_setup = nullptr;
     std::mutex mu;
@@ -90,14 +91,23 @@ struct Server {
     std::thread solve_thread, setup_thread;
     std::string error;
 
+    // device bytes charged for the shared assembly workspace if r were admitted
+    size_t ws_with(const Request *r) const
+    {
+        return std::max(std::max(ws_need, r->extra), ctx->asm_ws.held.load());
+    }
+
     void admit_locked()
     {
         while (!pending.empty() && in_flight < max_slots) {
             Request *r = pending.front();
-            if (used + r->steady + r->extra > budget && in_flight > 0) break; // wait for memory
+            if (used + r->steady + ws_with(r) > budget && in_flight > 0) break; // wait for memory
             pending.pop_front();
+            ws_need = ws_with(r);
             used += r->steady;
             ++in_flight;
+            r->t_admit = std::chrono::steady_clock::now();
+            r->res.t_wait_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
             to_setup.push_back(r);
         }
     }
@@ -114,7 +124,9 @@ struct Server {
                 r = to_setup.front();
                 to_setup.pop_front();
             }
+            const double wait = r->res.t_wait_s;
             r->run = new NewtonRun(r->p, r->o, &r->res, nullptr);
+            r->res.t_wait_s = wait;
             // the setup part of the state machine: assembly, linear-solve request
             try {
                 ensure_all(*r->p, s_setup);
@@ -132,9 +144,15 @@ struct Server {
     void complete_locked(Request *r)
     {
         r->done = true;
+        // every device allocation of the request (operators, mesh, Krylov and
+        // work buffers) is freed before its budget is handed to the next one
+        try {
+            PB_HIP(hipStreamSynchronize(s_solve));
+        } catch (const Error &) {
+        }
+        release_device_state(*r->p);
         used -= std::min(used, r->steady);
         --in_flight;
-        release_all_scratch(*r->p); // Krylov and work buffers back to the pool
         admit_locked();
         cv.notify_all();
     }
@@ -256,6 +274,7 @@ pbfb_status pbfb_server_submit(pbfb_server *sv, pbfb_problem *pp, const pbfb_sol
         r->p = &p;
         r->steady = steady;
         r->extra = extra;
+        r->t_submit = std::chrono::steady_clock::now();
         std::lock_guard<std::mutex> lk(sv->s.mu);
         r->ticket = sv->s.next_ticket++;
         sv->s.all[r->ticket] = r;
@@ -263,6 +282,25 @@ pbfb_status pbfb_server_submit(pbfb_server *sv, pbfb_problem *pp, const pbfb_sol
         sv->s.admit_locked();
         sv->s.cv.notify_all();
         *ticket = r->ticket;
+        return PBFB_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    }
+}
+
+pbfb_status pbfb_request_footprint(const pbfb_problem *pp, const pbfb_solve_opts *o, size_t *steady_bytes,
+                                   size_t *setup_bytes)
+{
+    try {
+        PB_CHECK(pp && steady_bytes && setup_bytes, PBFB_EINVAL, "null argument");
+        const Problem &p = pp->p;
+        PB_CHECK(p.have_mesh, PBFB_ESTATE, "set_mesh must precede the footprint estimate");
+        pbfb_solve_opts O;
+        if (o) O = *o;
+        else pbfb_solve_opts_default(&O);
+        check_opts(O);
+        footprint_estimate(p, O.gmres_restart, steady_bytes, setup_bytes);
         return PBFB_OK;
     } catch (const Error &e) {
         set_error(e.msg);

@@ -29,9 +29,10 @@ int tile_shape_index(int ta, int tb)
     return -1;
 }
 
-// Blocks of `bs` consecutive Morton-ordered triangles: unique local vertex
-// lists, and for every local vertex the (triangle-in-block * 3 + corner)
-// slots that touch it; per surface vertex its expanded indices.
+// Blocks of `bs` consecutive Morton-ordered triangles: their vertex lists
+// (ascending operator index), for every local vertex the (triangle-in-block
+// * 3 + corner) slots that touch it, and a colouring of the blocks in which
+// blocks of one colour share no vertex.
 const BlockSide &block_side(SurfaceTopo &S, int bs)
 {
     auto found = S.sides.find(bs);
@@ -41,14 +42,14 @@ const BlockSide &block_side(SurfaceTopo &S, int bs)
     B.nb = (S.nt + bs - 1) / bs;
     B.pref.assign(B.nb + 1, 0);
     B.nvb.assign(B.nb, 0);
-    std::vector<std::vector<int32_t>> blk_verts(B.nb);
+    std::vector<std::vector<int32_t>> blk_verts(B.nb); // operator (Morton) indices, ascending
     for (int64_t b = 0; b < B.nb; ++b) {
         std::vector<int32_t> vs;
         for (int k = 0; k < bs; ++k) {
             int64_t m = b * bs + k;
             if (m >= S.nt) break;
             int32_t t = S.morton[m];
-            for (int a = 0; a < 3; ++a) vs.push_back(S.tri[3 * t + a]);
+            for (int a = 0; a < 3; ++a) vs.push_back(S.minv[S.tri[3 * t + a]]);
         }
         std::sort(vs.begin(), vs.end());
         vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
@@ -57,35 +58,53 @@ const BlockSide &block_side(SurfaceTopo &S, int bs)
         B.pref[b + 1] = B.pref[b] + B.nvb[b];
     }
     B.S = B.pref[B.nb];
-    B.slot_blk.resize(B.S);
-    for (int64_t b = 0; b < B.nb; ++b)
-        for (int32_t k = B.pref[b]; k < B.pref[b + 1]; ++k) B.slot_blk[k] = int32_t(b);
+    B.vid.resize(B.S);
     B.slots.assign(B.S * MAXS, -1);
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> vlist(S.nv);
+    std::vector<std::vector<int32_t>> vblocks(S.nv); // blocks of each operator index
     for (int64_t b = 0; b < B.nb; ++b) {
         const auto &vs = blk_verts[b];
+        std::copy(vs.begin(), vs.end(), B.vid.begin() + B.pref[b]);
         std::vector<int> fill(vs.size(), 0);
         for (int k = 0; k < bs; ++k) {
             int64_t m = b * bs + k;
             if (m >= S.nt) break;
             int32_t t = S.morton[m];
             for (int a = 0; a < 3; ++a) {
-                int32_t v = S.tri[3 * t + a];
+                int32_t v = S.minv[S.tri[3 * t + a]];
                 int32_t li = int32_t(std::lower_bound(vs.begin(), vs.end(), v) - vs.begin());
-                PB_CHECK(fill[li] < MAXS, PBFB_EMESH, "vertex valence too high for the assembly blocks");
+                PB_CHECK(fill[li] < MAXS, PBFB_EMESH,
+                         "a surface vertex has more than " + std::to_string(MAXS) + " triangles");
                 B.slots[(int64_t(B.pref[b]) + li) * MAXS + fill[li]++] = k * 3 + a;
             }
         }
-        for (size_t li = 0; li < vs.size(); ++li) vlist[vs[li]].push_back({B.pref[b] + int32_t(li), int32_t(b)});
+        for (int32_t v : vs) vblocks[v].push_back(int32_t(b));
         for (int f : fill) B.ms_max = std::max(B.ms_max, f);
     }
-    B.L_ptr.assign(S.nv + 1, 0);
-    for (int64_t i = 0; i < S.nv; ++i) {
-        B.L_ptr[i + 1] = B.L_ptr[i] + int32_t(vlist[i].size());
-        for (auto &e : vlist[i]) {
-            B.L.push_back(e.first);
-            B.L_blk.push_back(e.second);
+    // greedy colouring in block order: the smallest colour no earlier block
+    // sharing a vertex with this one has taken
+    std::vector<int32_t> color(B.nb, -1);
+    std::vector<int64_t> seen;
+    for (int64_t b = 0; b < B.nb; ++b) {
+        seen.clear();
+        for (int32_t v : blk_verts[b])
+            for (int32_t o : vblocks[v])
+                if (color[o] >= 0) seen.push_back(color[o]);
+        std::sort(seen.begin(), seen.end());
+        int32_t c = 0;
+        for (int64_t x : seen) {
+            if (x == c) ++c;
+            else if (x > c) break;
         }
+        color[b] = c;
+        B.ncolor = std::max(B.ncolor, int(c) + 1);
+    }
+    B.col_ptr.assign(B.ncolor + 1, 0);
+    for (int64_t b = 0; b < B.nb; ++b) B.col_ptr[color[b] + 1]++;
+    for (int c = 0; c < B.ncolor; ++c) B.col_ptr[c + 1] += B.col_ptr[c];
+    B.col_blk.resize(B.nb);
+    {
+        std::vector<int32_t> fill(B.col_ptr.begin(), B.col_ptr.end() - 1);
+        for (int64_t b = 0; b < B.nb; ++b) B.col_blk[fill[color[b]]++] = int32_t(b);
     }
     return S.sides.emplace(bs, std::move(B)).first->second;
 }
@@ -162,6 +181,21 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
         S.morton.resize(ntri);
         for (int64_t m = 0; m < ntri; ++m) S.morton[m] = key[m].second;
     }
+    // Morton vertex order: first appearance along the Morton triangle order,
+    // so that the vertices of a block of consecutive triangles have nearby
+    // operator indices
+    S.minv.assign(S.nv, -1);
+    S.mvert.clear();
+    for (int64_t m = 0; m < ntri; ++m)
+        for (int a = 0; a < 3; ++a) {
+            const int32_t v = S.tri[3 * S.morton[m] + a];
+            if (S.minv[v] < 0) {
+                S.minv[v] = int32_t(S.mvert.size());
+                S.mvert.push_back(v);
+            }
+        }
+    S.gmv.resize(S.nv);
+    for (int64_t k = 0; k < S.nv; ++k) S.gmv[k] = S.g[S.mvert[k]];
     // blocks of the default tile shape (other block sizes are built when a
     // shape using them is timed or chosen)
     block_side(S, TILE_SHAPES[0].ta);
@@ -330,30 +364,32 @@ void near_pattern(SurfaceTopo &S)
     }
 }
 
-// vertices j > i within two rings of i, ascending: every pair (i, j) whose
-// entry can receive a touching-pair block (j on a triangle that shares a
-// vertex with a triangle at i)
+// In the Morton vertex order (operator indices): for each k the indices
+// l > k within two rings of vertex mvert[k], ascending: every pair whose
+// entry can receive a touching-pair block (a vertex on a triangle that shares
+// a vertex with a triangle at the other)
 void delta_pattern(SurfaceTopo &S)
 {
     if (!S.d2_ptr.empty()) return;
     std::vector<int32_t> mark(S.nv, -1), cur;
     S.d2_ptr.assign(S.nv + 1, 0);
     S.d2_col.clear();
-    for (int64_t i = 0; i < S.nv; ++i) {
+    for (int64_t k = 0; k < S.nv; ++k) {
         cur.clear();
+        const int32_t i = S.mvert[k];
         for (int32_t e = S.ring_ptr[i]; e < S.ring_ptr[i + 1]; ++e) {
             const int32_t a = S.ring[e];
             for (int32_t f = S.ring_ptr[a]; f < S.ring_ptr[a + 1]; ++f) {
-                const int32_t b = S.ring[f];
-                if (b > i && mark[b] != int32_t(i)) {
-                    mark[b] = int32_t(i);
-                    cur.push_back(b);
+                const int32_t l = S.minv[S.ring[f]];
+                if (l > k && mark[l] != int32_t(k)) {
+                    mark[l] = int32_t(k);
+                    cur.push_back(l);
                 }
             }
         }
         std::sort(cur.begin(), cur.end());
         S.d2_col.insert(S.d2_col.end(), cur.begin(), cur.end());
-        S.d2_ptr[i + 1] = int32_t(S.d2_col.size());
+        S.d2_ptr[k + 1] = int32_t(S.d2_col.size());
     }
 }
 

@@ -135,3 +135,71 @@ def test_server_rejects_oversized_request(setup):
         srv.submit(g)
     assert e.value.code == pb.ENOMEM
     srv.close()
+
+
+def test_server_budget_binds_requests_wait(setup):
+    """An HBM budget that holds one request at a time: later requests wait for
+    admission (t_wait_s > 0) instead of failing, the device memory in use
+    (hipMemGetInfo, sampled while serving) stays within the budget, every
+    completed request has released its device memory, and each result equals
+    its solo result bit for bit."""
+    import threading
+
+    import torch
+    pb, ctx, probs, solo = setup
+    gs = [pb.Problem.from_inputs(ctx, prob) for prob in probs]
+    fp = [g.footprint(**OPTS) for g in gs]
+    budget = int(1.2 * max(a + b for a, b in fp))
+    assert min(a for a, _ in fp) * 2 > budget  # no two requests fit together
+    low, free0 = [0], 0
+    stop = threading.Event()
+    th = None
+    out, tickets = {}, []
+    srv = pb.Server(ctx, hbm_budget_bytes=budget, max_slots=4)
+    gw = pb.Problem.from_inputs(ctx, probs[0])
+    try:
+        # one request first, so that the runtime's own lazy allocations (code
+        # objects, queues, graph resources) are in place before the baseline
+        tw = srv.submit(gw, **OPTS)
+        t0 = time.time()
+        while srv.poll(tw) is None and time.time() - t0 < 60:
+            time.sleep(0.002)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        low[0] = free0
+
+        def sample():
+            while not stop.is_set():
+                low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=sample, daemon=True)
+        th.start()
+        tickets = [srv.submit(g, **OPTS) for g in gs]
+        t0 = time.time()
+        while len(out) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in out:
+                    r = srv.poll(t)
+                    if r is not None:
+                        out[t] = r
+            time.sleep(0.002)
+    finally:
+        srv.close()
+        stop.set()
+        if th is not None:
+            th.join()
+    assert len(out) == len(tickets)
+    waits = [out[t]["t_wait_s"] for t in tickets]
+    print(f"  budget {budget / 2**20:.0f} MiB (footprints {[(round(a / 2**20), round(b / 2**20)) for a, b in fp]} "
+          f"MiB), admission waits {['%.3f' % w for w in waits]} s, peak device use "
+          f"{(free0 - low[0]) / 2**20:.1f} MiB", flush=True)
+    assert sum(w > 1e-3 for w in waits) >= len(tickets) - 2
+    assert free0 - low[0] <= budget
+    for g in gs + [gw]:
+        assert g.hbm() == 0  # released at completion
+    for t, s in zip(tickets, solo):
+        assert out[t]["status"] == 0
+        assert out[t]["total"] == s["total"], (out[t]["total"], s["total"])
+    for g in gs + [gw]:
+        g.close()

@@ -128,25 +128,23 @@ def test_symmetric_apply_matches_full_rows(tiles, precision):
         assert rowrel(Js[None, :], o.apply_jacobian(oracle.HS, phi, v)[None, :]) < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(16, 16), (16, 32)])
-def test_chunked_assembly_matches(tiles, shape):
-    """A tiny workspace cap builds the expanded matrix in many chunks (one
-    block of target rows each), the path large surfaces take: the operators
-    equal the one-chunk ones to rounding and the oracle's, for the symmetric
-    square shape and a rectangular one."""
+def test_assembly_is_reproducible_and_launch_order_fixed(tiles):
+    """The tiles of one launch add into disjoint operator entries (coloured
+    blocks) and the launches follow each other, so the stored operators are
+    bitwise the same on every assembly, for a square and a rectangular
+    shape and both precisions."""
     pb, ctx, prob, refs = tiles
-    g = pb.Problem.from_inputs(ctx, prob)
-    g.set_tile_shape(*shape)
-    one = [g.export_bem(s) for s in (0, 1)]
-    g.set_assembly_chunk(1)
-    many = [g.export_bem(s) for s in (0, 1)]
-    for s in (0, 1):
-        for a, b, r in zip(many[s], one[s], refs[s]):
-            e1, e2 = rowrel(a, b), rowrel(a, r)
-            log(f"  shape {shape} surf {s}: chunked vs one chunk {e1:.2e}, vs oracle {e2:.2e}")
-            assert e1 < 1e-14 and e2 < 1e-12
-    g.set_assembly_chunk(0)
-    g.close()
+    for precision in (0, 1):
+        for shape in ((16, 16), (16, 32)):
+            g = pb.Problem.from_inputs(ctx, prob, precision=precision)
+            g.set_tile_shape(*shape)
+            first = [g.export_bem(s) for s in (0, 1)]
+            for _ in range(2):
+                g.reset_operators()
+                again = [g.export_bem(s) for s in (0, 1)]
+                for s in (0, 1):
+                    assert np.array_equal(again[s][0], first[s][0]) and np.array_equal(again[s][1], first[s][1])
+            g.close()
 
 
 def test_bad_tile_shape_rejected(tiles):
@@ -194,23 +192,52 @@ def uv_sphere(nlon=9, nlat=6):
     return verts, tris
 
 
-def test_high_valence_mesh_matches_oracle(tiles):
-    pb, ctx, _, _ = tiles
-    unit, tris = uv_sphere()
+def valence_problem(nlon):
+    unit, tris = uv_sphere(nlon=nlon, nlat=7)
     nodes, tets, tri_m, tri_s = pbgen.shell_mesh(unit, tris, 4.0 * np.ones(unit.shape[0]), 3.0, 2)
-    prob = pbgen.Problem(nodes=nodes, tets=tets, tri_m=tri_m, tri_s=tri_s, q_xyz=np.zeros((1, 3)),
+    return pbgen.Problem(nodes=nodes, tets=tets, tri_m=tri_m, tri_s=tri_s, q_xyz=np.array([[0.0, 0.0, 0.5]]),
                          q_z=np.array([1.0]), eps_in=4.0, eps_out=80.0, kappa=0.2, info={})
+
+
+@pytest.mark.parametrize("nlon", [9, 16, 24])
+def test_high_valence_mesh_matches_oracle(tiles, nlon):
+    """Poles of valence 9, 16 and 24 (the corner lists of the fold then take
+    12 and 24 slots): every tile shape assembles the oracle's blocks."""
+    pb, ctx, _, _ = tiles
+    prob = valence_problem(nlon)
     o = oracle.Oracle.from_problem(prob)
-    for shape in ((8, 32), (8, 64)):
+    ref = []
+    for surf in (0, 1):
+        V, K = o.bem_dense(surf)
+        nv = V.shape[0]
+        M = np.stack([o.surface_mass_apply(surf, e) for e in np.eye(nv)], 1)
+        ref.append((-V if surf == 0 else V, 0.5 * M + (K if surf == 0 else -K)))
+    for shape in SHAPES:
         g = pb.Problem.from_inputs(ctx, prob)
         g.set_tile_shape(*shape)
         for surf in (0, 1):
-            V, K = o.bem_dense(surf)
-            nv = V.shape[0]
-            M = np.stack([o.surface_mass_apply(surf, e) for e in np.eye(nv)], 1)
             Vp, Kp = g.export_bem(surf)
-            eV = rowrel(Vp, -V if surf == 0 else V)
-            eK = rowrel(Kp, 0.5 * M + (K if surf == 0 else -K))
-            log(f"  valence-{9} mesh, shape {shape}, surf {surf}: V {eV:.2e} K {eK:.2e}")
+            eV, eK = rowrel(Vp, ref[surf][0]), rowrel(Kp, ref[surf][1])
+            log(f"  valence-{nlon} mesh, shape {shape}, surf {surf}: V {eV:.2e} K {eK:.2e}")
             assert eV < 1e-12 and eK < 1e-12
         g.close()
+
+
+def test_high_valence_solve_matches_oracle(tiles):
+    """A tight nonlinear solve on the valence-16 mesh (tuned shape) equals the
+    oracle's energy and surface potential to 1e-10."""
+    pb, ctx, _, _ = tiles
+    prob = valence_problem(16)
+    o = oracle.Oracle.from_problem(prob)
+    kw = dict(tol_nl=1e-10, tol_gr=1e-12, tol_gr0=1e-12, tol_omega=1e-9, l_e=0.0, max_gmres=20000)
+    g = pb.Problem.from_inputs(ctx, prob)
+    phi = np.zeros(2 * g.n)
+    r = g.solve(phi_out=phi, **kw)
+    ro, pl, pnl = o.solve(**kw)
+    gs = o.surface_nodes(0)
+    u, uo = (phi[:g.n] + phi[g.n:])[gs], (pl + pnl)[gs]
+    eE = abs(r["total"] - ro["total"]) / abs(ro["total"])
+    eU = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    log(f"  valence-16 solve: total {r['total']:.12f} vs {ro['total']:.12f} ({eE:.1e}), potential {eU:.1e}")
+    assert r["status"] == 0 and eE < 1e-10 and eU < 1e-10
+    g.close()
