@@ -125,6 +125,23 @@ pbfb_status pbfb_residual(pbfb_problem *p, int scheme, const double *phi, double
 pbfb_status pbfb_apply_jacobian(pbfb_problem *p, int scheme, const double *phi, const double *v, double *Jv,
                                 int mem, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of pbfb_residual (same kernels, same result) with every work
+ * buffer taken from a fixed per-device work array of 256 MiB that the
+ * library holds from its first context on that device until the process
+ * ends; the call itself allocates and frees nothing.  phi and F are device
+ * memory of the context's GPU (length n_unknowns); the problem must already
+ * be set up (pbfb_setup or any earlier call), with dense boundary operators.
+ * Errors: ESTATE (not set up), EINVAL (host pointers, matrix-free mode, or a
+ * problem whose work memory -- 8 bytes per FEM node, 32 per tet, and per
+ * interface of n vertices about 8 n^2 / 16 + 16 n -- exceeds 256 MiB, about
+ * 15k vertices per interface).  Every call on one GPU shares the work array:
+ * calls that overlap in time on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller.  F is complete when the stream
+ * reaches the end of the call. */
+pbfb_status pbfb_residual_noalloc(pbfb_problem *p, int scheme, const double *phi, double *F, void *hip_stream);
+
 /* ---- Newton solve (Sec. 2.4.2, 2.5, App. A, App. B) --------------------- */
 typedef struct {
     int scheme_first;    /* PBFB_T3 (cubic start, default) or PBFB_HS; ignored when n_schedule > 0 */

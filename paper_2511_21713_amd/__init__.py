@@ -25,7 +25,7 @@ T_APPLY, T_GEMV, T_SPMV, T_ASM, T_SING = 0, 1, 2, 3, 4
 
 EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_problem_create", "pbfb_problem_destroy",
            "pbfb_set_mesh", "pbfb_set_charges", "pbfb_set_params", "pbfb_get_sizes", "pbfb_setup",
-           "pbfb_reset_operators", "pbfb_residual",
+           "pbfb_reset_operators", "pbfb_residual", "pbfb_residual_noalloc",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
            "pbfb_server_submit", "pbfb_server_poll", "pbfb_request_footprint", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
            "pbfb_export_bem_rows", "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_two_field", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
@@ -101,6 +101,7 @@ def lib():
         L.pbfb_setup.argtypes = [P, P]
         L.pbfb_reset_operators.argtypes = [P]
         L.pbfb_residual.argtypes = [P, C.c_int, P, P, C.c_int, P]
+        L.pbfb_residual_noalloc.argtypes = [P, C.c_int, P, P, P]
         L.pbfb_apply_jacobian.argtypes = [P, C.c_int, P, P, P, C.c_int, P]
         L.pbfb_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.pbfb_solve_opts_default.restype = None
@@ -312,6 +313,15 @@ class Problem:
         o, mem2, keep2 = _vec(out, self.n, "out")
         assert mem == mem2
         _check(lib().pbfb_residual(self.h, scheme, p, o, mem, _stream(stream)))
+        return out
+
+    def residual_noalloc(self, scheme, phi, out, stream=None):
+        """pbfb_residual_noalloc: phi and out are device tensors; nothing is allocated."""
+        p, mem, keep = _vec(phi, self.n, "phi")
+        o, mem2, keep2 = _vec(out, self.n, "out")
+        if mem != MEM_DEVICE or mem2 != MEM_DEVICE:
+            raise PbfbError(EINVAL, "residual_noalloc takes device tensors")
+        _check(lib().pbfb_residual_noalloc(self.h, scheme, p, o, _stream(stream)))
         return out
 
     def apply_jacobian(self, scheme, phi, v, out=None, stream=None):

@@ -345,6 +345,13 @@ pbfb_status pbfb_ctx_create(int device, pbfb_ctx **out)
         PB_HIP(e);
     }
     (void)rules();
+    try {
+        noalloc_init(device); // device address of the allocation-free residual's work array
+    } catch (...) {
+        (void)hipStreamDestroy(c->c.stream);
+        delete c;
+        throw;
+    }
     *out = c;
     API_END
 }

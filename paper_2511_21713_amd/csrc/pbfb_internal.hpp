@@ -338,6 +338,7 @@ struct ApplyBufs {
     double *P[2] = {nullptr, nullptr};
 };
 int64_t sym_partials_doubles(int64_t nv);
+void noalloc_init(int device); // noalloc.hip: once per device, with the device current
 // A only (no J_N), with caller-provided buffers (no allocation, no timing)
 void coupled_apply_linear_bufs(Problem &p, const double *x, double *y, hipStream_t s, const ApplyBufs &bufs);
 // N_scheme(u) into out (FEM rows) with a caller-provided element buffer of 4 ntet doubles
