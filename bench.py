@@ -32,12 +32,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of k_gemv_f64 on this workload from the two rocprofv3
-# --pmc runs (FETCH_SIZE then WRITE_SIZE, each scaled by the factor the same
-# counter reads for a copy of known size), valid for the kernel source whose
-# hash is recorded with it; see profiles/gemv_f64_rna20k_hbm_counters.md.
+# HBM bytes per dense apply (k_bgemv + k_bgemv_fin, both interfaces) at the
+# 80k-triangle size from two rocprofv3 --pmc runs (FETCH_SIZE x 2: the
+# counter reads 0.5 x the bytes of a plain device copy; WRITE_SIZE x 1), valid
+# for the row routines whose source hash is recorded with them; see
+# profiles/gemv_rna80k_hbm_counters.md.
 GEMV_TRAFFIC = {
-    "rna20k_f64": {"src_sha256_16": "d9c2eb2ba90cdfa6", "bytes": 2.53424e9 + 7.9254e7 + 5.3112e7},
+    "rna80k_f32": {"src_sha256_16": "e99e76a41c79d012",
+                   "bytes": 9873106.12 * 2048 + 823614.31 * 1024 + 627200.24 * 2048 + 1283.35 * 1024},
+    "rna80k_f64": {"src_sha256_16": "e99e76a41c79d012",
+                   "bytes": 19709882.83 * 2048 + 822815.26 * 1024 + 627200.24 * 2048 + 1283.35 * 1024},
 }
 
 
@@ -233,18 +237,27 @@ def serve_requests(count, nmax):
     return probs
 
 
-def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0, budget=48 << 30, slots=16):
+def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0, budget=None, slots=16):
     """Serving workload: the requests `probs` (RNA-like generator with its
     partial charges, triangles log-uniform over 320..20 n_max^2, random kappa)
     arriving as a Poisson process at `load` x the measured service rate,
     submitted to a continuous-batching server with an HBM budget that binds
     (requests wait for admission); latency = submit to completion, admission
     wait = submit to admission.  The service rate is the mean solo solve time
-    of every fifth request (setup included)."""
+    of every fifth request (setup included).  Default budget: 1.1 x the
+    largest request's footprint (steady + setup workspace), so that a large
+    request waits for the running ones and the budget binds."""
     import numpy as np
 
     count = len(probs)
     ctx = pb.Context(0)
+    if budget is None:
+        fps = []
+        for p in probs:
+            g = pb.Problem.from_inputs(ctx, p, precision=precision)
+            fps.append(sum(g.footprint()))
+            g.close()
+        budget = int(1.1 * max(fps))
     svc = []
     for p in probs[::5]:
         g = pb.Problem.from_inputs(ctx, p, precision=precision)
@@ -417,7 +430,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="instances of the batched leg (0: skip)")
     ap.add_argument("--serve", type=int, default=40, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-nmax", type=int, default=64, help="largest icosphere frequency of served requests")
-    ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="HBM budget of the serving leg")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="HBM budget of the serving leg (0: 1.1 x the largest request's footprint)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,1.0")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="run one device copy of this size first (counter calibration for rocprofv3 --pmc)")
@@ -469,6 +483,7 @@ def main():
     nnz = fem_nnz(prob)
     nn = prob.nodes.shape[0]
     flops = apply_flops(nm, ns, nnz)
+    sym_tiles = all(a == b for a, b in f64["tiles"].values())
     kname = ("k_bgemv + k_bgemv_fin / k_gemv + k_gemv_fin (gemv_rows_sym: K' and the lower triangle of V', "
              f"{'FP32' if elem == 4 else 'FP64'} storage, FP64 accumulation, both interfaces)" if sym else
              f"k_bgemv / k_gemv (gemv_rows: dense [K'|V'] {'FP32' if elem == 4 else 'FP64'} GEMV, both interfaces)")
@@ -514,7 +529,10 @@ def main():
         out["fp64"] = leg_summary(f64, args.cmp_steps)
         g64_ms = f64["timing"]["gemv"][0]
         gb64 = gemv_bytes(nm, ns, 8, all(a == b for a, b in f64["tiles"].values()))
+        t64 = gemv_traffic_key(cfg, 8)
         out["fp64"]["gemv"] = {"ms": g64_ms, "bytes_per_launch": gb64,
+                               "traffic": (GEMV_TRAFFIC[t64]["bytes"] if t64 in GEMV_TRAFFIC and
+                                           gemv_source_hash() == GEMV_TRAFFIC[t64]["src_sha256_16"] else None),
                                "achieved_gbs": gb64 / (g64_ms * 1e-3) / 1e9 if g64_ms else None,
                                "frac": gb64 / (g64_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if g64_ms else None}
         out["mixed_speedup_vs_fp64"] = out["value"] / out["fp64"]["value"]
@@ -546,7 +564,8 @@ def main():
                 "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
                 "nnz": nnz, "value_bytes": e,
                 "cache_note": (f"each launch follows the dense apply of the same coupled apply, which streams "
-                               f"{gemv_bytes(nm, ns, e, sym) / 1e9:.1f} GB through the 256 MB Infinity Cache")}
+                               f"{gemv_bytes(nm, ns, e, sym_tiles) / 1e9:.1f} GB through the 256 MB "
+                               f"Infinity Cache")}
 
     out["bem_assembly"] = {"fp64": asm_report(f64, FP64_PEAK_TFLOPS, f64["steps"])}
     out["fem_spmv"] = {"fp64": spmv_report(f64, 8)}
@@ -573,10 +592,9 @@ def main():
     if args.serve > 0:
         reqs = serve_requests(args.serve, args.serve_nmax)
         loads = tuple(float(x) for x in args.serve_loads.split(","))
-        out["serving"] = {"mixed": serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED, loads,
-                                             budget=int(args.serve_budget_gb * 2**30)),
-                          "fp64": serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64, (0.8,),
-                                            budget=int(args.serve_budget_gb * 2**30))}
+        bud = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb > 0 else None
+        out["serving"] = {"mixed": serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED, loads, budget=bud),
+                          "fp64": serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64, (0.8,), budget=bud)}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle, bounded sample, extrapolated)")
         t0 = time.perf_counter()

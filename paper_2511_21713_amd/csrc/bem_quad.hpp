@@ -41,9 +41,10 @@ inline QRule6 q6arg()
     }
     return r;
 }
-// the orbit factors of the 6-point rule in FP32
+// the orbit factors of the 6-point rule and the products w_q b_q[a] in FP32
 struct QRule6F {
     float oA[2], oD[2];
+    float wb[6][3];
 };
 inline QRule6F q6farg()
 {
@@ -53,6 +54,8 @@ inline QRule6F q6farg()
         r.oA[o] = float(R.oA[o]);
         r.oD[o] = float(R.oD[o]);
     }
+    for (int q = 0; q < 6; ++q)
+        for (int a = 0; a < 3; ++a) r.wb[q][a] = float(R.w[q] * R.b[q][a]);
     return r;
 }
 

@@ -93,11 +93,15 @@ __device__ inline void gemv_rows(const MT *__restrict__ B, const double *__restr
 // groups of gsym_g chunks of the row stream), blk = r0 / 16.  Rows past n
 // contribute nothing.  Reads n + r0 + 16 entries of each row instead of 2 n.
 constexpr int GSYM = 4 * GEMV_RW;
-// chunks per LDS exchange: 32 KB of column partials per workgroup.  The
-// partials are FP64 for both storage precisions: with FP32 partials the
-// apply is linear only to FP32 rounding of the partial sums, which left
-// strongly charged instances short of the Newton tolerance in mixed mode.
-template <typename MT> constexpr int gsym_g() { return sizeof(MT) == 8 ? 8 : 4; }
+// chunks per LDS exchange (FP64 storage: 16, 64 KB of column partials per
+// workgroup, two workgroups per CU: measured 4 % faster than 8 at the
+// 80k-triangle size; FP32: 4, 32 KB).  The partials are FP64 for both
+// storage precisions: with FP32 partials the apply is linear only to FP32
+// rounding of the partial sums, which left strongly charged instances short
+// of the Newton tolerance in mixed mode.
+template <typename MT> constexpr int gsym_g() { return sizeof(MT) == 8 ? 16 : 4; }
+// occupancy of the dense-apply kernels: the FP64 symmetric form's LDS allows two workgroups per CU
+template <typename MT> constexpr int gemv_occupancy() { return sizeof(MT) == 8 ? 2 : 4; }
 template <typename MT> using sym_part_t = double;
 
 template <typename MT>

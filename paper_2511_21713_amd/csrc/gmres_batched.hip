@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
 // a kernel holding both row routines would be register-allocated for their
 // union and run at half the occupancy of either.
 template <typename MT>
-__global__ void __launch_bounds__(256, 4) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+__global__ void __launch_bounds__(256, gemv_occupancy<MT>()) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S)
 {
     const WItem it = wl[blockIdx.x];

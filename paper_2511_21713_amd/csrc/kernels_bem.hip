@@ -120,11 +120,10 @@ template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int6
 // column), so the reads pipeline.  MS >= the largest number of corners of
 // any vertex of either block: the lists past it hold only absent corners,
 // whose +0 terms are skipped.
-template <int TA, int TB, int MS, typename MT>
+template <int TA, int TB, int MS, typename MT, typename ST, typename XT>
 __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
-                                     const int (*sSb)[MS], double (*acc)[TB * 3 + 1], const double *Xl,
-                                     const int *vA, const int *vB, MT *__restrict__ U, int64_t ld, int64_t off,
-                                     double sc)
+                                     const int (*sSb)[MS], ST (*acc)[TB * 3 + 1], const XT *Xl, const int *vA,
+                                     const int *vB, MT *__restrict__ U, int64_t ld, int64_t off, double sc)
 {
     constexpr int NT = TA * TB;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -140,7 +139,7 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = Xl[3 * a + b];
+        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = ST(Xl[3 * a + b]);
     __syncthreads();
     constexpr int RMAX = TA * 3;
     constexpr int RPT = (RMAX + NT / (TB * 3) - 1) / (NT / (TB * 3)); // rows per thread, nB <= TB * 3
@@ -154,7 +153,7 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
             if (sa < RMAX) {
                 double v[MS];
 #pragma unroll
-                for (int l = 0; l < MS; ++l) v[l] = acc[sa][cb[l]];
+                for (int l = 0; l < MS; ++l) v[l] = double(acc[sa][cb[l]]);
 #pragma unroll
                 for (int l = 0; l < MS; ++l) t += v[l];
                 nrow = r + 1;
@@ -163,10 +162,11 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
         }
     }
     __syncthreads();
+    // (an FP32 tile stores the FP64 column sums rounded to FP32)
     if (colthread)
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
-            if (r < nrow) acc[r0 + r * rstep][jb] = colsum[r];
+            if (r < nrow) acc[r0 + r * rstep][jb] = ST(colsum[r]);
     __syncthreads();
     if (colthread) {
         const int64_t col = off + vB[jb];
@@ -175,7 +175,7 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
                 const int ra = sSa[ia][k];
-                v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
+                v[k] = double(acc[ra < 0 ? TA * 3 : ra][jb]);
             }
             double t = 0.0;
 #pragma unroll
@@ -191,12 +191,13 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
 // two operators; then V goes to column nv + vB[jb] with factor sV and K to
 // column vB[jb] with factor sK of row vA[ia].  Otherwise as fold_tile_one.
 typedef double dpair __attribute__((ext_vector_type(2))); // (V, K)
+typedef float fpair __attribute__((ext_vector_type(2)));  // (V, K) of an FP32 tile
 
-template <int TA, int TB, int MS, typename MT>
+template <int TA, int TB, int MS, typename MT, typename PT, typename XT>
 __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
-                                      const int (*sSb)[MS], dpair (*acc)[TB * 3 + 1], const double *Vl,
-                                      const double *Kl, const int *vA, const int *vB, MT *__restrict__ U, int64_t ld,
-                                      int64_t nv, double sV, double sK)
+                                      const int (*sSb)[MS], PT (*acc)[TB * 3 + 1], const XT *Vl, const XT *Kl,
+                                      const int *vA, const int *vB, MT *__restrict__ U, int64_t ld, int64_t nv,
+                                      double sV, double sK)
 {
     constexpr int NT = TA * TB;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -208,12 +209,13 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
         cb[l] = c < 0 ? TB * 3 : c;
     }
     const dpair zero = {0.0, 0.0};
-    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = zero;
-    if (tid < TA * 3) acc[tid][TB * 3] = zero;
+    const PT pzero = {0, 0};
+    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = pzero;
+    if (tid < TA * 3) acc[tid][TB * 3] = pzero;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = dpair{Vl[3 * a + b], Kl[3 * a + b]};
+        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = PT{Vl[3 * a + b], Kl[3 * a + b]};
     __syncthreads();
     // source corners: rows r0, r0 + rstep, ... of each thread, in rounds of
     // RC rows held in registers between the reads and the in-place writes
@@ -231,7 +233,7 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
                 if (sa < RMAX) {
                     dpair v[MS];
 #pragma unroll
-                    for (int l = 0; l < MS; ++l) v[l] = acc[sa][cb[l]];
+                    for (int l = 0; l < MS; ++l) v[l] = __builtin_convertvector(acc[sa][cb[l]], dpair);
 #pragma unroll
                     for (int l = 0; l < MS; ++l) t += v[l];
                     nrow = r + 1;
@@ -243,7 +245,7 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
         if (colthread)
 #pragma unroll
             for (int r = 0; r < RC; ++r)
-                if (r < nrow) acc[r0 + (rb + r) * rstep][jb] = colsum[r];
+                if (r < nrow) acc[r0 + (rb + r) * rstep][jb] = __builtin_convertvector(colsum[r], PT);
         __syncthreads();
     }
     if (colthread) {
@@ -253,7 +255,7 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
                 const int ra = sSa[ia][k];
-                v[k] = acc[ra < 0 ? TA * 3 : ra][jb];
+                v[k] = __builtin_convertvector(acc[ra < 0 ? TA * 3 : ra][jb], dpair);
             }
             dpair t = zero;
 #pragma unroll
@@ -310,8 +312,8 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ int sVa[TA][3], sVb[TB][3];
     __shared__ int sSa[TA * 3][MS], sSb[TB * 3][MS];
     __shared__ int sIa[TA * 3], sIb[TB * 3]; // operator index of each block vertex
-    // the tile: (V, K) pairs (FP64) or one operator at a time (FP32); + a zero row and a zero column
-    __shared__ std::conditional_t<F32, double, dpair> acc[TA * 3 + 1][TB * 3 + 1];
+    // the tile of (V, K) pairs in the evaluation precision, + a zero row and a zero column
+    __shared__ std::conditional_t<F32, fpair, dpair> acc[TA * 3 + 1][TB * 3 + 1];
 
     const int tid = threadIdx.x;
     const int nA = A_nv[bA], nB = B_nv[bB];
@@ -357,11 +359,13 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
 
     // this thread's pair (target tl, source sl)
     const int tl = tid / TB, sl = tid % TB;
-    double Vl[9], Kl[9], Ktl[SYM ? 9 : 1];
+    // the pair's 3x3 blocks, summed over its 36 quadrature pairs in the
+    // evaluation precision (FP32 tiles: widened once, in the fold)
+    RT Vl[9], Kl[9], Ktl[SYM ? 9 : 1];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Vl[k] = Kl[k] = 0.0;
+    for (int k = 0; k < 9; ++k) Vl[k] = Kl[k] = RT(0);
 #pragma unroll
-    for (int k = 0; k < (SYM ? 9 : 1); ++k) Ktl[k] = 0.0;
+    for (int k = 0; k < (SYM ? 9 : 1); ++k) Ktl[k] = RT(0);
     bool touch = false;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
@@ -383,7 +387,7 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
                 dm[q] = (sY[sl][3 * q] - xa0) * m0 + (sY[sl][3 * q + 1] - xa1) * m1 + (sY[sl][3 * q + 2] - xa2) * m2;
         }
         const RT kap = RT(kappa);
-        const double sc = sAa[tl] * sAb[sl] * INV4PI;
+        const RT sc = RT(sAa[tl] * sAb[sl] * INV4PI);
         // target point p outermost: 6-term source sums, then folded into the 3x3 blocks
         // (not unrolled: the 6 source points of one target point are the unit of ILP).
         // The source points lie in the plane of the source triangle, so the
@@ -440,32 +444,30 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const double wa = sc * R.w[p] * R.b[p][a];
-                Vl[3 * a] += wa * double(sv0);
-                Vl[3 * a + 1] += wa * double(sv1);
-                Vl[3 * a + 2] += wa * double(sv2);
-                Kl[3 * a] += wa * double(sk0);
-                Kl[3 * a + 1] += wa * double(sk1);
-                Kl[3 * a + 2] += wa * double(sk2);
+                RT wb;
+                if constexpr (F32) wb = RF.wb[p][a];
+                else wb = R.w[p] * R.b[p][a];
+                const RT wa = sc * wb;
+                Vl[3 * a] += wa * sv0;
+                Vl[3 * a + 1] += wa * sv1;
+                Vl[3 * a + 2] += wa * sv2;
+                Kl[3 * a] += wa * sk0;
+                Kl[3 * a + 1] += wa * sk1;
+                Kl[3 * a + 2] += wa * sk2;
                 if constexpr (SYM) {
-                    Ktl[3 * a] += wa * double(st0);
-                    Ktl[3 * a + 1] += wa * double(st1);
-                    Ktl[3 * a + 2] += wa * double(st2);
+                    Ktl[3 * a] += wa * st0;
+                    Ktl[3 * a + 1] += wa * st1;
+                    Ktl[3 * a + 2] += wa * st2;
                 }
             }
         }
     }
 
-    if constexpr (F32) {
-        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, sIa, sIb, U, ld, nv, sV);
-        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Kl, sIa, sIb, U, ld, 0, sK);
-    } else {
-        fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, sIa, sIb, U, ld, nv, sV, sK);
-    }
+    fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, sIa, sIb, U, ld, nv, sV, sK);
     if constexpr (SYM) {
         __syncthreads();
-        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, reinterpret_cast<double (*)[TB * 3 + 1]>(acc), Ktl,
-                                  sIa, sIb, T, nv, 0, sK);
+        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, reinterpret_cast<RT (*)[TB * 3 + 1]>(acc), Ktl, sIa,
+                                  sIb, T, nv, 0, sK);
     }
 }
 
@@ -1285,6 +1287,8 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     PB_HIP(hipGetLastError());
     // diagonal of V', symmetric storage use (Delta from the stored values),
     // approximate inverse of the single-layer block (from the stored values)
+    // symmetric use: the apply reads K' and the lower triangle of V' (square
+    // tiles leave the regular part of V' bitwise symmetric)
     S.sym = sym;
     PB_HIP(hipMemsetAsync(p.d_bad, 0, sizeof(int), s));
     if (f32) {

@@ -54,7 +54,7 @@ struct GemvSurf {
 };
 
 template <typename MT>
-__global__ void __launch_bounds__(256, 4) k_gemv(GemvSurf S0, GemvSurf S1, int64_t nblk0)
+__global__ void __launch_bounds__(256, gemv_occupancy<MT>()) k_gemv(GemvSurf S0, GemvSurf S1, int64_t nblk0)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool s1 = blockIdx.x >= nblk0;

@@ -128,6 +128,34 @@ def test_symmetric_apply_matches_full_rows(tiles, precision):
         assert rowrel(Js[None, :], o.apply_jacobian(oracle.HS, phi, v)[None, :]) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(16, 16), (16, 32)])
+def test_mixed_apply_accumulates_in_fp64(tiles, shape):
+    """Mixed precision stores the boundary blocks in FP32 but forms every
+    product in FP64: the device's Gamma_m and Gamma_s rows of J v equal a host
+    FP64 product of the exported (widened) stored rows to 1e-13 of the sum of
+    the products' magnitudes, far below the FP32 rounding of a partial sum."""
+    pb, ctx, prob, refs = tiles
+    g = pb.Problem.from_inputs(ctx, prob, precision=pb.MIXED)
+    g.set_tile_shape(*shape)
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal(g.n)
+    v = rng.standard_normal(g.n)
+    Jv = g.apply_jacobian(oracle.LIN, phi, v)
+    o = oracle.Oracle.from_problem(prob)
+    off = g.n_nodes
+    for surf, nv in ((0, g.n_m), (1, g.n_s)):
+        Vp, Kp = g.export_bem(surf)
+        u = v[o.surface_nodes(surf)]
+        lam = v[off:off + nv]
+        host = Kp @ u + Vp @ lam
+        scale = np.abs(Kp) @ np.abs(u) + np.abs(Vp) @ np.abs(lam)
+        err = (np.abs(Jv[off:off + nv] - host) / scale).max()
+        log(f"  shape {shape} surf {surf}: mixed device rows vs host FP64 product {err:.2e}")
+        assert err < 1e-13
+        off += nv
+    g.close()
+
+
 def test_assembly_is_reproducible_and_launch_order_fixed(tiles):
     """The tiles of one launch add into disjoint operator entries (coloured
     blocks) and the launches follow each other, so the stored operators are
