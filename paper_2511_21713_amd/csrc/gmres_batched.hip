@@ -84,7 +84,7 @@ struct WItem {
 };
 
 constexpr int CH = 256;      // rows per chunk: one per thread of a workgroup
-constexpr int GROWS = 4 * GEMV_RW; // GEMV rows per workgroup (4 wavefronts)
+constexpr int GROWS = GSYM; // GEMV rows per workgroup
 
 
 __device__ inline bool applies(int st) { return st == G_ARN || st == G_RES; }
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_bcheb(const WItem *__restrict__ wl, con
 // a kernel holding both row routines would be register-allocated for their
 // union and run at half the occupancy of either.
 template <typename MT>
-__global__ void __launch_bounds__(256, gemv_occupancy<MT>()) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
+__global__ void __launch_bounds__(GEMV_THREADS, gemv_occupancy<MT>()) k_bgemv(const WItem *__restrict__ wl, const GDesc *__restrict__ D,
                                                const GState *__restrict__ S)
 {
     const WItem it = wl[blockIdx.x];
@@ -781,8 +781,8 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         if (tm) tm->begin(T_APPLY, s);
         hipLaunchKernelGGL(k_bpack, dim3(npack), dim3(256), 0, s, dpack, dD, dS);
         if (tm) tm->begin(T_GEMV, s);
-        if (types & 1) hipLaunchKernelGGL(k_bgemv<double>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
-        if (types & 2) hipLaunchKernelGGL(k_bgemv<float>, dim3(ngemv), dim3(256), 0, s, dgemv, dD, dS);
+        if (types & 1) hipLaunchKernelGGL(k_bgemv<double>, dim3(ngemv), dim3(GEMV_THREADS), 0, s, dgemv, dD, dS);
+        if (types & 2) hipLaunchKernelGGL(k_bgemv<float>, dim3(ngemv), dim3(GEMV_THREADS), 0, s, dgemv, dD, dS);
         if (nfin) hipLaunchKernelGGL(k_bgemv_fin, dim3(nfin), dim3(256), 0, s, dfin, dD, dS);
         // matrix-free instances: their own launches, gated by their state word
         for (size_t q = 0; q < jobs.size() && any_mf; ++q) {

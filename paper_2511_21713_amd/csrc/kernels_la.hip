@@ -54,7 +54,7 @@ struct GemvSurf {
 };
 
 template <typename MT>
-__global__ void __launch_bounds__(256, gemv_occupancy<MT>()) k_gemv(GemvSurf S0, GemvSurf S1, int64_t nblk0)
+__global__ void __launch_bounds__(GEMV_THREADS, gemv_occupancy<MT>()) k_gemv(GemvSurf S0, GemvSurf S1, int64_t nblk0)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool s1 = blockIdx.x >= nblk0;
@@ -193,9 +193,9 @@ static void gemv_launch(Problem &p, const ApplyBufs &bf, double *y, hipStream_t 
     const GemvSurf G0 = gemv_surf(p, 0, bf.xm, y + p.nn, bf.P[0]), G1 = gemv_surf(p, 1, bf.xs, y + p.nn + M.nv, bf.P[1]);
     if (timed) p.timer.begin(T_GEMV, s);
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, G0, G1, nb0);
+        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(GEMV_THREADS), 0, s, G0, G1, nb0);
     else
-        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(256), 0, s, G0, G1, nb0);
+        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(GEMV_THREADS), 0, s, G0, G1, nb0);
     if (G0.sym || G1.sym) {
         const int64_t f0 = skip_m ? 0 : (M.nv + GFIN_ROWS - 1) / GFIN_ROWS, f1 = (S.nv + GFIN_ROWS - 1) / GFIN_ROWS;
         hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0 + f1)), dim3(256), 0, s, G0, G1, f0);
@@ -295,9 +295,9 @@ static void gemv_m(Problem &p, const double *xm, double *y, hipStream_t s)
                                                : nullptr);
     const int64_t nb0 = (G.n + GSYM - 1) / GSYM, f0 = (G.n + GFIN_ROWS - 1) / GFIN_ROWS;
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0)), dim3(256), 0, s, G, G, nb0);
+        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0)), dim3(GEMV_THREADS), 0, s, G, G, nb0);
     else
-        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0)), dim3(256), 0, s, G, G, nb0);
+        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0)), dim3(GEMV_THREADS), 0, s, G, G, nb0);
     if (G.sym) hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0)), dim3(256), 0, s, G, G, f0);
 }
 
