@@ -30,12 +30,12 @@
 // In mixed precision the regular tiles evaluate the kernels in FP32: each
 // quadrature point is held as an FP32 offset from its triangle's centroid,
 // the centroid difference of a pair is formed in FP64 and rounded once, so
-// x - y never cancels large coordinates in FP32.  The 6-term sums over the
-// source points of a pair are FP32; everything from the pair's 3x3 blocks
-// upward (the pair blocks and their fold onto a tile's vertices) accumulates
-// in FP64, and the touching pairs stay FP64 throughout; each tile's sum is
-// added to the FP32 stored entry in FP64 and rounded (an entry receives one
-// tile's sum for each pair of blocks holding its two vertices).
+// x - y never cancels large coordinates in FP32.  A pair's 3x3 V and K
+// blocks are summed over its 36 quadrature pairs in FP32; the fold onto a
+// tile's vertices adds in FP64 (its intermediate column sums are kept in LDS
+// as FP32), and each tile's sum is added to the FP32 stored entry in FP64
+// and rounded once (an entry receives one tile's sum for each pair of blocks
+// holding its two vertices).  The touching pairs stay FP64 throughout.
 #include <cmath>
 #include <type_traits>
 

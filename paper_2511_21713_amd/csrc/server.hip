@@ -44,7 +44,7 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
     for (int w = 0; w < 2 && !p.bem_mf; ++w) {
         const SurfaceTopo &T = p.topo[w];
         dense += size_t(T.nv) * bem_ld(T.nv) * elem;
-        dense += size_t((T.nv + 15) / 16) * T.nv * 8 + size_t(T.nv) * 20 * 12; // symmetric use: partials, Delta
+        dense += size_t(sym_partials_doubles(T.nv)) * 8 + size_t(T.nv) * 20 * 12; // symmetric use: partials, Delta
         dense += size_t(T.nt) * 18 * 8 * 2 + size_t(T.nv) * (8 * 8 + 16 * 4);  // Morton copies, block tables, rings
         tmp = std::max(tmp, (size_t(T.nv) * T.nv * elem + 255) / 256 * 256 + size_t(T.nv) * 3 * 8 +
                                 T.tp_sig.size() * 18 * 8 + 64);
