@@ -110,6 +110,10 @@ def lib():
         L.pbref_reaction_potential.argtypes = [P, dp, C.c_int64, dp, dp]
         L.pbref_set_two_field.argtypes = [P, C.c_int64]
         L.pbref_lambda_m.argtypes = [P, dp, C.c_int, dp]
+        L.pbref_set_reaction_surface.argtypes = [P, C.c_int64, dp, C.c_int64, ip]
+        L.pbref_gamma_m_vertices.argtypes = [P]
+        L.pbref_gamma_m_vertices.restype = C.c_int64
+        L.pbref_gamma_m_trace.argtypes = [P, dp, dp]
         L.pbref_rule_tri6.argtypes = [dp, dp]
         L.pbref_rule_tet27.argtypes = [dp, dp]
         L.pbref_rule_gauss01.argtypes = [C.c_int, dp, dp]
@@ -223,7 +227,7 @@ class Oracle:
     """One oracle problem instance built from mesh, charges and parameters."""
 
     def __init__(self, nodes, tets, tri_m, tri_s, q_xyz, q_z, eps_in, eps_out, kappa,
-                 temperature=298.15, reg_order=0, n_ss=4, n_tets_m=0):
+                 temperature=298.15, reg_order=0, n_ss=4, n_tets_m=0, reaction_surface=None):
         L = lib()
         self._keep = [_f64(nodes), np.ascontiguousarray(tets, np.int32), np.ascontiguousarray(tri_m, np.int32),
                       np.ascontiguousarray(tri_s, np.int32), _f64(np.reshape(q_xyz, (-1, 3))), _f64(q_z)]
@@ -236,6 +240,8 @@ class Oracle:
         self.two_field = n_tets_m > 0
         if self.two_field and L.pbref_set_two_field(self.h, int(n_tets_m)) != 0:
             raise ValueError("bad solute tet count")
+        if reaction_surface is not None:
+            self.set_reaction_surface(*reaction_surface)
         s = np.zeros(4, np.int64)
         L.pbref_sizes(self.h, _l(s))
         self.n_nodes, self.n_m, self.n_s, self.n = (int(v) for v in s)
@@ -246,6 +252,8 @@ class Oracle:
     @classmethod
     def from_problem(cls, p, **kw):
         kw.setdefault("n_tets_m", getattr(p, "n_tets_m", 0))
+        if getattr(p, "rs_verts", None) is not None:
+            kw.setdefault("reaction_surface", (p.rs_verts, p.rs_tris))
         return cls(p.nodes, p.tets, p.tri_m, p.tri_s, p.q_xyz, p.q_z, p.eps_in, p.eps_out, p.kappa, **kw)
 
     def __del__(self):
@@ -406,10 +414,34 @@ class Oracle:
         lib().pbref_energy(self.h, _d(pl), _d(pn) if pn is not None else None, _d(out))
         return dict(total=out[0], lc=out[1], nc=out[2], dg_omega_i=out[3])
 
+    def set_reaction_surface(self, verts, tris):
+        """Two-field form: the Gamma_m mesh independent of the volume mesh
+        (lam_m and the reaction potential live on it; the trace of u is its P1
+        interpolant at the vertices).  verts = None removes it."""
+        if verts is None:
+            lib().pbref_set_reaction_surface(self.h, 0, None, 0, None)
+            self._rs = None
+            return
+        v = _f64(np.reshape(verts, (-1, 3)))
+        t = np.ascontiguousarray(tris, np.int32)
+        r = lib().pbref_set_reaction_surface(self.h, v.shape[0], _d(v), t.shape[0], _i(t))
+        if r == -3:
+            raise ValueError("a Gamma_m vertex lies outside the FEM mesh")
+        if r != 0:
+            raise ValueError("bad Gamma_m surface")
+        self._rs = (v, t)
+
+    def gamma_m_trace(self, u):
+        """u on the vertices of the surface that carries lam_m."""
+        u = _f64(u)
+        out = np.zeros(int(lib().pbref_gamma_m_vertices(self.h)))
+        lib().pbref_gamma_m_trace(self.h, _d(u), _d(out))
+        return out
+
     def lambda_m(self, u, with_load=True):
         """lam_m from the trace of u on Gamma_m (Sec. 2.3.1), by a dense solve."""
         u = _f64(u)
-        out = np.zeros(self.n_m)
+        out = np.zeros(int(lib().pbref_gamma_m_vertices(self.h)))
         if lib().pbref_lambda_m(self.h, _d(u), int(bool(with_load)), _d(out)) != 0:
             raise RuntimeError("singular single layer")
         return out

@@ -274,7 +274,10 @@ int pbref_rule_tet27(double *bary, double *w)
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int64_t nv, nt;
-    int32_t *g;       /* local vertex -> FEM node */
+    int32_t *g;       /* local vertex -> FEM node (a surface given over FEM nodes) */
+    double *xv;       /* own vertex coordinates (a surface given independently), else NULL */
+    int32_t *itet;    /* independent surface: the tet holding each vertex ... */
+    double *iw;       /* ... and the vertex's 4 barycentric coordinates in it */
     int32_t *tri;     /* triangles in local vertex ids, 3*nt */
     int32_t *v2t_ptr; /* vertex -> triangles adjacency */
     int32_t *v2t;
@@ -289,7 +292,7 @@ struct pbref {
     int32_t *tet;
     double *qx, *qz;
     double eps_m, eps_s, kappa, temp, lB, kT;
-    surface s[2];
+    surface s[3];    /* Gamma_m, Gamma_s; s[2]: the independent Gamma_m mesh of the two-field form */
     int32_t *loc[2]; /* FEM node -> local surface vertex or -1 */
     int reg_order, n_ss;
     int nrq;
@@ -304,6 +307,10 @@ struct pbref {
      * term; otherwise nt_i = nt and every tet is in the shell */
     int64_t nt_i;
     int two_field;
+    /* two-field form with a Gamma_m surface mesh independent of the volume
+     * mesh (s[2]): the reaction potential and lam_m live on it, and its
+     * trace of u is the P1 interpolant of u at its vertices (Sec. 2.3.1) */
+    int has_r;
 };
 
 /* permittivity and reaction coefficient eps kappa^2 of tet t */
@@ -447,22 +454,28 @@ pbref *pbref_create(int64_t n_nodes, const double *nodes, int64_t n_tets, const 
     return p;
 }
 
+static void free_surface(surface *S)
+{
+    free(S->g);
+    free(S->xv);
+    free(S->itet);
+    free(S->iw);
+    free(S->tri);
+    free(S->v2t_ptr);
+    free(S->v2t);
+    free(S->area);
+    free(S->nrm);
+    free(S->V);
+    free(S->K);
+    memset(S, 0, sizeof *S);
+}
+
 void pbref_destroy(pbref *p)
 {
     if (!p) return;
     free(p->rhs_extra);
-    for (int w = 0; w < 2; ++w) {
-        surface *S = &p->s[w];
-        free(S->g);
-        free(S->tri);
-        free(S->v2t_ptr);
-        free(S->v2t);
-        free(S->area);
-        free(S->nrm);
-        free(S->V);
-        free(S->K);
-        free(p->loc[w]);
-    }
+    for (int w = 0; w < 3; ++w) free_surface(&p->s[w]);
+    for (int w = 0; w < 2; ++w) free(p->loc[w]);
     free(p->x);
     free(p->tet);
     free(p->qx);
@@ -515,7 +528,10 @@ static void kernel_eval(double kappa, const double *x, const double *y, const do
     *dg = vdot(d, ny) * (1.0 + kappa * r) * e / (4.0 * PI * r * r * r);
 }
 
-static const double *vx(const pbref *p, const surface *S, int32_t lv) { return p->x + 3 * S->g[lv]; }
+static const double *vx(const pbref *p, const surface *S, int32_t lv)
+{
+    return S->xv ? S->xv + 3 * lv : p->x + 3 * S->g[lv];
+}
 
 /* Regular (non-touching) pair: tensor product of the triangle rule. */
 static void pair_regular(const pbref *p, const surface *S, int64_t ta, int64_t sb, double V[3][3],
@@ -764,9 +780,8 @@ static double coulomb(const pbref *p, const double *x)
 }
 
 /* f_i = int_{Gamma_m} phi_i phi_coul, with the regular triangle rule. */
-void pbref_coulomb_load(const pbref *p, double *f)
+static void coulomb_load_on(const pbref *p, const surface *S, double *f)
 {
-    const surface *S = &p->s[0];
     memset(f, 0, sizeof(double) * S->nv);
     for (int64_t t = 0; t < S->nt; ++t)
         for (int q = 0; q < p->nrq; ++q) {
@@ -778,6 +793,8 @@ void pbref_coulomb_load(const pbref *p, double *f)
             for (int a = 0; a < 3; ++a) f[S->tri[3 * t + a]] += c * l[a];
         }
 }
+
+void pbref_coulomb_load(const pbref *p, double *f) { coulomb_load_on(p, &p->s[0], f); }
 
 /* ------------------------------------------------------------------------- */
 /* FEM on the shell                                                           */
@@ -1066,6 +1083,121 @@ int pbref_set_two_field(pbref *p, int64_t n_tets_m)
     if (n_tets_m <= 0 || n_tets_m >= p->nt) return -1;
     p->nt_i = p->nt - n_tets_m;
     p->two_field = 1;
+    return 0;
+}
+
+/* The tet of the FEM mesh that holds x: the one whose smallest barycentric
+ * coordinate of x is largest (ties: the lowest tet id), and those
+ * coordinates.  -1 if x lies outside every tet (by more than rounding). */
+static int64_t locate_point(const pbref *p, const double *x, double l_out[4])
+{
+    int64_t best = -1;
+    double bmin = -1e300;
+    for (int64_t t = 0; t < p->nt; ++t) {
+        double G[4][3], vol, l[4], d[3], lo = 1e300;
+        tet_geom(p, t, G, &vol);
+        vsub(x, p->x + 3 * p->tet[4 * t], d);
+        for (int a = 0; a < 4; ++a) {
+            l[a] = (a == 0 ? 1.0 : 0.0) + vdot(G[a], d);
+            if (l[a] < lo) lo = l[a];
+        }
+        if (lo > bmin) {
+            bmin = lo;
+            best = t;
+            memcpy(l_out, l, sizeof(double) * 4);
+        }
+    }
+    return (best >= 0 && bmin >= -1e-10) ? best : -1;
+}
+
+/* Two-field form: a Gamma_m surface mesh given independently of the volume
+ * mesh (its own vertices verts[3 nv] and triangles tri[3 nt], oriented like
+ * the interface).  Sec. 2.3.1 takes the trace of the volume solution on it
+ * by interpolation between the two meshes: here the P1 interpolant, i.e.
+ * at each vertex the value of u in the tet that holds the vertex.  nv = 0
+ * removes it.  Returns -1 for bad sizes or ids, -3 if a vertex lies outside
+ * the FEM mesh. */
+int pbref_set_reaction_surface(pbref *p, int64_t nv, const double *verts, int64_t nt, const int32_t *tri)
+{
+    surface *S = &p->s[2];
+    free_surface(S);
+    p->has_r = 0;
+    if (nv == 0) return 0;
+    if (nv < 3 || nt < 1) return -1;
+    for (int64_t k = 0; k < 3 * nt; ++k)
+        if (tri[k] < 0 || tri[k] >= nv) return -1;
+    S->nv = nv;
+    S->nt = nt;
+    S->kappa = 0.0;
+    S->xv = malloc(sizeof(double) * 3 * nv);
+    memcpy(S->xv, verts, sizeof(double) * 3 * nv);
+    S->g = malloc(sizeof(int32_t) * nv);
+    for (int64_t i = 0; i < nv; ++i) S->g[i] = -1; /* no FEM node */
+    S->tri = malloc(sizeof(int32_t) * 3 * nt);
+    memcpy(S->tri, tri, sizeof(int32_t) * 3 * nt);
+    S->area = malloc(sizeof(double) * nt);
+    S->nrm = malloc(sizeof(double) * 3 * nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        const double *a = vx(p, S, tri[3 * t]), *b = vx(p, S, tri[3 * t + 1]), *c = vx(p, S, tri[3 * t + 2]);
+        double e1[3], e2[3], n[3];
+        vsub(b, a, e1);
+        vsub(c, a, e2);
+        vcross(e1, e2, n);
+        double len = sqrt(vdot(n, n));
+        S->area[t] = 0.5 * len;
+        for (int d = 0; d < 3; ++d) S->nrm[3 * t + d] = n[d] / len;
+    }
+    S->v2t_ptr = calloc(nv + 1, sizeof(int32_t));
+    for (int64_t t = 0; t < 3 * nt; ++t) S->v2t_ptr[S->tri[t] + 1]++;
+    for (int64_t i = 0; i < nv; ++i) S->v2t_ptr[i + 1] += S->v2t_ptr[i];
+    S->v2t = malloc(sizeof(int32_t) * 3 * nt);
+    int32_t *fill = calloc(nv, sizeof(int32_t));
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = S->tri[3 * t + k];
+            S->v2t[S->v2t_ptr[v] + fill[v]++] = (int32_t)t;
+        }
+    free(fill);
+    S->itet = malloc(sizeof(int32_t) * nv);
+    S->iw = malloc(sizeof(double) * 4 * nv);
+    int bad = 0;
+#pragma omp parallel for reduction(| : bad)
+    for (int64_t i = 0; i < nv; ++i) {
+        int64_t t = locate_point(p, S->xv + 3 * i, S->iw + 4 * i);
+        S->itet[i] = (int32_t)t;
+        if (t < 0) bad = 1;
+    }
+    if (bad) {
+        free_surface(S);
+        return -3;
+    }
+    p->has_r = 1;
+    return 0;
+}
+
+/* Values of u on the vertices of S: node selection for a surface given
+ * over FEM nodes, the P1 interpolant for an independent one. */
+static void surface_trace(const pbref *p, const surface *S, const double *u, double *out)
+{
+    for (int64_t i = 0; i < S->nv; ++i) {
+        if (S->itet) {
+            const int32_t *T = p->tet + 4 * (int64_t)S->itet[i];
+            const double *l = S->iw + 4 * i;
+            out[i] = l[0] * u[T[0]] + l[1] * u[T[1]] + l[2] * u[T[2]] + l[3] * u[T[3]];
+        } else {
+            out[i] = u[S->g[i]];
+        }
+    }
+}
+
+/* the surface that carries lam_m and the reaction potential */
+static int gamma_m_index(const pbref *p) { return (p->two_field && p->has_r) ? 2 : 0; }
+
+int64_t pbref_gamma_m_vertices(const pbref *p) { return p->s[gamma_m_index(p)].nv; }
+
+int pbref_gamma_m_trace(const pbref *p, const double *u, double *out)
+{
+    surface_trace(p, &p->s[gamma_m_index(p)], u, out);
     return 0;
 }
 
@@ -1679,10 +1811,11 @@ int pbref_gmres(pbref *p, int scheme, const double *phi, const double *b, double
     return pbref_gmres_pc(p, scheme, phi, b, x, tol, restart, maxit, PBREF_PC_DIAG, 1, 1.0, iters);
 }
 
-int pbref_reaction_potential(const pbref *p, const double *phi, int64_t np, const double *pts, double *out)
+/* u_r(x) = (V lam)(x) - (K um)(x) over the surface S (eq.
+ * Potential_in_Omega_m), with lam and um its per-vertex lam_m and trace */
+static void reaction_potential_on(const pbref *p, const surface *S, const double *lam, const double *um,
+                                  int64_t np, const double *pts, double *out)
 {
-    const surface *S = &p->s[0];
-    const double *lam = phi + p->nn;
 #pragma omp parallel for
     for (int64_t k = 0; k < np; ++k) {
         double s = 0.0;
@@ -1694,7 +1827,7 @@ int pbref_reaction_potential(const pbref *p, const double *phi, int64_t np, cons
                 for (int a = 0; a < 3; ++a) {
                     for (int d = 0; d < 3; ++d) y[d] += l[a] * vx(p, S, T[a])[d];
                     lh += l[a] * lam[T[a]];
-                    uh += l[a] * phi[S->g[T[a]]];
+                    uh += l[a] * um[T[a]];
                 }
                 double g, dg;
                 kernel_eval(0.0, pts + 3 * k, y, S->nrm + 3 * t, &g, &dg);
@@ -1703,6 +1836,15 @@ int pbref_reaction_potential(const pbref *p, const double *phi, int64_t np, cons
         }
         out[k] = s;
     }
+}
+
+int pbref_reaction_potential(const pbref *p, const double *phi, int64_t np, const double *pts, double *out)
+{
+    const surface *S = &p->s[0];
+    double *um = malloc(sizeof(double) * (S->nv > 0 ? S->nv : 1));
+    surface_trace(p, S, phi, um);
+    reaction_potential_on(p, S, phi + p->nn, um, np, pts, out);
+    free(um);
     return 0;
 }
 
@@ -1746,15 +1888,16 @@ static int dense_solve(int64_t n, double *A, double *r)
  * Phi_L carries the charges; the correction Phi_NL does not). */
 int pbref_lambda_m(pbref *p, const double *u, int with_load, double *lam)
 {
-    int r = pbref_bem_dense(p, 0);
+    const int w = gamma_m_index(p);
+    int r = pbref_bem_dense(p, w);
     if (r) return r;
-    const surface *S = &p->s[0];
+    const surface *S = &p->s[w];
     int64_t nm = S->nv;
     double *um = malloc(sizeof(double) * nm), *fm = malloc(sizeof(double) * nm);
     double *A = malloc(sizeof(double) * nm * nm);
-    for (int64_t i = 0; i < nm; ++i) um[i] = u[S->g[i]];
-    pbref_surface_mass_apply(p, 0, um, lam);
-    if (with_load) pbref_coulomb_load(p, fm);
+    surface_trace(p, S, u, um);
+    pbref_surface_mass_apply(p, w, um, lam);
+    if (with_load) coulomb_load_on(p, S, fm);
     for (int64_t i = 0; i < nm; ++i) {
         double s = 0.5 * lam[i];
         for (int64_t j = 0; j < nm; ++j) s += S->K[i * nm + j] * um[j];
@@ -1773,34 +1916,35 @@ int pbref_lambda_m(pbref *p, const double *u, int with_load, double *lam)
  * dG = kT/(4 pi l_B) * 1/2 eps_s kappa^2 int (u sinh u - 2 cosh u + 2). */
 int pbref_energy(pbref *p, const double *phi_lin, const double *phi_nl, double out[4])
 {
-    double *pl = NULL, *pn = NULL;
-    if (p->two_field) {
-        /* the reaction potential needs lam_m: recover it from the trace of u
-         * for each part (Sec. 2.3.1) */
-        const int64_t n = nunk(p);
-        pl = malloc(sizeof(double) * n);
-        memcpy(pl, phi_lin, sizeof(double) * n);
-        int r = pbref_lambda_m(p, phi_lin, 1, pl + p->nn);
-        if (!r && phi_nl) {
-            pn = malloc(sizeof(double) * n);
-            memcpy(pn, phi_nl, sizeof(double) * n);
-            r = pbref_lambda_m(p, phi_nl, 0, pn + p->nn);
-        }
-        if (r) {
-            free(pl);
-            free(pn);
-            return r;
-        }
-        phi_lin = pl;
-        if (phi_nl) phi_nl = pn;
-    }
+    /* the reaction potential from lam_m and the trace of u on Gamma_m; in the
+     * two-field form lam_m is recovered from the trace for each part first
+     * (Sec. 2.3.1), on the independent Gamma_m mesh when one is set */
+    const int w = p->two_field ? gamma_m_index(p) : 0;
+    const surface *S = &p->s[w];
+    const int64_t nm = S->nv > 0 ? S->nv : 1;
+    double *lam = malloc(sizeof(double) * nm), *um = malloc(sizeof(double) * nm);
     double *ur = malloc(sizeof(double) * (p->nq > 0 ? p->nq : 1));
     double lc = 0.0, nc = 0.0;
-    pbref_reaction_potential(p, phi_lin, p->nq, p->qx, ur);
-    for (int64_t k = 0; k < p->nq; ++k) lc += 0.5 * p->kT * p->qz[k] * ur[k];
-    if (phi_nl) {
-        pbref_reaction_potential(p, phi_nl, p->nq, p->qx, ur);
-        for (int64_t k = 0; k < p->nq; ++k) nc += 0.5 * p->kT * p->qz[k] * ur[k];
+    for (int part = 0; part < 2; ++part) {
+        const double *phi = part == 0 ? phi_lin : phi_nl;
+        if (!phi) continue;
+        if (p->two_field) {
+            int r = pbref_lambda_m(p, phi, part == 0, lam);
+            if (r) {
+                free(lam);
+                free(um);
+                free(ur);
+                return r;
+            }
+        } else {
+            memcpy(lam, phi + p->nn, sizeof(double) * S->nv);
+        }
+        surface_trace(p, S, phi, um);
+        reaction_potential_on(p, S, lam, um, p->nq, p->qx, ur);
+        double e = 0.0;
+        for (int64_t k = 0; k < p->nq; ++k) e += 0.5 * p->kT * p->qz[k] * ur[k];
+        if (part == 0) lc = e;
+        else nc = e;
     }
     double integral = 0.0;
     for (int64_t t = 0; t < p->nt_i; ++t) { /* Omega_i only */
@@ -1820,8 +1964,8 @@ int pbref_energy(pbref *p, const double *phi_lin, const double *phi_nl, double o
     out[2] = nc;
     out[3] = dg;
     free(ur);
-    free(pl);
-    free(pn);
+    free(lam);
+    free(um);
     return 0;
 }
 

@@ -70,7 +70,21 @@ int pbref_rhs(pbref *, double *b);
  * identity (lam_m is recovered after the solve by pbref_lambda_m, and
  * pbref_energy does so itself).  Returns -1 unless 0 < n_tets_m < n_tets. */
 int pbref_set_two_field(pbref *, int64_t n_tets_m);
-/* lam = V0^-1 ((1/2 M_m + K0_m) u|Gamma_m - [with_load] f_m) (Sec. 2.3.1) */
+/* Two-field form: a Gamma_m surface mesh independent of the volume mesh
+ * (own vertices verts[3 nv], triangles tri[3 nt] oriented like the
+ * interface).  lam_m and the reaction potential then live on it, and the
+ * trace of u on it is the P1 interpolant of u at its vertices, each vertex
+ * in the tet holding it (Sec. 2.3.1: the trace by interpolation between the
+ * volume and surface meshes).  nv = 0 removes it.  -1 for bad sizes or ids,
+ * -3 if a vertex lies outside the FEM mesh. */
+int pbref_set_reaction_surface(pbref *, int64_t nv, const double *verts, int64_t nt, const int32_t *tri);
+/* vertices of the surface that carries lam_m and the reaction potential
+ * (the independent mesh in the two-field form when set, else Gamma_m) */
+int64_t pbref_gamma_m_vertices(const pbref *);
+/* the trace of the FEM field u on that surface (pbref_gamma_m_vertices values) */
+int pbref_gamma_m_trace(const pbref *, const double *u, double *out);
+/* lam = V0^-1 ((1/2 M_m + K0_m) u|Gamma_m - [with_load] f_m) (Sec. 2.3.1), on
+ * that surface (pbref_gamma_m_vertices values) */
 int pbref_lambda_m(pbref *, const double *u, int with_load, double *lam);
 /* add a fixed vector to b in pbref_rhs, pbref_residual and pbref_solve (NULL clears);
  * used to impose the volume source and interface jumps of manufactured solutions */

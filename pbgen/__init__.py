@@ -49,6 +49,10 @@ class Problem:
     kappa: float
     info: dict
     n_tets_m: int = 0      # > 0: the last n_tets_m tets fill the solute (two-field form)
+    # two-field form: an independent Gamma_m surface mesh (own vertices on the
+    # smooth solute surface, outward triangles), or None
+    rs_verts: np.ndarray = None
+    rs_tris: np.ndarray = None
 
     @property
     def n_nodes(self):
@@ -163,23 +167,38 @@ def _real_sph_harm_eval(lmax, xyz):
     return np.stack(cols, axis=1)
 
 
-def radial_surface(unit, a, c, rng=None, lmax=8, amp_range=(0.5, 1.5)):
+def radial_surface(unit, a, c, rng=None, lmax=8, amp_range=(0.5, 1.5), with_fn=False):
     """Radius r(x) of the star-shaped solute along each unit direction.
 
     Spheroid with semi-axes (a, a, c) plus, if rng is given, a seeded real
     spherical-harmonic bump sum_{l,m} c_lm Y_lm with c_lm ~ N(0,1)/(l+1)^2,
     rescaled so that max |bump| over the given directions equals A ~ U(amp_range).
+    with_fn: also return the radius as a function of any unit directions
+    (the same spheroid, coefficients and scale).
     """
-    r = 1.0 / np.sqrt((unit[:, 0] ** 2 + unit[:, 1] ** 2) / a ** 2 + unit[:, 2] ** 2 / c ** 2)
-    amp = 0.0
+    def spheroid(u):
+        return 1.0 / np.sqrt((u[:, 0] ** 2 + u[:, 1] ** 2) / a ** 2 + u[:, 2] ** 2 / c ** 2)
+
+    r = spheroid(unit)
+    amp, coef, scale = 0.0, None, 0.0
     if rng is not None:
         amp = float(rng.uniform(*amp_range))
         ls = np.concatenate([[l] * (2 * l + 1) for l in range(1, lmax + 1)])
         coef = rng.standard_normal(ls.size) / (ls + 1.0) ** 2
         bump = _real_sph_harm(lmax, unit) @ coef
-        bump *= amp / np.max(np.abs(bump))
+        scale = amp / np.max(np.abs(bump))
+        bump *= scale
         r = r + bump
-    return r, amp
+    if not with_fn:
+        return r, amp
+
+    def fn(u):
+        out = spheroid(u)
+        if coef is not None:
+            out = out + (_real_sph_harm(lmax, u) @ coef) * scale
+        return out
+
+    return r, amp, fn
 
 
 def shell_mesh(unit, tris, r_in, thickness, layers):
@@ -556,13 +575,16 @@ def config_params(cfg: int):
 
 
 def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
-                 eps_in=4.0, eps_out=80.0, clearance=1.5, center_charge=None, solute_layers=0):
+                 eps_in=4.0, eps_out=80.0, clearance=1.5, center_charge=None, solute_layers=0, reaction_n=None):
     """solute_layers > 0 adds the tets of the solute (Sec. 2.3's FEM domain
     Omega_m u Omega_i): they follow the shell tets, their new nodes follow the
-    shell nodes, and Problem.n_tets_m counts them."""
+    shell nodes, and Problem.n_tets_m counts them.  reaction_n (with
+    solute_layers): an independent Gamma_m surface mesh, the icosphere of
+    frequency reaction_n with its vertices on the smooth solute surface
+    (Problem.rs_verts, rs_tris), not a face set of the volume mesh."""
     rng = np.random.default_rng(list(seed))
     unit, tris = icosphere(n)
-    r, amp = radial_surface(unit, a, c, rng if bump else None)
+    r, amp, rfn = radial_surface(unit, a, c, rng if bump else None, with_fn=True)
     nodes, tets, tri_m, tri_s = shell_mesh(unit, tris, r, t, L)
     n_tets_m = 0
     if solute_layers:
@@ -572,6 +594,14 @@ def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
         n_tets_m = int(itets.shape[0])
         tets = np.concatenate([tets, itets.astype(np.int32)])
     log = dict(n=n, a=a, c=c, amp=amp, t=t, L=L, seed=list(seed), solute_layers=int(solute_layers))
+    rs_verts = rs_tris = None
+    if reaction_n:
+        if not solute_layers:
+            raise ValueError("an independent Gamma_m mesh needs the two-field form (solute_layers > 0)")
+        uf, rs_tris = icosphere(int(reaction_n))
+        rs_verts = np.ascontiguousarray(rfn(uf)[:, None] * uf)
+        rs_tris = np.ascontiguousarray(rs_tris, dtype=np.int32)
+        log["reaction_n"] = int(reaction_n)
     gm = nodes[: unit.shape[0]]
     qx, qz = [], []
     if center_charge is not None:
@@ -591,7 +621,8 @@ def make_problem(n, a, c, bump, t, L, helix, partials, kappa, seed=(0, 0),
                    tri_m=np.ascontiguousarray(tri_m), tri_s=np.ascontiguousarray(tri_s),
                    q_xyz=np.ascontiguousarray(q_xyz, dtype=np.float64),
                    q_z=np.ascontiguousarray(q_z, dtype=np.float64),
-                   eps_in=eps_in, eps_out=eps_out, kappa=kappa, info=log, n_tets_m=n_tets_m)
+                   eps_in=eps_in, eps_out=eps_out, kappa=kappa, info=log, n_tets_m=n_tets_m,
+                   rs_verts=rs_verts, rs_tris=rs_tris)
 
 
 def make_config(cfg: int, instance: int = 0, **override):

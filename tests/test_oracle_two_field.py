@@ -18,6 +18,14 @@ Checks, each against something fixed independently of the oracle's code:
 * recovering lam_m from the three-field solution's trace returns its lam_m
   (the recovery equation is that solution's Gamma_m row);
 * Born / Debye-Hueckel sphere: the energy converges to the closed form.
+
+Gamma_m as its own surface mesh (the trace by interpolation, Sec. 2.3.1):
+* the interpolated trace reproduces linear fields at every vertex of a finer
+  surface (and not quadratic ones);
+* the interface faces given as an independent, renumbered mesh give the
+  conforming form's lam_m and energy;
+* Born sphere with a finer Gamma_m mesh: second-order convergence;
+* a surface outside the FEM mesh is refused.
 """
 import numpy as np
 
@@ -147,3 +155,79 @@ def test_nonlinear_sphere_two_field_matches_radial_reference():
     E_ex, _ = radial_reference(4.0, 8.0, 8.0, 0.125, 4.0, 80.0, o.l_bjerrum, o.kT)
     e = [abs(v - E_ex) / abs(E_ex) for v in tot]
     assert e[1] < 5e-3 and 3.0 < e[0] / e[1] < 5.0
+
+
+# ---------------------------------------------------------------------------
+# Gamma_m given as its own surface mesh (Sec. 2.3.1: the trace of the volume
+# solution on it by interpolation between the two meshes)
+# ---------------------------------------------------------------------------
+def test_independent_gamma_m_trace_reproduces_linear_fields():
+    """The P1 interpolant of a linear field is the field itself, at every
+    vertex of a finer surface that is not a face set of the volume mesh."""
+    p = pbgen.make_problem(solute_layers=3, reaction_n=2 * SPEC["n"] + 1, **SPEC)
+    o = oracle.Oracle.from_problem(p)
+    assert p.rs_verts.shape[0] == 10 * (2 * SPEC["n"] + 1) ** 2 + 2
+    c, c0 = np.array([0.3, -1.1, 0.7]), 0.25
+    tr = o.gamma_m_trace(p.nodes @ c + c0)
+    expect = p.rs_verts @ c + c0
+    assert np.abs(tr - expect).max() < 1e-12 * np.abs(expect).max()
+    # a quadratic field is not reproduced (the interpolation is P1, not node selection)
+    q = o.gamma_m_trace((p.nodes ** 2).sum(1))
+    assert np.abs(q - (p.rs_verts ** 2).sum(1)).max() > 1e-4
+
+
+def test_independent_gamma_m_on_the_interface_matches_the_conforming_form():
+    """The interface faces of the volume mesh given as an independent mesh
+    (own vertex array, renumbered): every vertex is a tet vertex, so the
+    interpolated trace is the nodal value (to the rounding of the barycentric
+    coordinates) and lam_m and the energy equal the conforming two-field
+    form's."""
+    p, o = two_field()
+    x = lin_solve(o, tol=1e-12)
+    nodes_m = np.unique(p.tri_m)
+    perm = np.random.default_rng(5).permutation(nodes_m.size)   # independent numbering
+    new_id = np.empty(p.n_nodes, np.int64)
+    new_id[nodes_m[perm]] = np.arange(nodes_m.size)
+    verts = np.empty((nodes_m.size, 3))
+    verts[new_id[nodes_m]] = p.nodes[nodes_m]
+    tris = new_id[p.tri_m].astype(np.int32)
+    e0 = o.energy(x)
+    lam0 = o.lambda_m(x[:o.n_nodes])
+    o.set_reaction_surface(verts, tris)
+    tr = o.gamma_m_trace(x[:o.n_nodes])[new_id[nodes_m]]
+    assert np.abs(tr - x[nodes_m]).max() < 1e-13 * np.abs(x[nodes_m]).max()
+    lam1 = o.lambda_m(x[:o.n_nodes])
+    assert np.abs(lam1[new_id[nodes_m]] - lam0).max() < 1e-11 * np.abs(lam0).max()
+    e1 = o.energy(x)
+    assert abs(e1["total"] - e0["total"]) < 1e-11 * abs(e0["total"])
+
+
+def test_born_sphere_with_a_finer_independent_gamma_m():
+    """Born / Debye-Hueckel with lam_m and the reaction potential on a sphere
+    mesh finer than the volume's interface (its vertices on the exact
+    sphere): the energy converges to the closed form at second order as both
+    meshes are refined."""
+    res = {}
+    for n, lay, nr in ((4, 3, 6), (8, 6, 12)):
+        p = pbgen.make_problem(n=n, a=4.0, c=4.0, bump=False, t=4.0, L=6, helix=0, partials=0, kappa=0.125,
+                               center_charge=1.0, solute_layers=lay, reaction_n=nr)
+        assert np.allclose(np.linalg.norm(p.rs_verts, axis=1), 4.0, rtol=0, atol=1e-12)
+        o = oracle.Oracle.from_problem(p)
+        x = lin_solve(o)
+        res[n] = o.energy(x)["total"]
+        assert o.lambda_m(x[:o.n_nodes]).shape == (10 * nr * nr + 2,)  # lam_m lives on the finer mesh
+    E_ex, _ = born_energy(o, 4.0, 1.0, 4.0, 80.0, 0.125)
+    e4, e8 = abs(res[4] - E_ex) / abs(E_ex), abs(res[8] - E_ex) / abs(E_ex)
+    assert e8 < 5e-3 and 3.0 < e4 / e8 < 5.0
+
+
+def test_independent_gamma_m_outside_the_mesh_is_refused():
+    p, o = two_field()
+    bad = np.array([[0.0, 0.0, 100.0], [1.0, 0.0, 100.0], [0.0, 1.0, 100.0], [0.0, 0.0, 101.0]])
+    tris = np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]], np.int32)
+    try:
+        o.set_reaction_surface(bad, tris)
+    except ValueError as e:
+        assert "outside" in str(e)
+    else:
+        raise AssertionError("a surface outside the FEM mesh was accepted")
