@@ -76,7 +76,8 @@ const char *pbfb_last_error(void);
 /* precision PBFB_FP64: every operator evaluated, stored and applied in FP64.
  * PBFB_MIXED: the regular (non-touching) boundary-element quadrature is
  * evaluated in FP32 (point offsets from FP64 triangle centroids, FP32 kernel
- * values and sums over the 6 source points) and accumulated in FP64; dense
+ * values and per-pair sums over the 36 quadrature pairs), folded onto the
+ * vertices in FP64; dense
  * boundary operators and FEM matrix values are stored in FP32 (rounded once
  * from their FP64 sums) and every product is accumulated in FP64.  Krylov
  * vectors (unless krylov_fp32), Newton update, relaxation search,
@@ -321,6 +322,25 @@ pbfb_status pbfb_set_bem_mode(pbfb_problem *p, int mode);
  * matrix-free while it is on); PBFB_ESTATE before set_mesh, PBFB_EINVAL
  * unless 0 <= n_tets_m < n_tets.  set_mesh resets it to 0. */
 pbfb_status pbfb_set_two_field(pbfb_problem *p, int64_t n_tets_m);
+
+/* Two-field form: a surface mesh of Gamma_m given independently of the
+ * volume mesh (Sec. 2.3.1, where the trace of the volume solution on Gamma_m
+ * is taken by interpolating between the volume and the surface meshes):
+ * verts[3*n_verts] in Angstrom, tri[3*n_tri] 0-based vertex ids, oriented
+ * like the interface (right-hand normals away from the solute).  lambda_m is
+ * then recovered on this mesh, with its own Laplace operators and Coulomb
+ * load, from the trace of u at its vertices -- the P1 interpolant of u in the
+ * FEM tet that holds each vertex (the one whose smallest barycentric
+ * coordinate is largest, ties to the lower tet id) -- and the reaction
+ * potential and energy are taken on it.  The interface faces of the volume
+ * mesh (tri_m of set_mesh) still separate the permittivities.  Used only in
+ * the two-field form; n_verts = 0 removes it; set_mesh removes it.  The
+ * arrays are copied.  Errors: PBFB_ESTATE before set_mesh; PBFB_EINVAL (sizes,
+ * ids out of range, non-finite coordinates); PBFB_EMESH (not closed, not
+ * consistently oriented; at setup: zero-area triangle, oriented inward, or a
+ * vertex outside every FEM tet). */
+pbfb_status pbfb_set_reaction_surface(pbfb_problem *p, int64_t n_verts, const double *verts, int64_t n_tri,
+                                      const int32_t *tri);
 
 /* ---- inspection --------------------------------------------------------- */
 /* Copy the two dense blocks stored for surface `surf` (0 = Gamma_m, Laplace;

@@ -28,7 +28,7 @@ EXPORTS = ["pbfb_ctx_create", "pbfb_ctx_destroy", "pbfb_last_error", "pbfb_probl
            "pbfb_reset_operators", "pbfb_residual", "pbfb_residual_noalloc",
            "pbfb_apply_jacobian", "pbfb_solve_opts_default", "pbfb_solve", "pbfb_solve_batch", "pbfb_server_create",
            "pbfb_server_submit", "pbfb_server_poll", "pbfb_request_footprint", "pbfb_server_destroy", "pbfb_energy", "pbfb_export_bem",
-           "pbfb_export_bem_rows", "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_two_field", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
+           "pbfb_export_bem_rows", "pbfb_export_rhs", "pbfb_set_bem_mode", "pbfb_set_two_field", "pbfb_set_reaction_surface", "pbfb_set_tile_shape", "pbfb_get_tile_shape", "pbfb_timing_enable", "pbfb_timing"]
 
 
 class PbfbError(RuntimeError):
@@ -119,6 +119,7 @@ def lib():
         L.pbfb_set_tile_shape.argtypes = [P, C.c_int, C.c_int]
         L.pbfb_set_bem_mode.argtypes = [P, C.c_int]
         L.pbfb_set_two_field.argtypes = [P, C.c_int64]
+        L.pbfb_set_reaction_surface.argtypes = [P, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
         L.pbfb_get_tile_shape.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pbfb_timing_enable.argtypes = [P, C.c_int]
         L.pbfb_timing.argtypes = [P, C.c_int, C.POINTER(C.c_double), I64P, C.c_int]
@@ -260,6 +261,8 @@ class Problem:
         self.set_params(prob.eps_in, prob.eps_out, prob.kappa, temperature)
         if getattr(prob, "n_tets_m", 0):
             self.set_two_field(prob.n_tets_m)
+            if getattr(prob, "rs_verts", None) is not None:
+                self.set_reaction_surface(prob.rs_verts, prob.rs_tris)
         return self
 
     def close(self):
@@ -392,6 +395,17 @@ class Problem:
     def set_two_field(self, n_tets_m):
         """Two-field form: the last n_tets_m tets fill the solute (0: shell-only form)."""
         _check(lib().pbfb_set_two_field(self.h, int(n_tets_m)))
+
+    def set_reaction_surface(self, verts, tris):
+        """Two-field form: a Gamma_m surface mesh independent of the volume mesh
+        (lambda_m, the reaction potential and the energy on it; the trace of u
+        by P1 interpolation at its vertices).  verts = None removes it."""
+        if verts is None:
+            _check(lib().pbfb_set_reaction_surface(self.h, 0, None, 0, None))
+            return
+        v = np.ascontiguousarray(np.reshape(verts, (-1, 3)), dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        _check(lib().pbfb_set_reaction_surface(self.h, v.shape[0], v.ctypes.data, t.shape[0], t.ctypes.data))
 
     def set_tile_shape(self, ta=0, tb=0):
         """Pin the regular-assembly tile shape (ta x tb triangles); 0, 0 = tuned."""

@@ -158,7 +158,7 @@ void release_device_state(Problem &p)
 {
     release_all_scratch(p);
     p.mesh_arena.release();
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < NSURF; ++w) {
         p.bem_arena[w].release();
         p.surf[w].sides.clear();
         p.surf[w].tile = -1;
@@ -402,14 +402,14 @@ void pbfb_problem_destroy(pbfb_problem *pp)
     p.timer.destroy();
     release_all_scratch(p);
     p.mesh_arena.release();
-    p.bem_arena[0].release();
-    p.bem_arena[1].release();
+    for (int w = 0; w < NSURF; ++w) p.bem_arena[w].release();
     delete pp;
 }
 
 static void invalidate_geometry(Problem &p)
 {
-    p.geom_ready = p.val_ready = p.fm_ready = p.bem_ready[0] = p.bem_ready[1] = false;
+    p.geom_ready = p.val_ready = p.fm_ready = false;
+    for (int w = 0; w < NSURF; ++w) p.bem_ready[w] = false;
 }
 
 pbfb_status pbfb_set_mesh(pbfb_problem *pp, int64_t n_nodes, const double *nodes, int64_t n_tets,
@@ -424,8 +424,11 @@ pbfb_status pbfb_set_mesh(pbfb_problem *pp, int64_t n_nodes, const double *nodes
     PB_HIP(hipSetDevice(p.ctx->device));
     (void)hipDeviceSynchronize();
     invalidate_geometry(p);
-    p.topo_ready = p.bem_topo_ready[0] = p.bem_topo_ready[1] = false;
+    p.topo_ready = false;
+    for (int w = 0; w < NSURF; ++w) p.bem_topo_ready[w] = false;
     p.have_mesh = false;
+    p.rs_x.clear();
+    p.topo[2] = SurfaceTopo();
     p.nn = n_nodes;
     p.ntet = n_tets;
     p.ntet_m = 0;
@@ -493,7 +496,8 @@ pbfb_status pbfb_get_sizes(const pbfb_problem *pp, int64_t *n_nodes, int64_t *n_
     if (n_s) *n_s = p.topo[1].nv;
     if (n_unknowns) *n_unknowns = p.n();
     if (hbm_bytes) {
-        size_t b = p.mesh_arena.bytes + p.bem_arena[0].bytes + p.bem_arena[1].bytes;
+        size_t b = p.mesh_arena.bytes;
+        for (int w = 0; w < NSURF; ++w) b += p.bem_arena[w].bytes;
         for (int i = 0; i < SCR_N; ++i) b += p.scr[i].bytes;
         *hbm_bytes = int64_t(b);
     }
@@ -740,8 +744,7 @@ pbfb_status pbfb_set_bem_mode(pbfb_problem *pp, int mode)
     PB_CHECK(!(mf && p.two_field()), PBFB_EINVAL, "the two-field form needs dense boundary operators");
     if (mf != p.bem_mf) {
         p.bem_mf = mf;
-        p.bem_ready[0] = p.bem_ready[1] = false;
-        p.bem_topo_ready[0] = p.bem_topo_ready[1] = false;
+        for (int w = 0; w < NSURF; ++w) p.bem_ready[w] = p.bem_topo_ready[w] = false;
     }
     API_END
 }
@@ -762,6 +765,33 @@ pbfb_status pbfb_set_two_field(pbfb_problem *pp, int64_t n_tets_m)
     API_END
 }
 
+pbfb_status pbfb_set_reaction_surface(pbfb_problem *pp, int64_t n_verts, const double *verts, int64_t n_tri,
+                                      const int32_t *tri)
+{
+    API_BEGIN
+    PB_CHECK(pp, PBFB_EINVAL, "null problem");
+    Problem &p = live(pp);
+    PB_CHECK(p.have_mesh, PBFB_ESTATE, "set_mesh must precede set_reaction_surface");
+    PB_CHECK(n_verts == 0 || (verts && tri && n_verts >= 4 && n_tri >= 4), PBFB_EINVAL, "bad surface arguments");
+    PB_CHECK(n_verts < (int64_t(1) << 31) && 3 * n_tri < (int64_t(1) << 31), PBFB_EINVAL, "surface too large");
+    PB_HIP(hipSetDevice(p.ctx->device));
+    (void)hipDeviceSynchronize();
+    SurfaceTopo T;
+    std::vector<double> xs;
+    if (n_verts > 0) {
+        xs.assign(verts, verts + 3 * n_verts);
+        for (double v : xs) PB_CHECK(std::isfinite(v), PBFB_EINVAL, "non-finite vertex coordinate");
+        build_surface_topo_on(T, n_verts, xs.data(), n_tri, tri);
+    }
+    // the device topology and geometry are built again with the new surface
+    invalidate_geometry(p);
+    p.topo_ready = false;
+    p.bem_topo_ready[2] = false;
+    p.topo[2] = std::move(T);
+    p.rs_x = std::move(xs);
+    API_END
+}
+
 pbfb_status pbfb_set_tile_shape(pbfb_problem *pp, int ta, int tb)
 {
     API_BEGIN
@@ -774,7 +804,7 @@ pbfb_status pbfb_set_tile_shape(pbfb_problem *pp, int ta, int tb)
     Problem &p = live(pp);
     if (k != p.tile_fixed) {
         p.tile_fixed = k;
-        p.bem_ready[0] = p.bem_ready[1] = false;
+        for (int w = 0; w < NSURF; ++w) p.bem_ready[w] = false;
     }
     API_END
 }

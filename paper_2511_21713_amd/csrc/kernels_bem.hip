@@ -1175,7 +1175,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     }
     int32_t *d_tptau = S.tp_tau;
     hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, S.morton, S.tri, S.qp, S.nrm,
-                       S.area, S.g, p.d_x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
+                       S.area, S.g, S.x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
 
     // the context's assembly workspace (see below) is used by one assembly at a time
     std::lock_guard<std::mutex> ws_lock(p.ctx->asm_ws.mu);
@@ -1186,7 +1186,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     if (p.bem_mf) {
         // matrix-free: only the touching-pair blocks (kept) and the diagonal of V'
         double *vxm = p.ctx->asm_ws.doubles(3 * T.nv);
-        hipLaunchKernelGGL(k_gather_coords, dim3(nblk(T.nv, 256)), dim3(256), 0, s, T.nv, S.g, p.d_x, vxm);
+        hipLaunchKernelGGL(k_gather_coords, dim3(nblk(T.nv, 256)), dim3(256), 0, s, T.nv, S.g, S.x, vxm);
         GL4 G = gl4arg();
         if (p.timing) p.timer.begin(T_SING, s);
         if (yuk)
@@ -1206,7 +1206,9 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     }
     const int64_t nv = T.nv, ld = bem_ld(nv);
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
-    const double sV = (w == 0) ? -1.0 : 1.0, sK = (w == 0) ? 1.0 : -1.0;
+    // Gamma_m (and an independent Gamma_m mesh): V' = -V0, K' = 1/2 M + K0;
+    // Gamma_s: V' = +Vk, K' = 1/2 M - Kk
+    const double sV = (w != 1) ? -1.0 : 1.0, sK = (w != 1) ? 1.0 : -1.0;
     RegArgs ra;
     ra.nt = T.nt;
     ra.m_tri = S.m_tri;
@@ -1267,7 +1269,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         PB_HIP(hipGetLastError());
     }
     // touching pairs
-    hipLaunchKernelGGL(k_gather_coords, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, S.g, p.d_x, vx);
+    hipLaunchKernelGGL(k_gather_coords, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, S.g, S.x, vx);
     GL4 G = gl4arg();
     if (p.timing) p.timer.begin(T_SING, s);
     if (yuk)
@@ -1329,6 +1331,7 @@ void ensure_all(Problem &p, hipStream_t s)
     ensure_rhs(p, s);
     ensure_bem(p, 0, s);
     ensure_bem(p, 1, s);
+    if (p.gm() == 2) ensure_bem(p, 2, s); // lambda_m and u_r on the independent Gamma_m mesh
 }
 
 } // namespace pbfb

@@ -429,6 +429,16 @@ __global__ void __launch_bounds__(256) k_point_locate(int64_t nt0, int64_t nt, c
     }
 }
 
+// the vertices of a surface as points for k_point_locate (x, y, z, 0)
+__global__ void k_surface_points(int64_t nv, const double *__restrict__ x, const int32_t *__restrict__ g,
+                                 double *__restrict__ pts)
+{
+    const int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (v >= nv) return;
+    for (int d = 0; d < 3; ++d) pts[4 * v + d] = x[3 * int64_t(g[v]) + d];
+    pts[4 * v + 3] = 0.0;
+}
+
 __global__ void k_point_scatter(int64_t nq, const int32_t *__restrict__ tet, const double *__restrict__ q,
                                 const double *__restrict__ loc, double qscale, double *__restrict__ b)
 {
@@ -477,10 +487,26 @@ __global__ void k_gather_vertex(int64_t nv, const int32_t *__restrict__ v2t_ptr,
 // u_r(x) = int [g0(x,y) lambda_m(y) - dg0/dn_y(x,y) u(y)] dy over Gamma_m
 // one block per charge; two densities (Phi_L and Phi_NL) at once
 // ---------------------------------------------------------------------------
+// u_r(x_k) = (V lam)(x_k) - (K u)(x_k) over Gamma_m (eq. Potential_in_Omega_m) for
+// two fields at once (Phi_L, Phi_NL); lam0 / lam1: lambda_m per surface
+// vertex; the trace of u0 / u1 at vertex v is u[g[v]], or on an independent
+// Gamma_m mesh (loc non-null: tet and barycentric coordinates per vertex,
+// 6 doubles) the P1 interpolant.
+__device__ inline double surface_trace(const double *__restrict__ u, int32_t v, const int32_t *__restrict__ g,
+                                       const double *__restrict__ loc, const int32_t *__restrict__ tet)
+{
+    if (!loc) return u[g[v]];
+    const double *l = loc + 6 * int64_t(v);
+    const int32_t *T = tet + 4 * int64_t(l[0]);
+    return l[2] * u[T[0]] + l[3] * u[T[1]] + l[4] * u[T[2]] + l[5] * u[T[3]];
+}
+
 __global__ void k_reaction_potential(int64_t nt, const double *__restrict__ qp, const double *__restrict__ nrm,
                                      const double *__restrict__ area, const int32_t *__restrict__ tri,
-                                     const int32_t *__restrict__ g, int64_t nn, const double *__restrict__ q,
-                                     const double *__restrict__ phi0, const double *__restrict__ phi1, TriRuleArg R,
+                                     const int32_t *__restrict__ g, const double *__restrict__ loc,
+                                     const int32_t *__restrict__ tet, const double *__restrict__ q,
+                                     const double *__restrict__ phi0, const double *__restrict__ lam0,
+                                     const double *__restrict__ phi1, const double *__restrict__ lam1, TriRuleArg R,
                                      double *__restrict__ out)
 {
     __shared__ double r0[256], r1[256];
@@ -492,10 +518,10 @@ __global__ void k_reaction_potential(int64_t nt, const double *__restrict__ qp, 
         int32_t v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
         double l0[3], u0[3], l1[3], u1[3];
         for (int a = 0; a < 3; ++a) {
-            l0[a] = phi0[nn + v[a]];
-            u0[a] = phi0[g[v[a]]];
-            l1[a] = phi1 ? phi1[nn + v[a]] : 0.0;
-            u1[a] = phi1 ? phi1[g[v[a]]] : 0.0;
+            l0[a] = lam0[v[a]];
+            u0[a] = surface_trace(phi0, v[a], g, loc, tet);
+            l1[a] = phi1 ? lam1[v[a]] : 0.0;
+            u1[a] = phi1 ? surface_trace(phi1, v[a], g, loc, tet) : 0.0;
         }
         const double *n = nrm + 3 * t;
         for (int p = 0; p < 6; ++p) {
@@ -627,11 +653,19 @@ void ensure_topology(Problem &p, hipStream_t s)
     p.d_val = A.alloc<double>(p.nnz);
     p.d_val32 = p.precision == PBFB_MIXED ? A.alloc<float>(p.nnz) : nullptr;
     p.d_bad = A.alloc<int>(1);
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < NSURF; ++w) {
         SurfaceTopo &T = p.topo[w];
         SurfaceDev &S = p.surf[w];
         S.nv = T.nv;
         S.nt = T.nt;
+        S.itet = nullptr;
+        S.iw = nullptr;
+        if (w == 2 && !p.has_rs()) {
+            S.x = nullptr;
+            continue;
+        }
+        // coordinates indexed through g: the FEM nodes, or the independent mesh's own vertices
+        S.x = w == 2 ? A.upload(p.rs_x, s) : p.d_x;
         S.g = A.upload(T.g, s);
         S.mvert = A.upload(T.mvert, s);
         S.minv = A.upload(T.minv, s);
@@ -642,7 +676,8 @@ void ensure_topology(Problem &p, hipStream_t s)
         S.qp = A.alloc<double>(18 * T.nt);
         S.nrm = A.alloc<double>(3 * T.nt);
         S.area = A.alloc<double>(T.nt);
-        S.cslot = A.upload(cslot[w], s);
+        S.cslot = w < 2 ? A.upload(cslot[w], s) : nullptr;
+        if (w == 2) S.iw = A.alloc<double>(6 * T.nv);
     }
     PB_HIP(hipStreamSynchronize(s));
     p.topo_ready = true;
@@ -658,16 +693,27 @@ void ensure_geometry(Problem &p, hipStream_t s)
     hipLaunchKernelGGL(k_tet_geom, dim3(nblocks(p.ntet, 256)), dim3(256), 0, s, p.ntet, p.d_x, p.d_tet, p.d_tgeo,
                        p.d_bad);
     TriRuleArg TR = tri_rule_arg();
-    double *d_vol = scratch<double>(p, SCR_VOL, 2);
-    for (int w = 0; w < 2; ++w) {
+    double *d_vol = scratch<double>(p, SCR_VOL, NSURF);
+    const int nsurf = p.has_rs() ? 3 : 2;
+    for (int w = 0; w < nsurf; ++w) {
         SurfaceDev &S = p.surf[w];
-        hipLaunchKernelGGL(k_tri_geom, dim3(nblocks(S.nt, 256)), dim3(256), 0, s, S.nt, p.d_x, S.g, S.tri, TR, S.qp,
+        hipLaunchKernelGGL(k_tri_geom, dim3(nblocks(S.nt, 256)), dim3(256), 0, s, S.nt, S.x, S.g, S.tri, TR, S.qp,
                            S.nrm, S.area, p.d_bad);
-        hipLaunchKernelGGL(k_enclosed_volume, dim3(1), dim3(256), 0, s, S.nt, p.d_x, S.g, S.tri, S.nrm, S.area,
+        hipLaunchKernelGGL(k_enclosed_volume, dim3(1), dim3(256), 0, s, S.nt, S.x, S.g, S.tri, S.nrm, S.area,
                            d_vol + w);
     }
+    if (p.has_rs()) {
+        // the tet of the FEM mesh that holds each vertex of the independent
+        // Gamma_m mesh, and the vertex's barycentric coordinates there: the
+        // trace of u on it is the P1 interpolant (Sec. 2.3.1)
+        SurfaceDev &R = p.surf[2];
+        double *pts = scratch<double>(p, SCR_RLOC, 4 * R.nv);
+        hipLaunchKernelGGL(k_surface_points, dim3(nblocks(R.nv, 256)), dim3(256), 0, s, R.nv, R.x, R.g, pts);
+        hipLaunchKernelGGL(k_point_locate, dim3(unsigned(R.nv)), dim3(256), 0, s, int64_t(0), p.ntet, p.d_x, p.d_tet,
+                           p.d_tgeo, pts, R.iw);
+    }
     int bad = 0;
-    double vol[2] = {0.0, 0.0};
+    double vol[NSURF] = {0.0, 0.0, 0.0};
     PB_HIP(hipMemcpyAsync(&bad, p.d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
     PB_HIP(hipMemcpyAsync(vol, d_vol, sizeof(vol), hipMemcpyDeviceToHost, s));
     PB_HIP(hipStreamSynchronize(s));
@@ -678,6 +724,16 @@ void ensure_geometry(Problem &p, hipStream_t s)
     // enclose a positive volume
     PB_CHECK(vol[0] > 0.0, PBFB_EMESH, "Gamma_m is oriented inward (its right-hand normals enclose a negative volume)");
     PB_CHECK(vol[1] > 0.0, PBFB_EMESH, "Gamma_s is oriented inward (its right-hand normals enclose a negative volume)");
+    if (p.has_rs()) {
+        PB_CHECK(vol[2] > 0.0, PBFB_EMESH,
+                 "the Gamma_m surface mesh is oriented inward (its right-hand normals enclose a negative volume)");
+        std::vector<double> loc(6 * p.surf[2].nv);
+        PB_HIP(hipMemcpyAsync(loc.data(), p.surf[2].iw, sizeof(double) * loc.size(), hipMemcpyDeviceToHost, s));
+        PB_HIP(hipStreamSynchronize(s));
+        for (int64_t v = 0; v < p.surf[2].nv; ++v)
+            PB_CHECK(loc[6 * v] >= 0 && loc[6 * v + 1] >= -1e-10, PBFB_EMESH,
+                     "vertex " + std::to_string(v) + " of the Gamma_m surface mesh lies outside the FEM mesh");
+    }
     p.geom_ready = true;
 }
 
@@ -724,13 +780,15 @@ void ensure_rhs(Problem &p, hipStream_t s)
             PB_CHECK(chk[2 * k] >= 1.0, PBFB_ECHARGE,
                      "charge " + std::to_string(k) + " is closer than 1 A to Gamma_m");
         }
-        double *trif = scratch<double>(p, SCR_TRIF, 3 * S.nt);
         // the Coulomb load f_m: the Gamma_m rows of b, or (two-field form) kept
-        // for the recovery of lambda_m while the point charges load the FEM rows
-        double *fm = p.two_field() ? scratch<double>(p, SCR_FM, S.nv) : p.d_b + p.nn;
-        hipLaunchKernelGGL(k_coulomb_tri, dim3(nblocks(S.nt, 128)), dim3(128), 0, s, S.nt, S.qp, S.area, p.d_q, p.nq,
+        // for the recovery of lambda_m while the point charges load the FEM
+        // rows, on the surface that carries lambda_m
+        const SurfaceDev &F = p.surf[p.gm()];
+        double *trif = scratch<double>(p, SCR_TRIF, 3 * F.nt);
+        double *fm = p.two_field() ? scratch<double>(p, SCR_FM, F.nv) : p.d_b + p.nn;
+        hipLaunchKernelGGL(k_coulomb_tri, dim3(nblocks(F.nt, 128)), dim3(128), 0, s, F.nt, F.qp, F.area, p.d_q, p.nq,
                            p.lB / p.eps_m, tri_rule_arg(), trif);
-        hipLaunchKernelGGL(k_gather_vertex, dim3(nblocks(S.nv, 256)), dim3(256), 0, s, S.nv, S.v2t_ptr, S.v2t, trif,
+        hipLaunchKernelGGL(k_gather_vertex, dim3(nblocks(F.nv, 256)), dim3(256), 0, s, F.nv, F.v2t_ptr, F.v2t, trif,
                            fm);
         if (p.two_field()) {
             double *loc = scratch<double>(p, SCR_PLOC, 6 * p.nq);
@@ -813,27 +871,27 @@ double fem_energy_integral(Problem &p, const double *ul, const double *unl, hipS
 void energy(Problem &p, const double *phi_lin, const double *phi_nl, double out[4], hipStream_t s)
 {
     ensure_rhs(p, s);
+    // lambda_m per vertex of the surface that carries it: part of Phi in the
+    // three-field form; in the two-field form recovered from the trace of u,
+    // with the Coulomb load for the linear part only (Sec. 2.3.1), on the
+    // independent Gamma_m mesh when one is set
+    const SurfaceDev &S = p.surf[p.gm()];
+    const double *lam_l = phi_lin + p.nn, *lam_n = phi_nl ? phi_nl + p.nn : nullptr;
     if (p.two_field()) {
-        // the reaction potential needs lambda_m: recovered from the trace of u,
-        // with the Coulomb load for the linear part only (Sec. 2.3.1)
-        const int64_t n = p.n();
-        double *pl = scratch<double>(p, SCR_PL, n);
-        PB_HIP(hipMemcpyAsync(pl, phi_lin, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        lambda_m_recover(p, phi_lin, true, pl + p.nn, s);
-        phi_lin = pl;
+        double *ll = scratch<double>(p, SCR_PL, S.nv);
+        lambda_m_recover(p, phi_lin, true, ll, s);
+        lam_l = ll;
         if (phi_nl) {
-            double *pn = scratch<double>(p, SCR_PN, n);
-            PB_HIP(hipMemcpyAsync(pn, phi_nl, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-            lambda_m_recover(p, phi_nl, false, pn + p.nn, s);
-            phi_nl = pn;
+            double *ln = scratch<double>(p, SCR_PN, S.nv);
+            lambda_m_recover(p, phi_nl, false, ln, s);
+            lam_n = ln;
         }
     }
     double lc = 0.0, nc = 0.0;
     if (p.nq > 0) {
-        SurfaceDev &S = p.surf[0];
         double *d_ur = scratch<double>(p, SCR_UR, 2 * p.nq);
         hipLaunchKernelGGL(k_reaction_potential, dim3(unsigned(p.nq)), dim3(256), 0, s, S.nt, S.qp, S.nrm, S.area,
-                           S.tri, S.g, p.nn, p.d_q, phi_lin, phi_nl, tri_rule_arg(), d_ur);
+                           S.tri, S.g, S.iw, p.d_tet, p.d_q, phi_lin, lam_l, phi_nl, lam_n, tri_rule_arg(), d_ur);
         std::vector<double> ur(2 * p.nq);
         PB_HIP(hipMemcpyAsync(ur.data(), d_ur, sizeof(double) * 2 * p.nq, hipMemcpyDeviceToHost, s));
         PB_HIP(hipStreamSynchronize(s));

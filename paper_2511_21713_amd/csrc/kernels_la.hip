@@ -280,6 +280,23 @@ __global__ void k_pack_m(int64_t nm, int64_t ldm, const int32_t *__restrict__ gm
     xm[k] = v;
 }
 
+// packed Gamma_m input [trace of u | 0] of an independent Gamma_m mesh: at
+// Morton position k the P1 interpolant of u at vertex mv[k] (loc: its tet and
+// barycentric coordinates, 6 doubles per vertex)
+__global__ void k_pack_trace(int64_t nm, int64_t ldm, const int32_t *__restrict__ mv, const double *__restrict__ loc,
+                             const int32_t *__restrict__ tet, const double *__restrict__ u, double *__restrict__ xm)
+{
+    const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (k >= ldm) return;
+    double v = 0.0;
+    if (k < nm) {
+        const double *l = loc + 6 * int64_t(mv[k]);
+        const int32_t *T = tet + 4 * int64_t(l[0]);
+        v = l[2] * u[T[0]] + l[3] * u[T[1]] + l[4] * u[T[2]] + l[5] * u[T[3]];
+    }
+    xm[k] = v;
+}
+
 template <typename MT>
 __global__ void k_vdiag_inv(int64_t nm, int64_t ld, const int32_t *__restrict__ mv, const MT *__restrict__ B,
                             double *__restrict__ dinv)
@@ -288,10 +305,12 @@ __global__ void k_vdiag_inv(int64_t nm, int64_t ld, const int32_t *__restrict__ 
     if (k < nm) dinv[mv[k]] = -1.0 / double(B[k * ld + nm + k]);
 }
 
-static void gemv_m(Problem &p, const double *xm, double *y, hipStream_t s)
+// rows of one Gamma_m operator (w = 0, or 2: an independent Gamma_m mesh)
+static void gemv_m(Problem &p, int w, const double *xm, double *y, hipStream_t s)
 {
-    const GemvSurf G = gemv_surf(p, 0, xm, y,
-                                 p.surf[0].sym ? scratch<double>(p, SCR_SYMP0, sym_partials_doubles(p.surf[0].nv))
+    const GemvSurf G = gemv_surf(p, w, xm, y,
+                                 p.surf[w].sym ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP2,
+                                                                 sym_partials_doubles(p.surf[w].nv))
                                                : nullptr);
     const int64_t nb0 = (G.n + GSYM - 1) / GSYM, f0 = (G.n + GFIN_ROWS - 1) / GFIN_ROWS;
     if (p.precision == PBFB_MIXED)
@@ -348,8 +367,12 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
 {
     PB_CHECK(!p.bem_mf, PBFB_ESTATE, "the two-field form needs the dense Gamma_m operator");
     ensure_rhs(p, s);
-    const SurfaceDev &M = p.surf[0];
-    const SurfaceTopo &TM = p.topo[0];
+    // the surface that carries lambda_m: Gamma_m, or the independent Gamma_m
+    // mesh (whose trace of u is the P1 interpolant at its vertices)
+    const int w = p.gm();
+    ensure_bem(p, w, s);
+    const SurfaceDev &M = p.surf[w];
+    const SurfaceTopo &TM = p.topo[w];
     const int64_t nm = M.nv, ldm = bem_ld(nm);
     double *xm = scratch<double>(p, SCR_CGX, ldm);
     double *wv = scratch<double>(p, SCR_CGV, 6 * nm + 8);
@@ -366,8 +389,12 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
         hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, nm, k, T, part);
         hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, red);
     };
-    hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.gmv, M.mvert, phi, (const double *)nullptr, xm);
-    gemv_m(p, xm, b, s);
+    if (M.iw)
+        hipLaunchKernelGGL(k_pack_trace, dim3(g), dim3(256), 0, s, nm, ldm, M.mvert, M.iw, p.d_tet, phi, xm);
+    else
+        hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.gmv, M.mvert, phi, (const double *)nullptr,
+                           xm);
+    gemv_m(p, w, xm, b, s);
     if (with_load && p.nq > 0) vec_axpby(nm, -1.0, scratch<double>(p, SCR_FM, nm), 1.0, b, s);
     if (p.precision == PBFB_MIXED)
         hipLaunchKernelGGL(k_vdiag_inv<float>, dim3(gn), dim3(256), 0, s, nm, ldm, M.mvert,
@@ -422,7 +449,7 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
             for (int k = 0; k < CHECK; ++k, ++it) {
                 hipLaunchKernelGGL(k_pack_m, dim3(g), dim3(256), 0, s, nm, ldm, M.gmv, M.mvert, (const double *)nullptr, d,
                                    xm);
-                gemv_m(p, xm, q, s); // q = V' d = -V0 d
+                gemv_m(p, w, xm, q, s); // q = V' d = -V0 d
                 dev_dots(1, d, q, nullptr, nullptr);
                 hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, red, sc);
                 hipLaunchKernelGGL(k_cg_update_spai, dim3(gn), dim3(256), 0, s, nm, sc, d, q, lam, r);

@@ -113,6 +113,8 @@ struct BlockSideDev {
 };
 
 // host-side topology of one boundary surface
+constexpr int NSURF = 3; // Gamma_m, Gamma_s, independent Gamma_m mesh (two-field form)
+
 struct SurfaceTopo {
     int64_t nv = 0, nt = 0;
     std::vector<int32_t> g;            // local vertex -> FEM node (ascending)
@@ -141,6 +143,14 @@ struct SurfaceTopo {
 struct SurfaceDev {
     int64_t nv = 0, nt = 0;
     int32_t *g = nullptr, *tri = nullptr, *v2t_ptr = nullptr, *v2t = nullptr;
+    // vertex coordinates, indexed through g (the FEM nodes, or the own
+    // vertices of an independent Gamma_m mesh)
+    const double *x = nullptr;
+    // independent Gamma_m mesh (two-field form): the tet holding each vertex
+    // and its 4 barycentric coordinates there (the trace of u by P1
+    // interpolation); null for a surface made of FEM nodes
+    int32_t *itet = nullptr;
+    double *iw = nullptr;
     int32_t *mvert = nullptr, *minv = nullptr, *gmv = nullptr; // Morton vertex order (SurfaceTopo)
     double *qp = nullptr, *nrm = nullptr, *area = nullptr; // original order: 18, 3, 1 per triangle
     // Morton-ordered triangle data for the regular assembly
@@ -222,7 +232,7 @@ enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
     SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1, SCR_SYMP0, SCR_SYMP1,
-    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC, SCR_TSLOT, SCR_VOL,
+    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC, SCR_TSLOT, SCR_VOL, SCR_SYMP2, SCR_TRL, SCR_TRN, SCR_RLOC,
     SCR_N
 };
 
@@ -236,9 +246,9 @@ struct Problem {
     int device = 0;     // the context's device, kept for the problem's own release
     int precision = PBFB_FP64;
     bool have_mesh = false, have_charges = false, have_params = false;
-    bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[2] = {false, false};
+    bool topo_ready = false, geom_ready = false, fm_ready = false, bem_ready[NSURF] = {false, false, false};
     bool val_ready = false; // FEM stiffness and coupling values (depend on the permittivities)
-    bool bem_topo_ready[2] = {false, false};
+    bool bem_topo_ready[NSURF] = {false, false, false};
     int tile_fixed = -1; // tile shape forced by pbfb_set_tile_shape (index), -1: tuned
     bool bem_mf = false; // boundary operators applied matrix-free (no dense storage)
     // host copies
@@ -252,10 +262,16 @@ struct Problem {
     std::vector<double> x;
     std::vector<int32_t> tet;
     std::vector<double> q; // 4 per charge: x, y, z, valence
-    SurfaceTopo topo[2];
+    // surfaces: Gamma_m, Gamma_s (both over FEM nodes) and, in the two-field
+    // form, optionally an independent Gamma_m mesh (own vertices rs_x) that
+    // carries lambda_m and the reaction potential (Sec. 2.3.1)
+    SurfaceTopo topo[NSURF];
+    std::vector<double> rs_x;
+    bool has_rs() const { return topo[2].nv > 0; }
+    int gm() const { return two_field() && has_rs() ? 2 : 0; } // the surface of lambda_m and u_r
     double eps_m = 0, eps_s = 0, kappa = 0, temp = 298.15, lB = 0, kT = 0;
     // device
-    Arena mesh_arena, bem_arena[2];
+    Arena mesh_arena, bem_arena[NSURF];
     ScratchBuf scr[SCR_N];
     double *d_x = nullptr, *d_tgeo = nullptr, *d_q = nullptr;
     int32_t *d_tet = nullptr, *d_n2t_ptr = nullptr, *d_n2t = nullptr, *d_slot4 = nullptr;
@@ -270,7 +286,7 @@ struct Problem {
     int64_t nnz_row = 0; // nonzeros of the rows (without it)
     double *d_b = nullptr; // right-hand side, length n
     int *d_bad = nullptr;
-    SurfaceDev surf[2];
+    SurfaceDev surf[NSURF];
     int64_t n() const { return nn + topo[0].nv + topo[1].nv; }
     // timers
     bool timing = false;
@@ -293,6 +309,8 @@ void release_device_state(Problem &p);
 
 // host preprocessing (setup.hip)
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri);
+// the same for triangles over vertices 0..nverts-1 at coordinates x
+void build_surface_topo_on(SurfaceTopo &S, int64_t nverts, const double *x, int64_t ntri, const int32_t *tri);
 const BlockSide &block_side(SurfaceTopo &S, int bs); // built on first use
 constexpr int SLICE = 64; // FEM rows per sliced-ELL slice: one wavefront
 // Krylov state of a batched GMRES instance (the state word every batched kernel reads)

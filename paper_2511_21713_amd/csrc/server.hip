@@ -41,7 +41,8 @@ void footprint_estimate(const Problem &p, int restart, size_t *steady, size_t *s
         dense += T.tp_sig.size() * 18 * 8 + size_t(T.nt) * 15 * 8 + size_t(T.nv) * 40 * 16;
         tmp = std::max(tmp, size_t(T.nv) * 3 * 8);
     }
-    for (int w = 0; w < 2 && !p.bem_mf; ++w) {
+    for (int w = 0; w < NSURF && !p.bem_mf; ++w) {
+        if (w == 2 && p.gm() != 2) continue; // the independent Gamma_m mesh: only when it is used
         const SurfaceTopo &T = p.topo[w];
         dense += size_t(T.nv) * bem_ld(T.nv) * elem;
         dense += size_t(sym_partials_doubles(T.nv)) * 8 + size_t(T.nv) * 20 * 12; // symmetric use: partials, Delta

@@ -111,16 +111,20 @@ const BlockSide &block_side(SurfaceTopo &S, int bs)
 
 void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
 {
-    SurfaceTopo &S = p.topo[which];
+    build_surface_topo_on(p.topo[which], p.nn, p.x.data(), ntri, tri);
+}
+
+void build_surface_topo_on(SurfaceTopo &S, int64_t nverts, const double *x, int64_t ntri, const int32_t *tri)
+{
     S = SurfaceTopo();
     S.nt = ntri;
     PB_CHECK(ntri >= 4, PBFB_EMESH, "surface needs at least 4 triangles");
-    std::vector<int32_t> loc(p.nn, -1);
+    std::vector<int32_t> loc(nverts, -1);
     for (int64_t k = 0; k < 3 * ntri; ++k) {
-        PB_CHECK(tri[k] >= 0 && tri[k] < p.nn, PBFB_EINVAL, "surface triangle references a node out of range");
+        PB_CHECK(tri[k] >= 0 && tri[k] < nverts, PBFB_EINVAL, "surface triangle references a node out of range");
         loc[tri[k]] = 0;
     }
-    for (int64_t i = 0; i < p.nn; ++i)
+    for (int64_t i = 0; i < nverts; ++i)
         if (loc[i] == 0) {
             loc[i] = int32_t(S.g.size());
             S.g.push_back(int32_t(i));
@@ -162,8 +166,8 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int64_t i = 0; i < S.nv; ++i)
             for (int d = 0; d < 3; ++d) {
-                lo[d] = std::min(lo[d], p.x[3 * S.g[i] + d]);
-                hi[d] = std::max(hi[d], p.x[3 * S.g[i] + d]);
+                lo[d] = std::min(lo[d], x[3 * S.g[i] + d]);
+                hi[d] = std::max(hi[d], x[3 * S.g[i] + d]);
             }
         double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-30});
         std::vector<std::pair<uint32_t, int32_t>> key(ntri);
@@ -171,7 +175,7 @@ void build_surface_topo(Problem &p, int which, int64_t ntri, const int32_t *tri)
             uint32_t code = 0;
             for (int d = 0; d < 3; ++d) {
                 double c = 0;
-                for (int a = 0; a < 3; ++a) c += p.x[3 * S.g[S.tri[3 * t + a]] + d];
+                for (int a = 0; a < 3; ++a) c += x[3 * S.g[S.tri[3 * t + a]] + d];
                 c = (c / 3.0 - lo[d]) / span;
                 code |= spread10(uint32_t(std::min(1023.0, std::max(0.0, c * 1023.0)))) << d;
             }

@@ -156,3 +156,112 @@ def test_two_field_errors(ctx):
     with pytest.raises(pb.PbfbError):
         g.set_two_field(prob.n_tets_m)
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# Gamma_m given as its own surface mesh, finer than the volume mesh's
+# interface and not a face set of it (Sec. 2.3.1: the trace of the volume
+# solution on it by interpolation between the two meshes)
+# ---------------------------------------------------------------------------
+RS_CASES = {
+    "bumpy_n3_rs7": dict(CASES["bumpy_n3"], reaction_n=7),
+    "sphere_n8_rs12": dict(CASES["sphere_n8"], reaction_n=12),
+}
+_RS_ORACLE = {}
+
+
+@pytest.fixture(scope="module", params=sorted(RS_CASES))
+def rs_case(request, ctx):
+    import paper_2511_21713_amd as pb
+    name = request.param
+    log(f"[gpu two-field, independent Gamma_m] case {name}")
+    prob = pbgen.make_problem(**RS_CASES[name])
+    o = oracle.Oracle.from_problem(prob)
+    g = pb.Problem.from_inputs(ctx, prob)
+    return name, prob, o, g
+
+
+def rs_oracle_solve(name, o):
+    if name not in _RS_ORACLE:
+        _RS_ORACLE[name] = o.solve(**TIGHT)
+    return _RS_ORACLE[name]
+
+
+def test_independent_gamma_m_solve_matches_oracle(rs_case, ctx):
+    import paper_2511_21713_amd as pb
+    name, prob, o, g = rs_case
+    phi = np.zeros(2 * o.n)
+    rg = g.solve(phi_out=phi, **TIGHT)
+    ro, pl, pn = rs_oracle_solve(name, o)
+    log(f"  {name}: total {rg['total']!r} vs {ro['total']!r} (lc {rg['lc']:.6f} nc {rg['nc']:.6f}), "
+        f"newton {rg['newton_iters']}/{ro['newton_iters']}")
+    assert rg["status"] == 0 and rg["newton_iters"] == ro["newton_iters"]
+    for k in ("total", "lc", "nc", "dg_omega_i"):
+        assert abs(rg[k] - ro[k]) <= 1e-10 * abs(ro["total"]), k
+    assert rel(phi[:o.n], pl) < 1e-9 and rel(phi[o.n:], pn) < 1e-8
+    e = g.energy(phi[:o.n], phi[o.n:])
+    assert abs(e["total"] - rg["total"]) <= 1e-12 * abs(rg["total"])
+    # the same volume mesh with the interface faces as Gamma_m: the volume
+    # solution is the same, the energy differs by the surface discretisation
+    base = {k: v for k, v in RS_CASES[name].items() if k != "reaction_n"}
+    g0 = pb.Problem.from_inputs(ctx, pbgen.make_problem(**base))
+    e0 = g0.energy(phi[:o.n], phi[o.n:])
+    d = abs(e0["total"] - rg["total"]) / abs(rg["total"])
+    log(f"  {name}: conforming-Gamma_m energy differs by {d:.2e}")
+    assert 1e-8 < d < 0.05
+    g0.close()
+
+
+def test_independent_gamma_m_mixed_precision(rs_case, ctx):
+    import paper_2511_21713_amd as pb
+    name, prob, o, _ = rs_case
+    gm = pb.Problem.from_inputs(ctx, prob, precision=pb.MIXED)
+    rm = gm.solve(**dict(TIGHT, tol_nl=1e-7, tol_gr=1e-9, tol_gr0=1e-9, tol_omega=1e-7))
+    ro, _, _ = rs_oracle_solve(name, o)
+    eE = abs(rm["total"] - ro["total"]) / abs(ro["total"])
+    log(f"  {name} mixed: energy {eE:.2e}")
+    assert rm["status"] == 0 and eE < 1e-5
+    gm.close()
+
+
+def test_independent_gamma_m_batch_equals_solo(ctx):
+    import paper_2511_21713_amd as pb
+    probs = [pbgen.make_problem(**RS_CASES["bumpy_n3_rs7"]), pbgen.make_problem(**CASES["bumpy_n3"])]
+    solo = []
+    for prob in probs:
+        g = pb.Problem.from_inputs(ctx, prob)
+        solo.append(g.solve(**TIGHT))
+        g.close()
+    gs = [pb.Problem.from_inputs(ctx, prob) for prob in probs]
+    code, res = pb.solve_batch(ctx, gs, **TIGHT)
+    assert code == 0
+    for r, s in zip(res, solo):
+        assert r["total"] == s["total"] and r["gmres_iters"] == s["gmres_iters"]
+    for g in gs:
+        g.close()
+
+
+def test_independent_gamma_m_errors(ctx):
+    import paper_2511_21713_amd as pb
+    prob = pbgen.make_problem(**RS_CASES["bumpy_n3_rs7"])
+    v, t = prob.rs_verts, prob.rs_tris
+    g = pb.Problem.from_inputs(ctx, prob)
+    with pytest.raises(pb.PbfbError):          # vertex id out of range
+        g.set_reaction_surface(v, np.where(t == 0, len(v), t))
+    with pytest.raises(pb.PbfbError):          # not closed
+        g.set_reaction_surface(v, t[1:])
+    # oriented inward: refused at setup
+    g.set_reaction_surface(v, t[:, ::-1].copy())
+    with pytest.raises(pb.PbfbError):
+        g.solve(**TIGHT)
+    # a surface outside the FEM mesh: refused at setup
+    g.set_reaction_surface(v + np.array([0.0, 0.0, 100.0]), t)
+    with pytest.raises(pb.PbfbError):
+        g.solve(**TIGHT)
+    # removed: the conforming two-field form again (bitwise the plain one)
+    g.set_reaction_surface(None, None)
+    r = g.solve(**TIGHT)
+    g2 = pb.Problem.from_inputs(ctx, pbgen.make_problem(**CASES["bumpy_n3"]))
+    assert r["total"] == g2.solve(**TIGHT)["total"]
+    g.close()
+    g2.close()
