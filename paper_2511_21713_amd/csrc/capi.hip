@@ -368,7 +368,13 @@ void pbfb_ctx_destroy(pbfb_ctx *ctx)
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     (void)hipStreamDestroy(ctx->c.stream);
-    if (ctx->c.asm_ws.ptr) (void)hipFree(ctx->c.asm_ws.ptr);
+    for (hipStream_t st : ctx->c.setup_stream)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    for (Workspace &w : ctx->c.asm_ws)
+        if (w.ptr) (void)hipFree(w.ptr);
     delete ctx;
 }
 

@@ -36,7 +36,9 @@
 // as FP32), and each tile's sum is added to the FP32 stored entry in FP64
 // and rounded once (an entry receives one tile's sum for each pair of blocks
 // holding its two vertices).  The touching pairs stay FP64 throughout.
+#include <chrono>
 #include <cmath>
+#include <thread>
 #include <type_traits>
 
 #include "bem_quad.hpp"
@@ -1177,15 +1179,27 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     hipLaunchKernelGGL(k_tri_morton, dim3(nblk(T.nt, 256)), dim3(256), 0, s, T.nt, S.morton, S.tri, S.qp, S.nrm,
                        S.area, S.g, S.x, S.m_tri, S.m_qp, S.m_nrm, S.m_area, S.m_cen, S.m_qf, S.m_nf);
 
-    // the context's assembly workspace (see below) is used by one assembly at a time
-    std::lock_guard<std::mutex> ws_lock(p.ctx->asm_ws.mu);
+    // one of the context's assembly workspaces (see below), used by one assembly at a time
+    Workspace *wsp = nullptr;
+    std::unique_lock<std::mutex> ws_lock;
+    while (!wsp) {
+        for (Workspace &W : p.ctx->asm_ws) {
+            std::unique_lock<std::mutex> l(W.mu, std::try_to_lock);
+            if (l.owns_lock()) {
+                wsp = &W;
+                ws_lock = std::move(l);
+                break;
+            }
+        }
+        if (!wsp) std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
     struct Drain { // on every exit the stream drains before the workspace is released
         hipStream_t s;
         ~Drain() { (void)hipStreamSynchronize(s); }
     } drain{s};
     if (p.bem_mf) {
         // matrix-free: only the touching-pair blocks (kept) and the diagonal of V'
-        double *vxm = p.ctx->asm_ws.doubles(3 * T.nv);
+        double *vxm = wsp->doubles(3 * T.nv);
         hipLaunchKernelGGL(k_gather_coords, dim3(nblk(T.nv, 256)), dim3(256), 0, s, T.nv, S.g, S.x, vxm);
         GL4 G = gl4arg();
         if (p.timing) p.timer.begin(T_SING, s);
@@ -1228,7 +1242,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     // square-tile assembly (nv x nv in the storage precision), vertex
     // coordinates and the touching-pair blocks
     const size_t tbytes = (size_t(nv) * nv * elem + 255) / 256 * 256;
-    double *ws = p.ctx->asm_ws.doubles((tbytes + 8 * (3 * size_t(nv) + 18 * size_t(S.ntp))) / 8 + 1);
+    double *ws = wsp->doubles((tbytes + 8 * (3 * size_t(nv) + 18 * size_t(S.ntp))) / 8 + 1);
     void *Tm = ws;
     double *vx = reinterpret_cast<double *>(static_cast<char *>(Tm) + tbytes), *tpv = vx + 3 * nv;
     ra.T = Tm;
@@ -1236,6 +1250,7 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     int shape = p.tile_fixed;
     if (shape < 0) {
         const int key = tile_key(p.precision, yuk, T.nt);
+        std::lock_guard<std::mutex> tl(p.ctx->tune_mu);
         auto it = p.ctx->tile_choice.find(key);
         if (it != p.ctx->tile_choice.end()) {
             shape = it->second;

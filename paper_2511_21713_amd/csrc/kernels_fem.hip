@@ -242,8 +242,12 @@ template <int MODE>
 __global__ void __launch_bounds__(128)
     k_tet_reaction(int64_t ntet, const double *__restrict__ tg, const int32_t *__restrict__ tet,
                    const double *__restrict__ u, const double *__restrict__ D, double omega, int scheme, double c,
-                   TetRuleArg R, int64_t nt_i, double *__restrict__ out)
+                   TetRuleArg R, int64_t nt_i, double *__restrict__ out, const double *__restrict__ wdev,
+                   const int *__restrict__ skip)
 {
+    // MODE_W: omega from wdev when given (a search on the device); skip: optional flag, nonzero = nothing to do
+    if (skip && *skip) return;
+    if (MODE == MODE_W && wdev) omega = *wdev;
     const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (t >= ntet) return;
     constexpr int NZ = MODE == MODE_N ? 4 : MODE == MODE_W ? 12 : 16;
@@ -320,8 +324,9 @@ __global__ void k_jacobian(int64_t nn, const int32_t *__restrict__ sptr, const d
 template <int K>
 __global__ void k_node_gather(int64_t nn, const int32_t *__restrict__ n2t_ptr, const int32_t *__restrict__ n2t,
                               const double *__restrict__ per_tet, double *__restrict__ o0, double *__restrict__ o1,
-                              double *__restrict__ o2)
+                              double *__restrict__ o2, const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (a >= nn) return;
     double s[K];
@@ -813,7 +818,8 @@ void fem_assemble_jacobian(Problem &p, int scheme, const double *u, hipStream_t 
     const double c = p.eps_s * p.kappa * p.kappa;
     double *Jt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_J>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
-                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Jt);
+                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Jt,
+                       (const double *)nullptr, (const int *)nullptr);
     hipLaunchKernelGGL(k_jacobian, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_sptr, p.d_val0, p.d_val,
                        p.d_val32, p.d_n2t_ptr, p.d_n2t, p.d_slot4, Jt);
     PB_HIP(hipGetLastError());
@@ -836,21 +842,22 @@ void fem_nonlinear_buf(Problem &p, int scheme, const double *u, double *out, dou
 {
     const double c = p.eps_s * p.kappa * p.kappa;
     hipLaunchKernelGGL(k_tet_reaction<MODE_N>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
-                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Nt);
+                       u, (const double *)nullptr, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Nt,
+                       (const double *)nullptr, (const int *)nullptr);
     hipLaunchKernelGGL(k_node_gather<1>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Nt,
-                       out, (double *)nullptr, (double *)nullptr);
+                       out, (double *)nullptr, (double *)nullptr, (const int *)nullptr);
     PB_HIP(hipGetLastError());
 }
 
-void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN, double *rJ,
-                     double *rH, hipStream_t s)
+void fem_omega_terms_dev(Problem &p, int scheme, const double *u, const double *D, const double *wdev,
+                         const int *skip, double *rN, double *rJ, double *rH, hipStream_t s)
 {
     const double c = p.eps_s * p.kappa * p.kappa;
     double *Wt = scratch<double>(p, SCR_TETR, 16 * size_t(p.ntet));
     hipLaunchKernelGGL(k_tet_reaction<MODE_W>, dim3(nblocks(p.ntet, 128)), dim3(128), 0, s, p.ntet, p.d_tgeo, p.d_tet,
-                       u, D, omega, scheme, c, tet_rule_arg(), p.ntet_i(), Wt);
+                       u, D, 0.0, scheme, c, tet_rule_arg(), p.ntet_i(), Wt, wdev, skip);
     hipLaunchKernelGGL(k_node_gather<3>, dim3(nblocks(p.nn, 128)), dim3(128), 0, s, p.nn, p.d_n2t_ptr, p.d_n2t, Wt,
-                       rN, rJ, rH);
+                       rN, rJ, rH, skip);
     PB_HIP(hipGetLastError());
 }
 

@@ -119,9 +119,12 @@ struct PtrTab {
     const double *b[8];
 };
 
-// partial dot products of k <= 8 vector pairs; partial[b * k + j]
-__global__ void __launch_bounds__(256) k_dots_partial(int64_t n, int k, PtrTab T, double *__restrict__ partial)
+// partial dot products of k <= 8 vector pairs; partial[b * k + j] (skip:
+// optional device flag, nonzero = nothing to do)
+__global__ void __launch_bounds__(256) k_dots_partial(int64_t n, int k, PtrTab T, double *__restrict__ partial,
+                                                      const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const double *const *A = T.a;
     const double *const *Bv = T.b;
     __shared__ double red[8][256];
@@ -139,8 +142,10 @@ __global__ void __launch_bounds__(256) k_dots_partial(int64_t n, int k, PtrTab T
     if (threadIdx.x < k) partial[blockIdx.x * k + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_reduce_partial(int nb, int k, const double *__restrict__ partial, double *__restrict__ out)
+__global__ void k_reduce_partial(int nb, int k, const double *__restrict__ partial, double *__restrict__ out,
+                                 const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     __shared__ double red[256];
     const int j = blockIdx.x;
     double s = 0.0;
@@ -386,8 +391,9 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
         T.b[0] = b0;
         T.a[1] = a1;
         T.b[1] = b1;
-        hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, nm, k, T, part);
-        hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, red);
+        hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, nm, k, T, part, (const int *)nullptr);
+        hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, red,
+                           (const int *)nullptr);
     };
     if (M.iw)
         hipLaunchKernelGGL(k_pack_trace, dim3(g), dim3(256), 0, s, nm, ldm, M.mvert, M.iw, p.d_tet, phi, xm);
@@ -472,18 +478,24 @@ void lambda_m_recover(Problem &p, const double *phi, bool with_load, double *lam
 }
 void coupled_apply_linear(Problem &p, const double *x, double *y, hipStream_t s) { apply_impl(p, x, y, false, s); }
 
-void dots(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out, hipStream_t s)
+void dots_dev(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out,
+              const int *skip, hipStream_t s)
 {
-    // k <= 8 pairs
+    // k <= 8 pairs; fixed-order partial sums over RED_BLOCKS blocks, then one block each
     double *part = scratch<double>(p, SCR_DOT, RED_BLOCKS * 8 + 8);
-    double *res = part + RED_BLOCKS * 8;
     PtrTab T{};
     for (int j = 0; j < k; ++j) {
         T.a[j] = a[j];
         T.b[j] = b[j];
     }
-    hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, n, k, T, part);
-    hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, res);
+    hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(256), 0, s, n, k, T, part, skip);
+    hipLaunchKernelGGL(k_reduce_partial, dim3(k), dim3(256), 0, s, RED_BLOCKS, k, part, out, skip);
+}
+
+void dots(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out, hipStream_t s)
+{
+    double *res = scratch<double>(p, SCR_DOT, RED_BLOCKS * 8 + 8) + RED_BLOCKS * 8;
+    dots_dev(p, k, a, b, n, res, nullptr, s);
     PB_HIP(hipMemcpyAsync(out, res, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     PB_HIP(hipStreamSynchronize(s));
 }

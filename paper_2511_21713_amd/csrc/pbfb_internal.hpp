@@ -186,9 +186,10 @@ struct SurfaceDev {
 };
 
 // Device workspace shared by the problems of a context for their dense
-// assembly (expanded tile matrices, gather buffers, FP64 staging): grown on
-// demand, never shrunk, freed with the context.  One assembly uses it at a
-// time (the mutex is held until the assembly's stream has drained).
+// assembly (the mirrored double layer of a square-tile assembly, vertex
+// coordinates, touching-pair blocks): grown on demand, never shrunk, freed
+// with the context.  One assembly uses it at a time (the mutex is held until
+// the assembly's stream has drained).
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -198,12 +199,26 @@ struct Workspace {
 };
 
 struct Problem;
+// assemblies of one context that may run at once (the device setup of a
+// batch runs on this many host threads and streams)
+constexpr int N_ASM_WS = 4;
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    Workspace asm_ws;
-    // tuned tile shape per (precision, kernel, size class); guarded by asm_ws.mu
+    Workspace asm_ws[N_ASM_WS];
+    hipStream_t setup_stream[N_ASM_WS] = {}; // streams of a batch's parallel device setup, created on first use
+    std::mutex setup_mu;                     // guards their creation
+    // tuned tile shape per (precision, kernel, size class); tune_mu guards it
+    // and serialises the tuning, so every problem of the context sees one choice
+    std::mutex tune_mu;
     std::map<int, int> tile_choice;
+    size_t ws_held() const
+    {
+        size_t b = 0;
+        for (const Workspace &w : asm_ws) b += w.held.load();
+        return b;
+    }
     // problems created in this context and not yet destroyed
     std::mutex live_mu;
     std::set<Problem *> live;
@@ -232,7 +247,7 @@ enum ScratchSlot {
     SCR_CHK, SCR_TRIF, SCR_Q, SCR_EPART, SCR_UR, SCR_B, SCR_DOT, SCR_XM, SCR_XS, SCR_TPTAU,
     SCR_G0, SCR_G1, SCR_G2, SCR_G3, SCR_G4, SCR_G5, SCR_G6, SCR_G7, SCR_G8, SCR_G9, SCR_G10, SCR_G11, SCR_G12,
     SCR_BASIS, SCR_BASIS32, SCR_HPART, SCR_HVEC, SCR_NRM, SCR_CNT, SCR_PZ, SCR_PT, SCR_PZB, SCR_PDK, SCR_LMAX, SCR_PCOEF, SCR_TETR, SCR_MF0, SCR_MF1, SCR_SYMP0, SCR_SYMP1,
-    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC, SCR_TSLOT, SCR_VOL, SCR_SYMP2, SCR_TRL, SCR_TRN, SCR_RLOC,
+    SCR_FM, SCR_PL, SCR_PN, SCR_CGX, SCR_CGV, SCR_PLOC, SCR_TSLOT, SCR_VOL, SCR_SYMP2, SCR_RLOC, SCR_OMEGA,
     SCR_N
 };
 
@@ -342,8 +357,10 @@ void mf_spai(Problem &p, int w, hipStream_t s);
 void near_pattern(SurfaceTopo &S); // host: the 3-ring pattern (nf_ptr, nf_col), once
 void delta_pattern(SurfaceTopo &S); // host: the upper two-ring pattern (d2_ptr, d2_col), once
 void fem_nonlinear(Problem &p, int scheme, const double *u, double *out, hipStream_t s);
-void fem_omega_terms(Problem &p, int scheme, const double *u, const double *D, double omega, double *rN,
-                     double *rJ, double *rH, hipStream_t s);
+// f_d terms of the relaxation search at the omega held in device memory
+// (wdev); every kernel returns at once while *skip is nonzero
+void fem_omega_terms_dev(Problem &p, int scheme, const double *u, const double *D, const double *wdev,
+                         const int *skip, double *rN, double *rJ, double *rH, hipStream_t s);
 double fem_energy_integral(Problem &p, const double *u_lin, const double *u_nl, hipStream_t s);
 
 // coupled operator y = J x with the current CSR values (pack + GEMV + SpMV)
@@ -370,6 +387,9 @@ void vec_mul(int64_t n, const double *a, const double *x, double *y, hipStream_t
 void vec_add(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
 double dot(Problem &p, const double *a, const double *b, int64_t n, hipStream_t s);
 void dots(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out, hipStream_t s);
+// the same into device memory (out[0..k)), no host round trip; skip as above
+void dots_dev(Problem &p, int k, const double *const *a, const double *const *b, int64_t n, double *out,
+              const int *skip, hipStream_t s);
 
 // energy
 void energy(Problem &p, const double *phi_lin, const double *phi_nl, double out[4], hipStream_t s);
@@ -416,9 +436,20 @@ struct NewtonRun {
     GmresJob job{};
     std::string message;
     std::chrono::steady_clock::time_point t0, t1;
+    // relaxation search of the current step, run on the device (OmegaSearch
+    // in device memory) for every searching instance of a batch together
+    bool searching = false, searched = false;
+    double omega = 1.0;
+    void *om_dev = nullptr;  // the device state
+    double om_host[4] = {0, 0, 0, 0}; // read back: done, omega, evaluations, fallback
     NewtonRun(Problem *p_, const pbfb_solve_opts &o_, pbfb_result *res_, double *out);
 };
 bool advance(NewtonRun &r, hipStream_t s);               // true: needs its linear solve
+// advances every unfinished run to its next linear solve (its job appended to
+// jobs) or to its end (appended to finished, if given); the relaxation
+// searches of all runs between two linear solves run together on the device
+void advance_all(std::vector<NewtonRun *> &runs, std::vector<GmresJob *> &jobs, std::vector<NewtonRun *> *finished,
+                 hipStream_t s);
 void run_newton(std::vector<NewtonRun *> &runs, hipStream_t s);
 pbfb_status solve(Problem &p, const pbfb_solve_opts &o, pbfb_result &res, double *phi_out_dev, hipStream_t s);
 

@@ -95,7 +95,7 @@ struct Server {
     // device bytes charged for the shared assembly workspace if r were admitted
     size_t ws_with(const Request *r) const
     {
-        return std::max(std::max(ws_need, r->extra), ctx->asm_ws.held.load());
+        return std::max(std::max(ws_need, r->extra), ctx->ws_held());
     }
 
     void admit_locked()
@@ -185,9 +185,12 @@ struct Server {
             if (running.empty()) continue;
             jobs.clear();
             std::vector<Request *> finished;
-            for (Request *r : running) {
-                if (advance(*r->run, s_solve)) jobs.push_back(&r->run->job);
-                else finished.push_back(r);
+            {
+                std::vector<NewtonRun *> runs, done;
+                for (Request *r : running) runs.push_back(r->run);
+                advance_all(runs, jobs, &done, s_solve);
+                for (Request *r : running)
+                    if (std::find(done.begin(), done.end(), r->run) != done.end()) finished.push_back(r);
             }
             if (!jobs.empty()) {
                 try {

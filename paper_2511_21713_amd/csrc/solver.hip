@@ -14,8 +14,10 @@
 // once e_k < L_e, and the GMRES tolerance is tightened tenfold per step once
 // e_k < 1250 tol (App. B).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <thread>
 
 #include "pbfb_internal.hpp"
 
@@ -100,7 +102,8 @@ void fem_gershgorin(Problem &p, double *lmax_dev, hipStream_t s)
     PB_HIP(hipGetLastError());
 }
 
-enum RunPhase { PH_START = 0, PH_LINEAR = 1, PH_NEWTON = 2, PH_DONE = 3 };
+enum RunPhase { PH_START = 0, PH_LINEAR = 1, PH_NEWTON = 2, PH_DONE = 3, PH_POST = 4 };
+// PH_POST: back from a Newton linear solve, omega of the step set up (searched with the batch's)
 
 // the linear-solve request of the current Newton matrix (its FEM values,
 // diagonal and Chebyshev bound are computed here)
@@ -182,224 +185,365 @@ static bool newton_pre(NewtonRun &r, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // root of f_d (Sec. 2.5; the appendix on one-dimensional root finding and
-// the first-iteration start of the appendix on other optimisations).
-// Every method stops at |f_d| < tol_omega or after max_omega_it
+// the first-iteration start of the appendix on other optimisations), on the
+// device.  Every method stops at |f_d| < tol_omega or after max_omega_it
 // evaluations; iterates are clamped to [omega_min, omega_max]; an undefined
 // f_d (beta = 0) or a vanishing derivative / secant slope gives omega = 1.
+//
+// The search of one instance is a small state machine in device memory
+// (OmegaSearch).  One evaluation round is: the f_d terms at S.w (the element
+// kernel reads omega from S.w), their six dot products into S.v, then
+// k_omega_step, one thread that forms f_d and f_d' and moves the state to
+// the next point to evaluate or to its result.  Once S.done is set the
+// round's kernels return at once.  The host enqueues rounds for every
+// searching instance of the batch and reads the done flags back only every
+// few rounds, one copy and one synchronisation for all of them.
 // ---------------------------------------------------------------------------
-static double clampw(double w, const pbfb_solve_opts &o) { return std::min(o.omega_max, std::max(o.omega_min, w)); }
+enum OmPhase {
+    OM_NEWTON = 0, // evaluating w of the Newton iteration
+    OM_SEC_A,      // secant: the first point w0
+    OM_SEC_B,      // secant: the second point / each new point w1
+    OM_BIS_LO,     // bisection: the lower end
+    OM_BIS_HI,     // bisection: the upper end
+    OM_BIS_MID,    // bisection: a midpoint
+    OM_BS_START,   // first-iteration start: the three midpoints of [2, 3]
+    OM_BS_SEC,     // first-iteration start: its secant steps
+    OM_DF          // direct secant through (0, 1): the point 1/8
+};
 
-template <class F>
-static double omega_newton(const pbfb_solve_opts &o, F &f, double w, int &ev, bool &fb)
+struct OmegaSearch {
+    // setup
+    int method, k, max_it;
+    double tol, wmin, wmax, omega0;
+    double pp; // p.p of this step
+    // state
+    int phase, ev, done, fb, si;
+    double w; // the point of the next evaluation (the element kernel reads it)
+    double lo, hi, flo, wstart;
+    double w0, f0, w1, f1;
+    double blo, bhi, bw[3], bf[3];
+    double result;
+    double v[6]; // (p . r) over all unknowns, then (rJ.r, rJ.p, rJ.rJ, r.rH, p.rH) over the FEM rows
+};
+
+__device__ inline double om_clamp(const OmegaSearch &S, double w) { return fmin(S.wmax, fmax(S.wmin, w)); }
+__device__ inline void om_finish(OmegaSearch &S, double w, bool fallback)
 {
-    while (ev < o.max_omega_it) {
-        double fd = 0.0, dfd = 0.0;
-        ++ev;
-        if (!f(w, fd, dfd)) {
-            fb = true;
-            return 1.0;
-        }
-        if (std::fabs(fd) < o.tol_omega) return w;
-        if (dfd == 0.0 || !std::isfinite(dfd)) {
-            fb = true;
-            return 1.0;
-        }
-        w = clampw(w - fd / dfd, o);
-    }
-    return w;
+    S.result = w;
+    S.fb = fallback ? 1 : S.fb;
+    S.done = 1;
+}
+// Newton from w (the while condition of the iteration is checked first)
+__device__ inline void om_newton_start(OmegaSearch &S, double w)
+{
+    if (S.ev >= S.max_it) return om_finish(S, w, false);
+    S.phase = OM_NEWTON;
+    S.w = w;
+}
+__device__ inline void om_bisect_start(OmegaSearch &S, double lo, double hi, double wstart)
+{
+    S.lo = lo;
+    S.hi = hi;
+    S.wstart = wstart;
+    S.phase = OM_BIS_LO;
+    S.w = lo;
+}
+__device__ inline void om_secant_start(OmegaSearch &S, double w0, double w1)
+{
+    S.w0 = w0;
+    S.w1 = w1;
+    S.phase = OM_SEC_A;
+    S.w = w0;
+}
+// the secant loop of the first-iteration start, from (w0, f0), (w1, f1)
+__device__ inline void om_bs_loop(OmegaSearch &S)
+{
+    if (S.ev >= S.max_it) return om_newton_start(S, S.w1);
+    const double slope = S.f0 - S.f1;
+    if (slope == 0.0 || !isfinite(slope)) return om_newton_start(S, S.w1);
+    const double w2 = om_clamp(S, S.w0 - (S.w0 - S.w1) * S.f0 / slope);
+    if (fabs(w2 - S.w1) < 0.05) return om_newton_start(S, w2);
+    S.w0 = S.w1;
+    S.f0 = S.f1;
+    S.w1 = w2;
+    S.phase = OM_BS_SEC;
+    S.w = w2;
 }
 
-// secant from the pair (w0, w1)
-template <class F>
-static double omega_secant(const pbfb_solve_opts &o, F &f, double w0, double w1, int &ev, bool &fb)
+__global__ void k_omega_init(OmegaSearch *__restrict__ S_, int method, int k, int max_it, double tol, double wmin,
+                             double wmax, double omega0)
 {
-    double f0 = 0.0, f1 = 0.0, d = 0.0;
-    ++ev;
-    if (!f(w0, f0, d)) {
-        fb = true;
-        return 1.0;
-    }
-    if (std::fabs(f0) < o.tol_omega) return w0;
-    ++ev;
-    if (!f(w1, f1, d)) {
-        fb = true;
-        return 1.0;
-    }
-    while (std::fabs(f1) >= o.tol_omega && ev < o.max_omega_it) {
-        const double slope = f0 - f1;
-        if (slope == 0.0 || !std::isfinite(slope)) {
-            fb = true;
-            return 1.0;
-        }
-        const double w2 = clampw(w0 - (w0 - w1) * f0 / slope, o);
-        w0 = w1;
-        f0 = f1;
-        w1 = w2;
-        ++ev;
-        if (!f(w1, f1, d)) {
-            fb = true;
-            return 1.0;
-        }
-    }
-    return w1;
-}
-
-// bisection of [lo, hi]; Newton from w_start when f_d keeps its sign over it
-template <class F>
-static double omega_bisect(const pbfb_solve_opts &o, F &f, double lo, double hi, double w_start, int &ev, bool &fb)
-{
-    double flo = 0.0, fhi = 0.0, d = 0.0;
-    ++ev;
-    if (!f(lo, flo, d)) {
-        fb = true;
-        return 1.0;
-    }
-    if (std::fabs(flo) < o.tol_omega) return lo;
-    ++ev;
-    if (!f(hi, fhi, d)) {
-        fb = true;
-        return 1.0;
-    }
-    if (std::fabs(fhi) < o.tol_omega) return hi;
-    if ((flo > 0.0) == (fhi > 0.0)) return omega_newton(o, f, w_start, ev, fb);
-    double mid = 0.5 * (lo + hi);
-    while (ev < o.max_omega_it) {
-        mid = 0.5 * (lo + hi);
-        double fm = 0.0;
-        ++ev;
-        if (!f(mid, fm, d)) {
-            fb = true;
-            return 1.0;
-        }
-        if (std::fabs(fm) < o.tol_omega) return mid;
-        if ((fm > 0.0) == (flo > 0.0)) {
-            lo = mid;
-            flo = fm;
-        } else {
-            hi = mid;
-        }
-    }
-    return mid;
-}
-
-// first-iteration start: three bisection midpoints of [2, 3] (a positive
-// f_d moves up: f_d decreases through its root), then secant steps from the
-// last two until successive iterates differ by less than 0.05
-template <class F> static double omega_start_bs(const pbfb_solve_opts &o, F &f, int &ev, bool &fb)
-{
-    double lo = 2.0, hi = 3.0, w[3], fv[3], d = 0.0;
-    for (int i = 0; i < 3; ++i) {
-        w[i] = 0.5 * (lo + hi);
-        ++ev;
-        if (!f(w[i], fv[i], d)) {
-            fb = true;
-            return 1.0;
-        }
-        if (fv[i] > 0.0) lo = w[i];
-        else hi = w[i];
-    }
-    double w0 = w[1], f0 = fv[1], w1 = w[2], f1 = fv[2];
-    while (ev < o.max_omega_it) {
-        const double slope = f0 - f1;
-        if (slope == 0.0 || !std::isfinite(slope)) break;
-        const double w2 = clampw(w0 - (w0 - w1) * f0 / slope, o);
-        if (std::fabs(w2 - w1) < 0.05) return w2;
-        w0 = w1;
-        f0 = f1;
-        w1 = w2;
-        ++ev;
-        if (!f(w1, f1, d)) {
-            fb = true;
-            return 1.0;
-        }
-    }
-    return w1;
-}
-
-// the root finder of opts.omega_method at nonlinear iteration k (1-based)
-template <class F>
-static double omega_root(const pbfb_solve_opts &o, int k, double omega0, F &f, int &ev, bool &fb)
-{
-    switch (o.omega_method) {
-    case PBFB_OMEGA_BISECT: return omega_bisect(o, f, o.omega_min, o.omega_max, omega0, ev, fb);
-    case PBFB_OMEGA_SECANT: return omega_secant(o, f, omega0, omega0 + 0.125, ev, fb);
+    if (threadIdx.x != 0) return;
+    OmegaSearch S{};
+    S.method = method;
+    S.k = k;
+    S.max_it = max_it;
+    S.tol = tol;
+    S.wmin = wmin;
+    S.wmax = wmax;
+    S.omega0 = omega0;
+    switch (method) {
+    case PBFB_OMEGA_BISECT: om_bisect_start(S, wmin, wmax, omega0); break;
+    case PBFB_OMEGA_SECANT: om_secant_start(S, omega0, omega0 + 0.125); break;
     case PBFB_OMEGA_BSEC:
-        if (k == 1) return omega_bisect(o, f, o.omega_min, o.omega_max, omega0, ev, fb);
-        return omega_secant(o, f, omega0, omega0 + 0.125, ev, fb);
+        if (k == 1) om_bisect_start(S, wmin, wmax, omega0);
+        else om_secant_start(S, omega0, omega0 + 0.125);
+        break;
     case PBFB_OMEGA_NEWTON_BS:
         if (k == 1) {
-            const double w = omega_start_bs(o, f, ev, fb);
-            if (fb) return w;
-            return omega_newton(o, f, w, ev, fb);
+            S.blo = 2.0;
+            S.bhi = 3.0;
+            S.si = 0;
+            S.phase = OM_BS_START;
+            S.w = 2.5;
+        } else {
+            om_newton_start(S, omega0);
         }
-        return omega_newton(o, f, omega0, ev, fb);
+        break;
     case PBFB_OMEGA_BSEC_DF:
-        if (k == 1) return omega_bisect(o, f, o.omega_min, o.omega_max, omega0, ev, fb);
-        {
-            // the secant through (0, 1) and (w0, f_d(w0)): f_d(0) = 1 in a Picard step
-            const double w0 = 0.125;
-            double f0 = 0.0, d = 0.0;
-            ++ev;
-            if (!f(w0, f0, d) || f0 == 1.0 || !std::isfinite(f0)) {
-                fb = true;
-                return 1.0;
-            }
-            return clampw(w0 / (1.0 - f0), o);
+        if (k == 1) {
+            om_bisect_start(S, wmin, wmax, omega0);
+        } else {
+            S.phase = OM_DF;
+            S.w = 0.125;
         }
-    default: return omega_newton(o, f, omega0, ev, fb);
+        break;
+    default: om_newton_start(S, omega0); break;
     }
+    *S_ = S;
 }
 
-// omega search and update after the Newton linear solve; true when converged
-static bool newton_post(NewtonRun &r, hipStream_t s)
+// f_d and f_d' at S.w from the dot products (eq. fd=0 and its derivative,
+// r' = -[rJ; 0; 0], r'' = -[rH; 0; 0]), then the next state
+__global__ void k_omega_step(OmegaSearch *__restrict__ S_)
+{
+    if (threadIdx.x != 0) return;
+    OmegaSearch S = *S_;
+    if (S.done) return;
+    const double w = S.w;
+    const double a = S.v[0] - S.v[1];     // (p + r').r
+    const double beta = S.pp - S.v[2];    // (p + r').p
+    const bool ok = beta != 0.0;
+    double fd = 0.0, dfd = 0.0;
+    if (ok) {
+        fd = -a / beta - w;
+        dfd = -(-S.v[2] + S.v[3] - S.v[4]) / beta + a * (-S.v[5]) / (beta * beta) - 1.0;
+    }
+    ++S.ev;
+    if (!ok) {
+        om_finish(S, 1.0, true);
+        *S_ = S;
+        return;
+    }
+    switch (S.phase) {
+    case OM_NEWTON:
+        if (fabs(fd) < S.tol) om_finish(S, w, false);
+        else if (dfd == 0.0 || !isfinite(dfd)) om_finish(S, 1.0, true);
+        else {
+            const double wn = om_clamp(S, w - fd / dfd);
+            if (S.ev >= S.max_it) om_finish(S, wn, false);
+            else S.w = wn;
+        }
+        break;
+    case OM_SEC_A:
+        if (fabs(fd) < S.tol) {
+            om_finish(S, w, false);
+        } else {
+            S.f0 = fd;
+            S.phase = OM_SEC_B;
+            S.w = S.w1;
+        }
+        break;
+    case OM_SEC_B:
+        S.f1 = fd;
+        if (fabs(S.f1) >= S.tol && S.ev < S.max_it) {
+            const double slope = S.f0 - S.f1;
+            if (slope == 0.0 || !isfinite(slope)) {
+                om_finish(S, 1.0, true);
+            } else {
+                const double w2 = om_clamp(S, S.w0 - (S.w0 - S.w1) * S.f0 / slope);
+                S.w0 = S.w1;
+                S.f0 = S.f1;
+                S.w1 = w2;
+                S.w = w2;
+            }
+        } else {
+            om_finish(S, S.w1, false);
+        }
+        break;
+    case OM_BIS_LO:
+        if (fabs(fd) < S.tol) {
+            om_finish(S, S.lo, false);
+        } else {
+            S.flo = fd;
+            S.phase = OM_BIS_HI;
+            S.w = S.hi;
+        }
+        break;
+    case OM_BIS_HI:
+        if (fabs(fd) < S.tol) om_finish(S, S.hi, false);
+        else if ((S.flo > 0.0) == (fd > 0.0)) om_newton_start(S, S.wstart); // no sign change over the interval
+        else if (S.ev >= S.max_it) om_finish(S, 0.5 * (S.lo + S.hi), false);
+        else {
+            S.phase = OM_BIS_MID;
+            S.w = 0.5 * (S.lo + S.hi);
+        }
+        break;
+    case OM_BIS_MID:
+        if (fabs(fd) < S.tol) {
+            om_finish(S, w, false);
+        } else {
+            if ((fd > 0.0) == (S.flo > 0.0)) {
+                S.lo = w;
+                S.flo = fd;
+            } else {
+                S.hi = w;
+            }
+            if (S.ev < S.max_it) S.w = 0.5 * (S.lo + S.hi);
+            else om_finish(S, w, false);
+        }
+        break;
+    case OM_BS_START:
+        S.bw[S.si] = w;
+        S.bf[S.si] = fd;
+        if (fd > 0.0) S.blo = w;
+        else S.bhi = w;
+        ++S.si;
+        if (S.si < 3) {
+            S.w = 0.5 * (S.blo + S.bhi);
+        } else {
+            S.w0 = S.bw[1];
+            S.f0 = S.bf[1];
+            S.w1 = S.bw[2];
+            S.f1 = S.bf[2];
+            om_bs_loop(S);
+        }
+        break;
+    case OM_BS_SEC:
+        S.f1 = fd;
+        om_bs_loop(S);
+        break;
+    case OM_DF:
+        if (fd == 1.0 || !isfinite(fd)) om_finish(S, 1.0, true);
+        else om_finish(S, om_clamp(S, 0.125 / (1.0 - fd)), false);
+        break;
+    default: om_finish(S, 1.0, true); break;
+    }
+    *S_ = S;
+}
+
+__global__ void k_omega_read(const OmegaSearch *__restrict__ S, double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    out[0] = S->done;
+    out[1] = S->result;
+    out[2] = S->ev;
+    out[3] = S->fb;
+}
+
+__global__ void k_sub_fem_skip(int64_t nn, const double *__restrict__ c, const double *__restrict__ f,
+                               double *__restrict__ out, const int *__restrict__ skip)
+{
+    if (*skip) return;
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < nn) out[i] = c[i] - f[i];
+}
+
+static OmegaSearch *om_state(NewtonRun &r) { return static_cast<OmegaSearch *>(r.om_dev); }
+
+// one evaluation round of a search: f_d terms at S.w, the dot products, the step
+static void omega_round(NewtonRun &r, hipStream_t s)
 {
     Problem &p = *r.p;
     const int64_t n = p.n(), nn = p.nn;
+    OmegaSearch *S = om_state(r);
+    const int *skip = &S->done;
+    fem_omega_terms_dev(p, r.sch, r.phi, r.D, &S->w, skip, r.rN, r.rJ, r.rH, s);
+    hipLaunchKernelGGL(k_sub_fem_skip, dim3(nbk(nn, 256)), dim3(256), 0, s, nn, r.c, r.rN, r.rv, skip);
+    const double *pa = r.pv, *pb = r.rv;
+    dots_dev(p, 1, &pa, &pb, n, S->v, skip, s);
+    const double *A5[5] = {r.rJ, r.rJ, r.rJ, r.rv, r.pv};
+    const double *B5[5] = {r.rv, r.pv, r.rJ, r.rH, r.rH};
+    dots_dev(p, 5, A5, B5, nn, S->v + 1, skip, s);
+    hipLaunchKernelGGL(k_omega_step, dim3(1), dim3(64), 0, s, S);
+}
+
+// the searches of all runs in `srch` together: rounds for every run whose
+// search is not known to be done, the done flags read back every few rounds
+static void omega_search_all(std::vector<NewtonRun *> &srch, hipStream_t s)
+{
+    constexpr int ROUNDS = 2; // evaluation rounds between two host checks
+    std::vector<NewtonRun *> act = srch;
+    while (!act.empty()) {
+        for (int q = 0; q < ROUNDS; ++q)
+            for (NewtonRun *r : act) omega_round(*r, s);
+        for (NewtonRun *r : act) {
+            double *h = scratch<double>(*r->p, SCR_OMEGA, sizeof(OmegaSearch) / 8 + 8) + sizeof(OmegaSearch) / 8 + 2;
+            hipLaunchKernelGGL(k_omega_read, dim3(1), dim3(64), 0, s, om_state(*r), h);
+            PB_HIP(hipMemcpyAsync(r->om_host, h, sizeof(r->om_host), hipMemcpyDeviceToHost, s));
+        }
+        PB_HIP(hipStreamSynchronize(s));
+        std::vector<NewtonRun *> next;
+        for (NewtonRun *r : act) {
+            if (r->om_host[0] != 0.0) {
+                r->omega = r->om_host[1];
+                r->searching = false;
+            } else {
+                next.push_back(r);
+            }
+        }
+        act.swap(next);
+    }
+}
+
+// omega of this step: fixed, frozen, reused (Picard) or searched.  A search
+// is set up here (p = -A Delta, p.p into the device state) and run later
+// together with the other instances' (omega_search_all).
+static void newton_post_begin(NewtonRun &r, hipStream_t s)
+{
+    Problem &p = *r.p;
+    const int64_t n = p.n();
     const pbfb_solve_opts &o = r.o;
-    const int idx = std::min(r.k - 1, 63);
-    double omega;
-    int oit = 0;
-    bool searched = false; // r.pv = -A Delta was formed
+    r.searching = r.searched = false;
     if (!o.omega_auto) {
-        omega = o.omega_fixed;
+        r.omega = o.omega_fixed;
     } else if (r.frozen) {
-        omega = r.omega_last;
+        r.omega = r.omega_last;
     } else if (o.nonlinear_method == PBFB_PICARD && o.r_e > 0 && r.k >= 3 && r.e_km2 >= o.r_e * r.e_km1) {
-        omega = r.omega_last; // e_{k-2} / e_{k-1} >= R_e: converging fast enough, reuse
+        r.omega = r.omega_last; // e_{k-2} / e_{k-1} >= R_e: converging fast enough, reuse
     } else {
         const double omega0 = r.sch == PBFB_T3 ? o.omega0_first : o.omega0_next;
         // p = -A Delta
         coupled_apply_linear(p, r.D, r.pv, s);
         r.res->applies += 1;
-        searched = true;
+        r.searched = r.searching = true;
         vec_axpby(n, -1.0, r.pv, 0.0, r.pv, s);
-        const double pp = dot(p, r.pv, r.pv, n, s);
         PB_HIP(hipMemcpyAsync(r.rv, r.c, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        // f_d(omega) and f_d'(omega) (eq. fd=0 and its derivative); false when beta = 0
-        auto fd_at = [&](double w, double &fd, double &dfd) {
-            fem_omega_terms(p, r.sch, r.phi, r.D, w, r.rN, r.rJ, r.rH, s);
-            hipLaunchKernelGGL(k_sub_fem, dim3(nbk(nn, 256)), dim3(256), 0, s, nn, r.c, r.rN, r.rv);
-            const double pr = dot(p, r.pv, r.rv, n, s);
-            const double *A5[5] = {r.rJ, r.rJ, r.rJ, r.rv, r.pv};
-            const double *B5[5] = {r.rv, r.pv, r.rJ, r.rH, r.rH};
-            double v5[5];
-            dots(p, 5, A5, B5, nn, v5, s);
-            // r' = -[rJ; 0; 0], r'' = -[rH; 0; 0]
-            const double a = pr - v5[0];    // (p + r').r
-            const double beta = pp - v5[1]; // (p + r').p
-            if (beta == 0.0) return false;
-            fd = -a / beta - w;
-            dfd = -(-v5[1] + v5[2] - v5[3]) / beta + a * (-v5[4]) / (beta * beta) - 1.0;
-            return true;
-        };
-        int evals = 0;
-        bool fallback = false;
-        omega = omega_root(o, r.k, omega0, fd_at, evals, fallback);
+        r.om_dev = scratch<double>(p, SCR_OMEGA, sizeof(OmegaSearch) / 8 + 8);
+        OmegaSearch *S = om_state(r);
+        hipLaunchKernelGGL(k_omega_init, dim3(1), dim3(64), 0, s, S, o.omega_method, r.k, o.max_omega_it, o.tol_omega,
+                           o.omega_min, o.omega_max, omega0);
+        const double *pa = r.pv;
+        dots_dev(p, 1, &pa, &pa, n, &S->pp, nullptr, s);
+    }
+}
+
+// update and stop test after the search (or without one); true when converged
+static bool newton_post_end(NewtonRun &r, hipStream_t s)
+{
+    Problem &p = *r.p;
+    const int64_t n = p.n();
+    const pbfb_solve_opts &o = r.o;
+    const int idx = std::min(r.k - 1, 63);
+    const double omega = r.omega;
+    int oit = 0;
+    if (r.searched) {
+        const int evals = int(r.om_host[2]);
         oit = evals > 0 ? evals - 1 : 0;
         r.omega_last = omega;
     }
     vec_axpby(n, omega, r.D, 1.0, r.phinl, s);
-    if (searched) {
+    if (r.searched) {
         // A (Phi + omega Delta) = A Phi - omega p: the next c = b - A Phi without an apply
         vec_axpby(n, omega, r.pv, 1.0, r.c, s);
         r.c_ready = true;
@@ -483,11 +627,17 @@ static bool advance_impl(NewtonRun &r, hipStream_t s)
             finish(r, s);
             return false;
         }
-        if (newton_post(r, s)) {
+        newton_post_begin(r, s);
+        r.phase = PH_POST; // the search (if any) runs with the other instances'
+        return false;
+    }
+    if (r.phase == PH_POST) {
+        if (newton_post_end(r, s)) {
             finish(r, s);
             return false;
         }
         ++r.k;
+        r.phase = PH_NEWTON;
         if (!newton_pre(r, s)) {
             finish(r, s);
             return false;
@@ -510,13 +660,87 @@ bool advance(NewtonRun &r, hipStream_t s)
     }
 }
 
+// Device setup (geometry, load, operators) of the runs that have not
+// started, on up to N_ASM_WS host threads with a stream of the context each:
+// the assembly kernels of a small instance leave most of the GPU idle, and
+// several instances at once fill it.  Each run's state machine then finds its
+// operators ready.  An error ends that run with its code.
+static void parallel_setup(std::vector<NewtonRun *> &fresh, hipStream_t s)
+{
+    Ctx *C = fresh[0]->p->ctx;
+    for (NewtonRun *r : fresh)
+        if (r->p->ctx != C) return; // the streams and workspaces are the context's
+    const int nt = int(std::min<size_t>(N_ASM_WS, fresh.size()));
+    PB_HIP(hipStreamSynchronize(s)); // work the caller enqueued before the solve is complete
+    {
+        std::lock_guard<std::mutex> lk(C->setup_mu);
+        for (int t = 0; t < nt; ++t)
+            if (!C->setup_stream[t]) PB_HIP(hipStreamCreateWithFlags(&C->setup_stream[t], hipStreamNonBlocking));
+    }
+    std::atomic<size_t> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            const bool dev_ok = hipSetDevice(C->device) == hipSuccess;
+            for (size_t i; (i = next++) < fresh.size();) {
+                NewtonRun &r = *fresh[i];
+                try {
+                    PB_CHECK(dev_ok, PBFB_EDEVICE, "hipSetDevice failed in the setup thread");
+                    ensure_all(*r.p, C->setup_stream[t]);
+                    PB_HIP(hipStreamSynchronize(C->setup_stream[t]));
+                } catch (const Error &e) {
+                    r.status = e.code;
+                    r.message = e.msg;
+                    r.res->status = e.code;
+                    r.phase = PH_DONE;
+                }
+            }
+        });
+    for (std::thread &x : th) x.join();
+}
+
+void advance_all(std::vector<NewtonRun *> &runs, std::vector<GmresJob *> &jobs, std::vector<NewtonRun *> *finished,
+                 hipStream_t s)
+{
+    std::vector<NewtonRun *> fresh;
+    for (NewtonRun *r : runs)
+        if (r->phase == PH_START) fresh.push_back(r);
+    if (fresh.size() > 1) parallel_setup(fresh, s);
+    for (NewtonRun *r : fresh)
+        if (r->phase == PH_DONE && finished) finished->push_back(r);
+    auto step = [&](NewtonRun *r) {
+        if (advance(*r, s)) jobs.push_back(&r->job);
+        else if (r->phase == PH_DONE && finished) finished->push_back(r);
+    };
+    for (NewtonRun *r : runs)
+        if (r->phase != PH_DONE && r->phase != PH_POST) step(r);
+    // relaxation searches of every instance between two linear solves, together
+    std::vector<NewtonRun *> srch;
+    for (NewtonRun *r : runs)
+        if (r->phase == PH_POST && r->searching) srch.push_back(r);
+    if (!srch.empty()) {
+        try {
+            omega_search_all(srch, s);
+        } catch (const Error &e) {
+            for (NewtonRun *r : srch) {
+                r->status = e.code;
+                r->message = e.msg;
+                r->res->status = e.code;
+                r->phase = PH_DONE;
+                if (finished) finished->push_back(r);
+            }
+        }
+    }
+    for (NewtonRun *r : runs)
+        if (r->phase == PH_POST) step(r);
+}
+
 void run_newton(std::vector<NewtonRun *> &runs, hipStream_t s)
 {
     std::vector<GmresJob *> jobs;
     for (;;) {
         jobs.clear();
-        for (NewtonRun *r : runs)
-            if (r->phase != PH_DONE && advance(*r, s)) jobs.push_back(&r->job);
+        advance_all(runs, jobs, nullptr, s);
         if (jobs.empty()) break;
         try {
             batched_gmres(jobs, s);
