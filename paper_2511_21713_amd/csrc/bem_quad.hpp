@@ -20,6 +20,7 @@ struct QRule6 {
     double b[6][3];
     double w[6];
     double oA[2], oD[2];
+    double wb[6][3]; // w_q b_q[a]
 };
 inline QRule6 q6arg()
 {
@@ -28,6 +29,7 @@ inline QRule6 q6arg()
     for (int q = 0; q < 6; ++q) {
         for (int k = 0; k < 3; ++k) r.b[q][k] = R.tri_bary[q][k];
         r.w[q] = R.tri_w[q];
+        for (int k = 0; k < 3; ++k) r.wb[q][k] = R.tri_w[q] * R.tri_bary[q][k];
     }
     for (int o = 0; o < 2; ++o) {
         // the orbit structure the regular kernel relies on
@@ -55,7 +57,7 @@ inline QRule6F q6farg()
         r.oD[o] = float(R.oD[o]);
     }
     for (int q = 0; q < 6; ++q)
-        for (int a = 0; a < 3; ++a) r.wb[q][a] = float(R.w[q] * R.b[q][a]);
+        for (int a = 0; a < 3; ++a) r.wb[q][a] = float(R.wb[q][a]);
     return r;
 }
 
@@ -69,5 +71,33 @@ __device__ inline double rsqrt_pos(double x)
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 __device__ inline float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// e^{-a} for finite a >= 0 (the FP64 Yukawa kernel): -a = k ln 2 + f with
+// |f| <= ln(2)/2 (Cody-Waite reduction: ln 2 split into a head of 21
+// significant bits, so that k times it is exact, and a tail), e^f by its
+// Taylor polynomial of degree 13 in Horner form (truncation below 5e-18
+// relative), scaled by 2^k.  a is clamped at 800, where e^{-a} has
+// underflowed to 0, which keeps k within int range.
+__device__ inline double exp_neg(double a)
+{
+    a = fmin(a, 800.0);
+    const double k = rint(a * -1.4426950408889634);
+    const double f = fma(-k, 4.7493250390316726e-07, fma(-k, 0.6931467056274414, -a));
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, f, 1.0 / 479001600.0);
+    p = fma(p, f, 1.0 / 39916800.0);
+    p = fma(p, f, 1.0 / 3628800.0);
+    p = fma(p, f, 1.0 / 362880.0);
+    p = fma(p, f, 1.0 / 40320.0);
+    p = fma(p, f, 1.0 / 5040.0);
+    p = fma(p, f, 1.0 / 720.0);
+    p = fma(p, f, 1.0 / 120.0);
+    p = fma(p, f, 1.0 / 24.0);
+    p = fma(p, f, 1.0 / 6.0);
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    return ldexp(p, int(k));
+}
 
 } // namespace pbfb

@@ -112,8 +112,9 @@ template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int6
 }
 
 // Fold of a tile's pair blocks onto the blocks' vertices through the shared
-// tile (one operator; FP32 evaluation folds V then K one at a time in half
-// the LDS of the paired fold below, so more workgroups fit per CU): first
+// tile, one operator at a time (FP64 evaluation: V, K and the mirrored K in
+// turn through one FP64 plane, which keeps the LDS of a workgroup small
+// enough for four per CU): first
 // the source corners of each source vertex (in place, row by row), then the
 // target corners of each target vertex, added into U at row vA[ia], column
 // off + vB[jb] with factor sc.  A thread owns one source vertex jb and a
@@ -188,83 +189,86 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
     __syncthreads();
 }
 
-// Fold of a tile's pair blocks (FP64 evaluation), V and K together: each
-// tile entry holds both, so one address and one 16-byte LDS access serve the
-// two operators; then V goes to column nv + vB[jb] with factor sV and K to
-// column vB[jb] with factor sK of row vA[ia].  Otherwise as fold_tile_one.
-typedef double dpair __attribute__((ext_vector_type(2))); // (V, K)
-typedef float fpair __attribute__((ext_vector_type(2)));  // (V, K) of an FP32 tile
-
-template <int TA, int TB, int MS, typename MT, typename PT, typename XT>
-__device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
-                                      const int (*sSb)[MS], PT (*acc)[TB * 3 + 1], const XT *Vl, const XT *Kl,
-                                      const int *vA, const int *vB, MT *__restrict__ U, int64_t ld, int64_t nv,
-                                      double sV, double sK)
+// Fold of an FP32 tile's pair blocks, V and K in two FP32 planes of the
+// shared tile read at the same index (TOT = false: V to column off + vB[jb]
+// with factor s0, K to column vB[jb] with factor s1 of row vA[ia] of U), or
+// the mirrored K of a square tile in one plane (TOT = true: to column vB[jb]
+// of row vA[ia] of U = T with factor s0); otherwise as fold_tile_one.
+template <int TA, int TB, int MS, bool TOT, typename MT>
+__device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
+                                     const int (*sSb)[MS], float (*acc)[TA * 3 + 1][TB * 3 + 1],
+                                     const float (*blk)[9], const int *vA, const int *vB, MT *__restrict__ U,
+                                     int64_t ld, int64_t off, double s0, double s1)
 {
-    constexpr int NT = TA * TB;
+    constexpr int NT = TA * TB, RMAX = TA * 3, CMAX = TB * 3, RC = 4, NPL = TOT ? 1 : 2;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
     const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
     int cb[MS];
 #pragma unroll
     for (int l = 0; l < MS; ++l) {
         const int c = sSb[jb][l];
-        cb[l] = c < 0 ? TB * 3 : c;
+        cb[l] = c < 0 ? CMAX : c;
     }
-    const dpair zero = {0.0, 0.0};
-    const PT pzero = {0, 0};
-    for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = pzero;
-    if (tid < TA * 3) acc[tid][TB * 3] = pzero;
+    for (int k = tid; k < CMAX + 1; k += NT)
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int pl = 0; pl < NPL; ++pl) acc[pl][RMAX][k] = 0.0f;
+    if (tid < RMAX)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) acc[3 * tl + a][3 * sl + b] = PT{Vl[3 * a + b], Kl[3 * a + b]};
+        for (int pl = 0; pl < NPL; ++pl) acc[pl][tid][CMAX] = 0.0f;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[pl][3 * tl + a][3 * sl + b] = blk[pl][3 * a + b];
     __syncthreads();
-    // source corners: rows r0, r0 + rstep, ... of each thread, in rounds of
-    // RC rows held in registers between the reads and the in-place writes
-    // (one round unless the source block has more than NT / (3 RC) vertices)
-    constexpr int RMAX = TA * 3, RC = 4;
     const int rows_pt = (RMAX + rstep - 1) / rstep; // uniform
     for (int rb = 0; rb < rows_pt; rb += RC) {
-        dpair colsum[RC];
+        double colsum[RC][NPL];
         int nrow = 0;
         if (colthread) {
 #pragma unroll
             for (int r = 0; r < RC; ++r) {
                 const int sa = r0 + (rb + r) * rstep;
-                dpair t = zero;
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl) colsum[r][pl] = 0.0;
                 if (sa < RMAX) {
-                    dpair v[MS];
 #pragma unroll
-                    for (int l = 0; l < MS; ++l) v[l] = __builtin_convertvector(acc[sa][cb[l]], dpair);
+                    for (int l = 0; l < MS; ++l)
 #pragma unroll
-                    for (int l = 0; l < MS; ++l) t += v[l];
+                        for (int pl = 0; pl < NPL; ++pl) colsum[r][pl] += double(acc[pl][sa][cb[l]]);
                     nrow = r + 1;
                 }
-                colsum[r] = t;
             }
         }
         __syncthreads();
         if (colthread)
 #pragma unroll
             for (int r = 0; r < RC; ++r)
-                if (r < nrow) acc[r0 + (rb + r) * rstep][jb] = __builtin_convertvector(colsum[r], PT);
+                if (r < nrow)
+#pragma unroll
+                    for (int pl = 0; pl < NPL; ++pl) acc[pl][r0 + (rb + r) * rstep][jb] = float(colsum[r][pl]);
         __syncthreads();
     }
     if (colthread) {
         const int64_t col = vB[jb];
         for (int ia = r0; ia < nA; ia += rstep) {
-            dpair v[MS];
+            double t[NPL];
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) t[pl] = 0.0;
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
-                const int ra = sSa[ia][k];
-                v[k] = __builtin_convertvector(acc[ra < 0 ? TA * 3 : ra][jb], dpair);
-            }
-            dpair t = zero;
+                const int ra = sSa[ia][k] < 0 ? RMAX : sSa[ia][k];
 #pragma unroll
-            for (int k = 0; k < MS; ++k) t += v[k];
+                for (int pl = 0; pl < NPL; ++pl) t[pl] += double(acc[pl][ra][jb]);
+            }
             const int64_t row = int64_t(vA[ia]) * ld;
-            add_entry(U, row + nv + col, sV * t.x);
-            add_entry(U, row + col, sK * t.y);
+            if constexpr (TOT) {
+                add_entry(U, row + col, s0 * t[0]);
+            } else {
+                add_entry(U, row + off + col, s0 * t[0]);
+                add_entry(U, row + col, s1 * t[1]);
+            }
         }
     }
 }
@@ -288,8 +292,16 @@ __device__ inline void fold_tile_pair(int tid, int tl, int sl, int nA, int nB, c
 // added, transposed, to T (nv x nv: T[i][j] collects sK K(j, i)); V of
 // (sigma, tau) is the transpose of V of (tau, sigma).  k_bem_symm then
 // completes the operator: V' = U_V + U_V^T, K' = U_K + T^T.
+//
+// Every lane runs the quadrature: a pair that is not evaluated (padding
+// triangle, shared vertex, or the mirror of a diagonal-tile pair) has its
+// target moved 1e4 away and a zero factor, so its terms are exact zeros.
+// occupancy asked of the compiler: FP32 tiles fit in 80 VGPRs (six
+// wavefronts per SIMD by registers and LDS), FP64 tiles in 128 (four)
+constexpr int TILE_F32_WAVES = 5;
+constexpr int TILE_F64_WAVES = 4;
 template <bool YUK, typename RT, typename MT, int TA, int TB, int MS, bool SYM>
-__global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 ? TILE_F32_WAVES : TILE_F64_WAVES)))
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
                   const RT *__restrict__ nq, const double *__restrict__ cen, const double *__restrict__ m_area,
                   const int32_t *__restrict__ A_pref, const int32_t *__restrict__ A_nv,
@@ -305,8 +317,8 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
     constexpr int NT = TA * TB;
     const int64_t bA = listA[blockIdx.y], bB = listB[blockIdx.x];
     if (SYM && skip_lower && bB < bA) return; // evaluated as (bB, bA)
-    __shared__ RT sX[TA][18];
-    __shared__ RT sY[TB][18];
+    __shared__ RT sX[TA * 18]; // quadrature points, 18 values per triangle
+    __shared__ RT sY[TB * 18];
     __shared__ RT sN[TB][3];
     __shared__ RT sNa[SYM ? TA : 1][3];
     __shared__ double sCa[F32 ? TA : 1][3], sCb[F32 ? TB : 1][3];
@@ -314,22 +326,21 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ int sVa[TA][3], sVb[TB][3];
     __shared__ int sSa[TA * 3][MS], sSb[TB * 3][MS];
     __shared__ int sIa[TA * 3], sIb[TB * 3]; // operator index of each block vertex
-    // the tile of (V, K) pairs in the evaluation precision, + a zero row and a zero column
-    __shared__ std::conditional_t<F32, fpair, dpair> acc[TA * 3 + 1][TB * 3 + 1];
+    // the tile of pair blocks in the evaluation precision, + a zero row and a
+    // zero column: FP32 one plane each for V and K, then the mirrored K of a
+    // square tile in the first; FP64 one plane, one operator at a time
+    constexpr int NPL = F32 ? 2 : 1;
+    __shared__ std::conditional_t<F32, float, double> acc[NPL][TA * 3 + 1][TB * 3 + 1];
 
     const int tid = threadIdx.x;
     const int nA = A_nv[bA], nB = B_nv[bB];
     const int64_t pA = A_pref[bA], pB = B_pref[bB];
 
-    for (int k = tid; k < TA * 18; k += NT) {
-        int tl = k / 18, c = k % 18;
-        int64_t m = bA * TA + tl;
-        sX[tl][c] = m < nt ? xq[18 * m + c] : RT(0);
-    }
-    for (int k = tid; k < TB * 18; k += NT) {
-        int sl = k / 18, c = k % 18;
-        int64_t m = bB * TB + sl;
-        sY[sl][c] = m < nt ? xq[18 * m + c] : RT(0);
+    {
+        // a block's quadrature points are contiguous
+        const int64_t xa = 18 * bA * TA, xb = 18 * bB * TB, xe = 18 * nt;
+        for (int k = tid; k < TA * 18; k += NT) sX[k] = xa + k < xe ? xq[xa + k] : RT(0);
+        for (int k = tid; k < TB * 18; k += NT) sY[k] = xb + k < xe ? xq[xb + k] : RT(0);
     }
     if (tid < TB * 3) {
         int sl = tid / 3, c = tid % 3;
@@ -361,115 +372,139 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(3)
 
     // this thread's pair (target tl, source sl)
     const int tl = tid / TB, sl = tid % TB;
-    // the pair's 3x3 blocks, summed over its 36 quadrature pairs in the
-    // evaluation precision (FP32 tiles: widened once, in the fold)
-    RT Vl[9], Kl[9], Ktl[SYM ? 9 : 1];
+    bool live = sVa[tl][0] >= 0 && sVb[sl][0] >= 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Vl[k] = Kl[k] = RT(0);
-#pragma unroll
-    for (int k = 0; k < (SYM ? 9 : 1); ++k) Ktl[k] = RT(0);
-    bool touch = false;
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) touch |= (sVa[tl][a] == sVb[sl][b]);
-    if (SYM && bA == bB && sl <= tl) touch = true; // the mirror pair carries it
-    if ((sVa[tl][0] >= 0) && (sVb[sl][0] >= 0) && !touch) {
-        RT c0 = 0, c1 = 0, c2 = 0; // FP32: target frame relative to the source centroid
-        if constexpr (F32) {
-            c0 = float(sCa[tl][0] - sCb[sl][0]);
-            c1 = float(sCa[tl][1] - sCb[sl][1]);
-            c2 = float(sCa[tl][2] - sCb[sl][2]);
-        }
-        const RT n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
-        RT dm[SYM ? 6 : 1]; // (y_q - x).n_tau, the same for every target point x
-        if constexpr (SYM) {
-            const RT m0 = sNa[tl][0], m1 = sNa[tl][1], m2 = sNa[tl][2];
-            const RT xa0 = sX[tl][0] + c0, xa1 = sX[tl][1] + c1, xa2 = sX[tl][2] + c2;
 #pragma unroll
-            for (int q = 0; q < 6; ++q)
-                dm[q] = (sY[sl][3 * q] - xa0) * m0 + (sY[sl][3 * q + 1] - xa1) * m1 + (sY[sl][3 * q + 2] - xa2) * m2;
-        }
-        const RT kap = RT(kappa);
-        const RT sc = RT(sAa[tl] * sAb[sl] * INV4PI);
-        // target point p outermost: 6-term source sums, then folded into the 3x3 blocks
-        // (not unrolled: the 6 source points of one target point are the unit of ILP).
-        // The source points lie in the plane of the source triangle, so the
-        // normal distance (x - y_q).n is the same for all six: it is taken
-        // once per target point (from source point 0) and factored out of
-        // the double-layer sum.
-#pragma unroll 1
-        for (int p = 0; p < 6; ++p) {
-            const RT x0 = sX[tl][3 * p] + c0, x1 = sX[tl][3 * p + 1] + c1, x2 = sX[tl][3 * p + 2] + c2;
-            const RT dn = (x0 - sY[sl][0]) * n0 + (x1 - sY[sl][1]) * n1 + (x2 - sY[sl][2]) * n2;
-            RT gv[6], hk[6]; // single-layer kernel, double-layer kernel / (x - y).n
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const RT d0 = x0 - sY[sl][3 * q], d1 = x1 - sY[sl][3 * q + 1], d2 = x2 - sY[sl][3 * q + 2];
-                const RT r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                const RT ri = rsqrt_pos(r2);
-                const RT ri3 = ri * ri * ri;
-                if (YUK) {
-                    const RT r = r2 * ri;
-                    RT e;
-                    if constexpr (F32) e = __builtin_amdgcn_exp2f(-1.44269504088896341f * kap * r);
-                    else e = exp(-kap * r);
-                    gv[q] = e * ri;
-                    hk[q] = (RT(1) + kap * r) * e * ri3;
-                } else {
-                    gv[q] = ri;
-                    hk[q] = ri3;
-                }
-            }
-            RT oA0, oA1, oD0, oD1;
-            if constexpr (F32) {
-                oA0 = RF.oA[0], oA1 = RF.oA[1], oD0 = RF.oD[0], oD1 = RF.oD[1];
-            } else {
-                oA0 = R.oA[0], oA1 = R.oA[1], oD0 = R.oD[0], oD1 = R.oD[1];
-            }
-            const RT cv = oA0 * (gv[0] + gv[1] + gv[2]) + oA1 * (gv[3] + gv[4] + gv[5]);
-            const RT ck = oA0 * (hk[0] + hk[1] + hk[2]) + oA1 * (hk[3] + hk[4] + hk[5]);
-            const RT sv0 = cv + oD0 * gv[0] + oD1 * gv[3], sv1 = cv + oD0 * gv[1] + oD1 * gv[4],
-                     sv2 = cv + oD0 * gv[2] + oD1 * gv[5];
-            RT sk0 = ck + oD0 * hk[0] + oD1 * hk[3], sk1 = ck + oD0 * hk[1] + oD1 * hk[4],
-               sk2 = ck + oD0 * hk[2] + oD1 * hk[5];
-            sk0 *= dn;
-            sk1 *= dn;
-            sk2 *= dn;
-            RT st0 = 0, st1 = 0, st2 = 0; // K of (sigma, tau): normal distance inside the source sum
-            if constexpr (SYM) {
-                RT hm[6];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) hm[q] = hk[q] * dm[q];
-                const RT cm = oA0 * (hm[0] + hm[1] + hm[2]) + oA1 * (hm[3] + hm[4] + hm[5]);
-                st0 = cm + oD0 * hm[0] + oD1 * hm[3];
-                st1 = cm + oD0 * hm[1] + oD1 * hm[4];
-                st2 = cm + oD0 * hm[2] + oD1 * hm[5];
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                RT wb;
-                if constexpr (F32) wb = RF.wb[p][a];
-                else wb = R.w[p] * R.b[p][a];
-                const RT wa = sc * wb;
-                Vl[3 * a] += wa * sv0;
-                Vl[3 * a + 1] += wa * sv1;
-                Vl[3 * a + 2] += wa * sv2;
-                Kl[3 * a] += wa * sk0;
-                Kl[3 * a + 1] += wa * sk1;
-                Kl[3 * a + 2] += wa * sk2;
-                if constexpr (SYM) {
-                    Ktl[3 * a] += wa * st0;
-                    Ktl[3 * a + 1] += wa * st1;
-                    Ktl[3 * a + 2] += wa * st2;
-                }
-            }
-        }
+        for (int b = 0; b < 3; ++b) live = live && sVa[tl][a] != sVb[sl][b];
+    if (SYM && bA == bB && sl <= tl) live = false; // the mirror pair carries it
+    RT c0 = RT(0), c1 = RT(0), c2 = RT(0); // FP32: target frame relative to the source centroid
+    if constexpr (F32) {
+        c0 = float(sCa[tl][0] - sCb[sl][0]);
+        c1 = float(sCa[tl][1] - sCb[sl][1]);
+        c2 = float(sCa[tl][2] - sCb[sl][2]);
     }
-
-    fold_tile_pair<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc, Vl, Kl, sIa, sIb, U, ld, nv, sV, sK);
+    if (!live) c0 += RT(1.0e4);
+    const RT sc = live ? RT(sAa[tl] * sAb[sl] * INV4PI) : RT(0);
+    const RT *xt = sX + 18 * tl, *ys = sY + 18 * sl;
+    const RT n0 = sN[sl][0], n1 = sN[sl][1], n2 = sN[sl][2];
+    RT y0n = RT(0); // FP32: y_0.n (offsets from the source centroid are small)
+    if constexpr (F32) y0n = ys[0] * n0 + ys[1] * n1 + ys[2] * n2;
+    RT dm[SYM ? 6 : 1]; // (y_q - x).n_tau, the same for every target point x
     if constexpr (SYM) {
-        __syncthreads();
-        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, reinterpret_cast<RT (*)[TB * 3 + 1]>(acc), Ktl, sIa,
-                                  sIb, T, nv, 0, sK);
+        const RT m0 = sNa[tl][0], m1 = sNa[tl][1], m2 = sNa[tl][2];
+        const RT xa0 = xt[0] + c0, xa1 = xt[1] + c1, xa2 = xt[2] + c2;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            dm[q] = (ys[3 * q] - xa0) * m0 + (ys[3 * q + 1] - xa1) * m1 + (ys[3 * q + 2] - xa2) * m2;
+    }
+    RT oA0, oA1, oD0, oD1;
+    if constexpr (F32) {
+        oA0 = RF.oA[0], oA1 = RF.oA[1], oD0 = RF.oD[0], oD1 = RF.oD[1];
+    } else {
+        oA0 = R.oA[0], oA1 = R.oA[1], oD0 = R.oD[0], oD1 = R.oD[1];
+    }
+    const RT kap = RT(kappa);
+    const RT kl2 = RT(-1.44269504088896341 * kappa); // FP32: e^{-kappa r} = 2^{kl2 r}
+
+    // Target point p: the kernels at its 6 source points and their sums with
+    // the source rule's orbits.  The source points lie in the plane of the
+    // source triangle, so the normal distance (x - y_q).n is the same for all
+    // six: it is taken once per target point and factored out of the
+    // double-layer sums.  s: single layer, t: double layer / (x - y).n, u:
+    // mirrored double layer (SYM).
+    auto point = [&](int p, RT (&s)[3], RT (&t)[3], RT (&u)[3], RT &dn) {
+        const RT x0 = xt[3 * p] + c0;
+        RT x1 = xt[3 * p + 1], x2 = xt[3 * p + 2];
+        if constexpr (F32) {
+            x1 += c1;
+            x2 += c2;
+            dn = x0 * n0 + x1 * n1 + x2 * n2 - y0n;
+        } else {
+            dn = (x0 - ys[0]) * n0 + (x1 - ys[1]) * n1 + (x2 - ys[2]) * n2;
+        }
+        RT gv[6], hk[6]; // single-layer kernel, double-layer kernel / (x - y).n
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const RT d0 = x0 - ys[3 * q], d1 = x1 - ys[3 * q + 1], d2 = x2 - ys[3 * q + 2];
+            const RT r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const RT ri = rsqrt_pos(r2);
+            if constexpr (YUK) {
+                const RT r = r2 * ri;
+                RT e;
+                if constexpr (F32) e = __builtin_amdgcn_exp2f(kl2 * r);
+                else e = exp_neg(kap * r);
+                gv[q] = e * ri;
+                hk[q] = gv[q] * (ri * ri) * (RT(1) + kap * r);
+            } else {
+                gv[q] = ri;
+                hk[q] = ri * ri * ri;
+            }
+        }
+        auto orb = [&](const RT (&g)[6], RT (&o)[3]) {
+            const RT c = oA0 * (g[0] + g[1] + g[2]) + oA1 * (g[3] + g[4] + g[5]);
+            o[0] = c + oD0 * g[0] + oD1 * g[3];
+            o[1] = c + oD0 * g[1] + oD1 * g[4];
+            o[2] = c + oD0 * g[2] + oD1 * g[5];
+        };
+        orb(gv, s);
+        orb(hk, t);
+        if constexpr (SYM) {
+            RT hm[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) hm[q] = hk[q] * dm[q];
+            orb(hm, u);
+        }
+    };
+
+    // the pair's 3x3 blocks, summed over its 36 quadrature pairs; the first
+    // target point assigns them
+    RT Vl[9] = {}, Kl[9] = {}, Ktl[SYM ? 9 : 1] = {};
+    auto accumulate = [&](auto first, int p) {
+        // the source points are read from LDS at every target point rather
+        // than held in registers (a compiler-only fence): fewer registers,
+        // more wavefronts per SIMD
+        asm volatile("" ::: "memory");
+        RT s[3], t[3], u[3], dn;
+        point(p, s, t, u, dn);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            RT wa;
+            if constexpr (F32) wa = sc * RF.wb[p][a];
+            else wa = sc * R.wb[p][a];
+            const RT wk = wa * dn;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                Vl[3 * a + b] = decltype(first)::value ? wa * s[b] : fma(wa, s[b], Vl[3 * a + b]);
+                Kl[3 * a + b] = decltype(first)::value ? wk * t[b] : fma(wk, t[b], Kl[3 * a + b]);
+                if constexpr (SYM)
+                    Ktl[3 * a + b] = decltype(first)::value ? wa * u[b] : fma(wa, u[b], Ktl[3 * a + b]);
+            }
+        }
+    };
+    accumulate(std::true_type{}, 0);
+    // not unrolled: the 6 source points of one target point are the unit of ILP
+#pragma unroll 1
+    for (int p = 1; p < 6; ++p) accumulate(std::false_type{}, p);
+
+    if constexpr (F32) {
+        float blk[2][9], bmt[1][9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            blk[0][k] = Vl[k];
+            blk[1][k] = Kl[k];
+            bmt[0][k] = Ktl[SYM ? k : 0];
+        }
+        fold_tile_f32<TA, TB, MS, false>(tid, tl, sl, nA, nB, sSa, sSb, acc, blk, sIa, sIb, U, ld, nv, sV, sK);
+        if constexpr (SYM) {
+            __syncthreads();
+            fold_tile_f32<TA, TB, MS, true>(tid, tl, sl, nA, nB, sSa, sSb, acc, bmt, sIa, sIb, T, nv, 0, sK, 0.0);
+        }
+    } else {
+        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Vl, sIa, sIb, U, ld, nv, sV);
+        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Kl, sIa, sIb, U, ld, 0, sK);
+        if constexpr (SYM)
+            fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Ktl, sIa, sIb, T, nv, 0, sK);
     }
 }
 
@@ -813,10 +848,15 @@ __global__ void __launch_bounds__(256)
 }
 
 // Rows whose 1-ring has at most SPAI_SMALL vertices (every vertex of the
-// usual surface meshes): one wavefront per row, each lane streams whole
-// columns of the m rows and keeps the m (m + 1) / 2 Gram partial sums in
-// registers; a fixed xor-shuffle tree then sums them across the lanes.
-template <typename MT>
+// usual surface meshes): one wavefront per row, each lane streams W
+// consecutive columns at a time (one W-wide load per row; W is chosen from
+// the alignment of the V' columns) of the m rows and keeps the m (m + 1) / 2
+// Gram partial sums in registers; a fixed xor-shuffle tree then sums them
+// across the lanes.
+template <typename MT, int W> struct alignas(W * sizeof(MT)) SpaiVec {
+    MT v[W];
+};
+template <typename MT, int W>
 __global__ void __launch_bounds__(256)
     k_spai_small(int64_t nv, const MT *__restrict__ B, int64_t ld, const int32_t *__restrict__ minv,
                  const int32_t *__restrict__ ring_ptr, const int32_t *__restrict__ ring, double *__restrict__ val,
@@ -834,15 +874,29 @@ __global__ void __launch_bounds__(256)
     double g[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) g[k] = 0.0;
-    for (int64_t c = lane; c < nv; c += 64) {
-        double x[SPAI_SMALL];
+    for (int64_t c = int64_t(W) * lane; c < nv; c += 64 * W) {
+        double x[SPAI_SMALL][W];
+        if (c + W <= nv) {
 #pragma unroll
-        for (int a = 0; a < SPAI_SMALL; ++a) x[a] = a < m ? double(rows[a][c]) : 0.0;
-        int k = 0;
+            for (int a = 0; a < SPAI_SMALL; ++a) {
+                const SpaiVec<MT, W> t = *reinterpret_cast<const SpaiVec<MT, W> *>(rows[a] + c);
 #pragma unroll
-        for (int a = 0; a < SPAI_SMALL; ++a)
+                for (int w = 0; w < W; ++w) x[a][w] = a < m ? double(t.v[w]) : 0.0;
+            }
+        } else {
 #pragma unroll
-            for (int b = 0; b <= a; ++b, ++k) g[k] = fma(x[a], x[b], g[k]);
+            for (int a = 0; a < SPAI_SMALL; ++a)
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[a][w] = a < m && c + w < nv ? double(rows[a][c + w]) : 0.0;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < SPAI_SMALL; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b, ++k) g[k] = fma(x[a][w], x[b][w], g[k]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k)
@@ -1314,8 +1368,16 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         if (sym)
             hipLaunchKernelGGL(k_sym_delta<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, Bf, S.d_ptr, S.d_col,
                                S.d_val);
-        hipLaunchKernelGGL(k_spai_small<float>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv, S.ring_ptr,
-                           S.ring, S.spai, p.d_bad);
+        // the V' columns start at column nv of rows of ld (a multiple of 256) entries
+        if (nv % 4 == 0)
+            hipLaunchKernelGGL((k_spai_small<float, 4>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
+                               S.ring_ptr, S.ring, S.spai, p.d_bad);
+        else if (nv % 2 == 0)
+            hipLaunchKernelGGL((k_spai_small<float, 2>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
+                               S.ring_ptr, S.ring, S.spai, p.d_bad);
+        else
+            hipLaunchKernelGGL((k_spai_small<float, 1>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
+                               S.ring_ptr, S.ring, S.spai, p.d_bad);
         if (T.max_ring > SPAI_SMALL)
             hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, Bf, ld, S.minv, S.ring_ptr,
                                S.ring, S.spai, p.d_bad);
@@ -1325,8 +1387,12 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         if (sym)
             hipLaunchKernelGGL(k_sym_delta<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, Bd, S.d_ptr,
                                S.d_col, S.d_val);
-        hipLaunchKernelGGL(k_spai_small<double>, dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv, S.ring_ptr,
-                           S.ring, S.spai, p.d_bad);
+        if (nv % 2 == 0)
+            hipLaunchKernelGGL((k_spai_small<double, 2>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv,
+                               S.ring_ptr, S.ring, S.spai, p.d_bad);
+        else
+            hipLaunchKernelGGL((k_spai_small<double, 1>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv,
+                               S.ring_ptr, S.ring, S.spai, p.d_bad);
         if (T.max_ring > SPAI_SMALL)
             hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, Bd, ld, S.minv, S.ring_ptr,
                                S.ring, S.spai, p.d_bad);
