@@ -170,7 +170,7 @@ typedef struct {
                           *   single-layer blocks: sparse approximate inverse on each vertex 1-ring
                           *   (row i minimises || m^T V' - e_i^T ||_2);
                           * PBFB_PC_DIAG: inverse of the diagonal of J */
-    int cheb_degree;     /* 16 (1..64) */
+    int cheb_degree;     /* 24 (1..64) */
     double cheb_ratio;   /* 200 (> 1) */
     int hip_graph;       /* 1 (default): each Krylov step of a batch is captured once as a HIP graph and replayed;
                           * 0: kernels launched one by one (also the case while kernel timing is enabled or on

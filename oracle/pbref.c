@@ -1991,7 +1991,7 @@ void pbref_opts_default(pbref_opts *o)
     o->gmres_restart = 200;
     o->max_gmres = 2000;
     o->precond = PBREF_PC_CHEB_SPAI;
-    o->cheb_degree = 16;
+    o->cheb_degree = 24;
     o->cheb_ratio = 200.0;
     o->omega_method = PBREF_OMEGA_NEWTON;
     o->nonlinear_method = PBREF_NEWTON;

@@ -583,7 +583,7 @@ void pbfb_solve_opts_default(pbfb_solve_opts *o)
     o->max_gmres = 2000;
     o->krylov_fp32 = 0;
     o->precond = PBFB_PC_CHEB_SPAI;
-    o->cheb_degree = 16;
+    o->cheb_degree = 24;
     o->cheb_ratio = 200.0;
     o->hip_graph = 1;
     o->omega_method = PBFB_OMEGA_NEWTON;
