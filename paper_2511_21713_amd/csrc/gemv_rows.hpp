@@ -13,8 +13,8 @@
 // waits count vector memory only.
 //
 // This is the bandwidth-bound kernel of every coupled apply: it reads
-// n * ld * sizeof(MT) bytes of operator per interface (n * (n + ld / 2) with
-// the symmetric use below).
+// n * ld * sizeof(MT) bytes of operator per interface (about n * (n + n / 2)
+// with the symmetric use below).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -103,27 +103,76 @@ __device__ inline void gemv_lds_barrier()
 
 // Symmetric single layer.  The regular part of V' is stored bitwise
 // symmetric; the touching-pair blocks make V' differ from its transpose on
-// a sparse pattern only, kept as Delta = upper(V') - lower(V')^T.  A workgroup
-// owns GSYM = 64 rows r0.. (r0 a multiple of 64) and reads K' in full but V'
-// only up to its diagonal block:
-//   y_i = sum_j K'_ij u_j + sum_{j <= i} V'_ij l_j                  (here)
+// a sparse pattern only, kept as Delta = upper(V') - lower(V')^T.  A row
+// block of GSYM = 64 rows r0.. (r0 a multiple of 64) is two work items of
+// one launch: its K item reads the chunks entirely inside K' (full rows of
+// uniform length), its V item the remaining chunks up to the block's
+// diagonal (the few K' columns of the chunk that straddles column n and the
+// lower triangle of V'):
+//   y_i = sum_{j < kch CW} K'_ij u_j                                 (K item)
+//       + sum_{kch CW <= j' , j <= i} [K' | V']_ij' x_j'               (V item)
 //       + sum_{j > i} V'_ji l_j + sum_{j > i} Delta_ij l_j      (gemv_sym_finish)
-// For the third sum the workgroup forms the column sums
+// For the third sum the V item forms the column sums
 // P[blk][j] = sum_{r in its rows, r > j} V'_rj l_r over the V' columns it
 // reads (the eight wavefronts' partials added in LDS in a fixed tree order,
-// GSYM_G chunks of the row stream at a time), blk = r0 / 64.  Rows past n
-// contribute nothing.  Reads n + r0 + 64 entries of each row instead of 2 n;
-// the partials are 1/64 of the V' bytes read (written once, read once).
+// GSYM_G chunks of the row stream at a time), blk = r0 / 64; its row sums go
+// to P[nblk * n + row] and the finish adds them.  Rows past n contribute
+// nothing.  Together the items read n + r0 + 64 entries of each row instead
+// of 2 n; the partials are 1/64 of the V' bytes read (written once, read
+// once).  Splitting the row block lets the launch order the items for the
+// memory system (gemv_item): the uniform K items and the triangle's V items
+// of decreasing length overlap instead of every workgroup streaming both.
 constexpr int GSYM_G = 4; // chunks per LDS exchange (64 KB of partials for FP32, 32 KB for FP64)
 // The partials are FP64 for both storage precisions: with FP32 partials the
 // apply is linear only to FP32 rounding of the partial sums, which left
 // strongly charged instances short of the Newton tolerance in mixed mode.
 template <typename MT> using sym_part_t = double;
 
+// K item: row sums over the chunks entirely inside K', written to y
 template <typename MT>
-__device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
-                                     const int32_t *__restrict__ oidx, double *__restrict__ P, int64_t n,
-                                     int64_t ld, int64_t r0, int tid)
+__device__ inline void gemv_rows_symK(const MT *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
+                                      const int32_t *__restrict__ oidx, int64_t n, int64_t ld, int64_t r0, int tid)
+{
+    constexpr int RW = GEMV_RW;
+    using C = GemvChunk<MT>;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t rw = r0 + RW * wv; // this wavefront's first row
+    gptr<typename GemvLoad<MT>::T> rows[RW];
+    double acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        acc[r] = 0.0;
+        rows[r] = (gptr<typename GemvLoad<MT>::T>)(B + (rw + r < n ? rw + r : n - 1) * ld);
+    }
+    const gptr<dvec2> xg = (gptr<dvec2>)(x);
+    const int64_t kch = n / C::CW; // chunks entirely in K'
+    for (int64_t c = 0; c < kch; ++c) {
+        C ch;
+        ch.load(rows, xg, c, lane);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+#pragma unroll
+            for (int e = 0; e < C::EL; ++e) acc[r] = fma(ch.bv(r, e), ch.xv(e), acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+    if (lane < RW && rw + lane < n) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < RW; ++r)
+            if (lane == r) v = acc[r];
+        y[oidx[rw + lane]] = v;
+    }
+}
+
+// V item: row sums of the entries j <= row from chunk kch on, column
+// partials of j < row; P holds nblk * n partials, then the n row sums
+template <typename MT>
+__device__ inline void gemv_rows_symV(const MT *__restrict__ B, const double *__restrict__ x,
+                                      double *__restrict__ P, int64_t n, int64_t ld, int64_t r0, int tid)
 {
     constexpr int RW = GEMV_RW, WV = GEMV_WAVES, G = GSYM_G;
     static_assert(WV == 8, "the partials are added in an eight-term tree");
@@ -133,7 +182,7 @@ __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__r
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t rw = r0 + RW * wv; // this wavefront's first row
-    const int64_t blk = r0 / GSYM;
+    const int64_t blk = r0 / GSYM, nblk = (n + GSYM - 1) / GSYM;
     gptr<typename GemvLoad<MT>::T> rows[RW];
     double acc[RW], lam[RW];
 #pragma unroll
@@ -145,19 +194,8 @@ __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__r
     }
     const gptr<dvec2> xg = (gptr<dvec2>)(x);
     const int64_t cend = n + r0 + GSYM;                          // columns [0, cend) are used
-    const int64_t kch = n / CW;                                  // chunks entirely in K'
+    const int64_t kch = n / CW;                                  // chunks of the K item
     const int64_t nch = std::min((cend + CW - 1) / CW, ld / CW); // chunks read (ld: multiple of 256)
-    // K' only: row sums
-    for (int64_t c = 0; c < kch; ++c) {
-        C ch;
-        ch.load(rows, xg, c, lane);
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-#pragma unroll
-            for (int e = 0; e < EL; ++e) acc[r] = fma(ch.bv(r, e), ch.xv(e), acc[r]);
-        }
-    }
-    // chunks that reach V': row sums of the entries j <= row, column partials of j < row
     for (int64_t g0 = kch; g0 < nch; g0 += G) {
         // every column of the group is a V' column left of every row of the workgroup
         const bool clean = g0 * CW >= n && (g0 + G) * CW <= n + r0;
@@ -215,14 +253,66 @@ __device__ inline void gemv_rows_sym(const MT *__restrict__ B, const double *__r
 #pragma unroll
         for (int r = 1; r < RW; ++r)
             if (lane == r) v = acc[r];
-        y[oidx[rw + lane]] = v;
+        P[nblk * n + rw + lane] = v;
     }
 }
 
-// y_i += sum over blocks blk >= i / 64 of P[blk][i] + sum_j Delta_ij l_j.  A
-// workgroup of 256 threads takes GFIN_ROWS rows i0..: thread (ty, tx) adds
-// the blocks ty, ty + GFIN_NY, ... for row i0 + tx, and the GFIN_NY partial
-// sums are then added in ty order (fixed, so the result is reproducible).
+// Order of the work items of a launch over two surfaces: surface s has
+// nk_s K items (its row blocks; full-row items when it is not used
+// symmetrically) and nv_s V items (nb or 0).  The h0 / h1 heaviest V items
+// (last row blocks first) come first, then every K item, then the remaining
+// V items, heaviest first; inside each stretch the two surfaces alternate.
+// Measured on the 80k-triangle operators: FP64 storage is fastest with a
+// quarter of the V items first (h = nb / 4), FP32 storage with every K item
+// first (h = 0).
+struct GemvItem {
+    int s;     // surface
+    bool k;    // K item (else V item)
+    int64_t b; // row block
+};
+__device__ inline void gemv_alternate(int64_t k, int64_t c0, int64_t c1, int &s, int64_t &i)
+{
+    const int64_t m = c0 < c1 ? c0 : c1;
+    if (k < 2 * m) {
+        s = int(k & 1);
+        i = k >> 1;
+    } else {
+        s = c0 > c1 ? 0 : 1;
+        i = m + (k - 2 * m);
+    }
+}
+__device__ inline GemvItem gemv_item(int64_t bi, int64_t nk0, int64_t nk1, int64_t nv0, int64_t nv1, int64_t h0,
+                                     int64_t h1)
+{
+    GemvItem it;
+    int64_t i;
+    if (bi < h0 + h1) {
+        gemv_alternate(bi, h0, h1, it.s, i);
+        it.k = false;
+        it.b = (it.s ? nv1 : nv0) - 1 - i;
+        return it;
+    }
+    bi -= h0 + h1;
+    if (bi < nk0 + nk1) {
+        gemv_alternate(bi, nk0, nk1, it.s, i);
+        it.k = true;
+        it.b = i;
+        return it;
+    }
+    bi -= nk0 + nk1;
+    gemv_alternate(bi, nv0 - h0, nv1 - h1, it.s, i);
+    it.k = false;
+    it.b = (it.s ? nv1 - h1 : nv0 - h0) - 1 - i;
+    return it;
+}
+// V items dispatched before the K items (see gemv_item), of nv
+inline int64_t gemv_heavy(bool f32, int64_t nv) { return f32 ? 0 : (nv + 3) / 4; }
+
+// y_i += (V item's row sum) + sum over blocks blk >= i / 64 of P[blk][i] +
+// sum_j Delta_ij l_j.  A workgroup of 256 threads takes GFIN_ROWS rows
+// i0..: thread (ty, tx) adds the blocks ty, ty + GFIN_NY, ... for row
+// i0 + tx, and the GFIN_NY partial sums are then added in ty order (fixed,
+// so the result is reproducible).
 constexpr int GFIN_ROWS = 32, GFIN_NY = 256 / GFIN_ROWS;
 template <typename PT>
 __device__ inline void gemv_sym_finish(int64_t n, const PT *__restrict__ P, const int32_t *__restrict__ dptr,
@@ -242,9 +332,9 @@ __device__ inline void gemv_sym_finish(int64_t n, const PT *__restrict__ P, cons
     red[ty][tx] = s;
     __syncthreads();
     if (ty == 0 && i < n) {
-        double t = red[0][tx];
+        double t = double(P[nblk * n + i]);
 #pragma unroll
-        for (int k = 1; k < GFIN_NY; ++k) t += red[k][tx];
+        for (int k = 0; k < GFIN_NY; ++k) t += red[k][tx];
         for (int32_t e = dptr[i]; e < dptr[i + 1]; ++e) t = fma(dval[e], x[n + dcol[e]], t);
         y[oidx[i]] += t;
     }

@@ -234,17 +234,19 @@ __global__ void __launch_bounds__(GEMV_THREADS, gemv_occupancy<MT>()) k_bgemv(co
     const GDesc &d = D[it.inst];
     if (d.mf || d.f32 != (sizeof(MT) == 4)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t n = it.a == 0 ? d.nm : d.ns;
-    const int64_t ld = it.a == 0 ? d.ldm : d.lds;
-    const double *x = it.a == 0 ? d.xm : d.xs;
-    double *y = d.w + d.nn + (it.a == 0 ? 0 : d.nm);
-    const MT *B = static_cast<const MT *>(it.a == 0 ? d.Bm : d.Bs);
-    if (d.symm[it.a]) {
-        gemv_rows_sym<MT>(B, x, y, it.a == 0 ? d.mvm : d.mvs, static_cast<sym_part_t<MT> *>(d.symP[it.a]), n, ld,
-                          it.b, threadIdx.x);
-    } else {
+    const int a = it.a & 1; // surface; it.a & 2: K item of the symmetric use
+    const int64_t n = a == 0 ? d.nm : d.ns;
+    const int64_t ld = a == 0 ? d.ldm : d.lds;
+    const double *x = a == 0 ? d.xm : d.xs;
+    double *y = d.w + d.nn + (a == 0 ? 0 : d.nm);
+    const MT *B = static_cast<const MT *>(a == 0 ? d.Bm : d.Bs);
+    if (!d.symm[a]) {
         const int64_t r0 = it.b + wv * GEMV_RW;
-        if (r0 < n) gemv_rows<MT>(B, x, y, it.a == 0 ? d.mvm : d.mvs, n, ld, r0, lane);
+        if (r0 < n) gemv_rows<MT>(B, x, y, a == 0 ? d.mvm : d.mvs, n, ld, r0, lane);
+    } else if (it.a & 2) {
+        gemv_rows_symK<MT>(B, x, y, a == 0 ? d.mvm : d.mvs, n, ld, it.b, threadIdx.x);
+    } else {
+        gemv_rows_symV<MT>(B, x, static_cast<sym_part_t<MT> *>(d.symP[a]), n, ld, it.b, threadIdx.x);
     }
 }
 
@@ -621,6 +623,9 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
     std::vector<GDesc> desc(nb);
     std::vector<GState> st(nb);
     std::vector<WItem> wl_vec, wl_gemv, wl_spmv, wl_pack, wl_dot, wl_fin;
+    // GEMV items in the order of gemv_item, over the batch: the heavy V items
+    // of every instance, then the K and full-row items, then the other V items
+    std::vector<WItem> wl_gemv_k, wl_gemv_v;
     int maxiter_host = 0, kmax = 1;
     for (int q = 0; q < nb; ++q) {
         GmresJob &J = *jobs[q];
@@ -658,7 +663,7 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
             const SurfaceDev &SD = p.surf[w];
             d.symm[w] = (!p.bem_mf && SD.sym) ? 1 : 0;
             d.symP[w] = d.symm[w] ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP1,
-                                                    size_t((SD.nv + GSYM - 1) / GSYM) * SD.nv)
+                                                    size_t(sym_partials_doubles(SD.nv)))
                                   : nullptr;
             d.dl_ptr[w] = SD.d_ptr;
             d.dl_col[w] = SD.d_col;
@@ -701,19 +706,39 @@ void batched_gmres(std::vector<GmresJob *> &jobs, hipStream_t s)
         for (int64_t c = 0; c < d.nch; ++c) wl_vec.push_back(WItem{q, int(c), c * CH});
         for (int64_t c = 0; c < d.nchb; ++c) wl_dot.push_back(WItem{q, int(c), c * CHB});
         static_assert(GROWS == GSYM, "GEMV work items are the symmetric routine's row blocks");
-        for (int a = d.two_field ? 1 : 0; a < 2; ++a) {
-            const int64_t nv = a == 0 ? d.nm : d.ns;
-            if (d.symm[a]) { // the last rows read the most: dispatched first
-                for (int64_t r = (nv - 1) / GROWS * GROWS; r >= 0; r -= GROWS) wl_gemv.push_back(WItem{q, a, r});
-                for (int64_t r = 0; r < nv; r += GFIN_ROWS) wl_fin.push_back(WItem{q, a, r});
-            } else {
-                for (int64_t r = 0; r < nv; r += GROWS) wl_gemv.push_back(WItem{q, a, r});
+        {
+            // per surface: K (or full-row) items in row order, V items last
+            // row block first (the last rows read the most); the first
+            // gemv_heavy of the V items go before every K item; the two
+            // surfaces alternate inside each stretch
+            std::vector<WItem> kit[2], vit[2];
+            for (int a = d.two_field ? 1 : 0; a < 2; ++a) {
+                const int64_t nv = a == 0 ? d.nm : d.ns;
+                for (int64_t r = 0; r < nv; r += GROWS) kit[a].push_back(WItem{q, a | (d.symm[a] ? 2 : 0), r});
+                if (d.symm[a]) {
+                    for (int64_t r = (nv - 1) / GROWS * GROWS; r >= 0; r -= GROWS) vit[a].push_back(WItem{q, a, r});
+                    for (int64_t r = 0; r < nv; r += GFIN_ROWS) wl_fin.push_back(WItem{q, a, r});
+                }
             }
+            auto alternate = [](const std::vector<WItem> &u, size_t u0, size_t u1, const std::vector<WItem> &v,
+                                size_t v0, size_t v1, std::vector<WItem> &out) {
+                for (size_t i = u0, j = v0; i < u1 || j < v1;) {
+                    if (i < u1) out.push_back(u[i++]);
+                    if (j < v1) out.push_back(v[j++]);
+                }
+            };
+            const size_t h0 = size_t(gemv_heavy(d.f32 != 0, int64_t(vit[0].size())));
+            const size_t h1 = size_t(gemv_heavy(d.f32 != 0, int64_t(vit[1].size())));
+            alternate(vit[0], 0, h0, vit[1], 0, h1, wl_gemv);
+            alternate(kit[0], 0, kit[0].size(), kit[1], 0, kit[1].size(), wl_gemv_k);
+            alternate(vit[0], h0, vit[0].size(), vit[1], h1, vit[1].size(), wl_gemv_v);
         }
         for (int64_t r = 0; r < p.nn; r += SLICE) wl_spmv.push_back(WItem{q, 0, r});
         for (int64_t k = 0; k < std::max(d.ldm, d.lds); k += CH) wl_pack.push_back(WItem{q, 0, k});
         maxiter_host = std::max(maxiter_host, J.maxit + J.maxit / std::max(m, 1) + 4);
     }
+    wl_gemv.insert(wl_gemv.end(), wl_gemv_k.begin(), wl_gemv_k.end());
+    wl_gemv.insert(wl_gemv.end(), wl_gemv_v.begin(), wl_gemv_v.end());
     int maxm = 0;
     for (auto *J : jobs) maxm = std::max(maxm, J->restart);
     // device copies of descriptors, states and work lists

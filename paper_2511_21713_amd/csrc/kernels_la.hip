@@ -53,24 +53,40 @@ struct GemvSurf {
     const double *dval;
 };
 
+// work items in gemv_item order: K and V items of the symmetric use, full-row
+// items of a surface that is not used symmetrically
+struct GemvGrid {
+    int64_t nk0, nk1, nv0, nv1, h0, h1;
+};
 template <typename MT>
-__global__ void __launch_bounds__(GEMV_THREADS, gemv_occupancy<MT>()) k_gemv(GemvSurf S0, GemvSurf S1, int64_t nblk0)
+__global__ void __launch_bounds__(GEMV_THREADS, gemv_occupancy<MT>()) k_gemv(GemvSurf S0, GemvSurf S1, GemvGrid W)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool s1 = blockIdx.x >= nblk0;
-    const GemvSurf &S = s1 ? S1 : S0;
-    const int64_t bi = s1 ? blockIdx.x - nblk0 : blockIdx.x;
-    const int64_t nb = (S.n + GSYM - 1) / GSYM;
-    // symmetric use: the last rows read the most, so they are dispatched first
-    const int64_t r0 = (S.sym ? nb - 1 - bi : bi) * int64_t(GSYM);
+    const GemvItem it = gemv_item(blockIdx.x, W.nk0, W.nk1, W.nv0, W.nv1, W.h0, W.h1);
+    const GemvSurf &S = it.s ? S1 : S0;
+    const int64_t r0 = it.b * int64_t(GSYM);
     const MT *B = static_cast<const MT *>(S.B);
-    if (S.sym) {
-        gemv_rows_sym<MT>(B, S.x, S.y, S.oidx, static_cast<sym_part_t<MT> *>(S.P), S.n, S.ld, r0, threadIdx.x);
+    if (!it.k) {
+        gemv_rows_symV<MT>(B, S.x, static_cast<sym_part_t<MT> *>(S.P), S.n, S.ld, r0, threadIdx.x);
+    } else if (S.sym) {
+        gemv_rows_symK<MT>(B, S.x, S.y, S.oidx, S.n, S.ld, r0, threadIdx.x);
     } else {
-        const int64_t rw = r0 + wv * GEMV_RW;
-        if (rw < S.n) gemv_rows<MT>(B, S.x, S.y, S.oidx, S.n, S.ld, rw, lane);
+        const int64_t rw = r0 + (threadIdx.x >> 6) * GEMV_RW;
+        if (rw < S.n) gemv_rows<MT>(B, S.x, S.y, S.oidx, S.n, S.ld, rw, threadIdx.x & 63);
     }
 }
+// the grid of surfaces 0 / 1 (n0 = 0: surface 0 left out)
+static GemvGrid gemv_grid(const GemvSurf &S0, int64_t n0, const GemvSurf &S1, int64_t n1)
+{
+    GemvGrid W;
+    W.nk0 = (n0 + GSYM - 1) / GSYM;
+    W.nk1 = (n1 + GSYM - 1) / GSYM;
+    W.nv0 = S0.sym ? W.nk0 : 0;
+    W.nv1 = S1.sym ? W.nk1 : 0;
+    W.h0 = gemv_heavy(S0.f32 != 0, W.nv0);
+    W.h1 = gemv_heavy(S1.f32 != 0, W.nv1);
+    return W;
+}
+static unsigned gemv_items(const GemvGrid &W) { return unsigned(W.nk0 + W.nk1 + W.nv0 + W.nv1); }
 
 // second stage of the symmetric use: transposed column partials and Delta
 __global__ void __launch_bounds__(256) k_gemv_fin(GemvSurf S0, GemvSurf S1, int64_t nb0)
@@ -169,7 +185,7 @@ __global__ void k_add_vec(int64_t n, const double *__restrict__ a, const double 
 // host wrappers
 // ===========================================================================
 // column partials of the symmetric use: ((nv + GSYM - 1) / GSYM) x nv FP64
-int64_t sym_partials_doubles(int64_t nv) { return ((nv + GSYM - 1) / GSYM) * nv; }
+int64_t sym_partials_doubles(int64_t nv) { return ((nv + GSYM - 1) / GSYM) * nv + nv; }
 
 static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y, double *P)
 {
@@ -194,13 +210,13 @@ static GemvSurf gemv_surf(Problem &p, int w, const double *x, double *y, double 
 static void gemv_launch(Problem &p, const ApplyBufs &bf, double *y, hipStream_t s, bool skip_m, bool timed)
 {
     const SurfaceDev &M = p.surf[0], &S = p.surf[1];
-    const int64_t nb0 = skip_m ? 0 : (M.nv + GSYM - 1) / GSYM, nb1 = (S.nv + GSYM - 1) / GSYM;
     const GemvSurf G0 = gemv_surf(p, 0, bf.xm, y + p.nn, bf.P[0]), G1 = gemv_surf(p, 1, bf.xs, y + p.nn + M.nv, bf.P[1]);
+    const GemvGrid W = gemv_grid(G0, skip_m ? 0 : M.nv, G1, S.nv);
     if (timed) p.timer.begin(T_GEMV, s);
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0 + nb1)), dim3(GEMV_THREADS), 0, s, G0, G1, nb0);
+        hipLaunchKernelGGL(k_gemv<float>, dim3(gemv_items(W)), dim3(GEMV_THREADS), 0, s, G0, G1, W);
     else
-        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0 + nb1)), dim3(GEMV_THREADS), 0, s, G0, G1, nb0);
+        hipLaunchKernelGGL(k_gemv<double>, dim3(gemv_items(W)), dim3(GEMV_THREADS), 0, s, G0, G1, W);
     if (G0.sym || G1.sym) {
         const int64_t f0 = skip_m ? 0 : (M.nv + GFIN_ROWS - 1) / GFIN_ROWS, f1 = (S.nv + GFIN_ROWS - 1) / GFIN_ROWS;
         hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0 + f1)), dim3(256), 0, s, G0, G1, f0);
@@ -317,11 +333,12 @@ static void gemv_m(Problem &p, int w, const double *xm, double *y, hipStream_t s
                                  p.surf[w].sym ? scratch<double>(p, w == 0 ? SCR_SYMP0 : SCR_SYMP2,
                                                                  sym_partials_doubles(p.surf[w].nv))
                                                : nullptr);
-    const int64_t nb0 = (G.n + GSYM - 1) / GSYM, f0 = (G.n + GFIN_ROWS - 1) / GFIN_ROWS;
+    const int64_t f0 = (G.n + GFIN_ROWS - 1) / GFIN_ROWS;
+    const GemvGrid W = gemv_grid(G, G.n, G, 0);
     if (p.precision == PBFB_MIXED)
-        hipLaunchKernelGGL(k_gemv<float>, dim3(unsigned(nb0)), dim3(GEMV_THREADS), 0, s, G, G, nb0);
+        hipLaunchKernelGGL(k_gemv<float>, dim3(gemv_items(W)), dim3(GEMV_THREADS), 0, s, G, G, W);
     else
-        hipLaunchKernelGGL(k_gemv<double>, dim3(unsigned(nb0)), dim3(GEMV_THREADS), 0, s, G, G, nb0);
+        hipLaunchKernelGGL(k_gemv<double>, dim3(gemv_items(W)), dim3(GEMV_THREADS), 0, s, G, G, W);
     if (G.sym) hipLaunchKernelGGL(k_gemv_fin, dim3(unsigned(f0)), dim3(256), 0, s, G, G, f0);
 }
 

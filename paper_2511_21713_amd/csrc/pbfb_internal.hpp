@@ -366,8 +366,9 @@ double fem_energy_integral(Problem &p, const double *u_lin, const double *u_nl, 
 // coupled operator y = J x with the current CSR values (pack + GEMV + SpMV)
 void coupled_apply(Problem &p, const double *x, double *y, hipStream_t s);
 // work buffers of one apply: packed surface inputs (bem_ld(nv) each) and the
-// FP64 column partials of the symmetric use (sym_partials_doubles(nv) each,
-// null where a surface is not stored symmetric)
+// FP64 column partials and V-item row sums of the symmetric use
+// (sym_partials_doubles(nv) each, null where a surface is not stored
+// symmetric)
 struct ApplyBufs {
     double *xm = nullptr, *xs = nullptr;
     double *P[2] = {nullptr, nullptr};
