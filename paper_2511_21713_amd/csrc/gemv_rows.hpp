@@ -35,8 +35,12 @@ constexpr int GEMV_WAVES = 8;                    // wavefronts per workgroup
 constexpr int GEMV_THREADS = 64 * GEMV_WAVES;    // threads per workgroup
 constexpr int GEMV_RW = 8;                       // rows per wavefront
 constexpr int GSYM = GEMV_WAVES * GEMV_RW;       // rows per workgroup (both forms)
-// minimum wavefronts per SIMD of the dense-apply kernels (register budget)
-template <typename MT> constexpr int gemv_occupancy() { return 2; }
+// minimum wavefronts per SIMD of the dense-apply kernels (register budget):
+// FP64 storage asks for four (at most 128 VGPRs, two 512-thread workgroups per
+// CU), which the FP64 routines fit without spills; at 200 VGPRs (one
+// workgroup per CU) the same FP64 apply ran at 0.61 of HBM instead of 0.80.
+// The FP32 routines need more registers (one workgroup per CU either way).
+template <typename MT> constexpr int gemv_occupancy() { return sizeof(MT) == 8 ? 4 : 2; }
 
 // one chunk of GEMV_RW rows (EL entries per lane) and the matching input entries
 template <typename MT> struct GemvChunk {
