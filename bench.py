@@ -484,8 +484,9 @@ def main():
     nn = prob.nodes.shape[0]
     flops = apply_flops(nm, ns, nnz)
     sym_tiles = all(a == b for a, b in f64["tiles"].values())
-    kname = ("k_bgemv + k_bgemv_fin / k_gemv + k_gemv_fin (gemv_rows_sym: K' and the lower triangle of V', "
-             f"{'FP32' if elem == 4 else 'FP64'} storage, FP64 accumulation, both interfaces)" if sym else
+    kname = ("k_bgemv + k_bgemv_fin / k_gemv + k_gemv_fin (gemv_rows_symK / gemv_rows_symV work items: K' and "
+             f"the lower triangle of V', {'FP32' if elem == 4 else 'FP64'} storage, FP64 accumulation, both "
+             "interfaces)" if sym else
              f"k_bgemv / k_gemv (gemv_rows: dense [K'|V'] {'FP32' if elem == 4 else 'FP64'} GEMV, both interfaces)")
     tkey = gemv_traffic_key(cfg, elem)
     workload = (f"RNA-like solute, large: {prob.tri_m.shape[0]} triangles per interface, {prob.tets.shape[0]} shell "
