@@ -273,6 +273,11 @@ __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, co
     }
 }
 
+// occupancy asked of the compiler: FP32 tiles fit in 80 VGPRs (six
+// wavefronts per SIMD by registers and LDS), FP64 tiles in 128 (four)
+constexpr int TILE_F32_WAVES = 5;
+constexpr int TILE_F64_WAVES = 4;
+
 // RT = double: positions and normals in FP64 (xq, nq: m_qp, m_nrm; cen unused)
 // RT = float : FP32 offsets from FP64 centroids (xq, nq: m_qf, m_nf; cen: m_cen)
 // MT: storage of the operator (double, or float in mixed precision)
@@ -296,10 +301,6 @@ __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, co
 // Every lane runs the quadrature: a pair that is not evaluated (padding
 // triangle, shared vertex, or the mirror of a diagonal-tile pair) has its
 // target moved 1e4 away and a zero factor, so its terms are exact zeros.
-// occupancy asked of the compiler: FP32 tiles fit in 80 VGPRs (six
-// wavefronts per SIMD by registers and LDS), FP64 tiles in 128 (four)
-constexpr int TILE_F32_WAVES = 5;
-constexpr int TILE_F64_WAVES = 4;
 template <bool YUK, typename RT, typename MT, int TA, int TB, int MS, bool SYM>
 __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 ? TILE_F32_WAVES : TILE_F64_WAVES)))
     k_bem_regular(int64_t nt, const int32_t *__restrict__ m_tri, const RT *__restrict__ xq,
