@@ -111,6 +111,13 @@ template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int6
     U[at] = MT(double(U[at]) + v);
 }
 
+// Rows of the fold's last stage whose operator entries a thread reads before
+// the quadrature (the rest are read when they are added to).  FP32 tiles: one
+// (342 -> 325 ms per 80k-triangle assembly; two cost registers and gained
+// nothing more); FP64 tiles: none (the registers they would take spill)
+constexpr int FOLD_PF32 = 1, FOLD_PF64 = 0;
+template <typename MT> constexpr int fold_pf() { return sizeof(MT) == 4 ? FOLD_PF32 : FOLD_PF64; }
+
 // Fold of a tile's pair blocks onto the blocks' vertices through the shared
 // tile, one operator at a time (FP64 evaluation: V, K and the mirrored K in
 // turn through one FP64 plane, which keeps the LDS of a workgroup small
@@ -123,10 +130,11 @@ template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int6
 // column), so the reads pipeline.  MS >= the largest number of corners of
 // any vertex of either block: the lists past it hold only absent corners,
 // whose +0 terms are skipped.
-template <int TA, int TB, int MS, typename MT, typename ST, typename XT>
+template <int TA, int TB, int MS, int SLOT, typename MT, typename ST, typename XT>
 __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
                                      const int (*sSb)[MS], ST (*acc)[TB * 3 + 1], const XT *Xl, const int *vA,
-                                     const int *vB, MT *__restrict__ U, int64_t ld, int64_t off, double sc)
+                                     const int *vB, MT *__restrict__ U, int64_t ld, int64_t off, double sc,
+                                     const MT (*pre)[3])
 {
     constexpr int NT = TA * TB;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -173,7 +181,7 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
     __syncthreads();
     if (colthread) {
         const int64_t col = off + vB[jb];
-        for (int ia = r0; ia < nA; ia += rstep) {
+        auto rowsum = [&](int ia) {
             double v[MS];
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
@@ -183,8 +191,15 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
             double t = 0.0;
 #pragma unroll
             for (int k = 0; k < MS; ++k) t += v[k];
-            add_entry(U, int64_t(vA[ia]) * ld + col, sc * t);
+            return t;
+        };
+        // the first fold_pf rows add to the entries read before the quadrature
+#pragma unroll
+        for (int k = 0; k < fold_pf<MT>(); ++k) {
+            const int ia = r0 + k * rstep;
+            if (ia < nA) U[int64_t(vA[ia]) * ld + col] = MT(double(pre[k][SLOT]) + sc * rowsum(ia));
         }
+        for (int ia = r0 + fold_pf<MT>() * rstep; ia < nA; ia += rstep) add_entry(U, int64_t(vA[ia]) * ld + col, sc * rowsum(ia));
     }
     __syncthreads();
 }
@@ -198,7 +213,7 @@ template <int TA, int TB, int MS, bool TOT, typename MT>
 __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
                                      const int (*sSb)[MS], float (*acc)[TA * 3 + 1][TB * 3 + 1],
                                      const float (*blk)[9], const int *vA, const int *vB, MT *__restrict__ U,
-                                     int64_t ld, int64_t off, double s0, double s1)
+                                     int64_t ld, int64_t off, double s0, double s1, const MT (*pre)[3])
 {
     constexpr int NT = TA * TB, RMAX = TA * 3, CMAX = TB * 3, RC = 4, NPL = TOT ? 1 : 2;
     const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
@@ -252,8 +267,7 @@ __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, co
     }
     if (colthread) {
         const int64_t col = vB[jb];
-        for (int ia = r0; ia < nA; ia += rstep) {
-            double t[NPL];
+        auto rowsum = [&](int ia, double (&t)[NPL]) {
 #pragma unroll
             for (int pl = 0; pl < NPL; ++pl) t[pl] = 0.0;
 #pragma unroll
@@ -262,6 +276,26 @@ __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, co
 #pragma unroll
                 for (int pl = 0; pl < NPL; ++pl) t[pl] += double(acc[pl][ra][jb]);
             }
+        };
+        // the first fold_pf rows add to the entries read before the quadrature
+#pragma unroll
+        for (int k = 0; k < fold_pf<MT>(); ++k) {
+            const int ia = r0 + k * rstep;
+            if (ia < nA) {
+                double t[NPL];
+                rowsum(ia, t);
+                const int64_t row = int64_t(vA[ia]) * ld;
+                if constexpr (TOT) {
+                    U[row + col] = MT(double(pre[k][2]) + s0 * t[0]);
+                } else {
+                    U[row + off + col] = MT(double(pre[k][0]) + s0 * t[0]);
+                    U[row + col] = MT(double(pre[k][1]) + s1 * t[1]);
+                }
+            }
+        }
+        for (int ia = r0 + fold_pf<MT>() * rstep; ia < nA; ia += rstep) {
+            double t[NPL];
+            rowsum(ia, t);
             const int64_t row = int64_t(vA[ia]) * ld;
             if constexpr (TOT) {
                 add_entry(U, row + col, s0 * t[0]);
@@ -458,6 +492,28 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
         }
     };
 
+    // The stored entries this thread adds to in the fold's last stage (row
+    // vA[ia], column vB[jb] of V', K' and, square tiles, T; the fold's thread
+    // map), read now so that their latency hides behind the quadrature.  No
+    // other workgroup of the launch touches them.
+    MT pre[fold_pf<MT>() > 0 ? fold_pf<MT>() : 1][3];
+    {
+        const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+        if (r0 < rstep) {
+            const int64_t col = sIb[jb];
+#pragma unroll
+            for (int k = 0; k < fold_pf<MT>(); ++k) {
+                const int ia = r0 + k * rstep;
+                if (ia < nA) {
+                    const int64_t row = sIa[ia];
+                    pre[k][0] = U[row * ld + nv + col];
+                    pre[k][1] = U[row * ld + col];
+                    if constexpr (SYM) pre[k][2] = T[row * nv + col];
+                }
+            }
+        }
+    }
+
     // the pair's 3x3 blocks, summed over its 36 quadrature pairs; the first
     // target point assigns them
     RT Vl[9] = {}, Kl[9] = {}, Ktl[SYM ? 9 : 1] = {};
@@ -496,16 +552,17 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
             blk[1][k] = Kl[k];
             bmt[0][k] = Ktl[SYM ? k : 0];
         }
-        fold_tile_f32<TA, TB, MS, false>(tid, tl, sl, nA, nB, sSa, sSb, acc, blk, sIa, sIb, U, ld, nv, sV, sK);
+        fold_tile_f32<TA, TB, MS, false>(tid, tl, sl, nA, nB, sSa, sSb, acc, blk, sIa, sIb, U, ld, nv, sV, sK, pre);
         if constexpr (SYM) {
             __syncthreads();
-            fold_tile_f32<TA, TB, MS, true>(tid, tl, sl, nA, nB, sSa, sSb, acc, bmt, sIa, sIb, T, nv, 0, sK, 0.0);
+            fold_tile_f32<TA, TB, MS, true>(tid, tl, sl, nA, nB, sSa, sSb, acc, bmt, sIa, sIb, T, nv, 0, sK, 0.0,
+                                            pre);
         }
     } else {
-        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Vl, sIa, sIb, U, ld, nv, sV);
-        fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Kl, sIa, sIb, U, ld, 0, sK);
+        fold_tile_one<TA, TB, MS, 0>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Vl, sIa, sIb, U, ld, nv, sV, pre);
+        fold_tile_one<TA, TB, MS, 1>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Kl, sIa, sIb, U, ld, 0, sK, pre);
         if constexpr (SYM)
-            fold_tile_one<TA, TB, MS>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Ktl, sIa, sIb, T, nv, 0, sK);
+            fold_tile_one<TA, TB, MS, 2>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Ktl, sIa, sIb, T, nv, 0, sK, pre);
     }
 }
 
