@@ -227,10 +227,26 @@ def batch_leg(pb, torch, count, steps, precision):
             "status": code}
 
 
-def serve_requests(count, nmax):
+def _serve_instance(args):
     import pbgen
+    return pbgen.serve_instance(args[0], n_hi=args[1])
+
+
+def serve_requests(count, nmax):
+    """The serving stream's requests, generated on the host before any GPU
+    work (a long stream is generated by a pool of forked workers)."""
     t0 = time.perf_counter()
-    probs = [pbgen.serve_instance(i, n_hi=nmax) for i in range(count)]
+    work = [(i, nmax) for i in range(count)]
+    if count > 64:
+        import multiprocessing as mp
+        probs = []
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+            for p in pool.imap(_serve_instance, work, chunksize=4):
+                probs.append(p)
+                if len(probs) % 250 == 0:
+                    progress(f"serve: {len(probs)} of {count} requests generated")
+    else:
+        probs = [_serve_instance(w) for w in work]
     tris = sorted(p.tri_m.shape[0] for p in probs)
     progress(f"serve: generated {count} requests in {time.perf_counter() - t0:.1f} s, triangles per interface "
              f"{tris[0]}..{tris[-1]} (median {tris[len(tris) // 2]})")
@@ -244,22 +260,25 @@ def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0, 
     submitted to a continuous-batching server with an HBM budget that binds
     (requests wait for admission); latency = submit to completion, admission
     wait = submit to admission.  The service rate is the mean solo solve time
-    of every fifth request (setup included).  Default budget: 1.1 x the
-    largest request's footprint (steady + setup workspace), so that a large
-    request waits for the running ones and the budget binds."""
+    of every fifth request (of about 40 evenly spaced ones in a long stream;
+    setup included).  Default budget: 1.1 x the largest request's footprint
+    (steady + setup workspace, taken over the 8 largest meshes), so that a
+    large request waits for the running ones and the budget binds."""
     import numpy as np
 
     count = len(probs)
     ctx = pb.Context(0)
     if budget is None:
+        # the footprint grows with the mesh: the largest requests set the budget
+        big = sorted(probs, key=lambda p: (p.tri_m.shape[0], p.tets.shape[0]))[-8:]
         fps = []
-        for p in probs:
+        for p in big:
             g = pb.Problem.from_inputs(ctx, p, precision=precision)
             fps.append(sum(g.footprint()))
             g.close()
         budget = int(1.1 * max(fps))
     svc = []
-    for p in probs[::5]:
+    for p in probs[::max(5, count // 40)]:
         g = pb.Problem.from_inputs(ctx, p, precision=precision)
         g.solve()
         g.reset_operators()
@@ -277,7 +296,14 @@ def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0, 
         free0 = torch.cuda.mem_get_info()[0]
         low = free0
         srv = pb.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
-        gs = [pb.Problem.from_inputs(ctx, p, precision=precision) for p in probs]
+        t0 = time.perf_counter()
+        gs = []
+        for p in probs:
+            gs.append(pb.Problem.from_inputs(ctx, p, precision=precision))
+            if count > 100 and len(gs) % 250 == 0:
+                progress(f"serve ({prec}, load {load}): {len(gs)} problems set up")
+        progress(f"serve ({prec}, load {load}): {count} problems set up on the host in "
+                 f"{time.perf_counter() - t0:.1f} s")
         submit, done, res = {}, {}, {}
         tickets, rejected = [], 0
         start = time.perf_counter()
@@ -302,6 +328,8 @@ def serve_leg(pb, torch, probs, nmax, precision, loads=(0.5, 0.8, 1.0), seed=0, 
                     if r is not None:
                         done[t] = time.perf_counter()
                         res[t] = r
+                        if count > 100 and len(done) % 200 == 0:
+                            progress(f"serve ({prec}, load {load}): {len(done)} of {count} requests done")
             low = min(low, torch.cuda.mem_get_info()[0])
             time.sleep(0.0005)
         makespan = time.perf_counter() - start
@@ -433,6 +461,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="HBM budget of the serving leg (0: 1.1 x the largest request's footprint)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,1.0")
+    ap.add_argument("--serve-precisions", type=str, default="mixed,fp64",
+                    help="precisions of the serving leg (the FP64 one at load 0.8)")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="run one device copy of this size first (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -440,6 +470,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU row-block sharding is a design, not built)", file=sys.stderr)
         sys.exit(2)
+    reqs = serve_requests(args.serve, args.serve_nmax) if args.serve > 0 else None
     import torch
 
     import paper_2511_21713_amd as pb
@@ -591,11 +622,13 @@ def main():
         out["batched"] = {"mixed": batch_leg(pb, torch, args.batch, 1, pb.MIXED),
                           "fp64": batch_leg(pb, torch, args.batch, 1, pb.FP64)}
     if args.serve > 0:
-        reqs = serve_requests(args.serve, args.serve_nmax)
         loads = tuple(float(x) for x in args.serve_loads.split(","))
         bud = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb > 0 else None
-        out["serving"] = {"mixed": serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED, loads, budget=bud),
-                          "fp64": serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64, (0.8,), budget=bud)}
+        out["serving"] = {}
+        if "mixed" in args.serve_precisions:
+            out["serving"]["mixed"] = serve_leg(pb, torch, reqs, args.serve_nmax, pb.MIXED, loads, budget=bud)
+        if "fp64" in args.serve_precisions:
+            out["serving"]["fp64"] = serve_leg(pb, torch, reqs, args.serve_nmax, pb.FP64, (0.8,), budget=bud)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle, bounded sample, extrapolated)")
         t0 = time.perf_counter()
