@@ -605,6 +605,76 @@ __global__ void __launch_bounds__(256) k_bem_symm(int64_t nv, int64_t ld, MT *__
     }
 }
 
+// The same completion for an even nv (every row offset of B and T is then
+// even, so each thread moves aligned pairs of entries), launched over the
+// tile pairs I <= J only (block k = J (J + 1) / 2 + I), with the stored K'
+// entries read together with the other inputs, before the exchange.  The
+// sums are those of k_bem_symm, so the results are identical.
+template <typename MT>
+__global__ void __launch_bounds__(256) k_bem_symm2(int64_t nv, int64_t ld, MT *__restrict__ B,
+                                                   const MT *__restrict__ T)
+{
+    typedef MT pair_t __attribute__((ext_vector_type(2)));
+    const int64_t k = blockIdx.x;
+    int64_t J = int64_t((sqrt(8.0 * double(k) + 1.0) - 1.0) * 0.5);
+    while (J * (J + 1) / 2 > k) --J;
+    while ((J + 1) * (J + 2) / 2 <= k) ++J;
+    const int64_t I = k - J * (J + 1) / 2;
+    __shared__ double a[SYMT][SYMT + 1], b[SYMT][SYMT + 1], t1[SYMT][SYMT + 1], t2[SYMT][SYMT + 1];
+    constexpr int TXN = SYMT / 2, RP = 256 / TXN; // threads per tile row, rows per pass
+    const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN, c = 2 * tx;
+    pair_t k1[SYMT / RP], k2[SYMT / RP]; // stored K' of tile (I, J) and of tile (J, I)
+#pragma unroll
+    for (int h = 0; h < SYMT / RP; ++h) {
+        const int r = ty + h * RP;
+        const int64_t i = I * SYMT + r, j = J * SYMT + c;   // tile (I, J)
+        const int64_t i2 = J * SYMT + r, j2 = I * SYMT + c; // tile (J, I)
+        // nv even and c even: the pair (j, j + 1) lies entirely inside or outside
+        const bool in1 = i < nv && j < nv, in2 = i2 < nv && j2 < nv;
+        const pair_t z = {MT(0), MT(0)};
+        const pair_t va = in1 ? *reinterpret_cast<const pair_t *>(B + i * ld + nv + j) : z;
+        const pair_t vt2 = in1 ? *reinterpret_cast<const pair_t *>(T + i * nv + j) : z;
+        const pair_t vb = in2 ? *reinterpret_cast<const pair_t *>(B + i2 * ld + nv + j2) : z;
+        const pair_t vt1 = in2 ? *reinterpret_cast<const pair_t *>(T + i2 * nv + j2) : z;
+        k1[h] = in1 ? *reinterpret_cast<const pair_t *>(B + i * ld + j) : z;
+        k2[h] = in2 && I != J ? *reinterpret_cast<const pair_t *>(B + i2 * ld + j2) : z;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            a[r][c + e] = double(va[e]);
+            t2[r][c + e] = double(vt2[e]);
+            b[r][c + e] = double(vb[e]);
+            t1[r][c + e] = double(vt1[e]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < SYMT / RP; ++h) {
+        const int r = ty + h * RP;
+        const int64_t i = I * SYMT + r, j = J * SYMT + c;
+        if (i < nv && j < nv) {
+            pair_t v, w;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                v[e] = MT(a[r][c + e] + b[c + e][r]);
+                w[e] = MT(double(k1[h][e]) + t1[c + e][r]);
+            }
+            *reinterpret_cast<pair_t *>(B + i * ld + nv + j) = v;
+            *reinterpret_cast<pair_t *>(B + i * ld + j) = w;
+        }
+        const int64_t i2 = J * SYMT + r, j2 = I * SYMT + c;
+        if (I != J && i2 < nv && j2 < nv) {
+            pair_t v, w;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                v[e] = MT(b[r][c + e] + a[c + e][r]);
+                w[e] = MT(double(k2[h][e]) + t2[c + e][r]);
+            }
+            *reinterpret_cast<pair_t *>(B + i2 * ld + nv + j2) = v;
+            *reinterpret_cast<pair_t *>(B + i2 * ld + j2) = w;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 3. touching pairs: Sauter-Schwab (Sauter & Schwab, Boundary Element
 //    Methods, Sec. 5.2) on the reference triangle {0 <= xi2 <= xi1 <= 1},
@@ -907,10 +977,12 @@ __global__ void __launch_bounds__(256)
 
 // Rows whose 1-ring has at most SPAI_SMALL vertices (every vertex of the
 // usual surface meshes): one wavefront per row, each lane streams W
-// consecutive columns at a time (one W-wide load per row; W is chosen from
-// the alignment of the V' columns) of the m rows and keeps the m (m + 1) / 2
-// Gram partial sums in registers; a fixed xor-shuffle tree then sums them
-// across the lanes.
+// consecutive columns at a time (one 16-byte load per row: W = 4 for FP32,
+// 2 for FP64) of the m rows and keeps the m (m + 1) / 2 Gram partial sums in
+// registers; a fixed xor-shuffle tree then sums them across the lanes.  The
+// V' columns start at column nv of rows of ld (a multiple of 256) entries,
+// so the first head = (-nv) mod W columns are taken one per lane and the
+// W-wide loads start at an aligned column.
 template <typename MT, int W> struct alignas(W * sizeof(MT)) SpaiVec {
     MT v[W];
 };
@@ -932,7 +1004,18 @@ __global__ void __launch_bounds__(256)
     double g[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) g[k] = 0.0;
-    for (int64_t c = int64_t(W) * lane; c < nv; c += 64 * W) {
+    const int head = int((W - nv % W) % W);
+    if (lane < head) {
+        double x[SPAI_SMALL];
+#pragma unroll
+        for (int a = 0; a < SPAI_SMALL; ++a) x[a] = a < m ? double(rows[a][lane]) : 0.0;
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < SPAI_SMALL; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++k) g[k] = fma(x[a], x[b], g[k]);
+    }
+    for (int64_t c = head + int64_t(W) * lane; c < nv; c += 64 * W) {
         double x[SPAI_SMALL][W];
         if (c + W <= nv) {
 #pragma unroll
@@ -1387,7 +1470,13 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
     PB_HIP(hipGetLastError());
     if (sym) {
         const unsigned nbt = unsigned((nv + SYMT - 1) / SYMT);
-        if (f32)
+        // FP32 storage with an even nv: pairs of entries, upper tile pairs only
+        // (11.3 -> 7.7 ms per 80k-triangle interface); the same form ran FP64
+        // storage slower (14.5 -> 19.9 ms), which keeps the one-entry kernel
+        if (f32 && nv % 2 == 0 && ld % 2 == 0)
+            hipLaunchKernelGGL(k_bem_symm2<float>, dim3(unsigned(int64_t(nbt) * (nbt + 1) / 2)), dim3(256), 0, s,
+                               nv, ld, static_cast<float *>(S.B), static_cast<const float *>(Tm));
+        else if (f32)
             hipLaunchKernelGGL(k_bem_symm<float>, dim3(nbt, nbt), dim3(256), 0, s, nv, ld, static_cast<float *>(S.B),
                                static_cast<const float *>(Tm));
         else
@@ -1426,16 +1515,8 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         if (sym)
             hipLaunchKernelGGL(k_sym_delta<float>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, Bf, S.d_ptr, S.d_col,
                                S.d_val);
-        // the V' columns start at column nv of rows of ld (a multiple of 256) entries
-        if (nv % 4 == 0)
-            hipLaunchKernelGGL((k_spai_small<float, 4>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
-                               S.ring_ptr, S.ring, S.spai, p.d_bad);
-        else if (nv % 2 == 0)
-            hipLaunchKernelGGL((k_spai_small<float, 2>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
-                               S.ring_ptr, S.ring, S.spai, p.d_bad);
-        else
-            hipLaunchKernelGGL((k_spai_small<float, 1>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
-                               S.ring_ptr, S.ring, S.spai, p.d_bad);
+        hipLaunchKernelGGL((k_spai_small<float, 4>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bf, ld, S.minv,
+                           S.ring_ptr, S.ring, S.spai, p.d_bad);
         if (T.max_ring > SPAI_SMALL)
             hipLaunchKernelGGL(k_spai<float>, dim3(unsigned(nv)), dim3(256), 0, s, nv, Bf, ld, S.minv, S.ring_ptr,
                                S.ring, S.spai, p.d_bad);
@@ -1445,12 +1526,8 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         if (sym)
             hipLaunchKernelGGL(k_sym_delta<double>, dim3(nblk(nv, 256)), dim3(256), 0, s, nv, ld, Bd, S.d_ptr,
                                S.d_col, S.d_val);
-        if (nv % 2 == 0)
-            hipLaunchKernelGGL((k_spai_small<double, 2>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv,
-                               S.ring_ptr, S.ring, S.spai, p.d_bad);
-        else
-            hipLaunchKernelGGL((k_spai_small<double, 1>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv,
-                               S.ring_ptr, S.ring, S.spai, p.d_bad);
+        hipLaunchKernelGGL((k_spai_small<double, 2>), dim3(nblk(nv, 4)), dim3(256), 0, s, nv, Bd, ld, S.minv,
+                           S.ring_ptr, S.ring, S.spai, p.d_bad);
         if (T.max_ring > SPAI_SMALL)
             hipLaunchKernelGGL(k_spai<double>, dim3(unsigned(nv)), dim3(256), 0, s, nv, Bd, ld, S.minv, S.ring_ptr,
                                S.ring, S.spai, p.d_bad);

@@ -220,8 +220,8 @@ def uv_sphere(nlon=9, nlat=6):
     return verts, tris
 
 
-def valence_problem(nlon):
-    unit, tris = uv_sphere(nlon=nlon, nlat=7)
+def valence_problem(nlon, nlat=7):
+    unit, tris = uv_sphere(nlon=nlon, nlat=nlat)
     nodes, tets, tri_m, tri_s = pbgen.shell_mesh(unit, tris, 4.0 * np.ones(unit.shape[0]), 3.0, 2)
     return pbgen.Problem(nodes=nodes, tets=tets, tri_m=tri_m, tri_s=tri_s, q_xyz=np.array([[0.0, 0.0, 0.5]]),
                          q_z=np.array([1.0]), eps_in=4.0, eps_out=80.0, kappa=0.2, info={})
@@ -248,6 +248,34 @@ def test_high_valence_mesh_matches_oracle(tiles, nlon):
             eV, eK = rowrel(Vp, ref[surf][0]), rowrel(Kp, ref[surf][1])
             log(f"  valence-{nlon} mesh, shape {shape}, surf {surf}: V {eV:.2e} K {eK:.2e}")
             assert eV < 1e-12 and eK < 1e-12
+        g.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_odd_vertex_count_matches_oracle(tiles, precision):
+    """A surface with an odd number of vertices (47: the symmetric completion
+    of FP32 storage then moves single entries instead of aligned pairs)
+    assembles the oracle's blocks with every tile shape."""
+    pb, ctx, _, _ = tiles
+    prob = valence_problem(9, nlat=6)
+    o = oracle.Oracle.from_problem(prob)
+    bar = 1e-12 if precision == 0 else 1e-6
+    ref = []
+    for surf in (0, 1):
+        V, K = o.bem_dense(surf)
+        nv = V.shape[0]
+        assert nv % 2 == 1
+        M = np.stack([o.surface_mass_apply(surf, e) for e in np.eye(nv)], 1)
+        ref.append((-V if surf == 0 else V, 0.5 * M + (K if surf == 0 else -K)))
+    for shape in SHAPES:
+        g = pb.Problem.from_inputs(ctx, prob, precision=precision)
+        g.set_tile_shape(*shape)
+        for surf in (0, 1):
+            Vp, Kp = g.export_bem(surf)
+            eV, eK = rowrel(Vp, ref[surf][0]), rowrel(Kp, ref[surf][1])
+            log(f"  {Vp.shape[0]}-vertex mesh, shape {shape}, precision {precision}, surf {surf}: "
+                f"V {eV:.2e} K {eK:.2e}")
+            assert eV < bar and eK < bar
         g.close()
 
 
