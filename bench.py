@@ -53,9 +53,11 @@ FLOPS_QP = {"laplace": 37, "yukawa": 46}
 # the same for the matrix-free apply's k_mf_pot (one potential pair per
 # quadrature pair): 3 sub, 5 for r^2, rsqrt, 2 mul r^-3, 2 FMA for the two
 # strength sums = 15, plus the per-target-point normal distance and FP64
-# accumulation (11 flops over the 6 source points) = 17; Yukawa adds r = r^2
-# r^-1, the exponent (2 mul), exp, e r^-1, (1 + kappa r) (FMA), 2 mul = 9
-MF_FLOPS_QP = {"laplace": 17, "yukawa": 26}
+# accumulation (11 flops over the 6 source points) = 17; Yukawa forms the
+# double-layer factor as e r^-1 r^-1 (r^-1 + kappa) instead of r^-3: r = r^2
+# r^-1, the exponent (2 mul), exp, e r^-1, then add + 2 mul, in place of the
+# 2 mul of r^-3 = +6
+MF_FLOPS_QP = {"laplace": 17, "yukawa": 23}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 

@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
                 if constexpr (F32) e = __builtin_amdgcn_exp2f(kl2 * r);
                 else e = exp_neg(kap * r);
                 gv[q] = e * ri;
-                hk[q] = gv[q] * (ri * ri) * (RT(1) + kap * r);
+                hk[q] = gv[q] * ri * (ri + kap); // e (1 + kappa r) / r^3
             } else {
                 gv[q] = ri;
                 hk[q] = ri * ri * ri;

@@ -137,18 +137,17 @@ __global__ void __launch_bounds__(MF_NT, 2)
                 const RT d0 = x0 - sY[sli][3 * q], d1 = x1 - sY[sli][3 * q + 1], d2 = x2 - sY[sli][3 * q + 2];
                 const RT r2 = d0 * d0 + d1 * d1 + d2 * d2;
                 const RT ri = rsqrt_pos(r2);
-                const RT ri3 = ri * ri * ri;
                 RT gv, hk;
                 if constexpr (YUK) {
                     const RT r = r2 * ri;
                     RT e;
                     if constexpr (F32) e = __builtin_amdgcn_exp2f(-1.44269504088896341f * kap * r);
-                    else e = exp(-kap * r);
+                    else e = exp_neg(kap * r);
                     gv = e * ri;
-                    hk = (RT(1) + kap * r) * e * ri3;
+                    hk = gv * ri * (ri + kap); // e (1 + kappa r) / r^3
                 } else {
                     gv = ri;
-                    hk = ri3;
+                    hk = ri * ri * ri;
                 }
                 av += gv * sL[sli][q];
                 ak += hk * sU[sli][q];
