@@ -31,11 +31,11 @@
 // quadrature point is held as an FP32 offset from its triangle's centroid,
 // the centroid difference of a pair is formed in FP64 and rounded once, so
 // x - y never cancels large coordinates in FP32.  A pair's 3x3 V and K
-// blocks are summed over its 36 quadrature pairs in FP32; the fold onto a
-// tile's vertices adds in FP64 (its intermediate column sums are kept in LDS
-// as FP32), and each tile's sum is added to the FP32 stored entry in FP64
-// and rounded once (an entry receives one tile's sum for each pair of blocks
-// holding its two vertices).  The touching pairs stay FP64 throughout.
+// blocks are summed over its 36 quadrature pairs in FP32, and so are the
+// fold's corner sums onto a tile's vertices (at most MS terms each); each
+// tile's sum is added to the FP32 stored entry in FP64 and rounded once (an
+// entry receives one tile's sum for each pair of blocks holding its two
+// vertices).  The touching pairs stay FP64 throughout.
 #include <chrono>
 #include <cmath>
 #include <thread>
@@ -173,7 +173,6 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
         }
     }
     __syncthreads();
-    // (an FP32 tile stores the FP64 column sums rounded to FP32)
     if (colthread)
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
@@ -204,8 +203,9 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
     __syncthreads();
 }
 
-// Fold of an FP32 tile's pair blocks, V and K in two FP32 planes of the
-// shared tile read at the same index (TOT = false: V to column off + vB[jb]
+// Fold of an FP32 tile's pair blocks (corner sums in FP32, the evaluation
+// precision), V and K in two FP32 planes of the shared tile read at the same
+// index (TOT = false: V to column off + vB[jb]
 // with factor s0, K to column vB[jb] with factor s1 of row vA[ia] of U), or
 // the mirrored K of a square tile in one plane (TOT = true: to column vB[jb]
 // of row vA[ia] of U = T with factor s0); otherwise as fold_tile_one.
@@ -239,19 +239,19 @@ __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, co
     __syncthreads();
     const int rows_pt = (RMAX + rstep - 1) / rstep; // uniform
     for (int rb = 0; rb < rows_pt; rb += RC) {
-        double colsum[RC][NPL];
+        float colsum[RC][NPL];
         int nrow = 0;
         if (colthread) {
 #pragma unroll
             for (int r = 0; r < RC; ++r) {
                 const int sa = r0 + (rb + r) * rstep;
 #pragma unroll
-                for (int pl = 0; pl < NPL; ++pl) colsum[r][pl] = 0.0;
+                for (int pl = 0; pl < NPL; ++pl) colsum[r][pl] = 0.0f;
                 if (sa < RMAX) {
 #pragma unroll
                     for (int l = 0; l < MS; ++l)
 #pragma unroll
-                        for (int pl = 0; pl < NPL; ++pl) colsum[r][pl] += double(acc[pl][sa][cb[l]]);
+                        for (int pl = 0; pl < NPL; ++pl) colsum[r][pl] += acc[pl][sa][cb[l]];
                     nrow = r + 1;
                 }
             }
@@ -262,20 +262,23 @@ __device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, co
             for (int r = 0; r < RC; ++r)
                 if (r < nrow)
 #pragma unroll
-                    for (int pl = 0; pl < NPL; ++pl) acc[pl][r0 + (rb + r) * rstep][jb] = float(colsum[r][pl]);
+                    for (int pl = 0; pl < NPL; ++pl) acc[pl][r0 + (rb + r) * rstep][jb] = colsum[r][pl];
         __syncthreads();
     }
     if (colthread) {
         const int64_t col = vB[jb];
         auto rowsum = [&](int ia, double (&t)[NPL]) {
+            float f[NPL];
 #pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) t[pl] = 0.0;
+            for (int pl = 0; pl < NPL; ++pl) f[pl] = 0.0f;
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
                 const int ra = sSa[ia][k] < 0 ? RMAX : sSa[ia][k];
 #pragma unroll
-                for (int pl = 0; pl < NPL; ++pl) t[pl] += double(acc[pl][ra][jb]);
+                for (int pl = 0; pl < NPL; ++pl) f[pl] += acc[pl][ra][jb];
             }
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) t[pl] = double(f[pl]);
         };
         // the first fold_pf rows add to the entries read before the quadrature
 #pragma unroll
