@@ -1476,9 +1476,10 @@ void ensure_bem(Problem &p, int w, hipStream_t s)
         // FP32 storage with an even nv: pairs of entries, upper tile pairs only
         // (11.3 -> 7.7 ms per 80k-triangle interface); the same form ran FP64
         // storage slower (14.5 -> 19.9 ms), which keeps the one-entry kernel
-        if (f32 && nv % 2 == 0 && ld % 2 == 0)
-            hipLaunchKernelGGL(k_bem_symm2<float>, dim3(unsigned(int64_t(nbt) * (nbt + 1) / 2)), dim3(256), 0, s,
-                               nv, ld, static_cast<float *>(S.B), static_cast<const float *>(Tm));
+        const int64_t npair = int64_t(nbt) * (nbt + 1) / 2; // one-dimensional grid: npair * 256 < 2^32
+        if (f32 && nv % 2 == 0 && ld % 2 == 0 && npair * 256 < (int64_t(1) << 32))
+            hipLaunchKernelGGL(k_bem_symm2<float>, dim3(unsigned(npair)), dim3(256), 0, s, nv, ld,
+                               static_cast<float *>(S.B), static_cast<const float *>(Tm));
         else if (f32)
             hipLaunchKernelGGL(k_bem_symm<float>, dim3(nbt, nbt), dim3(256), 0, s, nv, ld, static_cast<float *>(S.B),
                                static_cast<const float *>(Tm));
