@@ -111,11 +111,15 @@ template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int6
     U[at] = MT(double(U[at]) + v);
 }
 
-// Rows of the fold's last stage whose operator entries a thread reads before
-// the quadrature (the rest are read when they are added to).  FP32 tiles: one
-// (342 -> 325 ms per 80k-triangle assembly; two cost registers and gained
-// nothing more); FP64 tiles: none (the registers they would take spill)
-constexpr int FOLD_PF32 = 1, FOLD_PF64 = 0;
+// Rows of the fold's last stage whose operator entries a thread reads ahead
+// (the rest are read when they are added to): FP32 tiles one, before the
+// quadrature (342 -> 325 ms per 80k-triangle assembly; two cost registers and
+// gained nothing more); FP64 tiles one, after the quadrature, whose registers
+// are free by then, so that the reads overlap the fold's LDS passes (before
+// it they spill; 572 -> 565 ms).  The two reads are written out in place:
+// the FP32 kernels' register allocation (six wavefronts per SIMD) did not
+// survive moving them into a shared function.
+constexpr int FOLD_PF32 = 1, FOLD_PF64 = 1;
 template <typename MT> constexpr int fold_pf() { return sizeof(MT) == 4 ? FOLD_PF32 : FOLD_PF64; }
 
 // Fold of a tile's pair blocks onto the blocks' vertices through the shared
@@ -495,12 +499,12 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
         }
     };
 
-    // The stored entries this thread adds to in the fold's last stage (row
-    // vA[ia], column vB[jb] of V', K' and, square tiles, T; the fold's thread
-    // map), read now so that their latency hides behind the quadrature.  No
-    // other workgroup of the launch touches them.
+    // FP32: the stored entries this thread adds to in the fold's last stage
+    // (row vA[ia], column vB[jb] of V', K' and, square tiles, T; the fold's
+    // thread map), read now so that their latency hides behind the
+    // quadrature.  No other workgroup of the launch touches them.
     MT pre[fold_pf<MT>() > 0 ? fold_pf<MT>() : 1][3];
-    {
+    if constexpr (F32) {
         const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
         if (r0 < rstep) {
             const int64_t col = sIb[jb];
@@ -562,6 +566,21 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
                                             pre);
         }
     } else {
+        // FP64: the stored entries are read after the quadrature, whose registers are free by now
+        const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+        if (r0 < rstep) {
+            const int64_t col = sIb[jb];
+#pragma unroll
+            for (int k = 0; k < fold_pf<MT>(); ++k) {
+                const int ia = r0 + k * rstep;
+                if (ia < nA) {
+                    const int64_t row = sIa[ia];
+                    pre[k][0] = U[row * ld + nv + col];
+                    pre[k][1] = U[row * ld + col];
+                    if constexpr (SYM) pre[k][2] = T[row * nv + col];
+                }
+            }
+        }
         fold_tile_one<TA, TB, MS, 0>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Vl, sIa, sIb, U, ld, nv, sV, pre);
         fold_tile_one<TA, TB, MS, 1>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Kl, sIa, sIb, U, ld, 0, sK, pre);
         if constexpr (SYM)
