@@ -38,10 +38,10 @@ HBM_PEAK_GBS = 8000.0
 # for the row routines whose source hash is recorded with them; see
 # profiles/gemv_rna80k_hbm_counters.md.
 GEMV_TRAFFIC = {
-    "rna80k_f32": {"src_sha256_16": "6095e1a4da7a1d9d",
-                   "bytes": 9865463.18 * 2048 + 219596.62 * 1024 + 157890.78 * 2048 + 1235.39 * 1024},
-    "rna80k_f64": {"src_sha256_16": "6095e1a4da7a1d9d",
-                   "bytes": 19708633.05 * 2048 + 210752.29 * 1024 + 157890.78 * 2048 + 1235.39 * 1024},
+    "rna80k_f32": {"src_sha256_16": "deeceee34205a861",
+                   "bytes": 9868457.90 * 2048 + 207660.05 * 1024 + 157913.34 * 2048 + 1234.99 * 1024},
+    "rna80k_f64": {"src_sha256_16": "deeceee34205a861",
+                   "bytes": 19708620.99 * 2048 + 210754.01 * 1024 + 157913.34 * 2048 + 1234.99 * 1024},
 }
 
 
