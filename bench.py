@@ -38,10 +38,10 @@ HBM_PEAK_GBS = 8000.0
 # for the row routines whose source hash is recorded with them; see
 # profiles/gemv_rna80k_hbm_counters.md.
 GEMV_TRAFFIC = {
-    "rna80k_f32": {"src_sha256_16": "deeceee34205a861",
-                   "bytes": 9868457.90 * 2048 + 207660.05 * 1024 + 157913.34 * 2048 + 1234.99 * 1024},
-    "rna80k_f64": {"src_sha256_16": "deeceee34205a861",
-                   "bytes": 19708620.99 * 2048 + 210754.01 * 1024 + 157913.34 * 2048 + 1234.99 * 1024},
+    "rna80k_f32": {"src_sha256_16": "9066d2ee5bfca69e",
+                   "bytes": 9868269.03 * 2048 + 207677.50 * 1024 + 157896.09 * 2048 + 1235.06 * 1024},
+    "rna80k_f64": {"src_sha256_16": "9066d2ee5bfca69e",
+                   "bytes": 19708630.60 * 2048 + 210751.00 * 1024 + 157896.09 * 2048 + 1235.06 * 1024},
 }
 
 

@@ -119,14 +119,17 @@ __device__ inline void gemv_lds_barrier()
 // For the third sum the V item forms the column sums
 // P[blk][j] = sum_{r in its rows, r > j} V'_rj l_r over the V' columns it
 // reads (the eight wavefronts' partials added in LDS in a fixed tree order,
-// GSYM_G chunks of the row stream at a time), blk = r0 / 64; its row sums go
+// gsym_g chunks of the row stream at a time), blk = r0 / 64; its row sums go
 // to P[nblk * n + row] and the finish adds them.  Rows past n contribute
 // nothing.  Together the items read n + r0 + 64 entries of each row instead
 // of 2 n; the partials are 1/64 of the V' bytes read (written once, read
 // once).  Splitting the row block lets the launch order the items for the
 // memory system (gemv_item): the uniform K items and the triangle's V items
 // of decreasing length overlap instead of every workgroup streaming both.
-constexpr int GSYM_G = 4; // chunks per LDS exchange (64 KB of partials for FP32, 32 KB for FP64)
+// chunks per LDS exchange: FP32 storage 8 (128 KB of partials; its kernel runs
+// one workgroup per CU either way; 0.769 -> 0.772 of HBM against 4, 2 slower),
+// FP64 storage 4 (32 KB, two workgroups per CU)
+template <typename MT> constexpr int gsym_g() { return sizeof(MT) == 4 ? 8 : 4; }
 // The partials are FP64 for both storage precisions: with FP32 partials the
 // apply is linear only to FP32 rounding of the partial sums, which left
 // strongly charged instances short of the Newton tolerance in mixed mode.
@@ -178,7 +181,7 @@ template <typename MT>
 __device__ inline void gemv_rows_symV(const MT *__restrict__ B, const double *__restrict__ x,
                                       double *__restrict__ P, int64_t n, int64_t ld, int64_t r0, int tid)
 {
-    constexpr int RW = GEMV_RW, WV = GEMV_WAVES, G = GSYM_G;
+    constexpr int RW = GEMV_RW, WV = GEMV_WAVES, G = gsym_g<MT>();
     static_assert(WV == 8, "the partials are added in an eight-term tree");
     using C = GemvChunk<MT>;
     constexpr int EL = C::EL, CW = C::CW;
