@@ -207,6 +207,28 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
     __syncthreads();
 }
 
+// A thread's part of the fold of an FP32 tile, the same for every operator
+// folded: source vertex jb, first row r0 and row step of its strided rows, and
+// the tile columns of jb's corners (absent corners: the zero column CMAX)
+template <int MS> struct FoldMap {
+    int jb, r0, rstep;
+    int cb[MS];
+};
+template <int NT, int MS>
+__device__ inline FoldMap<MS> fold_map(int tid, int nB, const int (*sSb)[MS], int cmax)
+{
+    FoldMap<MS> fm;
+    fm.jb = tid % nB;
+    fm.r0 = tid / nB;
+    fm.rstep = NT / nB;
+#pragma unroll
+    for (int l = 0; l < MS; ++l) {
+        const int c = sSb[fm.jb][l];
+        fm.cb[l] = c < 0 ? cmax : c;
+    }
+    return fm;
+}
+
 // Fold of an FP32 tile's pair blocks (corner sums in FP32, the evaluation
 // precision), V and K in two FP32 planes of the shared tile read at the same
 // index (TOT = false: V to column off + vB[jb]
@@ -214,20 +236,15 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
 // the mirrored K of a square tile in one plane (TOT = true: to column vB[jb]
 // of row vA[ia] of U = T with factor s0); otherwise as fold_tile_one.
 template <int TA, int TB, int MS, bool TOT, typename MT>
-__device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
-                                     const int (*sSb)[MS], float (*acc)[TA * 3 + 1][TB * 3 + 1],
+__device__ inline void fold_tile_f32(int tid, int tl, int sl, int nA, const FoldMap<MS> &fm, const int (*sSa)[MS],
+                                     float (*acc)[TA * 3 + 1][TB * 3 + 1],
                                      const float (*blk)[9], const int *vA, const int *vB, MT *__restrict__ U,
                                      int64_t ld, int64_t off, double s0, double s1, const MT (*pre)[3])
 {
     constexpr int NT = TA * TB, RMAX = TA * 3, CMAX = TB * 3, RC = 4, NPL = TOT ? 1 : 2;
-    const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+    const int jb = fm.jb, r0 = fm.r0, rstep = fm.rstep;
     const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
-    int cb[MS];
-#pragma unroll
-    for (int l = 0; l < MS; ++l) {
-        const int c = sSb[jb][l];
-        cb[l] = c < 0 ? CMAX : c;
-    }
+    const int (&cb)[MS] = fm.cb;
     for (int k = tid; k < CMAX + 1; k += NT)
 #pragma unroll
         for (int pl = 0; pl < NPL; ++pl) acc[pl][RMAX][k] = 0.0f;
@@ -559,11 +576,11 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
             blk[1][k] = Kl[k];
             bmt[0][k] = Ktl[SYM ? k : 0];
         }
-        fold_tile_f32<TA, TB, MS, false>(tid, tl, sl, nA, nB, sSa, sSb, acc, blk, sIa, sIb, U, ld, nv, sV, sK, pre);
+        const FoldMap<MS> fm = fold_map<NT, MS>(tid, nB, sSb, TB * 3);
+        fold_tile_f32<TA, TB, MS, false>(tid, tl, sl, nA, fm, sSa, acc, blk, sIa, sIb, U, ld, nv, sV, sK, pre);
         if constexpr (SYM) {
             __syncthreads();
-            fold_tile_f32<TA, TB, MS, true>(tid, tl, sl, nA, nB, sSa, sSb, acc, bmt, sIa, sIb, T, nv, 0, sK, 0.0,
-                                            pre);
+            fold_tile_f32<TA, TB, MS, true>(tid, tl, sl, nA, fm, sSa, acc, bmt, sIa, sIb, T, nv, 0, sK, 0.0, pre);
         }
     } else {
         // FP64: the stored entries are read after the quadrature, whose registers are free by now
