@@ -122,6 +122,28 @@ template <typename MT> __device__ inline void add_entry(MT *__restrict__ U, int6
 constexpr int FOLD_PF32 = 1, FOLD_PF64 = 1;
 template <typename MT> constexpr int fold_pf() { return sizeof(MT) == 4 ? FOLD_PF32 : FOLD_PF64; }
 
+// A thread's part of the fold of a tile, the same for every operator
+// folded: source vertex jb, first row r0 and row step of its strided rows, and
+// the tile columns of jb's corners (absent corners: the zero column CMAX)
+template <int MS> struct FoldMap {
+    int jb, r0, rstep;
+    int cb[MS];
+};
+template <int NT, int MS>
+__device__ inline FoldMap<MS> fold_map(int tid, int nB, const int (*sSb)[MS], int cmax)
+{
+    FoldMap<MS> fm;
+    fm.jb = tid % nB;
+    fm.r0 = tid / nB;
+    fm.rstep = NT / nB;
+#pragma unroll
+    for (int l = 0; l < MS; ++l) {
+        const int c = sSb[fm.jb][l];
+        fm.cb[l] = c < 0 ? cmax : c;
+    }
+    return fm;
+}
+
 // Fold of a tile's pair blocks onto the blocks' vertices through the shared
 // tile, one operator at a time (FP64 evaluation: V, K and the mirrored K in
 // turn through one FP64 plane, which keeps the LDS of a workgroup small
@@ -135,20 +157,15 @@ template <typename MT> constexpr int fold_pf() { return sizeof(MT) == 4 ? FOLD_P
 // any vertex of either block: the lists past it hold only absent corners,
 // whose +0 terms are skipped.
 template <int TA, int TB, int MS, int SLOT, typename MT, typename ST, typename XT>
-__device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, const int (*sSa)[MS],
-                                     const int (*sSb)[MS], ST (*acc)[TB * 3 + 1], const XT *Xl, const int *vA,
+__device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, const FoldMap<MS> &fm, const int (*sSa)[MS],
+                                     ST (*acc)[TB * 3 + 1], const XT *Xl, const int *vA,
                                      const int *vB, MT *__restrict__ U, int64_t ld, int64_t off, double sc,
                                      const MT (*pre)[3])
 {
     constexpr int NT = TA * TB;
-    const int jb = tid % nB, r0 = tid / nB, rstep = NT / nB;
+    const int jb = fm.jb, r0 = fm.r0, rstep = fm.rstep;
     const bool colthread = r0 < rstep; // NT - rstep * nB threads stay idle
-    int cb[MS];
-#pragma unroll
-    for (int l = 0; l < MS; ++l) {
-        const int c = sSb[jb][l];
-        cb[l] = c < 0 ? TB * 3 : c;
-    }
+    const int (&cb)[MS] = fm.cb;
     for (int k = tid; k < TB * 3 + 1; k += NT) acc[TA * 3][k] = 0.0;
     if (tid < TA * 3) acc[tid][TB * 3] = 0.0;
 #pragma unroll
@@ -205,28 +222,6 @@ __device__ inline void fold_tile_one(int tid, int tl, int sl, int nA, int nB, co
         for (int ia = r0 + fold_pf<MT>() * rstep; ia < nA; ia += rstep) add_entry(U, int64_t(vA[ia]) * ld + col, sc * rowsum(ia));
     }
     __syncthreads();
-}
-
-// A thread's part of the fold of an FP32 tile, the same for every operator
-// folded: source vertex jb, first row r0 and row step of its strided rows, and
-// the tile columns of jb's corners (absent corners: the zero column CMAX)
-template <int MS> struct FoldMap {
-    int jb, r0, rstep;
-    int cb[MS];
-};
-template <int NT, int MS>
-__device__ inline FoldMap<MS> fold_map(int tid, int nB, const int (*sSb)[MS], int cmax)
-{
-    FoldMap<MS> fm;
-    fm.jb = tid % nB;
-    fm.r0 = tid / nB;
-    fm.rstep = NT / nB;
-#pragma unroll
-    for (int l = 0; l < MS; ++l) {
-        const int c = sSb[fm.jb][l];
-        fm.cb[l] = c < 0 ? cmax : c;
-    }
-    return fm;
 }
 
 // Fold of an FP32 tile's pair blocks (corner sums in FP32, the evaluation
@@ -598,10 +593,11 @@ __global__ void __launch_bounds__(TA * TB) __attribute__((amdgpu_waves_per_eu(si
                 }
             }
         }
-        fold_tile_one<TA, TB, MS, 0>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Vl, sIa, sIb, U, ld, nv, sV, pre);
-        fold_tile_one<TA, TB, MS, 1>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Kl, sIa, sIb, U, ld, 0, sK, pre);
+        const FoldMap<MS> fm = fold_map<NT, MS>(tid, nB, sSb, TB * 3);
+        fold_tile_one<TA, TB, MS, 0>(tid, tl, sl, nA, fm, sSa, acc[0], Vl, sIa, sIb, U, ld, nv, sV, pre);
+        fold_tile_one<TA, TB, MS, 1>(tid, tl, sl, nA, fm, sSa, acc[0], Kl, sIa, sIb, U, ld, 0, sK, pre);
         if constexpr (SYM)
-            fold_tile_one<TA, TB, MS, 2>(tid, tl, sl, nA, nB, sSa, sSb, acc[0], Ktl, sIa, sIb, T, nv, 0, sK, pre);
+            fold_tile_one<TA, TB, MS, 2>(tid, tl, sl, nA, fm, sSa, acc[0], Ktl, sIa, sIb, T, nv, 0, sK, pre);
     }
 }
 
